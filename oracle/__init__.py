@@ -1,0 +1,251 @@
+"""FP64 CPU oracle of the localization path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports, links or executes anything here, and this
+package never imports the product path; the two share only the seeded input
+generators in ``smlm_synth``.
+
+The arithmetic lives in ``oracle.c`` (plain C, double precision, loops in the
+order of the definition).  This module compiles it with gcc and wraps it with
+ctypes, plus the few steps that are plain bookkeeping (record assembly).
+
+Definitions followed (paper Sec. 2.2, Sec. 3.2, Sec. 3.2.1, Sec. 3.3):
+see the header of ``oracle.c``.  Readings where the paper is silent are listed
+in DESIGN.md ("Readings of the paper").
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+
+#: sigma(TAU) == 0.3: detection threshold on the logit
+TAU = math.log(0.3 / 0.7)
+
+GCC_FLAGS = ["-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
+             "-fopenmp", "-fPIC", "-shared", "-std=c99"]
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` into ``oracle/_build/liboracle.so`` (gcc, no fast-math,
+    no FMA contraction, so every operation rounds as written)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        d, i, l = ctypes.c_double, ctypes.c_int, ctypes.c_long
+        P = ctypes.c_void_p
+        _lib.or_round_bf16.restype = d
+        _lib.or_round_bf16.argtypes = [d]
+        _lib.or_round_e4m3.restype = d
+        _lib.or_round_e4m3.argtypes = [d]
+        _lib.or_preprocess.argtypes = [P, l, d, d, d, P]
+        _lib.or_conv3x3.argtypes = [P, i, i, i, P, P, i, i, P]
+        _lib.or_net_maps.restype = i
+        _lib.or_net_maps.argtypes = [P, i, i, d, d, d, P, i, i, P, i, P]
+        _lib.or_detect.argtypes = [P, i, i, d, P]
+        _lib.or_gate_pool.argtypes = [P, i, i, i, P]
+        _lib.or_gate_forward.argtypes = [P, i, i, i, P, P]
+        _lib.or_bce.restype = d
+        _lib.or_bce.argtypes = [P, P, i, P]
+        _lib.or_gate_backward.argtypes = [P, i, i, i, P, P, P]
+        _lib.or_adam_step.argtypes = [P, P, P, P, i, i, d, d, d, d]
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+# ----------------------------------------------------------------- rounding
+def round_bf16(v: np.ndarray) -> np.ndarray:
+    v = np.asarray(v, np.float64)
+    f = np.vectorize(_L().or_round_bf16, otypes=[np.float64])
+    return f(v)
+
+
+def round_e4m3(v: np.ndarray) -> np.ndarray:
+    v = np.asarray(v, np.float64)
+    f = np.vectorize(_L().or_round_e4m3, otypes=[np.float64])
+    return f(v)
+
+
+# ----------------------------------------------------------- preprocessing
+def preprocess(frames: np.ndarray, gain: float, offset: float, in_scale: float) -> np.ndarray:
+    F = np.ascontiguousarray(frames, np.uint16)
+    x = np.empty(F.shape, np.float64)
+    _L().or_preprocess(_p(F), F.size, gain, offset, in_scale, _p(x))
+    return x
+
+
+# ------------------------------------------------------------- convolution
+def conv3x3(x: np.ndarray, W: np.ndarray, b: Optional[np.ndarray], d: int) -> np.ndarray:
+    """One 3x3 convolution with dilation ``d``: x [cin][h][w] -> [cout][h][w]."""
+    x = np.ascontiguousarray(x, np.float64)
+    W = np.ascontiguousarray(W, np.float64)
+    cin, h, w = x.shape
+    cout = W.shape[0]
+    assert W.shape == (cout, cin, 3, 3)
+    out = np.empty((cout, h, w), np.float64)
+    bb = None if b is None else np.ascontiguousarray(b, np.float64)
+    _L().or_conv3x3(_p(x), cin, h, w, _p(W), None if bb is None else _p(bb), cout, int(d), _p(out))
+    return out
+
+
+# ------------------------------------------------------------- the network
+QUANT = {"fp32": 0, "fp64": 0, "exact": 0, "bf16": 1, "fp8": 2}
+
+
+def _flat(spec, weights: Dict[str, np.ndarray]) -> np.ndarray:
+    from smlm_synth import flat_weights
+    return np.ascontiguousarray(flat_weights(spec, weights), np.float32)
+
+
+def net_maps(frame: np.ndarray, spec, weights: Dict[str, np.ndarray], gain: float = 0.5,
+             offset: float = 100.0, quant: str = "exact") -> np.ndarray:
+    """Maps [5][h][w] (logit, dx, dy, dz, photons) of one uint16 frame, FP64."""
+    F = np.ascontiguousarray(frame, np.uint16)
+    h, w = F.shape
+    params = _flat(spec, weights)
+    dil = np.asarray(spec.dilations, np.int32)
+    maps = np.empty((5, h, w), np.float64)
+    rc = _L().or_net_maps(_p(F), h, w, gain, offset, spec.in_scale, _p(params), spec.C,
+                          len(spec.dilations), _p(dil), QUANT[quant], _p(maps))
+    if rc != 0:
+        raise RuntimeError("oracle net failed")
+    return maps
+
+
+def net_maps_batch(frames: np.ndarray, spec, weights, gain=0.5, offset=100.0, quant="exact"):
+    return np.stack([net_maps(f, spec, weights, gain, offset, quant) for f in frames])
+
+
+def net_maps_window(frame: np.ndarray, spec, weights, y0: int, x0: int, hh: int, ww: int,
+                    gain=0.5, offset=100.0, quant="exact", margin: Optional[int] = None) -> np.ndarray:
+    """Exact maps of the output window [y0, y0+hh) x [x0, x0+ww) of a large frame.
+
+    The net reads at most ``R = 1 + 2 * sum(dilations)`` pixels away, so running
+    it on the frame cropped to the window plus an R-pixel margin gives exact
+    values inside the window (the crop edge coincides with the frame edge where
+    the margin is clipped, and is at least R away elsewhere)."""
+    H, W = frame.shape
+    R = 1 + 2 * sum(spec.dilations) if margin is None else margin
+    cy0, cx0 = max(0, y0 - R), max(0, x0 - R)
+    cy1, cx1 = min(H, y0 + hh + R), min(W, x0 + ww + R)
+    crop = frame[cy0:cy1, cx0:cx1]
+    m = net_maps(crop, spec, weights, gain, offset, quant)
+    return m[:, y0 - cy0:y0 - cy0 + hh, x0 - cx0:x0 - cx0 + ww]
+
+
+# --------------------------------------------------------------- detection
+def detect(logit: np.ndarray, tau: float = TAU) -> np.ndarray:
+    """bool [h][w]: logit > tau and a strict winner of its 3x3 neighbourhood in
+    the order (value, then smaller raster index)."""
+    L = np.ascontiguousarray(logit, np.float64)
+    h, w = L.shape
+    det = np.empty((h, w), np.uint8)
+    _L().or_detect(_p(L), h, w, float(tau), _p(det))
+    return det.astype(bool)
+
+
+EMITTER_DTYPE = np.dtype([("frame", "<i4"), ("row", "<i4"), ("col", "<i4"), ("x", "<f8"),
+                          ("y", "<f8"), ("z", "<f8"), ("photons", "<f8"), ("prob", "<f8")])
+
+
+def records(maps: np.ndarray, det: np.ndarray, spec, frame: int = 0) -> np.ndarray:
+    """Emitter records of one frame in raster order: x = col + 0.5 + dx,
+    y = row + 0.5 + dy (pixel centres), z = dz * z_scale, photons = ph * ph_scale,
+    prob = 1 / (1 + exp(-logit))."""
+    rows, cols = np.nonzero(det)            # row-major order == raster order
+    out = np.empty(rows.size, EMITTER_DTYPE)
+    out["frame"] = frame
+    out["row"] = rows
+    out["col"] = cols
+    out["x"] = cols + 0.5 + maps[1, rows, cols]
+    out["y"] = rows + 0.5 + maps[2, rows, cols]
+    out["z"] = maps[3, rows, cols] * spec.z_scale
+    out["photons"] = maps[4, rows, cols] * spec.ph_scale
+    out["prob"] = 1.0 / (1.0 + np.exp(-maps[0, rows, cols]))
+    return out
+
+
+def localize(frames: np.ndarray, spec, weights, gain=0.5, offset=100.0, threshold=0.3,
+             quant="exact", return_maps=False):
+    """Whole path: frames -> maps -> detections -> records (frame, row, col order)."""
+    tau = math.log(threshold / (1.0 - threshold))
+    recs, allmaps = [], []
+    for f, F in enumerate(frames):
+        m = net_maps(F, spec, weights, gain, offset, quant)
+        recs.append(records(m, detect(m[0], tau), spec, f))
+        if return_maps:
+            allmaps.append(m)
+    r = np.concatenate(recs) if recs else np.empty(0, EMITTER_DTYPE)
+    return (r, np.stack(allmaps)) if return_maps else r
+
+
+# -------------------------------------------------------------------- gate
+GATE_NPARAM = 673
+
+
+def gate_pool(x_tile: np.ndarray, pool: int = 4) -> np.ndarray:
+    x = np.ascontiguousarray(x_tile, np.float64)
+    th, tw = x.shape
+    p = np.empty((th // pool, tw // pool), np.float64)
+    _L().or_gate_pool(_p(x), th, tw, pool, _p(p))
+    return p
+
+
+def gate_forward(pooled: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    P = np.ascontiguousarray(pooled, np.float64)
+    th = np.ascontiguousarray(theta, np.float64)
+    assert th.size == GATE_NPARAM
+    n, ph, pw = P.shape
+    g = np.empty(n, np.float64)
+    _L().or_gate_forward(_p(P), n, ph, pw, _p(th), _p(g))
+    return g
+
+
+def bce(g: np.ndarray, y: np.ndarray):
+    g = np.ascontiguousarray(g, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    dg = np.empty_like(g)
+    L = _L().or_bce(_p(g), _p(y), g.size, _p(dg))
+    return L, dg
+
+
+def gate_backward(pooled: np.ndarray, theta: np.ndarray, dg: np.ndarray) -> np.ndarray:
+    P = np.ascontiguousarray(pooled, np.float64)
+    th = np.ascontiguousarray(theta, np.float64)
+    dg = np.ascontiguousarray(dg, np.float64)
+    n, ph, pw = P.shape
+    grad = np.empty(GATE_NPARAM, np.float64)
+    _L().or_gate_backward(_p(P), n, ph, pw, _p(th), _p(dg), _p(grad))
+    return grad
+
+
+def adam_step(theta, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays theta, m, v."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, np.float64)
+    _L().or_adam_step(_p(theta), _p(m), _p(v), _p(g), theta.size, int(t), lr, b1, b2, eps)

@@ -1,0 +1,437 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of the localization path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call, link or
+ * load this file; it exists so the tests, the smoke check and the CPU
+ * baseline leg of the benchmark can compare the HIP library against an
+ * obviously correct, slow definition.  It shares no code with the HIP path.
+ *
+ * What is computed (paper Sec. 2.2: the network runs on the preloaded frames
+ * and post-processing stays on the device; Sec. 3.2: a dilated-convolution
+ * network whose per-pixel output is a detection probability plus sub-pixel
+ * offsets, as in DECODE; Sec. 3.2.1: dilated 3x3 convolutions):
+ *
+ *   x      = (ADU - offset) * gain * in_scale                       preprocessing
+ *   a      = ReLU(conv_1(x; stem))                                  stem, 1 -> C
+ *   per block k with dilation d_k:
+ *     t    = ReLU(conv_dk(a; W_k1, b_k1))
+ *     a    = ReLU(a + conv_dk(t; W_k2, b_k2))                       residual block
+ *   maps   = head(a), 1x1, C -> 5: logit, dx, dy, dz, photons
+ *
+ * conv_d is a cross-correlation with taps spaced d pixels apart and zero
+ * "same" padding applied at the true frame border at every layer:
+ *   y[o][i][j] = b[o] + sum_c sum_{u,v in -1..1} W[o][c][u+1][v+1] * x[c][i+d*u][j+d*v]
+ *
+ * Every multiply and add is done in double precision in the plain loop order
+ * written below (no blocking, no reordering).  Parallelism (OpenMP) is only
+ * over independent output rows/channels and never changes an output's
+ * summation order.
+ *
+ * Emulation modes (quant = 1: BF16, quant = 2: FP8 e4m3) round the stored
+ * activations and block-convolution operands the way the reduced-precision
+ * forms store them; products and sums stay in double.
+ *
+ * Pins (tests/test_oracle_*.py): delta input reproduces the kernel weights;
+ * linearity; constant field; torch-CPU float64 conv2d(dilation=d); residual
+ * special cases; positive homogeneity of a bias-free net; locality (crop with
+ * receptive-radius margin == whole frame); NMS brute force on tiny frames;
+ * BF16/e4m3 rounding against torch casts; gate gradients against central
+ * differences and torch autograd; Adam against torch.optim.Adam.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR (-1)
+
+/* ---------------------------------------------------------------- rounding */
+
+/* float64 -> bfloat16 -> float64, round to nearest even (via the float32 value
+ * the reduced-precision path starts from). NaN is not expected. */
+double or_round_bf16(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    u &= 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* OCP e4m3fn value nearest to v (ties to even mantissa), saturating at +-448.
+ * Finite e4m3fn values: subnormals m * 2^-9 (m = 1..7), normals
+ * (1 + m/8) * 2^(e-7) for e = 1..15 (m <= 6 when e = 15). */
+double or_round_e4m3(double v)
+{
+    double a = fabs(v);
+    double s = v < 0 ? -1.0 : 1.0;
+    if (a >= 448.0) return s * 448.0;
+    if (a == 0.0) return 0.0 * s;
+    int e;
+    frexp(a, &e);              /* a = f * 2^e, f in [0.5, 1) -> a in [2^(e-1), 2^e) */
+    int ex = e - 1;            /* a in [2^ex, 2^(ex+1)) */
+    if (ex < -6) ex = -6;      /* subnormal range shares the quantum 2^-9 */
+    double q = ldexp(1.0, ex - 3);   /* spacing of representable values */
+    double r = a / q;                /* exact: scaling by a power of two */
+    double fl = floor(r);
+    double frac = r - fl;
+    double n;
+    if (frac > 0.5) n = fl + 1.0;
+    else if (frac < 0.5) n = fl;
+    else n = (fmod(fl, 2.0) == 0.0) ? fl : fl + 1.0;
+    double out = n * q;
+    if (out > 448.0) out = 448.0;
+    return s * out;
+}
+
+static double store_round(double v, int quant)
+{
+    if (quant == 1 || quant == 2) return or_round_bf16(v);
+    return v;
+}
+
+/* ------------------------------------------------------------ preprocessing */
+
+void or_preprocess(const uint16_t *F, long npx, double gain, double offset,
+                   double in_scale, double *x)
+{
+    for (long p = 0; p < npx; ++p)
+        x[p] = ((double)F[p] - offset) * gain * in_scale;
+}
+
+/* ------------------------------------------------------------- convolution */
+
+/* One 3x3 dilated convolution, planar [cin][h][w] -> [cout][h][w], zero padding
+ * outside the frame.  W is [cout][cin][3][3], b is [cout] (may be NULL). */
+void or_conv3x3(const double *in, int cin, int h, int w, const double *W,
+                const double *b, int cout, int d, double *out)
+{
+    long hw = (long)h * w;
+#pragma omp parallel for schedule(static)
+    for (int o = 0; o < cout; ++o) {
+        double *y = out + (long)o * hw;
+        for (long p = 0; p < hw; ++p) y[p] = b ? b[o] : 0.0;
+        for (int c = 0; c < cin; ++c) {
+            const double *xc = in + (long)c * hw;
+            for (int u = -1; u <= 1; ++u) {
+                for (int v = -1; v <= 1; ++v) {
+                    double wt = W[(((long)o * cin + c) * 3 + (u + 1)) * 3 + (v + 1)];
+                    for (int i = 0; i < h; ++i) {
+                        int ii = i + d * u;
+                        if (ii < 0 || ii >= h) continue;
+                        int j0 = 0, j1 = w;           /* j + d*v inside [0, w) */
+                        if (d * v < 0) j0 = -d * v;
+                        if (d * v > 0) j1 = w - d * v;
+                        double *yr = y + (long)i * w;
+                        const double *xr = xc + (long)ii * w + d * v;
+                        for (int j = j0; j < j1; ++j) yr[j] += wt * xr[j];
+                    }
+                }
+            }
+        }
+    }
+}
+
+/* -------------------------------------------------------------- the network */
+
+/* Parameters arrive as the FP32 blob tensors in order:
+ *   stem.w [C][1][3][3], stem.b [C],
+ *   per block: w1 [C][C][3][3], b1 [C], w2 [C][C][3][3], b2 [C],
+ *   head.w [5][C], head.b [5]
+ * quant: 0 = exact FP64, 1 = BF16 emulation, 2 = FP8 emulation. */
+static void promote(const float *src, long n, double *dst)
+{
+    for (long i = 0; i < n; ++i) dst[i] = (double)src[i];
+}
+
+/* per-output-channel e4m3 weight quantisation: ws[o] = max|W[o]| / 448 (FP32),
+ * Wq = e4m3(W * fl32(448 / max|W[o]|)) * ws[o], i.e. the dequantised value. */
+static void quant_weights_fp8(double *W, int cout, long per_out)
+{
+    for (int o = 0; o < cout; ++o) {
+        double *wo = W + (long)o * per_out;
+        double mx = 0.0;
+        for (long k = 0; k < per_out; ++k) if (fabs(wo[k]) > mx) mx = fabs(wo[k]);
+        if (mx == 0.0) continue;
+        float inv = (float)(448.0 / mx);
+        float ws = (float)(mx / 448.0);
+        for (long k = 0; k < per_out; ++k) {
+            float sc = (float)wo[k] * inv;
+            wo[k] = or_round_e4m3((double)sc) * (double)ws;
+        }
+    }
+}
+
+/* e4m3 activation quantisation of a whole [c][h][w] tensor with one scale:
+ * s = amax / 448 (FP32), a_q = e4m3(fl32(a * fl32(448 / amax))) * s. */
+static void quant_act_fp8(double *a, long n)
+{
+    double mx = 0.0;
+    for (long k = 0; k < n; ++k) if (fabs(a[k]) > mx) mx = fabs(a[k]);
+    if (mx == 0.0) return;
+    float inv = (float)(448.0 / (double)(float)mx);
+    float s = (float)((double)(float)mx / 448.0);
+    for (long k = 0; k < n; ++k) {
+        float sc = (float)a[k] * inv;
+        a[k] = or_round_e4m3((double)sc) * (double)s;
+    }
+}
+
+int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
+                double in_scale, const float *params, int C, int nblocks,
+                const int *dil, int quant, double *maps /* [5][h][w] */)
+{
+    if (h <= 0 || w <= 0 || C <= 0 || nblocks < 0 || quant < 0 || quant > 2) return OR_ERR;
+    long hw = (long)h * w;
+    long nconv = (long)C * C * 9;
+    double *x = malloc(sizeof(double) * hw);
+    double *a = malloc(sizeof(double) * hw * C);
+    double *t = malloc(sizeof(double) * hw * C);
+    double *u = malloc(sizeof(double) * hw * C);
+    double *Wd = malloc(sizeof(double) * nconv);
+    double *bd = malloc(sizeof(double) * (C > 5 ? C : 5));
+    if (!x || !a || !t || !u || !Wd || !bd) {
+        free(x); free(a); free(t); free(u); free(Wd); free(bd);
+        return OR_ERR;
+    }
+    const float *p = params;
+
+    or_preprocess(F, hw, gain, offset, in_scale, x);
+
+    /* stem: 1 -> C, dilation 1, FP32-exact weights in every mode */
+    promote(p, (long)C * 9, Wd); p += (long)C * 9;
+    promote(p, C, bd); p += C;
+    or_conv3x3(x, 1, h, w, Wd, bd, C, 1, a);
+    for (long k = 0; k < hw * C; ++k) a[k] = store_round(a[k] > 0 ? a[k] : 0.0, quant);
+
+    for (int blk = 0; blk < nblocks; ++blk) {
+        int d = dil[blk];
+        /* t = ReLU(conv_d(a; W1, b1)) */
+        promote(p, nconv, Wd); p += nconv;
+        promote(p, C, bd); p += C;
+        if (quant == 1) for (long k = 0; k < nconv; ++k) Wd[k] = or_round_bf16(Wd[k]);
+        if (quant == 2) { quant_weights_fp8(Wd, C, (long)C * 9); memcpy(u, a, sizeof(double) * hw * C); quant_act_fp8(u, hw * C); }
+        or_conv3x3(quant == 2 ? u : a, C, h, w, Wd, bd, C, d, t);
+        for (long k = 0; k < hw * C; ++k) t[k] = store_round(t[k] > 0 ? t[k] : 0.0, quant);
+        /* a = ReLU(a + conv_d(t; W2, b2)) */
+        promote(p, nconv, Wd); p += nconv;
+        promote(p, C, bd); p += C;
+        if (quant == 1) for (long k = 0; k < nconv; ++k) Wd[k] = or_round_bf16(Wd[k]);
+        if (quant == 2) { quant_weights_fp8(Wd, C, (long)C * 9); quant_act_fp8(t, hw * C); }
+        or_conv3x3(t, C, h, w, Wd, bd, C, d, u);
+        for (long k = 0; k < hw * C; ++k) {
+            double s = a[k] + u[k];
+            a[k] = store_round(s > 0 ? s : 0.0, quant);
+        }
+    }
+
+    /* head: 1x1, C -> 5, FP32 weights in every mode */
+    promote(p, 5L * C, Wd); p += 5L * C;
+    promote(p, 5, bd); p += 5;
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < 5; ++q) {
+        double *m = maps + (long)q * hw;
+        for (long k = 0; k < hw; ++k) m[k] = bd[q];
+        for (int c = 0; c < C; ++c) {
+            double wt = Wd[q * C + c];
+            const double *ac = a + (long)c * hw;
+            for (long k = 0; k < hw; ++k) m[k] += wt * ac[k];
+        }
+    }
+    free(x); free(a); free(t); free(u); free(Wd); free(bd);
+    return OR_OK;
+}
+
+/* --------------------------------------------------------------- detection */
+
+/* Pixel (i, j) is detected iff logit > tau and it beats every in-frame
+ * 8-neighbour in the order (value, then smaller raster index). */
+void or_detect(const double *logit, int h, int w, double tau, uint8_t *det)
+{
+    for (int i = 0; i < h; ++i) {
+        for (int j = 0; j < w; ++j) {
+            long idx = (long)i * w + j;
+            double v = logit[idx];
+            int keep = v > tau;
+            for (int di = -1; di <= 1 && keep; ++di) {
+                for (int dj = -1; dj <= 1 && keep; ++dj) {
+                    if (di == 0 && dj == 0) continue;
+                    int ii = i + di, jj = j + dj;
+                    if (ii < 0 || ii >= h || jj < 0 || jj >= w) continue;
+                    long nidx = (long)ii * w + jj;
+                    double nv = logit[nidx];
+                    if (!(v > nv || (v == nv && idx < nidx))) keep = 0;
+                }
+            }
+            det[idx] = (uint8_t)keep;
+        }
+    }
+}
+
+/* ------------------------------------------------------------- tile gate */
+
+/* Gate network on one pooled 64x64 tile p (mean of 4x4 input blocks):
+ *   z1 = conv(p; g1.w, g1.b)  (1 -> 8, 3x3, pad 1), h1 = ReLU(z1)
+ *   z2 = conv(h1; g2.w, g2.b) (8 -> 8),            h2 = ReLU(z2)
+ *   m  = mean over pixels of h2,  g = fc.w . m + fc.b
+ * Gate parameters (673) in order: g1.w[8][1][3][3] g1.b[8] g2.w[8][8][3][3]
+ * g2.b[8] fc.w[8] fc.b[1]. */
+#define GC 8
+void or_gate_pool(const double *x, int th, int tw, int pool, double *p)
+{
+    int ph = th / pool, pw = tw / pool;
+    for (int i = 0; i < ph; ++i)
+        for (int j = 0; j < pw; ++j) {
+            double s = 0.0;
+            for (int u = 0; u < pool; ++u)
+                for (int v = 0; v < pool; ++v) s += x[(long)(i * pool + u) * tw + j * pool + v];
+            p[(long)i * pw + j] = s / (double)(pool * pool);
+        }
+}
+
+static void gate_forward_one(const double *p, int ph, int pw, const double *th,
+                             double *z1, double *h1, double *z2, double *h2,
+                             double *m, double *g)
+{
+    const double *w1 = th, *b1 = th + 72, *w2 = th + 80, *b2 = th + 656, *fw = th + 664, *fb = th + 672;
+    long hw = (long)ph * pw;
+    or_conv3x3(p, 1, ph, pw, w1, b1, GC, 1, z1);
+    for (long k = 0; k < GC * hw; ++k) h1[k] = z1[k] > 0 ? z1[k] : 0.0;
+    or_conv3x3(h1, GC, ph, pw, w2, b2, GC, 1, z2);
+    for (long k = 0; k < GC * hw; ++k) h2[k] = z2[k] > 0 ? z2[k] : 0.0;
+    double gg = fb[0];
+    for (int c = 0; c < GC; ++c) {
+        double s = 0.0;
+        for (long k = 0; k < hw; ++k) s += h2[(long)c * hw + k];
+        m[c] = s / (double)hw;
+        gg += fw[c] * m[c];
+    }
+    *g = gg;
+}
+
+/* Forward for n pooled tiles [n][ph][pw]; params theta[673] (double). */
+void or_gate_forward(const double *pooled, int n, int ph, int pw, const double *theta, double *g)
+{
+    long hw = (long)ph * pw;
+#pragma omp parallel
+    {
+        double *z1 = malloc(sizeof(double) * GC * hw), *h1 = malloc(sizeof(double) * GC * hw);
+        double *z2 = malloc(sizeof(double) * GC * hw), *h2 = malloc(sizeof(double) * GC * hw);
+        double m[GC];
+#pragma omp for schedule(static)
+        for (int b = 0; b < n; ++b)
+            gate_forward_one(pooled + (long)b * hw, ph, pw, theta, z1, h1, z2, h2, m, &g[b]);
+        free(z1); free(h1); free(z2); free(h2);
+    }
+}
+
+/* Binary cross-entropy with logits, mean over the batch (paper Sec. 3.3):
+ *   L = -(1/n) sum_b [ y_b ln s(g_b) + (1 - y_b) ln(1 - s(g_b)) ]
+ * written in the overflow-free form max(g,0) - g*y + ln(1 + e^-|g|).
+ * dL/dg_b = (s(g_b) - y_b) / n. */
+double or_bce(const double *g, const double *y, int n, double *dg)
+{
+    double L = 0.0;
+    for (int b = 0; b < n; ++b) {
+        double gb = g[b];
+        L += (gb > 0 ? gb : 0.0) - gb * y[b] + log1p(exp(-fabs(gb)));
+        if (dg) dg[b] = (1.0 / (1.0 + exp(-gb)) - y[b]) / (double)n;
+    }
+    return L / (double)n;
+}
+
+/* Backward: gradient of sum_b dg[b] * g_b with respect to theta (673), summed
+ * over the batch; ReLU'(z) = 1 for z > 0 else 0. */
+void or_gate_backward(const double *pooled, int n, int ph, int pw, const double *theta,
+                      const double *dg, double *grad)
+{
+    long hw = (long)ph * pw;
+    const double *w2 = theta + 80, *fw = theta + 664;
+    memset(grad, 0, sizeof(double) * 673);
+    double *z1 = malloc(sizeof(double) * GC * hw), *h1 = malloc(sizeof(double) * GC * hw);
+    double *z2 = malloc(sizeof(double) * GC * hw), *h2 = malloc(sizeof(double) * GC * hw);
+    double *dz2 = malloc(sizeof(double) * GC * hw), *dz1 = malloc(sizeof(double) * GC * hw);
+    double m[GC], g;
+    for (int b = 0; b < n; ++b) {
+        const double *p = pooled + (long)b * hw;
+        gate_forward_one(p, ph, pw, theta, z1, h1, z2, h2, m, &g);
+        double d = dg[b];
+        /* linear layer */
+        for (int c = 0; c < GC; ++c) grad[664 + c] += d * m[c];
+        grad[672] += d;
+        /* mean pool + ReLU */
+        for (int c = 0; c < GC; ++c)
+            for (long k = 0; k < hw; ++k)
+                dz2[(long)c * hw + k] = z2[(long)c * hw + k] > 0 ? d * fw[c] / (double)hw : 0.0;
+        /* conv2: dW2, db2, dh1 */
+        for (int o = 0; o < GC; ++o) {
+            for (long k = 0; k < hw; ++k) grad[656 + o] += dz2[(long)o * hw + k];
+            for (int c = 0; c < GC; ++c)
+                for (int u = -1; u <= 1; ++u)
+                    for (int v = -1; v <= 1; ++v) {
+                        double s = 0.0;
+                        for (int i = 0; i < ph; ++i) {
+                            int ii = i + u;
+                            if (ii < 0 || ii >= ph) continue;
+                            for (int j = 0; j < pw; ++j) {
+                                int jj = j + v;
+                                if (jj < 0 || jj >= pw) continue;
+                                s += dz2[(long)o * hw + (long)i * pw + j] * h1[(long)c * hw + (long)ii * pw + jj];
+                            }
+                        }
+                        grad[80 + ((o * GC + c) * 3 + (u + 1)) * 3 + (v + 1)] += s;
+                    }
+        }
+        /* dh1[c][ii][jj] = sum_o sum_uv W2[o][c][u][v] dz2[o][ii-u][jj-v]; then ReLU */
+        for (int c = 0; c < GC; ++c)
+            for (int ii = 0; ii < ph; ++ii)
+                for (int jj = 0; jj < pw; ++jj) {
+                    double s = 0.0;
+                    for (int o = 0; o < GC; ++o)
+                        for (int u = -1; u <= 1; ++u)
+                            for (int v = -1; v <= 1; ++v) {
+                                int i = ii - u, j = jj - v;
+                                if (i < 0 || i >= ph || j < 0 || j >= pw) continue;
+                                s += w2[((o * GC + c) * 3 + (u + 1)) * 3 + (v + 1)] * dz2[(long)o * hw + (long)i * pw + j];
+                            }
+                    long k = (long)c * hw + (long)ii * pw + jj;
+                    dz1[k] = z1[k] > 0 ? s : 0.0;
+                }
+        /* conv1: dW1, db1 */
+        for (int o = 0; o < GC; ++o) {
+            for (long k = 0; k < hw; ++k) grad[72 + o] += dz1[(long)o * hw + k];
+            for (int u = -1; u <= 1; ++u)
+                for (int v = -1; v <= 1; ++v) {
+                    double s = 0.0;
+                    for (int i = 0; i < ph; ++i) {
+                        int ii = i + u;
+                        if (ii < 0 || ii >= ph) continue;
+                        for (int j = 0; j < pw; ++j) {
+                            int jj = j + v;
+                            if (jj < 0 || jj >= pw) continue;
+                            s += dz1[(long)o * hw + (long)i * pw + j] * p[(long)ii * pw + jj];
+                        }
+                    }
+                    grad[(o * 3 + (u + 1)) * 3 + (v + 1)] += s;
+                }
+        }
+    }
+    free(z1); free(h1); free(z2); free(h2); free(dz2); free(dz1);
+}
+
+/* Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); t counts from 1. */
+void or_adam_step(double *theta, double *m, double *v, const double *grad, int n, int t,
+                  double lr, double b1, double b2, double eps)
+{
+    double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (int k = 0; k < n; ++k) {
+        m[k] = b1 * m[k] + (1.0 - b1) * grad[k];
+        v[k] = b2 * v[k] + (1.0 - b2) * grad[k] * grad[k];
+        theta[k] -= lr * (m[k] / c1) / (sqrt(v[k] / c2) + eps);
+    }
+}
