@@ -1,0 +1,220 @@
+/*
+ * dloc.h -- C ABI of the MI355X localization library (libdloc.so).
+ *
+ * The library turns raw uint16 SMLM camera frames into an emitter list on the
+ * GPU: gain/offset preprocessing, a residual network of 3x3 dilated
+ * convolutions, a 1x1 head giving per-pixel detection logit and sub-pixel
+ * offsets, then thresholding, 3x3 local-maximum suppression and an ordered
+ * compaction into emitter records.
+ *
+ * Paper passages the calls follow (An Efficient Inference Frame for Single
+ * Molecule Localization Microscopy):
+ *   - Sec. 2.2: frames are loaded ahead of time into memory the network reads
+ *     from fixed locations (preloading); post-processing is kept in GPU memory
+ *     and only the post-processed coordinates leave the device.
+ *   - Sec. 3.2: the network's output follows DECODE: per pixel a detection
+ *     probability plus the emitter's offset relative to that pixel.
+ *   - Sec. 3.2.1: feature extraction with dilated 3x3 convolutions whose
+ *     dilation sets the receptive field.
+ *   - Sec. 3.3: binary cross-entropy (used here to train the tile gate).
+ *
+ * Conventions
+ *   - Every function returns DL_OK (0) or a negative dl_status; nothing throws
+ *     or aborts across the ABI.  Arguments are validated on the host before any
+ *     HIP call, so argument errors are reported even without a GPU.
+ *   - After any error the handle stays usable; dl_last_error() describes it.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ *   - "device" pointers are HIP device memory (for example torch CUDA tensors)
+ *     on the handle's device; "host" pointers are ordinary host memory.
+ *   - Work queued by the *_device calls runs on the caller's HIP stream
+ *     (hipStream_t passed as void*, NULL = the null stream) and is not
+ *     synchronised: results are valid once that stream has completed.
+ *   - Frames are uint16 [n][h][w] row-major; maps are float [n][5][h][w]
+ *     (planes: logit, dx, dy, dz, photons); emitter records are ordered by
+ *     (frame, row, col).
+ */
+#ifndef DLOC_H
+#define DLOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DL_ABI_VERSION 1u
+
+typedef enum {
+    DL_OK = 0,
+    DL_ERR_INVALID_ARG = -1,   /* NULL/misaligned pointer, bad size, bad enum */
+    DL_ERR_BAD_WEIGHTS = -2,   /* weights blob: bad magic/version/size/NaN    */
+    DL_ERR_UNSUPPORTED = -3,   /* shape or precision this build does not run  */
+    DL_ERR_OOM = -4,           /* allocation failed or workspace cap exceeded */
+    DL_ERR_DEVICE = -5,        /* a HIP call failed; see dl_last_error        */
+    DL_ERR_CAPACITY = -6       /* more emitters than the output capacity      */
+} dl_status;
+
+typedef enum { DL_FP32 = 0, DL_BF16 = 1, DL_FP8 = 2 } dl_precision;
+
+/* flags */
+#define DL_FLAG_GATE 1u        /* skip tiles the tile gate predicts empty */
+
+typedef struct {
+    int32_t precision;          /* dl_precision of the 3x3 block convolutions      */
+    float threshold;            /* detection probability threshold, (0, 1); 0.3    */
+    float gain;                 /* photons per ADU; 0.5                            */
+    float offset;               /* camera offset in ADU; 100                       */
+    int32_t device;             /* HIP device ordinal; 0                           */
+    uint32_t flags;             /* DL_FLAG_*                                       */
+    uint64_t max_workspace_bytes; /* device workspace cap, 0 = no cap             */
+    int32_t tile_rows;          /* conv tile rows (0 = tuned/default)              */
+    int32_t reserved[7];
+} dl_config;
+
+/* One detected emitter, 32 bytes.  x_px = col + 0.5 + dx, y_px = row + 0.5 + dy
+ * (the frame spans [0, w) x [0, h) pixels, pixel centres at +0.5), z_nm = dz *
+ * z_scale, photons = ph * ph_scale, prob = sigmoid(logit). */
+typedef struct {
+    int32_t frame, row, col;
+    float x_px, y_px, z_nm, photons, prob;
+} dl_emitter;
+
+/* One region of interest of an uneven batch (device data). */
+typedef struct {
+    const uint16_t *data;       /* device pointer to the ROI's first pixel */
+    int32_t h, w;               /* 1 <= h, w                               */
+    int64_t row_stride;         /* elements between rows, >= w             */
+} dl_roi;
+
+typedef struct dl_net dl_net;
+
+/* Network description read from a weights blob (dl_inspect_weights). */
+typedef struct {
+    int32_t C, nblocks;
+    int32_t dilation[8];
+    float in_scale, z_scale, ph_scale;
+    int32_t receptive_radius;   /* 1 + 2 * sum(dilation): halo a tile needs     */
+    int64_t nparams;            /* FP32 values after the 64-byte header          */
+} dl_net_info;
+
+/* Library ABI version (DL_ABI_VERSION). */
+uint32_t dl_abi_version(void);
+
+/* Fill *cfg with the defaults listed in dl_config.  cfg must not be NULL. */
+int dl_default_config(dl_config *cfg);
+
+/* Create a network from a little-endian "DLW1" weights blob:
+ *   header (64 B): char magic[4] = "DLW1"; u32 version = 1; u32 C; u32 nblocks;
+ *   u32 dilation[8]; f32 in_scale; f32 z_scale; f32 ph_scale; u32 reserved;
+ *   then FP32 tensors: stem.w [C][1][3][3], stem.b [C], for each block
+ *   w1 [C][C][3][3], b1 [C], w2 [C][C][3][3], b2 [C]; head.w [5][C], head.b [5].
+ * Network (Sec. 3.2, Sec. 3.2.1): x = (ADU - offset) * gain * in_scale;
+ * a = ReLU(conv_1(x)); per block with dilation d: t = ReLU(conv_d(a)),
+ * a = ReLU(a + conv_d(t)); maps = head(a).  Supported: C in {16, 32, 48, 64},
+ * 1 <= nblocks <= 8, dilations 1..64.
+ * The blob is copied; the caller keeps ownership.  cfg may be NULL (defaults).
+ * *out receives a handle the caller frees with dl_destroy_net.
+ * Errors: DL_ERR_INVALID_ARG, DL_ERR_BAD_WEIGHTS, DL_ERR_UNSUPPORTED,
+ * DL_ERR_OOM, DL_ERR_DEVICE. */
+int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_net **out);
+
+/* Validate a weights blob and describe it, on the host only (no HIP call).
+ * Same checks and error codes as dl_create_net's blob validation. */
+int dl_inspect_weights(const void *weights, size_t nbytes, dl_net_info *info);
+
+/* Free every device and pinned allocation of the handle; NULL is a no-op. */
+void dl_destroy_net(dl_net *net);
+
+/* Text of the last error on this handle ("" if none); valid until the next
+ * call on the handle.  With net == NULL: the last error of dl_create_net or of
+ * a call that had no handle. */
+const char *dl_last_error(const dl_net *net);
+
+/* Change precision / threshold / gain / offset of an existing handle. */
+int dl_set_config(dl_net *net, const dl_config *cfg);
+
+/* Localize, device-resident (Sec. 2.2: frames already in GPU memory, only the
+ * post-processed coordinates are produced).
+ *   d_frames  device uint16 [n][h][w]
+ *   d_out     device dl_emitter[cap]; records in (frame, row, col) order; only
+ *             the first cap records are written
+ *   d_counts  device uint32[n + 1]: emitters per frame, then the total
+ * Work is queued on `stream`.  Overflow (total > cap) is visible as
+ * d_counts[n] > cap once the stream completes; the call itself returns DL_OK. */
+int dl_localize_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
+                       void *stream, dl_emitter *d_out, size_t cap, uint32_t *d_counts);
+
+/* Per-pixel maps of the network, device-resident: d_maps float [n][5][h][w]
+ * (logit, dx, dy, dz, photons before scaling).  For parity checks. */
+int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
+                   void *stream, float *d_maps);
+
+/* Localize host frames (synchronous).  The frames are copied host->device on
+ * the handle's copy stream (from the caller's buffer directly when it is
+ * pinned memory from dl_host_alloc, else through a pinned staging buffer),
+ * processed on the compute stream, and the records copied back.
+ *   frames  host uint16 [n][h][w]; out host dl_emitter[cap]; *count = total.
+ * Returns DL_ERR_CAPACITY (after writing the first cap records) if the total
+ * exceeds cap. */
+int dl_localize(dl_net *net, const uint16_t *frames, int n, int h, int w,
+                dl_emitter *out, size_t cap, size_t *count);
+
+/* Pipelined host localization of `nbatch` consecutive batches of n frames
+ * (frames host uint16 [nbatch][n][h][w]): batch k+1 is copied host->device on
+ * a side stream while batch k is processed (Sec. 2.2 preloading and
+ * pipelining).  Records of all batches are concatenated in order, with
+ * `frame` counted across batches.  overlap = 0 runs copy and compute
+ * serially (the reference workflow, for comparison). */
+int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w,
+                          int overlap, dl_emitter *out, size_t cap, size_t *count);
+
+/* Uneven batch of ROIs (device data; the dl_roi array itself is host memory).
+ * Same outputs as dl_localize_device with n = nroi. */
+int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream,
+                            dl_emitter *d_out, size_t cap, uint32_t *d_counts);
+
+/* Maps of an uneven ROI batch: ROI k's maps [5][h_k][w_k] start at
+ * d_maps + 5 * sum_{j<k} h_j * w_j. */
+int dl_maps_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, float *d_maps);
+
+/* Pinned host memory for frames (Sec. 2.2 "specified memory locations"). */
+int dl_host_alloc(size_t bytes, void **p);
+void dl_host_free(void *p);
+
+/* ---- stage timing ----
+ * With profiling on, every kernel launch of the path is bracketed by two HIP
+ * events recorded on the stream it runs on.  dl_profile_read waits for the
+ * recorded events and returns, per stage, the summed elapsed milliseconds and
+ * the number of launches since the previous read. */
+enum {
+    DL_STAGE_STEM = 0,       /* preprocessing + stem convolution              */
+    DL_STAGE_CONV = 1,       /* 3x3 block convolutions without the head       */
+    DL_STAGE_CONV_HEAD = 2,  /* last block convolution with the fused head    */
+    DL_STAGE_DETECT = 3,     /* threshold + 3x3 local maximum, masks + counts */
+    DL_STAGE_SCAN = 4,       /* row offsets and per-frame counts              */
+    DL_STAGE_EMIT = 5,       /* ordered emitter records                       */
+    DL_STAGE_GATE = 6,       /* tile gate inference and tile selection        */
+    DL_NSTAGES = 8
+};
+int dl_profile_enable(dl_net *net, int on);
+int dl_profile_read(dl_net *net, double *ms /*[DL_NSTAGES]*/, int64_t *launches /*[DL_NSTAGES]*/);
+
+/* ---- debug / parity entry points (device pointers, queued on stream) ---- */
+
+/* One 3x3 convolution layer of the handle's precision on an NHWC FP32 tensor:
+ * d_in float [n][h][w][C] -> d_out float [n][h][w][C],
+ * out = ReLU(conv_d(in; block `blk` conv `which` (0 or 1)) + (d_res ? res : 0)). */
+int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int n, int h, int w,
+                        int blk, int which, void *stream, float *d_out);
+
+/* Threshold + 3x3 local-maximum test on a logit plane stack: d_logit float
+ * [n][h][w] -> d_det uint8 [n][h][w] (1 = detected).  tau is the logit
+ * threshold (ln(p / (1 - p))). */
+int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, float tau,
+                    void *stream, uint8_t *d_det);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DLOC_H */

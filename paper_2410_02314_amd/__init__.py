@@ -1,0 +1,298 @@
+"""MI355X-native SMLM localization: Python binding of libdloc (ctypes).
+
+This module only marshals arguments: every step of the localization path runs
+in the HIP kernels of ``_build/libdloc.so`` (built by ``_build.build()``).
+PyTorch is used for device memory and streams.  If the library has not been
+built, importing this package raises ``ImportError`` -- there is no fallback.
+
+Names follow the C ABI in ``include/dloc.h``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_build", "libdloc.so")
+
+DL_OK = 0
+DL_ERR_INVALID_ARG = -1
+DL_ERR_BAD_WEIGHTS = -2
+DL_ERR_UNSUPPORTED = -3
+DL_ERR_OOM = -4
+DL_ERR_DEVICE = -5
+DL_ERR_CAPACITY = -6
+STATUS_NAMES = {0: "DL_OK", -1: "DL_ERR_INVALID_ARG", -2: "DL_ERR_BAD_WEIGHTS", -3: "DL_ERR_UNSUPPORTED",
+                -4: "DL_ERR_OOM", -5: "DL_ERR_DEVICE", -6: "DL_ERR_CAPACITY"}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+DL_FLAG_GATE = 1
+STAGES = ("stem", "conv", "conv_head", "detect", "scan", "emit", "gate")
+NSTAGES = 8
+
+EMITTER_DTYPE = np.dtype([("frame", "<i4"), ("row", "<i4"), ("col", "<i4"), ("x_px", "<f4"),
+                          ("y_px", "<f4"), ("z_nm", "<f4"), ("photons", "<f4"), ("prob", "<f4")])
+assert EMITTER_DTYPE.itemsize == 32
+
+
+class DLConfig(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("threshold", ctypes.c_float), ("gain", ctypes.c_float),
+                ("offset", ctypes.c_float), ("device", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("max_workspace_bytes", ctypes.c_uint64), ("tile_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class DLRoi(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("row_stride", ctypes.c_int64)]
+
+
+class DLNetInfo(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_int32), ("nblocks", ctypes.c_int32), ("dilation", ctypes.c_int32 * 8),
+                ("in_scale", ctypes.c_float), ("z_scale", ctypes.c_float), ("ph_scale", ctypes.c_float),
+                ("receptive_radius", ctypes.c_int32), ("nparams", ctypes.c_int64)]
+
+
+class DlocError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+def _load():
+    # The library must run on the same HIP runtime instance as PyTorch, whose
+    # device pointers and streams it receives.  PyTorch ships its own
+    # libamdhip64.so.7; loading torch first makes the dynamic loader resolve
+    # libdloc's dependency to that already-loaded copy.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libdloc.so is not built ({LIB_PATH}); run "
+                          "`python -m paper_2410_02314_amd._build` (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    sig = {
+        "dl_abi_version": (ctypes.c_uint32, []),
+        "dl_default_config": (I, [ctypes.POINTER(DLConfig)]),
+        "dl_create_net": (I, [P, Z, ctypes.POINTER(DLConfig), ctypes.POINTER(P)]),
+        "dl_inspect_weights": (I, [P, Z, ctypes.POINTER(DLNetInfo)]),
+        "dl_destroy_net": (None, [P]),
+        "dl_last_error": (ctypes.c_char_p, [P]),
+        "dl_set_config": (I, [P, ctypes.POINTER(DLConfig)]),
+        "dl_localize_device": (I, [P, P, I, I, I, P, P, Z, P]),
+        "dl_maps_device": (I, [P, P, I, I, I, P, P]),
+        "dl_localize": (I, [P, P, I, I, I, P, Z, ctypes.POINTER(Z)]),
+        "dl_localize_pipelined": (I, [P, P, I, I, I, I, I, P, Z, ctypes.POINTER(Z)]),
+        "dl_localize_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P, Z, P]),
+        "dl_maps_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P]),
+        "dl_host_alloc": (I, [Z, ctypes.POINTER(P)]),
+        "dl_host_free": (None, [P]),
+        "dl_debug_conv_layer": (I, [P, P, P, I, I, I, I, I, P, P]),
+        "dl_debug_detect": (I, [P, P, I, I, I, ctypes.c_float, P, P]),
+        "dl_profile_enable": (I, [P, I]),
+        "dl_profile_read": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    """The loaded ctypes library."""
+    return _lib
+
+
+def abi_version() -> int:
+    return int(_lib.dl_abi_version())
+
+
+def last_error(handle=None) -> str:
+    s = _lib.dl_last_error(handle)
+    return s.decode() if s else ""
+
+
+def _check(rc: int, handle=None):
+    if rc != DL_OK:
+        raise DlocError(rc, last_error(handle))
+
+
+def make_config(precision: str = "fp32", threshold: float = 0.3, gain: float = 0.5, offset: float = 100.0,
+                device: int = 0, flags: int = 0, max_workspace_bytes: int = 0, tile_rows: int = 0) -> DLConfig:
+    c = DLConfig()
+    _lib.dl_default_config(ctypes.byref(c))
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    c.threshold = threshold
+    c.gain = gain
+    c.offset = offset
+    c.device = device
+    c.flags = flags
+    c.max_workspace_bytes = max_workspace_bytes
+    c.tile_rows = tile_rows
+    return c
+
+
+def _ptr(t) -> int:
+    """Device (or host) address of a torch tensor / numpy array / int."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def inspect_weights(weights: bytes) -> dict:
+    """Validate a DLW1 blob on the host and describe the network (no GPU needed)."""
+    info = DLNetInfo()
+    buf = ctypes.create_string_buffer(bytes(weights), len(weights))
+    _check(_lib.dl_inspect_weights(buf, len(weights), ctypes.byref(info)))
+    return {"C": info.C, "nblocks": info.nblocks, "dilations": tuple(info.dilation[:info.nblocks]),
+            "in_scale": info.in_scale, "z_scale": info.z_scale, "ph_scale": info.ph_scale,
+            "receptive_radius": info.receptive_radius, "nparams": info.nparams}
+
+
+def create_net(weights: bytes, **cfg) -> "Net":
+    return Net(weights, **cfg)
+
+
+class Net:
+    """Handle of one network on one device (``dl_create_net``)."""
+
+    def __init__(self, weights: bytes, **cfg):
+        self.config = make_config(**cfg)
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(bytes(weights), len(weights))
+        _check(_lib.dl_create_net(buf, len(weights), ctypes.byref(self.config), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.dl_destroy_net(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_config(self, **cfg):
+        c = make_config(**cfg)
+        _check(_lib.dl_set_config(self.handle, ctypes.byref(c)), self.handle)
+        self.config = c
+
+    # ---- device-resident ----
+    def localize_device(self, frames, out, counts, stream=None) -> int:
+        """frames: cuda uint16 [n, h, w]; out: cuda tensor of cap*32 bytes; counts: cuda int32 [n+1]."""
+        n, h, w = frames.shape
+        cap = out.numel() * out.element_size() // 32
+        return self._rc(_lib.dl_localize_device(self.handle, _ptr(frames), n, h, w, _stream(stream),
+                                                _ptr(out), cap, _ptr(counts)))
+
+    def maps_device(self, frames, maps, stream=None) -> int:
+        n, h, w = frames.shape
+        return self._rc(_lib.dl_maps_device(self.handle, _ptr(frames), n, h, w, _stream(stream), _ptr(maps)))
+
+    def localize_rois_device(self, rois: Sequence, out, counts, stream=None) -> int:
+        """rois: sequence of cuda uint16 [h, w] tensors (rows may be strided)."""
+        arr = self._roi_array(rois)
+        cap = out.numel() * out.element_size() // 32
+        return self._rc(_lib.dl_localize_rois_device(self.handle, arr, len(rois), _stream(stream), _ptr(out),
+                                                     cap, _ptr(counts)))
+
+    def maps_rois_device(self, rois: Sequence, maps, stream=None) -> int:
+        arr = self._roi_array(rois)
+        return self._rc(_lib.dl_maps_rois_device(self.handle, arr, len(rois), _stream(stream), _ptr(maps)))
+
+    @staticmethod
+    def _roi_array(rois):
+        arr = (DLRoi * len(rois))()
+        for k, r in enumerate(rois):
+            arr[k].data = _ptr(r)
+            arr[k].h = r.shape[0]
+            arr[k].w = r.shape[1]
+            arr[k].row_stride = r.stride(0)
+        return arr
+
+    def debug_conv_layer(self, x, res, blk: int, which: int, out, stream=None) -> int:
+        n, h, w, _ = x.shape
+        return self._rc(_lib.dl_debug_conv_layer(self.handle, _ptr(x), _ptr(res), n, h, w, blk, which,
+                                                 _stream(stream), _ptr(out)))
+
+    def debug_detect(self, logit, tau: float, det, stream=None) -> int:
+        n, h, w = logit.shape
+        return self._rc(_lib.dl_debug_detect(self.handle, _ptr(logit), n, h, w, float(tau), _stream(stream),
+                                             _ptr(det)))
+
+    # ---- host ----
+    def localize(self, frames: np.ndarray, cap: Optional[int] = None) -> np.ndarray:
+        """Host frames uint16 [n, h, w] -> structured array of emitters (EMITTER_DTYPE)."""
+        return self.localize_pipelined(frames[None], overlap=False, cap=cap)
+
+    def localize_pipelined(self, frames: np.ndarray, overlap: bool = True, cap: Optional[int] = None) -> np.ndarray:
+        """Host frames uint16 [nbatch, n, h, w]; batches are copied on a side stream
+        while the previous batch is processed (overlap=True)."""
+        F = np.ascontiguousarray(frames, np.uint16)
+        nb, n, h, w = F.shape
+        if cap is None:
+            cap = max(1024, F.size // 16)
+        out = np.empty(cap, EMITTER_DTYPE)
+        cnt = ctypes.c_size_t()
+        rc = _lib.dl_localize_pipelined(self.handle, F.ctypes.data, nb, n, h, w, int(bool(overlap)),
+                                        out.ctypes.data, cap, ctypes.byref(cnt))
+        if rc == DL_ERR_CAPACITY:
+            return self.localize_pipelined(frames, overlap, cap=int(cnt.value))
+        _check(rc, self.handle)
+        return out[:cnt.value].copy()
+
+    def profile(self, on: bool = True):
+        self._rc(_lib.dl_profile_enable(self.handle, int(bool(on))))
+
+    def profile_read(self) -> dict:
+        """Per-stage {name: (total_ms, launches)} since the last read (waits for the events)."""
+        ms = (ctypes.c_double * NSTAGES)()
+        n = (ctypes.c_int64 * NSTAGES)()
+        self._rc(_lib.dl_profile_read(self.handle, ms, n))
+        return {STAGES[i]: (ms[i], n[i]) for i in range(len(STAGES))}
+
+    def _rc(self, rc):
+        _check(rc, self.handle)
+        return rc
+
+
+def emitters_from_device(out, counts_total: int) -> np.ndarray:
+    """Copy the first ``counts_total`` records of a device record buffer to a numpy structured array."""
+    raw = out.reshape(-1).view(__import__("torch").uint8)[: counts_total * 32].cpu().numpy()
+    return raw.view(EMITTER_DTYPE).copy()
+
+
+def host_alloc(nbytes: int) -> int:
+    p = ctypes.c_void_p()
+    _check(_lib.dl_host_alloc(nbytes, ctypes.byref(p)))
+    return p.value
+
+
+def host_free(p: int):
+    _lib.dl_host_free(p)

@@ -1,0 +1,866 @@
+// C ABI of libdloc: argument validation, weights parsing, device workspace,
+// streams, and the launch sequence of the localization path.
+//
+// Launch sequence for a batch (paper Sec. 2.2: everything after the copy of
+// the preloaded frames stays on the GPU):
+//   stem (preprocess + 3x3 conv 1->C) -> per block: conv_d, conv_d + residual
+//   (last one with the 1x1 head fused, writing the 5 planar maps) ->
+//   detect (threshold + 3x3 local max, 64-bit masks + per-row counts) ->
+//   scan (row offsets, per-frame counts) -> emit (ordered records).
+#include "dloc_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace dloc;
+
+namespace {
+
+constexpr int DESC_SLOTS = 8;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+thread_local std::string g_err;   // errors with no handle
+
+size_t param_count(int C, int nb) { return (size_t)C * 9 + C + (size_t)nb * 2 * ((size_t)C * C * 9 + C) + 5 * (size_t)C + 5; }
+
+}  // namespace
+
+struct dl_net {
+    dl_config cfg{};
+    int dev = 0, ncu = 256;
+    int C = 0, nb = 0;
+    int dil[8] = {0};
+    float in_scale = 0.f, z_scale = 0.f, ph_scale = 0.f;
+    std::vector<float> params;
+
+    float *d_stem = nullptr;        // w [C][9] then b [C]
+    float *d_head = nullptr;        // w [5][C] then b [5]
+    float *d_bias = nullptr;        // [nb][2][C]
+    void *d_wpk = nullptr;          // packed conv weights [nb][2][...]
+    size_t wpk_stride = 0;
+    int packed_precision = -1;
+
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    FrameDesc *h_desc = nullptr;    // pinned, DESC_SLOTS * desc_cap
+    FrameDesc *d_desc = nullptr;    // device, DESC_SLOTS * desc_cap
+    int desc_cap = 0;
+    hipEvent_t desc_ev[DESC_SLOTS] = {};
+    int desc_next = 0;
+
+    hipStream_t copy_stream = nullptr, compute_stream = nullptr;
+    std::string err;
+
+    // per-stage timing with HIP events recorded on the launch stream
+    bool profiling = false;
+    struct Ev { int stage; hipEvent_t a, b; };
+    std::vector<Ev> prof_pending;
+    std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+int fail(dl_net *net, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (net) net->err = buf; else g_err = buf;
+    return code;
+}
+
+#define HIPCHK(net, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((net), DL_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_all(const float *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+int check_config(dl_net *net, const dl_config *c)
+{
+    if (c->precision < DL_FP32 || c->precision > DL_FP8)
+        return fail(net, DL_ERR_INVALID_ARG, "precision %d is not one of DL_FP32/DL_BF16/DL_FP8", c->precision);
+    if (!(c->threshold > 0.f && c->threshold < 1.f))
+        return fail(net, DL_ERR_INVALID_ARG, "threshold must lie in (0, 1)");
+    if (!std::isfinite(c->gain) || !(c->gain > 0.f))
+        return fail(net, DL_ERR_INVALID_ARG, "gain must be finite and > 0");
+    if (!std::isfinite(c->offset)) return fail(net, DL_ERR_INVALID_ARG, "offset must be finite");
+    if (c->device < 0) return fail(net, DL_ERR_INVALID_ARG, "device must be >= 0");
+    if (!(c->tile_rows == 0 || c->tile_rows == 4 || c->tile_rows == 8 || c->tile_rows == 16))
+        return fail(net, DL_ERR_INVALID_ARG, "tile_rows must be 0, 4, 8 or 16");
+    if (c->flags & ~DL_FLAG_GATE) return fail(net, DL_ERR_INVALID_ARG, "unknown flag bits");
+    return DL_OK;
+}
+
+int tile_rows_of(const dl_net *net) { return net->cfg.tile_rows ? net->cfg.tile_rows : 8; }
+
+// Build the frame descriptors of a uniform batch or a ROI list.
+void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, const uint16_t *const *data,
+                    const int64_t *strides, std::vector<FrameDesc> &fd, Geometry &g)
+{
+    const int rows = tile_rows_of(net);
+    fd.resize(n);
+    g = Geometry{};
+    g.nf = n;
+    g.tile_rows = rows;
+    for (int f = 0; f < n; ++f) {
+        FrameDesc &d = fd[f];
+        d.data = data[f];
+        d.stride = strides[f];
+        d.h = hs[f];
+        d.w = ws_[f];
+        d.px_off = g.total_px;
+        d.row_start = g.total_rows;
+        d.tile_start = g.total_tiles;
+        d.mask_start = g.total_words;
+        d.tiles_x = (d.w + TILE_COLS - 1) / TILE_COLS;
+        d.words = (d.w + 63) / 64;
+        g.total_px += (int64_t)d.h * d.w;
+        g.total_rows += d.h;
+        g.total_tiles += (int64_t)((d.h + rows - 1) / rows) * d.tiles_x;
+        g.total_words += (int64_t)d.h * d.words;
+        if (d.w > g.maxw) g.maxw = d.w;
+    }
+}
+
+struct Plan {
+    size_t act0 = 0, act1 = 0, maps = 0, mask = 0, rc = 0, roff = 0, total = 0;
+};
+
+Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
+{
+    const size_t esz = net->cfg.precision == DL_FP32 ? 4 : 2;
+    Plan p;
+    size_t o = 0;
+    p.act0 = o; o = align_up(o + (size_t)g.total_px * net->C * esz);
+    p.act1 = o; o = align_up(o + (size_t)g.total_px * net->C * esz);
+    p.maps = o; if (!ext_maps) o = align_up(o + (size_t)g.total_px * 5 * 4);
+    p.mask = o; o = align_up(o + (size_t)g.total_words * 8);
+    p.rc = o; o = align_up(o + (size_t)g.total_rows * 4);
+    p.roff = o; o = align_up(o + (size_t)(g.total_rows + 1) * 4);
+    p.total = o;
+    return p;
+}
+
+int ensure_workspace(dl_net *net, size_t bytes, hipStream_t s)
+{
+    if (bytes <= net->ws_bytes) return DL_OK;
+    if (net->cfg.max_workspace_bytes && bytes > net->cfg.max_workspace_bytes)
+        return fail(net, DL_ERR_OOM, "workspace of %zu bytes exceeds max_workspace_bytes %llu", bytes,
+                    (unsigned long long)net->cfg.max_workspace_bytes);
+    if (net->ws) {
+        HIPCHK(net, hipStreamSynchronize(s));
+        HIPCHK(net, hipDeviceSynchronize());
+        HIPCHK(net, hipFree(net->ws));
+        net->ws = nullptr;
+        net->ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&net->ws, bytes);
+    if (e != hipSuccess) {
+        net->ws = nullptr;
+        (void)hipGetLastError();
+        return fail(net, DL_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    net->ws_bytes = bytes;
+    return DL_OK;
+}
+
+// Upload descriptors into the next ring slot; returns the device pointer.
+int upload_desc(dl_net *net, const std::vector<FrameDesc> &fd, hipStream_t s, FrameDesc **out)
+{
+    const int n = (int)fd.size();
+    if (n > net->desc_cap) {
+        for (int i = 0; i < DESC_SLOTS; ++i)
+            if (net->desc_ev[i]) HIPCHK(net, hipEventSynchronize(net->desc_ev[i]));
+        if (net->h_desc) HIPCHK(net, hipHostFree(net->h_desc));
+        if (net->d_desc) HIPCHK(net, hipFree(net->d_desc));
+        net->h_desc = nullptr;
+        net->d_desc = nullptr;
+        int cap = 64;
+        while (cap < n) cap *= 2;
+        HIPCHK(net, hipHostMalloc((void **)&net->h_desc, sizeof(FrameDesc) * cap * DESC_SLOTS, hipHostMallocDefault));
+        HIPCHK(net, hipMalloc((void **)&net->d_desc, sizeof(FrameDesc) * cap * DESC_SLOTS));
+        net->desc_cap = cap;
+    }
+    const int slot = net->desc_next;
+    net->desc_next = (slot + 1) % DESC_SLOTS;
+    HIPCHK(net, hipEventSynchronize(net->desc_ev[slot]));
+    FrameDesc *h = net->h_desc + (size_t)slot * net->desc_cap;
+    FrameDesc *d = net->d_desc + (size_t)slot * net->desc_cap;
+    std::memcpy(h, fd.data(), sizeof(FrameDesc) * n);
+    HIPCHK(net, hipMemcpyAsync(d, h, sizeof(FrameDesc) * n, hipMemcpyHostToDevice, s));
+    *out = d;
+    return slot;
+}
+
+int ensure_packed(dl_net *net)
+{
+    if (net->packed_precision == net->cfg.precision) return DL_OK;
+    if (net->cfg.precision != DL_FP32 && net->cfg.precision != DL_BF16)
+        return fail(net, DL_ERR_UNSUPPORTED, "precision %d is not available in this build", net->cfg.precision);
+    const int C = net->C;
+    const size_t per = conv_packed_bytes(C, net->cfg.precision);
+    const size_t stride = align_up(per);
+    std::vector<char> host(stride * net->nb * 2);
+    const float *p = net->params.data() + (size_t)C * 9 + C;
+    for (int b = 0; b < net->nb; ++b)
+        for (int k = 0; k < 2; ++k) {
+            pack_conv_weights(C, net->cfg.precision, p, host.data() + (size_t)(b * 2 + k) * stride);
+            p += (size_t)C * C * 9 + C;
+        }
+    if (net->d_wpk) {
+        HIPCHK(net, hipDeviceSynchronize());
+        HIPCHK(net, hipFree(net->d_wpk));
+        net->d_wpk = nullptr;
+    }
+    HIPCHK(net, hipMalloc(&net->d_wpk, host.size()));
+    HIPCHK(net, hipMemcpy(net->d_wpk, host.data(), host.size(), hipMemcpyHostToDevice));
+    net->wpk_stride = stride;
+    net->packed_precision = net->cfg.precision;
+    return DL_OK;
+}
+
+// Profiling: when enabled, every launch of the path is bracketed by two HIP
+// events on its stream; dl_profile_read sums the elapsed times per stage.
+hipEvent_t pool_event(dl_net *net)
+{
+    if (!net->ev_pool.empty()) {
+        hipEvent_t e = net->ev_pool.back();
+        net->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct StageTimer {
+    dl_net *net;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(dl_net *n, int st, hipStream_t str) : net(n), stage(st), s(str)
+    {
+        if (!net->profiling) return;
+        a = pool_event(net);
+        b = pool_event(net);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~StageTimer()
+    {
+        if (!net->profiling || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        net->prof_pending.push_back({stage, a, b});
+    }
+};
+
+// Run stem + blocks (+ fused head into maps).
+int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, float *maps, hipStream_t s)
+{
+    const int C = net->C;
+    void *a0 = net->ws + p.act0;
+    void *a1 = net->ws + p.act1;
+    const float scale = net->cfg.gain * net->in_scale;
+    {
+        StageTimer t(net, DL_STAGE_STEM, s);
+        HIPCHK(net, launch_stem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset, scale, a0,
+                                net->cfg.precision != DL_FP32, s));
+    }
+    const int maxg = conv_max_grid(C, net->cfg.precision, g.tile_rows, net->ncu);
+    int grid = (int)std::min<int64_t>(g.total_tiles, maxg);
+    grid = std::max(8, grid / 8 * 8);
+    for (int b = 0; b < net->nb; ++b) {
+        ConvArgs a{};
+        a.fd = d_fd;
+        a.d = net->dil[b];
+        a.in = a0;
+        a.out = a1;
+        a.res = nullptr;
+        a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2) * net->wpk_stride;
+        a.bias = net->d_bias + (size_t)(b * 2) * C;
+        {
+            StageTimer t(net, DL_STAGE_CONV, s);
+            HIPCHK(net, launch_conv(C, net->cfg.precision, a, g, grid, s));
+        }
+        a.in = a1;
+        a.res = a0;
+        a.out = a0;
+        a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2 + 1) * net->wpk_stride;
+        a.bias = net->d_bias + (size_t)(b * 2 + 1) * C;
+        if (b == net->nb - 1) {
+            a.head = net->d_head;
+            a.maps = maps;
+            a.out = nullptr;
+        }
+        StageTimer t(net, b == net->nb - 1 ? DL_STAGE_CONV_HEAD : DL_STAGE_CONV, s);
+        HIPCHK(net, launch_conv(C, net->cfg.precision, a, g, grid, s));
+    }
+    return DL_OK;
+}
+
+int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, const float *maps,
+             dl_emitter *d_out, size_t cap, uint32_t *d_counts, hipStream_t s)
+{
+    const float thr = net->cfg.threshold;
+    const float tau = (float)std::log((double)thr / (1.0 - (double)thr));
+    uint64_t *mask = reinterpret_cast<uint64_t *>(net->ws + p.mask);
+    uint32_t *rc = reinterpret_cast<uint32_t *>(net->ws + p.rc);
+    uint32_t *roff = reinterpret_cast<uint32_t *>(net->ws + p.roff);
+    {
+        StageTimer t(net, DL_STAGE_DETECT, s);
+        HIPCHK(net, launch_detect_mask(maps, 5, d_fd, g, tau, mask, rc, s));
+    }
+    {
+        StageTimer t(net, DL_STAGE_SCAN, s);
+        HIPCHK(net, launch_scan(rc, d_fd, g, roff, d_counts, s));
+    }
+    {
+        StageTimer t(net, DL_STAGE_EMIT, s);
+        HIPCHK(net, launch_emit(maps, mask, roff, d_fd, g, net->z_scale, net->ph_scale, d_out, cap, s));
+    }
+    return DL_OK;
+}
+
+int check_uniform(dl_net *net, const void *frames, int n, int h, int w)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (!frames) return fail(net, DL_ERR_INVALID_ARG, "frames is NULL");
+    if (reinterpret_cast<uintptr_t>(frames) % 2) return fail(net, DL_ERR_INVALID_ARG, "frames must be 2-byte aligned");
+    if (n <= 0 || h <= 0 || w <= 0) return fail(net, DL_ERR_INVALID_ARG, "n, h, w must be > 0 (got %d, %d, %d)", n, h, w);
+    if ((int64_t)h * w > (int64_t)1 << 28) return fail(net, DL_ERR_UNSUPPORTED, "frame of %d x %d pixels is too large", h, w);
+    if ((int64_t)n * h > (int64_t)1 << 30) return fail(net, DL_ERR_UNSUPPORTED, "too many rows in the batch");
+    return DL_OK;
+}
+
+int set_device(dl_net *net) { HIPCHK(net, hipSetDevice(net->dev)); return DL_OK; }
+
+int uniform_geometry(dl_net *net, const uint16_t *d_frames, int n, int h, int w, std::vector<FrameDesc> &fd, Geometry &g)
+{
+    std::vector<int> hs(n, h), ws(n, w);
+    std::vector<const uint16_t *> ptr(n);
+    std::vector<int64_t> st(n, w);
+    for (int f = 0; f < n; ++f) ptr[f] = d_frames ? d_frames + (size_t)f * h * w : nullptr;
+    build_geometry(net, n, hs.data(), ws.data(), ptr.data(), st.data(), fd, g);
+    return DL_OK;
+}
+
+int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g, hipStream_t s,
+                  dl_emitter *d_out, size_t cap, uint32_t *d_counts, float *ext_maps)
+{
+    int rc;
+    if ((rc = set_device(net))) return rc;
+    if ((rc = ensure_packed(net))) return rc;
+    const Plan p = make_plan(net, g, ext_maps != nullptr);
+    if ((rc = ensure_workspace(net, p.total, s))) return rc;
+    FrameDesc *d_fd = nullptr;
+    const int slot = upload_desc(net, fd, s, &d_fd);
+    if (slot < 0) return slot;
+    float *maps = ext_maps ? ext_maps : reinterpret_cast<float *>(net->ws + p.maps);
+    if ((rc = run_net(net, d_fd, g, p, maps, s))) return rc;
+    if (d_out || d_counts)
+        if ((rc = run_post(net, d_fd, g, p, maps, d_out, cap, d_counts, s))) return rc;
+    HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
+    return DL_OK;
+}
+
+}  // namespace
+
+// ============================================================== public ABI
+extern "C" {
+
+uint32_t dl_abi_version(void) { return DL_ABI_VERSION; }
+
+int dl_default_config(dl_config *cfg)
+{
+    if (!cfg) return fail(nullptr, DL_ERR_INVALID_ARG, "cfg is NULL");
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->precision = DL_FP32;
+    cfg->threshold = 0.3f;
+    cfg->gain = 0.5f;
+    cfg->offset = 100.f;
+    return DL_OK;
+}
+
+const char *dl_last_error(const dl_net *net) { return net ? net->err.c_str() : g_err.c_str(); }
+
+static int parse_weights(const void *weights, size_t nbytes, dl_net_info *info, std::vector<float> *params)
+{
+    if (!weights) return fail(nullptr, DL_ERR_INVALID_ARG, "weights is NULL");
+    if (nbytes < 64) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "weights blob of %zu bytes is shorter than its header", nbytes);
+    const unsigned char *b = static_cast<const unsigned char *>(weights);
+    if (std::memcmp(b, "DLW1", 4) != 0) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "bad magic (expected DLW1)");
+    // header: magic, u32 version, u32 C, u32 nblocks, u32 dilation[8], f32 in_scale,
+    // f32 z_scale, f32 ph_scale, u32 reserved
+    uint32_t hdr[11];
+    std::memcpy(hdr, b + 4, sizeof hdr);
+    const uint32_t version = hdr[0], C = hdr[1], nb = hdr[2];
+    float sc[3];
+    std::memcpy(sc, b + 4 + 11 * 4, sizeof sc);
+    if (version != 1) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "unsupported weights version %u", version);
+    if (nb < 1 || nb > 8) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "nblocks %u outside 1..8", nb);
+    if (!(C == 16 || C == 32 || C == 48 || C == 64))
+        return fail(nullptr, DL_ERR_UNSUPPORTED, "C = %u not supported (16, 32, 48 or 64)", C);
+    for (uint32_t k = 0; k < nb; ++k)
+        if (hdr[3 + k] < 1 || hdr[3 + k] > 64) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "dilation %u of block %u outside 1..64", hdr[3 + k], k);
+    if (!finite_all(sc, 3) || !(sc[0] > 0.f)) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "bad in_scale/z_scale/ph_scale");
+    const size_t np = param_count((int)C, (int)nb);
+    if (nbytes != 64 + np * 4)
+        return fail(nullptr, DL_ERR_BAD_WEIGHTS, "blob is %zu bytes, expected %zu for C=%u, %u blocks", nbytes, 64 + np * 4, C, nb);
+    std::vector<float> tmp(np);
+    std::memcpy(tmp.data(), b + 64, np * 4);
+    if (!finite_all(tmp.data(), np)) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "weights contain NaN or Inf");
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->C = (int32_t)C;
+        info->nblocks = (int32_t)nb;
+        for (uint32_t k = 0; k < nb; ++k) info->dilation[k] = (int32_t)hdr[3 + k];
+        info->in_scale = sc[0];
+        info->z_scale = sc[1];
+        info->ph_scale = sc[2];
+        info->nparams = (int64_t)np;
+        int R = 1;
+        for (uint32_t k = 0; k < nb; ++k) R += 2 * (int)hdr[3 + k];
+        info->receptive_radius = R;
+    }
+    if (params) *params = std::move(tmp);
+    return DL_OK;
+}
+
+int dl_inspect_weights(const void *weights, size_t nbytes, dl_net_info *info)
+{
+    if (!info) return fail(nullptr, DL_ERR_INVALID_ARG, "info is NULL");
+    return parse_weights(weights, nbytes, info, nullptr);
+}
+
+int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_net **out)
+{
+    if (!out) return fail(nullptr, DL_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!weights) return fail(nullptr, DL_ERR_INVALID_ARG, "weights is NULL");
+    dl_config c;
+    dl_default_config(&c);
+    if (cfg) c = *cfg;
+    int rc = check_config(nullptr, &c);
+    if (rc) return rc;
+    dl_net_info info;
+    std::vector<float> params;
+    if ((rc = parse_weights(weights, nbytes, &info, &params))) return rc;
+    const uint32_t C = (uint32_t)info.C, nb = (uint32_t)info.nblocks;
+
+    // ---- arguments are valid; device work starts here ----
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(nullptr, DL_ERR_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+    if (c.device >= ndev) return fail(nullptr, DL_ERR_INVALID_ARG, "device %d >= device count %d", c.device, ndev);
+
+    dl_net *net = new (std::nothrow) dl_net();
+    if (!net) return fail(nullptr, DL_ERR_OOM, "out of host memory");
+    net->cfg = c;
+    net->dev = c.device;
+    net->C = (int)C;
+    net->nb = (int)nb;
+    for (uint32_t k = 0; k < nb; ++k) net->dil[k] = info.dilation[k];
+    net->in_scale = info.in_scale;
+    net->z_scale = info.z_scale;
+    net->ph_scale = info.ph_scale;
+    net->params = std::move(params);
+
+    auto bail = [&](int code) {
+        g_err = net->err;
+        dl_destroy_net(net);
+        return code;
+    };
+    if ((rc = set_device(net))) return bail(rc);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, net->dev) == hipSuccess) net->ncu = prop.multiProcessorCount;
+    const float *p = net->params.data();
+    const size_t nstem = (size_t)C * 9 + C, nhead = 5 * (size_t)C + 5;
+    if (hipMalloc(&net->d_stem, nstem * 4) != hipSuccess || hipMalloc(&net->d_head, nhead * 4) != hipSuccess ||
+        hipMalloc(&net->d_bias, (size_t)nb * 2 * C * 4) != hipSuccess)
+        return bail(fail(net, DL_ERR_OOM, "hipMalloc of weights failed"));
+    if (hipMemcpy(net->d_stem, p, nstem * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net->d_head, p + net->params.size() - nhead, nhead * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(net, DL_ERR_DEVICE, "weight upload failed"));
+    {
+        std::vector<float> bias((size_t)nb * 2 * C);
+        const float *q = p + nstem;
+        for (uint32_t k = 0; k < nb; ++k)
+            for (int j = 0; j < 2; ++j) {
+                q += (size_t)C * C * 9;
+                std::memcpy(bias.data() + (size_t)(k * 2 + j) * C, q, C * 4);
+                q += C;
+            }
+        if (hipMemcpy(net->d_bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(net, DL_ERR_DEVICE, "bias upload failed"));
+    }
+    for (int i = 0; i < DESC_SLOTS; ++i)
+        if (hipEventCreateWithFlags(&net->desc_ev[i], hipEventDisableTiming) != hipSuccess)
+            return bail(fail(net, DL_ERR_DEVICE, "hipEventCreate failed"));
+    if (hipStreamCreateWithFlags(&net->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&net->compute_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(net, DL_ERR_DEVICE, "hipStreamCreate failed"));
+    if ((rc = ensure_packed(net))) return bail(rc);
+    *out = net;
+    return DL_OK;
+}
+
+void dl_destroy_net(dl_net *net)
+{
+    if (!net) return;
+    (void)hipSetDevice(net->dev);
+    (void)hipDeviceSynchronize();
+    for (auto &e : net->prof_pending) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (auto e : net->ev_pool) (void)hipEventDestroy(e);
+    if (net->ws) (void)hipFree(net->ws);
+    if (net->d_stem) (void)hipFree(net->d_stem);
+    if (net->d_head) (void)hipFree(net->d_head);
+    if (net->d_bias) (void)hipFree(net->d_bias);
+    if (net->d_wpk) (void)hipFree(net->d_wpk);
+    if (net->h_desc) (void)hipHostFree(net->h_desc);
+    if (net->d_desc) (void)hipFree(net->d_desc);
+    for (int i = 0; i < DESC_SLOTS; ++i)
+        if (net->desc_ev[i]) (void)hipEventDestroy(net->desc_ev[i]);
+    if (net->copy_stream) (void)hipStreamDestroy(net->copy_stream);
+    if (net->compute_stream) (void)hipStreamDestroy(net->compute_stream);
+    delete net;
+}
+
+int dl_set_config(dl_net *net, const dl_config *cfg)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (!cfg) return fail(net, DL_ERR_INVALID_ARG, "cfg is NULL");
+    int rc = check_config(net, cfg);
+    if (rc) return rc;
+    if (cfg->device != net->cfg.device) return fail(net, DL_ERR_INVALID_ARG, "device cannot change");
+    const int old = net->cfg.precision;
+    net->cfg = *cfg;
+    if (cfg->precision != old) {
+        if ((rc = set_device(net))) return rc;
+        if ((rc = ensure_packed(net))) {
+            net->cfg.precision = old;
+            return rc;
+        }
+    }
+    return DL_OK;
+}
+
+int dl_localize_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream,
+                       dl_emitter *d_out, size_t cap, uint32_t *d_counts)
+{
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
+    if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_counts) % 4)
+        return fail(net, DL_ERR_INVALID_ARG, "d_out must be 16-byte and d_counts 4-byte aligned");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, d_frames, n, h, w, fd, g);
+    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr);
+}
+
+int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, float *d_maps)
+{
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (!d_maps) return fail(net, DL_ERR_INVALID_ARG, "d_maps is NULL");
+    if (reinterpret_cast<uintptr_t>(d_maps) % 4) return fail(net, DL_ERR_INVALID_ARG, "d_maps must be 4-byte aligned");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, d_frames, n, h, w, fd, g);
+    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), nullptr, 0, nullptr, d_maps);
+}
+
+static int check_rois(dl_net *net, const dl_roi *rois, int nroi)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (!rois || nroi <= 0) return fail(net, DL_ERR_INVALID_ARG, "rois is NULL or nroi <= 0");
+    int64_t rows = 0;
+    for (int k = 0; k < nroi; ++k) {
+        const dl_roi &r = rois[k];
+        if (!r.data || reinterpret_cast<uintptr_t>(r.data) % 2) return fail(net, DL_ERR_INVALID_ARG, "roi %d: NULL or misaligned data", k);
+        if (r.h <= 0 || r.w <= 0) return fail(net, DL_ERR_INVALID_ARG, "roi %d: h and w must be > 0", k);
+        if (r.row_stride < r.w) return fail(net, DL_ERR_INVALID_ARG, "roi %d: row_stride < w", k);
+        if ((int64_t)r.h * r.w > (int64_t)1 << 28) return fail(net, DL_ERR_UNSUPPORTED, "roi %d too large", k);
+        rows += r.h;
+    }
+    if (rows > (int64_t)1 << 30) return fail(net, DL_ERR_UNSUPPORTED, "too many rows in the batch");
+    return DL_OK;
+}
+
+static void roi_geometry(dl_net *net, const dl_roi *rois, int nroi, std::vector<FrameDesc> &fd, Geometry &g)
+{
+    std::vector<int> hs(nroi), ws(nroi);
+    std::vector<const uint16_t *> ptr(nroi);
+    std::vector<int64_t> st(nroi);
+    for (int k = 0; k < nroi; ++k) {
+        hs[k] = rois[k].h;
+        ws[k] = rois[k].w;
+        ptr[k] = rois[k].data;
+        st[k] = rois[k].row_stride;
+    }
+    build_geometry(net, nroi, hs.data(), ws.data(), ptr.data(), st.data(), fd, g);
+}
+
+int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, dl_emitter *d_out,
+                            size_t cap, uint32_t *d_counts)
+{
+    int rc = check_rois(net, rois, nroi);
+    if (rc) return rc;
+    if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
+    if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    roi_geometry(net, rois, nroi, fd, g);
+    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr);
+}
+
+int dl_maps_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, float *d_maps)
+{
+    int rc = check_rois(net, rois, nroi);
+    if (rc) return rc;
+    if (!d_maps) return fail(net, DL_ERR_INVALID_ARG, "d_maps is NULL");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    roi_geometry(net, rois, nroi, fd, g);
+    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), nullptr, 0, nullptr, d_maps);
+}
+
+int dl_host_alloc(size_t bytes, void **p)
+{
+    if (!p) return fail(nullptr, DL_ERR_INVALID_ARG, "p is NULL");
+    *p = nullptr;
+    if (bytes == 0) return fail(nullptr, DL_ERR_INVALID_ARG, "bytes is 0");
+    hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(nullptr, DL_ERR_OOM, "hipHostMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return DL_OK;
+}
+
+void dl_host_free(void *p)
+{
+    if (p) (void)hipHostFree(p);
+}
+
+static bool is_pinned(const void *p)
+{
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeHost;
+}
+
+int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w, int overlap,
+                          dl_emitter *out, size_t cap, size_t *count)
+{
+    int rc = check_uniform(net, frames, n, h, w);
+    if (rc) return rc;
+    if (nbatch <= 0) return fail(net, DL_ERR_INVALID_ARG, "nbatch must be > 0");
+    if (!count) return fail(net, DL_ERR_INVALID_ARG, "count is NULL");
+    if (cap > 0 && !out) return fail(net, DL_ERR_INVALID_ARG, "out is NULL with cap > 0");
+    if ((rc = set_device(net))) return rc;
+    *count = 0;
+    const size_t fbytes = (size_t)n * h * w * 2;
+    const bool pinned = is_pinned(frames);
+    // two device frame buffers + two pinned staging buffers (when needed),
+    // device outputs per batch
+    uint16_t *d_frames[2] = {nullptr, nullptr};
+    uint16_t *h_stage[2] = {nullptr, nullptr};
+    dl_emitter *d_out = nullptr;
+    uint32_t *d_counts = nullptr;
+    hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_used[2] = {nullptr, nullptr};
+    const size_t cap_dev = std::max<size_t>(cap, 1);
+    std::vector<uint32_t> h_counts((size_t)(n + 1) * nbatch);
+    int result = DL_OK;
+    auto cleanup = [&]() {
+        (void)hipDeviceSynchronize();
+        for (int i = 0; i < 2; ++i) {
+            if (d_frames[i]) (void)hipFree(d_frames[i]);
+            if (h_stage[i]) (void)hipHostFree(h_stage[i]);
+            if (ev_copied[i]) (void)hipEventDestroy(ev_copied[i]);
+            if (ev_used[i]) (void)hipEventDestroy(ev_used[i]);
+        }
+        if (d_out) (void)hipFree(d_out);
+        if (d_counts) (void)hipFree(d_counts);
+    };
+#define PCHK(expr)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            result = fail(net, DL_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+            cleanup();                                                                              \
+            return result;                                                                          \
+        }                                                                                           \
+    } while (0)
+    for (int i = 0; i < 2; ++i) {
+        PCHK(hipMalloc(&d_frames[i], fbytes));
+        if (!pinned) PCHK(hipHostMalloc((void **)&h_stage[i], fbytes, hipHostMallocDefault));
+        PCHK(hipEventCreateWithFlags(&ev_copied[i], hipEventDisableTiming));
+        PCHK(hipEventCreateWithFlags(&ev_used[i], hipEventDisableTiming));
+    }
+    PCHK(hipMalloc(&d_out, cap_dev * sizeof(dl_emitter)));
+    PCHK(hipMalloc(&d_counts, h_counts.size() * 4));
+    hipStream_t cs = net->compute_stream, xs = overlap ? net->copy_stream : net->compute_stream;
+    size_t written = 0;
+    uint32_t *hc = h_counts.data();
+    std::vector<dl_emitter> tmp;
+    for (int k = 0; k < nbatch; ++k) {
+        const int buf = k & 1;
+        const uint16_t *src = frames + (size_t)k * n * h * w;
+        PCHK(hipEventSynchronize(ev_used[buf]));     // the compute that read this buffer is done
+        if (!pinned) {
+            std::memcpy(h_stage[buf], src, fbytes);
+            src = h_stage[buf];
+        }
+        PCHK(hipMemcpyAsync(d_frames[buf], src, fbytes, hipMemcpyHostToDevice, xs));
+        PCHK(hipEventRecord(ev_copied[buf], xs));
+        PCHK(hipStreamWaitEvent(cs, ev_copied[buf], 0));
+        std::vector<FrameDesc> fd;
+        Geometry g;
+        uniform_geometry(net, d_frames[buf], n, h, w, fd, g);
+        const size_t room = written < cap ? cap - written : 0;
+        rc = localize_geom(net, fd, g, cs, room ? d_out : nullptr, room, d_counts + (size_t)k * (n + 1), nullptr);
+        if (rc) { cleanup(); return rc; }
+        PCHK(hipEventRecord(ev_used[buf], cs));
+        // results of this batch: counts then records (compute stream order)
+        PCHK(hipMemcpyAsync(hc + (size_t)k * (n + 1), d_counts + (size_t)k * (n + 1), (n + 1) * 4, hipMemcpyDeviceToHost, cs));
+        PCHK(hipStreamSynchronize(cs));
+        const uint32_t tot = hc[(size_t)k * (n + 1) + n];
+        const size_t take = std::min<size_t>(tot, room);
+        if (take) {
+            PCHK(hipMemcpy(out + written, d_out, take * sizeof(dl_emitter), hipMemcpyDeviceToHost));
+            for (size_t r = 0; r < take; ++r) out[written + r].frame += k * n;
+        }
+        written += take;
+        *count += tot;
+    }
+    cleanup();
+#undef PCHK
+    if (*count > cap) return fail(net, DL_ERR_CAPACITY, "%zu emitters exceed capacity %zu", *count, cap);
+    return DL_OK;
+}
+
+int dl_localize(dl_net *net, const uint16_t *frames, int n, int h, int w, dl_emitter *out, size_t cap, size_t *count)
+{
+    return dl_localize_pipelined(net, frames, 1, n, h, w, 0, out, cap, count);
+}
+
+int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int n, int h, int w, int blk,
+                        int which, void *stream, float *d_out)
+{
+    int rc = check_uniform(net, d_in, n, h, w);
+    if (rc) return rc;
+    if (!d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL");
+    if (blk < 0 || blk >= net->nb || which < 0 || which > 1) return fail(net, DL_ERR_INVALID_ARG, "bad blk/which");
+    if (net->cfg.precision != DL_FP32) return fail(net, DL_ERR_UNSUPPORTED, "debug conv layer takes FP32 tensors; set precision FP32");
+    if (reinterpret_cast<uintptr_t>(d_in) % 16 || reinterpret_cast<uintptr_t>(d_out) % 16 ||
+        reinterpret_cast<uintptr_t>(d_res) % 16)
+        return fail(net, DL_ERR_INVALID_ARG, "tensors must be 16-byte aligned");
+    if ((rc = set_device(net))) return rc;
+    if ((rc = ensure_packed(net))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, reinterpret_cast<const uint16_t *>(d_in), n, h, w, fd, g);
+    FrameDesc *d_fd = nullptr;
+    const int slot = upload_desc(net, fd, s, &d_fd);
+    if (slot < 0) return slot;
+    ConvArgs a{};
+    a.fd = d_fd;
+    a.d = net->dil[blk];
+    a.in = d_in;
+    a.res = d_res;
+    a.out = d_out;
+    a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(blk * 2 + which) * net->wpk_stride;
+    a.bias = net->d_bias + (size_t)(blk * 2 + which) * net->C;
+    const int maxg = conv_max_grid(net->C, net->cfg.precision, g.tile_rows, net->ncu);
+    int grid = (int)std::min<int64_t>(g.total_tiles, maxg);
+    grid = std::max(8, grid / 8 * 8);
+    HIPCHK(net, launch_conv(net->C, net->cfg.precision, a, g, grid, s));
+    HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
+    return DL_OK;
+}
+
+int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, float tau, void *stream, uint8_t *d_det)
+{
+    int rc = check_uniform(net, d_logit, n, h, w);
+    if (rc) return rc;
+    if (!d_det) return fail(net, DL_ERR_INVALID_ARG, "d_det is NULL");
+    if (!std::isfinite(tau)) return fail(net, DL_ERR_INVALID_ARG, "tau must be finite");
+    if (reinterpret_cast<uintptr_t>(d_logit) % 4) return fail(net, DL_ERR_INVALID_ARG, "d_logit must be 4-byte aligned");
+    if ((rc = set_device(net))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, nullptr, n, h, w, fd, g);
+    const Plan p = make_plan(net, g, true);
+    if ((rc = ensure_workspace(net, p.total, s))) return rc;
+    FrameDesc *d_fd = nullptr;
+    const int slot = upload_desc(net, fd, s, &d_fd);
+    if (slot < 0) return slot;
+    uint64_t *mask = reinterpret_cast<uint64_t *>(net->ws + p.mask);
+    uint32_t *rcnt = reinterpret_cast<uint32_t *>(net->ws + p.rc);
+    HIPCHK(net, launch_detect_mask(d_logit, 1, d_fd, g, tau, mask, rcnt, s));
+    HIPCHK(net, launch_mask_to_u8(mask, d_fd, g, d_det, s));
+    HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
+    return DL_OK;
+}
+
+int dl_profile_enable(dl_net *net, int on)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    net->profiling = on != 0;
+    return DL_OK;
+}
+
+int dl_profile_read(dl_net *net, double *ms, int64_t *launches)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (!ms || !launches) return fail(net, DL_ERR_INVALID_ARG, "ms/launches is NULL");
+    for (int i = 0; i < DL_NSTAGES; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    int rc = DL_OK;
+    for (auto &e : net->prof_pending) {
+        float t = 0.f;
+        if (rc == DL_OK) {
+            hipError_t err = hipEventSynchronize(e.b);
+            if (err == hipSuccess) err = hipEventElapsedTime(&t, e.a, e.b);
+            if (err != hipSuccess) rc = fail(net, DL_ERR_DEVICE, "event timing failed: %s", hipGetErrorString(err));
+        }
+        if (e.stage >= 0 && e.stage < DL_NSTAGES) {
+            ms[e.stage] += t;
+            launches[e.stage] += 1;
+        }
+        net->ev_pool.push_back(e.a);
+        net->ev_pool.push_back(e.b);
+    }
+    net->prof_pending.clear();
+    return rc;
+}
+
+}  // extern "C"

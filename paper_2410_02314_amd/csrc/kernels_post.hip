@@ -1,0 +1,286 @@
+// Bandwidth-bound stages: preprocessing + stem convolution, detection
+// (threshold + 3x3 local maximum), ordered compaction into emitter records.
+//
+// Paper Sec. 2.2: pre- and post-processing stay in GPU memory; only the
+// post-processed coordinates leave the device.  Sec. 3.2: per pixel the
+// network gives a detection probability and the emitter's offset from that
+// pixel; the record converts the offset into absolute frame coordinates.
+#include "dloc_internal.h"
+
+namespace dloc {
+
+namespace {
+
+__device__ __forceinline__ int64_t row_key(const FrameDesc &d) { return d.row_start; }
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------- stem
+// One workgroup per global row.  x = (ADU - offset) * scale (scale = gain *
+// in_scale), then a = ReLU(b + sum_tap w * x) for C channels, 3x3, d = 1,
+// zero padding.  A thread produces 4 channels of one pixel, so consecutive
+// threads store consecutive 16-byte chunks of the NHWC row.
+template <int C, bool BF16OUT>
+__global__ void __launch_bounds__(256)
+k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
+       const float *__restrict__ b, float offset, float scale, void *__restrict__ act)
+{
+    __shared__ float sw[C * 9];
+    __shared__ float sb[C];
+    for (int i = threadIdx.x; i < C * 9; i += 256) sw[i] = w[i];
+    for (int i = threadIdx.x; i < C; i += 256) sb[i] = b[i];
+    __syncthreads();
+
+    const int64_t row = blockIdx.x;
+    const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
+    const FrameDesc fd = fdp[f];
+    const int y = (int)(row - fd.row_start);
+    const int H = fd.h, W = fd.w;
+    constexpr int CG = C / 4;
+    for (int i = threadIdx.x; i < W * CG; i += 256) {
+        const int x = i / CG;
+        const int cg = i - x * CG;
+        float xin[9];
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const int yy = y + u - 1, xx = x + v - 1;
+                const bool ok = (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+                xin[u * 3 + v] = ok ? ((float)fd.data[(int64_t)yy * fd.stride + xx] - offset) * scale : 0.f;
+            }
+        float o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = cg * 4 + k;
+            float acc = sb[c];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc = fmaf(sw[c * 9 + t], xin[t], acc);
+            o[k] = fmaxf(acc, 0.f);
+        }
+        const int64_t pix = fd.px_off + (int64_t)y * W + x;
+        if (BF16OUT) {
+            uint2 pk;
+            pk.x = (uint32_t)f32_to_bf16_rne(o[0]) | ((uint32_t)f32_to_bf16_rne(o[1]) << 16);
+            pk.y = (uint32_t)f32_to_bf16_rne(o[2]) | ((uint32_t)f32_to_bf16_rne(o[3]) << 16);
+            *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(act) + pix * C + cg * 4) = pk;
+        } else {
+            *reinterpret_cast<v4f *>(static_cast<float *>(act) + pix * C + cg * 4) = v4f{o[0], o[1], o[2], o[3]};
+        }
+    }
+}
+
+template <int C>
+hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
+                  float offset, float scale, void *act, int bf16, hipStream_t s)
+{
+    if (bf16)
+        hipLaunchKernelGGL((k_stem<C, true>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset, scale, act);
+    else
+        hipLaunchKernelGGL((k_stem<C, false>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset, scale, act);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ detection
+// One workgroup (4 waves) per global row.  Pixel (y, x) is detected iff its
+// logit exceeds tau and beats every in-frame 8-neighbour in the order (value,
+// then smaller raster index) -- a strict local maximum with a deterministic
+// tie-break, so a plateau yields exactly one detection.  Each wave turns 64
+// decisions into one 64-bit mask word (ballot); the row's count goes to
+// row_counts for the scan.
+__global__ void __launch_bounds__(256)
+k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__restrict__ fdp, int nf,
+              float tau, uint64_t *__restrict__ mask, uint32_t *__restrict__ row_counts)
+{
+    const int64_t row = blockIdx.x;
+    const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
+    const FrameDesc fd = fdp[f];
+    const int y = (int)(row - fd.row_start);
+    const int H = fd.h, W = fd.w;
+    const float *L = maps + planes * fd.px_off;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t cnt = 0;
+    for (int xb = wave * 64; xb < W; xb += 256) {
+        const int x = xb + lane;
+        bool det = false;
+        if (x < W) {
+            const int64_t idx = (int64_t)y * W + x;
+            const float v = L[idx];
+            det = v > tau;
+            if (det) {
+#pragma unroll
+                for (int di = -1; di <= 1; ++di)
+#pragma unroll
+                    for (int dj = -1; dj <= 1; ++dj) {
+                        if (di == 0 && dj == 0) continue;
+                        const int yy = y + di, xx = x + dj;
+                        if ((unsigned)yy >= (unsigned)H || (unsigned)xx >= (unsigned)W) continue;
+                        const float nv = L[(int64_t)yy * W + xx];
+                        // neighbours before (y, x) in raster order win ties
+                        const bool earlier = di < 0 || (di == 0 && dj < 0);
+                        if (nv > v || (nv == v && earlier)) det = false;
+                    }
+            }
+        }
+        const uint64_t m = __ballot(det);
+        if (lane == 0) mask[fd.mask_start + (int64_t)y * fd.words + (xb >> 6)] = m;
+        cnt += (uint32_t)__popcll(m);
+    }
+    __shared__ uint32_t sc[4];
+    if (lane == 0) sc[wave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) row_counts[row] = sc[0] + sc[1] + sc[2] + sc[3];
+}
+
+// ----------------------------------------------------------------- scan
+// Exclusive scan of the per-row counts over the whole batch (one workgroup:
+// each thread sums a contiguous chunk, the chunk sums are scanned in LDS, and
+// each thread writes its chunk's offsets), then per-frame counts and total.
+__global__ void __launch_bounds__(1024)
+k_scan(const uint32_t *__restrict__ rc, int64_t R, const FrameDesc *__restrict__ fdp, int nf,
+       uint32_t *__restrict__ row_off, uint32_t *__restrict__ counts)
+{
+    __shared__ uint32_t sh[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (R + 1023) / 1024;
+    const int64_t lo = (int64_t)tid * per;
+    const int64_t hi = lo + per < R ? lo + per : R;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += rc[i];
+    sh[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = tid >= o ? sh[tid - o] : 0u;
+        __syncthreads();
+        sh[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = sh[tid] - s;
+    for (int64_t i = lo; i < hi; ++i) {
+        row_off[i] = run;
+        run += rc[i];
+    }
+    if (tid == 1023) row_off[R] = sh[1023];
+    __syncthreads();
+    for (int f = tid; f < nf; f += 1024) {
+        const FrameDesc fd = fdp[f];
+        counts[f] = row_off[fd.row_start + fd.h] - row_off[fd.row_start];
+    }
+    if (tid == 0) counts[nf] = sh[1023];
+}
+
+// ----------------------------------------------------------------- emit
+// One workgroup per global row: each wave takes its mask word, the block
+// scans the 4 word counts, and every detected lane writes its record at
+// row_off[row] + (detections before it in raster order).  Records beyond
+// `cap` are dropped (the total is still reported by the scan).
+__global__ void __launch_bounds__(256)
+k_emit(const float *__restrict__ maps, const uint64_t *__restrict__ mask,
+       const uint32_t *__restrict__ row_off, const FrameDesc *__restrict__ fdp, int nf,
+       float z_scale, float ph_scale, dl_emitter *__restrict__ out, uint64_t cap)
+{
+    const int64_t row = blockIdx.x;
+    const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
+    const FrameDesc fd = fdp[f];
+    const int y = (int)(row - fd.row_start);
+    const int W = fd.w;
+    const int64_t plane = (int64_t)fd.h * W;
+    const float *M = maps + 5 * fd.px_off + (int64_t)y * W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ uint32_t sc[4];
+    uint32_t base = row_off[row];
+    for (int xb0 = 0; xb0 < W; xb0 += 256) {
+        const int xb = xb0 + wave * 64;
+        const uint64_t m = xb < W ? mask[fd.mask_start + (int64_t)y * fd.words + (xb >> 6)] : 0ull;
+        __syncthreads();
+        if (lane == 0) sc[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t wb = base;
+        for (int k = 0; k < wave; ++k) wb += sc[k];
+        const uint32_t tot = sc[0] + sc[1] + sc[2] + sc[3];
+        if ((m >> lane) & 1ull) {
+            const uint64_t below = lane ? (m & ((1ull << lane) - 1ull)) : 0ull;
+            const uint64_t idx = (uint64_t)wb + (uint64_t)__popcll(below);
+            if (idx < cap) {
+                const int x = xb + lane;
+                const float lg = M[x];
+                dl_emitter e;
+                e.frame = f;
+                e.row = y;
+                e.col = x;
+                e.x_px = (float)x + 0.5f + M[plane + x];
+                e.y_px = (float)y + 0.5f + M[2 * plane + x];
+                e.z_nm = M[3 * plane + x] * z_scale;
+                e.photons = M[4 * plane + x] * ph_scale;
+                e.prob = 1.f / (1.f + expf(-lg));
+                out[idx] = e;
+            }
+        }
+        base += tot;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_mask_to_u8(const uint64_t *__restrict__ mask, const FrameDesc *__restrict__ fdp, int nf,
+             uint8_t *__restrict__ det)
+{
+    const int64_t row = blockIdx.x;
+    const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
+    const FrameDesc fd = fdp[f];
+    const int y = (int)(row - fd.row_start);
+    for (int x = threadIdx.x; x < fd.w; x += 256) {
+        const uint64_t m = mask[fd.mask_start + (int64_t)y * fd.words + (x >> 6)];
+        det[fd.px_off + (int64_t)y * fd.w + x] = (uint8_t)((m >> (x & 63)) & 1ull);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
+                       float offset, float scale, void *act, int act_bf16, hipStream_t s)
+{
+    switch (C) {
+    case 16: return stem_c<16>(fd, g, w, b, offset, scale, act, act_bf16, s);
+    case 32: return stem_c<32>(fd, g, w, b, offset, scale, act, act_bf16, s);
+    case 48: return stem_c<48>(fd, g, w, b, offset, scale, act, act_bf16, s);
+    case 64: return stem_c<64>(fd, g, w, b, offset, scale, act, act_bf16, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_detect_mask(const float *maps, int planes, const FrameDesc *fd, const Geometry &g, float tau,
+                              uint64_t *mask, uint32_t *row_counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_detect_mask, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, fd, g.nf, tau, mask, row_counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t *row_counts, const FrameDesc *fd, const Geometry &g,
+                       uint32_t *row_off, uint32_t *counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, row_counts, g.total_rows, fd, g.nf, row_off, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const float *maps, const uint64_t *mask, const uint32_t *row_off,
+                       const FrameDesc *fd, const Geometry &g, float z_scale, float ph_scale,
+                       dl_emitter *out, uint64_t cap, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, mask, row_off, fd, g.nf,
+                       z_scale, ph_scale, out, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_to_u8(const uint64_t *mask, const FrameDesc *fd, const Geometry &g,
+                             uint8_t *det, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mask_to_u8, dim3((unsigned)g.total_rows), dim3(256), 0, s, mask, fd, g.nf, det);
+    return hipGetLastError();
+}
+
+}  // namespace dloc

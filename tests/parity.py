@@ -1,0 +1,80 @@
+"""Comparison helpers for GPU-vs-oracle parity (shared by the tests, smoke and bench).
+
+Readings used (listed in the design doc):
+* maps: |gpu - oracle| <= tol * (|oracle| + rms of that map over the frame),
+  a relative error that stays defined where a map crosses zero;
+* emitter sets: identical except pixels the FP64 oracle puts within 1e-3 of the
+  probability threshold, or whose logit ties a neighbour's to 1e-4 relative
+  (there the FP32 rounding decides the local maximum); such pixels are exempt
+  and counted.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def map_rel_err(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Max relative error per map plane; arrays [n][5][h][w] (or [5][h][w])."""
+    g = np.asarray(got, np.float64)
+    r = np.asarray(ref, np.float64)
+    if g.ndim == 3:
+        g, r = g[None], r[None]
+    out = np.zeros(r.shape[1])
+    for c in range(r.shape[1]):
+        rms = np.sqrt(np.mean(r[:, c] ** 2)) or 1.0
+        out[c] = np.max(np.abs(g[:, c] - r[:, c]) / (np.abs(r[:, c]) + rms))
+    return out
+
+
+def exempt_mask(logit: np.ndarray, threshold: float = 0.3, band: float = 1e-3, tie: float = 1e-4) -> np.ndarray:
+    """Pixels whose detection decision FP32 rounding may legitimately flip."""
+    L = np.asarray(logit, np.float64)
+    p = 1.0 / (1.0 + np.exp(-L))
+    ex = np.abs(p - threshold) <= band
+    h, w = L.shape
+    pad = np.pad(L, 1, constant_values=np.nan)
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            if di == 0 and dj == 0:
+                continue
+            nb = pad[1 + di:1 + di + h, 1 + dj:1 + dj + w]
+            with np.errstate(invalid="ignore"):
+                ex |= np.abs(L - nb) <= tie * (1.0 + np.abs(L))
+    return ex
+
+
+def compare_emitters(got, ref, ref_maps: np.ndarray, threshold: float = 0.3):
+    """got: records with fields frame,row,col,(x_px|x),(y_px|y),...; ref: oracle records;
+    ref_maps: [n][5][h][w] oracle maps.  Returns a summary dict."""
+    gk = {(int(a), int(b), int(c)): i for i, (a, b, c) in enumerate(zip(got["frame"], got["row"], got["col"]))}
+    rk = {(int(a), int(b), int(c)): i for i, (a, b, c) in enumerate(zip(ref["frame"], ref["row"], ref["col"]))}
+    ex = [exempt_mask(ref_maps[f, 0], threshold) for f in range(ref_maps.shape[0])]
+    only_g = [k for k in gk if k not in rk]
+    only_r = [k for k in rk if k not in gk]
+    bad = [k for k in only_g + only_r if not ex[k[0]][k[1], k[2]]]
+    both = [k for k in gk if k in rk]
+    gx = got["x_px"] if "x_px" in got.dtype.names else got["x"]
+    gy = got["y_px"] if "y_px" in got.dtype.names else got["y"]
+    dx = np.array([gx[gk[k]] - ref["x"][rk[k]] for k in both]) if both else np.zeros(0)
+    dy = np.array([gy[gk[k]] - ref["y"][rk[k]] for k in both]) if both else np.zeros(0)
+    gz = got["z_nm"] if "z_nm" in got.dtype.names else got["z"]
+    dz = np.array([gz[gk[k]] - ref["z"][rk[k]] for k in both]) if both else np.zeros(0)
+    order_ok = list(zip(got["frame"], got["row"], got["col"])) == sorted(zip(got["frame"], got["row"], got["col"]))
+    n_ref = len(rk)
+    return {
+        "n_got": len(gk), "n_ref": n_ref, "matched": len(both),
+        "only_gpu": len(only_g), "only_oracle": len(only_r), "non_exempt_mismatch": len(bad),
+        "bad": bad[:10], "order_ok": order_ok,
+        "recall": len(both) / n_ref if n_ref else 1.0,
+        "precision": len(both) / len(gk) if gk else 1.0,
+        "rms_dx_px": float(np.sqrt(np.mean(dx ** 2))) if dx.size else 0.0,
+        "rms_dy_px": float(np.sqrt(np.mean(dy ** 2))) if dy.size else 0.0,
+        "rms_dz_nm": float(np.sqrt(np.mean(dz ** 2))) if dz.size else 0.0,
+        "max_dxy_px": float(max(np.abs(dx).max(initial=0), np.abs(dy).max(initial=0))),
+    }
+
+
+def logit_tau(threshold: float = 0.3) -> float:
+    return math.log(threshold / (1.0 - threshold))

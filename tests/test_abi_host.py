@@ -1,0 +1,131 @@
+"""C-ABI host tests: no GPU needed.  The library loads, exports every function
+declared in include/dloc.h, parses weights blobs, and rejects bad arguments
+before any HIP call."""
+import ctypes
+import math
+import os
+import re
+import struct
+
+import numpy as np
+import pytest
+
+import smlm_synth as S
+
+dl = pytest.importorskip("paper_2410_02314_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "dloc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dl_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = header_functions()
+    assert len(names) >= 15
+    L = ctypes.CDLL(dl.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_abi_version_and_defaults():
+    assert dl.abi_version() == 1
+    c = dl.DLConfig()
+    assert dl.lib().dl_default_config(ctypes.byref(c)) == 0
+    assert (c.precision, c.device, c.flags, c.tile_rows) == (0, 0, 0, 0)
+    assert abs(c.threshold - 0.3) < 1e-7 and c.gain == 0.5 and c.offset == 100.0
+    assert dl.lib().dl_default_config(None) == dl.DL_ERR_INVALID_ARG
+
+
+def blob(name="A", seed=1):
+    spec, w = S.make_net(name, seed)
+    return spec, w, S.serialize_weights(spec, w)
+
+
+@pytest.mark.parametrize("name", ["A", "B"])
+def test_inspect_weights_reads_header(name):
+    spec, w, b = blob(name)
+    info = dl.inspect_weights(b)
+    assert info["C"] == spec.C and info["dilations"] == spec.dilations
+    assert info["nparams"] == S.param_count(spec)
+    assert info["receptive_radius"] == S.receptive_radius(spec)
+    assert math.isclose(info["in_scale"], spec.in_scale, rel_tol=1e-7)
+    assert info["z_scale"] == spec.z_scale and info["ph_scale"] == spec.ph_scale
+
+
+def _code(b):
+    info = dl.DLNetInfo()
+    buf = ctypes.create_string_buffer(bytes(b), len(b))
+    return dl.lib().dl_inspect_weights(buf, len(b), ctypes.byref(info))
+
+
+def test_bad_blobs_are_rejected():
+    spec, w, b = blob("A")
+    assert _code(b) == 0
+    assert _code(b"XXXX" + b[4:]) == dl.DL_ERR_BAD_WEIGHTS              # magic
+    assert _code(b[:-4]) == dl.DL_ERR_BAD_WEIGHTS                        # truncated
+    assert _code(b + b"\0\0\0\0") == dl.DL_ERR_BAD_WEIGHTS               # trailing bytes
+    assert _code(b[:40]) == dl.DL_ERR_BAD_WEIGHTS                        # shorter than header
+    bad = bytearray(b); bad[4:8] = struct.pack("<I", 2)
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS                           # version
+    bad = bytearray(b); bad[8:12] = struct.pack("<I", 24)
+    assert _code(bad) == dl.DL_ERR_UNSUPPORTED                           # C
+    bad = bytearray(b); bad[12:16] = struct.pack("<I", 0)
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS                           # nblocks
+    bad = bytearray(b); bad[16:20] = struct.pack("<I", 0)
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS                           # dilation 0
+    bad = bytearray(b); bad[48:52] = struct.pack("<f", -1.0)
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS                           # in_scale
+    bad = bytearray(b); bad[100:104] = struct.pack("<f", float("nan"))
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS                           # NaN weight
+    assert "NaN" in dl.last_error()
+    assert dl.lib().dl_inspect_weights(None, 10, ctypes.byref(dl.DLNetInfo())) == dl.DL_ERR_INVALID_ARG
+
+
+def _create(b, **cfg):
+    c = dl.make_config(**cfg)
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(bytes(b), len(b))
+    rc = dl.lib().dl_create_net(buf, len(b), ctypes.byref(c), ctypes.byref(h))
+    if rc == 0:
+        dl.lib().dl_destroy_net(h)
+    return rc
+
+
+@pytest.mark.parametrize("cfg", [dict(precision=7), dict(threshold=0.0), dict(threshold=1.0),
+                                 dict(gain=0.0), dict(gain=float("nan")), dict(offset=float("inf")),
+                                 dict(device=-1), dict(tile_rows=5), dict(flags=0x80)])
+def test_create_rejects_bad_config_before_device(cfg):
+    _, _, b = blob("A")
+    assert _create(b, **cfg) == dl.DL_ERR_INVALID_ARG
+
+
+def test_create_rejects_bad_blob_and_null_pointers():
+    _, _, b = blob("A")
+    assert _create(b[:-1]) == dl.DL_ERR_BAD_WEIGHTS
+    h = ctypes.c_void_p()
+    assert dl.lib().dl_create_net(None, 100, None, ctypes.byref(h)) == dl.DL_ERR_INVALID_ARG
+    buf = ctypes.create_string_buffer(bytes(b), len(b))
+    assert dl.lib().dl_create_net(buf, len(b), None, None) == dl.DL_ERR_INVALID_ARG
+
+
+def test_calls_on_null_handle_fail_cleanly():
+    L = dl.lib()
+    assert L.dl_localize_device(None, 16, 1, 8, 8, None, 16, 4, 16) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_maps_device(None, 16, 1, 8, 8, None, 16) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_set_config(None, None) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_profile_enable(None, 1) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_host_alloc(0, ctypes.byref(ctypes.c_void_p())) == dl.DL_ERR_INVALID_ARG
+    assert "bytes is 0" in dl.last_error()
+    L.dl_destroy_net(None)                       # no-op
+    L.dl_host_free(None)                         # no-op
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    _, _, b = blob("B")
+    assert _create(b) == dl.DL_ERR_DEVICE
