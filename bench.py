@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of the localization path on one MI355X: Mpixel/s from uint16
+frames (resident in HBM) to the emitter list (in HBM).
+
+Workload (default): 16 frames of 2048 x 2048 uint16, astigmatic 3D PSF,
+density U(0.5, 2) / um^2, lognormal photons, background U(50, 200), sCMOS-like
+noise; net B (C = 48, residual blocks at dilations 1, 2, 4, 8, 16), FP32.
+A step is one pass of the whole path over the batch: preprocessing + stem,
+10 dilated convolutions (head fused into the last), detection, scan, emit.
+
+Prints ONE JSON line.  Besides the throughput it reports the roofline of the
+dominant kernel (the 3x3 block convolution, MFMA-bound) from HIP events
+recorded around each launch on its stream during the timed steps, and the
+FP64 CPU oracle timed on a bounded sample of the same workload (which also
+checks the GPU output on that sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel/s frame->emitter list: FP32 vs BF16/FP8/gated at oracle-matched recall"
+PEAKS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}     # dense MFMA TFLOP/s, MI355X
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return min(n, int(omp)) if omp and omp.isdigit() else n
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=640, help="side of the oracle's sample crop (0 = skip)")
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="processes rendering the frames (0 = automatic; 1 under profilers)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB first (scale reference for HBM counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
+              "frames are independent, the multi-GPU form is a design note only.", file=sys.stderr)
+        sys.exit(2)
+
+    import smlm_synth as S
+
+    # inputs first, before anything touches the GPU (workers are forked)
+    spec, w = S.make_net("B", 2)
+    n, side = args.frames, args.size
+    t0 = time.time()
+    frames = S.render_frames(n, side, side, "full", 1002, workers=args.gen_workers or None)
+    log(f"generated {n} x {side}^2 frames in {time.time() - t0:.1f}s")
+
+    import torch
+    import paper_2410_02314_amd as dl
+
+    assert torch.cuda.is_available(), "no HIP device"
+    dev = torch.device("cuda:0")
+    net = dl.Net(S.serialize_weights(spec, w), precision=args.precision, tile_rows=args.tile_rows)
+    d_frames = torch.from_numpy(frames).to(dev)
+    cap = n * side * side // 64
+    d_out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
+    d_counts = torch.zeros(n + 1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    if args.copy_probe_mib > 0:
+        # plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale between counter units and bytes moved
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nb} bytes read + {nb} bytes written per launch")
+        del src, dst
+
+    for _ in range(args.warmup):
+        net.localize_device(d_frames, d_out, d_counts, stream)
+    torch.cuda.synchronize()
+    net.profile(True)
+    net.profile_read()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.localize_device(d_frames, d_out, d_counts, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    prof = net.profile_read()
+    net.profile(False)
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    total_px = n * side * side
+    value = total_px / (ms_step * 1e-3) / 1e6
+    counts = d_counts.cpu().numpy()
+    log(f"{ms_step:.2f} ms/step, {value:.1f} Mpx/s, wall {wall / args.steps * 1e3:.2f} ms/step, "
+        f"{int(counts[n])} emitters/step")
+    log("stages: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f} ms x{v[1]}" for k, v in prof.items() if v[1]))
+
+    C = spec.C
+    conv_ms, conv_n = prof["conv"]
+    avg_s = conv_ms / conv_n * 1e-3
+    flop_launch = 2.0 * 9 * C * C * total_px
+    achieved = flop_launch / avg_s / 1e12
+    roofline = {"bound": "mfma", "kernel": f"k_conv_{args.precision} (3x3 dilated conv, C={C})",
+                "achieved": round(achieved, 2), "peak": PEAKS[args.precision], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAKS[args.precision], 4),
+                "traffic": measured_traffic(f"k_conv {args.precision} C={C} {n}x{side}x{side}"),
+                "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_launch": flop_launch}
+    stage_ms = {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        recs = dl.emitters_from_device(d_out, min(int(counts[n]), cap))
+        cpu = cpu_baseline(args, spec, w, frames, net, dev, recs)
+
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+        "data": "synthetic (seeded astigmatic-PSF SMLM frames; random-init calibrated net)",
+        "config": {"workload": f"{n} x {side}x{side} uint16 frames, astigmatic 3D PSF, net B "
+                               f"(C=48, d=1,2,4,8,16), {args.precision}",
+                   "frames": n, "height": side, "width": side, "net": "B", "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "stage_ms_per_step": stage_ms, "emitters_per_step": int(counts[n]),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    net.close()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (scaled by a plain copy kernel), or None if
+    there is no record for this kernel/workload or the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2410_02314_amd", "csrc", "kernels_conv.hip")
+    try:
+        rec = json.load(open(path)).get(key)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def cpu_baseline(args, spec, w, frames, net, dev, recs):
+    """FP64 oracle on a bounded sample: the top-left crop of frame 0.  Also checks
+    the GPU maps/detections on the part of the crop the oracle computes exactly
+    (at least R pixels from the crop's inner edges)."""
+    import torch
+    import oracle
+    from tests.parity import compare_emitters, map_rel_err
+    s = min(args.cpu_sample, args.size)
+    crop = np.ascontiguousarray(frames[0, :s, :s])
+    t0 = time.perf_counter()
+    rec, ref_maps = oracle.localize(crop[None], spec, w, return_maps=True)
+    dt = time.perf_counter() - t0
+    R = 1 + 2 * sum(spec.dilations)
+    e = s - R
+    maps = torch.empty((1, 5, args.size, args.size), dtype=torch.float32, device=dev)
+    net.maps_device(torch.from_numpy(np.ascontiguousarray(frames[:1])).to(dev), maps)
+    torch.cuda.synchronize()
+    g = maps[0, :, :e, :e].cpu().numpy()
+    err = map_rel_err(g, ref_maps[0, :, :e, :e])
+    # detections on [0, e-1) x [0, e-1) (their neighbours lie in the exact region):
+    # the GPU's own emitter records against the oracle's detections there
+    from tests.parity import exempt_mask
+    ref_det = oracle.detect(ref_maps[0, 0, :e, :e])[:-1, :-1]
+    sel = (recs["frame"] == 0) & (recs["row"] < e - 1) & (recs["col"] < e - 1)
+    got_det = np.zeros_like(ref_det)
+    got_det[recs["row"][sel], recs["col"][sel]] = True
+    ex = exempt_mask(ref_maps[0, 0, :e, :e])[:-1, :-1]
+    mism = int(np.sum((ref_det != got_det) & ~ex))
+    matched = int(np.sum(ref_det & got_det))
+    return {"value": round(s * s / dt / 1e6, 4), "unit": "Mpixel/s", "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"frame 0 crop {s}x{s} of the same workload, FP64 oracle (net + detection + records), "
+                      f"{dt:.1f} s",
+            "sample_check": {"max_map_rel_err": float(err.max()), "oracle_detections": int(ref_det.sum()),
+                             "gpu_detections": int(got_det.sum()), "matched": matched,
+                             "recall_vs_oracle": matched / max(1, int(ref_det.sum())),
+                             "non_exempt_detection_mismatch": mism, "region": f"{e - 1}x{e - 1}"}}
+
+
+if __name__ == "__main__":
+    main()

@@ -178,9 +178,70 @@ int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *str
  * d_maps + 5 * sum_{j<k} h_j * w_j. */
 int dl_maps_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, float *d_maps);
 
+/* ---- HIP graphs ----
+ * Capture the whole localization of one fixed batch (frames at d_frames, or
+ * the ROI list) into a HIP graph that owns its workspace and descriptors.
+ * Refill the frame buffer in place and replay with dl_graph_launch: one
+ * launch per batch instead of ~20 kernel launches (Sec. 2.2: the network reads
+ * preloaded frames from fixed memory locations).  Outputs as for
+ * dl_localize_device.  The graph holds the handle's weights and precision at
+ * creation; destroy graphs before their handle.  Not available with the gate. */
+typedef struct dl_graph dl_graph;
+int dl_graph_create(dl_net *net, const uint16_t *d_frames, int n, int h, int w, dl_emitter *d_out, size_t cap,
+                    uint32_t *d_counts, dl_graph **out);
+int dl_graph_create_rois(dl_net *net, const dl_roi *rois, int nroi, dl_emitter *d_out, size_t cap,
+                         uint32_t *d_counts, dl_graph **out);
+int dl_graph_launch(dl_graph *g, void *stream);
+void dl_graph_destroy(dl_graph *g);
+
 /* Pinned host memory for frames (Sec. 2.2 "specified memory locations"). */
 int dl_host_alloc(size_t bytes, void **p);
 void dl_host_free(void *p);
+
+/* ---- tile-occupancy gate ----
+ * A small learned classifier decides per 256 x 256 tile whether the network
+ * needs to run there.  Per tile of preprocessed input x (DL_GATE_TILE pixels
+ * square): p = 4x4 mean pooling (64 x 64); h1 = ReLU(conv3x3(p; 1 -> 8, pad 1));
+ * h2 = ReLU(conv3x3(h1; 8 -> 8, pad 1)); m = mean of h2 over pixels;
+ * g = fw . m + fb (logit).  theta[DL_GATE_NPARAM] holds W1[8][1][3][3], b1[8],
+ * W2[8][8][3][3], b2[8], fw[8], fb in that order (FP32).  Training uses binary
+ * cross-entropy on g (paper Sec. 3.3) and Adam.  All pointers are device
+ * memory; work is queued on `stream`; these calls need no network handle. */
+#define DL_GATE_TILE 256
+#define DL_GATE_NPARAM 673
+
+/* d_frames uint16 [n][h][w] (h, w multiples of 256) -> d_pooled float
+ * [n * (h/256) * (w/256)][64][64], tiles frame-major then row-major. */
+int dl_gate_pool(const uint16_t *d_frames, int n, int h, int w, float gain, float offset, float in_scale,
+                 void *stream, float *d_pooled);
+/* d_logits[ntiles] = g of every pooled tile. */
+int dl_gate_forward(const float *d_pooled, int ntiles, const float *d_theta, void *stream, float *d_logits);
+/* Forward plus the gradient of sum_b d_dlogits[b] * g_b with respect to theta:
+ * d_logits[ntiles], d_grad[DL_GATE_NPARAM].  d_work: float[ntiles * DL_GATE_NPARAM]
+ * scratch (per-tile partial gradients, summed in tile order: deterministic). */
+int dl_gate_backward(const float *d_pooled, int ntiles, const float *d_theta, const float *d_dlogits,
+                     float *d_work, void *stream, float *d_logits, float *d_grad);
+/* Mean binary cross-entropy of logits against labels in {0, 1}:
+ * d_loss[1] (may be NULL) and d_dlogits[n] = (sigmoid(g) - y) / n (may be NULL). */
+int dl_gate_bce(const float *d_logits, const float *d_labels, int n, void *stream, float *d_loss, float *d_dlogits);
+/* One Adam step (step counts from 1) on n parameters, in place. */
+int dl_gate_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, int n, int step, float lr, float b1,
+                 float b2, float eps, void *stream);
+
+/* Attach a trained gate to a network (theta host float[DL_GATE_NPARAM],
+ * copied; NULL detaches).  With DL_FLAG_GATE set in the config, uniform
+ * batches whose h and w are multiples of 256 run the gate first; a 256^2 tile
+ * is kept iff sigmoid(g) > threshold.  Each convolution layer then computes
+ * only the tiles within its remaining receptive radius of a kept tile, so
+ * kept tiles get exactly the ungated maps.  Skipped tiles produce no
+ * emitters, and their pixels do not count as neighbours in the local-maximum
+ * test.  Other shapes return DL_ERR_UNSUPPORTED while the flag is set. */
+int dl_set_gate(dl_net *net, const float *theta, float threshold);
+
+/* Copy the keep flags (uint8, 1 = kept) of the last gated run, frame-major
+ * then row-major over 256^2 tiles, to device memory d_keep (cap bytes);
+ * *ntiles = number of flags.  DL_ERR_CAPACITY if cap is too small. */
+int dl_gate_keep_map(dl_net *net, void *stream, uint8_t *d_keep, size_t cap, size_t *ntiles);
 
 /* ---- stage timing ----
  * With profiling on, every kernel launch of the path is bracketed by two HIP

@@ -91,6 +91,17 @@ def _load():
         "dl_debug_conv_layer": (I, [P, P, P, I, I, I, I, I, P, P]),
         "dl_debug_detect": (I, [P, P, I, I, I, ctypes.c_float, P, P]),
         "dl_profile_enable": (I, [P, I]),
+        "dl_set_gate": (I, [P, P, ctypes.c_float]),
+        "dl_graph_create": (I, [P, P, I, I, I, P, Z, P, ctypes.POINTER(P)]),
+        "dl_graph_create_rois": (I, [P, ctypes.POINTER(DLRoi), I, P, Z, P, ctypes.POINTER(P)]),
+        "dl_graph_launch": (I, [P, P]),
+        "dl_graph_destroy": (None, [P]),
+        "dl_gate_keep_map": (I, [P, P, P, Z, ctypes.POINTER(Z)]),
+        "dl_gate_pool": (I, [P, I, I, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P]),
+        "dl_gate_forward": (I, [P, I, P, P, P]),
+        "dl_gate_backward": (I, [P, I, P, P, P, P, P, P]),
+        "dl_gate_bce": (I, [P, P, I, P, P, P]),
+        "dl_gate_adam": (I, [P, P, P, P, I, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),
         "dl_profile_read": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
@@ -267,6 +278,37 @@ class Net:
         _check(rc, self.handle)
         return out[:cnt.value].copy()
 
+    def graph(self, frames, out, counts) -> "Graph":
+        """Capture localization of this fixed frame buffer into a HIP graph."""
+        n, h, w = frames.shape
+        cap = out.numel() * out.element_size() // 32
+        g = ctypes.c_void_p()
+        self._rc(_lib.dl_graph_create(self.handle, _ptr(frames), n, h, w, _ptr(out), cap, _ptr(counts),
+                                      ctypes.byref(g)))
+        return Graph(self, g, (frames, out, counts))
+
+    def graph_rois(self, rois, out, counts) -> "Graph":
+        arr = self._roi_array(rois)
+        cap = out.numel() * out.element_size() // 32
+        g = ctypes.c_void_p()
+        self._rc(_lib.dl_graph_create_rois(self.handle, arr, len(rois), _ptr(out), cap, _ptr(counts),
+                                           ctypes.byref(g)))
+        return Graph(self, g, (rois, out, counts))
+
+    def set_gate(self, theta, threshold: float = 0.05):
+        """Attach gate parameters (host array of 673 floats, or None to detach)."""
+        if theta is None:
+            self._rc(_lib.dl_set_gate(self.handle, None, threshold))
+            return
+        th = np.ascontiguousarray(theta, np.float32)
+        assert th.size == GATE_NPARAM
+        self._rc(_lib.dl_set_gate(self.handle, th.ctypes.data, float(threshold)))
+
+    def gate_keep_map(self, keep, stream=None) -> int:
+        n = ctypes.c_size_t()
+        self._rc(_lib.dl_gate_keep_map(self.handle, _stream(stream), _ptr(keep), keep.numel(), ctypes.byref(n)))
+        return int(n.value)
+
     def profile(self, on: bool = True):
         self._rc(_lib.dl_profile_enable(self.handle, int(bool(on))))
 
@@ -282,10 +324,59 @@ class Net:
         return rc
 
 
+class Graph:
+    """A captured localization (``dl_graph_create``); keeps its buffers alive."""
+
+    def __init__(self, net: Net, handle, buffers):
+        self.net, self.handle, self._buffers = net, handle, buffers
+
+    def launch(self, stream=None):
+        _check(_lib.dl_graph_launch(self.handle, _stream(stream)), self.net.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.dl_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def emitters_from_device(out, counts_total: int) -> np.ndarray:
     """Copy the first ``counts_total`` records of a device record buffer to a numpy structured array."""
     raw = out.reshape(-1).view(__import__("torch").uint8)[: counts_total * 32].cpu().numpy()
     return raw.view(EMITTER_DTYPE).copy()
+
+
+# ---------------------------------------------------------------- tile gate
+GATE_TILE = 256
+GATE_NPARAM = 673
+
+
+def gate_pool(frames, pooled, gain=0.5, offset=100.0, in_scale=0.01, stream=None):
+    n, h, w = frames.shape
+    _check(_lib.dl_gate_pool(_ptr(frames), n, h, w, gain, offset, in_scale, _stream(stream), _ptr(pooled)))
+
+
+def gate_forward(pooled, theta, logits, stream=None):
+    _check(_lib.dl_gate_forward(_ptr(pooled), pooled.shape[0], _ptr(theta), _stream(stream), _ptr(logits)))
+
+
+def gate_backward(pooled, theta, dlogits, work, logits, grad, stream=None):
+    _check(_lib.dl_gate_backward(_ptr(pooled), pooled.shape[0], _ptr(theta), _ptr(dlogits), _ptr(work),
+                                 _stream(stream), _ptr(logits), _ptr(grad)))
+
+
+def gate_bce(logits, labels, loss, dlogits, stream=None):
+    _check(_lib.dl_gate_bce(_ptr(logits), _ptr(labels), logits.shape[0], _stream(stream), _ptr(loss), _ptr(dlogits)))
+
+
+def gate_adam(theta, m, v, grad, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    _check(_lib.dl_gate_adam(_ptr(theta), _ptr(m), _ptr(v), _ptr(grad), theta.numel(), int(step), lr, b1, b2, eps,
+                             _stream(stream)))
 
 
 def host_alloc(nbytes: int) -> int:

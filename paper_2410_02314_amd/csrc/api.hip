@@ -58,6 +58,14 @@ struct dl_net {
     hipStream_t copy_stream = nullptr, compute_stream = nullptr;
     std::string err;
 
+    // tile gate
+    float *d_gate_theta = nullptr;  // [673]
+    float gate_tau = 0.f;           // keep a tile iff its logit > gate_tau
+    bool gate_set = false;
+    int *d_radius = nullptr;        // [1 + 2 nb]: stem radius, then per conv layer
+    int64_t last_gate_tiles = 0;
+    size_t last_keep_off = 0;
+
     // per-stage timing with HIP events recorded on the launch stream
     bool profiling = false;
     struct Ev { int stage; hipEvent_t a, b; };
@@ -131,6 +139,11 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         d.mask_start = g.total_words;
         d.tiles_x = (d.w + TILE_COLS - 1) / TILE_COLS;
         d.words = (d.w + 63) / 64;
+        d.gtx = d.w / GATE_TILE;
+        d.gty = d.h / GATE_TILE;
+        d.keep_start = g.gate_tiles;
+        d.pad_ = 0;
+        g.gate_tiles += (int64_t)d.gtx * d.gty;
         g.total_px += (int64_t)d.h * d.w;
         g.total_rows += d.h;
         g.total_tiles += (int64_t)((d.h + rows - 1) / rows) * d.tiles_x;
@@ -140,8 +153,13 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
 }
 
 struct Plan {
+    char *ws = nullptr;             // workspace base the offsets refer to
     size_t act0 = 0, act1 = 0, maps = 0, mask = 0, rc = 0, roff = 0, total = 0;
+    bool gated = false;
+    size_t pooled = 0, glog = 0, keep = 0, lists = 0, lcount = 0;
 };
+
+bool gated_run(const dl_net *net) { return (net->cfg.flags & DL_FLAG_GATE) && net->gate_set; }
 
 Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
 {
@@ -154,6 +172,15 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     p.mask = o; o = align_up(o + (size_t)g.total_words * 8);
     p.rc = o; o = align_up(o + (size_t)g.total_rows * 4);
     p.roff = o; o = align_up(o + (size_t)(g.total_rows + 1) * 4);
+    if (gated_run(net)) {
+        const int L = 2 * net->nb;
+        p.gated = true;
+        p.pooled = o; o = align_up(o + (size_t)g.gate_tiles * 4096 * 4);
+        p.glog = o; o = align_up(o + (size_t)g.gate_tiles * 4);
+        p.keep = o; o = align_up(o + (size_t)g.gate_tiles);
+        p.lists = o; o = align_up(o + (size_t)L * g.total_tiles * 4);
+        p.lcount = o; o = align_up(o + (size_t)L * 4);
+    }
     p.total = o;
     return p;
 }
@@ -270,17 +297,43 @@ struct StageTimer {
     }
 };
 
+// Gated runs: pool the input per 256^2 tile, run the gate, keep tiles whose
+// logit exceeds the threshold, and build each conv layer's list of tiles that
+// lie within that layer's remaining receptive radius of a kept tile.
+int run_gate(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, const uint16_t *d_frames,
+             int n, int h, int w, hipStream_t s)
+{
+    StageTimer t(net, DL_STAGE_GATE, s);
+    float *pooled = reinterpret_cast<float *>(p.ws + p.pooled);
+    float *glog = reinterpret_cast<float *>(p.ws + p.glog);
+    uint8_t *keep = reinterpret_cast<uint8_t *>(p.ws + p.keep);
+    HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * net->in_scale, pooled, s));
+    HIPCHK(net, launch_gate(pooled, (int)g.gate_tiles, net->d_gate_theta, glog, nullptr, nullptr, s));
+    HIPCHK(net, launch_gate_keep(glog, g.gate_tiles, net->gate_tau, keep, s));
+    HIPCHK(net, launch_active_lists(d_fd, g, keep, net->d_radius + 1, 2 * net->nb,
+                                    reinterpret_cast<int32_t *>(p.ws + p.lists),
+                                    reinterpret_cast<uint32_t *>(p.ws + p.lcount), s));
+    net->last_gate_tiles = g.gate_tiles;
+    net->last_keep_off = (size_t)(p.ws - net->ws) + p.keep;
+    return DL_OK;
+}
+
 // Run stem + blocks (+ fused head into maps).
 int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, float *maps, hipStream_t s)
 {
     const int C = net->C;
-    void *a0 = net->ws + p.act0;
-    void *a1 = net->ws + p.act1;
+    void *a0 = p.ws + p.act0;
+    void *a1 = p.ws + p.act1;
     const float scale = net->cfg.gain * net->in_scale;
+    const uint8_t *keep = p.gated ? reinterpret_cast<const uint8_t *>(p.ws + p.keep) : nullptr;
+    const int32_t *lists = p.gated ? reinterpret_cast<const int32_t *>(p.ws + p.lists) : nullptr;
+    const uint32_t *lcount = p.gated ? reinterpret_cast<const uint32_t *>(p.ws + p.lcount) : nullptr;
+    int stem_r = 0;
+    for (int b = 0; b < net->nb; ++b) stem_r += 2 * net->dil[b];
     {
         StageTimer t(net, DL_STAGE_STEM, s);
         HIPCHK(net, launch_stem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset, scale, a0,
-                                net->cfg.precision != DL_FP32, s));
+                                net->cfg.precision != DL_FP32, keep, stem_r, s));
     }
     const int maxg = conv_max_grid(C, net->cfg.precision, g.tile_rows, net->ncu);
     int grid = (int)std::min<int64_t>(g.total_tiles, maxg);
@@ -294,6 +347,10 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         a.res = nullptr;
         a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2) * net->wpk_stride;
         a.bias = net->d_bias + (size_t)(b * 2) * C;
+        if (lists) {
+            a.list = lists + (size_t)(2 * b) * g.total_tiles;
+            a.list_count = lcount + 2 * b;
+        }
         {
             StageTimer t(net, DL_STAGE_CONV, s);
             HIPCHK(net, launch_conv(C, net->cfg.precision, a, g, grid, s));
@@ -303,6 +360,10 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         a.out = a0;
         a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2 + 1) * net->wpk_stride;
         a.bias = net->d_bias + (size_t)(b * 2 + 1) * C;
+        if (lists) {
+            a.list = lists + (size_t)(2 * b + 1) * g.total_tiles;
+            a.list_count = lcount + 2 * b + 1;
+        }
         if (b == net->nb - 1) {
             a.head = net->d_head;
             a.maps = maps;
@@ -319,12 +380,13 @@ int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
 {
     const float thr = net->cfg.threshold;
     const float tau = (float)std::log((double)thr / (1.0 - (double)thr));
-    uint64_t *mask = reinterpret_cast<uint64_t *>(net->ws + p.mask);
-    uint32_t *rc = reinterpret_cast<uint32_t *>(net->ws + p.rc);
-    uint32_t *roff = reinterpret_cast<uint32_t *>(net->ws + p.roff);
+    uint64_t *mask = reinterpret_cast<uint64_t *>(p.ws + p.mask);
+    uint32_t *rc = reinterpret_cast<uint32_t *>(p.ws + p.rc);
+    uint32_t *roff = reinterpret_cast<uint32_t *>(p.ws + p.roff);
     {
         StageTimer t(net, DL_STAGE_DETECT, s);
-        HIPCHK(net, launch_detect_mask(maps, 5, d_fd, g, tau, mask, rc, s));
+        const uint8_t *keep = p.gated ? reinterpret_cast<const uint8_t *>(p.ws + p.keep) : nullptr;
+        HIPCHK(net, launch_detect_mask(maps, 5, d_fd, g, tau, keep, mask, rc, s));
     }
     {
         StageTimer t(net, DL_STAGE_SCAN, s);
@@ -361,21 +423,102 @@ int uniform_geometry(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
 }
 
 int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g, hipStream_t s,
-                  dl_emitter *d_out, size_t cap, uint32_t *d_counts, float *ext_maps)
+                  dl_emitter *d_out, size_t cap, uint32_t *d_counts, float *ext_maps,
+                  const uint16_t *d_frames = nullptr, int n = 0, int h = 0, int w = 0)
 {
     int rc;
     if ((rc = set_device(net))) return rc;
     if ((rc = ensure_packed(net))) return rc;
-    const Plan p = make_plan(net, g, ext_maps != nullptr);
+    if (gated_run(net)) {
+        if (!d_frames) return fail(net, DL_ERR_UNSUPPORTED, "the tile gate runs on uniform batches only (not ROI lists)");
+        if (h % GATE_TILE || w % GATE_TILE)
+            return fail(net, DL_ERR_UNSUPPORTED, "the tile gate needs h and w multiples of %d (got %d x %d)", GATE_TILE, h, w);
+    }
+    Plan p = make_plan(net, g, ext_maps != nullptr);
     if ((rc = ensure_workspace(net, p.total, s))) return rc;
+    p.ws = net->ws;
     FrameDesc *d_fd = nullptr;
     const int slot = upload_desc(net, fd, s, &d_fd);
     if (slot < 0) return slot;
-    float *maps = ext_maps ? ext_maps : reinterpret_cast<float *>(net->ws + p.maps);
+    float *maps = ext_maps ? ext_maps : reinterpret_cast<float *>(p.ws + p.maps);
+    if (p.gated && (rc = run_gate(net, d_fd, g, p, d_frames, n, h, w, s))) return rc;
     if ((rc = run_net(net, d_fd, g, p, maps, s))) return rc;
     if (d_out || d_counts)
         if ((rc = run_post(net, d_fd, g, p, maps, d_out, cap, d_counts, s))) return rc;
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
+    return DL_OK;
+}
+
+}  // namespace
+
+// A captured localization of one fixed batch geometry: its own workspace and
+// descriptor buffer (so later calls on the handle can never move memory the
+// graph points at), the kernel sequence as a hipGraphExec.
+struct dl_graph {
+    dl_net *net = nullptr;
+    char *ws = nullptr;
+    FrameDesc *d_fd = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static int check_rois(dl_net *net, const dl_roi *rois, int nroi);
+static void roi_geometry(dl_net *net, const dl_roi *rois, int nroi, std::vector<FrameDesc> &fd, Geometry &g);
+
+namespace {
+
+int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g, dl_emitter *d_out, size_t cap,
+                uint32_t *d_counts, dl_graph **out)
+{
+    int rc;
+    if ((rc = set_device(net))) return rc;
+    if ((rc = ensure_packed(net))) return rc;
+    if (gated_run(net)) return fail(net, DL_ERR_UNSUPPORTED, "graph capture of gated runs is not supported");
+    dl_graph *gr = new (std::nothrow) dl_graph();
+    if (!gr) return fail(net, DL_ERR_OOM, "out of host memory");
+    gr->net = net;
+    auto bail = [&](int code) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        if (gr->ws) (void)hipFree(gr->ws);
+        if (gr->d_fd) (void)hipFree(gr->d_fd);
+        delete gr;
+        return code;
+    };
+    Plan p = make_plan(net, g, false);
+    if (net->cfg.max_workspace_bytes && p.total > net->cfg.max_workspace_bytes)
+        return bail(fail(net, DL_ERR_OOM, "graph workspace of %zu bytes exceeds max_workspace_bytes", p.total));
+    if (hipMalloc(&gr->ws, p.total) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(net, DL_ERR_OOM, "hipMalloc(%zu) for the graph workspace failed", p.total));
+    }
+    if (hipMalloc(&gr->d_fd, sizeof(FrameDesc) * fd.size()) != hipSuccess ||
+        hipMemcpy(gr->d_fd, fd.data(), sizeof(FrameDesc) * fd.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(net, DL_ERR_DEVICE, "descriptor upload failed"));
+    p.ws = gr->ws;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(net, DL_ERR_DEVICE, "hipStreamCreate failed"));
+    const bool prof = net->profiling;
+    net->profiling = false;           // no timing events inside the graph
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        float *maps = reinterpret_cast<float *>(p.ws + p.maps);
+        rc = run_net(net, gr->d_fd, g, p, maps, cs);
+        if (!rc) rc = run_post(net, gr->d_fd, g, p, maps, d_out, cap, d_counts, cs);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        gr->graph = graph;
+        if (!rc && e2 != hipSuccess) rc = fail(net, DL_ERR_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e2));
+        if (!rc && hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess)
+            rc = fail(net, DL_ERR_DEVICE, "hipGraphInstantiate failed");
+    } else {
+        rc = fail(net, DL_ERR_DEVICE, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+    }
+    net->profiling = prof;
+    (void)hipStreamDestroy(cs);
+    if (rc) return bail(rc);
+    *out = gr;
     return DL_OK;
 }
 
@@ -515,6 +658,21 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     if (hipStreamCreateWithFlags(&net->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&net->compute_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(net, DL_ERR_DEVICE, "hipStreamCreate failed"));
+    {
+        // remaining receptive radius after each layer: stem, then every conv
+        std::vector<int> rad(1 + 2 * nb);
+        int r = 0;
+        for (int b = (int)nb - 1; b >= 0; --b) {
+            rad[1 + 2 * b + 1] = r;
+            r += net->dil[b];
+            rad[1 + 2 * b] = r;
+            r += net->dil[b];
+        }
+        rad[0] = r;
+        if (hipMalloc(&net->d_radius, rad.size() * sizeof(int)) != hipSuccess ||
+            hipMemcpy(net->d_radius, rad.data(), rad.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(net, DL_ERR_DEVICE, "radius upload failed"));
+    }
     if ((rc = ensure_packed(net))) return bail(rc);
     *out = net;
     return DL_OK;
@@ -535,6 +693,8 @@ void dl_destroy_net(dl_net *net)
     if (net->d_head) (void)hipFree(net->d_head);
     if (net->d_bias) (void)hipFree(net->d_bias);
     if (net->d_wpk) (void)hipFree(net->d_wpk);
+    if (net->d_gate_theta) (void)hipFree(net->d_gate_theta);
+    if (net->d_radius) (void)hipFree(net->d_radius);
     if (net->h_desc) (void)hipHostFree(net->h_desc);
     if (net->d_desc) (void)hipFree(net->d_desc);
     for (int i = 0; i < DESC_SLOTS; ++i)
@@ -575,7 +735,7 @@ int dl_localize_device(dl_net *net, const uint16_t *d_frames, int n, int h, int 
     std::vector<FrameDesc> fd;
     Geometry g;
     uniform_geometry(net, d_frames, n, h, w, fd, g);
-    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr);
+    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr, d_frames, n, h, w);
 }
 
 int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, float *d_maps)
@@ -587,7 +747,7 @@ int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w, v
     std::vector<FrameDesc> fd;
     Geometry g;
     uniform_geometry(net, d_frames, n, h, w, fd, g);
-    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), nullptr, 0, nullptr, d_maps);
+    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), nullptr, 0, nullptr, d_maps, d_frames, n, h, w);
 }
 
 static int check_rois(dl_net *net, const dl_roi *rois, int nroi)
@@ -742,7 +902,8 @@ int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n
         Geometry g;
         uniform_geometry(net, d_frames[buf], n, h, w, fd, g);
         const size_t room = written < cap ? cap - written : 0;
-        rc = localize_geom(net, fd, g, cs, room ? d_out : nullptr, room, d_counts + (size_t)k * (n + 1), nullptr);
+        rc = localize_geom(net, fd, g, cs, room ? d_out : nullptr, room, d_counts + (size_t)k * (n + 1), nullptr,
+                           d_frames[buf], n, h, w);
         if (rc) { cleanup(); return rc; }
         PCHK(hipEventRecord(ev_used[buf], cs));
         // results of this batch: counts then records (compute stream order)
@@ -816,16 +977,102 @@ int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, floa
     std::vector<FrameDesc> fd;
     Geometry g;
     uniform_geometry(net, nullptr, n, h, w, fd, g);
-    const Plan p = make_plan(net, g, true);
+    Plan p = make_plan(net, g, true);
     if ((rc = ensure_workspace(net, p.total, s))) return rc;
+    p.ws = net->ws;
     FrameDesc *d_fd = nullptr;
     const int slot = upload_desc(net, fd, s, &d_fd);
     if (slot < 0) return slot;
-    uint64_t *mask = reinterpret_cast<uint64_t *>(net->ws + p.mask);
-    uint32_t *rcnt = reinterpret_cast<uint32_t *>(net->ws + p.rc);
-    HIPCHK(net, launch_detect_mask(d_logit, 1, d_fd, g, tau, mask, rcnt, s));
+    uint64_t *mask = reinterpret_cast<uint64_t *>(p.ws + p.mask);
+    uint32_t *rcnt = reinterpret_cast<uint32_t *>(p.ws + p.rc);
+    HIPCHK(net, launch_detect_mask(d_logit, 1, d_fd, g, tau, nullptr, mask, rcnt, s));
     HIPCHK(net, launch_mask_to_u8(mask, d_fd, g, d_det, s));
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
+    return DL_OK;
+}
+
+int dl_graph_create(dl_net *net, const uint16_t *d_frames, int n, int h, int w, dl_emitter *d_out, size_t cap,
+                    uint32_t *d_counts, dl_graph **out)
+{
+    if (!out) return fail(net, DL_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
+    if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, d_frames, n, h, w, fd, g);
+    return graph_build(net, fd, g, d_out, cap, d_counts, out);
+}
+
+int dl_graph_create_rois(dl_net *net, const dl_roi *rois, int nroi, dl_emitter *d_out, size_t cap, uint32_t *d_counts,
+                         dl_graph **out)
+{
+    if (!out) return fail(net, DL_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_rois(net, rois, nroi);
+    if (rc) return rc;
+    if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
+    if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    roi_geometry(net, rois, nroi, fd, g);
+    return graph_build(net, fd, g, d_out, cap, d_counts, out);
+}
+
+int dl_graph_launch(dl_graph *g, void *stream)
+{
+    if (!g) return fail(nullptr, DL_ERR_INVALID_ARG, "graph is NULL");
+    dl_net *net = g->net;
+    int rc;
+    if ((rc = set_device(net))) return rc;
+    HIPCHK(net, hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return DL_OK;
+}
+
+void dl_graph_destroy(dl_graph *g)
+{
+    if (!g) return;
+    (void)hipSetDevice(g->net->dev);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ws) (void)hipFree(g->ws);
+    if (g->d_fd) (void)hipFree(g->d_fd);
+    delete g;
+}
+
+int dl_set_gate(dl_net *net, const float *theta, float threshold)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (!theta) {
+        net->gate_set = false;
+        return DL_OK;
+    }
+    if (!(threshold > 0.f && threshold < 1.f)) return fail(net, DL_ERR_INVALID_ARG, "gate threshold must lie in (0, 1)");
+    if (!finite_all(theta, DL_GATE_NPARAM)) return fail(net, DL_ERR_INVALID_ARG, "gate parameters contain NaN or Inf");
+    int rc;
+    if ((rc = set_device(net))) return rc;
+    if (!net->d_gate_theta) HIPCHK(net, hipMalloc(&net->d_gate_theta, DL_GATE_NPARAM * sizeof(float)));
+    HIPCHK(net, hipDeviceSynchronize());
+    HIPCHK(net, hipMemcpy(net->d_gate_theta, theta, DL_GATE_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    net->gate_tau = (float)std::log((double)threshold / (1.0 - (double)threshold));
+    net->gate_set = true;
+    return DL_OK;
+}
+
+int dl_gate_keep_map(dl_net *net, void *stream, uint8_t *d_keep, size_t cap, size_t *ntiles)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (!ntiles) return fail(net, DL_ERR_INVALID_ARG, "ntiles is NULL");
+    *ntiles = (size_t)net->last_gate_tiles;
+    if (net->last_gate_tiles == 0) return fail(net, DL_ERR_INVALID_ARG, "no gated run yet");
+    if (!d_keep || cap < *ntiles) return fail(net, DL_ERR_CAPACITY, "keep map needs %zu bytes", *ntiles);
+    int rc;
+    if ((rc = set_device(net))) return rc;
+    HIPCHK(net, hipMemcpyAsync(d_keep, net->ws + net->last_keep_off, *ntiles, hipMemcpyDeviceToDevice,
+                               static_cast<hipStream_t>(stream)));
     return DL_OK;
 }
 
@@ -861,6 +1108,65 @@ int dl_profile_read(dl_net *net, double *ms, int64_t *launches)
     }
     net->prof_pending.clear();
     return rc;
+}
+
+// ------------------------------------------------------------------ gate
+#define GCHK(expr)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail(nullptr, DL_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int dl_gate_pool(const uint16_t *d_frames, int n, int h, int w, float gain, float offset, float in_scale,
+                 void *stream, float *d_pooled)
+{
+    if (!d_frames || !d_pooled) return fail(nullptr, DL_ERR_INVALID_ARG, "NULL pointer");
+    if (n <= 0 || h <= 0 || w <= 0) return fail(nullptr, DL_ERR_INVALID_ARG, "n, h, w must be > 0");
+    if (h % DL_GATE_TILE || w % DL_GATE_TILE)
+        return fail(nullptr, DL_ERR_UNSUPPORTED, "gate tiles need h and w multiples of %d", DL_GATE_TILE);
+    if (!std::isfinite(gain) || !std::isfinite(offset) || !std::isfinite(in_scale) || !(gain > 0.f) || !(in_scale > 0.f))
+        return fail(nullptr, DL_ERR_INVALID_ARG, "bad gain/offset/in_scale");
+    GCHK(launch_gate_pool(d_frames, n, h, w, offset, gain * in_scale, d_pooled, static_cast<hipStream_t>(stream)));
+    return DL_OK;
+}
+
+int dl_gate_forward(const float *d_pooled, int ntiles, const float *d_theta, void *stream, float *d_logits)
+{
+    if (!d_pooled || !d_theta || !d_logits) return fail(nullptr, DL_ERR_INVALID_ARG, "NULL pointer");
+    if (ntiles <= 0) return fail(nullptr, DL_ERR_INVALID_ARG, "ntiles must be > 0");
+    GCHK(launch_gate(d_pooled, ntiles, d_theta, d_logits, nullptr, nullptr, static_cast<hipStream_t>(stream)));
+    return DL_OK;
+}
+
+int dl_gate_backward(const float *d_pooled, int ntiles, const float *d_theta, const float *d_dlogits,
+                     float *d_work, void *stream, float *d_logits, float *d_grad)
+{
+    if (!d_pooled || !d_theta || !d_dlogits || !d_work || !d_logits || !d_grad)
+        return fail(nullptr, DL_ERR_INVALID_ARG, "NULL pointer");
+    if (ntiles <= 0) return fail(nullptr, DL_ERR_INVALID_ARG, "ntiles must be > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GCHK(launch_gate(d_pooled, ntiles, d_theta, d_logits, d_dlogits, d_work, s));
+    GCHK(launch_gate_reduce(d_work, ntiles, d_grad, s));
+    return DL_OK;
+}
+
+int dl_gate_bce(const float *d_logits, const float *d_labels, int n, void *stream, float *d_loss, float *d_dlogits)
+{
+    if (!d_logits || !d_labels || (!d_loss && !d_dlogits)) return fail(nullptr, DL_ERR_INVALID_ARG, "NULL pointer");
+    if (n <= 0) return fail(nullptr, DL_ERR_INVALID_ARG, "n must be > 0");
+    GCHK(launch_gate_bce(d_logits, d_labels, n, d_loss, d_dlogits, static_cast<hipStream_t>(stream)));
+    return DL_OK;
+}
+
+int dl_gate_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, int n, int step, float lr, float b1,
+                 float b2, float eps, void *stream)
+{
+    if (!d_theta || !d_m || !d_v || !d_grad) return fail(nullptr, DL_ERR_INVALID_ARG, "NULL pointer");
+    if (n <= 0 || step <= 0) return fail(nullptr, DL_ERR_INVALID_ARG, "n and step must be > 0");
+    if (!(lr > 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+        return fail(nullptr, DL_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+    GCHK(launch_adam(d_theta, d_m, d_v, d_grad, n, lr, b1, b2, eps, step, static_cast<hipStream_t>(stream)));
+    return DL_OK;
 }
 
 }  // extern "C"

@@ -127,7 +127,7 @@ k_conv(ConvArgs a, Geometry geo)
     const int kq = lane >> 4;      // K lane group
     const int dd = a.d;
 
-    const int64_t T = geo.total_tiles;
+    const int64_t T = a.list ? (int64_t)*a.list_count : geo.total_tiles;
     const int xcd = blockIdx.x % NXCD;
     const int slot = blockIdx.x / NXCD;
     const int nslot = gridDim.x / NXCD;
@@ -135,7 +135,8 @@ k_conv(ConvArgs a, Geometry geo)
     const int64_t t0 = (int64_t)xcd * chunk;
     const int64_t t1 = t0 + chunk < T ? t0 + chunk : T;
 
-    for (int64_t t = t0 + slot; t < t1; t += nslot) {
+    for (int64_t ti = t0 + slot; ti < t1; ti += nslot) {
+        const int64_t t = a.list ? (int64_t)a.list[ti] : ti;
         const int f = find_frame(a.fd, geo.nf, t, [](const FrameDesc &d) { return d.tile_start; });
         const FrameDesc fd = a.fd[f];
         const int64_t local = t - fd.tile_start;

@@ -28,7 +28,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 template <int C, bool BF16OUT>
 __global__ void __launch_bounds__(256)
 k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
-       const float *__restrict__ b, float offset, float scale, void *__restrict__ act)
+       const float *__restrict__ b, float offset, float scale, void *__restrict__ act,
+       const uint8_t *__restrict__ keep, int radius)
 {
     __shared__ float sw[C * 9];
     __shared__ float sb[C];
@@ -42,9 +43,12 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
     const int y = (int)(row - fd.row_start);
     const int H = fd.h, W = fd.w;
     constexpr int CG = C / 4;
+    // gated runs: only rows / 64-pixel segments within `radius` of a kept tile
+    if (!near_kept(keep, fd, y, y, 0, W - 1, radius)) return;
     for (int i = threadIdx.x; i < W * CG; i += 256) {
         const int x = i / CG;
         const int cg = i - x * CG;
+        if (keep && !near_kept(keep, fd, y, y, x & ~63, min(W - 1, (x & ~63) + 63), radius)) continue;
         float xin[9];
 #pragma unroll
         for (int u = 0; u < 3; ++u)
@@ -77,12 +81,12 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
 
 template <int C>
 hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                  float offset, float scale, void *act, int bf16, hipStream_t s)
+                  float offset, float scale, void *act, int bf16, const uint8_t *keep, int radius, hipStream_t s)
 {
     if (bf16)
-        hipLaunchKernelGGL((k_stem<C, true>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset, scale, act);
+        hipLaunchKernelGGL((k_stem<C, true>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset, scale, act, keep, radius);
     else
-        hipLaunchKernelGGL((k_stem<C, false>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset, scale, act);
+        hipLaunchKernelGGL((k_stem<C, false>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset, scale, act, keep, radius);
     return hipGetLastError();
 }
 
@@ -95,7 +99,8 @@ hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const 
 // row_counts for the scan.
 __global__ void __launch_bounds__(256)
 k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__restrict__ fdp, int nf,
-              float tau, uint64_t *__restrict__ mask, uint32_t *__restrict__ row_counts)
+              float tau, const uint8_t *__restrict__ keep, uint64_t *__restrict__ mask,
+              uint32_t *__restrict__ row_counts)
 {
     const int64_t row = blockIdx.x;
     const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
@@ -108,7 +113,10 @@ k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__res
     for (int xb = wave * 64; xb < W; xb += 256) {
         const int x = xb + lane;
         bool det = false;
-        if (x < W) {
+        // gated runs: pixels of skipped gate tiles are neither detected nor neighbours
+        const uint8_t *kp = keep ? keep + fd.keep_start : nullptr;
+        auto kept = [&](int yy, int xx) { return !kp || kp[(yy / GATE_TILE) * fd.gtx + xx / GATE_TILE]; };
+        if (x < W && kept(y, x)) {
             const int64_t idx = (int64_t)y * W + x;
             const float v = L[idx];
             det = v > tau;
@@ -120,6 +128,7 @@ k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__res
                         if (di == 0 && dj == 0) continue;
                         const int yy = y + di, xx = x + dj;
                         if ((unsigned)yy >= (unsigned)H || (unsigned)xx >= (unsigned)W) continue;
+                        if (!kept(yy, xx)) continue;
                         const float nv = L[(int64_t)yy * W + xx];
                         // neighbours before (y, x) in raster order win ties
                         const bool earlier = di < 0 || (di == 0 && dj < 0);
@@ -239,24 +248,79 @@ k_mask_to_u8(const uint64_t *__restrict__ mask, const FrameDesc *__restrict__ fd
     }
 }
 
+// ----------------------------------------------------------- gated runs
+__global__ void __launch_bounds__(256)
+k_gate_keep(const float *__restrict__ logits, int64_t n, float tau, uint8_t *__restrict__ keep)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) keep[t] = logits[t] > tau ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(64)
+k_zero_u32(uint32_t *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// One thread per conv tile: append the tile to the list of every layer whose
+// radius brings it within reach of a kept gate tile.  List order depends on
+// atomic arrival, which changes only which workgroup computes a tile.
+__global__ void __launch_bounds__(256)
+k_active_lists(const FrameDesc *__restrict__ fdp, int nf, int64_t T, int rows, const uint8_t *__restrict__ keep,
+               const int *__restrict__ radius, int nlayers, int32_t *__restrict__ lists, uint32_t *__restrict__ counts)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= T) return;
+    const int f = find_frame(fdp, nf, t, [](const FrameDesc &d) { return d.tile_start; });
+    const FrameDesc fd = fdp[f];
+    const int64_t local = t - fd.tile_start;
+    const int ty = (int)(local / fd.tiles_x), tx = (int)(local - (int64_t)ty * fd.tiles_x);
+    const int y0 = ty * rows, y1 = min(fd.h - 1, y0 + rows - 1);
+    const int x0 = tx * TILE_COLS, x1 = min(fd.w - 1, x0 + TILE_COLS - 1);
+    for (int l = 0; l < nlayers; ++l)
+        if (near_kept(keep, fd, y0, y1, x0, x1, radius[l])) {
+            const uint32_t i = atomicAdd(&counts[l], 1u);
+            lists[(int64_t)l * T + i] = (int32_t)t;
+        }
+}
+
 }  // namespace
 
+hipError_t launch_gate_keep(const float *logits, int64_t n, float tau, uint8_t *keep, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gate_keep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, logits, n, tau, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uint8_t *keep, const int *radius,
+                               int nlayers, int32_t *lists, uint32_t *counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counts, nlayers);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_active_lists, dim3((unsigned)((g.total_tiles + 255) / 256)), dim3(256), 0, s, fd, g.nf,
+                       g.total_tiles, g.tile_rows, keep, radius, nlayers, lists, counts);
+    return hipGetLastError();
+}
+
 hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                       float offset, float scale, void *act, int act_bf16, hipStream_t s)
+                       float offset, float scale, void *act, int act_bf16, const uint8_t *keep, int radius,
+                       hipStream_t s)
 {
     switch (C) {
-    case 16: return stem_c<16>(fd, g, w, b, offset, scale, act, act_bf16, s);
-    case 32: return stem_c<32>(fd, g, w, b, offset, scale, act, act_bf16, s);
-    case 48: return stem_c<48>(fd, g, w, b, offset, scale, act, act_bf16, s);
-    case 64: return stem_c<64>(fd, g, w, b, offset, scale, act, act_bf16, s);
+    case 16: return stem_c<16>(fd, g, w, b, offset, scale, act, act_bf16, keep, radius, s);
+    case 32: return stem_c<32>(fd, g, w, b, offset, scale, act, act_bf16, keep, radius, s);
+    case 48: return stem_c<48>(fd, g, w, b, offset, scale, act, act_bf16, keep, radius, s);
+    case 64: return stem_c<64>(fd, g, w, b, offset, scale, act, act_bf16, keep, radius, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_detect_mask(const float *maps, int planes, const FrameDesc *fd, const Geometry &g, float tau,
-                              uint64_t *mask, uint32_t *row_counts, hipStream_t s)
+                              const uint8_t *keep, uint64_t *mask, uint32_t *row_counts, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_detect_mask, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, fd, g.nf, tau, mask, row_counts);
+    hipLaunchKernelGGL(k_detect_mask, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, fd, g.nf, tau, keep,
+                       mask, row_counts);
     return hipGetLastError();
 }
 

@@ -179,11 +179,13 @@ def _render_one(h: int, w: int, model: FrameModel, rng: np.random.Generator):
 
 
 def render_frames(n: int, h: int, w: int, model: FrameModel | str, seed: int,
-                  frame_ids: Optional[Sequence[int]] = None, with_truth: bool = False):
+                  frame_ids: Optional[Sequence[int]] = None, with_truth: bool = False,
+                  workers: Optional[int] = None):
     """Render ``n`` frames of ``h x w`` uint16 (frame k seeded by ``(seed, k)``).
 
     ``frame_ids`` selects which frame indices of the seeded sequence to render
     (default ``range(n)``), so any frame can be regenerated on its own.
+    ``workers`` > 1 renders frames in forked processes (default: automatic).
     """
     if isinstance(model, str):
         model = CONFIG_MODELS[model]
@@ -191,7 +193,8 @@ def render_frames(n: int, h: int, w: int, model: FrameModel | str, seed: int,
     out = np.empty((len(ids), h, w), dtype=np.uint16)
     truths = []
     jobs = [(h, w, model, int(seed), int(fid)) for fid in ids]
-    workers = min(len(ids), _pool_size()) if len(ids) * h * w >= (1 << 22) else 1
+    if workers is None:
+        workers = min(len(ids), _pool_size()) if len(ids) * h * w >= (1 << 22) else 1
     if workers > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:

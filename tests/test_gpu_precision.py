@@ -1,0 +1,99 @@
+"""Reduced-precision form: BF16 block convolutions with FP32 accumulation.
+
+* Quantisation logic, pinned bit for bit: with small-integer weights and
+  inputs every product and sum is exact in FP32 and FP64, so the GPU's BF16
+  form must equal the oracle's BF16 emulation exactly -- including the rounding
+  of stored integers above 256, which bfloat16 cannot all represent.
+* Realistic weights: the GPU stays as close to the emulation as bfloat16
+  noise allows (differences start where FP32 and FP64 accumulation land on
+  opposite sides of a bfloat16 rounding boundary and then propagate).
+* Accuracy against the exact FP64 oracle (tiny workload): emitters matched
+  one-to-one within 1 px; recall, precision and RMS offset differences are
+  printed and held to the measured level of the oracle's own BF16 emulation.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import smlm_synth as S
+from tests.parity import map_rel_err, match_by_distance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no HIP device", allow_module_level=True)
+import paper_2410_02314_amd as dl  # noqa: E402
+from tests.test_gpu_fp32 import gpu_localize, gpu_maps  # noqa: E402
+
+
+def integer_net(C=16, dil=(1, 2), seed=15):
+    spec = S.NetSpec("int", C, dil, in_scale=1.0)
+    r = np.random.default_rng(seed)
+    w = {}
+    for n, s in S.tensor_layout(spec):
+        if n.endswith(("w1", "w2")):
+            w[n] = (r.integers(-1, 3, size=s) * (r.random(s) < 0.08)).astype(np.float32)
+        elif n == "stem.w":
+            w[n] = r.integers(0, 2, size=s).astype(np.float32)
+        else:
+            w[n] = r.integers(-1, 2, size=s).astype(np.float32)
+    return spec, w
+
+
+def test_bf16_integer_net_bit_exact_vs_emulation():
+    spec, w = integer_net()
+    r = np.random.default_rng(3)
+    frames = (100 + r.integers(0, 20, size=(2, 37, 70))).astype(np.uint16)
+    net = dl.Net(S.serialize_weights(spec, w), precision="bf16", gain=1.0, offset=100.0)
+    got = gpu_maps(net, frames)
+    emu = np.stack([oracle.net_maps(f, spec, w, gain=1.0, offset=100.0, quant="bf16") for f in frames])
+    ex = np.stack([oracle.net_maps(f, spec, w, gain=1.0, offset=100.0) for f in frames])
+    assert np.abs(ex).max() < 2 ** 24                 # every sum exact in FP32 too
+    assert not np.array_equal(emu, ex)                # rounding of stored values really happens
+    assert np.array_equal(got, emu)
+
+
+def _setup(prec, name="A", seed=1, frames_seed=1001, n=4, h=128, w=128, model="tiny"):
+    spec, wts = S.make_net(name, seed)
+    net = dl.Net(S.serialize_weights(spec, wts), precision=prec)
+    frames = S.render_frames(n, h, w, model, frames_seed)
+    return spec, wts, net, frames
+
+
+def test_bf16_close_to_emulation():
+    spec, wts, net, frames = _setup("bf16")
+    got = gpu_maps(net, frames)
+    emu = oracle.net_maps_batch(frames, spec, wts, quant="bf16")
+    ex = oracle.net_maps_batch(frames, spec, wts)
+    e_gpu = map_rel_err(got, emu)
+    e_emu = map_rel_err(emu, ex)
+    print("gpu vs emulation", e_gpu, "emulation vs exact", e_emu)
+    assert np.all(e_gpu <= 2.0 * e_emu + 1e-4)
+
+
+@pytest.mark.parametrize("name,model,n,side", [("A", "tiny", 4, 128), ("B", "full", 2, 256)])
+def test_bf16_accuracy_vs_fp64(name, model, n, side):
+    spec, wts, net, frames = _setup("bf16", name, 1 if name == "A" else 2, 1001, n, side, side, model)
+    ref = oracle.localize(frames, spec, wts)
+    emu = oracle.localize(frames, spec, wts, quant="bf16")
+    rec, counts = gpu_localize(net, frames)
+    got = match_by_distance(rec, ref, 1.0)
+    base = match_by_distance(emu, ref, 1.0)
+    print({"gpu_bf16": got, "oracle_bf16_emulation": base})
+    assert got["recall"] >= min(0.99, base["recall"] - 0.01)
+    assert got["precision"] >= min(0.99, base["precision"] - 0.01)
+    assert got["rms_dx_px"] <= max(0.15, 1.5 * base["rms_dx_px"])
+    assert got["rms_dy_px"] <= max(0.15, 1.5 * base["rms_dy_px"])
+
+
+def test_bf16_full_size_tiling_invariance_and_window():
+    """Net B, BF16, a 2048 x 2048 frame; tile shape does not change the result."""
+    spec, wts, net, frames = _setup("bf16", "B", 2, 1002, n=1, h=2048, w=2048, model="full")
+    got = gpu_maps(net, frames)
+    net4 = dl.Net(S.serialize_weights(spec, wts), precision="bf16", tile_rows=4)
+    assert np.array_equal(got, gpu_maps(net4, frames))
+    y0, x0, hh, ww = 900, 1100, 32, 48
+    emu = oracle.net_maps_window(frames[0], spec, wts, y0, x0, hh, ww, quant="bf16")
+    ex = oracle.net_maps_window(frames[0], spec, wts, y0, x0, hh, ww)
+    assert np.all(map_rel_err(got[0, :, y0:y0 + hh, x0:x0 + ww], emu) <= 2.0 * map_rel_err(emu, ex) + 1e-4)
