@@ -56,6 +56,10 @@ def main():
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--cpu-sample", type=int, default=640, help="side of the oracle's sample crop (0 = skip)")
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--workload", default="full", choices=["full", "tiny", "rois", "sparse", "pipeline"],
+                    help="full: the headline (16 x 2048^2, net B); tiny: 4 x 128^2 net A; rois: 256 uneven "
+                         "ROIs, net A; sparse: gated BF16 net B on 64 x 2048^2 sparse frames; pipeline: "
+                         "host frames with H2D overlapped on a side stream")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes rendering the frames (0 = automatic; 1 under profilers)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -69,6 +73,11 @@ def main():
         sys.exit(2)
 
     import smlm_synth as S
+
+    if args.workload != "full":
+        from bench_workloads import run_workload
+        run_workload(args)
+        return
 
     # inputs first, before anything touches the GPU (workers are forked)
     spec, w = S.make_net("B", 2)

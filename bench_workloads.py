@@ -1,0 +1,204 @@
+"""Secondary benchmark workloads of bench.py (``--workload``): the small
+latency-bound batch, the uneven ROI batch, the gated sparse batch and the
+host-to-device pipelined run.  Each prints one JSON line in bench.py's
+format.  Timing: HIP events on the launch stream around K steps after W
+warm-up steps; inputs resident in HBM unless the workload says otherwise."""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from bench import METRIC, PEAKS, cpu_threads, log
+
+
+def _timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _line(args, value, ms, config, extra):
+    res = {"metric": METRIC, "value": round(value, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.precision, "data": "synthetic (seeded SMLM frames)",
+           "config": config, **extra}
+    print(json.dumps(res), flush=True)
+
+
+def run_workload(args):
+    import smlm_synth as S
+    if args.workload == "tiny":
+        return tiny(args, S)
+    if args.workload == "rois":
+        return rois(args, S)
+    if args.workload == "sparse":
+        return sparse(args, S)
+    if args.workload == "pipeline":
+        return pipeline(args, S)
+    raise SystemExit(f"unknown workload {args.workload}")
+
+
+def tiny(args, S):
+    """4 x 128^2 frames, net A: eager launches and one HIP-graph replay per step."""
+    frames = S.render_frames(4, 128, 128, "tiny", 1001)
+    import torch
+    import paper_2410_02314_amd as dl
+    spec, w = S.make_net("A", 1)
+    net = dl.Net(S.serialize_weights(spec, w), precision=args.precision)
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(frames).to(dev)
+    out = torch.empty((8192, 8), dtype=torch.int32, device=dev)
+    counts = torch.zeros(5, dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream()
+    steps = max(args.steps, 200)
+    ms_eager = _timed(lambda: net.localize_device(d, out, counts, st), steps, max(args.warmup, 20), st)
+    g = net.graph(d, out, counts)
+    ms_graph = _timed(lambda: g.launch(st), steps, max(args.warmup, 20), st)
+    px = 4 * 128 * 128
+    _line(args, px / (ms_graph * 1e-3) / 1e6, ms_graph,
+          {"workload": "4 x 128x128 uint16 frames, 2D Gaussian PSF, net A (C=32, d=1,2,4)", "net": "A",
+           "precision": args.precision, "frames": 4, "height": 128, "width": 128},
+          {"eager_ms_per_step": round(ms_eager, 4), "graph_ms_per_step": round(ms_graph, 4),
+           "eager_mpx_s": round(px / (ms_eager * 1e-3) / 1e6, 3), "emitters_per_step": int(counts[4].item())})
+    g.close()
+
+
+def rois(args, S):
+    """256 ROIs with sides from {128, ..., 1024}, net A, one call per step (and a graph)."""
+    rois_np = S.render_rois(256, "rois", 1004)
+    import torch
+    import paper_2410_02314_amd as dl
+    spec, w = S.make_net("A", 1)
+    net = dl.Net(S.serialize_weights(spec, w), precision=args.precision, tile_rows=args.tile_rows)
+    dev = torch.device("cuda:0")
+    d = [torch.from_numpy(r).to(dev) for r in rois_np]
+    px = sum(r.size for r in rois_np)
+    cap = px // 32
+    out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
+    counts = torch.zeros(257, dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream()
+    net.profile(True)
+    ms = _timed(lambda: net.localize_rois_device(d, out, counts, st), args.steps, args.warmup, st)
+    prof = net.profile_read()
+    net.profile(False)
+    g = net.graph_rois(d, out, counts)
+    ms_graph = _timed(lambda: g.launch(st), args.steps, args.warmup, st)
+    conv_ms, conv_n = prof["conv"]
+    flop = 2.0 * 9 * spec.C * spec.C * px
+    ach = flop / (conv_ms / conv_n * 1e-3) / 1e12
+    _line(args, px / (ms * 1e-3) / 1e6, ms,
+          {"workload": f"256 uneven ROIs (sides 128..1024), {px / 1e6:.1f} Mpx, net A", "net": "A",
+           "precision": args.precision, "frames": 256, "pixels": px},
+          {"graph_ms_per_step": round(ms_graph, 3), "emitters_per_step": int(counts[256].item()),
+           "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAKS[args.precision],
+                        "unit": "TFLOP/s", "frac": round(ach / PEAKS[args.precision], 4), "traffic": None}})
+    g.close()
+
+
+def sparse(args, S):
+    """Tile gate on sparse frames: train the gate on separately seeded frames
+    (labels = the ungated BF16 net's detections), then time gated vs ungated
+    BF16 net B on 64 x 2048^2 frames and report skip, speedup and recall."""
+    n_eval, side = args.frames if args.frames != 16 else 64, args.size
+    t0 = time.time()
+    ev = S.render_frames(n_eval, side, side, "sparse", 1005, workers=args.gen_workers or None)
+    n_train = 313                                    # 313 frames x 64 tiles >= 20,000 tiles
+    train_frames = [S.render_frames(16, side, side, "sparse", 2005, frame_ids=range(k, min(k + 16, n_train)),
+                                    workers=args.gen_workers or None) for k in range(0, n_train, 16)]
+    log(f"generated frames in {time.time() - t0:.1f}s")
+    import torch
+    import paper_2410_02314_amd as dl
+    from paper_2410_02314_amd import gate_train as GT
+    dev = torch.device("cuda:0")
+    spec, w = S.make_net("B", 2)
+    blob = S.serialize_weights(spec, w)
+    net = dl.Net(blob, precision="bf16")
+    t0 = time.time()
+    pooled, labels = GT.labelled_tiles(net, iter(train_frames), dev)
+    pooled, labels = pooled[:20000], labels[:20000]
+    theta0 = S.gate_flat(S.gate_init(3005))
+    res = GT.train(pooled, labels, theta0, epochs=20, batch=256, lr=3e-3)
+    thr = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.995)
+    log(f"gate trained in {time.time() - t0:.1f}s: {res.history[-1]}; threshold {thr:.4f}")
+    d = torch.from_numpy(ev).to(dev)
+    cap = n_eval * side * side // 64
+    st = torch.cuda.current_stream()
+
+    def run(gate_theta, thr=0.05):
+        g = dl.Net(blob, precision="bf16", flags=dl.DL_FLAG_GATE if gate_theta is not None else 0)
+        if gate_theta is not None:
+            g.set_gate(gate_theta, thr)
+        out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
+        counts = torch.zeros(n_eval + 1, dtype=torch.int32, device=dev)
+        ms = _timed(lambda: g.localize_device(d, out, counts, st), args.steps, args.warmup, st)
+        rec = dl.emitters_from_device(out, min(int(counts[-1].item()), cap))
+        keep = None
+        if gate_theta is not None:
+            k = torch.zeros(n_eval * (side // 256) ** 2, dtype=torch.uint8, device=dev)
+            g.gate_keep_map(k)
+            torch.cuda.synchronize()
+            keep = k.cpu().numpy().astype(bool)
+        return ms, rec, keep
+
+    ms0, rec0, _ = run(None)
+    ms1, rec1, keep = run(res.theta, thr)
+    ms5, rec5, keep5 = run(res.theta, 0.05)
+    k0 = {(a, b, c) for a, b, c in zip(rec0["frame"], rec0["row"], rec0["col"])}
+    k1 = {(a, b, c) for a, b, c in zip(rec1["frame"], rec1["row"], rec1["col"])}
+    k5 = {(a, b, c) for a, b, c in zip(rec5["frame"], rec5["row"], rec5["col"])}
+    px = n_eval * side * side
+    _line(args, px / (ms1 * 1e-3) / 1e6, ms1,
+          {"workload": f"{n_eval} x {side}x{side} sparse frames (30-70% empty 256^2 tiles), gated BF16 net B",
+           "net": "B", "precision": "bf16",
+           "gate": f"2 conv x 8 ch + mean pool, threshold {thr:.4f} (99.5% held-out tile recall)",
+           "frames": n_eval},
+          {"ungated_ms_per_step": round(ms0, 3), "ungated_mpx_s": round(px / (ms0 * 1e-3) / 1e6, 2),
+           "speedup_vs_ungated": round(ms0 / ms1, 3), "skipped_tile_fraction": round(float(1 - keep.mean()), 4),
+           "recall_vs_ungated": round(len(k0 & k1) / max(1, len(k0)), 5), "extra_border_detections": len(k1 - k0),
+           "at_threshold_0.05": {"skipped_tile_fraction": round(float(1 - keep5.mean()), 4),
+                                 "speedup_vs_ungated": round(ms0 / ms5, 3),
+                                 "recall_vs_ungated": round(len(k0 & k5) / max(1, len(k0)), 5)},
+           "gate_val": res.history[-1]})
+
+
+def pipeline(args, S):
+    """Host frames: batches copied host->device on a side stream while the
+    previous batch is processed, against the serial copy-then-compute order."""
+    nb = 4
+    frames = S.render_frames(args.frames * nb, args.size, args.size, "full", 1002,
+                             workers=args.gen_workers or None).reshape(nb, args.frames, args.size, args.size)
+    import torch
+    import paper_2410_02314_amd as dl
+    spec, w = S.make_net("B", 2)
+    net = dl.Net(S.serialize_weights(spec, w), precision=args.precision)
+    import ctypes
+    pin = dl.host_alloc(frames.nbytes)               # pinned: copied to the GPU without staging
+    buf = (ctypes.c_char * frames.nbytes).from_address(pin)
+    arr = np.frombuffer(buf, dtype=np.uint16).reshape(frames.shape)
+    arr[...] = frames
+    out = {}
+    for overlap in (1, 0):
+        net.localize_pipelined(arr, overlap=bool(overlap))          # warm-up
+        t0 = time.perf_counter()
+        rec = net.localize_pipelined(arr, overlap=bool(overlap))
+        out[overlap] = (time.perf_counter() - t0, len(rec))
+    dl.host_free(pin)
+    px = frames.size
+    _line(args, px / out[1][0] / 1e6, out[1][0] * 1e3 / nb,
+          {"workload": f"{nb} batches of {args.frames} x {args.size}^2 host frames (pinned), net B, "
+                       f"H2D on a side stream overlapped with compute", "net": "B", "precision": args.precision},
+          {"serial_mpx_s": round(px / out[0][0] / 1e6, 2), "overlap_speedup": round(out[0][0] / out[1][0], 3),
+           "emitters": out[1][1]})

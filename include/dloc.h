@@ -178,6 +178,17 @@ int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *str
  * d_maps + 5 * sum_{j<k} h_j * w_j. */
 int dl_maps_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, float *d_maps);
 
+/* ---- autotuning ----
+ * Time the network (no post-processing) on the given batch for every
+ * candidate convolution tile shape (lattice rows per workgroup: 8, then 4),
+ * `reps` times each after one warm-up, with HIP events on `stream`; keep the
+ * fastest on the handle (as cfg.tile_rows) and return it in *best_rows.
+ * ms (may be NULL) receives the mean time per pass of each candidate.
+ * Synchronous. */
+#define DL_TUNE_CANDIDATES 2
+int dl_autotune(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, int reps,
+                int32_t *best_rows, float *ms /*[DL_TUNE_CANDIDATES]*/);
+
 /* ---- HIP graphs ----
  * Capture the whole localization of one fixed batch (frames at d_frames, or
  * the ROI list) into a HIP graph that owns its workspace and descriptors.

@@ -95,6 +95,7 @@ def _load():
         "dl_graph_create": (I, [P, P, I, I, I, P, Z, P, ctypes.POINTER(P)]),
         "dl_graph_create_rois": (I, [P, ctypes.POINTER(DLRoi), I, P, Z, P, ctypes.POINTER(P)]),
         "dl_graph_launch": (I, [P, P]),
+        "dl_autotune": (I, [P, P, I, I, I, P, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]),
         "dl_graph_destroy": (None, [P]),
         "dl_gate_keep_map": (I, [P, P, P, Z, ctypes.POINTER(Z)]),
         "dl_gate_pool": (I, [P, I, I, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P]),
@@ -294,6 +295,15 @@ class Net:
         self._rc(_lib.dl_graph_create_rois(self.handle, arr, len(rois), _ptr(out), cap, _ptr(counts),
                                            ctypes.byref(g)))
         return Graph(self, g, (rois, out, counts))
+
+    def autotune(self, frames, reps: int = 3, stream=None):
+        """Pick the fastest convolution tile shape for this batch shape; returns
+        (rows, {rows: ms per pass})."""
+        n, h, w = frames.shape
+        best = ctypes.c_int32()
+        ms = (ctypes.c_float * 2)()
+        self._rc(_lib.dl_autotune(self.handle, _ptr(frames), n, h, w, _stream(stream), reps, ctypes.byref(best), ms))
+        return int(best.value), {8: float(ms[0]), 4: float(ms[1])}
 
     def set_gate(self, theta, threshold: float = 0.05):
         """Attach gate parameters (host array of 673 floats, or None to detach)."""

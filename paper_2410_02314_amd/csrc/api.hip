@@ -43,6 +43,8 @@ struct dl_net {
     float *d_head = nullptr;        // w [5][C] then b [5]
     float *d_bias = nullptr;        // [nb][2][C]
     void *d_wpk = nullptr;          // packed conv weights [nb][2][...]
+    float *d_wscale = nullptr;      // FP8 per-output-channel weight scales [nb][2][C]
+    int *d_dil = nullptr;           // dilations [nb]
     size_t wpk_stride = 0;
     int packed_precision = -1;
 
@@ -110,8 +112,8 @@ int check_config(dl_net *net, const dl_config *c)
         return fail(net, DL_ERR_INVALID_ARG, "gain must be finite and > 0");
     if (!std::isfinite(c->offset)) return fail(net, DL_ERR_INVALID_ARG, "offset must be finite");
     if (c->device < 0) return fail(net, DL_ERR_INVALID_ARG, "device must be >= 0");
-    if (!(c->tile_rows == 0 || c->tile_rows == 4 || c->tile_rows == 8 || c->tile_rows == 16))
-        return fail(net, DL_ERR_INVALID_ARG, "tile_rows must be 0, 4, 8 or 16");
+    if (!(c->tile_rows == 0 || c->tile_rows == 4 || c->tile_rows == 8))
+        return fail(net, DL_ERR_INVALID_ARG, "tile_rows must be 0, 4 or 8");
     if (c->flags & ~DL_FLAG_GATE) return fail(net, DL_ERR_INVALID_ARG, "unknown flag bits");
     return DL_OK;
 }
@@ -122,34 +124,35 @@ int tile_rows_of(const dl_net *net) { return net->cfg.tile_rows ? net->cfg.tile_
 void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, const uint16_t *const *data,
                     const int64_t *strides, std::vector<FrameDesc> &fd, Geometry &g)
 {
-    const int rows = tile_rows_of(net);
     fd.resize(n);
     g = Geometry{};
     g.nf = n;
-    g.tile_rows = rows;
+    conv_tile_shape(net->C, net->cfg.precision, tile_rows_of(net), &g.tr, &g.tc);
     for (int f = 0; f < n; ++f) {
         FrameDesc &d = fd[f];
+        std::memset(&d, 0, sizeof d);
         d.data = data[f];
         d.stride = strides[f];
         d.h = hs[f];
         d.w = ws_[f];
         d.px_off = g.total_px;
         d.row_start = g.total_rows;
-        d.tile_start = g.total_tiles;
         d.mask_start = g.total_words;
-        d.tiles_x = (d.w + TILE_COLS - 1) / TILE_COLS;
         d.words = (d.w + 63) / 64;
         d.gtx = d.w / GATE_TILE;
         d.gty = d.h / GATE_TILE;
         d.keep_start = g.gate_tiles;
-        d.pad_ = 0;
+        for (int b = 0; b < net->nb; ++b) {
+            d.tile_start[b] = g.tiles[b];
+            g.tiles[b] += conv_tiles(d.h, d.w, net->dil[b], g.tr, g.tc);
+        }
         g.gate_tiles += (int64_t)d.gtx * d.gty;
         g.total_px += (int64_t)d.h * d.w;
         g.total_rows += d.h;
-        g.total_tiles += (int64_t)((d.h + rows - 1) / rows) * d.tiles_x;
         g.total_words += (int64_t)d.h * d.words;
         if (d.w > g.maxw) g.maxw = d.w;
     }
+    for (int b = 0; b < net->nb; ++b) g.max_tiles = std::max(g.max_tiles, g.tiles[b]);
 }
 
 struct Plan {
@@ -157,6 +160,8 @@ struct Plan {
     size_t act0 = 0, act1 = 0, maps = 0, mask = 0, rc = 0, roff = 0, total = 0;
     bool gated = false;
     size_t pooled = 0, glog = 0, keep = 0, lists = 0, lcount = 0;
+    size_t amax = 0;                // FP8: per-frame activation maxima, one row per producing layer
+    bool fp8 = false;
 };
 
 bool gated_run(const dl_net *net) { return (net->cfg.flags & DL_FLAG_GATE) && net->gate_set; }
@@ -172,13 +177,17 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     p.mask = o; o = align_up(o + (size_t)g.total_words * 8);
     p.rc = o; o = align_up(o + (size_t)g.total_rows * 4);
     p.roff = o; o = align_up(o + (size_t)(g.total_rows + 1) * 4);
+    if (net->cfg.precision == DL_FP8) {
+        p.fp8 = true;
+        p.amax = o; o = align_up(o + (size_t)2 * net->nb * g.nf * 4);
+    }
     if (gated_run(net)) {
         const int L = 2 * net->nb;
         p.gated = true;
         p.pooled = o; o = align_up(o + (size_t)g.gate_tiles * 4096 * 4);
         p.glog = o; o = align_up(o + (size_t)g.gate_tiles * 4);
         p.keep = o; o = align_up(o + (size_t)g.gate_tiles);
-        p.lists = o; o = align_up(o + (size_t)L * g.total_tiles * 4);
+        p.lists = o; o = align_up(o + (size_t)L * g.max_tiles * 4);
         p.lcount = o; o = align_up(o + (size_t)L * 4);
     }
     p.total = o;
@@ -239,18 +248,20 @@ int upload_desc(dl_net *net, const std::vector<FrameDesc> &fd, hipStream_t s, Fr
 int ensure_packed(dl_net *net)
 {
     if (net->packed_precision == net->cfg.precision) return DL_OK;
-    if (net->cfg.precision != DL_FP32 && net->cfg.precision != DL_BF16)
-        return fail(net, DL_ERR_UNSUPPORTED, "precision %d is not available in this build", net->cfg.precision);
     const int C = net->C;
     const size_t per = conv_packed_bytes(C, net->cfg.precision);
     const size_t stride = align_up(per);
     std::vector<char> host(stride * net->nb * 2);
+    std::vector<float> wscale((size_t)net->nb * 2 * C, 0.f);
     const float *p = net->params.data() + (size_t)C * 9 + C;
     for (int b = 0; b < net->nb; ++b)
         for (int k = 0; k < 2; ++k) {
-            pack_conv_weights(C, net->cfg.precision, p, host.data() + (size_t)(b * 2 + k) * stride);
+            pack_conv_weights(C, net->cfg.precision, p, host.data() + (size_t)(b * 2 + k) * stride,
+                              wscale.data() + (size_t)(b * 2 + k) * C);
             p += (size_t)C * C * 9 + C;
         }
+    if (!net->d_wscale) HIPCHK(net, hipMalloc(&net->d_wscale, wscale.size() * sizeof(float)));
+    HIPCHK(net, hipMemcpy(net->d_wscale, wscale.data(), wscale.size() * sizeof(float), hipMemcpyHostToDevice));
     if (net->d_wpk) {
         HIPCHK(net, hipDeviceSynchronize());
         HIPCHK(net, hipFree(net->d_wpk));
@@ -310,7 +321,7 @@ int run_gate(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * net->in_scale, pooled, s));
     HIPCHK(net, launch_gate(pooled, (int)g.gate_tiles, net->d_gate_theta, glog, nullptr, nullptr, s));
     HIPCHK(net, launch_gate_keep(glog, g.gate_tiles, net->gate_tau, keep, s));
-    HIPCHK(net, launch_active_lists(d_fd, g, keep, net->d_radius + 1, 2 * net->nb,
+    HIPCHK(net, launch_active_lists(d_fd, g, keep, net->d_radius + 1, net->d_dil, 2 * net->nb,
                                     reinterpret_cast<int32_t *>(p.ws + p.lists),
                                     reinterpret_cast<uint32_t *>(p.ws + p.lcount), s));
     net->last_gate_tiles = g.gate_tiles;
@@ -330,25 +341,35 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
     const uint32_t *lcount = p.gated ? reinterpret_cast<const uint32_t *>(p.ws + p.lcount) : nullptr;
     int stem_r = 0;
     for (int b = 0; b < net->nb; ++b) stem_r += 2 * net->dil[b];
+    // FP8: row l of amax holds the per-frame max of layer l's stored output
+    // (l = 0: stem), which sets the activation scale of conv layer l
+    uint32_t *amax = p.fp8 ? reinterpret_cast<uint32_t *>(p.ws + p.amax) : nullptr;
+    if (amax) HIPCHK(net, launch_zero_u32(amax, (int64_t)2 * net->nb * g.nf, s));
     {
         StageTimer t(net, DL_STAGE_STEM, s);
         HIPCHK(net, launch_stem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset, scale, a0,
-                                net->cfg.precision != DL_FP32, keep, stem_r, s));
+                                net->cfg.precision != DL_FP32, amax, keep, stem_r, s));
     }
-    const int maxg = conv_max_grid(C, net->cfg.precision, g.tile_rows, net->ncu);
-    int grid = (int)std::min<int64_t>(g.total_tiles, maxg);
-    grid = std::max(8, grid / 8 * 8);
+    const int maxg = conv_max_grid(C, net->cfg.precision, g.tr, net->ncu);
     for (int b = 0; b < net->nb; ++b) {
+        int grid = (int)std::min<int64_t>(g.tiles[b], maxg);
+        grid = std::max(8, grid / 8 * 8);
         ConvArgs a{};
         a.fd = d_fd;
         a.d = net->dil[b];
+        a.blk = b;
+        if (amax) {
+            a.wscale = net->d_wscale + (size_t)(b * 2) * C;
+            a.amax_in = amax + (size_t)(2 * b) * g.nf;
+            a.amax_out = amax + (size_t)(2 * b + 1) * g.nf;
+        }
         a.in = a0;
         a.out = a1;
         a.res = nullptr;
         a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2) * net->wpk_stride;
         a.bias = net->d_bias + (size_t)(b * 2) * C;
         if (lists) {
-            a.list = lists + (size_t)(2 * b) * g.total_tiles;
+            a.list = lists + (size_t)(2 * b) * g.max_tiles;
             a.list_count = lcount + 2 * b;
         }
         {
@@ -360,8 +381,13 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         a.out = a0;
         a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2 + 1) * net->wpk_stride;
         a.bias = net->d_bias + (size_t)(b * 2 + 1) * C;
+        if (amax) {
+            a.wscale = net->d_wscale + (size_t)(b * 2 + 1) * C;
+            a.amax_in = amax + (size_t)(2 * b + 1) * g.nf;
+            a.amax_out = b + 1 < net->nb ? amax + (size_t)(2 * b + 2) * g.nf : nullptr;
+        }
         if (lists) {
-            a.list = lists + (size_t)(2 * b + 1) * g.total_tiles;
+            a.list = lists + (size_t)(2 * b + 1) * g.max_tiles;
             a.list_count = lcount + 2 * b + 1;
         }
         if (b == net->nb - 1) {
@@ -670,7 +696,9 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
         }
         rad[0] = r;
         if (hipMalloc(&net->d_radius, rad.size() * sizeof(int)) != hipSuccess ||
-            hipMemcpy(net->d_radius, rad.data(), rad.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            hipMemcpy(net->d_radius, rad.data(), rad.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMalloc(&net->d_dil, nb * sizeof(int)) != hipSuccess ||
+            hipMemcpy(net->d_dil, net->dil, nb * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(net, DL_ERR_DEVICE, "radius upload failed"));
     }
     if ((rc = ensure_packed(net))) return bail(rc);
@@ -695,6 +723,8 @@ void dl_destroy_net(dl_net *net)
     if (net->d_wpk) (void)hipFree(net->d_wpk);
     if (net->d_gate_theta) (void)hipFree(net->d_gate_theta);
     if (net->d_radius) (void)hipFree(net->d_radius);
+    if (net->d_dil) (void)hipFree(net->d_dil);
+    if (net->d_wscale) (void)hipFree(net->d_wscale);
     if (net->h_desc) (void)hipHostFree(net->h_desc);
     if (net->d_desc) (void)hipFree(net->d_desc);
     for (int i = 0; i < DESC_SLOTS; ++i)
@@ -952,13 +982,14 @@ int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int 
     ConvArgs a{};
     a.fd = d_fd;
     a.d = net->dil[blk];
+    a.blk = blk;
     a.in = d_in;
     a.res = d_res;
     a.out = d_out;
     a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(blk * 2 + which) * net->wpk_stride;
     a.bias = net->d_bias + (size_t)(blk * 2 + which) * net->C;
-    const int maxg = conv_max_grid(net->C, net->cfg.precision, g.tile_rows, net->ncu);
-    int grid = (int)std::min<int64_t>(g.total_tiles, maxg);
+    const int maxg = conv_max_grid(net->C, net->cfg.precision, g.tr, net->ncu);
+    int grid = (int)std::min<int64_t>(g.tiles[blk], maxg);
     grid = std::max(8, grid / 8 * 8);
     HIPCHK(net, launch_conv(net->C, net->cfg.precision, a, g, grid, s));
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
@@ -1041,6 +1072,54 @@ void dl_graph_destroy(dl_graph *g)
     if (g->ws) (void)hipFree(g->ws);
     if (g->d_fd) (void)hipFree(g->d_fd);
     delete g;
+}
+
+int dl_autotune(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, int reps,
+                int32_t *best_rows, float *ms)
+{
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (reps <= 0 || reps > 1000) return fail(net, DL_ERR_INVALID_ARG, "reps must lie in 1..1000");
+    if ((rc = set_device(net))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    static const int cand[DL_TUNE_CANDIDATES] = {8, 4};
+    const int saved = net->cfg.tile_rows;
+    const bool prof = net->profiling;
+    net->profiling = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(net, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(net, DL_ERR_DEVICE, "hipEventCreate failed");
+    }
+    float best = 0.f;
+    int pick = cand[0];
+    for (int c = 0; c < DL_TUNE_CANDIDATES && rc == DL_OK; ++c) {
+        net->cfg.tile_rows = cand[c];
+        std::vector<FrameDesc> fd;
+        Geometry g;
+        uniform_geometry(net, d_frames, n, h, w, fd, g);
+        rc = localize_geom(net, fd, g, s, nullptr, 0, nullptr, nullptr, d_frames, n, h, w);   // warm-up
+        if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = fail(net, DL_ERR_DEVICE, "hipEventRecord failed");
+        for (int r = 0; r < reps && !rc; ++r)
+            rc = localize_geom(net, fd, g, s, nullptr, 0, nullptr, nullptr, d_frames, n, h, w);
+        float t = 0.f;
+        if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+            rc = fail(net, DL_ERR_DEVICE, "event timing failed");
+        t /= (float)reps;
+        if (ms) ms[c] = t;
+        if (!rc && (c == 0 || t < best)) {
+            best = t;
+            pick = cand[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    net->profiling = prof;
+    net->cfg.tile_rows = rc ? saved : pick;
+    if (!rc && best_rows) *best_rows = pick;
+    return rc;
 }
 
 int dl_set_gate(dl_net *net, const float *theta, float threshold)

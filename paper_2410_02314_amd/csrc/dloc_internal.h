@@ -10,31 +10,63 @@ namespace dloc {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Tile of the convolution kernels: TILE_ROWS rows (one wave per row) x
-// TILE_COLS = 16 * PB columns.
-constexpr int PB = 4;             // 16-pixel MFMA column blocks per wave
-constexpr int TILE_COLS = 16 * PB;
+constexpr int MAXBLK = 8;         // residual blocks a network may have
+constexpr int GATE_TILE = 256;    // gate tile side (pixels)
+
+// Convolution tiles.  For a layer of dilation d a frame is cut into regions
+// of (tr d) x (tc d) pixels; a region holds d*d phase tiles, and phase (py, px)
+// covers the pixels (Y0 + d i, X0 + d j), i < tr, j < tc, with
+// Y0 = region_y * tr d + py, X0 = region_x * tc d + px.  On that d-strided
+// sub-lattice the dilated 3x3 convolution is an ordinary 3x3 convolution, so a
+// tile's input is always (tr + 2) x (tc + 2) lattice points.  Tiles are
+// numbered region-major, phase-minor: consecutive tiles cover the same pixels'
+// neighbourhood and share cache lines.
+__host__ __device__ inline int64_t conv_tiles(int h, int w, int d, int tr, int tc)
+{
+    const int ry = (h + tr * d - 1) / (tr * d), rx = (w + tc * d - 1) / (tc * d);
+    return (int64_t)ry * rx * d * d;
+}
 
 // One frame (or ROI) of a batch, as every kernel sees it.  Per-pixel buffers
 // (activations, maps) are packed frame after frame; px_off is the frame's
-// first pixel in that packing.  Rows and conv tiles are numbered globally over
-// the batch; row_start / tile_start are the frame's first global row / tile.
+// first pixel in that packing.  Rows, detection words, gate tiles and conv
+// tiles (per block, since the tiling depends on the dilation) are numbered
+// globally over the batch; the *_start fields are the frame's first ones.
 struct FrameDesc {
-    const uint16_t *data;   // device frame (uint16), rows row_stride apart
+    const uint16_t *data;   // device frame (uint16), rows `stride` elements apart
     int64_t stride;
     int64_t px_off;
     int64_t row_start;
-    int64_t tile_start;
     int64_t mask_start;     // first 64-bit detection word of the frame
     int64_t keep_start;     // first gate-tile flag of the frame (gated runs)
+    int64_t tile_start[MAXBLK];
     int32_t h, w;
-    int32_t tiles_x;        // conv tiles per tile row
     int32_t words;          // 64-pixel detection words per row = ceil(w / 64)
     int32_t gtx, gty;       // gate tiles per row / column (gated runs)
-    int32_t pad_;
+    int32_t pad_[3];
 };
 
-constexpr int GATE_TILE = 256;
+struct Geometry {
+    int nf = 0;
+    int64_t total_px = 0, total_rows = 0, total_words = 0, gate_tiles = 0;
+    int64_t tiles[MAXBLK] = {0};   // conv tiles of each block's layers
+    int64_t max_tiles = 0;
+    int tr = 8, tc = 64;           // conv tile shape on the sub-lattice
+    int maxw = 0;
+};
+
+__device__ __forceinline__ void decode_tile(const FrameDesc &fd, int64_t local, int d, int tr, int tc, int &Y0,
+                                            int &X0)
+{
+    const int d2 = d * d;
+    const int64_t r = local / d2;
+    const int ph = (int)(local - r * d2);
+    const int py = ph / d, px = ph - (ph / d) * d;
+    const int rxn = (fd.w + tc * d - 1) / (tc * d);
+    const int ry = (int)(r / rxn), rx = (int)(r - (int64_t)ry * rxn);
+    Y0 = ry * tr * d + py;
+    X0 = rx * tc * d + px;
+}
 
 // Is any kept gate tile within distance r of the pixel box [y0, y1] x [x0, x1]
 // (inclusive)?  keep == nullptr means every tile is kept.
@@ -51,14 +83,6 @@ __device__ __forceinline__ bool near_kept(const uint8_t *keep, const FrameDesc &
     return false;
 }
 
-struct Geometry {
-    int nf = 0;
-    int64_t total_px = 0, total_rows = 0, total_tiles = 0, total_words = 0;
-    int tile_rows = 0;
-    int maxw = 0;
-    int64_t gate_tiles = 0;
-};
-
 // binary search: largest f with key(f) <= idx, for a key increasing in f
 template <typename F>
 __device__ __forceinline__ int find_frame(const FrameDesc *fd, int nf, int64_t idx, F key)
@@ -73,33 +97,42 @@ __device__ __forceinline__ int find_frame(const FrameDesc *fd, int nf, int64_t i
 
 // ---- launchers (kernels_*.hip) ----
 // all return hipError_t of the launch
+// act_bf16: store BF16 activations; amax (nullable): per-frame running max of
+// the stored values, as float bits, for the FP8 form's activation scales
 hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                       float offset, float scale, void *act, int act_bf16, const uint8_t *keep, int radius,
-                       hipStream_t s);
+                       float offset, float scale, void *act, int act_bf16, uint32_t *amax, const uint8_t *keep,
+                       int radius, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // gated runs: keep[t] = logit[t] > tau_gate; then one compacted list of conv
 // tiles per layer (tiles within radius[l] of a kept gate tile)
 hipError_t launch_gate_keep(const float *logits, int64_t n, float tau, uint8_t *keep, hipStream_t s);
 hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uint8_t *keep, const int *radius,
-                               int nlayers, int32_t *lists, uint32_t *counts, hipStream_t s);
+                               const int *dil, int nlayers, int32_t *lists, uint32_t *counts, hipStream_t s);
 
 struct ConvArgs {
-    const void *in;          // NHWC activations (fp32 or bf16)
+    const void *in;          // NHWC activations (FP32, or BF16 for the BF16 and FP8 forms)
     const void *res;         // residual (same layout as out) or null
     void *out;               // NHWC output (or null when the head is fused)
     const void *wpk;         // packed weights
     const float *bias;       // [C]
+    const float *wscale;     // FP8: per-output-channel weight scale [C]
+    const uint32_t *amax_in; // FP8: per-frame max of the input activations (float bits)
+    uint32_t *amax_out;      // FP8: per-frame max of the stored output (float bits), or null
     const float *head;       // fused head: w [5][C] then b [5]; null = no head
     float *maps;             // fused head output, planar [5][h][w] per frame
     const FrameDesc *fd;
     int d;
-    const int32_t *list;       // active tiles of this layer (gated runs) or null = all tiles
+    int blk;                 // block index: selects the frame's tile numbering
+    const int32_t *list;     // active tiles of this layer (gated runs) or null = all tiles
     const uint32_t *list_count;
 };
-hipError_t launch_conv(int C, int precision, const ConvArgs &a, const Geometry &g, int grid,
-                       hipStream_t s);
-int conv_max_grid(int C, int precision, int tile_rows, int ncu);
+hipError_t launch_conv(int C, int precision, const ConvArgs &a, const Geometry &g, int grid, hipStream_t s);
+// tile shape of the conv kernel: rows = 4 or 8 (anything else: 8)
+void conv_tile_shape(int C, int precision, int rows, int *tr, int *tc);
+int conv_max_grid(int C, int precision, int tr, int ncu);
 size_t conv_packed_bytes(int C, int precision);
-void pack_conv_weights(int C, int precision, const float *W /*[C][C][3][3]*/, void *dst);
+// pack one 3x3 C->C layer W [C][C][3][3]; FP8 also writes scale[C]
+void pack_conv_weights(int C, int precision, const float *W, void *dst, float *scale);
 
 // maps: `planes` planes per frame, the logit plane first (5 for the head
 // output, 1 for a plain logit stack)

@@ -29,7 +29,7 @@ template <int C, bool BF16OUT>
 __global__ void __launch_bounds__(256)
 k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
        const float *__restrict__ b, float offset, float scale, void *__restrict__ act,
-       const uint8_t *__restrict__ keep, int radius)
+       uint32_t *__restrict__ amax, const uint8_t *__restrict__ keep, int radius)
 {
     __shared__ float sw[C * 9];
     __shared__ float sb[C];
@@ -45,6 +45,7 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
     constexpr int CG = C / 4;
     // gated runs: only rows / 64-pixel segments within `radius` of a kept tile
     if (!near_kept(keep, fd, y, y, 0, W - 1, radius)) return;
+    float vmax = 0.f;
     for (int i = threadIdx.x; i < W * CG; i += 256) {
         const int x = i / CG;
         const int cg = i - x * CG;
@@ -69,24 +70,35 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
         }
         const int64_t pix = fd.px_off + (int64_t)y * W + x;
         if (BF16OUT) {
+            const uint32_t b0 = f32_to_bf16_rne(o[0]), b1 = f32_to_bf16_rne(o[1]);
+            const uint32_t b2 = f32_to_bf16_rne(o[2]), b3 = f32_to_bf16_rne(o[3]);
             uint2 pk;
-            pk.x = (uint32_t)f32_to_bf16_rne(o[0]) | ((uint32_t)f32_to_bf16_rne(o[1]) << 16);
-            pk.y = (uint32_t)f32_to_bf16_rne(o[2]) | ((uint32_t)f32_to_bf16_rne(o[3]) << 16);
+            pk.x = b0 | (b1 << 16);
+            pk.y = b2 | (b3 << 16);
             *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(act) + pix * C + cg * 4) = pk;
+            vmax = fmaxf(vmax, fmaxf(fmaxf(__uint_as_float(b0 << 16), __uint_as_float(b1 << 16)),
+                                     fmaxf(__uint_as_float(b2 << 16), __uint_as_float(b3 << 16))));
         } else {
             *reinterpret_cast<v4f *>(static_cast<float *>(act) + pix * C + cg * 4) = v4f{o[0], o[1], o[2], o[3]};
         }
     }
+    if (amax) {
+        // stored values are >= 0, so float order equals unsigned order of the bits
+        for (int o = 1; o < 64; o <<= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+        if ((threadIdx.x & 63) == 0) atomicMax(amax + f, __float_as_uint(vmax));
+    }
 }
 
 template <int C>
-hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                  float offset, float scale, void *act, int bf16, const uint8_t *keep, int radius, hipStream_t s)
+hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const float *b, float offset,
+                  float scale, void *act, int bf16, uint32_t *amax, const uint8_t *keep, int radius, hipStream_t s)
 {
     if (bf16)
-        hipLaunchKernelGGL((k_stem<C, true>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset, scale, act, keep, radius);
+        hipLaunchKernelGGL((k_stem<C, true>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset,
+                           scale, act, amax, keep, radius);
     else
-        hipLaunchKernelGGL((k_stem<C, false>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset, scale, act, keep, radius);
+        hipLaunchKernelGGL((k_stem<C, false>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset,
+                           scale, act, nullptr, keep, radius);
     return hipGetLastError();
 }
 
@@ -256,32 +268,39 @@ k_gate_keep(const float *__restrict__ logits, int64_t n, float tau, uint8_t *__r
     if (t < n) keep[t] = logits[t] > tau ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(64)
-k_zero_u32(uint32_t *p, int n)
+__global__ void __launch_bounds__(256)
+k_zero_u32(uint32_t *p, int64_t n)
 {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
-// One thread per conv tile: append the tile to the list of every layer whose
-// radius brings it within reach of a kept gate tile.  List order depends on
-// atomic arrival, which changes only which workgroup computes a tile.
+// One thread per conv tile of block b (blockIdx.y): append the tile to the
+// lists of the block's two layers when their radius brings it within reach
+// of a kept gate tile.  List order depends on atomic arrival, which changes
+// only which workgroup computes a tile.
 __global__ void __launch_bounds__(256)
-k_active_lists(const FrameDesc *__restrict__ fdp, int nf, int64_t T, int rows, const uint8_t *__restrict__ keep,
-               const int *__restrict__ radius, int nlayers, int32_t *__restrict__ lists, uint32_t *__restrict__ counts)
+k_active_lists(const FrameDesc *__restrict__ fdp, Geometry geo, const uint8_t *__restrict__ keep,
+               const int *__restrict__ radius, const int *__restrict__ dil, int32_t *__restrict__ lists,
+               uint32_t *__restrict__ counts)
 {
+    const int b = blockIdx.y;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= T) return;
-    const int f = find_frame(fdp, nf, t, [](const FrameDesc &d) { return d.tile_start; });
-    const FrameDesc fd = fdp[f];
-    const int64_t local = t - fd.tile_start;
-    const int ty = (int)(local / fd.tiles_x), tx = (int)(local - (int64_t)ty * fd.tiles_x);
-    const int y0 = ty * rows, y1 = min(fd.h - 1, y0 + rows - 1);
-    const int x0 = tx * TILE_COLS, x1 = min(fd.w - 1, x0 + TILE_COLS - 1);
-    for (int l = 0; l < nlayers; ++l)
-        if (near_kept(keep, fd, y0, y1, x0, x1, radius[l])) {
+    if (t >= geo.tiles[b]) return;
+    const int f = find_frame(fdp, geo.nf, t, [b](const FrameDesc &d) { return d.tile_start[b]; });
+    const FrameDesc &fd = fdp[f];       // read in place: tile_start is indexed by the block
+    const int d = dil[b];
+    int Y0, X0;
+    decode_tile(fd, t - fd.tile_start[b], d, geo.tr, geo.tc, Y0, X0);
+    if (Y0 >= fd.h || X0 >= fd.w) return;
+    const int y1 = min(fd.h - 1, Y0 + d * (geo.tr - 1)), x1 = min(fd.w - 1, X0 + d * (geo.tc - 1));
+    for (int k = 0; k < 2; ++k) {
+        const int l = 2 * b + k;
+        if (near_kept(keep, fd, Y0, y1, X0, x1, radius[l])) {
             const uint32_t i = atomicAdd(&counts[l], 1u);
-            lists[(int64_t)l * T + i] = (int32_t)t;
+            lists[(int64_t)l * geo.max_tiles + i] = (int32_t)t;
         }
+    }
 }
 
 }  // namespace
@@ -292,26 +311,31 @@ hipError_t launch_gate_keep(const float *logits, int64_t n, float tau, uint8_t *
     return hipGetLastError();
 }
 
-hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uint8_t *keep, const int *radius,
-                               int nlayers, int32_t *lists, uint32_t *counts, hipStream_t s)
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counts, nlayers);
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uint8_t *keep, const int *radius,
+                               const int *dil, int nlayers, int32_t *lists, uint32_t *counts, hipStream_t s)
+{
+    hipError_t e = launch_zero_u32(counts, nlayers, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_active_lists, dim3((unsigned)((g.total_tiles + 255) / 256)), dim3(256), 0, s, fd, g.nf,
-                       g.total_tiles, g.tile_rows, keep, radius, nlayers, lists, counts);
+    hipLaunchKernelGGL(k_active_lists, dim3((unsigned)((g.max_tiles + 255) / 256), nlayers / 2), dim3(256), 0, s,
+                       fd, g, keep, radius, dil, lists, counts);
     return hipGetLastError();
 }
 
 hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                       float offset, float scale, void *act, int act_bf16, const uint8_t *keep, int radius,
-                       hipStream_t s)
+                       float offset, float scale, void *act, int act_bf16, uint32_t *amax, const uint8_t *keep,
+                       int radius, hipStream_t s)
 {
     switch (C) {
-    case 16: return stem_c<16>(fd, g, w, b, offset, scale, act, act_bf16, keep, radius, s);
-    case 32: return stem_c<32>(fd, g, w, b, offset, scale, act, act_bf16, keep, radius, s);
-    case 48: return stem_c<48>(fd, g, w, b, offset, scale, act, act_bf16, keep, radius, s);
-    case 64: return stem_c<64>(fd, g, w, b, offset, scale, act, act_bf16, keep, radius, s);
+    case 16: return stem_c<16>(fd, g, w, b, offset, scale, act, act_bf16, amax, keep, radius, s);
+    case 32: return stem_c<32>(fd, g, w, b, offset, scale, act, act_bf16, amax, keep, radius, s);
+    case 48: return stem_c<48>(fd, g, w, b, offset, scale, act, act_bf16, amax, keep, radius, s);
+    case 64: return stem_c<64>(fd, g, w, b, offset, scale, act, act_bf16, amax, keep, radius, s);
     default: return hipErrorInvalidValue;
     }
 }

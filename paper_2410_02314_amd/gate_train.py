@@ -60,6 +60,17 @@ def labelled_tiles(net: Net, frames_iter, device, gain=0.5, offset=100.0, in_sca
 class TrainResult:
     theta: np.ndarray
     history: List[Dict[str, float]] = field(default_factory=list)
+    val_idx: Optional[np.ndarray] = None
+
+
+def threshold_at_recall(pooled, labels, theta, idx, target: float = 0.995) -> float:
+    """Gate probability threshold chosen on held-out tiles: the largest one
+    that keeps at least ``target`` of the positive tiles."""
+    import torch
+    g = gate_logits(pooled, theta, idx).astype(np.float64)
+    y = labels.index_select(0, torch.from_numpy(np.asarray(idx)).to(labels.device)).cpu().numpy() > 0.5
+    t = threshold_for_recall(g, y, target)
+    return float(1.0 / (1.0 + math.exp(-t)))
 
 
 def train(pooled, labels, theta0: np.ndarray, epochs: int = 20, batch: int = 256, lr: float = 1e-3,
@@ -81,7 +92,7 @@ def train(pooled, labels, theta0: np.ndarray, epochs: int = 20, batch: int = 256
     logits = torch.empty(batch, dtype=torch.float32, device=dev)
     dlog = torch.empty(batch, dtype=torch.float32, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
-    res = TrainResult(theta=np.asarray(theta0, np.float32))
+    res = TrainResult(theta=np.asarray(theta0, np.float32), val_idx=va_idx)
     step = 0
     for ep in range(epochs):
         order = tr_idx[rng.permutation(tr_idx.size)]

@@ -71,3 +71,16 @@ def test_graph_rois_match_eager():
         torch.cuda.synchronize()
         assert torch.equal(c2, counts) and torch.equal(out2[:n], got)
     g.close()
+
+
+def test_autotune_picks_a_candidate_and_keeps_results():
+    spec, w = S.make_net("B", 2)
+    net = dl.Net(S.serialize_weights(spec, w))
+    frames = S.render_frames(2, 256, 384, "full", 5)
+    d = torch.from_numpy(frames).to(DEV)
+    ref, _ = eager(net, d, 1 << 14)
+    rows, ms = net.autotune(d, reps=2)
+    assert rows in (4, 8) and all(v > 0 for v in ms.values())
+    assert ms[rows] == min(ms.values())
+    got, _ = eager(net, d, 1 << 14)
+    assert torch.equal(got, ref)              # the tile shape never changes results

@@ -97,3 +97,32 @@ def test_bf16_full_size_tiling_invariance_and_window():
     emu = oracle.net_maps_window(frames[0], spec, wts, y0, x0, hh, ww, quant="bf16")
     ex = oracle.net_maps_window(frames[0], spec, wts, y0, x0, hh, ww)
     assert np.all(map_rel_err(got[0, :, y0:y0 + hh, x0:x0 + ww], emu) <= 2.0 * map_rel_err(emu, ex) + 1e-4)
+
+
+# ------------------------------------------------------------------ FP8
+@pytest.mark.parametrize("name,model,n,side", [("A", "tiny", 4, 128), ("B", "full", 2, 256)])
+def test_fp8_close_to_emulation_and_accuracy(name, model, n, side):
+    """FP8 e4m3 block convolutions (per-output-channel weight scales, per-frame
+    activation scales, FP32 accumulation) against the oracle's FP8 emulation and
+    the exact FP64 oracle."""
+    spec, wts, net, frames = _setup("fp8", name, 1 if name == "A" else 2, 1001, n, side, side, model)
+    got = gpu_maps(net, frames)
+    emu = oracle.net_maps_batch(frames, spec, wts, quant="fp8")
+    ex = oracle.net_maps_batch(frames, spec, wts)
+    e_gpu, e_emu = map_rel_err(got, emu), map_rel_err(emu, ex)
+    print("fp8: gpu vs emulation", e_gpu, "emulation vs exact", e_emu)
+    assert np.all(e_gpu <= 2.0 * e_emu + 1e-4)
+    ref = oracle.localize(frames, spec, wts)
+    emu_rec = oracle.localize(frames, spec, wts, quant="fp8")
+    rec, _ = gpu_localize(net, frames)
+    g = match_by_distance(rec, ref, 1.0)
+    b = match_by_distance(emu_rec, ref, 1.0)
+    print({"gpu_fp8": g, "oracle_fp8_emulation": b})
+    assert g["recall"] >= b["recall"] - 0.02 and g["precision"] >= b["precision"] - 0.02
+
+
+def test_fp8_tiling_invariance():
+    """Activation scales are per frame, so the tile shape does not change FP8 results."""
+    spec, wts, net, frames = _setup("fp8", "B", 2, 1002, n=2, h=320, w=448, model="full")
+    net4 = dl.Net(S.serialize_weights(spec, wts), precision="fp8", tile_rows=4)
+    assert np.array_equal(gpu_maps(net, frames), gpu_maps(net4, frames))
