@@ -68,7 +68,7 @@ typedef struct {
     int32_t device;             /* HIP device ordinal; 0                           */
     uint32_t flags;             /* DL_FLAG_*                                       */
     uint64_t max_workspace_bytes; /* device workspace cap, 0 = no cap             */
-    int32_t tile_rows;          /* conv tile rows (0 = tuned/default)              */
+    int32_t tile_rows;          /* conv tile rows 4 or 8; 0 = the form's default   */
     int32_t reserved[7];
 } dl_config;
 

@@ -118,7 +118,31 @@ int check_config(dl_net *net, const dl_config *c)
     return DL_OK;
 }
 
-int tile_rows_of(const dl_net *net) { return net->cfg.tile_rows ? net->cfg.tile_rows : 8; }
+int tile_rows_of(const dl_net *net) { return net->cfg.tile_rows ? net->cfg.tile_rows : 0; }
+
+// Activation layout of block b's layers (input, intermediate and residual):
+// the phase layout of its dilation when that is a power of two, plain NHWC
+// for the first block (the stem writes plain rows) and other dilations.
+int block_layout(const dl_net *net, int b)
+{
+    const int d = net->dil[b];
+    return b > 0 && d > 1 && (d & (d - 1)) == 0 ? d : 1;
+}
+
+// activation points one frame needs: the largest layout the net uses
+int64_t frame_act_points(const dl_net *net, int h, int w)
+{
+    int64_t m = act_points(h, w, 1);
+    for (int b = 0; b < net->nb; ++b) m = std::max(m, act_points(h, w, block_layout(net, b)));
+    return m;
+}
+
+// the conv kernels address a frame's activations with 32-bit byte offsets
+bool frame_act_fits(const dl_net *net, int h, int w)
+{
+    const int64_t esz = net->cfg.precision == DL_FP32 ? 4 : 2;
+    return frame_act_points(net, h, w) * net->C * esz < ((int64_t)1 << 31);
+}
 
 // Build the frame descriptors of a uniform batch or a ROI list.
 void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, const uint16_t *const *data,
@@ -136,6 +160,7 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         d.h = hs[f];
         d.w = ws_[f];
         d.px_off = g.total_px;
+        d.act_off = g.total_act;
         d.row_start = g.total_rows;
         d.mask_start = g.total_words;
         d.words = (d.w + 63) / 64;
@@ -148,6 +173,7 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         }
         g.gate_tiles += (int64_t)d.gtx * d.gty;
         g.total_px += (int64_t)d.h * d.w;
+        g.total_act += frame_act_points(net, d.h, d.w);
         g.total_rows += d.h;
         g.total_words += (int64_t)d.h * d.words;
         if (d.w > g.maxw) g.maxw = d.w;
@@ -157,7 +183,10 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
 
 struct Plan {
     char *ws = nullptr;             // workspace base the offsets refer to
-    size_t act0 = 0, act1 = 0, maps = 0, mask = 0, rc = 0, roff = 0, total = 0;
+    // activations: act0 / act2 alternate as block input and output, act1
+    // holds the intermediate of a block (a block writes its output in the next
+    // block's layout, so it cannot overwrite its own input in place)
+    size_t act0 = 0, act1 = 0, act2 = 0, maps = 0, mask = 0, rc = 0, roff = 0, total = 0;
     bool gated = false;
     size_t pooled = 0, glog = 0, keep = 0, lists = 0, lcount = 0;
     size_t amax = 0;                // FP8: per-frame activation maxima, one row per producing layer
@@ -171,8 +200,9 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     const size_t esz = net->cfg.precision == DL_FP32 ? 4 : 2;
     Plan p;
     size_t o = 0;
-    p.act0 = o; o = align_up(o + (size_t)g.total_px * net->C * esz);
-    p.act1 = o; o = align_up(o + (size_t)g.total_px * net->C * esz);
+    p.act0 = o; o = align_up(o + (size_t)g.total_act * net->C * esz);
+    p.act1 = o; o = align_up(o + (size_t)g.total_act * net->C * esz);
+    p.act2 = o; o = align_up(o + (size_t)g.total_act * net->C * esz);
     p.maps = o; if (!ext_maps) o = align_up(o + (size_t)g.total_px * 5 * 4);
     p.mask = o; o = align_up(o + (size_t)g.total_words * 8);
     p.rc = o; o = align_up(o + (size_t)g.total_rows * 4);
@@ -351,19 +381,24 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
                                 net->cfg.precision != DL_FP32, amax, keep, stem_r, s));
     }
     const int maxg = conv_max_grid(C, net->cfg.precision, g.tr, net->ncu);
+    void *x = a0, *xn = p.ws + p.act2;      // block input, block output (alternating)
     for (int b = 0; b < net->nb; ++b) {
         int grid = (int)std::min<int64_t>(g.tiles[b], maxg);
         grid = std::max(8, grid / 8 * 8);
+        const int lay = block_layout(net, b);
+        const int lay_next = b + 1 < net->nb ? block_layout(net, b + 1) : 1;
         ConvArgs a{};
         a.fd = d_fd;
         a.d = net->dil[b];
         a.blk = b;
+        a.in_phase = lay == net->dil[b] && lay > 1;
+        a.out_shift = __builtin_ctz((unsigned)lay);
         if (amax) {
             a.wscale = net->d_wscale + (size_t)(b * 2) * C;
             a.amax_in = amax + (size_t)(2 * b) * g.nf;
             a.amax_out = amax + (size_t)(2 * b + 1) * g.nf;
         }
-        a.in = a0;
+        a.in = x;
         a.out = a1;
         a.res = nullptr;
         a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2) * net->wpk_stride;
@@ -377,8 +412,9 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
             HIPCHK(net, launch_conv(C, net->cfg.precision, a, g, grid, s));
         }
         a.in = a1;
-        a.res = a0;
-        a.out = a0;
+        a.res = x;
+        a.out = xn;
+        a.out_shift = __builtin_ctz((unsigned)lay_next);
         a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2 + 1) * net->wpk_stride;
         a.bias = net->d_bias + (size_t)(b * 2 + 1) * C;
         if (amax) {
@@ -397,6 +433,7 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         }
         StageTimer t(net, b == net->nb - 1 ? DL_STAGE_CONV_HEAD : DL_STAGE_CONV, s);
         HIPCHK(net, launch_conv(C, net->cfg.precision, a, g, grid, s));
+        std::swap(x, xn);
     }
     return DL_OK;
 }
@@ -431,7 +468,8 @@ int check_uniform(dl_net *net, const void *frames, int n, int h, int w)
     if (!frames) return fail(net, DL_ERR_INVALID_ARG, "frames is NULL");
     if (reinterpret_cast<uintptr_t>(frames) % 2) return fail(net, DL_ERR_INVALID_ARG, "frames must be 2-byte aligned");
     if (n <= 0 || h <= 0 || w <= 0) return fail(net, DL_ERR_INVALID_ARG, "n, h, w must be > 0 (got %d, %d, %d)", n, h, w);
-    if ((int64_t)h * w > (int64_t)1 << 28) return fail(net, DL_ERR_UNSUPPORTED, "frame of %d x %d pixels is too large", h, w);
+    if ((int64_t)h * w > (int64_t)1 << 28 || !frame_act_fits(net, h, w))
+        return fail(net, DL_ERR_UNSUPPORTED, "frame of %d x %d pixels is too large", h, w);
     if ((int64_t)n * h > (int64_t)1 << 30) return fail(net, DL_ERR_UNSUPPORTED, "too many rows in the batch");
     return DL_OK;
 }
@@ -790,7 +828,8 @@ static int check_rois(dl_net *net, const dl_roi *rois, int nroi)
         if (!r.data || reinterpret_cast<uintptr_t>(r.data) % 2) return fail(net, DL_ERR_INVALID_ARG, "roi %d: NULL or misaligned data", k);
         if (r.h <= 0 || r.w <= 0) return fail(net, DL_ERR_INVALID_ARG, "roi %d: h and w must be > 0", k);
         if (r.row_stride < r.w) return fail(net, DL_ERR_INVALID_ARG, "roi %d: row_stride < w", k);
-        if ((int64_t)r.h * r.w > (int64_t)1 << 28) return fail(net, DL_ERR_UNSUPPORTED, "roi %d too large", k);
+        if ((int64_t)r.h * r.w > (int64_t)1 << 28 || !frame_act_fits(net, r.h, r.w))
+            return fail(net, DL_ERR_UNSUPPORTED, "roi %d too large", k);
         rows += r.h;
     }
     if (rows > (int64_t)1 << 30) return fail(net, DL_ERR_UNSUPPORTED, "too many rows in the batch");
@@ -976,11 +1015,14 @@ int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int 
     std::vector<FrameDesc> fd;
     Geometry g;
     uniform_geometry(net, reinterpret_cast<const uint16_t *>(d_in), n, h, w, fd, g);
+    for (FrameDesc &d : fd) d.act_off = d.px_off;    // caller tensors: plain NHWC, frame after frame
     FrameDesc *d_fd = nullptr;
     const int slot = upload_desc(net, fd, s, &d_fd);
     if (slot < 0) return slot;
     ConvArgs a{};
     a.fd = d_fd;
+    a.in_phase = 0;
+    a.out_shift = 0;
     a.d = net->dil[blk];
     a.blk = blk;
     a.in = d_in;

@@ -27,15 +27,17 @@ __host__ __device__ inline int64_t conv_tiles(int h, int w, int d, int tr, int t
     return (int64_t)ry * rx * d * d;
 }
 
-// One frame (or ROI) of a batch, as every kernel sees it.  Per-pixel buffers
-// (activations, maps) are packed frame after frame; px_off is the frame's
-// first pixel in that packing.  Rows, detection words, gate tiles and conv
-// tiles (per block, since the tiling depends on the dilation) are numbered
-// globally over the batch; the *_start fields are the frame's first ones.
+// One frame (or ROI) of a batch, as every kernel sees it.  Per-pixel maps
+// are packed frame after frame from px_off; activations from act_off, with
+// room for the largest phase layout the net uses (see act_points).  Rows,
+// detection words, gate tiles and conv tiles (per block, since the tiling
+// depends on the dilation) are numbered globally over the batch; the *_start
+// fields are the frame's first ones.
 struct FrameDesc {
     const uint16_t *data;   // device frame (uint16), rows `stride` elements apart
     int64_t stride;
     int64_t px_off;
+    int64_t act_off;        // first activation point of the frame
     int64_t row_start;
     int64_t mask_start;     // first 64-bit detection word of the frame
     int64_t keep_start;     // first gate-tile flag of the frame (gated runs)
@@ -43,29 +45,39 @@ struct FrameDesc {
     int32_t h, w;
     int32_t words;          // 64-pixel detection words per row = ceil(w / 64)
     int32_t gtx, gty;       // gate tiles per row / column (gated runs)
-    int32_t pad_[3];
+    int32_t pad_;
 };
+
+// Activation layouts.  Layout 1 is plain NHWC.  Phase layout l (a power of
+// two) stores the l*l phase sub-images of a frame one after the other, each a
+// dense NHWC image of ceil(h/l) x ceil(w/l) points: pixel (y, x) sits in
+// sub-image (y mod l, x mod l) at (y div l, x div l).  A dilation-l layer
+// reads its phase tiles from contiguous rows of one sub-image.
+__host__ __device__ inline int64_t act_points(int h, int w, int l)
+{
+    const int64_t hd = (h + l - 1) / l, wd = (w + l - 1) / l;
+    return (int64_t)l * l * hd * wd;
+}
 
 struct Geometry {
     int nf = 0;
-    int64_t total_px = 0, total_rows = 0, total_words = 0, gate_tiles = 0;
+    int64_t total_px = 0, total_act = 0, total_rows = 0, total_words = 0, gate_tiles = 0;
     int64_t tiles[MAXBLK] = {0};   // conv tiles of each block's layers
     int64_t max_tiles = 0;
     int tr = 8, tc = 64;           // conv tile shape on the sub-lattice
     int maxw = 0;
 };
 
-__device__ __forceinline__ void decode_tile(const FrameDesc &fd, int64_t local, int d, int tr, int tc, int &Y0,
-                                            int &X0)
+__device__ __forceinline__ void decode_tile(int w, int64_t local, int d, int tr, int tc, int &Y0, int &X0)
 {
-    const int d2 = d * d;
-    const int64_t r = local / d2;
-    const int ph = (int)(local - r * d2);
-    const int py = ph / d, px = ph - (ph / d) * d;
-    const int rxn = (fd.w + tc * d - 1) / (tc * d);
-    const int ry = (int)(r / rxn), rx = (int)(r - (int64_t)ry * rxn);
-    Y0 = ry * tr * d + py;
-    X0 = rx * tc * d + px;
+    // a frame has fewer than 2^32 tiles: 32-bit arithmetic suffices
+    const uint32_t l = (uint32_t)local, d2 = (uint32_t)(d * d);
+    const uint32_t r = l / d2, ph = l - r * d2;
+    const uint32_t py = ph / (uint32_t)d, px = ph - py * (uint32_t)d;
+    const uint32_t rxn = (uint32_t)((w + tc * d - 1) / (tc * d));
+    const uint32_t ry = r / rxn, rx = r - ry * rxn;
+    Y0 = (int)(ry * (uint32_t)(tr * d) + py);
+    X0 = (int)(rx * (uint32_t)(tc * d) + px);
 }
 
 // Is any kept gate tile within distance r of the pixel box [y0, y1] x [x0, x1]
@@ -81,6 +93,16 @@ __device__ __forceinline__ bool near_kept(const uint8_t *keep, const FrameDesc &
         for (int tx = tx0; tx <= tx1; ++tx)
             if (k[ty * d.gtx + tx]) return true;
     return false;
+}
+
+// Read of memory that no kernel writes while the reader runs (descriptors,
+// lists and scales made by earlier launches): through the constant address
+// space, so uniform addresses become scalar loads, which are not counted with
+// the vector memory loads a kernel may have in flight.
+template <class T>
+__device__ __forceinline__ T ld_const(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)p;
 }
 
 // binary search: largest f with key(f) <= idx, for a key increasing in f
@@ -110,7 +132,7 @@ hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uin
                                const int *dil, int nlayers, int32_t *lists, uint32_t *counts, hipStream_t s);
 
 struct ConvArgs {
-    const void *in;          // NHWC activations (FP32, or BF16 for the BF16 and FP8 forms)
+    const void *in;          // activations (FP32, or BF16 for the BF16 and FP8 forms), frame at act_off
     const void *res;         // residual (same layout as out) or null
     void *out;               // NHWC output (or null when the head is fused)
     const void *wpk;         // packed weights
@@ -125,9 +147,12 @@ struct ConvArgs {
     int blk;                 // block index: selects the frame's tile numbering
     const int32_t *list;     // active tiles of this layer (gated runs) or null = all tiles
     const uint32_t *list_count;
+    int in_phase;            // input and residual in phase layout d (1) or plain NHWC (0)
+    int out_shift;           // output in phase layout 1 << out_shift (0: plain NHWC)
 };
 hipError_t launch_conv(int C, int precision, const ConvArgs &a, const Geometry &g, int grid, hipStream_t s);
-// tile shape of the conv kernel: rows = 4 or 8 (anything else: 8)
+// tile shape of the conv kernel: rows = 4 or 8; 0 picks the form's default
+// (4 for FP32, 8 otherwise)
 void conv_tile_shape(int C, int precision, int rows, int *tr, int *tc);
 int conv_max_grid(int C, int precision, int tr, int ncu);
 size_t conv_packed_bytes(int C, int precision);

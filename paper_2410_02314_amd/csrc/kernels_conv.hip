@@ -10,7 +10,7 @@
 // workgroup computes TR x TC output pixels spaced d apart, whose input is the
 // (TR + 2) x (TC + 2) lattice points around them -- the same LDS footprint
 // for every dilation.  The workgroup stages that input once into LDS (points
-// padded so 16-byte reads of consecutive points hit distinct banks), then
+// strided so the MFMA operand reads are free of bank conflicts), then
 // wave w computes lattice row w for all C output channels.  Workgroups are
 // persistent; tiles are handed out XCD by XCD in contiguous ranges, and
 // consecutive tiles are the d*d phases of one region, so they share L2 lines.
@@ -26,7 +26,8 @@
 //   FP8   v_mfma_scale_f32_16x16x128_f8f6f4 with e4m3 operands (unit block
 //         scales); lane group kq of step m takes chunks 16 m + 4 kq + 0..3.
 //         Activations are stored in BF16; staging quantises them into LDS with
-//         the frame's scale amax / 448 (round to nearest even, saturating);
+//         the frame's scale amax / 448 (v_cvt_pk_fp8_f32: OCP e4m3, round to
+//         nearest even; inputs clamped to 448 so it saturates);
 //         weights carry a per-output-channel scale.  The epilogue multiplies
 //         the FP32 accumulator by both scales and tracks the max of what it
 //         stores, which sets the next layer's scale.
@@ -44,10 +45,29 @@ namespace {
 constexpr int NXCD = 8;
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef int v8i __attribute__((ext_vector_type(8)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-// smallest dword count >= dw that is 4 mod 8: 16-byte reads of consecutive
-// points then fall into distinct LDS banks
-constexpr int pad_dw(int dw) { return dw + ((4 - dw % 8) + 8) % 8; }
+// Buffer resource over nbytes at base (raw addressing: stride 0, offsets in
+// bytes).  A store whose offset lies past nbytes is dropped by the hardware,
+// which lets the epilogue store without a branch around pixels off the frame.
+constexpr uint32_t BUF_DWORD3 = 0x00020000u;
+constexpr int BUF_OOB = (int)0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(void *base, uint32_t nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)nbytes, (int)BUF_DWORD3);
+}
+
+// Dword stride of one lattice point in the LDS tile.  gfx950's LDS serves a
+// 16-byte read (ds_read_b128) of the 64 lanes in groups whose banks collide
+// unless the point stride is 8 mod 16 dwords; measured with rocprof's
+// SQ_LDS_BANK_CONFLICT over the exact read and staging-write patterns of the
+// FP32 and BF16 kernels (every C in 16..64: zero read conflicts at 8 mod 16,
+// about 4 extra cycles per read at 4 or 12 mod 16, 12 or more at 0 mod 16).
+// The FP8 kernel reads 8 bytes per lane (ds_read_b64); its strides are the
+// measured best, with no conflict-free choice among those tried.
+constexpr int stride_8_mod_16(int dw) { return dw + ((8 - dw % 16) + 16) % 16; }
+constexpr int fp8_stride(int dw) { return dw == 4 ? 10 : dw == 8 ? 10 : dw == 12 ? 12 : dw == 16 ? 18 : dw; }
 constexpr int align16(int b) { return (b + 15) / 16 * 16; }
 
 __device__ __forceinline__ v4f relu4(v4f v)
@@ -67,47 +87,39 @@ __device__ __forceinline__ uint32_t bf16_rne(float f)
 
 __device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(bf16_rne(f) << 16); }
 
-// OCP e4m3fn code of a finite float: round to nearest even, saturating at
-// +-448.  Normal range: round the 23-bit mantissa to 3 bits; below 2^-6 the
-// spacing is 2^-9 (subnormals), and 8 * 2^-9 is the smallest normal (code 8).
-__device__ __forceinline__ uint32_t f32_to_e4m3(float x)
-{
-    const uint32_t s = (__float_as_uint(x) >> 24) & 0x80u;
-    const float a = fabsf(x);
-    if (!(a < 448.f)) return s | 0x7Eu;
-    if (a < 0.015625f) return s | (uint32_t)__float2int_rn(a * 512.f);
-    uint32_t ua = __float_as_uint(a);
-    ua += 0x7FFFFu + ((ua >> 20) & 1u);
-    const uint32_t code = (((ua >> 23) - 120u) << 3) | ((ua >> 20) & 7u);
-    return s | (code > 0x7Eu ? 0x7Eu : code);
-}
-
 // storage of the activations in HBM: FP32, or BF16 (BF16 and FP8 forms)
 template <int P> struct Store {
     static constexpr int ESZ = 2;
-    __device__ static v4f load4(const void *base, int64_t idx)
+    using Raw = uint2;                      // 4 BF16 values as loaded
+    __device__ static Raw raw4(const void *base, int64_t idx)
     {
-        const uint2 u = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(base) + idx);
+        return *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(base) + idx);
+    }
+    __device__ static v4f unpack(Raw u)
+    {
         return v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xFFFF0000u),
                    __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xFFFF0000u)};
     }
-    __device__ static void store4(void *base, int64_t idx, v4f v)
+    // 4 values (already BF16-exact) at byte offset off of a buffer resource
+    __device__ static void bstore4(__amdgpu_buffer_rsrc_t rs, int off, v4f v)
     {
-        uint2 u;
-        u.x = bf16_rne(v[0]) | (bf16_rne(v[1]) << 16);
-        u.y = bf16_rne(v[2]) | (bf16_rne(v[3]) << 16);
-        *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(base) + idx) = u;
+        v2u u;
+        u[0] = (__float_as_uint(v[0]) >> 16) | (__float_as_uint(v[1]) & 0xFFFF0000u);
+        u[1] = (__float_as_uint(v[2]) >> 16) | (__float_as_uint(v[3]) & 0xFFFF0000u);
+        __builtin_amdgcn_raw_buffer_store_b64(u, rs, off, 0, 0);
     }
 };
 template <> struct Store<DL_FP32> {
     static constexpr int ESZ = 4;
-    __device__ static v4f load4(const void *base, int64_t idx)
+    using Raw = v4f;
+    __device__ static Raw raw4(const void *base, int64_t idx)
     {
         return *reinterpret_cast<const v4f *>(static_cast<const float *>(base) + idx);
     }
-    __device__ static void store4(void *base, int64_t idx, v4f v)
+    __device__ static v4f unpack(Raw u) { return u; }
+    __device__ static void bstore4(__amdgpu_buffer_rsrc_t rs, int off, v4f v)
     {
-        *reinterpret_cast<v4f *>(static_cast<float *>(base) + idx) = v;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), rs, off, 0, 0);
     }
 };
 
@@ -135,28 +147,38 @@ template <int C> struct KPlan<C, DL_FP8> {
 };
 
 // lattice columns per tile (TC; the rows, one wave each, are a template choice)
-// and the waves per SIMD the register budget is sized for (MINW)
 template <int P> struct TileShape;
-template <> struct TileShape<DL_FP32> { static constexpr int TC = 32, MINW = 4; };
-template <> struct TileShape<DL_BF16> { static constexpr int TC = 64, MINW = 2; };
-template <> struct TileShape<DL_FP8> { static constexpr int TC = 64, MINW = 2; };
+template <> struct TileShape<DL_FP32> { static constexpr int TC = 32; };
+template <> struct TileShape<DL_BF16> { static constexpr int TC = 64; };
+template <> struct TileShape<DL_FP8> { static constexpr int TC = 64; };
+// waves per SIMD the register budget is sized for: FP32 4-row tiles fit three
+// workgroups per CU in LDS (one wave per SIMD each); every other shape is
+// limited to one or two workgroups by LDS and gets the larger budget of two
+// waves per SIMD
+template <int P, int TR> constexpr int min_waves() { return P == DL_FP32 && TR == 4 ? 3 : 2; }
 
 template <int C, int P, int TR_>
 struct Lds {
     static constexpr int TR = TR_, TC = TileShape<P>::TC;
-    static constexpr int PS = pad_dw(C * KPlan<C, P>::LESZ / 4) * 4;   // bytes per lattice point
+    static constexpr int PS = (P == DL_FP8 ? fp8_stride(C / 4) : stride_8_mod_16(C * KPlan<C, P>::LESZ / 4)) * 4;   // bytes per point
     static constexpr int PW = TC + 2;
     static constexpr int NPT = (TR + 2) * PW;
     static constexpr int TBYTES = align16(NPT * PS);
     static constexpr int WOFF = TBYTES;
     static constexpr int BOFF = WOFF + KPlan<C, P>::LDS_W;            // bias [C]
     static constexpr int HOFF = BOFF + C * 4;                          // head [5C + 5]
-    static constexpr int TOTAL = align16(HOFF + (5 * C + 5) * 4);
+    static constexpr int SOFF = HOFF + (5 * C + 5) * 4;                // FP8 weight scales [C]
+    // BF16 and FP8 stage each wave's output row (TC pixels x C BF16 values,
+    // pixel-major) so it leaves in whole 16-byte lanes
+    static constexpr int OPX = C * 2;                                  // staging bytes per pixel
+    static constexpr int OWAVE = P == DL_FP32 ? 0 : TC * OPX;
+    static constexpr int OOFF = align16(SOFF + C * 4);
+    static constexpr int TOTAL = align16(OOFF + TR * OWAVE);
 };
 
 // --------------------------------------------------------------- kernel
 template <int C, int P, int TR_, bool RES, bool HEAD>
-__global__ void __launch_bounds__(TR_ * 64, TileShape<P>::MINW)
+__global__ void __launch_bounds__(TR_ * 64, (min_waves<P, TR_>()))
 k_conv(ConvArgs a, Geometry geo)
 {
     using L = Lds<C, P, TR_>;
@@ -166,8 +188,10 @@ k_conv(ConvArgs a, Geometry geo)
     char *sT = reinterpret_cast<char *>(smem);
     float *sB = reinterpret_cast<float *>(sT + L::BOFF);
     float *sH = reinterpret_cast<float *>(sT + L::HOFF);
+    float *sS = reinterpret_cast<float *>(sT + L::SOFF);
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: keeps row state scalar
     const int j = lane & 15, kq = lane >> 4;
     const int dd = a.d, blk = a.blk;
 
@@ -179,61 +203,186 @@ k_conv(ConvArgs a, Geometry geo)
     for (int i = tid; i < C; i += NT) sB[i] = a.bias[i];
     if (HEAD)
         for (int i = tid; i < 5 * C + 5; i += NT) sH[i] = a.head[i];
+    if constexpr (P == DL_FP8)
+        for (int i = tid; i < C; i += NT) sS[i] = a.wscale[i];
+    // FP32: the weights of K iteration 0, read ahead of every tile (the last
+    // iteration of a tile reads them for the next)
+    v4f awn[P == DL_FP32 ? NB : 1];
+    if constexpr (P == DL_FP32)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) awn[nb] = static_cast<const v4f *>(a.wpk)[nb * 64 + lane];
 
-    const int64_t T = a.list ? (int64_t)*a.list_count : geo.tiles[blk];
+    const int64_t T = a.list ? (int64_t)ld_const(a.list_count) : geo.tiles[blk];
     const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD, nslot = gridDim.x / NXCD;
     const int64_t chunk = (T + NXCD - 1) / NXCD;
     const int64_t t0 = (int64_t)xcd * chunk;
     const int64_t t1 = t0 + chunk < T ? t0 + chunk : T;
 
-    for (int64_t ti = t0 + slot; ti < t1; ti += nslot) {
-        const int64_t t = a.list ? (int64_t)a.list[ti] : ti;
-        const int f = find_frame(a.fd, geo.nf, t, [blk](const FrameDesc &d) { return d.tile_start[blk]; });
-        const FrameDesc &fd = a.fd[f];      // read in place: tile_start is indexed by the block
-        int Y0, X0;
-        decode_tile(fd, t - fd.tile_start[blk], dd, TR, TC, Y0, X0);
-        const int H = fd.h, W = fd.w;
-        const int64_t px_off = fd.px_off;
+    // Staging is software-pipelined: the input of the workgroup's next tile is
+    // loaded into registers (NPF 16-byte chunks per thread) while the MFMAs
+    // run on the current one, and written to LDS after the next barrier.  The
+    // loads are unconditional (off-frame points read zeros as out-of-range
+    // buffer loads), so no branch separates them from the compute they overlap.
+    constexpr int SESZ = Store<P>::ESZ;
+    constexpr int SCH = C * SESZ / 16;       // 16-byte source chunks per point
+    constexpr int NQ = NPT * SCH;
+    constexpr int NPF = (NQ + NT - 1) / NT;
+    v4f pf[NPF];
+    // the prefetched tile: frame, origin, the frame fields the tile needs, and
+    // where its input sits: point (ii, jj) of the tile, at pixel (Y0 + d ii,
+    // X0 + d jj), is activation point A0 + ii RS + jj CS of the frame.  In the
+    // phase layout of the tile's dilation that is row iy0 + ii, column
+    // ix0 + jj of one dense sub-image (RS = its width, CS = 1); in plain NHWC,
+    // RS = d w and CS = d.  A frame's activations span less than 2^31 bytes,
+    // so offsets within the frame are 32-bit; loads go through a buffer
+    // resource over the frame, and points off the frame take an out-of-range
+    // offset, which reads as zero.
+    int nf = 0, nY0 = 0, nX0 = 0, nH = 0, nW = 0, nA0 = 0, nRS = 0, nCS = 0;
+    int64_t npx = 0, nact = 0;
+    float namax = 0.f;
+    auto fetch = [&](int64_t ti) {
+        const int64_t t = a.list ? (int64_t)ld_const(a.list + ti) : ti;
+        nf = find_frame(a.fd, geo.nf, t, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
+        const FrameDesc *fd = a.fd + nf;     // fields read in place: tile_start is indexed by the block
+        nH = ld_const(&fd->h);
+        nW = ld_const(&fd->w);
+        npx = ld_const(&fd->px_off);
+        nact = ld_const(&fd->act_off);
+        decode_tile(nW, t - ld_const(&fd->tile_start[blk]), dd, TR, TC, nY0, nX0);
+        if (a.in_phase) {
+            const int hd = (nH + dd - 1) / dd, wd = (nW + dd - 1) / dd;
+            const int py = nY0 % dd, px = nX0 % dd;
+            nA0 = ((py * dd + px) * hd + nY0 / dd) * wd + nX0 / dd;
+            nRS = wd;
+            nCS = 1;
+        } else {
+            nA0 = nY0 * nW + nX0;
+            nRS = dd * nW;
+            nCS = dd;
+        }
+        if constexpr (P == DL_FP8) namax = __uint_as_float(ld_const(a.amax_in + nf));
+        const __amdgpu_buffer_rsrc_t rin =
+            buf_rsrc(const_cast<char *>(static_cast<const char *>(a.in)) + nact * (C * SESZ), 0x7FFFFFFFu);
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            const int q0 = tid + k * NT;
+            const int q = q0 < NQ ? q0 : NQ - 1;
+            const int pt = q / SCH, ch = q - (q / SCH) * SCH;
+            const int ii = pt / PW - 1, jj = pt - (pt / PW) * PW - 1;
+            const int y = nY0 + dd * ii, x = nX0 + dd * jj;
+            const bool ok = q0 < NQ && (unsigned)y < (unsigned)nH && (unsigned)x < (unsigned)nW;
+            pf[k] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(
+                                                rin, ok ? (nA0 + ii * nRS + jj * nCS) * (C * SESZ) + ch * 16 : BUF_OOB, 0, 0));
+        }
+    };
+
+    int64_t ti = t0 + slot;
+    if (ti < t1) fetch(ti);
+    // the first tile's data is waited for here, outside the loop: the
+    // compiler's wait at the loop top then only has to cover the loop's own
+    // path, where the previous tile's stores follow the loads
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) asm volatile("" : : "v"(pf[k]));
+    for (; ti < t1; ti += nslot) {
+        const int f = nf, Y0 = nY0, X0 = nX0, H = nH, W = nW, A0 = nA0, RS = nRS, CS = nCS;
+        const int64_t px_off = npx, act = nact;
         float qinv = 1.f, qscale = 1.f;          // FP8 activation quantisation
         if constexpr (P == DL_FP8) {
-            const float amax = __uint_as_float(a.amax_in[f]);
-            qinv = amax > 0.f ? 448.f / amax : 0.f;
-            qscale = amax / 448.f;
+            qinv = namax > 0.f ? 448.f / namax : 0.f;
+            qscale = namax / 448.f;
         }
 
         __syncthreads();   // the previous tile's LDS reads are done (and weights staged)
-        {
-            constexpr int SESZ = Store<P>::ESZ;
-            constexpr int SCH = C * SESZ / 16;   // 16-byte source chunks per point
-            const char *src = static_cast<const char *>(a.in) + px_off * C * SESZ;
-            for (int q = tid; q < NPT * SCH; q += NT) {
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            const int q = tid + k * NT;
+            if (q < NQ) {
                 const int pt = q / SCH, ch = q - (q / SCH) * SCH;
-                const int ii = pt / PW - 1, jj = pt - (pt / PW) * PW - 1;
-                const int y = Y0 + dd * ii, x = X0 + dd * jj;
-                const bool ok = (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
-                v4f v = {0.f, 0.f, 0.f, 0.f};
-                if (ok) v = *reinterpret_cast<const v4f *>(src + ((int64_t)y * W + x) * (C * SESZ) + ch * 16);
+                const v4f v = pf[k];
                 if constexpr (P != DL_FP8) {
                     *reinterpret_cast<v4f *>(sT + pt * PS + ch * 16) = v;
                 } else {
-                    uint32_t q8[8];
+                    // e4m3 codes, round to nearest even; values are >= 0 (ReLU outputs)
+                    // and at most 448 up to one rounding, clamped so the conversion
+                    // saturates instead of overflowing
+                    uint32_t w2[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const uint32_t w32 = __float_as_uint(v[e]);
-                        q8[2 * e] = f32_to_e4m3(__uint_as_float(w32 << 16) * qinv);
-                        q8[2 * e + 1] = f32_to_e4m3(__uint_as_float(w32 & 0xFFFF0000u) * qinv);
+                        const float lo = fminf(__uint_as_float(w32 << 16) * qinv, 448.f);
+                        const float hi = fminf(__uint_as_float(w32 & 0xFFFF0000u) * qinv, 448.f);
+                        w2[e] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(lo, hi, 0, false) & 0xFFFFu;
                     }
                     uint2 o;
-                    o.x = q8[0] | (q8[1] << 8) | (q8[2] << 16) | (q8[3] << 24);
-                    o.y = q8[4] | (q8[5] << 8) | (q8[6] << 16) | (q8[7] << 24);
+                    o.x = w2[0] | (w2[1] << 16);
+                    o.y = w2[2] | (w2[3] << 16);
                     *reinterpret_cast<uint2 *>(sT + pt * PS + ch * 8) = o;
                 }
             }
         }
         __syncthreads();
 
+        // The residual (block input) at this wave's output pixels, loaded
+        // unconditionally from clamped addresses (values of pixels off the
+        // frame are never stored).  BF16 and FP8 issue all these loads before
+        // the next tile's, so waiting for them does not wait for the prefetch
+        // (vector loads complete in order); FP32 has no registers to spare and
+        // loads them in the epilogue, one pixel block at a time.
         const int yo = Y0 + dd * wave;
-        if (yo >= H) continue;       // this wave's lattice row is off the frame (barriers are at the loop top)
+        // A wave whose lattice row is off the frame computes anyway (its LDS
+        // rows hold zeros) and stores nothing: keeping the loop body free of
+        // branches lets the compiler count the stores still in flight when it
+        // waits for the next tile's loads, instead of waiting for everything.
+        const bool row_ok = yo < H;
+        // BF16/FP8 without the head: output (and residual) pass through this
+        // wave's LDS staging row and move in whole 16-byte lanes.  The fused
+        // head layer keeps the residual in the MFMA layout (EARLY_RES), and
+        // FP32 loads it in the epilogue, one pixel block at a time.
+        constexpr bool STAGE = P != DL_FP32 && !HEAD;
+        constexpr bool EARLY_RES = RES && P != DL_FP32 && HEAD;
+        constexpr int CPX = C * 2 / 16;                     // 16-byte chunks per staged pixel
+        constexpr int NRC = STAGE ? TC * CPX / 64 : 1;      // chunks per lane
+        static_assert(!STAGE || (TC * CPX) % 64 == 0, "staging chunks per lane");
+        // this wave's output row: input-layout point of its lattice column c is
+        // Ar + c CS (the residual sits there); frame-relative, < 2^31 bytes
+        const int Ar = A0 + wave * RS;
+        v4u rc[RES && STAGE ? NRC : 1];
+        if constexpr (RES && STAGE) {
+            const __amdgpu_buffer_rsrc_t rres =
+                buf_rsrc(const_cast<char *>(static_cast<const char *>(a.res)) + act * C * 2, 0x7FFFFFFFu);
+#pragma unroll
+            for (int i = 0; i < NRC; ++i) {
+                const int q = lane + 64 * i, px = q / CPX, part = q - (q / CPX) * CPX;
+                const int xo = X0 + dd * px;
+                rc[i] = __builtin_amdgcn_raw_buffer_load_b128(
+                    rres, row_ok && xo < W ? (Ar + px * CS) * (C * 2) + part * 16 : BUF_OOB, 0, 0);
+            }
+        }
+        constexpr int RPB = EARLY_RES ? PB : 1;
+        typename Store<P>::Raw rr[RES && !STAGE ? NB : 1][RPB];
+        auto load_res = [&](int p0) {
+#pragma unroll
+            for (int pp = 0; pp < RPB; ++pp) {
+                const int c = 16 * (p0 + pp) + j, xo = X0 + dd * c;
+                const int64_t pix = act + (row_ok && xo < W ? Ar + c * CS : 0);   // off-frame: any valid point
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) rr[nb][pp] = Store<P>::raw4(a.res, pix * C + nb * 16 + kq * 4);
+            }
+        };
+        if constexpr (EARLY_RES) load_res(0);
+        // the next tile's input.  BF16/FP8: past the last tile the current one
+        // is read again (and not used), so no branch separates the residual
+        // loads from the prefetch and the wait for them stays exact; FP32 has
+        // nothing to wait for before its epilogue and skips the read.
+        if constexpr (P == DL_FP32) {
+            if (ti + nslot < t1) fetch(ti + nslot);
+        } else {
+            fetch(ti + nslot < t1 ? ti + nslot : ti);
+        }
+        // keep the scheduler from sinking these loads below the MFMAs they
+        // are meant to overlap
+        __builtin_amdgcn_sched_barrier(0);
+
 
         v4f acc[NB][PB];
 #pragma unroll
@@ -246,9 +395,6 @@ k_conv(ConvArgs a, Geometry geo)
         if constexpr (P == DL_FP32) {
             constexpr int G = C / 16, NIT = KPlan<C, P>::NIT;
             const v4f *gw = static_cast<const v4f *>(a.wpk);
-            v4f awn[NB];                             // weights of the next K iteration
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) awn[nb] = gw[nb * 64 + lane];
 #pragma unroll 1
             for (int tap = 0; tap < 9; ++tap) {
 #pragma unroll
@@ -257,9 +403,9 @@ k_conv(ConvArgs a, Geometry geo)
                     v4f aw[NB];
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) aw[nb] = awn[nb];
-                    if (it + 1 < NIT)
+                    const int itn = it + 1 < NIT ? it + 1 : 0;
 #pragma unroll
-                        for (int nb = 0; nb < NB; ++nb) awn[nb] = gw[((it + 1) * NB + nb) * 64 + lane];
+                    for (int nb = 0; nb < NB; ++nb) awn[nb] = gw[(itn * NB + nb) * 64 + lane];
                     v4f bv[PB];
 #pragma unroll
                     for (int p = 0; p < PB; ++p)
@@ -327,34 +473,64 @@ k_conv(ConvArgs a, Geometry geo)
             }
         }
 
-        // epilogue: D row = output channel 16 nb + 4 kq + r, column = pixel j
+        // epilogue: D row = output channel 16 nb + 4 kq + r, column = pixel j.
+        // Stores go through a resource over this wave's output row; pixels
+        // past the frame edge take an out-of-range offset and are dropped.
+        constexpr int ESZ = Store<P>::ESZ;
+        char *sO = sT + L::OOFF + wave * L::OWAVE;          // this wave's staging row
+        if constexpr (RES && STAGE) {
+#pragma unroll
+            for (int i = 0; i < NRC; ++i) {
+                const int q = lane + 64 * i, px = q / CPX, part = q - (q / CPX) * CPX;
+                *reinterpret_cast<v4u *>(sO + px * L::OPX + part * 16) = rc[i];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+        // output in phase layout lo = 2^out_shift (1: plain NHWC): pixel (y, x)
+        // is point ((y mod lo) lo + x mod lo) hd wd + (y div lo) wd + x div lo
+        // of the frame; pixels off the frame take an out-of-range offset
+        const int osh = a.out_shift, om = (1 << osh) - 1;
+        const int ohd = (H + om) >> osh, owd = (W + om) >> osh;
+        const int osub = (yo & om) << osh, oiy = yo >> osh;
+        auto out_point = [&](int xo) { return ((osub + (xo & om)) * ohd + oiy) * owd + (xo >> osh); };
+        const __amdgpu_buffer_rsrc_t orow =
+            buf_rsrc(HEAD ? nullptr : static_cast<char *>(a.out) + act * C * ESZ, HEAD ? 0u : 0x7FFFFFFFu);
         float wmax = 0.f;
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
             const int xo = X0 + dd * (16 * p + j);
             const bool ok = xo < W;
-            const int64_t pix = px_off + (int64_t)yo * W + xo;
             float h0 = 0.f, h1 = 0.f, h2 = 0.f, h3 = 0.f, h4 = 0.f;
+            if constexpr (RES && !STAGE && !EARLY_RES) load_res(p);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int oc = nb * 16 + kq * 4;
                 v4f v = acc[nb][p];
                 if constexpr (P == DL_FP8) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] *= a.wscale[oc + r] * qscale;
+                    for (int r = 0; r < 4; ++r) v[r] *= sS[oc + r] * qscale;
                 }
                 v[0] += sB[oc + 0]; v[1] += sB[oc + 1]; v[2] += sB[oc + 2]; v[3] += sB[oc + 3];
-                if (RES && ok) v += Store<P>::load4(a.res, pix * C + oc);
+                uint2 *so = reinterpret_cast<uint2 *>(sO + (16 * p + j) * L::OPX + oc * 2);
+                if constexpr (RES && STAGE) {
+                    const uint2 u = *so;
+                    v += v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xFFFF0000u),
+                             __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xFFFF0000u)};
+                } else if constexpr (RES) {
+                    v += Store<P>::unpack(rr[nb][EARLY_RES ? p : 0]);
+                }
                 v = relu4(v);
                 if constexpr (P != DL_FP32) {        // what is stored (and what the head reads) is BF16
                     v[0] = bf16_round(v[0]); v[1] = bf16_round(v[1]);
                     v[2] = bf16_round(v[2]); v[3] = bf16_round(v[3]);
                 }
-                if (!HEAD) {
-                    if (ok) {
-                        Store<P>::store4(a.out, pix * C + oc, v);
-                        wmax = fmaxf(wmax, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
-                    }
+                if constexpr (STAGE) {
+                    *so = uint2{(__float_as_uint(v[0]) >> 16) | (__float_as_uint(v[1]) & 0xFFFF0000u),
+                                (__float_as_uint(v[2]) >> 16) | (__float_as_uint(v[3]) & 0xFFFF0000u)};
+                    if constexpr (P == DL_FP8)
+                        if (ok && row_ok) wmax = fmaxf(wmax, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+                } else if constexpr (!HEAD) {
+                    Store<P>::bstore4(orow, ok && row_ok ? (out_point(xo) * C + oc) * ESZ : BUF_OOB, v);
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -366,13 +542,13 @@ k_conv(ConvArgs a, Geometry geo)
                     }
                 }
             }
-            if (HEAD) {
+            if constexpr (HEAD) {
                 h0 += __shfl_xor(h0, 16); h0 += __shfl_xor(h0, 32);
                 h1 += __shfl_xor(h1, 16); h1 += __shfl_xor(h1, 32);
                 h2 += __shfl_xor(h2, 16); h2 += __shfl_xor(h2, 32);
                 h3 += __shfl_xor(h3, 16); h3 += __shfl_xor(h3, 32);
                 h4 += __shfl_xor(h4, 16); h4 += __shfl_xor(h4, 32);
-                if (ok) {
+                if (ok && row_ok) {
                     const int64_t plane = (int64_t)H * W;
                     float *mp = a.maps + 5 * px_off + (int64_t)yo * W + xo;
                     const float mine = kq == 0 ? h0 : kq == 1 ? h1 : kq == 2 ? h2 : h3;
@@ -381,7 +557,20 @@ k_conv(ConvArgs a, Geometry geo)
                 }
             }
         }
-        if (!HEAD && a.amax_out) {
+        if constexpr (STAGE) {
+            // the staged row leaves in whole 16-byte lanes; pixels past the
+            // frame edge (and rows off the frame) are dropped as out of range
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+            for (int i = 0; i < NRC; ++i) {
+                const int q = lane + 64 * i, px = q / CPX, part = q - (q / CPX) * CPX;
+                const int xo = X0 + dd * px;
+                const v4u d = *reinterpret_cast<const v4u *>(sO + px * L::OPX + part * 16);
+                __builtin_amdgcn_raw_buffer_store_b128(d, orow, row_ok && xo < W ? out_point(xo) * (C * 2) + part * 16 : BUF_OOB,
+                                                       0, 0);
+            }
+        }
+        if (P == DL_FP8 && !HEAD && a.amax_out) {
             // ReLU outputs are >= 0, so float order equals unsigned order of the bits
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, o));
@@ -503,7 +692,7 @@ uint8_t host_e4m3(float x)
 void conv_tile_shape(int C, int precision, int rows, int *tr, int *tc)
 {
     (void)C;
-    *tr = rows == 4 ? 4 : 8;
+    *tr = rows == 4 || (rows == 0 && precision == DL_FP32) ? 4 : 8;
     switch (precision) {
     case DL_FP32: *tc = TileShape<DL_FP32>::TC; break;
     case DL_BF16: *tc = TileShape<DL_BF16>::TC; break;

@@ -68,7 +68,7 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
             for (int t = 0; t < 9; ++t) acc = fmaf(sw[c * 9 + t], xin[t], acc);
             o[k] = fmaxf(acc, 0.f);
         }
-        const int64_t pix = fd.px_off + (int64_t)y * W + x;
+        const int64_t pix = fd.act_off + (int64_t)y * W + x;     // plain NHWC
         if (BF16OUT) {
             const uint32_t b0 = f32_to_bf16_rne(o[0]), b1 = f32_to_bf16_rne(o[1]);
             const uint32_t b2 = f32_to_bf16_rne(o[2]), b3 = f32_to_bf16_rne(o[3]);
@@ -291,7 +291,7 @@ k_active_lists(const FrameDesc *__restrict__ fdp, Geometry geo, const uint8_t *_
     const FrameDesc &fd = fdp[f];       // read in place: tile_start is indexed by the block
     const int d = dil[b];
     int Y0, X0;
-    decode_tile(fd, t - fd.tile_start[b], d, geo.tr, geo.tc, Y0, X0);
+    decode_tile(fd.w, t - fd.tile_start[b], d, geo.tr, geo.tc, Y0, X0);
     if (Y0 >= fd.h || X0 >= fd.w) return;
     const int y1 = min(fd.h - 1, Y0 + d * (geo.tr - 1)), x1 = min(fd.w - 1, X0 + d * (geo.tc - 1));
     for (int k = 0; k < 2; ++k) {
