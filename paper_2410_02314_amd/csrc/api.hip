@@ -668,6 +668,9 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     dl_net_info info;
     std::vector<float> params;
     if ((rc = parse_weights(weights, nbytes, &info, &params))) return rc;
+    if (!conv_supported(info.C, c.precision))
+        return fail(nullptr, DL_ERR_UNSUPPORTED, "C = %d does not fit the %s conv kernel's LDS", info.C,
+                    c.precision == DL_FP32 ? "FP32" : c.precision == DL_BF16 ? "BF16" : "FP8");
     const uint32_t C = (uint32_t)info.C, nb = (uint32_t)info.nblocks;
 
     // ---- arguments are valid; device work starts here ----

@@ -152,9 +152,11 @@ struct ConvArgs {
 };
 hipError_t launch_conv(int C, int precision, const ConvArgs &a, const Geometry &g, int grid, hipStream_t s);
 // tile shape of the conv kernel: rows = 4 or 8; 0 picks the form's default
-// (4 for FP32, 8 otherwise)
+// (8, except FP32 with C > 48: 4)
 void conv_tile_shape(int C, int precision, int rows, int *tr, int *tc);
 int conv_max_grid(int C, int precision, int tr, int ncu);
+// does the conv kernel of this channel count and form fit in LDS (both tile heights)?
+bool conv_supported(int C, int precision);
 size_t conv_packed_bytes(int C, int precision);
 // pack one 3x3 C->C layer W [C][C][3][3]; FP8 also writes scale[C]
 void pack_conv_weights(int C, int precision, const float *W, void *dst, float *scale);

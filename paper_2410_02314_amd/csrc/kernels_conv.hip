@@ -128,7 +128,7 @@ template <int C, int P> struct KPlan;
 template <int C> struct KPlan<C, DL_FP32> {
     static constexpr int NIT = 9 * (C / 16);
     static constexpr int BYTES = 9 * C * C * 4;
-    static constexpr int LDS_W = 0;               // weights stay in global memory
+    static constexpr int LDS_W = BYTES;           // in LDS when the tile leaves room (see Lds)
     static constexpr int LESZ = 4;                // LDS bytes per channel
 };
 template <int C> struct KPlan<C, DL_BF16> {
@@ -164,8 +164,13 @@ struct Lds {
     static constexpr int PW = TC + 2;
     static constexpr int NPT = (TR + 2) * PW;
     static constexpr int TBYTES = align16(NPT * PS);
+    static constexpr int EXTRA = C * 4 + (5 * C + 5) * 4 + C * 4 + 64;  // bias, head, scales, alignment
+    // FP32 keeps its weights in LDS when they fit beside the tile (C <= 48 at
+    // 8 rows); otherwise each K iteration reads them from L2, one ahead
+    static constexpr bool LDSW_FP32 = TBYTES + KPlan<C, P>::BYTES + EXTRA <= 160 * 1024;
+    static constexpr int LDSW = P == DL_FP32 ? (LDSW_FP32 ? KPlan<C, P>::BYTES : 0) : KPlan<C, P>::LDS_W;
     static constexpr int WOFF = TBYTES;
-    static constexpr int BOFF = WOFF + KPlan<C, P>::LDS_W;            // bias [C]
+    static constexpr int BOFF = WOFF + LDSW;                           // bias [C]
     static constexpr int HOFF = BOFF + C * 4;                          // head [5C + 5]
     static constexpr int SOFF = HOFF + (5 * C + 5) * 4;                // FP8 weight scales [C]
     // BF16 and FP8 stage each wave's output row (TC pixels x C BF16 values,
@@ -174,6 +179,7 @@ struct Lds {
     static constexpr int OWAVE = P == DL_FP32 ? 0 : TC * OPX;
     static constexpr int OOFF = align16(SOFF + C * 4);
     static constexpr int TOTAL = align16(OOFF + TR * OWAVE);
+    static constexpr bool FITS = TOTAL <= 160 * 1024;   // else no kernel exists for this shape
 };
 
 // --------------------------------------------------------------- kernel
@@ -195,10 +201,10 @@ k_conv(ConvArgs a, Geometry geo)
     const int j = lane & 15, kq = lane >> 4;
     const int dd = a.d, blk = a.blk;
 
-    if constexpr (KPlan<C, P>::LDS_W > 0) {
+    if constexpr (L::LDSW > 0) {
         const v4f *gw = static_cast<const v4f *>(a.wpk);
         v4f *sW = reinterpret_cast<v4f *>(sT + L::WOFF);
-        for (int i = tid; i < KPlan<C, P>::LDS_W / 16; i += NT) sW[i] = gw[i];
+        for (int i = tid; i < L::LDSW / 16; i += NT) sW[i] = gw[i];
     }
     for (int i = tid; i < C; i += NT) sB[i] = a.bias[i];
     if (HEAD)
@@ -207,8 +213,9 @@ k_conv(ConvArgs a, Geometry geo)
         for (int i = tid; i < C; i += NT) sS[i] = a.wscale[i];
     // FP32: the weights of K iteration 0, read ahead of every tile (the last
     // iteration of a tile reads them for the next)
-    v4f awn[P == DL_FP32 ? NB : 1];
-    if constexpr (P == DL_FP32)
+    constexpr bool GW = P == DL_FP32 && !L::LDSW_FP32;
+    v4f awn[GW ? NB : 1];
+    if constexpr (GW)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) awn[nb] = static_cast<const v4f *>(a.wpk)[nb * 64 + lane];
 
@@ -336,10 +343,12 @@ k_conv(ConvArgs a, Geometry geo)
         const bool row_ok = yo < H;
         // BF16/FP8 without the head: output (and residual) pass through this
         // wave's LDS staging row and move in whole 16-byte lanes.  The fused
-        // head layer keeps the residual in the MFMA layout (EARLY_RES), and
-        // FP32 loads it in the epilogue, one pixel block at a time.
+        // head layer and FP32 with weights in LDS load the residual in the
+        // MFMA layout before the next tile's input (EARLY_RES); FP32 with
+        // weights in L2 has no registers to spare and loads it in the
+        // epilogue, one pixel block at a time.
         constexpr bool STAGE = P != DL_FP32 && !HEAD;
-        constexpr bool EARLY_RES = RES && P != DL_FP32 && HEAD;
+        constexpr bool EARLY_RES = RES && (P != DL_FP32 ? HEAD : L::LDSW_FP32);
         constexpr int CPX = C * 2 / 16;                     // 16-byte chunks per staged pixel
         constexpr int NRC = STAGE ? TC * CPX / 64 : 1;      // chunks per lane
         static_assert(!STAGE || (TC * CPX) % 64 == 0, "staging chunks per lane");
@@ -370,11 +379,12 @@ k_conv(ConvArgs a, Geometry geo)
             }
         };
         if constexpr (EARLY_RES) load_res(0);
-        // the next tile's input.  BF16/FP8: past the last tile the current one
-        // is read again (and not used), so no branch separates the residual
-        // loads from the prefetch and the wait for them stays exact; FP32 has
-        // nothing to wait for before its epilogue and skips the read.
-        if constexpr (P == DL_FP32) {
+        __builtin_amdgcn_sched_barrier(0);   // residual loads stay ahead of the prefetch
+        // the next tile's input.  Past the last tile the current one is read
+        // again (and not used), so no branch separates the residual loads from
+        // the prefetch and the wait for them stays exact.  FP32 with weights
+        // in L2 (4-row tiles, no register room for that) skips the read.
+        if constexpr (GW) {
             if (ti + nslot < t1) fetch(ti + nslot);
         } else {
             fetch(ti + nslot < t1 ? ti + nslot : ti);
@@ -395,17 +405,23 @@ k_conv(ConvArgs a, Geometry geo)
         if constexpr (P == DL_FP32) {
             constexpr int G = C / 16, NIT = KPlan<C, P>::NIT;
             const v4f *gw = static_cast<const v4f *>(a.wpk);
+            const v4f *sW = reinterpret_cast<const v4f *>(sT + L::WOFF);
 #pragma unroll 1
             for (int tap = 0; tap < 9; ++tap) {
 #pragma unroll
                 for (int gg = 0; gg < G; ++gg) {
                     const int it = tap * G + gg;
                     v4f aw[NB];
+                    if constexpr (GW) {
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) aw[nb] = awn[nb];
-                    const int itn = it + 1 < NIT ? it + 1 : 0;
+                        for (int nb = 0; nb < NB; ++nb) aw[nb] = awn[nb];
+                        const int itn = it + 1 < NIT ? it + 1 : 0;
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) awn[nb] = gw[(itn * NB + nb) * 64 + lane];
+                        for (int nb = 0; nb < NB; ++nb) awn[nb] = gw[(itn * NB + nb) * 64 + lane];
+                    } else {
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb) aw[nb] = sW[(it * NB + nb) * 64 + lane];
+                    }
                     v4f bv[PB];
 #pragma unroll
                     for (int p = 0; p < PB; ++p)
@@ -583,17 +599,21 @@ k_conv(ConvArgs a, Geometry geo)
 template <int C, int P, int TR, bool RES, bool HEAD>
 hipError_t launch_t(const ConvArgs &a, const Geometry &g, int grid, hipStream_t s)
 {
-    auto kern = k_conv<C, P, TR, RES, HEAD>;
-    constexpr size_t sh = Lds<C, P, TR>::TOTAL;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        if (e != hipSuccess) return e;
-        attr = true;
+    if constexpr (!Lds<C, P, TR>::FITS) {
+        return hipErrorInvalidValue;
+    } else {
+        auto kern = k_conv<C, P, TR, RES, HEAD>;
+        constexpr size_t sh = Lds<C, P, TR>::TOTAL;
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(TR * 64), sh, s, a, g);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TR * 64), sh, s, a, g);
-    return hipGetLastError();
 }
 
 template <int C, int P, int TR>
@@ -615,12 +635,29 @@ hipError_t launch_cp(const ConvArgs &a, const Geometry &g, int grid, hipStream_t
 template <int C, int P, int TR>
 int blocks_per_cu()
 {
-    int nb = 0;
-    auto kern = k_conv<C, P, TR, true, false>;
-    constexpr size_t sh = Lds<C, P, TR>::TOTAL;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, TR * 64, sh) != hipSuccess) nb = 1;
-    return nb > 0 ? nb : 1;
+    if constexpr (!Lds<C, P, TR>::FITS) {
+        return 1;
+    } else {
+        int nb = 0;
+        auto kern = k_conv<C, P, TR, true, false>;
+        constexpr size_t sh = Lds<C, P, TR>::TOTAL;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sh);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, TR * 64, sh) != hipSuccess) nb = 1;
+        return nb > 0 ? nb : 1;
+    }
+}
+
+template <int P>
+bool fits_p(int C)
+{
+    switch (C) {
+    case 16: return Lds<16, P, 4>::FITS && Lds<16, P, 8>::FITS;
+    case 32: return Lds<32, P, 4>::FITS && Lds<32, P, 8>::FITS;
+    case 48: return Lds<48, P, 4>::FITS && Lds<48, P, 8>::FITS;
+    case 64: return Lds<64, P, 4>::FITS && Lds<64, P, 8>::FITS;
+    default: return false;
+    }
 }
 
 template <int P>
@@ -691,13 +728,21 @@ uint8_t host_e4m3(float x)
 
 void conv_tile_shape(int C, int precision, int rows, int *tr, int *tc)
 {
-    (void)C;
-    *tr = rows == 4 || (rows == 0 && precision == DL_FP32) ? 4 : 8;
+    // FP32 defaults to 8 rows when its weights then fit in LDS (C <= 48)
+    *tr = rows == 4 || (rows == 0 && precision == DL_FP32 && C > 48) ? 4 : 8;
     switch (precision) {
     case DL_FP32: *tc = TileShape<DL_FP32>::TC; break;
     case DL_BF16: *tc = TileShape<DL_BF16>::TC; break;
     default: *tc = TileShape<DL_FP8>::TC; break;
     }
+}
+
+bool conv_supported(int C, int precision)
+{
+    if (precision == DL_FP32) return fits_p<DL_FP32>(C);
+    if (precision == DL_BF16) return fits_p<DL_BF16>(C);
+    if (precision == DL_FP8) return fits_p<DL_FP8>(C);
+    return false;
 }
 
 size_t conv_packed_bytes(int C, int precision)
