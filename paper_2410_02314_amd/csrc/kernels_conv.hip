@@ -24,7 +24,9 @@
 //         of 8 channels of one tap and lane group kq of step m takes chunk
 //         4 m + kq (one 16-byte LDS read).  Weights live in LDS.
 //   FP8   v_mfma_scale_f32_16x16x128_f8f6f4 with e4m3 operands (unit block
-//         scales); lane group kq of step m takes chunks 16 m + 4 kq + 0..3.
+//         scales); K runs tap by tap with each tap's channels padded to a
+//         multiple of 32, and lane group kq of step m takes one 32-channel
+//         half of one tap (two 16-byte LDS reads).
 //         Activations are stored in BF16; staging quantises them into LDS with
 //         the frame's scale amax / 448 (v_cvt_pk_fp8_f32: OCP e4m3, round to
 //         nearest even; inputs clamped to 448 so it saturates);
@@ -64,10 +66,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(void *base, uint32_t 
 // SQ_LDS_BANK_CONFLICT over the exact read and staging-write patterns of the
 // FP32 and BF16 kernels (every C in 16..64: zero read conflicts at 8 mod 16,
 // about 4 extra cycles per read at 4 or 12 mod 16, 12 or more at 0 mod 16).
-// The FP8 kernel reads 8 bytes per lane (ds_read_b64); its strides are the
-// measured best, with no conflict-free choice among those tried.
 constexpr int stride_8_mod_16(int dw) { return dw + ((8 - dw % 16) + 16) % 16; }
-constexpr int fp8_stride(int dw) { return dw == 4 ? 10 : dw == 8 ? 10 : dw == 12 ? 12 : dw == 16 ? 18 : dw; }
 constexpr int align16(int b) { return (b + 15) / 16 * 16; }
 
 __device__ __forceinline__ v4f relu4(v4f v)
@@ -139,8 +138,11 @@ template <int C> struct KPlan<C, DL_BF16> {
     static constexpr int LESZ = 2;
 };
 template <int C> struct KPlan<C, DL_FP8> {
-    static constexpr int CH8 = C / 8, NCH = 9 * CH8;
-    static constexpr int NIT = (NCH + 15) / 16;
+    // K runs tap by tap, each tap's channels padded to CT (a multiple of 32):
+    // K chunk g (32 channels) is half g % HPT of tap g / HPT, and lane group
+    // kq of step m takes chunk 4 m + kq -- 32 consecutive bytes of one point
+    static constexpr int CT = (C + 31) / 32 * 32, HPT = CT / 32, NG = 9 * HPT;
+    static constexpr int NIT = (NG + 3) / 4;
     static constexpr int BYTES = NIT * (C / 16) * 64 * 32;
     static constexpr int LDS_W = BYTES;
     static constexpr int LESZ = 1;
@@ -160,7 +162,9 @@ template <int P, int TR> constexpr int min_waves() { return P == DL_FP32 && TR =
 template <int C, int P, int TR_>
 struct Lds {
     static constexpr int TR = TR_, TC = TileShape<P>::TC;
-    static constexpr int PS = (P == DL_FP8 ? fp8_stride(C / 4) : stride_8_mod_16(C * KPlan<C, P>::LESZ / 4)) * 4;   // bytes per point
+    // bytes per point; FP8 points hold the tap's padded CT bytes (the padding
+    // is zeroed once, staging writes only the C real channels)
+    static constexpr int PS = stride_8_mod_16(P == DL_FP8 ? (C + 31) / 32 * 8 : C * KPlan<C, P>::LESZ / 4) * 4;
     static constexpr int PW = TC + 2;
     static constexpr int NPT = (TR + 2) * PW;
     static constexpr int TBYTES = align16(NPT * PS);
@@ -209,8 +213,12 @@ k_conv(ConvArgs a, Geometry geo)
     for (int i = tid; i < C; i += NT) sB[i] = a.bias[i];
     if (HEAD)
         for (int i = tid; i < 5 * C + 5; i += NT) sH[i] = a.head[i];
-    if constexpr (P == DL_FP8)
+    if constexpr (P == DL_FP8) {
         for (int i = tid; i < C; i += NT) sS[i] = a.wscale[i];
+        // the channel padding of every point must read as e4m3 zero (never
+        // written by staging, and uninitialised LDS may hold NaN codes)
+        for (int i = tid; i < L::TBYTES / 16; i += NT) smem[i] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
     // FP32: the weights of K iteration 0, read ahead of every tile (the last
     // iteration of a tile reads them for the next)
     constexpr bool GW = P == DL_FP32 && !L::LDSW_FP32;
@@ -281,6 +289,21 @@ k_conv(ConvArgs a, Geometry geo)
             pf[k] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(
                                                 rin, ok ? (nA0 + ii * nRS + jj * nCS) * (C * SESZ) + ch * 16 : BUF_OOB, 0, 0));
         }
+    };
+
+    // FP8: each wave keeps the max of what it stores over its consecutive
+    // tiles of one frame and publishes it with one atomic per frame change
+    // (ReLU outputs are >= 0, so float order is the unsigned order of the bits)
+    float run_max = 0.f;
+    int run_f = -1;
+    auto flush_max = [&]() {
+        if (run_f >= 0 && a.amax_out) {
+            float v = run_max;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+            if (lane == 0) atomicMax(a.amax_out + run_f, __float_as_uint(v));
+        }
+        run_max = 0.f;
     };
 
     int64_t ti = t0 + slot;
@@ -457,28 +480,27 @@ k_conv(ConvArgs a, Geometry geo)
                             __builtin_bit_cast(v8bf, av[nb]), __builtin_bit_cast(v8bf, bv[p]), acc[nb][p], 0, 0, 0);
             }
         } else {
-            constexpr int CH8 = KPlan<C, P>::CH8, NCH = KPlan<C, P>::NCH, NIT = KPlan<C, P>::NIT;
+            constexpr int HPT = KPlan<C, P>::HPT, NIT = KPlan<C, P>::NIT;
             const char *sW = sT + L::WOFF;
 #pragma unroll 1
             for (int m = 0; m < NIT; ++m) {
+                // this lane's K chunk: half hf of tap t (past the ninth tap the
+                // weights are zero and any point will do)
+                const int g = 4 * m + kq, t = g / HPT, hf = g - (g / HPT) * HPT;
+                const int tc = t < 9 ? t : 4;
+                const int boff = ((tc / 3) * PW + tc % 3) * PS + hf * 32;
                 v8i av[NB], bv[PB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const uint4 *pa = reinterpret_cast<const uint4 *>(sW + ((m * NB + nb) * 64 + lane) * 32);
-                    const uint4 lo = pa[0], hi = pa[1];
-                    av[nb] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                    const v4u *pa = reinterpret_cast<const v4u *>(sW + ((m * NB + nb) * 64 + lane) * 32);
+                    const v4u lo = pa[0], hi = pa[1];
+                    av[nb] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
                 }
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int ch = 16 * m + 4 * kq + s;
-                    const int tap = ch < NCH ? ch / CH8 : 4;
-                    const int c0 = ch < NCH ? (ch - (ch / CH8) * CH8) * 8 : 0;
-#pragma unroll
-                    for (int p = 0; p < PB; ++p) {
-                        const uint2 u = *reinterpret_cast<const uint2 *>(pt_addr(p, tap) + c0);
-                        bv[p][2 * s] = (int)u.x;
-                        bv[p][2 * s + 1] = (int)u.y;
-                    }
+                for (int p = 0; p < PB; ++p) {
+                    const v4u *pb = reinterpret_cast<const v4u *>(sT + (wave * PW + 16 * p + j) * PS + boff);
+                    const v4u lo = pb[0], hi = pb[1];
+                    bv[p] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
                 }
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
@@ -586,13 +608,15 @@ k_conv(ConvArgs a, Geometry geo)
                                                        0, 0);
             }
         }
-        if (P == DL_FP8 && !HEAD && a.amax_out) {
-            // ReLU outputs are >= 0, so float order equals unsigned order of the bits
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, o));
-            if (lane == 0) atomicMax(a.amax_out + f, __float_as_uint(wmax));
+        if constexpr (P == DL_FP8 && !HEAD) {
+            if (f != run_f) {
+                flush_max();
+                run_f = f;
+            }
+            run_max = fmaxf(run_max, wmax);
         }
     }
+    if constexpr (P == DL_FP8 && !HEAD) flush_max();
 }
 
 // ------------------------------------------------------------- launchers
@@ -750,7 +774,8 @@ size_t conv_packed_bytes(int C, int precision)
     const int NB = C / 16, NCH = 9 * (C / 8);
     if (precision == DL_FP32) return (size_t)9 * C * C * 4;
     if (precision == DL_BF16) return (size_t)((NCH + 3) / 4) * NB * 64 * 16;
-    return (size_t)((NCH + 15) / 16) * NB * 64 * 32;
+    const int HPT = (C + 31) / 32;
+    return (size_t)((9 * HPT + 3) / 4) * NB * 64 * 32;
 }
 
 void pack_conv_weights(int C, int precision, const float *W, void *dst, float *scale)
@@ -788,7 +813,8 @@ void pack_conv_weights(int C, int precision, const float *W, void *dst, float *s
         return;
     }
     // FP8: per-output-channel scale s[o] = max|W[o]| / 448; codes of W * (448 / max|W[o]|);
-    // step m, block nb, lane (i, kq): 32 bytes = chunks 16 m + 4 kq + 0..3
+    // step m, block nb, lane (i, kq): 32 bytes = channels 32 hf .. 32 hf + 31 of
+    // tap t, where K chunk g = 4 m + kq is half hf = g mod HPT of tap t = g / HPT
     std::vector<float> inv(C);
     for (int oc = 0; oc < C; ++oc) {
         float mx = 0.f;
@@ -796,15 +822,16 @@ void pack_conv_weights(int C, int precision, const float *W, void *dst, float *s
         scale[oc] = mx > 0.f ? (float)((double)mx / 448.0) : 0.f;
         inv[oc] = mx > 0.f ? (float)(448.0 / (double)mx) : 0.f;
     }
-    const int NIT = (NCH + 15) / 16;
+    const int HPT = (C + 31) / 32, NIT = (9 * HPT + 3) / 4;
     uint8_t *o = static_cast<uint8_t *>(dst);
     for (int m = 0; m < NIT; ++m)
         for (int nb = 0; nb < NB; ++nb)
             for (int lane = 0; lane < 64; ++lane) {
                 const int oc = nb * 16 + (lane & 15);
+                const int g = 4 * m + (lane >> 4), tap = g / HPT, hf = g % HPT;
                 for (int e = 0; e < 32; ++e) {
-                    const int ch = 16 * m + 4 * (lane >> 4) + e / 8;
-                    const float v = ch < NCH ? wt(oc, (ch % CH8) * 8 + e % 8, ch / CH8) : 0.f;
+                    const int c = hf * 32 + e;
+                    const float v = tap < 9 && c < C ? wt(oc, c, tap) : 0.f;
                     o[((size_t)(m * NB + nb) * 64 + lane) * 32 + e] = host_e4m3(v * inv[oc]);
                 }
             }
