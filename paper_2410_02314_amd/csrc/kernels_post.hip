@@ -11,8 +11,6 @@ namespace dloc {
 
 namespace {
 
-__device__ __forceinline__ int64_t row_key(const FrameDesc &d) { return d.row_start; }
-
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 {
     uint32_t u = __float_as_uint(f);
@@ -21,83 +19,117 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 }
 
 // ---------------------------------------------------------------- stem
-// One workgroup per global row.  x = (ADU - offset) * scale (scale = gain *
-// in_scale), then a = ReLU(b + sum_tap w * x) for C channels, 3x3, d = 1,
-// zero padding.  A thread produces 4 channels of one pixel, so consecutive
-// threads store consecutive 16-byte chunks of the NHWC row.
+// x = (ADU - offset) * scale (scale = gain * in_scale), then
+// a = ReLU(b + sum_tap w * x) for C channels, 3x3, d = 1, zero padding,
+// stored as plain NHWC rows.  Each workgroup takes a contiguous range of the
+// batch's rows; a row is done in segments of SSEG pixels whose three input rows (preprocessed,
+// with a one-pixel zero border) are staged in LDS.  A thread item is one
+// 16-byte piece of a pixel's output (8 BF16 or 4 FP32 channels), so
+// consecutive threads store consecutive 16 bytes of the row.
+constexpr int SSEG = 1024;
+
 template <int C, bool BF16OUT>
 __global__ void __launch_bounds__(256)
-k_stem(const FrameDesc *__restrict__ fdp, int nf, const float *__restrict__ w,
+k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__restrict__ w,
        const float *__restrict__ b, float offset, float scale, void *__restrict__ act,
        uint32_t *__restrict__ amax, const uint8_t *__restrict__ keep, int radius)
 {
+    constexpr int CQ = BF16OUT ? 8 : 4;      // channels per item: one 16-byte store
+    constexpr int IPX = C / CQ;              // items per pixel
     __shared__ float sw[C * 9];
     __shared__ float sb[C];
+    __shared__ float sx[3][SSEG + 2];
     for (int i = threadIdx.x; i < C * 9; i += 256) sw[i] = w[i];
     for (int i = threadIdx.x; i < C; i += 256) sb[i] = b[i];
-    __syncthreads();
 
-    const int64_t row = blockIdx.x;
-    const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
-    const FrameDesc fd = fdp[f];
-    const int y = (int)(row - fd.row_start);
-    const int H = fd.h, W = fd.w;
-    constexpr int CG = C / 4;
-    // gated runs: only rows / 64-pixel segments within `radius` of a kept tile
-    if (!near_kept(keep, fd, y, y, 0, W - 1, radius)) return;
-    float vmax = 0.f;
-    for (int i = threadIdx.x; i < W * CG; i += 256) {
-        const int x = i / CG;
-        const int cg = i - x * CG;
-        if (keep && !near_kept(keep, fd, y, y, x & ~63, min(W - 1, (x & ~63) + 63), radius)) continue;
-        float xin[9];
-#pragma unroll
-        for (int u = 0; u < 3; ++u)
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const int yy = y + u - 1, xx = x + v - 1;
-                const bool ok = (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
-                xin[u * 3 + v] = ok ? ((float)fd.data[(int64_t)yy * fd.stride + xx] - offset) * scale : 0.f;
+    // FP8: the max of what this wave stores, published once per frame change
+    // (outputs are >= 0, so float order is the unsigned order of the bits)
+    float run_max = 0.f;
+    int run_f = -1;
+    auto flush = [&]() {
+        if (amax && run_f >= 0) {
+            float v = run_max;
+            for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+            if ((threadIdx.x & 63) == 0) atomicMax(amax + run_f, __float_as_uint(v));
+        }
+        run_max = 0.f;
+    };
+
+    // a contiguous range of rows per workgroup (mostly one frame)
+    const int64_t per = (nrows + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(nrows, r0 + per);
+    for (int64_t row = r0; row < r1; ++row) {
+        const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
+        const FrameDesc &fd = fdp[f];
+        const int y = (int)(row - fd.row_start);
+        const int H = fd.h, W = fd.w;
+        if (f != run_f) {
+            flush();
+            run_f = f;
+        }
+        // gated runs: only rows / 64-pixel segments within `radius` of a kept tile
+        if (!near_kept(keep, fd, y, y, 0, W - 1, radius)) continue;
+        for (int x0 = 0; x0 < W; x0 += SSEG) {
+            const int n = min(SSEG, W - x0);
+            __syncthreads();                  // previous segment's reads (and the weights) are done
+            for (int i = threadIdx.x; i < 3 * (SSEG + 2); i += 256) {
+                const int r = i / (SSEG + 2), c = i - r * (SSEG + 2);
+                const int yy = y + r - 1, xx = x0 + c - 1;
+                const bool ok = c < n + 2 && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+                sx[r][c] = ok ? ((float)fd.data[(int64_t)yy * fd.stride + xx] - offset) * scale : 0.f;
             }
-        float o[4];
+            __syncthreads();
+            for (int i = threadIdx.x; i < n * IPX; i += 256) {
+                const int px = i / IPX, q = i - (i / IPX) * IPX;
+                const int x = x0 + px;
+                if (keep && !near_kept(keep, fd, y, y, x & ~63, min(W - 1, (x & ~63) + 63), radius)) continue;
+                float xin[9];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int c = cg * 4 + k;
-            float acc = sb[c];
+                for (int u = 0; u < 3; ++u)
 #pragma unroll
-            for (int t = 0; t < 9; ++t) acc = fmaf(sw[c * 9 + t], xin[t], acc);
-            o[k] = fmaxf(acc, 0.f);
-        }
-        const int64_t pix = fd.act_off + (int64_t)y * W + x;     // plain NHWC
-        if (BF16OUT) {
-            const uint32_t b0 = f32_to_bf16_rne(o[0]), b1 = f32_to_bf16_rne(o[1]);
-            const uint32_t b2 = f32_to_bf16_rne(o[2]), b3 = f32_to_bf16_rne(o[3]);
-            uint2 pk;
-            pk.x = b0 | (b1 << 16);
-            pk.y = b2 | (b3 << 16);
-            *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(act) + pix * C + cg * 4) = pk;
-            vmax = fmaxf(vmax, fmaxf(fmaxf(__uint_as_float(b0 << 16), __uint_as_float(b1 << 16)),
-                                     fmaxf(__uint_as_float(b2 << 16), __uint_as_float(b3 << 16))));
-        } else {
-            *reinterpret_cast<v4f *>(static_cast<float *>(act) + pix * C + cg * 4) = v4f{o[0], o[1], o[2], o[3]};
+                    for (int v = 0; v < 3; ++v) xin[u * 3 + v] = sx[u][px + v];
+                const int64_t base = (fd.act_off + (int64_t)y * W + x) * C + q * CQ;   // plain NHWC
+                float o[CQ];
+#pragma unroll
+                for (int k = 0; k < CQ; ++k) {
+                    const int c = q * CQ + k;
+                    float acc = sb[c];
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) acc = fmaf(sw[c * 9 + t], xin[t], acc);
+                    o[k] = fmaxf(acc, 0.f);
+                }
+                if constexpr (BF16OUT) {
+                    uint32_t bw[CQ];
+#pragma unroll
+                    for (int k = 0; k < CQ; ++k) {
+                        bw[k] = f32_to_bf16_rne(o[k]);
+                        run_max = fmaxf(run_max, __uint_as_float(bw[k] << 16));
+                    }
+                    uint4 pk;
+                    pk.x = bw[0] | (bw[1] << 16);
+                    pk.y = bw[2] | (bw[3] << 16);
+                    pk.z = bw[4] | (bw[5] << 16);
+                    pk.w = bw[6] | (bw[7] << 16);
+                    *reinterpret_cast<uint4 *>(static_cast<uint16_t *>(act) + base) = pk;
+                } else {
+                    *reinterpret_cast<v4f *>(static_cast<float *>(act) + base) = v4f{o[0], o[1], o[2], o[3]};
+                }
+            }
         }
     }
-    if (amax) {
-        // stored values are >= 0, so float order equals unsigned order of the bits
-        for (int o = 1; o < 64; o <<= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
-        if ((threadIdx.x & 63) == 0) atomicMax(amax + f, __float_as_uint(vmax));
-    }
+    flush();
 }
 
 template <int C>
 hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const float *b, float offset,
                   float scale, void *act, int bf16, uint32_t *amax, const uint8_t *keep, int radius, hipStream_t s)
 {
+    const unsigned grid = (unsigned)std::min<int64_t>(g.total_rows, 8192);
     if (bf16)
-        hipLaunchKernelGGL((k_stem<C, true>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset,
+        hipLaunchKernelGGL((k_stem<C, true>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
                            scale, act, amax, keep, radius);
     else
-        hipLaunchKernelGGL((k_stem<C, false>), dim3((unsigned)g.total_rows), dim3(256), 0, s, fd, g.nf, w, b, offset,
+        hipLaunchKernelGGL((k_stem<C, false>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
                            scale, act, nullptr, keep, radius);
     return hipGetLastError();
 }
