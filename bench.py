@@ -9,10 +9,12 @@ A step is one pass of the whole path over the batch: preprocessing + stem,
 10 dilated convolutions (head fused into the last), detection, scan, emit.
 
 Prints ONE JSON line.  Besides the throughput it reports the roofline of the
-dominant kernel (the 3x3 block convolution, MFMA-bound) from HIP events
-recorded around each launch on its stream during the timed steps, and the
-FP64 CPU oracle timed on a bounded sample of the same workload (which also
-checks the GPU output on that sample).
+dominant kernel (the 3x3 block convolution: MFMA-bound in FP32, HBM-bound in
+BF16 and FP8) from HIP events recorded around each launch on its stream
+during the timed steps, the BF16 and FP8 forms measured on the same frames
+(under "forms", with their speedup over FP32), and the FP64 CPU oracle timed
+on a bounded sample of the same workload, which also scores every form's
+emitters on that sample (recall, precision, RMS offset errors).
 """
 from __future__ import annotations
 
@@ -51,7 +53,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"],
+                    help="the headline form (value, roofline, dtype)")
+    ap.add_argument("--forms", default="bf16,fp8",
+                    help="further forms measured on the same frames and reported under 'forms' ('' = none)")
     ap.add_argument("--frames", type=int, default=16)
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--cpu-sample", type=int, default=640, help="side of the oracle's sample crop (0 = skip)")
@@ -91,12 +96,7 @@ def main():
 
     assert torch.cuda.is_available(), "no HIP device"
     dev = torch.device("cuda:0")
-    net = dl.Net(S.serialize_weights(spec, w), precision=args.precision, tile_rows=args.tile_rows)
     d_frames = torch.from_numpy(frames).to(dev)
-    cap = n * side * side // 64
-    d_out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
-    d_counts = torch.zeros(n + 1, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
     if args.copy_probe_mib > 0:
         # plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters give
         # the scale between counter units and bytes moved
@@ -109,6 +109,57 @@ def main():
         log(f"copy probe: {nb} bytes read + {nb} bytes written per launch")
         del src, dst
 
+    forms = [args.precision] + [f for f in args.forms.split(",") if f and f != args.precision]
+    results = {f: measure_form(args, f, spec, w, d_frames, dl, torch, dev) for f in forms}
+    head = results[args.precision]
+
+    cpu, ref = None, None
+    if args.cpu_sample > 0:
+        cpu, ref = cpu_baseline(args, spec, w, frames, head["net"], dev, head["records"])
+        for f, r in results.items():
+            r["accuracy_vs_oracle"] = accuracy_on_sample(r["records"], ref)
+
+    def public(r):
+        return {k: v for k, v in r.items() if k not in ("net", "records")}
+
+    n, side = args.frames, args.size
+    others = {}
+    for f in forms[1:]:
+        r = public(results[f])
+        r["speedup_vs_" + args.precision] = round(r["value"] / head["value"], 3)
+        others[f] = r
+    res = {
+        "metric": METRIC, "value": head["value"], "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+        "data": "synthetic (seeded astigmatic-PSF SMLM frames; random-init calibrated net)",
+        "config": {"workload": f"{n} x {side}x{side} uint16 frames, astigmatic 3D PSF, net B "
+                               f"(C=48, d=1,2,4,8,16), {args.precision}",
+                   "frames": n, "height": side, "width": side, "net": "B", "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "roofline": head["roofline"], "stage_ms_per_step": head["stage_ms_per_step"],
+        "emitters_per_step": head["emitters_per_step"],
+        "accuracy_vs_oracle": head.get("accuracy_vs_oracle"),
+        "forms": others,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    for r in results.values():
+        r["net"].close()
+
+
+def measure_form(args, precision, spec, w, d_frames, dl, torch, dev):
+    """Time `steps` passes of the whole path in one form on the resident frames;
+    returns throughput, per-stage HIP-event times and the dominant kernel's
+    roofline (the 3x3 block convolution; its launches are bracketed by HIP
+    events on the stream they run on)."""
+    import smlm_synth as S
+    n, side = args.frames, args.size
+    net = dl.Net(S.serialize_weights(spec, w), precision=precision, tile_rows=args.tile_rows)
+    cap = n * side * side // 64
+    d_out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
+    d_counts = torch.zeros(n + 1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         net.localize_device(d_frames, d_out, d_counts, stream)
     torch.cuda.synchronize()
@@ -129,41 +180,65 @@ def main():
     total_px = n * side * side
     value = total_px / (ms_step * 1e-3) / 1e6
     counts = d_counts.cpu().numpy()
-    log(f"{ms_step:.2f} ms/step, {value:.1f} Mpx/s, wall {wall / args.steps * 1e3:.2f} ms/step, "
+    log(f"[{precision}] {ms_step:.2f} ms/step, {value:.1f} Mpx/s, wall {wall / args.steps * 1e3:.2f} ms/step, "
         f"{int(counts[n])} emitters/step")
-    log("stages: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f} ms x{v[1]}" for k, v in prof.items() if v[1]))
+    log(f"[{precision}] stages: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f} ms x{v[1]}" for k, v in prof.items() if v[1]))
 
     C = spec.C
     conv_ms, conv_n = prof["conv"]
     avg_s = conv_ms / conv_n * 1e-3
     flop_launch = 2.0 * 9 * C * C * total_px
-    achieved = flop_launch / avg_s / 1e12
-    roofline = {"bound": "mfma", "kernel": f"k_conv_{args.precision} (3x3 dilated conv, C={C})",
-                "achieved": round(achieved, 2), "peak": PEAKS[args.precision], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAKS[args.precision], 4),
-                "traffic": measured_traffic(f"k_conv {args.precision} C={C} {n}x{side}x{side}"),
-                "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_launch": flop_launch}
-    stage_ms = {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]}
+    tflops = flop_launch / avg_s / 1e12
+    esz = 4 if precision == "fp32" else 2
+    # algorithmic HBM bytes of the mean non-head conv launch: input + output for
+    # all nine, + the residual for the four second convolutions of blocks 1-4
+    nb = len(spec.dilations)
+    n_conv = 2 * nb - 1
+    bytes_launch = total_px * C * esz * (2 * n_conv + (nb - 1)) / n_conv
+    gbs = bytes_launch / avg_s / 1e9
+    key = f"k_conv {precision} C={C} {n}x{side}x{side}"
+    if precision == "fp32":
+        roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAKS[precision], "unit": "TFLOP/s",
+                    "frac": round(tflops / PEAKS[precision], 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "mfma_frac": round(tflops / PEAKS[precision], 4)}
+    roofline.update({"traffic": measured_traffic(key),
+                     "kernel": f"k_conv {precision} (3x3 dilated conv, C={C}; mean of the {n_conv} non-head launches)",
+                     "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_launch": flop_launch,
+                     "algorithmic_bytes_per_launch": round(bytes_launch)})
+    recs = dl.emitters_from_device(d_out, min(int(counts[n]), cap))
+    return {"value": round(value, 2), "ms_per_step": round(ms_step, 3), "roofline": roofline,
+            "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]},
+            "emitters_per_step": int(counts[n]), "net": net, "records": recs}
 
-    cpu = None
-    if args.cpu_sample > 0:
-        recs = dl.emitters_from_device(d_out, min(int(counts[n]), cap))
-        cpu = cpu_baseline(args, spec, w, frames, net, dev, recs)
 
-    res = {
-        "metric": METRIC, "value": round(value, 2), "unit": "Mpixel/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
-        "data": "synthetic (seeded astigmatic-PSF SMLM frames; random-init calibrated net)",
-        "config": {"workload": f"{n} x {side}x{side} uint16 frames, astigmatic 3D PSF, net B "
-                               f"(C=48, d=1,2,4,8,16), {args.precision}",
-                   "frames": n, "height": side, "width": side, "net": "B", "precision": args.precision,
-                   "parallelism": "single GPU"},
-        "roofline": roofline, "stage_ms_per_step": stage_ms, "emitters_per_step": int(counts[n]),
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(res), flush=True)
-    net.close()
+def accuracy_on_sample(recs, ref):
+    """Emitters of frame 0 inside the oracle's exact region against the oracle's
+    records there: one-to-one matching within 1 px (recall, precision, RMS
+    coordinate errors of matched pairs) and the RMS coordinate errors of
+    detections at the same pixel."""
+    from tests.parity import match_by_distance
+    lim = ref["limit"]
+    got = recs[(recs["frame"] == 0) & (recs["row"] < lim) & (recs["col"] < lim)]
+    rr = ref["records"]
+    m = match_by_distance(got, rr, 1.0)
+    # detections at the same pixel in both: the offset heads' error from the
+    # form's arithmetic alone (a maximum that moved to a neighbour pixel
+    # carries a whole-pixel change of the reconstructed position instead)
+    gk = {(int(r), int(c)): i for i, (r, c) in enumerate(zip(got["row"], got["col"]))}
+    pairs = [(gk[(int(r), int(c))], j) for j, (r, c) in enumerate(zip(rr["row"], rr["col"])) if (int(r), int(c)) in gk]
+    if pairs:
+        gi = np.array([p_[0] for p_ in pairs])
+        ri = np.array([p_[1] for p_ in pairs])
+        d = {k: np.asarray(got[kg], np.float64)[gi] - np.asarray(rr[kr], np.float64)[ri]
+             for k, kg, kr in (("x", "x_px", "x"), ("y", "y_px", "y"), ("z", "z_nm", "z"))}
+        m.update({"same_pixel_pairs": len(pairs),
+                  "same_pixel_rms_dx_px": float(np.sqrt(np.mean(d["x"] ** 2))),
+                  "same_pixel_rms_dy_px": float(np.sqrt(np.mean(d["y"] ** 2))),
+                  "same_pixel_rms_dz_nm": float(np.sqrt(np.mean(d["z"] ** 2)))})
+    return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in m.items()}
 
 
 def measured_traffic(key):
@@ -213,13 +288,15 @@ def cpu_baseline(args, spec, w, frames, net, dev, recs):
     ex = exempt_mask(ref_maps[0, 0, :e, :e])[:-1, :-1]
     mism = int(np.sum((ref_det != got_det) & ~ex))
     matched = int(np.sum(ref_det & got_det))
+    rsel = (rec["row"] < e - 1) & (rec["col"] < e - 1)
+    ref = {"records": rec[rsel], "limit": e - 1}
     return {"value": round(s * s / dt / 1e6, 4), "unit": "Mpixel/s", "cores": cpu_threads(), "kind": "oracle",
             "sample": f"frame 0 crop {s}x{s} of the same workload, FP64 oracle (net + detection + records), "
                       f"{dt:.1f} s",
             "sample_check": {"max_map_rel_err": float(err.max()), "oracle_detections": int(ref_det.sum()),
                              "gpu_detections": int(got_det.sum()), "matched": matched,
                              "recall_vs_oracle": matched / max(1, int(ref_det.sum())),
-                             "non_exempt_detection_mismatch": mism, "region": f"{e - 1}x{e - 1}"}}
+                             "non_exempt_detection_mismatch": mism, "region": f"{e - 1}x{e - 1}"}}, ref
 
 
 if __name__ == "__main__":

@@ -152,6 +152,7 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
     g = Geometry{};
     g.nf = n;
     conv_tile_shape(net->C, net->cfg.precision, tile_rows_of(net), &g.tr, &g.tc);
+    g.minor_blk = net->nb - 1;        // its head writes plain planar maps
     for (int f = 0; f < n; ++f) {
         FrameDesc &d = fd[f];
         std::memset(&d, 0, sizeof d);

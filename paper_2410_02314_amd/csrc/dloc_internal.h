@@ -66,16 +66,41 @@ struct Geometry {
     int64_t max_tiles = 0;
     int tr = 8, tc = 64;           // conv tile shape on the sub-lattice
     int maxw = 0;
+    int minor_blk = -1;            // block whose tiles run phase-minor (see decode_tile)
 };
 
-__device__ __forceinline__ void decode_tile(int w, int64_t local, int d, int tr, int tc, int &Y0, int &X0)
+// Order of one frame's conv tiles for one block.  Phase-major: the d*d phase
+// sub-lattices one after another, and within a phase its ry x rx regions in
+// column strips TSTRIP regions wide, row by row inside a strip, so the tile
+// below a tile comes at most TSTRIP tiles later and finds the halo rows they
+// share still in L2 (tiles are handed out in order to the resident
+// workgroups of an XCD).  Phase-minor (the last block, whose head writes
+// plain planar maps): the d*d phases of one region in a row, regions row by
+// row, so the map pixels a region's phases write are written together.
+constexpr uint32_t TSTRIP = 8;
+__device__ __forceinline__ void decode_tile(int h, int w, int64_t local, int d, int tr, int tc, bool phase_minor,
+                                            int &Y0, int &X0)
 {
     // a frame has fewer than 2^32 tiles: 32-bit arithmetic suffices
-    const uint32_t l = (uint32_t)local, d2 = (uint32_t)(d * d);
-    const uint32_t r = l / d2, ph = l - r * d2;
-    const uint32_t py = ph / (uint32_t)d, px = ph - py * (uint32_t)d;
-    const uint32_t rxn = (uint32_t)((w + tc * d - 1) / (tc * d));
-    const uint32_t ry = r / rxn, rx = r - ry * rxn;
+    const uint32_t l = (uint32_t)local, ud = (uint32_t)d;
+    const uint32_t ryn = (uint32_t)((h + tr * d - 1) / (tr * d)), rxn = (uint32_t)((w + tc * d - 1) / (tc * d));
+    uint32_t ph, ry, rx;
+    if (phase_minor) {
+        const uint32_t r = l / (ud * ud);
+        ph = l - r * ud * ud;
+        ry = r / rxn;
+        rx = r - ry * rxn;
+    } else {
+        const uint32_t nreg = ryn * rxn;
+        ph = l / nreg;
+        const uint32_t r = l - ph * nreg;
+        const uint32_t sfull = ryn * TSTRIP;                  // tiles of a full strip
+        const uint32_t st = r / sfull, in = r - st * sfull;
+        const uint32_t sw = min(TSTRIP, rxn - st * TSTRIP);   // width of this strip
+        ry = in / sw;
+        rx = st * TSTRIP + (in - ry * sw);
+    }
+    const uint32_t py = ph / ud, px = ph - py * ud;
     Y0 = (int)(ry * (uint32_t)(tr * d) + py);
     X0 = (int)(rx * (uint32_t)(tc * d) + px);
 }

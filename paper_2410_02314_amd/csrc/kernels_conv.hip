@@ -9,17 +9,24 @@
 // Tiling.  A layer of dilation d works on phase tiles (see conv_tiles): a
 // workgroup computes TR x TC output pixels spaced d apart, whose input is the
 // (TR + 2) x (TC + 2) lattice points around them -- the same LDS footprint
-// for every dilation.  The workgroup stages that input once into LDS (points
-// strided so the MFMA operand reads are free of bank conflicts), then
-// wave w computes lattice row w for all C output channels.  Workgroups are
-// persistent; tiles are handed out XCD by XCD in contiguous ranges, and
-// consecutive tiles are the d*d phases of one region, so they share L2 lines.
+// for every dilation.  Activations feeding a dilation-d block are stored in
+// the phase layout of d (dloc_internal.h: act_points), where those lattice
+// points are contiguous rows of one dense sub-image, so a phase tile reads
+// like a d = 1 tile; each block writes its output straight into the next
+// block's layout.  The workgroup stages its input into LDS (points strided so
+// the MFMA operand reads are free of bank conflicts), then wave w computes
+// lattice row w for all C output channels.  Workgroups are persistent; tiles
+// are handed out XCD by XCD in contiguous ranges, in an order that keeps
+// vertically adjacent tiles close (see decode_tile), so the halo rows they
+// share are read from L2.  The next tile's input is loaded into registers
+// while the MFMAs run on the current one.
 //
 // GEMM view: M = output channels (blocks of 16), N = pixels (blocks of 16),
 // K = 9 taps x C input channels.
 //   FP32  v_mfma_f32_16x16x4_f32; lane group kq takes channels 16 g + 4 kq + s
-//         (s = MFMA step), so one float4 feeds 4 steps.  Weights are read from
-//         global memory (they stay in L1/L2), one K iteration ahead.
+//         (s = MFMA step), so one float4 feeds 4 steps.  Weights live in LDS
+//         when they fit beside the tile (C <= 48 with 8-row tiles); otherwise
+//         they are read from L2 one K iteration ahead.
 //   BF16  v_mfma_f32_16x16x32_bf16 (FP32 accumulation); K is cut into chunks
 //         of 8 channels of one tap and lane group kq of step m takes chunk
 //         4 m + kq (one 16-byte LDS read).  Weights live in LDS.
@@ -29,11 +36,14 @@
 //         half of one tap (two 16-byte LDS reads).
 //         Activations are stored in BF16; staging quantises them into LDS with
 //         the frame's scale amax / 448 (v_cvt_pk_fp8_f32: OCP e4m3, round to
-//         nearest even; inputs clamped to 448 so it saturates);
-//         weights carry a per-output-channel scale.  The epilogue multiplies
-//         the FP32 accumulator by both scales and tracks the max of what it
-//         stores, which sets the next layer's scale.
+//         nearest even; inputs clamped to 448 so it saturates); weights carry
+//         a per-output-channel scale.  The epilogue multiplies the FP32
+//         accumulator by both scales and tracks the max of what it stores,
+//         which sets the next layer's scale.
 // K is padded with zero-weight chunks when 9 C is not a multiple of the MFMA's K.
+// BF16 and FP8 pass each wave's output row (and residual) through LDS so they
+// move in whole 16-byte lanes; every store is a buffer store whose offset is
+// out of range for pixels off the frame, so the epilogue has no branches.
 #include "dloc_internal.h"
 
 #include <cmath>
@@ -263,7 +273,7 @@ k_conv(ConvArgs a, Geometry geo)
         nW = ld_const(&fd->w);
         npx = ld_const(&fd->px_off);
         nact = ld_const(&fd->act_off);
-        decode_tile(nW, t - ld_const(&fd->tile_start[blk]), dd, TR, TC, nY0, nX0);
+        decode_tile(nH, nW, t - ld_const(&fd->tile_start[blk]), dd, TR, TC, blk == geo.minor_blk, nY0, nX0);
         if (a.in_phase) {
             const int hd = (nH + dd - 1) / dd, wd = (nW + dd - 1) / dd;
             const int py = nY0 % dd, px = nX0 % dd;

@@ -323,7 +323,7 @@ k_active_lists(const FrameDesc *__restrict__ fdp, Geometry geo, const uint8_t *_
     const FrameDesc &fd = fdp[f];       // read in place: tile_start is indexed by the block
     const int d = dil[b];
     int Y0, X0;
-    decode_tile(fd.w, t - fd.tile_start[b], d, geo.tr, geo.tc, Y0, X0);
+    decode_tile(fd.h, fd.w, t - fd.tile_start[b], d, geo.tr, geo.tc, b == geo.minor_blk, Y0, X0);
     if (Y0 >= fd.h || X0 >= fd.w) return;
     const int y1 = min(fd.h - 1, Y0 + d * (geo.tr - 1)), x1 = min(fd.w - 1, X0 + d * (geo.tc - 1));
     for (int k = 0; k < 2; ++k) {
