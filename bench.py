@@ -241,17 +241,25 @@ def accuracy_on_sample(recs, ref):
     return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in m.items()}
 
 
+def conv_source_sha256():
+    """Hash of the sources that decide the conv kernel's memory traffic (the
+    kernel and the tile order / layouts it includes)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels_conv.hip", "dloc_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2410_02314_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(key):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (scaled by a plain copy kernel), or None if
     there is no record for this kernel/workload or the kernel source changed
     since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_2410_02314_amd", "csrc", "kernels_conv.hip")
     try:
         rec = json.load(open(path)).get(key)
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = conv_source_sha256()
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_source_sha256") != sha:
