@@ -112,6 +112,7 @@ def sparse(args, S):
     """Tile gate on sparse frames: train the gate on separately seeded frames
     (labels = the ungated BF16 net's detections), then time gated vs ungated
     BF16 net B on 64 x 2048^2 frames and report skip, speedup and recall."""
+    args.precision = "bf16"                          # the gated form runs the BF16 net
     n_eval, side = args.frames if args.frames != 16 else 64, args.size
     t0 = time.time()
     ev = S.render_frames(n_eval, side, side, "sparse", 1005, workers=args.gen_workers or None)
@@ -127,15 +128,21 @@ def sparse(args, S):
     blob = S.serialize_weights(spec, w)
     net = dl.Net(blob, precision="bf16")
     t0 = time.time()
-    pooled, labels = GT.labelled_tiles(net, iter(train_frames), dev)
-    pooled, labels = pooled[:20000], labels[:20000]
+    pooled, labels, counts = GT.labelled_tiles(net, iter(train_frames), dev, with_counts=True)
+    pooled, labels, counts = pooled[:20000], labels[:20000], counts[:20000]
     theta0 = S.gate_flat(S.gate_init(3005))
-    res = GT.train(pooled, labels, theta0, epochs=20, batch=256, lr=3e-3)
-    thr = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.995)
+    res = GT.train(pooled, labels, theta0, epochs=60, batch=256, lr=1e-2)
+    # threshold: 99.9 % of the held-out tiles' detections kept (a margin over
+    # the 99.5 % detection recall the gated form is judged by); the
+    # 99.5 %-of-positive-tiles threshold and the fixed 0.05 are reported beside it
+    thr = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.999, counts)
+    thr_tile = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.995)
     log(f"gate trained in {time.time() - t0:.1f}s: {res.history[-1]}; threshold {thr:.4f}")
     d = torch.from_numpy(ev).to(dev)
     cap = n_eval * side * side // 64
     st = torch.cuda.current_stream()
+
+    stages = {}
 
     def run(gate_theta, thr=0.05):
         g = dl.Net(blob, precision="bf16", flags=dl.DL_FLAG_GATE if gate_theta is not None else 0)
@@ -144,6 +151,12 @@ def sparse(args, S):
         out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
         counts = torch.zeros(n_eval + 1, dtype=torch.int32, device=dev)
         ms = _timed(lambda: g.localize_device(d, out, counts, st), args.steps, args.warmup, st)
+        g.profile(True)
+        g.profile_read()
+        g.localize_device(d, out, counts, st)
+        torch.cuda.synchronize()
+        stages.setdefault(gate_theta is not None, {k: round(v[0], 3) for k, v in g.profile_read().items() if v[1]})
+        g.profile(False)
         rec = dl.emitters_from_device(out, min(int(counts[-1].item()), cap))
         keep = None
         if gate_theta is not None:
@@ -156,22 +169,30 @@ def sparse(args, S):
     ms0, rec0, _ = run(None)
     ms1, rec1, keep = run(res.theta, thr)
     ms5, rec5, keep5 = run(res.theta, 0.05)
+    msT, recT, keepT = run(res.theta, thr_tile)
     k0 = {(a, b, c) for a, b, c in zip(rec0["frame"], rec0["row"], rec0["col"])}
     k1 = {(a, b, c) for a, b, c in zip(rec1["frame"], rec1["row"], rec1["col"])}
     k5 = {(a, b, c) for a, b, c in zip(rec5["frame"], rec5["row"], rec5["col"])}
+    kT = {(a, b, c) for a, b, c in zip(recT["frame"], recT["row"], recT["col"])}
     px = n_eval * side * side
     _line(args, px / (ms1 * 1e-3) / 1e6, ms1,
           {"workload": f"{n_eval} x {side}x{side} sparse frames (30-70% empty 256^2 tiles), gated BF16 net B",
            "net": "B", "precision": "bf16",
-           "gate": f"2 conv x 8 ch + mean pool, threshold {thr:.4f} (99.5% held-out tile recall)",
+           "gate": f"2 conv x 8 ch + mean pool, threshold {thr:.4f} (99.9% of held-out detections kept)",
            "frames": n_eval},
           {"ungated_ms_per_step": round(ms0, 3), "ungated_mpx_s": round(px / (ms0 * 1e-3) / 1e6, 2),
            "speedup_vs_ungated": round(ms0 / ms1, 3), "skipped_tile_fraction": round(float(1 - keep.mean()), 4),
            "recall_vs_ungated": round(len(k0 & k1) / max(1, len(k0)), 5), "extra_border_detections": len(k1 - k0),
+           "at_tile_recall_threshold": {"threshold": round(thr_tile, 4),
+                                        "skipped_tile_fraction": round(float(1 - keepT.mean()), 4),
+                                        "speedup_vs_ungated": round(ms0 / msT, 3),
+                                        "recall_vs_ungated": round(len(k0 & kT) / max(1, len(k0)), 5)},
            "at_threshold_0.05": {"skipped_tile_fraction": round(float(1 - keep5.mean()), 4),
                                  "speedup_vs_ungated": round(ms0 / ms5, 3),
                                  "recall_vs_ungated": round(len(k0 & k5) / max(1, len(k0)), 5)},
-           "gate_val": res.history[-1]})
+           "gate_val": res.history[-1],
+           "stage_ms_gated": stages.get(True), "stage_ms_ungated": stages.get(False),
+           "note": "stage times of one profiled step (gated: at the chosen threshold)"})
 
 
 def pipeline(args, S):

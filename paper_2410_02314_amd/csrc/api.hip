@@ -170,7 +170,9 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         d.keep_start = g.gate_tiles;
         for (int b = 0; b < net->nb; ++b) {
             d.tile_start[b] = g.tiles[b];
-            g.tiles[b] += conv_tiles(d.h, d.w, net->dil[b], g.tr, g.tc);
+            const int64_t nt = conv_tiles(d.h, d.w, net->dil[b], g.tr, g.tc);
+            g.tiles[b] += nt;
+            g.max_frame_tiles = std::max(g.max_frame_tiles, nt);
         }
         g.gate_tiles += (int64_t)d.gtx * d.gty;
         g.total_px += (int64_t)d.h * d.w;

@@ -64,6 +64,7 @@ struct Geometry {
     int64_t total_px = 0, total_act = 0, total_rows = 0, total_words = 0, gate_tiles = 0;
     int64_t tiles[MAXBLK] = {0};   // conv tiles of each block's layers
     int64_t max_tiles = 0;
+    int64_t max_frame_tiles = 0;   // most conv tiles of one frame in one block
     int tr = 8, tc = 64;           // conv tile shape on the sub-lattice
     int maxw = 0;
     int minor_blk = -1;            // block whose tiles run phase-minor (see decode_tile)

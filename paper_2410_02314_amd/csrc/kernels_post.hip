@@ -39,6 +39,7 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__
     __shared__ float sw[C * 9];
     __shared__ float sb[C];
     __shared__ float sx[3][SSEG + 2];
+    __shared__ bool sneed[SSEG / 64];
     for (int i = threadIdx.x; i < C * 9; i += 256) sw[i] = w[i];
     for (int i = threadIdx.x; i < C; i += 256) sb[i] = b[i];
 
@@ -78,11 +79,16 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__
                 const bool ok = c < n + 2 && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
                 sx[r][c] = ok ? ((float)fd.data[(int64_t)yy * fd.stride + xx] - offset) * scale : 0.f;
             }
+            // gated runs: which 64-pixel pieces of the segment are needed
+            if (threadIdx.x < SSEG / 64) {
+                const int xs = x0 + 64 * threadIdx.x;
+                sneed[threadIdx.x] = xs < W && near_kept(keep, fd, y, y, xs, min(W - 1, xs + 63), radius);
+            }
             __syncthreads();
             for (int i = threadIdx.x; i < n * IPX; i += 256) {
                 const int px = i / IPX, q = i - (i / IPX) * IPX;
                 const int x = x0 + px;
-                if (keep && !near_kept(keep, fd, y, y, x & ~63, min(W - 1, (x & ~63) + 63), radius)) continue;
+                if (!sneed[px >> 6]) continue;
                 float xin[9];
 #pragma unroll
                 for (int u = 0; u < 3; ++u)
@@ -307,30 +313,43 @@ k_zero_u32(uint32_t *p, int64_t n)
     if (i < n) p[i] = 0u;
 }
 
-// One thread per conv tile of block b (blockIdx.y): append the tile to the
+// One thread per conv tile of frame blockIdx.z and block blockIdx.y: append the tile to the
 // lists of the block's two layers when their radius brings it within reach
-// of a kept gate tile.  List order depends on atomic arrival, which changes
-// only which workgroup computes a tile.
+// of a kept gate tile.  A wave appends its (consecutive) tiles as one run with
+// one atomic, so a list keeps the tile order within runs of up to 64 tiles
+// and the conv kernels keep their L2 locality; the order of the runs depends
+// on atomic arrival, which changes only which workgroup computes a tile.
 __global__ void __launch_bounds__(256)
 k_active_lists(const FrameDesc *__restrict__ fdp, Geometry geo, const uint8_t *__restrict__ keep,
                const int *__restrict__ radius, const int *__restrict__ dil, int32_t *__restrict__ lists,
                uint32_t *__restrict__ counts)
 {
-    const int b = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= geo.tiles[b]) return;
-    const int f = find_frame(fdp, geo.nf, t, [b](const FrameDesc &d) { return d.tile_start[b]; });
-    const FrameDesc &fd = fdp[f];       // read in place: tile_start is indexed by the block
-    const int d = dil[b];
-    int Y0, X0;
-    decode_tile(fd.h, fd.w, t - fd.tile_start[b], d, geo.tr, geo.tc, b == geo.minor_blk, Y0, X0);
-    if (Y0 >= fd.h || X0 >= fd.w) return;
-    const int y1 = min(fd.h - 1, Y0 + d * (geo.tr - 1)), x1 = min(fd.w - 1, X0 + d * (geo.tc - 1));
+    const int b = blockIdx.y, f = blockIdx.z;
+    const FrameDesc &fd = fdp[f];           // read in place: tile_start is indexed by the block
+    const int64_t first = ld_const(&fd.tile_start[b]);
+    const int64_t end = f + 1 < geo.nf ? ld_const(&fdp[f + 1].tile_start[b]) : geo.tiles[b];
+    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x, t = first + l;
+    const int lane = threadIdx.x & 63;
+    bool act[2] = {false, false};
+    if (t < end) {
+        const int d = dil[b];
+        int Y0, X0;
+        decode_tile(fd.h, fd.w, l, d, geo.tr, geo.tc, b == geo.minor_blk, Y0, X0);
+        if (Y0 < fd.h && X0 < fd.w) {
+            const int y1 = min(fd.h - 1, Y0 + d * (geo.tr - 1)), x1 = min(fd.w - 1, X0 + d * (geo.tc - 1));
+            for (int k = 0; k < 2; ++k) act[k] = near_kept(keep, fd, Y0, y1, X0, x1, radius[2 * b + k]);
+        }
+    }
     for (int k = 0; k < 2; ++k) {
         const int l = 2 * b + k;
-        if (near_kept(keep, fd, Y0, y1, X0, x1, radius[l])) {
-            const uint32_t i = atomicAdd(&counts[l], 1u);
-            lists[(int64_t)l * geo.max_tiles + i] = (int32_t)t;
+        const uint64_t m = __ballot(act[k]);
+        if (m == 0) continue;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&counts[l], (uint32_t)__popcll(m));
+        base = __shfl(base, 0);
+        if (act[k]) {
+            const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            lists[(int64_t)l * geo.max_tiles + base + rank] = (int32_t)t;
         }
     }
 }
@@ -354,7 +373,7 @@ hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uin
 {
     hipError_t e = launch_zero_u32(counts, nlayers, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_active_lists, dim3((unsigned)((g.max_tiles + 255) / 256), nlayers / 2), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_active_lists, dim3((unsigned)((g.max_frame_tiles + 255) / 256), nlayers / 2, g.nf), dim3(256), 0, s,
                        fd, g, keep, radius, dil, lists, counts);
     return hipGetLastError();
 }

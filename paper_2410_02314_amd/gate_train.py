@@ -23,22 +23,28 @@ from . import GATE_NPARAM, GATE_TILE, Net, emitters_from_device, gate_adam, gate
     gate_forward, gate_pool
 
 
+def tile_counts(rec: np.ndarray, n: int, h: int, w: int) -> np.ndarray:
+    """Emitter records per 256^2 tile (tiles frame-major, then row-major)."""
+    gy, gx = h // GATE_TILE, w // GATE_TILE
+    cnt = np.zeros(n * gy * gx, np.float32)
+    if len(rec):
+        t = rec["frame"].astype(np.int64) * gy * gx + (rec["row"] // GATE_TILE) * gx + rec["col"] // GATE_TILE
+        np.add.at(cnt, t, 1.0)
+    return cnt
+
+
 def tile_labels(rec: np.ndarray, n: int, h: int, w: int) -> np.ndarray:
     """1.0 for every 256^2 tile holding at least one emitter record, else 0.0
     (tiles frame-major, then row-major)."""
-    gy, gx = h // GATE_TILE, w // GATE_TILE
-    lab = np.zeros(n * gy * gx, np.float32)
-    if len(rec):
-        t = rec["frame"].astype(np.int64) * gy * gx + (rec["row"] // GATE_TILE) * gx + rec["col"] // GATE_TILE
-        lab[np.unique(t)] = 1.0
-    return lab
+    return (tile_counts(rec, n, h, w) > 0).astype(np.float32)
 
 
-def labelled_tiles(net: Net, frames_iter, device, gain=0.5, offset=100.0, in_scale=0.01):
+def labelled_tiles(net: Net, frames_iter, device, gain=0.5, offset=100.0, in_scale=0.01, with_counts=False):
     """Pool every frame batch into gate tiles and label them with ``net``'s own
-    (ungated) detections.  frames_iter yields uint16 numpy batches [n][h][w]."""
+    (ungated) detections.  frames_iter yields uint16 numpy batches [n][h][w].
+    with_counts: also return the number of detections per tile."""
     import torch
-    pooled, labels = [], []
+    pooled, labels, counts_ = [], [], []
     for frames in frames_iter:
         n, h, w = frames.shape
         d = torch.from_numpy(np.ascontiguousarray(frames)).to(device)
@@ -52,8 +58,11 @@ def labelled_tiles(net: Net, frames_iter, device, gain=0.5, offset=100.0, in_sca
         total = int(counts[n].item())
         rec = emitters_from_device(out, min(total, cap))
         pooled.append(p)
-        labels.append(tile_labels(rec, n, h, w))
-    return torch.cat(pooled), torch.from_numpy(np.concatenate(labels)).to(device)
+        c = tile_counts(rec, n, h, w)
+        counts_.append(c)
+        labels.append((c > 0).astype(np.float32))
+    out = (torch.cat(pooled), torch.from_numpy(np.concatenate(labels)).to(device))
+    return out + (np.concatenate(counts_),) if with_counts else out
 
 
 @dataclass
@@ -63,13 +72,15 @@ class TrainResult:
     val_idx: Optional[np.ndarray] = None
 
 
-def threshold_at_recall(pooled, labels, theta, idx, target: float = 0.995) -> float:
+def threshold_at_recall(pooled, labels, theta, idx, target: float = 0.995, counts=None) -> float:
     """Gate probability threshold chosen on held-out tiles: the largest one
-    that keeps at least ``target`` of the positive tiles."""
+    that keeps at least ``target`` of the positive tiles, or, given the
+    detections per tile (``counts``), at least ``target`` of the detections."""
     import torch
     g = gate_logits(pooled, theta, idx).astype(np.float64)
     y = labels.index_select(0, torch.from_numpy(np.asarray(idx)).to(labels.device)).cpu().numpy() > 0.5
-    t = threshold_for_recall(g, y, target)
+    wts = None if counts is None else np.asarray(counts, np.float64)[np.asarray(idx)]
+    t = threshold_for_recall(g, y, target, wts)
     return float(1.0 / (1.0 + math.exp(-t)))
 
 
@@ -140,11 +151,19 @@ def evaluate(pooled, labels, theta, idx) -> Dict[str, float]:
             "val_skip@0.05": float(1 - keep.mean())}
 
 
-def threshold_for_recall(scores: np.ndarray, positive: np.ndarray, target: float) -> float:
-    """Largest threshold t such that the fraction of positives with score > t is
-    at least ``target`` (scores of skipped positives are the lowest ones)."""
-    sp = np.sort(scores[positive])
+def threshold_for_recall(scores: np.ndarray, positive: np.ndarray, target: float, weights=None) -> float:
+    """Largest threshold t such that the positives with score > t carry at
+    least ``target`` of the positives' total weight (unit weights: the
+    fraction of positive tiles; detection counts: the fraction of detections).
+    The positives given up are the lowest-scored ones."""
+    sp = scores[positive]
     if sp.size == 0:
         return float(np.max(scores)) + 1.0
-    k = int(math.floor((1.0 - target) * sp.size))        # positives we may lose
-    return float(np.nextafter(sp[k], -np.inf)) if k < sp.size else float(sp[-1])
+    wp = np.ones_like(sp) if weights is None else np.asarray(weights, np.float64)[positive]
+    order = np.argsort(sp, kind="stable")
+    sp, wp = sp[order], wp[order]
+    lose = np.cumsum(wp) <= (1.0 - target) * wp.sum() + 1e-12   # prefix we may give up
+    k = int(np.count_nonzero(lose))                          # positives with score < t
+    if k >= sp.size:
+        return float(sp[-1])
+    return float(np.nextafter(sp[k], -np.inf))

@@ -3,11 +3,11 @@ what it gains over running the network without it.
 
 Training tiles come from sparse frames seeded apart from the evaluation frames
 and are labelled by the ungated BF16 network's own detections.  The gate's
-threshold is chosen on held-out training tiles to keep 99.5 % of the positive
-tiles; on the evaluation frames the gate must then skip a substantial share of
-the tiles while keeping nearly every ungated detection.  The fixed 0.05
-threshold, the untrained initial gate and a non-learned brightness rule are
-reported beside it.
+threshold is chosen on held-out training tiles to keep 99.9 % of their
+detections (a margin over the 99.5 % recall target: the held-out set is small); on the evaluation frames the gate must then skip a substantial
+share of the tiles while keeping nearly every ungated detection.  The
+threshold for 99.5 % of the positive tiles, the fixed 0.05, the untrained
+initial gate and a non-learned brightness rule are reported beside it.
 """
 import numpy as np
 import pytest
@@ -42,7 +42,7 @@ def test_trained_gate_skips_empty_tiles_and_keeps_detections():
     blob = S.serialize_weights(spec, w)
     net = dl.Net(blob, precision="bf16")
     batches = (S.render_frames(16, SIDE, SIDE, "sparse", 2005, frame_ids=range(k, k + 16)) for k in range(0, 160, 16))
-    pooled, labels = GT.labelled_tiles(net, batches, DEV)
+    pooled, labels, counts = GT.labelled_tiles(net, batches, DEV, with_counts=True)
     assert pooled.shape[0] == 160 * 16
     frac_pos = float(labels.mean())
     theta0 = S.gate_flat(S.gate_init(3005))
@@ -59,10 +59,12 @@ def test_trained_gate_skips_empty_tiles_and_keeps_detections():
     level = float(np.median(np.maximum(pooled.cpu().numpy(), 0).mean(axis=(1, 2))))
     from tests.test_gpu_gated import brightness_gate
     bright = brightness_gate(level).astype(np.float32)
-    thr = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.995)
-    print("threshold at 99.5% held-out tile recall:", thr)
-    for name, th, p in [("trained", res.theta, thr), ("trained@0.05", res.theta, 0.05),
-                        ("untrained@0.05", theta0, 0.05), ("brightness", bright, 0.05)]:
+    thr = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.999, counts)
+    thr_tile = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.995)
+    print("thresholds at 99.9% held-out detection / 99.5% tile recall:", thr, thr_tile)
+    for name, th, p in [("trained", res.theta, thr), ("trained@tile-recall", res.theta, thr_tile),
+                        ("trained@0.05", res.theta, 0.05), ("untrained@0.05", theta0, 0.05),
+                        ("brightness", bright, 0.05)]:
         rec, keep = gated_eval(blob, th, ev, p)
         got = {(a, b, c) for a, b, c in zip(rec["frame"], rec["row"], rec["col"])}
         out[name] = {"threshold": p, "skip": float(1 - keep.mean()),
