@@ -59,7 +59,9 @@ def main():
                     help="further forms measured on the same frames and reported under 'forms' ('' = none)")
     ap.add_argument("--frames", type=int, default=16)
     ap.add_argument("--size", type=int, default=2048)
-    ap.add_argument("--cpu-sample", type=int, default=640, help="side of the oracle's sample crop (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=1536,
+                    help="side of the oracle's sample: the top-left crop of frame 0 (the frame size = the whole "
+                         "frame; 0 = skip)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--workload", default="full", choices=["full", "tiny", "rois", "sparse", "pipeline"],
                     help="full: the headline (16 x 2048^2, net B); tiny: 4 x 128^2 net A; rois: 256 uneven "
@@ -268,43 +270,46 @@ def measured_traffic(key):
 
 
 def cpu_baseline(args, spec, w, frames, net, dev, recs):
-    """FP64 oracle on a bounded sample: the top-left crop of frame 0.  Also checks
-    the GPU maps/detections on the part of the crop the oracle computes exactly
-    (at least R pixels from the crop's inner edges)."""
+    """FP64 oracle on a bounded sample: the top-left s x s crop of frame 0
+    (1536^2 by default, about 20 s on 16 host threads).  Also checks the GPU maps and detections where the
+    oracle's result is exact: all of a whole frame; in a smaller crop, the part
+    at least R pixels from the crop's inner edges (and one more pixel for the
+    detections, whose neighbours must be exact too)."""
     import torch
     import oracle
-    from tests.parity import compare_emitters, map_rel_err
+    from tests.parity import exempt_mask, map_rel_err
     s = min(args.cpu_sample, args.size)
     crop = np.ascontiguousarray(frames[0, :s, :s])
     t0 = time.perf_counter()
     rec, ref_maps = oracle.localize(crop[None], spec, w, return_maps=True)
     dt = time.perf_counter() - t0
+    whole = s == args.size
     R = 1 + 2 * sum(spec.dilations)
-    e = s - R
+    e = s if whole else s - R                 # exact maps on [0, e)^2
+    lim = e if whole else e - 1               # exact detections on [0, lim)^2
     maps = torch.empty((1, 5, args.size, args.size), dtype=torch.float32, device=dev)
     net.maps_device(torch.from_numpy(np.ascontiguousarray(frames[:1])).to(dev), maps)
     torch.cuda.synchronize()
     g = maps[0, :, :e, :e].cpu().numpy()
     err = map_rel_err(g, ref_maps[0, :, :e, :e])
-    # detections on [0, e-1) x [0, e-1) (their neighbours lie in the exact region):
     # the GPU's own emitter records against the oracle's detections there
-    from tests.parity import exempt_mask
-    ref_det = oracle.detect(ref_maps[0, 0, :e, :e])[:-1, :-1]
-    sel = (recs["frame"] == 0) & (recs["row"] < e - 1) & (recs["col"] < e - 1)
+    ref_det = oracle.detect(ref_maps[0, 0, :e, :e])[:lim, :lim]
+    sel = (recs["frame"] == 0) & (recs["row"] < lim) & (recs["col"] < lim)
     got_det = np.zeros_like(ref_det)
     got_det[recs["row"][sel], recs["col"][sel]] = True
-    ex = exempt_mask(ref_maps[0, 0, :e, :e])[:-1, :-1]
+    ex = exempt_mask(ref_maps[0, 0, :e, :e])[:lim, :lim]
     mism = int(np.sum((ref_det != got_det) & ~ex))
     matched = int(np.sum(ref_det & got_det))
-    rsel = (rec["row"] < e - 1) & (rec["col"] < e - 1)
-    ref = {"records": rec[rsel], "limit": e - 1}
+    rsel = (rec["row"] < lim) & (rec["col"] < lim)
+    ref = {"records": rec[rsel], "limit": lim}
+    what = "frame 0" if whole else f"frame 0 crop {s}x{s}"
     return {"value": round(s * s / dt / 1e6, 4), "unit": "Mpixel/s", "cores": cpu_threads(), "kind": "oracle",
-            "sample": f"frame 0 crop {s}x{s} of the same workload, FP64 oracle (net + detection + records), "
-                      f"{dt:.1f} s",
+            "sample": f"{what} of the same workload, FP64 oracle (net + detection + records), {dt:.1f} s",
             "sample_check": {"max_map_rel_err": float(err.max()), "oracle_detections": int(ref_det.sum()),
                              "gpu_detections": int(got_det.sum()), "matched": matched,
                              "recall_vs_oracle": matched / max(1, int(ref_det.sum())),
-                             "non_exempt_detection_mismatch": mism, "region": f"{e - 1}x{e - 1}"}}, ref
+                             "non_exempt_detection_mismatch": mism, "exempt_pixels": int(ex.sum()),
+                             "region": f"{lim}x{lim}"}}, ref
 
 
 if __name__ == "__main__":
