@@ -67,6 +67,9 @@ def main():
                     help="full: the headline (16 x 2048^2, net B); tiny: 4 x 128^2 net A; rois: 256 uneven "
                          "ROIs, net A; sparse: gated BF16 net B on 64 x 2048^2 sparse frames; pipeline: "
                          "host frames with H2D overlapped on a side stream")
+    ap.add_argument("--sparse-layout", default="iid", choices=["iid", "cell"],
+                    help="sparse workload: empty 256^2 tiles chosen independently (iid) or around one "
+                         "compact occupied region (cell)")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes rendering the frames (0 = automatic; 1 under profilers)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

@@ -114,10 +114,11 @@ def sparse(args, S):
     BF16 net B on 64 x 2048^2 frames and report skip, speedup and recall."""
     args.precision = "bf16"                          # the gated form runs the BF16 net
     n_eval, side = args.frames if args.frames != 16 else 64, args.size
+    model = "sparse" if args.sparse_layout == "iid" else "sparse_cell"
     t0 = time.time()
-    ev = S.render_frames(n_eval, side, side, "sparse", 1005, workers=args.gen_workers or None)
+    ev = S.render_frames(n_eval, side, side, model, 1005, workers=args.gen_workers or None)
     n_train = 313                                    # 313 frames x 64 tiles >= 20,000 tiles
-    train_frames = [S.render_frames(16, side, side, "sparse", 2005, frame_ids=range(k, min(k + 16, n_train)),
+    train_frames = [S.render_frames(16, side, side, model, 2005, frame_ids=range(k, min(k + 16, n_train)),
                                     workers=args.gen_workers or None) for k in range(0, n_train, 16)]
     log(f"generated frames in {time.time() - t0:.1f}s")
     import torch
@@ -176,7 +177,9 @@ def sparse(args, S):
     kT = {(a, b, c) for a, b, c in zip(recT["frame"], recT["row"], recT["col"])}
     px = n_eval * side * side
     _line(args, px / (ms1 * 1e-3) / 1e6, ms1,
-          {"workload": f"{n_eval} x {side}x{side} sparse frames (30-70% empty 256^2 tiles), gated BF16 net B",
+          {"workload": f"{n_eval} x {side}x{side} sparse frames (30-70% empty 256^2 tiles, "
+                       f"{'independent' if args.sparse_layout == 'iid' else 'around one compact occupied region'})"
+                       f", gated BF16 net B",
            "net": "B", "precision": "bf16",
            "gate": f"2 conv x 8 ch + mean pool, threshold {thr:.4f} (99.9% of held-out detections kept)",
            "frames": n_eval},

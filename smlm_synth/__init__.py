@@ -70,6 +70,10 @@ class FrameModel:
     astig_depth_nm: float = 400.0
     empty_tile: int = 0                      # >0: tile side for structured occupancy
     empty_frac: Tuple[float, float] = (0.0, 0.0)     # per-frame fraction of empty tiles
+    # where the empty tiles lie: "iid" = each tile empty independently; "cell" =
+    # the occupied tiles form one compact elliptical region (a cell in the field
+    # of view) and the empty ones surround it
+    empty_layout: str = "iid"
 
     def sigmas(self, z: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
         if self.psf == "gauss2d":
@@ -94,6 +98,8 @@ CONFIG_MODELS: Dict[str, FrameModel] = {
     "rois": FrameModel(density=(0.1, 5.0)),
     # sparse frames for the tile gate: 30-70 % of 256^2 tiles empty, density U(0.05,0.5) in the rest
     "sparse": FrameModel(density=(0.05, 0.5), empty_tile=256, empty_frac=(0.3, 0.7)),
+    # the same with the empty tiles around one compact occupied region
+    "sparse_cell": FrameModel(density=(0.05, 0.5), empty_tile=256, empty_frac=(0.3, 0.7), empty_layout="cell"),
 }
 
 ROI_SIDES = (128, 256, 384, 512, 768, 1024)
@@ -103,6 +109,32 @@ def _phi(t: np.ndarray) -> np.ndarray:
     """Standard normal CDF (used only to integrate the simulated PSF over a pixel)."""
     from scipy.special import ndtr
     return ndtr(t)
+
+
+def _occupancy(nty: int, ntx: int, q: float, layout: str, rng: np.random.Generator) -> np.ndarray:
+    """Occupied-tile map with an empty fraction of about ``q``.
+
+    "iid": every tile is empty with probability q.  "cell": the round((1 - q) N)
+    tiles whose centres are nearest (in an ellipse's metric) to a random centre
+    are occupied: axis ratio U(0.5, 1), orientation U(0, pi), centre uniform
+    over the middle half of the grid in each direction."""
+    if layout == "iid":
+        return rng.random((nty, ntx)) >= q
+    if layout != "cell":
+        raise ValueError(f"unknown empty-tile layout {layout!r}")
+    cy = rng.uniform(0.25, 0.75) * nty
+    cx = rng.uniform(0.25, 0.75) * ntx
+    ratio = rng.uniform(0.5, 1.0)
+    th = rng.uniform(0.0, math.pi)
+    yy, xx = np.mgrid[0:nty, 0:ntx]
+    dy, dx = yy + 0.5 - cy, xx + 0.5 - cx
+    u = dx * math.cos(th) + dy * math.sin(th)
+    v = -dx * math.sin(th) + dy * math.cos(th)
+    dist = (u * ratio) ** 2 + v ** 2           # the long axis runs along u
+    k = int(round((1.0 - q) * nty * ntx))
+    occ = np.zeros(nty * ntx, bool)
+    occ[np.argsort(dist.ravel(), kind="stable")[:k]] = True
+    return occ.reshape(nty, ntx)
 
 
 def _render_one(h: int, w: int, model: FrameModel, rng: np.random.Generator):
@@ -115,7 +147,7 @@ def _render_one(h: int, w: int, model: FrameModel, rng: np.random.Generator):
         t = model.empty_tile
         nty, ntx = -(-h // t), -(-w // t)
         q = rng.uniform(*model.empty_frac)
-        occupied = rng.random((nty, ntx)) >= q
+        occupied = _occupancy(nty, ntx, q, model.empty_layout, rng)
         occ_idx = np.flatnonzero(occupied.ravel())
         # occupied area (clipped tiles at the ragged edge count their real size)
         ty, tx = np.divmod(occ_idx, ntx)
