@@ -435,7 +435,43 @@ k_conv(ConvArgs a, Geometry geo)
         // LDS address of lattice point (row wave + u, column 16 p + j + v) for tap (u, v), u, v in 0..2
         auto pt_addr = [&](int p, int tap) { return sT + ((wave + tap / 3) * PW + 16 * p + j + tap % 3) * PS; };
 
-        if constexpr (P == DL_FP32) {
+        // FP32 with weights and tile in LDS and the register budget of two
+        // waves per SIMD: the operands of K step it + 1 are read while the
+        // MFMAs of step it run (the reads past the last step fetch step 0
+        // again and are not used), so the MFMAs wait only for reads issued one
+        // step earlier
+        constexpr bool PREF = P == DL_FP32 && !GW && min_waves<P, TR_>() == 2;
+        if constexpr (PREF) {
+            constexpr int G = C / 16, NIT = KPlan<C, P>::NIT;
+            const v4f *sW = reinterpret_cast<const v4f *>(sT + L::WOFF);
+            auto operands = [&](int it, v4f (&aw)[NB], v4f (&bv)[PB]) {
+                const int tap = it / G, gg = it - (it / G) * G;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) aw[nb] = sW[(it * NB + nb) * 64 + lane];
+#pragma unroll
+                for (int p = 0; p < PB; ++p)
+                    bv[p] = *reinterpret_cast<const v4f *>(pt_addr(p, tap) + (gg * 16 + kq * 4) * 4);
+            };
+            v4f aw[NB], bv[PB];
+            operands(0, aw, bv);
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                v4f an[NB], bn[PB];
+                operands(it + 1 < NIT ? it + 1 : 0, an, bn);
+                __builtin_amdgcn_sched_barrier(0);   // issued before this step's MFMAs
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int p = 0; p < PB; ++p)
+                            acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[nb][s], bv[p][s], acc[nb][p], 0, 0, 0);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) aw[nb] = an[nb];
+#pragma unroll
+                for (int p = 0; p < PB; ++p) bv[p] = bn[p];
+            }
+        } else if constexpr (P == DL_FP32) {
             constexpr int G = C / 16, NIT = KPlan<C, P>::NIT;
             const v4f *gw = static_cast<const v4f *>(a.wpk);
             const v4f *sW = reinterpret_cast<const v4f *>(sT + L::WOFF);
@@ -445,7 +481,7 @@ k_conv(ConvArgs a, Geometry geo)
                 for (int gg = 0; gg < G; ++gg) {
                     const int it = tap * G + gg;
                     v4f aw[NB];
-                    if constexpr (GW) {
+                    if constexpr (GW) {             // weights from L2, one K step ahead
 #pragma unroll
                         for (int nb = 0; nb < NB; ++nb) aw[nb] = awn[nb];
                         const int itn = it + 1 < NIT ? it + 1 : 0;
