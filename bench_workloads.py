@@ -138,6 +138,16 @@ def sparse(args, S):
     # 99.5 %-of-positive-tiles threshold and the fixed 0.05 are reported beside it
     thr = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.999, counts)
     thr_tile = GT.threshold_at_recall(pooled, labels, res.theta, res.val_idx, 0.995)
+    # non-learned control at the same target: keep a tile when its brightest
+    # pooled pixel exceeds a level chosen on the same held-out tiles
+    vi = np.asarray(res.val_idx)
+    peak = torch.clamp(pooled, min=0).amax(dim=(1, 2)).cpu().numpy()
+    level = GT.threshold_for_recall(peak[vi], labels.cpu().numpy()[vi] > 0.5, 0.999, counts[vi])
+    bright = np.zeros(S.gate_flat(S.gate_init(0)).size, np.float32)
+    bright[4] = 1.0                                  # h1[0] = ReLU(p)
+    bright[80 + 4] = 1.0                             # h2[0] = h1[0]
+    bright[664] = 50.0                               # g = 50 (max h2[0] - level) + logit(0.05)
+    bright[672] = -50.0 * level + math.log(0.05 / 0.95)
     log(f"gate trained in {time.time() - t0:.1f}s: {res.history[-1]}; threshold {thr:.4f}")
     d = torch.from_numpy(ev).to(dev)
     cap = n_eval * side * side // 64
@@ -171,17 +181,19 @@ def sparse(args, S):
     ms1, rec1, keep = run(res.theta, thr)
     ms5, rec5, keep5 = run(res.theta, 0.05)
     msT, recT, keepT = run(res.theta, thr_tile)
+    msB, recB, keepB = run(bright, 0.05)
     k0 = {(a, b, c) for a, b, c in zip(rec0["frame"], rec0["row"], rec0["col"])}
     k1 = {(a, b, c) for a, b, c in zip(rec1["frame"], rec1["row"], rec1["col"])}
     k5 = {(a, b, c) for a, b, c in zip(rec5["frame"], rec5["row"], rec5["col"])}
     kT = {(a, b, c) for a, b, c in zip(recT["frame"], recT["row"], recT["col"])}
+    kB = {(a, b, c) for a, b, c in zip(recB["frame"], recB["row"], recB["col"])}
     px = n_eval * side * side
     _line(args, px / (ms1 * 1e-3) / 1e6, ms1,
           {"workload": f"{n_eval} x {side}x{side} sparse frames (30-70% empty 256^2 tiles, "
                        f"{'independent' if args.sparse_layout == 'iid' else 'around one compact occupied region'})"
                        f", gated BF16 net B",
            "net": "B", "precision": "bf16",
-           "gate": f"2 conv x 8 ch + mean pool, threshold {thr:.4f} (99.9% of held-out detections kept)",
+           "gate": f"2 conv x 8 ch + global max pool, threshold {thr:.4f} (99.9% of held-out detections kept)",
            "frames": n_eval},
           {"ungated_ms_per_step": round(ms0, 3), "ungated_mpx_s": round(px / (ms0 * 1e-3) / 1e6, 2),
            "speedup_vs_ungated": round(ms0 / ms1, 3), "skipped_tile_fraction": round(float(1 - keep.mean()), 4),
@@ -190,6 +202,11 @@ def sparse(args, S):
                                         "skipped_tile_fraction": round(float(1 - keepT.mean()), 4),
                                         "speedup_vs_ungated": round(ms0 / msT, 3),
                                         "recall_vs_ungated": round(len(k0 & kT) / max(1, len(k0)), 5)},
+           "brightness_control": {"rule": f"brightest pooled pixel > {level:.4f} (level for 99.9% of held-out "
+                                          "detections)",
+                                  "skipped_tile_fraction": round(float(1 - keepB.mean()), 4),
+                                  "speedup_vs_ungated": round(ms0 / msB, 3),
+                                  "recall_vs_ungated": round(len(k0 & kB) / max(1, len(k0)), 5)},
            "at_threshold_0.05": {"skipped_tile_fraction": round(float(1 - keep5.mean()), 4),
                                  "speedup_vs_ungated": round(ms0 / ms5, 3),
                                  "recall_vs_ungated": round(len(k0 & k5) / max(1, len(k0)), 5)},

@@ -213,7 +213,8 @@ void dl_host_free(void *p);
  * A small learned classifier decides per 256 x 256 tile whether the network
  * needs to run there.  Per tile of preprocessed input x (DL_GATE_TILE pixels
  * square): p = 4x4 mean pooling (64 x 64); h1 = ReLU(conv3x3(p; 1 -> 8, pad 1));
- * h2 = ReLU(conv3x3(h1; 8 -> 8, pad 1)); m = mean of h2 over pixels;
+ * h2 = ReLU(conv3x3(h1; 8 -> 8, pad 1)); m = max of h2 over pixels (its
+ * gradient goes to the first maximising pixel in raster order);
  * g = fw . m + fb (logit).  theta[DL_GATE_NPARAM] holds W1[8][1][3][3], b1[8],
  * W2[8][8][3][3], b2[8], fw[8], fb in that order (FP32).  Training uses binary
  * cross-entropy on g (paper Sec. 3.3) and Adam.  All pointers are device

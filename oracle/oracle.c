@@ -277,7 +277,10 @@ void or_detect(const double *logit, int h, int w, double tau, uint8_t *det)
 /* Gate network on one pooled 64x64 tile p (mean of 4x4 input blocks):
  *   z1 = conv(p; g1.w, g1.b)  (1 -> 8, 3x3, pad 1), h1 = ReLU(z1)
  *   z2 = conv(h1; g2.w, g2.b) (8 -> 8),            h2 = ReLU(z2)
- *   m  = mean over pixels of h2,  g = fc.w . m + fc.b
+ *   m  = max over pixels of h2,   g = fc.w . m + fc.b
+ * The global pool is a max: a tile holds a detection as soon as one place in
+ * it looks like an emitter, which a mean over 4096 pixels dilutes away.  Its
+ * gradient goes to the first pixel in raster order that attains the max.
  * Gate parameters (673) in order: g1.w[8][1][3][3] g1.b[8] g2.w[8][8][3][3]
  * g2.b[8] fc.w[8] fc.b[1]. */
 #define GC 8
@@ -295,7 +298,7 @@ void or_gate_pool(const double *x, int th, int tw, int pool, double *p)
 
 static void gate_forward_one(const double *p, int ph, int pw, const double *th,
                              double *z1, double *h1, double *z2, double *h2,
-                             double *m, double *g)
+                             double *m, long *am, double *g)
 {
     const double *w1 = th, *b1 = th + 72, *w2 = th + 80, *b2 = th + 656, *fw = th + 664, *fb = th + 672;
     long hw = (long)ph * pw;
@@ -305,9 +308,11 @@ static void gate_forward_one(const double *p, int ph, int pw, const double *th,
     for (long k = 0; k < GC * hw; ++k) h2[k] = z2[k] > 0 ? z2[k] : 0.0;
     double gg = fb[0];
     for (int c = 0; c < GC; ++c) {
-        double s = 0.0;
-        for (long k = 0; k < hw; ++k) s += h2[(long)c * hw + k];
-        m[c] = s / (double)hw;
+        long a = 0;
+        for (long k = 1; k < hw; ++k)
+            if (h2[(long)c * hw + k] > h2[(long)c * hw + a]) a = k;
+        am[c] = a;
+        m[c] = h2[(long)c * hw + a];
         gg += fw[c] * m[c];
     }
     *g = gg;
@@ -322,9 +327,10 @@ void or_gate_forward(const double *pooled, int n, int ph, int pw, const double *
         double *z1 = malloc(sizeof(double) * GC * hw), *h1 = malloc(sizeof(double) * GC * hw);
         double *z2 = malloc(sizeof(double) * GC * hw), *h2 = malloc(sizeof(double) * GC * hw);
         double m[GC];
+        long am[GC];
 #pragma omp for schedule(static)
         for (int b = 0; b < n; ++b)
-            gate_forward_one(pooled + (long)b * hw, ph, pw, theta, z1, h1, z2, h2, m, &g[b]);
+            gate_forward_one(pooled + (long)b * hw, ph, pw, theta, z1, h1, z2, h2, m, am, &g[b]);
         free(z1); free(h1); free(z2); free(h2);
     }
 }
@@ -356,17 +362,18 @@ void or_gate_backward(const double *pooled, int n, int ph, int pw, const double 
     double *z2 = malloc(sizeof(double) * GC * hw), *h2 = malloc(sizeof(double) * GC * hw);
     double *dz2 = malloc(sizeof(double) * GC * hw), *dz1 = malloc(sizeof(double) * GC * hw);
     double m[GC], g;
+    long am[GC];
     for (int b = 0; b < n; ++b) {
         const double *p = pooled + (long)b * hw;
-        gate_forward_one(p, ph, pw, theta, z1, h1, z2, h2, m, &g);
+        gate_forward_one(p, ph, pw, theta, z1, h1, z2, h2, m, am, &g);
         double d = dg[b];
         /* linear layer */
         for (int c = 0; c < GC; ++c) grad[664 + c] += d * m[c];
         grad[672] += d;
-        /* mean pool + ReLU */
+        /* max pool (to its first maximising pixel) + ReLU */
         for (int c = 0; c < GC; ++c)
             for (long k = 0; k < hw; ++k)
-                dz2[(long)c * hw + k] = z2[(long)c * hw + k] > 0 ? d * fw[c] / (double)hw : 0.0;
+                dz2[(long)c * hw + k] = k == am[c] && z2[(long)c * hw + k] > 0 ? d * fw[c] : 0.0;
         /* conv2: dW2, db2, dh1 */
         for (int o = 0; o < GC; ++o) {
             for (long k = 0; k < hw; ++k) grad[656 + o] += dz2[(long)o * hw + k];

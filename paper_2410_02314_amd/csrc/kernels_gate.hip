@@ -4,18 +4,20 @@
 //   p  = mean of 4x4 blocks of x                  (64 x 64)
 //   z1 = conv3x3(p; W1, b1), pad 1, 1 -> 8;   h1 = ReLU(z1)
 //   z2 = conv3x3(h1; W2, b2), pad 1, 8 -> 8;  h2 = ReLU(z2)
-//   m  = mean over pixels of h2 (8);          g  = fw . m + fb   (logit)
-// Training loss is binary cross-entropy on g (paper Sec. 3.3), so
-// dL/dg = (sigmoid(g) - y) / batch.  Parameters theta[673] in the order
-// W1[8][1][3][3], b1[8], W2[8][8][3][3], b2[8], fw[8], fb[1].
+//   m  = max over pixels of h2 (8);           g  = fw . m + fb   (logit)
+// The global pool is a max (a single emitter-like spot decides that a tile is
+// occupied); its gradient goes to the first pixel in raster order that
+// attains the max.  Training loss is binary cross-entropy on g (paper
+// Sec. 3.3), so dL/dg = (sigmoid(g) - y) / batch.  Parameters theta[673] in
+// the order W1[8][1][3][3], b1[8], W2[8][8][3][3], b2[8], fw[8], fb[1].
 //
-// One workgroup per tile keeps p (padded 66 x 66), h1 (8 x 64 x 64) and the
-// sign mask of z2 (8 x 4096 bits) in LDS (~156 KB).  Backward re-uses that:
-// dz2[o][p] = dg * fw[o] / 4096 * [z2 > 0] is a scalar times a bit mask, so
-// dW2 = dg fw[o] / 4096 * sum_p mask2[o][p] h1[c][p + tap], and dz1 is written
-// over h1 in place.  Every reduction has a fixed order (shuffle butterflies,
-// fixed per-thread loops, per-tile partial gradients summed tile by tile), so
-// gradients are bitwise reproducible.
+// One workgroup per tile keeps p (padded 66 x 66) and h1 (8 x 64 x 64) in LDS
+// (~150 KB).  Backward: dz2[o] is k[o] = dg fw[o] [m[o] > 0] at the argmax
+// a[o] and zero elsewhere, so dW2[o][c][tap] = k[o] h1[c][a[o] + tap], and dz1
+// (written over h1 in place) is nonzero only around the eight argmaxes.  Every
+// reduction has a fixed order (shuffle butterflies, fixed per-thread loops,
+// per-tile partial gradients summed tile by tile), so gradients are bitwise
+// reproducible.
 #include "dloc_internal.h"
 
 namespace dloc {
@@ -69,11 +71,21 @@ k_gate_pool(const uint16_t *__restrict__ frames, int n, int h, int w, float offs
 struct GateSmem {
     float P[GPP * GPP];           // padded pooled tile
     float H1[GC * NPIX];          // h1, later dz1
-    uint64_t M2[GC * (NPIX / 64)];   // sign mask of z2
     float th[NPARAM + 3];
-    float red[GC * 4];
+    float red[GC * 4];            // per-wave maxima
+    int redi[GC * 4];             // and where they are
     float m[GC];
+    int am[GC];                   // argmax of each channel (first in raster order)
 };
+
+// (value, index) pairs: the larger value wins, a tie goes to the smaller index
+__device__ __forceinline__ void max_first(float &v, int &i, float v2, int i2)
+{
+    if (v2 > v || (v2 == v && i2 < i)) {
+        v = v2;
+        i = i2;
+    }
+}
 
 // Forward (and backward when BWD): logits[tile]; gpart[tile][673] holds the
 // tile's gradient of dlogit[tile] * g with respect to theta.
@@ -114,10 +126,14 @@ k_gate(const float *__restrict__ pooled, int ntiles, const float *__restrict__ t
     }
     __syncthreads();
 
-    // conv2 + ReLU, channel sums of h2, sign mask of z2
-    float msum[GC];
+    // conv2 + ReLU, channel maxima of h2 and their first positions
+    float mv[GC];
+    int mi[GC];
 #pragma unroll
-    for (int o = 0; o < GC; ++o) msum[o] = 0.f;
+    for (int o = 0; o < GC; ++o) {
+        mv[o] = -1.f;                 // below every ReLU output: the first pixel always enters
+        mi[o] = 0;
+    }
     for (int k = 0; k < NPIX / 256; ++k) {
         const int q = tid + 256 * k;
         const int i = q / GP, j = q - (q / GP) * GP;
@@ -141,18 +157,32 @@ k_gate(const float *__restrict__ pooled, int ntiles, const float *__restrict__ t
         }
 #pragma unroll
         for (int o = 0; o < GC; ++o) {
-            msum[o] += fmaxf(z[o], 0.f);
-            const uint64_t bits = __ballot(z[o] > 0.f);
-            if (BWD && lane == 0) S.M2[o * (NPIX / 64) + wave + 4 * k] = bits;
+            const float h = fmaxf(z[o], 0.f);
+            if (h > mv[o]) {          // q grows with k: the first maximum is kept
+                mv[o] = h;
+                mi[o] = q;
+            }
         }
     }
 #pragma unroll
     for (int o = 0; o < GC; ++o) {
-        const float s = wave_sum(msum[o]);
-        if (lane == 0) S.red[o * 4 + wave] = s;
+        float v = mv[o];
+        int ix = mi[o];
+#pragma unroll
+        for (int sh = 1; sh < 64; sh <<= 1) max_first(v, ix, __shfl_xor(v, sh), __shfl_xor(ix, sh));
+        if (lane == 0) {
+            S.red[o * 4 + wave] = v;
+            S.redi[o * 4 + wave] = ix;
+        }
     }
     __syncthreads();
-    if (tid < GC) S.m[tid] = (((S.red[tid * 4] + S.red[tid * 4 + 1]) + S.red[tid * 4 + 2]) + S.red[tid * 4 + 3]) * (1.f / NPIX);
+    if (tid < GC) {
+        float v = S.red[tid * 4];
+        int ix = S.redi[tid * 4];
+        for (int w = 1; w < 4; ++w) max_first(v, ix, S.red[tid * 4 + w], S.redi[tid * 4 + w]);
+        S.m[tid] = v;
+        S.am[tid] = ix;
+    }
     __syncthreads();
     if (tid == 0) {
         float g = FB;
@@ -162,69 +192,36 @@ k_gate(const float *__restrict__ pooled, int ntiles, const float *__restrict__ t
     if (!BWD) return;
 
     // ----------------------------------------------------------- backward
+    // k[o] = dg fw[o] where z2 > 0 at the argmax (m[o] > 0), else 0
     const float dg = dlogits[tile];
     float *gp = gpart + (int64_t)tile * NPARAM;
-    if (tid < GC) gp[664 + tid] = dg * S.m[tid];
-    if (tid == 0) gp[672] = dg;
     if (tid < GC) {
-        int cnt = 0;
-        for (int wd = 0; wd < NPIX / 64; ++wd) cnt += __popcll(S.M2[tid * (NPIX / 64) + wd]);
-        gp[656 + tid] = dg * FW[tid] * (1.f / NPIX) * (float)cnt;
+        gp[664 + tid] = dg * S.m[tid];
+        gp[656 + tid] = S.m[tid] > 0.f ? dg * FW[tid] : 0.f;
     }
-    // dW2[o][c][tap] = k[o] * sum_p mask2[o][p] h1[c][p + tap]
-    {
-        const int pair = tid >> 2, quarter = tid & 3;
-        const int o = pair >> 3, c = pair & 7;
-        float s[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) s[t] = 0.f;
-        for (int q = quarter * (NPIX / 4); q < (quarter + 1) * (NPIX / 4); ++q) {
-            if (!((S.M2[o * (NPIX / 64) + (q >> 6)] >> (q & 63)) & 1ull)) continue;
-            const int i = q / GP, j = q - (q / GP) * GP;
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                const int ii = i + u - 1;
-                if (ii < 0 || ii >= GP) continue;
-#pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    const int jj = j + v - 1;
-                    if (jj < 0 || jj >= GP) continue;
-                    s[u * 3 + v] += S.H1[c * NPIX + ii * GP + jj];
-                }
-            }
-        }
-        const float ko = dg * FW[o] * (1.f / NPIX);
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            float v = s[t];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            if (quarter == 0) gp[80 + (o * GC + c) * 9 + t] = ko * v;
-        }
+    if (tid == 0) gp[672] = dg;
+    // dW2[o][c][tap] = k[o] h1[c][a[o] + tap] (zero outside the tile)
+    for (int e = tid; e < GC * GC * 9; e += 256) {
+        const int o = e / (GC * 9), c = (e / 9) % GC, t = e % 9;
+        const int ai = S.am[o] / GP, aj = S.am[o] % GP;
+        const int ii = ai + t / 3 - 1, jj = aj + t % 3 - 1;
+        const float ko = S.m[o] > 0.f ? dg * FW[o] : 0.f;
+        const float hv = ii >= 0 && ii < GP && jj >= 0 && jj < GP ? S.H1[c * NPIX + ii * GP + jj] : 0.f;
+        gp[80 + e] = ko * hv;
     }
     __syncthreads();
-    // dz1[c][q] = [h1 > 0] * sum_o k[o] sum_tap W2[o][c][tap] mask2[o][q - tap], in place over h1
+    // dz1[c][q] = [h1 > 0] sum_o k[o] W2[o][c][q - a[o] + 1], in place over h1
     for (int q = tid; q < NPIX; q += 256) {
         const int i = q / GP, j = q - (q / GP) * GP;
         float dh[GC];
 #pragma unroll
         for (int c = 0; c < GC; ++c) dh[c] = 0.f;
         for (int o = 0; o < GC; ++o) {
-            const float ko = dg * FW[o] * (1.f / NPIX);
+            const int u = i - S.am[o] / GP + 1, v = j - S.am[o] % GP + 1;
+            if (u < 0 || u > 2 || v < 0 || v > 2 || !(S.m[o] > 0.f)) continue;
+            const float ko = dg * FW[o];
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                const int pi = i - (u - 1);
-                if (pi < 0 || pi >= GP) continue;
-#pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    const int pj = j - (v - 1);
-                    if (pj < 0 || pj >= GP) continue;
-                    const int pq = pi * GP + pj;
-                    if (!((S.M2[o * (NPIX / 64) + (pq >> 6)] >> (pq & 63)) & 1ull)) continue;
-#pragma unroll
-                    for (int c = 0; c < GC; ++c) dh[c] += ko * W2[(o * GC + c) * 9 + u * 3 + v];
-                }
-            }
+            for (int c = 0; c < GC; ++c) dh[c] += ko * W2[(o * GC + c) * 9 + u * 3 + v];
         }
 #pragma unroll
         for (int c = 0; c < GC; ++c) {

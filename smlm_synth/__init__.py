@@ -402,7 +402,7 @@ def flat_weights(spec: NetSpec, weights: Dict[str, np.ndarray]) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------------------
-# tile-gate network (2 conv layers of 8 channels + global mean + linear 8 -> 1)
+# tile-gate network (2 conv layers of 8 channels + global max + linear 8 -> 1)
 # --------------------------------------------------------------------------------------
 GATE_POOL = 4
 GATE_CH = 8

@@ -29,14 +29,16 @@ def theta_for(seed):
 
 def pooled_inputs(n, seed):
     """Seeded pooled tiles with the statistics of preprocessed frames
-    (background about 1, bright blobs)."""
+    (background about 1, bright blobs).  The values are FP32-representable,
+    so the oracle and the kernels see the same input and pick the same
+    maximising pixel of each channel (the global pool is a max)."""
     r = np.random.default_rng(seed)
     p = 1.0 + 0.1 * r.standard_normal((n, 64, 64))
     for b in range(n):
         for _ in range(r.integers(0, 6)):
             i, j = r.integers(0, 64, 2)
             p[b, max(0, i - 1):i + 2, max(0, j - 1):j + 2] += r.uniform(2, 10)
-    return p
+    return p.astype(np.float32).astype(np.float64)
 
 
 def t32(a):

@@ -28,8 +28,9 @@ DEV = torch.device("cuda:0")
 
 
 def brightness_gate(level, scale=50.0, thr=0.05):
-    """g = scale * (mean of ReLU(pooled x) - level) + logit(thr): keeps exactly
-    the tiles whose mean exceeds `level` at gate threshold `thr`."""
+    """g = scale * (max of ReLU(pooled x) - level) + logit(thr): keeps exactly
+    the tiles whose brightest pooled pixel exceeds `level` at gate threshold
+    `thr` (the gate's global pool is a max)."""
     th = np.zeros(673, np.float64)
     th[4] = 1.0                        # W1[0][0][1][1]: h1[0] = ReLU(p)
     th[80 + 4] = 1.0                   # W2[0][0][1][1]: h2[0] = ReLU(h1[0])
@@ -38,7 +39,7 @@ def brightness_gate(level, scale=50.0, thr=0.05):
     return th
 
 
-def oracle_tile_means(frames):
+def oracle_pooled_tiles(frames):
     out = []
     for F in frames:
         x = oracle.preprocess(F, 0.5, 100.0, 0.01)
@@ -87,9 +88,9 @@ def test_keep_none_gives_nothing():
 @pytest.mark.parametrize("name", ["A", "B"])
 def test_mixed_keep_map(name):
     frames = S.render_frames(2, 768, 1024, "sparse", 4042 if name == "A" else 4043)
-    pooled = oracle_tile_means(frames)
-    means = np.maximum(pooled, 0).mean(axis=(1, 2))
-    srt = np.sort(means)
+    pooled = oracle_pooled_tiles(frames)
+    peaks = np.maximum(pooled, 0).max(axis=(1, 2))
+    srt = np.sort(peaks)
     gaps = np.diff(srt)
     mid = len(srt) // 4 + np.argmax(gaps[len(srt) // 4: 3 * len(srt) // 4])   # widest gap in the middle half
     level = 0.5 * (srt[mid] + srt[mid + 1])

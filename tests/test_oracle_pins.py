@@ -367,7 +367,7 @@ def test_gate_forward_backward_match_torch_autograd():
     x = torch.from_numpy(pooled)[:, None]
     h1 = F.relu(F.conv2d(x, w1, b1, padding=1))
     h2 = F.relu(F.conv2d(h1, w2, b2, padding=1))
-    g = h2.mean(dim=(2, 3)) @ fw + fb
+    g = h2.amax(dim=(2, 3)) @ fw + fb
     L = F.binary_cross_entropy_with_logits(g, torch.from_numpy(y))
     L.backward()
     go = oracle.gate_forward(pooled, theta)
@@ -375,6 +375,44 @@ def test_gate_forward_backward_match_torch_autograd():
     assert np.allclose(go, g.detach().numpy(), rtol=1e-12, atol=1e-12)
     assert abs(Lo - L.item()) < 1e-12
     assert np.allclose(oracle.gate_backward(pooled, theta, dg), t.grad.numpy(), rtol=1e-10, atol=1e-12)
+
+
+def _identity_gate(fw0=2.0, fb=-1.0):
+    """Gate whose channel 0 passes the pooled tile through two identity
+    convolutions (h2[0] = ReLU(p)); every other channel is zero."""
+    theta = np.zeros(673)
+    theta[0 * 9 + 4] = 1.0                     # W1[0][0][1][1]
+    theta[80 + (0 * 8 + 0) * 9 + 4] = 1.0      # W2[0][0][1][1]
+    theta[664] = fw0
+    theta[672] = fb
+    return theta
+
+
+def test_gate_global_pool_is_max_closed_form():
+    r = rng(21)
+    pooled = r.standard_normal((3, 8, 8))
+    theta = _identity_gate()
+    g = oracle.gate_forward(pooled, theta)
+    expect = 2.0 * np.maximum(pooled, 0).reshape(3, -1).max(axis=1) - 1.0
+    assert np.allclose(g, expect, rtol=0, atol=1e-15)
+
+
+def test_gate_max_gradient_goes_to_first_maximum():
+    p = np.zeros((1, 8, 8))
+    p[0, 2, 3] = p[0, 5, 6] = 1.5               # a tie; (2, 3) comes first in raster order
+    p[0, 2, 4] = 0.25                           # neighbours that tell the two apart
+    p[0, 6, 6] = 0.75
+    theta = _identity_gate()
+    grad = oracle.gate_backward(p, theta, np.array([1.0]))
+    first, second = p.copy(), p.copy()
+    second[0, 2, 3] -= 1e-3                     # only (5, 6) attains the max
+    first[0, 5, 6] -= 1e-3                      # only (2, 3) attains the max
+    g_first = oracle.gate_backward(first, theta, np.array([1.0]))
+    g_second = oracle.gate_backward(second, theta, np.array([1.0]))
+    w2 = slice(80, 89)                          # dW2[0][0][:][:] = fw0 * h1 around the argmax
+    assert np.allclose(grad[w2], g_first[w2], atol=1e-12)
+    assert not np.allclose(grad[w2], g_second[w2], atol=1e-3)
+    assert grad[80 + 5] == 2.0 * 0.25 and g_second[80 + 7] == 2.0 * 0.75
 
 
 def test_gate_pool_mean_of_blocks():
