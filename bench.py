@@ -194,12 +194,13 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev):
     avg_s = conv_ms / conv_n * 1e-3
     flop_launch = 2.0 * 9 * C * C * total_px
     tflops = flop_launch / avg_s / 1e12
-    esz = 4 if precision == "fp32" else 2
+    # bytes per activation point: FP32 / BF16 values, FP8 codes + 2 group scale bytes
+    pt_bytes = {"fp32": 4 * C, "bf16": 2 * C, "fp8": C + 2}[precision]
     # algorithmic HBM bytes of the mean non-head conv launch: input + output for
     # all nine, + the residual for the four second convolutions of blocks 1-4
     nb = len(spec.dilations)
     n_conv = 2 * nb - 1
-    bytes_launch = total_px * C * esz * (2 * n_conv + (nb - 1)) / n_conv
+    bytes_launch = total_px * pt_bytes * (2 * n_conv + (nb - 1)) / n_conv
     gbs = bytes_launch / avg_s / 1e9
     key = f"k_conv {precision} C={C} {n}x{side}x{side}"
     if precision == "fp32":

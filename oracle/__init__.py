@@ -59,6 +59,9 @@ def _L():
         _lib.or_round_bf16.argtypes = [d]
         _lib.or_round_e4m3.restype = d
         _lib.or_round_e4m3.argtypes = [d]
+        _lib.or_fp8_group_exp.restype = i
+        _lib.or_fp8_group_exp.argtypes = [d]
+        _lib.or_store_fp8_groups.argtypes = [P, i, l]
         _lib.or_preprocess.argtypes = [P, l, d, d, d, P]
         _lib.or_conv3x3.argtypes = [P, i, i, i, P, P, i, i, P]
         _lib.or_net_maps.restype = i
@@ -88,6 +91,21 @@ def round_e4m3(v: np.ndarray) -> np.ndarray:
     v = np.asarray(v, np.float64)
     f = np.vectorize(_L().or_round_e4m3, otypes=[np.float64])
     return f(v)
+
+
+def fp8_group_exp(amax: float) -> int:
+    """Exponent k of the FP8 group scale 2^k (smallest with amax <= 448 2^k,
+    at least -126)."""
+    return int(_L().or_fp8_group_exp(float(amax)))
+
+
+def store_fp8_groups(a: np.ndarray) -> np.ndarray:
+    """FP8 storage of a planar [C][...] tensor: per pixel, groups of 32
+    channels share one power-of-two scale."""
+    out = np.ascontiguousarray(a, np.float64).copy()
+    C = out.shape[0]
+    _L().or_store_fp8_groups(_p(out), C, out.size // C)
+    return out
 
 
 # ----------------------------------------------------------- preprocessing

@@ -28,8 +28,12 @@
  * summation order.
  *
  * Emulation modes (quant = 1: BF16, quant = 2: FP8 e4m3) round the stored
- * activations and block-convolution operands the way the reduced-precision
- * forms store them; products and sums stay in double.
+ * activations and block-convolution weights the way the reduced-precision
+ * forms store them; products and sums stay in double.  FP8 stores every
+ * activation tensor that a block convolution reads as e4m3 codes with one
+ * power-of-two scale per 32-channel group of each pixel (the last block's
+ * output goes to the head unrounded); the block-convolution weights carry one
+ * scale per output channel.
  *
  * Pins (tests/test_oracle_*.py): delta input reproduces the kernel weights;
  * linearity; constant field; torch-CPU float64 conv2d(dilation=d); residual
@@ -90,8 +94,43 @@ double or_round_e4m3(double v)
 
 static double store_round(double v, int quant)
 {
-    if (quant == 1 || quant == 2) return or_round_bf16(v);
-    return v;
+    if (quant == 1) return or_round_bf16(v);
+    return v;   /* FP8 storage is applied per tensor (or_store_fp8_groups) */
+}
+
+/* Exponent k of the FP8 group scale 2^k: the smallest k with amax <= 448 2^k,
+ * kept to normal float scales (k in -126..127, E8M0 byte k + 127 in 1..254);
+ * amax = 0 gives k = -126. */
+int or_fp8_group_exp(double amax)
+{
+    if (!(amax > 0.0)) return -126;
+    int e;
+    double f = 2.0 * frexp(amax, &e);     /* amax = f 2^(e-1), f in [1, 2) */
+    int k = (e - 1) - (f <= 1.75 ? 8 : 7);
+    if (k < -126) k = -126;
+    if (k > 127) k = 127;
+    return k;
+}
+
+/* FP8 storage of a planar [C][hw] tensor: each pixel's channels are cut into
+ * groups of 32 (the last may be shorter); a value v of a group with largest
+ * magnitude amax is stored as e4m3(v / 2^k) 2^k with k = or_fp8_group_exp(amax). */
+void or_store_fp8_groups(double *a, int C, long hw)
+{
+    for (long p = 0; p < hw; ++p)
+        for (int c0 = 0; c0 < C; c0 += 32) {
+            int c1 = c0 + 32 < C ? c0 + 32 : C;
+            double amax = 0.0;
+            for (int c = c0; c < c1; ++c) {
+                double v = a[(long)c * hw + p];
+                if (fabs(v) > amax) amax = fabs(v);
+            }
+            int k = or_fp8_group_exp(amax);
+            for (int c = c0; c < c1; ++c) {
+                double v = a[(long)c * hw + p];
+                a[(long)c * hw + p] = ldexp(or_round_e4m3(ldexp(v, -k)), k);
+            }
+        }
 }
 
 /* ------------------------------------------------------------ preprocessing */
@@ -166,21 +205,6 @@ static void quant_weights_fp8(double *W, int cout, long per_out)
     }
 }
 
-/* e4m3 activation quantisation of a whole [c][h][w] tensor with one scale:
- * s = amax / 448 (FP32), a_q = e4m3(fl32(a * fl32(448 / amax))) * s. */
-static void quant_act_fp8(double *a, long n)
-{
-    double mx = 0.0;
-    for (long k = 0; k < n; ++k) if (fabs(a[k]) > mx) mx = fabs(a[k]);
-    if (mx == 0.0) return;
-    float inv = (float)(448.0 / (double)(float)mx);
-    float s = (float)((double)(float)mx / 448.0);
-    for (long k = 0; k < n; ++k) {
-        float sc = (float)a[k] * inv;
-        a[k] = or_round_e4m3((double)sc) * (double)s;
-    }
-}
-
 int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
                 double in_scale, const float *params, int C, int nblocks,
                 const int *dil, int quant, double *maps /* [5][h][w] */)
@@ -207,6 +231,7 @@ int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
     promote(p, C, bd); p += C;
     or_conv3x3(x, 1, h, w, Wd, bd, C, 1, a);
     for (long k = 0; k < hw * C; ++k) a[k] = store_round(a[k] > 0 ? a[k] : 0.0, quant);
+    if (quant == 2 && nblocks > 0) or_store_fp8_groups(a, C, hw);
 
     for (int blk = 0; blk < nblocks; ++blk) {
         int d = dil[blk];
@@ -214,19 +239,22 @@ int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
         promote(p, nconv, Wd); p += nconv;
         promote(p, C, bd); p += C;
         if (quant == 1) for (long k = 0; k < nconv; ++k) Wd[k] = or_round_bf16(Wd[k]);
-        if (quant == 2) { quant_weights_fp8(Wd, C, (long)C * 9); memcpy(u, a, sizeof(double) * hw * C); quant_act_fp8(u, hw * C); }
-        or_conv3x3(quant == 2 ? u : a, C, h, w, Wd, bd, C, d, t);
+        if (quant == 2) quant_weights_fp8(Wd, C, (long)C * 9);
+        or_conv3x3(a, C, h, w, Wd, bd, C, d, t);
         for (long k = 0; k < hw * C; ++k) t[k] = store_round(t[k] > 0 ? t[k] : 0.0, quant);
+        if (quant == 2) or_store_fp8_groups(t, C, hw);
         /* a = ReLU(a + conv_d(t; W2, b2)) */
         promote(p, nconv, Wd); p += nconv;
         promote(p, C, bd); p += C;
         if (quant == 1) for (long k = 0; k < nconv; ++k) Wd[k] = or_round_bf16(Wd[k]);
-        if (quant == 2) { quant_weights_fp8(Wd, C, (long)C * 9); quant_act_fp8(t, hw * C); }
+        if (quant == 2) quant_weights_fp8(Wd, C, (long)C * 9);
         or_conv3x3(t, C, h, w, Wd, bd, C, d, u);
         for (long k = 0; k < hw * C; ++k) {
             double s = a[k] + u[k];
             a[k] = store_round(s > 0 ? s : 0.0, quant);
         }
+        /* FP8: the last block's output feeds the head directly */
+        if (quant == 2 && blk + 1 < nblocks) or_store_fp8_groups(a, C, hw);
     }
 
     /* head: 1x1, C -> 5, FP32 weights in every mode */

@@ -140,7 +140,8 @@ int64_t frame_act_points(const dl_net *net, int h, int w)
 // the conv kernels address a frame's activations with 32-bit byte offsets
 bool frame_act_fits(const dl_net *net, int h, int w)
 {
-    const int64_t esz = net->cfg.precision == DL_FP32 ? 4 : 2;
+    // FP32 4, BF16 2, FP8 1 byte per value (FP8 scales: 2 bytes per point, also within range)
+    const int64_t esz = net->cfg.precision == DL_FP32 ? 4 : net->cfg.precision == DL_BF16 ? 2 : 1;
     return frame_act_points(net, h, w) * net->C * esz < ((int64_t)1 << 31);
 }
 
@@ -192,28 +193,25 @@ struct Plan {
     size_t act0 = 0, act1 = 0, act2 = 0, maps = 0, mask = 0, rc = 0, roff = 0, total = 0;
     bool gated = false;
     size_t pooled = 0, glog = 0, keep = 0, lists = 0, lcount = 0;
-    size_t amax = 0;                // FP8: per-frame activation maxima, one row per producing layer
-    bool fp8 = false;
 };
 
 bool gated_run(const dl_net *net) { return (net->cfg.flags & DL_FLAG_GATE) && net->gate_set; }
 
 Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
 {
-    const size_t esz = net->cfg.precision == DL_FP32 ? 4 : 2;
+    // bytes per activation point: FP32 / BF16 values, or FP8 codes plus two
+    // group scale bytes (the scales follow all codes of the buffer)
+    const int prec = net->cfg.precision;
+    const size_t pt_bytes = prec == DL_FP32 ? 4 * (size_t)net->C : prec == DL_BF16 ? 2 * (size_t)net->C : net->C + 2;
     Plan p;
     size_t o = 0;
-    p.act0 = o; o = align_up(o + (size_t)g.total_act * net->C * esz);
-    p.act1 = o; o = align_up(o + (size_t)g.total_act * net->C * esz);
-    p.act2 = o; o = align_up(o + (size_t)g.total_act * net->C * esz);
+    p.act0 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
+    p.act1 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
+    p.act2 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
     p.maps = o; if (!ext_maps) o = align_up(o + (size_t)g.total_px * 5 * 4);
     p.mask = o; o = align_up(o + (size_t)g.total_words * 8);
     p.rc = o; o = align_up(o + (size_t)g.total_rows * 4);
     p.roff = o; o = align_up(o + (size_t)(g.total_rows + 1) * 4);
-    if (net->cfg.precision == DL_FP8) {
-        p.fp8 = true;
-        p.amax = o; o = align_up(o + (size_t)2 * net->nb * g.nf * 4);
-    }
     if (gated_run(net)) {
         const int L = 2 * net->nb;
         p.gated = true;
@@ -374,14 +372,10 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
     const uint32_t *lcount = p.gated ? reinterpret_cast<const uint32_t *>(p.ws + p.lcount) : nullptr;
     int stem_r = 0;
     for (int b = 0; b < net->nb; ++b) stem_r += 2 * net->dil[b];
-    // FP8: row l of amax holds the per-frame max of layer l's stored output
-    // (l = 0: stem), which sets the activation scale of conv layer l
-    uint32_t *amax = p.fp8 ? reinterpret_cast<uint32_t *>(p.ws + p.amax) : nullptr;
-    if (amax) HIPCHK(net, launch_zero_u32(amax, (int64_t)2 * net->nb * g.nf, s));
     {
         StageTimer t(net, DL_STAGE_STEM, s);
         HIPCHK(net, launch_stem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset, scale, a0,
-                                net->cfg.precision != DL_FP32, amax, keep, stem_r, s));
+                                net->cfg.precision, keep, stem_r, s));
     }
     const int maxg = conv_max_grid(C, net->cfg.precision, g.tr, net->ncu);
     void *x = a0, *xn = p.ws + p.act2;      // block input, block output (alternating)
@@ -396,11 +390,7 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         a.blk = b;
         a.in_phase = lay == net->dil[b] && lay > 1;
         a.out_shift = __builtin_ctz((unsigned)lay);
-        if (amax) {
-            a.wscale = net->d_wscale + (size_t)(b * 2) * C;
-            a.amax_in = amax + (size_t)(2 * b) * g.nf;
-            a.amax_out = amax + (size_t)(2 * b + 1) * g.nf;
-        }
+        if (net->cfg.precision == DL_FP8) a.wscale = net->d_wscale + (size_t)(b * 2) * C;
         a.in = x;
         a.out = a1;
         a.res = nullptr;
@@ -420,11 +410,7 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         a.out_shift = __builtin_ctz((unsigned)lay_next);
         a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(b * 2 + 1) * net->wpk_stride;
         a.bias = net->d_bias + (size_t)(b * 2 + 1) * C;
-        if (amax) {
-            a.wscale = net->d_wscale + (size_t)(b * 2 + 1) * C;
-            a.amax_in = amax + (size_t)(2 * b + 1) * g.nf;
-            a.amax_out = b + 1 < net->nb ? amax + (size_t)(2 * b + 2) * g.nf : nullptr;
-        }
+        if (net->cfg.precision == DL_FP8) a.wscale = net->d_wscale + (size_t)(b * 2 + 1) * C;
         if (lists) {
             a.list = lists + (size_t)(2 * b + 1) * g.max_tiles;
             a.list_count = lcount + 2 * b + 1;

@@ -143,12 +143,52 @@ __device__ __forceinline__ int find_frame(const FrameDesc *fd, int nf, int64_t i
     return lo;
 }
 
+// two floats -> two BF16 (round to nearest even, v_cvt_pk_bf16_f32), packed
+// low value first
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pack2(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t{lo, hi}), bf16x2_t));
+}
+
+// ---- FP8 activation storage ----
+// The FP8 form stores an activation tensor as e4m3 codes, C bytes per point,
+// then (from byte offset total_act * C of the same buffer) two E8M0 scale
+// bytes per point, one per group of 32 channels: value = code * 2^(byte - 127).
+// A group's scale is the smallest power of two s with amax / s <= 448, where
+// amax is the largest magnitude in the group; s stays a normal float
+// (byte 1..254; an all-zero group gets byte 1).
+__device__ __forceinline__ uint32_t fp8_scale_byte(float amax)
+{
+    const uint32_t u = __float_as_uint(amax);
+    const int b = (int)(u >> 23) - ((u & 0x7FFFFFu) <= 0x600000u ? 8 : 7);
+    return (uint32_t)(b < 1 ? 1 : b > 254 ? 254 : b);
+}
+__device__ __forceinline__ float fp8_scale_value(uint32_t byte) { return __uint_as_float(byte << 23); }
+typedef short i16x2_t __attribute__((ext_vector_type(2)));
+// e4m3 codes (round to nearest even) of v / s for four values with |v| / s <= 448
+__device__ __forceinline__ uint32_t fp8_pack4(float v0, float v1, float v2, float v3, float s)
+{
+    i16x2_t r = {0, 0};
+    r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(r, v0, v1, s, false);
+    r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(r, v2, v3, s, true);
+    return __builtin_bit_cast(uint32_t, r);
+}
+// the four e4m3 codes of a word, each times s
+__device__ __forceinline__ v4f fp8_unpack4(uint32_t codes, float s)
+{
+    const f32x2_t lo = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(codes, s, false);
+    const f32x2_t hi = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(codes, s, true);
+    return v4f{lo[0], lo[1], hi[0], hi[1]};
+}
+
 // ---- launchers (kernels_*.hip) ----
 // all return hipError_t of the launch
-// act_bf16: store BF16 activations; amax (nullable): per-frame running max of
-// the stored values, as float bits, for the FP8 form's activation scales
+// precision: storage of the output activations (FP32, BF16, or FP8 codes
+// and group scales)
 hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                       float offset, float scale, void *act, int act_bf16, uint32_t *amax, const uint8_t *keep,
+                       float offset, float scale, void *act, int precision, const uint8_t *keep,
                        int radius, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // gated runs: keep[t] = logit[t] > tau_gate; then one compacted list of conv
@@ -158,14 +198,12 @@ hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uin
                                const int *dil, int nlayers, int32_t *lists, uint32_t *counts, hipStream_t s);
 
 struct ConvArgs {
-    const void *in;          // activations (FP32, or BF16 for the BF16 and FP8 forms), frame at act_off
+    const void *in;          // activations (FP32, BF16, or FP8 codes + group scales), frame at act_off
     const void *res;         // residual (same layout as out) or null
     void *out;               // NHWC output (or null when the head is fused)
     const void *wpk;         // packed weights
     const float *bias;       // [C]
     const float *wscale;     // FP8: per-output-channel weight scale [C]
-    const uint32_t *amax_in; // FP8: per-frame max of the input activations (float bits)
-    uint32_t *amax_out;      // FP8: per-frame max of the stored output (float bits), or null
     const float *head;       // fused head: w [5][C] then b [5]; null = no head
     float *maps;             // fused head output, planar [5][h][w] per frame
     const FrameDesc *fd;

@@ -30,16 +30,16 @@
 //   BF16  v_mfma_f32_16x16x32_bf16 (FP32 accumulation); K is cut into chunks
 //         of 8 channels of one tap and lane group kq of step m takes chunk
 //         4 m + kq (one 16-byte LDS read).  Weights live in LDS.
-//   FP8   v_mfma_scale_f32_16x16x128_f8f6f4 with e4m3 operands (unit block
-//         scales); K runs tap by tap with each tap's channels padded to a
-//         multiple of 32, and lane group kq of step m takes one 32-channel
-//         half of one tap (two 16-byte LDS reads).
-//         Activations are stored in BF16; staging quantises them into LDS with
-//         the frame's scale amax / 448 (v_cvt_pk_fp8_f32: OCP e4m3, round to
-//         nearest even; inputs clamped to 448 so it saturates); weights carry
-//         a per-output-channel scale.  The epilogue multiplies the FP32
-//         accumulator by both scales and tracks the max of what it stores,
-//         which sets the next layer's scale.
+//   FP8   v_mfma_scale_f32_16x16x128_f8f6f4 with e4m3 operands; K runs tap by
+//         tap with each tap's channels padded to a multiple of 32, and lane
+//         group kq of step m takes one 32-channel group of one tap (two
+//         16-byte LDS reads).  Activations are stored as e4m3 codes with one
+//         E8M0 scale byte per 32-channel group of each point (dloc_internal.h),
+//         which is exactly the MFMA's per-lane block scale of the activation
+//         operand; weights carry a per-output-channel scale applied in the
+//         epilogue.  The epilogue rounds its output to BF16, takes each group's
+//         max over the four lanes holding the pixel, and stores codes and
+//         scale bytes.
 // K is padded with zero-weight chunks when 9 C is not a multiple of the MFMA's K.
 // BF16 and FP8 pass each wave's output row (and residual) through LDS so they
 // move in whole 16-byte lanes; every store is a buffer store whose offset is
@@ -87,16 +87,9 @@ __device__ __forceinline__ v4f relu4(v4f v)
     return r;
 }
 
-__device__ __forceinline__ uint32_t bf16_rne(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
-}
 
-__device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(bf16_rne(f) << 16); }
-
-// storage of the activations in HBM: FP32, or BF16 (BF16 and FP8 forms)
+// storage of the activations in HBM: FP32, BF16, or FP8 (e4m3 codes plus
+// one scale byte per 32-channel group of a point, dloc_internal.h)
 template <int P> struct Store {
     static constexpr int ESZ = 2;
     using Raw = uint2;                      // 4 BF16 values as loaded
@@ -117,6 +110,11 @@ template <int P> struct Store {
         u[1] = (__float_as_uint(v[2]) >> 16) | (__float_as_uint(v[3]) & 0xFFFF0000u);
         __builtin_amdgcn_raw_buffer_store_b64(u, rs, off, 0, 0);
     }
+};
+template <> struct Store<DL_FP8> {
+    static constexpr int ESZ = 1;
+    using Raw = uint2;                      // 4 codes and their group's scale byte
+    __device__ static v4f unpack(Raw u) { return fp8_unpack4(u.x, fp8_scale_value(u.y)); }
 };
 template <> struct Store<DL_FP32> {
     static constexpr int ESZ = 4;
@@ -172,9 +170,11 @@ template <int P, int TR> constexpr int min_waves() { return P == DL_FP32 && TR =
 template <int C, int P, int TR_>
 struct Lds {
     static constexpr int TR = TR_, TC = TileShape<P>::TC;
-    // bytes per point; FP8 points hold the tap's padded CT bytes (the padding
-    // is zeroed once, staging writes only the C real channels)
-    static constexpr int PS = stride_8_mod_16(P == DL_FP8 ? (C + 31) / 32 * 8 : C * KPlan<C, P>::LESZ / 4) * 4;
+    // bytes per point; FP8 points hold the tap's padded CT codes (the padding
+    // is zeroed once, staging writes only the C real channels), then the
+    // point's two group scale bytes at byte CT
+    static constexpr int CT8 = (C + 31) / 32 * 32;
+    static constexpr int PS = stride_8_mod_16(P == DL_FP8 ? CT8 / 4 + 1 : C * KPlan<C, P>::LESZ / 4) * 4;
     static constexpr int PW = TC + 2;
     static constexpr int NPT = (TR + 2) * PW;
     static constexpr int TBYTES = align16(NPT * PS);
@@ -187,10 +187,13 @@ struct Lds {
     static constexpr int BOFF = WOFF + LDSW;                           // bias [C]
     static constexpr int HOFF = BOFF + C * 4;                          // head [5C + 5]
     static constexpr int SOFF = HOFF + (5 * C + 5) * 4;                // FP8 weight scales [C]
-    // BF16 and FP8 stage each wave's output row (TC pixels x C BF16 values,
-    // pixel-major) so it leaves in whole 16-byte lanes
-    static constexpr int OPX = C * 2;                                  // staging bytes per pixel
-    static constexpr int OWAVE = P == DL_FP32 ? 0 : TC * OPX;
+    // BF16 and FP8 stage each wave's output row (TC pixels x C BF16 values or
+    // e4m3 codes, pixel-major) so it leaves in whole 16-byte lanes; FP8 adds
+    // the row's residual scales and output scales (2 bytes per pixel each)
+    static constexpr int OPX = P == DL_FP8 ? C : C * 2;                // staging bytes per pixel
+    static constexpr int RSOFF = TC * OPX;                             // FP8: residual scales
+    static constexpr int OSOFF = RSOFF + TC * 2;                       // FP8: output scales
+    static constexpr int OWAVE = P == DL_FP32 ? 0 : P == DL_FP8 ? align16(OSOFF + TC * 2) : TC * OPX;
     static constexpr int OOFF = align16(SOFF + C * 4);
     static constexpr int TOTAL = align16(OOFF + TR * OWAVE);
     static constexpr bool FITS = TOTAL <= 160 * 1024;   // else no kernel exists for this shape
@@ -253,6 +256,11 @@ k_conv(ConvArgs a, Geometry geo)
     constexpr int NQ = NPT * SCH;
     constexpr int NPF = (NQ + NT - 1) / NT;
     v4f pf[NPF];
+    // FP8: the two group scale bytes of each point, from the scale region
+    // (byte total_act * C of the activation buffer)
+    constexpr int NPS = P == DL_FP8 ? (NPT + NT - 1) / NT : 1;
+    uint32_t psc[NPS];
+    const int64_t sc_off = geo.total_act * C;
     // the prefetched tile: frame, origin, the frame fields the tile needs, and
     // where its input sits: point (ii, jj) of the tile, at pixel (Y0 + d ii,
     // X0 + d jj), is activation point A0 + ii RS + jj CS of the frame.  In the
@@ -264,7 +272,6 @@ k_conv(ConvArgs a, Geometry geo)
     // offset, which reads as zero.
     int nf = 0, nY0 = 0, nX0 = 0, nH = 0, nW = 0, nA0 = 0, nRS = 0, nCS = 0;
     int64_t npx = 0, nact = 0;
-    float namax = 0.f;
     auto fetch = [&](int64_t ti) {
         const int64_t t = a.list ? (int64_t)ld_const(a.list + ti) : ti;
         nf = find_frame(a.fd, geo.nf, t, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
@@ -285,7 +292,6 @@ k_conv(ConvArgs a, Geometry geo)
             nRS = dd * nW;
             nCS = dd;
         }
-        if constexpr (P == DL_FP8) namax = __uint_as_float(ld_const(a.amax_in + nf));
         const __amdgpu_buffer_rsrc_t rin =
             buf_rsrc(const_cast<char *>(static_cast<const char *>(a.in)) + nact * (C * SESZ), 0x7FFFFFFFu);
 #pragma unroll
@@ -299,21 +305,19 @@ k_conv(ConvArgs a, Geometry geo)
             pf[k] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(
                                                 rin, ok ? (nA0 + ii * nRS + jj * nCS) * (C * SESZ) + ch * 16 : BUF_OOB, 0, 0));
         }
-    };
-
-    // FP8: each wave keeps the max of what it stores over its consecutive
-    // tiles of one frame and publishes it with one atomic per frame change
-    // (ReLU outputs are >= 0, so float order is the unsigned order of the bits)
-    float run_max = 0.f;
-    int run_f = -1;
-    auto flush_max = [&]() {
-        if (run_f >= 0 && a.amax_out) {
-            float v = run_max;
+        if constexpr (P == DL_FP8) {
+            const __amdgpu_buffer_rsrc_t rsc =
+                buf_rsrc(const_cast<char *>(static_cast<const char *>(a.in)) + sc_off + nact * 2, 0x7FFFFFFFu);
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
-            if (lane == 0) atomicMax(a.amax_out + run_f, __float_as_uint(v));
+            for (int k = 0; k < NPS; ++k) {
+                const int pt0 = tid + k * NT;
+                const int pt = pt0 < NPT ? pt0 : NPT - 1;
+                const int ii = pt / PW - 1, jj = pt - (pt / PW) * PW - 1;
+                const int y = nY0 + dd * ii, x = nX0 + dd * jj;
+                const bool ok = pt0 < NPT && (unsigned)y < (unsigned)nH && (unsigned)x < (unsigned)nW;
+                psc[k] = __builtin_amdgcn_raw_buffer_load_b16(rsc, ok ? (nA0 + ii * nRS + jj * nCS) * 2 : BUF_OOB, 0, 0);
+            }
         }
-        run_max = 0.f;
     };
 
     int64_t ti = t0 + slot;
@@ -323,14 +327,11 @@ k_conv(ConvArgs a, Geometry geo)
     // path, where the previous tile's stores follow the loads
 #pragma unroll
     for (int k = 0; k < NPF; ++k) asm volatile("" : : "v"(pf[k]));
+#pragma unroll
+    for (int k = 0; k < NPS; ++k) asm volatile("" : : "v"(psc[k]));
     for (; ti < t1; ti += nslot) {
-        const int f = nf, Y0 = nY0, X0 = nX0, H = nH, W = nW, A0 = nA0, RS = nRS, CS = nCS;
+        const int Y0 = nY0, X0 = nX0, H = nH, W = nW, A0 = nA0, RS = nRS, CS = nCS;
         const int64_t px_off = npx, act = nact;
-        float qinv = 1.f, qscale = 1.f;          // FP8 activation quantisation
-        if constexpr (P == DL_FP8) {
-            qinv = namax > 0.f ? 448.f / namax : 0.f;
-            qscale = namax / 448.f;
-        }
 
         __syncthreads();   // the previous tile's LDS reads are done (and weights staged)
 #pragma unroll
@@ -338,26 +339,14 @@ k_conv(ConvArgs a, Geometry geo)
             const int q = tid + k * NT;
             if (q < NQ) {
                 const int pt = q / SCH, ch = q - (q / SCH) * SCH;
-                const v4f v = pf[k];
-                if constexpr (P != DL_FP8) {
-                    *reinterpret_cast<v4f *>(sT + pt * PS + ch * 16) = v;
-                } else {
-                    // e4m3 codes, round to nearest even; values are >= 0 (ReLU outputs)
-                    // and at most 448 up to one rounding, clamped so the conversion
-                    // saturates instead of overflowing
-                    uint32_t w2[4];
+                *reinterpret_cast<v4f *>(sT + pt * PS + ch * 16) = pf[k];
+            }
+        }
+        if constexpr (P == DL_FP8) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const uint32_t w32 = __float_as_uint(v[e]);
-                        const float lo = fminf(__uint_as_float(w32 << 16) * qinv, 448.f);
-                        const float hi = fminf(__uint_as_float(w32 & 0xFFFF0000u) * qinv, 448.f);
-                        w2[e] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(lo, hi, 0, false) & 0xFFFFu;
-                    }
-                    uint2 o;
-                    o.x = w2[0] | (w2[1] << 16);
-                    o.y = w2[2] | (w2[3] << 16);
-                    *reinterpret_cast<uint2 *>(sT + pt * PS + ch * 8) = o;
-                }
+            for (int k = 0; k < NPS; ++k) {
+                const int pt = tid + k * NT;
+                if (pt < NPT) *reinterpret_cast<uint16_t *>(sT + pt * PS + L::CT8) = (uint16_t)psc[k];
             }
         }
         __syncthreads();
@@ -382,22 +371,30 @@ k_conv(ConvArgs a, Geometry geo)
         // epilogue, one pixel block at a time.
         constexpr bool STAGE = P != DL_FP32 && !HEAD;
         constexpr bool EARLY_RES = RES && (P != DL_FP32 ? HEAD : L::LDSW_FP32);
-        constexpr int CPX = C * 2 / 16;                     // 16-byte chunks per staged pixel
+        constexpr int CPX = L::OPX / 16;                    // 16-byte chunks per staged pixel
         constexpr int NRC = STAGE ? TC * CPX / 64 : 1;      // chunks per lane
         static_assert(!STAGE || (TC * CPX) % 64 == 0, "staging chunks per lane");
         // this wave's output row: input-layout point of its lattice column c is
         // Ar + c CS (the residual sits there); frame-relative, < 2^31 bytes
         const int Ar = A0 + wave * RS;
         v4u rc[RES && STAGE ? NRC : 1];
+        uint32_t rsc = 0;                                   // FP8: this lane's pixel's residual scales
+        static_assert(P != DL_FP8 || TC == 64, "FP8 staging: one lane per pixel of the row");
         if constexpr (RES && STAGE) {
             const __amdgpu_buffer_rsrc_t rres =
-                buf_rsrc(const_cast<char *>(static_cast<const char *>(a.res)) + act * C * 2, 0x7FFFFFFFu);
+                buf_rsrc(const_cast<char *>(static_cast<const char *>(a.res)) + act * L::OPX, 0x7FFFFFFFu);
 #pragma unroll
             for (int i = 0; i < NRC; ++i) {
                 const int q = lane + 64 * i, px = q / CPX, part = q - (q / CPX) * CPX;
                 const int xo = X0 + dd * px;
                 rc[i] = __builtin_amdgcn_raw_buffer_load_b128(
-                    rres, row_ok && xo < W ? (Ar + px * CS) * (C * 2) + part * 16 : BUF_OOB, 0, 0);
+                    rres, row_ok && xo < W ? (Ar + px * CS) * L::OPX + part * 16 : BUF_OOB, 0, 0);
+            }
+            if constexpr (P == DL_FP8) {
+                const __amdgpu_buffer_rsrc_t rrs =
+                    buf_rsrc(const_cast<char *>(static_cast<const char *>(a.res)) + sc_off + act * 2, 0x7FFFFFFFu);
+                const int xo = X0 + dd * lane;
+                rsc = __builtin_amdgcn_raw_buffer_load_b16(rrs, row_ok && xo < W ? (Ar + lane * CS) * 2 : BUF_OOB, 0, 0);
             }
         }
         constexpr int RPB = EARLY_RES ? PB : 1;
@@ -407,8 +404,17 @@ k_conv(ConvArgs a, Geometry geo)
             for (int pp = 0; pp < RPB; ++pp) {
                 const int c = 16 * (p0 + pp) + j, xo = X0 + dd * c;
                 const int64_t pix = act + (row_ok && xo < W ? Ar + c * CS : 0);   // off-frame: any valid point
+                if constexpr (P == DL_FP8) {
+                    const uint8_t *rb = static_cast<const uint8_t *>(a.res);
+                    const uint32_t sc2 = *reinterpret_cast<const uint16_t *>(rb + sc_off + pix * 2);
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) rr[nb][pp] = Store<P>::raw4(a.res, pix * C + nb * 16 + kq * 4);
+                    for (int nb = 0; nb < NB; ++nb)
+                        rr[nb][pp] = uint2{*reinterpret_cast<const uint32_t *>(rb + pix * C + nb * 16 + kq * 4),
+                                           (sc2 >> (8 * (nb >> 1))) & 0xFFu};
+                } else {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) rr[nb][pp] = Store<P>::raw4(a.res, pix * C + nb * 16 + kq * 4);
+                }
             }
         };
         if constexpr (EARLY_RES) load_res(0);
@@ -530,12 +536,27 @@ k_conv(ConvArgs a, Geometry geo)
             const char *sW = sT + L::WOFF;
 #pragma unroll 1
             for (int m = 0; m < NIT; ++m) {
-                // this lane's K chunk: half hf of tap t (past the ninth tap the
-                // weights are zero and any point will do)
-                const int g = 4 * m + kq, t = g / HPT, hf = g - (g / HPT) * HPT;
-                const int tc = t < 9 ? t : 4;
-                const int boff = ((tc / 3) * PW + tc % 3) * PS + hf * 32;
+                // The MFMA scales K in blocks of 32: block b of step m is K chunk
+                // 4 m + b (half hf of tap t: one channel group of one point;
+                // past the ninth tap the weights are zero and any point will
+                // do).  Its values are half kq & 1 of lane groups {0, 1} (b
+                // even) or {2, 3} (b odd), in bytes 0-15 (b < 2) or 16-31
+                // (b >= 2), and its scale comes from lane group b.  So this
+                // lane reads half kq & 1 of chunks 4 m + kq / 2 (low 16 bytes)
+                // and 4 m + 2 + kq / 2 (high), and the scale of chunk 4 m + kq.
+                auto chunk_off = [&](int g) {
+                    const int t = g / HPT, hf = g - (g / HPT) * HPT, tc = t < 9 ? t : 4;
+                    return ((tc / 3) * PW + tc % 3) * PS + hf * 32;
+                };
+                auto scale_off = [&](int g) {
+                    const int t = g / HPT, hf = g - (g / HPT) * HPT, tc = t < 9 ? t : 4;
+                    return ((tc / 3) * PW + tc % 3) * PS + L::CT8 + hf;
+                };
+                const int lo_off = chunk_off(4 * m + (kq >> 1)) + 16 * (kq & 1);
+                const int hi_off = chunk_off(4 * m + 2 + (kq >> 1)) + 16 * (kq & 1);
+                const int soff = scale_off(4 * m + kq);
                 v8i av[NB], bv[PB];
+                int sb[PB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     const v4u *pa = reinterpret_cast<const v4u *>(sW + ((m * NB + nb) * 64 + lane) * 32);
@@ -544,16 +565,21 @@ k_conv(ConvArgs a, Geometry geo)
                 }
 #pragma unroll
                 for (int p = 0; p < PB; ++p) {
-                    const v4u *pb = reinterpret_cast<const v4u *>(sT + (wave * PW + 16 * p + j) * PS + boff);
-                    const v4u lo = pb[0], hi = pb[1];
+                    const char *pt = sT + (wave * PW + 16 * p + j) * PS;
+                    const v4u lo = *reinterpret_cast<const v4u *>(pt + lo_off);
+                    const v4u hi = *reinterpret_cast<const v4u *>(pt + hi_off);
                     bv[p] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+                    sb[p] = *reinterpret_cast<const uint8_t *>(sT + (wave * PW + 16 * p + j) * PS + soff);
                 }
+                // weights: unit block scales (their per-channel scale is applied
+                // in the epilogue); activations: each lane's 32 K values are one
+                // group of one point, scaled by that group's E8M0 byte
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                     for (int p = 0; p < PB; ++p)
                         acc[nb][p] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                            av[nb], bv[p], acc[nb][p], 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
+                            av[nb], bv[p], acc[nb][p], 0, 0, 0, 0x7F7F7F7F, 0, sb[p]);
             }
         }
 
@@ -568,6 +594,7 @@ k_conv(ConvArgs a, Geometry geo)
                 const int q = lane + 64 * i, px = q / CPX, part = q - (q / CPX) * CPX;
                 *reinterpret_cast<v4u *>(sO + px * L::OPX + part * 16) = rc[i];
             }
+            if constexpr (P == DL_FP8) *reinterpret_cast<uint16_t *>(sO + L::RSOFF + lane * 2) = (uint16_t)rsc;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
         // output in phase layout lo = 2^out_shift (1: plain NHWC): pixel (y, x)
@@ -579,12 +606,13 @@ k_conv(ConvArgs a, Geometry geo)
         auto out_point = [&](int xo) { return ((osub + (xo & om)) * ohd + oiy) * owd + (xo >> osh); };
         const __amdgpu_buffer_rsrc_t orow =
             buf_rsrc(HEAD ? nullptr : static_cast<char *>(a.out) + act * C * ESZ, HEAD ? 0u : 0x7FFFFFFFu);
-        float wmax = 0.f;
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
             const int xo = X0 + dd * (16 * p + j);
             const bool ok = xo < W;
+            const int spx = 16 * p + j;                      // this lane's pixel in the staged row
             float h0 = 0.f, h1 = 0.f, h2 = 0.f, h3 = 0.f, h4 = 0.f;
+            v4f vs[P == DL_FP8 && STAGE ? NB : 1];           // FP8: quantised once all NB are known
             if constexpr (RES && !STAGE && !EARLY_RES) load_res(p);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
@@ -592,11 +620,15 @@ k_conv(ConvArgs a, Geometry geo)
                 v4f v = acc[nb][p];
                 if constexpr (P == DL_FP8) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] *= sS[oc + r] * qscale;
+                    for (int r = 0; r < 4; ++r) v[r] *= sS[oc + r];
                 }
                 v[0] += sB[oc + 0]; v[1] += sB[oc + 1]; v[2] += sB[oc + 2]; v[3] += sB[oc + 3];
-                uint2 *so = reinterpret_cast<uint2 *>(sO + (16 * p + j) * L::OPX + oc * 2);
-                if constexpr (RES && STAGE) {
+                uint2 *so = reinterpret_cast<uint2 *>(sO + spx * L::OPX + oc * 2);
+                if constexpr (RES && STAGE && P == DL_FP8) {
+                    const uint32_t codes = *reinterpret_cast<const uint32_t *>(sO + spx * L::OPX + oc);
+                    const uint32_t sbr = *reinterpret_cast<const uint8_t *>(sO + L::RSOFF + spx * 2 + (oc >> 5));
+                    v += fp8_unpack4(codes, fp8_scale_value(sbr));
+                } else if constexpr (RES && STAGE) {
                     const uint2 u = *so;
                     v += v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xFFFF0000u),
                              __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xFFFF0000u)};
@@ -604,15 +636,18 @@ k_conv(ConvArgs a, Geometry geo)
                     v += Store<P>::unpack(rr[nb][EARLY_RES ? p : 0]);
                 }
                 v = relu4(v);
-                if constexpr (P != DL_FP32) {        // what is stored (and what the head reads) is BF16
-                    v[0] = bf16_round(v[0]); v[1] = bf16_round(v[1]);
-                    v[2] = bf16_round(v[2]); v[3] = bf16_round(v[3]);
+                // BF16: what is stored, and what the head reads, is BF16
+                uint2 pk{0u, 0u};
+                if constexpr (P == DL_BF16) {
+                    pk = uint2{bf16_pack2(v[0], v[1]), bf16_pack2(v[2], v[3])};
+                    if constexpr (HEAD)
+                        v = v4f{__uint_as_float(pk.x << 16), __uint_as_float(pk.x & 0xFFFF0000u),
+                                __uint_as_float(pk.y << 16), __uint_as_float(pk.y & 0xFFFF0000u)};
                 }
-                if constexpr (STAGE) {
-                    *so = uint2{(__float_as_uint(v[0]) >> 16) | (__float_as_uint(v[1]) & 0xFFFF0000u),
-                                (__float_as_uint(v[2]) >> 16) | (__float_as_uint(v[3]) & 0xFFFF0000u)};
-                    if constexpr (P == DL_FP8)
-                        if (ok && row_ok) wmax = fmaxf(wmax, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+                if constexpr (STAGE && P == DL_FP8) {
+                    vs[nb] = v;
+                } else if constexpr (STAGE) {
+                    *so = pk;
                 } else if constexpr (!HEAD) {
                     Store<P>::bstore4(orow, ok && row_ok ? (out_point(xo) * C + oc) * ESZ : BUF_OOB, v);
                 } else {
@@ -625,6 +660,28 @@ k_conv(ConvArgs a, Geometry geo)
                         h4 += sH[4 * C + oc + r] * v[r];
                     }
                 }
+            }
+            if constexpr (STAGE && P == DL_FP8) {
+                // group g = channels 32 g .. 32 g + 31 = blocks nb = 2 g, 2 g + 1; its
+                // max over the pixel's four lane groups sets the scale byte
+                float gm[2] = {0.f, 0.f};
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    gm[nb >> 1] = fmaxf(gm[nb >> 1], fmaxf(fmaxf(vs[nb][0], vs[nb][1]), fmaxf(vs[nb][2], vs[nb][3])));
+                uint32_t sbyte[2];
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    gm[g] = fmaxf(gm[g], __shfl_xor(gm[g], 16));
+                    gm[g] = fmaxf(gm[g], __shfl_xor(gm[g], 32));
+                    sbyte[g] = fp8_scale_byte(gm[g]);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const v4f v = vs[nb];
+                    *reinterpret_cast<uint32_t *>(sO + spx * L::OPX + nb * 16 + kq * 4) =
+                        fp8_pack4(v[0], v[1], v[2], v[3], fp8_scale_value(sbyte[nb >> 1]));
+                }
+                if (kq == 0) *reinterpret_cast<uint16_t *>(sO + L::OSOFF + spx * 2) = (uint16_t)(sbyte[0] | (sbyte[1] << 8));
             }
             if constexpr (HEAD) {
                 h0 += __shfl_xor(h0, 16); h0 += __shfl_xor(h0, 32);
@@ -650,19 +707,18 @@ k_conv(ConvArgs a, Geometry geo)
                 const int q = lane + 64 * i, px = q / CPX, part = q - (q / CPX) * CPX;
                 const int xo = X0 + dd * px;
                 const v4u d = *reinterpret_cast<const v4u *>(sO + px * L::OPX + part * 16);
-                __builtin_amdgcn_raw_buffer_store_b128(d, orow, row_ok && xo < W ? out_point(xo) * (C * 2) + part * 16 : BUF_OOB,
+                __builtin_amdgcn_raw_buffer_store_b128(d, orow, row_ok && xo < W ? out_point(xo) * L::OPX + part * 16 : BUF_OOB,
                                                        0, 0);
             }
-        }
-        if constexpr (P == DL_FP8 && !HEAD) {
-            if (f != run_f) {
-                flush_max();
-                run_f = f;
+            if constexpr (P == DL_FP8) {            // one lane per pixel: its two scale bytes
+                const __amdgpu_buffer_rsrc_t osc =
+                    buf_rsrc(static_cast<char *>(a.out) + sc_off + act * 2, 0x7FFFFFFFu);
+                const int xo = X0 + dd * lane;
+                const uint32_t sc2 = *reinterpret_cast<const uint16_t *>(sO + L::OSOFF + lane * 2);
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)sc2, osc, row_ok && xo < W ? out_point(xo) * 2 : BUF_OOB, 0, 0);
             }
-            run_max = fmaxf(run_max, wmax);
         }
     }
-    if constexpr (P == DL_FP8 && !HEAD) flush_max();
 }
 
 // ------------------------------------------------------------- launchers
@@ -858,9 +914,11 @@ void pack_conv_weights(int C, int precision, const float *W, void *dst, float *s
                 }
         return;
     }
-    // FP8: per-output-channel scale s[o] = max|W[o]| / 448; codes of W * (448 / max|W[o]|);
-    // step m, block nb, lane (i, kq): 32 bytes = channels 32 hf .. 32 hf + 31 of
-    // tap t, where K chunk g = 4 m + kq is half hf = g mod HPT of tap t = g / HPT
+    // FP8: per-output-channel scale s[o] = max|W[o]| / 448; codes of W * (448 / max|W[o]|).
+    // K chunk g (32 values) is channels 32 hf .. 32 hf + 31 of tap t = g / HPT,
+    // hf = g mod HPT.  Step m, block nb, lane (i, kq): bytes 0-15 = 16-channel
+    // half kq & 1 of chunk 4 m + kq / 2, bytes 16-31 = the same half of chunk
+    // 4 m + 2 + kq / 2 (the MFMA's K order; see the kernel's FP8 loop)
     std::vector<float> inv(C);
     for (int oc = 0; oc < C; ++oc) {
         float mx = 0.f;
@@ -873,10 +931,13 @@ void pack_conv_weights(int C, int precision, const float *W, void *dst, float *s
     for (int m = 0; m < NIT; ++m)
         for (int nb = 0; nb < NB; ++nb)
             for (int lane = 0; lane < 64; ++lane) {
-                const int oc = nb * 16 + (lane & 15);
-                const int g = 4 * m + (lane >> 4), tap = g / HPT, hf = g % HPT;
+                // the MFMA's scale block b of step m is K chunk 4 m + b; its 32
+                // values are half kq & 1 of lane groups {0, 1} (b even) or
+                // {2, 3} (b odd), bytes 0-15 for b < 2 and 16-31 for b >= 2
+                const int oc = nb * 16 + (lane & 15), kq = lane >> 4;
                 for (int e = 0; e < 32; ++e) {
-                    const int c = hf * 32 + e;
+                    const int g = 4 * m + (e < 16 ? 0 : 2) + (kq >> 1), tap = g / HPT, hf = g % HPT;
+                    const int c = hf * 32 + 16 * (kq & 1) + (e & 15);
                     const float v = tap < 9 && c < C ? wt(oc, c, tap) : 0.f;
                     o[((size_t)(m * NB + nb) * 64 + lane) * 32 + e] = host_e4m3(v * inv[oc]);
                 }

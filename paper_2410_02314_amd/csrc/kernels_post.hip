@@ -11,13 +11,6 @@ namespace dloc {
 
 namespace {
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
 // ---------------------------------------------------------------- stem
 // x = (ADU - offset) * scale (scale = gain * in_scale), then
 // a = ReLU(b + sum_tap w * x) for C channels, 3x3, d = 1, zero padding,
@@ -25,36 +18,32 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 // batch's rows; a row is done in segments of SSEG pixels whose three input rows (preprocessed,
 // with a one-pixel zero border) are staged in LDS.  A thread item is one
 // 16-byte piece of a pixel's output (8 BF16 or 4 FP32 channels), so
-// consecutive threads store consecutive 16 bytes of the row.
+// consecutive threads store consecutive 16 bytes of the row.  In FP8 storage
+// a pixel has four 16-channel items in adjacent lanes (items past C idle):
+// each 32-channel group's max comes from its two items by one lane shuffle,
+// then each item stores its 16 e4m3 codes and the group's first item its
+// scale byte (region at scale_off).
 constexpr int SSEG = 1024;
 
-template <int C, bool BF16OUT>
+template <int C, int P>
 __global__ void __launch_bounds__(256)
 k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__restrict__ w,
-       const float *__restrict__ b, float offset, float scale, void *__restrict__ act,
-       uint32_t *__restrict__ amax, const uint8_t *__restrict__ keep, int radius)
+       const float *__restrict__ b, float offset, float scale, void *__restrict__ act, int64_t scale_off,
+       const uint8_t *__restrict__ keep, int radius)
 {
-    constexpr int CQ = BF16OUT ? 8 : 4;      // channels per item: one 16-byte store
-    constexpr int IPX = C / CQ;              // items per pixel
-    __shared__ float sw[C * 9];
-    __shared__ float sb[C];
+    constexpr int CQ = P == DL_FP8 ? 16 : P == DL_BF16 ? 8 : 4;   // channels per item
+    constexpr int IPX = P == DL_FP8 ? 4 : C / CQ;                  // items per pixel
+    static_assert(P != DL_FP8 || C <= 64, "FP8 stem: at most four 16-channel items");
+    constexpr int CP = IPX * CQ;             // channels the items cover (FP8: zero weights past C)
+    __shared__ __align__(16) float sw[9 * CP];      // tap-major: an item's channels are contiguous
+    __shared__ __align__(16) float sb[CP];
     __shared__ float sx[3][SSEG + 2];
     __shared__ bool sneed[SSEG / 64];
-    for (int i = threadIdx.x; i < C * 9; i += 256) sw[i] = w[i];
-    for (int i = threadIdx.x; i < C; i += 256) sb[i] = b[i];
-
-    // FP8: the max of what this wave stores, published once per frame change
-    // (outputs are >= 0, so float order is the unsigned order of the bits)
-    float run_max = 0.f;
-    int run_f = -1;
-    auto flush = [&]() {
-        if (amax && run_f >= 0) {
-            float v = run_max;
-            for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
-            if ((threadIdx.x & 63) == 0) atomicMax(amax + run_f, __float_as_uint(v));
-        }
-        run_max = 0.f;
-    };
+    for (int i = threadIdx.x; i < CP * 9; i += 256) {
+        const int t = i / CP, c = i - (i / CP) * CP;
+        sw[i] = c < C ? w[c * 9 + t] : 0.f;
+    }
+    for (int i = threadIdx.x; i < CP; i += 256) sb[i] = i < C ? b[i] : 0.f;
 
     // a contiguous range of rows per workgroup (mostly one frame)
     const int64_t per = (nrows + gridDim.x - 1) / gridDim.x;
@@ -64,10 +53,6 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__
         const FrameDesc &fd = fdp[f];
         const int y = (int)(row - fd.row_start);
         const int H = fd.h, W = fd.w;
-        if (f != run_f) {
-            flush();
-            run_f = f;
-        }
         // gated runs: only rows / 64-pixel segments within `radius` of a kept tile
         if (!near_kept(keep, fd, y, y, 0, W - 1, radius)) continue;
         for (int x0 = 0; x0 < W; x0 += SSEG) {
@@ -97,25 +82,34 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__
                 const int64_t base = (fd.act_off + (int64_t)y * W + x) * C + q * CQ;   // plain NHWC
                 float o[CQ];
 #pragma unroll
-                for (int k = 0; k < CQ; ++k) {
-                    const int c = q * CQ + k;
-                    float acc = sb[c];
+                for (int k = 0; k < CQ; ++k) o[k] = sb[q * CQ + k];
 #pragma unroll
-                    for (int t = 0; t < 9; ++t) acc = fmaf(sw[c * 9 + t], xin[t], acc);
-                    o[k] = fmaxf(acc, 0.f);
-                }
-                if constexpr (BF16OUT) {
-                    uint32_t bw[CQ];
+                for (int t = 0; t < 9; ++t)
 #pragma unroll
-                    for (int k = 0; k < CQ; ++k) {
-                        bw[k] = f32_to_bf16_rne(o[k]);
-                        run_max = fmaxf(run_max, __uint_as_float(bw[k] << 16));
+                    for (int k = 0; k < CQ; ++k) o[k] = fmaf(sw[t * CP + q * CQ + k], xin[t], o[k]);
+#pragma unroll
+                for (int k = 0; k < CQ; ++k) o[k] = fmaxf(o[k], 0.f);
+                if constexpr (P == DL_FP8) {
+                    // e4m3 codes under the group's power-of-two scale; the two
+                    // items of a group are lanes 2 g and 2 g + 1 of the pixel's four
+                    float m = 0.f;
+#pragma unroll
+                    for (int k = 0; k < CQ; ++k) m = fmaxf(m, o[k]);
+                    m = fmaxf(m, __shfl_xor(m, 1));
+                    const uint32_t sbyte = fp8_scale_byte(m);
+                    const float sv = fp8_scale_value(sbyte);
+                    if (q * CQ < C) {
+                        *reinterpret_cast<uint4 *>(static_cast<uint8_t *>(act) + base) =
+                            uint4{fp8_pack4(o[0], o[1], o[2], o[3], sv), fp8_pack4(o[4], o[5], o[6], o[7], sv),
+                                  fp8_pack4(o[8], o[9], o[10], o[11], sv), fp8_pack4(o[12], o[13], o[14], o[15], sv)};
+                        if ((q & 1) == 0) {
+                            const int64_t pt = fd.act_off + (int64_t)y * W + x;
+                            static_cast<uint8_t *>(act)[scale_off + 2 * pt + (q >> 1)] = (uint8_t)sbyte;
+                        }
                     }
-                    uint4 pk;
-                    pk.x = bw[0] | (bw[1] << 16);
-                    pk.y = bw[2] | (bw[3] << 16);
-                    pk.z = bw[4] | (bw[5] << 16);
-                    pk.w = bw[6] | (bw[7] << 16);
+                } else if constexpr (P == DL_BF16) {
+                    const uint4 pk{bf16_pack2(o[0], o[1]), bf16_pack2(o[2], o[3]), bf16_pack2(o[4], o[5]),
+                                   bf16_pack2(o[6], o[7])};
                     *reinterpret_cast<uint4 *>(static_cast<uint16_t *>(act) + base) = pk;
                 } else {
                     *reinterpret_cast<v4f *>(static_cast<float *>(act) + base) = v4f{o[0], o[1], o[2], o[3]};
@@ -123,20 +117,23 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__
             }
         }
     }
-    flush();
 }
 
 template <int C>
 hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const float *b, float offset,
-                  float scale, void *act, int bf16, uint32_t *amax, const uint8_t *keep, int radius, hipStream_t s)
+                  float scale, void *act, int precision, const uint8_t *keep, int radius, hipStream_t s)
 {
     const unsigned grid = (unsigned)std::min<int64_t>(g.total_rows, 8192);
-    if (bf16)
-        hipLaunchKernelGGL((k_stem<C, true>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
-                           scale, act, amax, keep, radius);
+    const int64_t soff = g.total_act * C;        // FP8: byte offset of the group scales
+    if (precision == DL_FP8)
+        hipLaunchKernelGGL((k_stem<C, DL_FP8>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
+                           scale, act, soff, keep, radius);
+    else if (precision == DL_BF16)
+        hipLaunchKernelGGL((k_stem<C, DL_BF16>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
+                           scale, act, soff, keep, radius);
     else
-        hipLaunchKernelGGL((k_stem<C, false>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
-                           scale, act, nullptr, keep, radius);
+        hipLaunchKernelGGL((k_stem<C, DL_FP32>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
+                           scale, act, soff, keep, radius);
     return hipGetLastError();
 }
 
@@ -379,14 +376,14 @@ hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uin
 }
 
 hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                       float offset, float scale, void *act, int act_bf16, uint32_t *amax, const uint8_t *keep,
+                       float offset, float scale, void *act, int precision, const uint8_t *keep,
                        int radius, hipStream_t s)
 {
     switch (C) {
-    case 16: return stem_c<16>(fd, g, w, b, offset, scale, act, act_bf16, amax, keep, radius, s);
-    case 32: return stem_c<32>(fd, g, w, b, offset, scale, act, act_bf16, amax, keep, radius, s);
-    case 48: return stem_c<48>(fd, g, w, b, offset, scale, act, act_bf16, amax, keep, radius, s);
-    case 64: return stem_c<64>(fd, g, w, b, offset, scale, act, act_bf16, amax, keep, radius, s);
+    case 16: return stem_c<16>(fd, g, w, b, offset, scale, act, precision, keep, radius, s);
+    case 32: return stem_c<32>(fd, g, w, b, offset, scale, act, precision, keep, radius, s);
+    case 48: return stem_c<48>(fd, g, w, b, offset, scale, act, precision, keep, radius, s);
+    case 64: return stem_c<64>(fd, g, w, b, offset, scale, act, precision, keep, radius, s);
     default: return hipErrorInvalidValue;
     }
 }

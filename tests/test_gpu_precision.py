@@ -102,9 +102,10 @@ def test_bf16_full_size_tiling_invariance_and_window():
 # ------------------------------------------------------------------ FP8
 @pytest.mark.parametrize("name,model,n,side", [("A", "tiny", 4, 128), ("B", "full", 2, 256)])
 def test_fp8_close_to_emulation_and_accuracy(name, model, n, side):
-    """FP8 e4m3 block convolutions (per-output-channel weight scales, per-frame
-    activation scales, FP32 accumulation) against the oracle's FP8 emulation and
-    the exact FP64 oracle."""
+    """FP8 e4m3 block convolutions (per-output-channel weight scales, stored
+    activations with one power-of-two scale per 32-channel group of each
+    pixel, FP32 accumulation) against the oracle's FP8 emulation and the exact
+    FP64 oracle."""
     spec, wts, net, frames = _setup("fp8", name, 1 if name == "A" else 2, 1001, n, side, side, model)
     got = gpu_maps(net, frames)
     emu = oracle.net_maps_batch(frames, spec, wts, quant="fp8")
@@ -122,7 +123,8 @@ def test_fp8_close_to_emulation_and_accuracy(name, model, n, side):
 
 
 def test_fp8_tiling_invariance():
-    """Activation scales are per frame, so the tile shape does not change FP8 results."""
+    """Activation scales are per pixel and channel group, so the tile shape does
+    not change FP8 results."""
     spec, wts, net, frames = _setup("fp8", "B", 2, 1002, n=2, h=320, w=448, model="full")
     net4 = dl.Net(S.serialize_weights(spec, wts), precision="fp8", tile_rows=4)
     assert np.array_equal(gpu_maps(net, frames), gpu_maps(net4, frames))

@@ -436,3 +436,38 @@ def test_adam_matches_torch():
         tt.grad = torch.from_numpy(g.copy())
         opt.step()
     assert np.allclose(theta, tt.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------------------------ FP8 storage
+def test_fp8_group_exponent_is_smallest_fitting_power_of_two():
+    r = rng(31)
+    vals = np.concatenate([r.lognormal(0, 3, 2000), [448.0, 448.0000001, 224.0, 1.0, 1.75, 1.7500001, 3.5e-30]])
+    for a in vals:
+        k = oracle.fp8_group_exp(a)
+        assert a <= 448.0 * 2.0 ** k and not a <= 448.0 * 2.0 ** (k - 1), (a, k)
+    assert oracle.fp8_group_exp(0.0) == -126
+
+
+def test_fp8_group_storage_brute_force():
+    r = rng(32)
+    C, n = 48, 300
+    a = np.abs(r.standard_normal((C, n))) * np.exp(r.uniform(-6, 6, n))[None, :]
+    got = oracle.store_fp8_groups(a)
+    b = a
+    for p in range(n):
+        for c0, c1 in ((0, 32), (32, 48)):
+            amax = np.max(np.abs(b[c0:c1, p]))
+            k = next(k for k in range(-140, 140) if amax <= 448.0 * 2.0 ** k)    # smallest fitting scale
+            k = max(k, -126)
+            expect = oracle.round_e4m3(b[c0:c1, p] / 2.0 ** k) * 2.0 ** k
+            assert np.array_equal(got[c0:c1, p], expect)
+            assert np.max(np.abs(got[c0:c1, p])) <= 448.0 * 2.0 ** k
+
+
+def test_fp8_group_storage_scale_invariant_and_exact_on_codes():
+    r = rng(33)
+    a = np.abs(r.standard_normal((40, 64)))
+    q = oracle.store_fp8_groups(a)
+    assert np.array_equal(oracle.store_fp8_groups(q), q)              # stored values are fixed points
+    assert np.array_equal(oracle.store_fp8_groups(a * 2.0 ** 9), q * 2.0 ** 9)   # power-of-two scaling commutes
+    assert np.max(np.abs(q - a) / np.maximum(np.abs(a), 1e-3)) < 0.07  # e4m3: 3 mantissa bits
