@@ -195,8 +195,17 @@ struct Lds {
     static constexpr int OSOFF = RSOFF + TC * 2;                       // FP8: output scales
     static constexpr int OWAVE = P == DL_FP32 ? 0 : P == DL_FP8 ? align16(OSOFF + TC * 2) : TC * OPX;
     static constexpr int OOFF = align16(SOFF + C * 4);
-    static constexpr int TOTAL = align16(OOFF + TR * OWAVE);
+    static constexpr int DOFF = align16(OOFF + TR * OWAVE);            // two decoded-tile slots
+    static constexpr int TOTAL = DOFF + 2 * 64;
     static constexpr bool FITS = TOTAL <= 160 * 1024;   // else no kernel exists for this shape
+};
+
+// a decoded tile: origin (y0, x0) and size of its frame, where its input
+// sits (point (ii, jj) of the tile is activation point a0 + ii rs + jj cs of
+// the frame), and the frame's map and activation offsets
+struct TileDec {
+    int y0, x0, h, w, a0, rs, cs;
+    int64_t px, act;
 };
 
 // --------------------------------------------------------------- kernel
@@ -270,58 +279,99 @@ k_conv(ConvArgs a, Geometry geo)
     // so offsets within the frame are 32-bit; loads go through a buffer
     // resource over the frame, and points off the frame take an out-of-range
     // offset, which reads as zero.
-    int nf = 0, nY0 = 0, nX0 = 0, nH = 0, nW = 0, nA0 = 0, nRS = 0, nCS = 0;
-    int64_t npx = 0, nact = 0;
-    auto fetch = [&](int64_t ti) {
+    TileDec n{};
+    auto decode = [&](int64_t ti) {
+        TileDec r;
         const int64_t t = a.list ? (int64_t)ld_const(a.list + ti) : ti;
-        nf = find_frame(a.fd, geo.nf, t, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
-        const FrameDesc *fd = a.fd + nf;     // fields read in place: tile_start is indexed by the block
-        nH = ld_const(&fd->h);
-        nW = ld_const(&fd->w);
-        npx = ld_const(&fd->px_off);
-        nact = ld_const(&fd->act_off);
-        decode_tile(nH, nW, t - ld_const(&fd->tile_start[blk]), dd, TR, TC, blk == geo.minor_blk, nY0, nX0);
+        const int f = find_frame(a.fd, geo.nf, t, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
+        const FrameDesc *fd = a.fd + f;      // fields read in place: tile_start is indexed by the block
+        r.h = ld_const(&fd->h);
+        r.w = ld_const(&fd->w);
+        r.px = ld_const(&fd->px_off);
+        r.act = ld_const(&fd->act_off);
+        decode_tile(r.h, r.w, t - ld_const(&fd->tile_start[blk]), dd, TR, TC, blk == geo.minor_blk, r.y0, r.x0);
         if (a.in_phase) {
-            const int hd = (nH + dd - 1) / dd, wd = (nW + dd - 1) / dd;
-            const int py = nY0 % dd, px = nX0 % dd;
-            nA0 = ((py * dd + px) * hd + nY0 / dd) * wd + nX0 / dd;
-            nRS = wd;
-            nCS = 1;
+            const int hd = (r.h + dd - 1) / dd, wd = (r.w + dd - 1) / dd;
+            const int py = r.y0 % dd, px = r.x0 % dd;
+            r.a0 = ((py * dd + px) * hd + r.y0 / dd) * wd + r.x0 / dd;
+            r.rs = wd;
+            r.cs = 1;
         } else {
-            nA0 = nY0 * nW + nX0;
-            nRS = dd * nW;
-            nCS = dd;
+            r.a0 = r.y0 * r.w + r.x0;
+            r.rs = dd * r.w;
+            r.cs = dd;
         }
+        return r;
+    };
+    // Wave 0 alone decodes tiles (the scalar unit is shared by the CU's
+    // waves): it publishes the tile after next in one of two LDS slots during
+    // its epilogue, and every wave picks it up after the next loop-top
+    // barrier.  A slot is rewritten only after every wave has passed the
+    // barrier that follows its last reading.
+    int *sdec = reinterpret_cast<int *>(sT + L::DOFF);
+    auto publish = [&](int sl, const TileDec &r) {
+        if (lane == 0) {
+            int4 *q = reinterpret_cast<int4 *>(sdec + 16 * sl);
+            q[0] = int4{r.y0, r.x0, r.h, r.w};
+            q[1] = int4{r.a0, r.rs, r.cs, 0};
+            q[2] = int4{(int)(uint32_t)r.px, (int)(r.px >> 32), (int)(uint32_t)r.act, (int)(r.act >> 32)};
+        }
+    };
+    auto pickup = [&](int sl) {
+        const int4 *q = reinterpret_cast<const int4 *>(sdec + 16 * sl);
+        const int4 u0 = q[0], u1 = q[1], u2 = q[2];
+        TileDec r;
+        r.y0 = __builtin_amdgcn_readfirstlane(u0.x);
+        r.x0 = __builtin_amdgcn_readfirstlane(u0.y);
+        r.h = __builtin_amdgcn_readfirstlane(u0.z);
+        r.w = __builtin_amdgcn_readfirstlane(u0.w);
+        r.a0 = __builtin_amdgcn_readfirstlane(u1.x);
+        r.rs = __builtin_amdgcn_readfirstlane(u1.y);
+        r.cs = __builtin_amdgcn_readfirstlane(u1.z);
+        r.px = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(u2.x) |
+               ((int64_t)__builtin_amdgcn_readfirstlane(u2.y) << 32);
+        r.act = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(u2.z) |
+                ((int64_t)__builtin_amdgcn_readfirstlane(u2.w) << 32);
+        return r;
+    };
+    // the tile's input into registers: point (ii, jj) of the tile is
+    // activation point a0 + ii rs + jj cs of the frame (off-frame points take
+    // an out-of-range offset and read zero)
+    auto issue = [&](const TileDec &r) {
         const __amdgpu_buffer_rsrc_t rin =
-            buf_rsrc(const_cast<char *>(static_cast<const char *>(a.in)) + nact * (C * SESZ), 0x7FFFFFFFu);
+            buf_rsrc(const_cast<char *>(static_cast<const char *>(a.in)) + r.act * (C * SESZ), 0x7FFFFFFFu);
 #pragma unroll
         for (int k = 0; k < NPF; ++k) {
             const int q0 = tid + k * NT;
             const int q = q0 < NQ ? q0 : NQ - 1;
             const int pt = q / SCH, ch = q - (q / SCH) * SCH;
             const int ii = pt / PW - 1, jj = pt - (pt / PW) * PW - 1;
-            const int y = nY0 + dd * ii, x = nX0 + dd * jj;
-            const bool ok = q0 < NQ && (unsigned)y < (unsigned)nH && (unsigned)x < (unsigned)nW;
+            const int y = r.y0 + dd * ii, x = r.x0 + dd * jj;
+            const bool ok = q0 < NQ && (unsigned)y < (unsigned)r.h && (unsigned)x < (unsigned)r.w;
             pf[k] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(
-                                                rin, ok ? (nA0 + ii * nRS + jj * nCS) * (C * SESZ) + ch * 16 : BUF_OOB, 0, 0));
+                                                rin, ok ? (r.a0 + ii * r.rs + jj * r.cs) * (C * SESZ) + ch * 16 : BUF_OOB, 0, 0));
         }
         if constexpr (P == DL_FP8) {
             const __amdgpu_buffer_rsrc_t rsc =
-                buf_rsrc(const_cast<char *>(static_cast<const char *>(a.in)) + sc_off + nact * 2, 0x7FFFFFFFu);
+                buf_rsrc(const_cast<char *>(static_cast<const char *>(a.in)) + sc_off + r.act * 2, 0x7FFFFFFFu);
 #pragma unroll
             for (int k = 0; k < NPS; ++k) {
                 const int pt0 = tid + k * NT;
                 const int pt = pt0 < NPT ? pt0 : NPT - 1;
                 const int ii = pt / PW - 1, jj = pt - (pt / PW) * PW - 1;
-                const int y = nY0 + dd * ii, x = nX0 + dd * jj;
-                const bool ok = pt0 < NPT && (unsigned)y < (unsigned)nH && (unsigned)x < (unsigned)nW;
-                psc[k] = __builtin_amdgcn_raw_buffer_load_b16(rsc, ok ? (nA0 + ii * nRS + jj * nCS) * 2 : BUF_OOB, 0, 0);
+                const int y = r.y0 + dd * ii, x = r.x0 + dd * jj;
+                const bool ok = pt0 < NPT && (unsigned)y < (unsigned)r.h && (unsigned)x < (unsigned)r.w;
+                psc[k] = __builtin_amdgcn_raw_buffer_load_b16(rsc, ok ? (r.a0 + ii * r.rs + jj * r.cs) * 2 : BUF_OOB, 0, 0);
             }
         }
     };
 
     int64_t ti = t0 + slot;
-    if (ti < t1) fetch(ti);
+    if (ti < t1) {
+        n = decode(ti);
+        issue(n);
+        if (wave == 0) publish(0, decode(ti + nslot < t1 ? ti + nslot : ti));
+    }
     // the first tile's data is waited for here, outside the loop: the
     // compiler's wait at the loop top then only has to cover the loop's own
     // path, where the previous tile's stores follow the loads
@@ -329,9 +379,9 @@ k_conv(ConvArgs a, Geometry geo)
     for (int k = 0; k < NPF; ++k) asm volatile("" : : "v"(pf[k]));
 #pragma unroll
     for (int k = 0; k < NPS; ++k) asm volatile("" : : "v"(psc[k]));
-    for (; ti < t1; ti += nslot) {
-        const int Y0 = nY0, X0 = nX0, H = nH, W = nW, A0 = nA0, RS = nRS, CS = nCS;
-        const int64_t px_off = npx, act = nact;
+    for (int par = 0; ti < t1; ti += nslot, par ^= 1) {
+        const int Y0 = n.y0, X0 = n.x0, H = n.h, W = n.w, A0 = n.a0, RS = n.rs, CS = n.cs;
+        const int64_t px_off = n.px, act = n.act;
 
         __syncthreads();   // the previous tile's LDS reads are done (and weights staged)
 #pragma unroll
@@ -424,9 +474,13 @@ k_conv(ConvArgs a, Geometry geo)
         // the prefetch and the wait for them stays exact.  FP32 with weights
         // in L2 (4-row tiles, no register room for that) skips the read.
         if constexpr (GW) {
-            if (ti + nslot < t1) fetch(ti + nslot);
+            if (ti + nslot < t1) {
+                n = pickup(par);
+                issue(n);
+            }
         } else {
-            fetch(ti + nslot < t1 ? ti + nslot : ti);
+            n = pickup(par);                 // the next tile, or this one again past the last
+            issue(n);
         }
         // keep the scheduler from sinking these loads below the MFMAs they
         // are meant to overlap
@@ -717,6 +771,12 @@ k_conv(ConvArgs a, Geometry geo)
                 const uint32_t sc2 = *reinterpret_cast<const uint16_t *>(sO + L::OSOFF + lane * 2);
                 __builtin_amdgcn_raw_buffer_store_b16((unsigned short)sc2, osc, row_ok && xo < W ? out_point(xo) * 2 : BUF_OOB, 0, 0);
             }
+        }
+        // wave 0: the tile the next iteration prefetches (or that tile again
+        // when it is the last), into the slot the next iteration reads
+        if (wave == 0 && ti + nslot < t1) {
+            const int64_t t2 = ti + 2 * nslot;
+            publish(par ^ 1, decode(t2 < t1 ? t2 : ti + nslot));
         }
     }
 }
