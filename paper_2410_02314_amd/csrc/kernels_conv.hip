@@ -495,6 +495,17 @@ k_conv(ConvArgs a, Geometry geo)
         // LDS address of lattice point (row wave + u, column 16 p + j + v) for tap (u, v), u, v in 0..2
         auto pt_addr = [&](int p, int tap) { return sT + ((wave + tap / 3) * PW + 16 * p + j + tap % 3) * PS; };
 
+        // Wave 0 decodes the tile the next iteration prefetches (or that tile
+        // again when it is the last) into the slot the next iteration reads.
+        // Each form calls this once per iteration inside its MFMA loop, where
+        // the other wave of the SIMD keeps the matrix unit busy while wave 0
+        // runs scalar code and waits for its descriptor loads.
+        auto ahead = [&]() {
+            if (wave == 0 && ti + nslot < t1) {
+                const int64_t t2 = ti + 2 * nslot;
+                publish(par ^ 1, decode(t2 < t1 ? t2 : ti + nslot));
+            }
+        };
         // FP32 with weights and tile in LDS and the register budget of two
         // waves per SIMD: the operands of K step it + 1 are read while the
         // MFMAs of step it run (the reads past the last step fetch step 0
@@ -519,6 +530,7 @@ k_conv(ConvArgs a, Geometry geo)
                 v4f an[NB], bn[PB];
                 operands(it + 1 < NIT ? it + 1 : 0, an, bn);
                 __builtin_amdgcn_sched_barrier(0);   // issued before this step's MFMAs
+                if (it == NIT / 2) ahead();
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -537,6 +549,7 @@ k_conv(ConvArgs a, Geometry geo)
             const v4f *sW = reinterpret_cast<const v4f *>(sT + L::WOFF);
 #pragma unroll 1
             for (int tap = 0; tap < 9; ++tap) {
+                if (tap == 4) ahead();
 #pragma unroll
                 for (int gg = 0; gg < G; ++gg) {
                     const int it = tap * G + gg;
@@ -569,6 +582,7 @@ k_conv(ConvArgs a, Geometry geo)
             const char *sW = sT + L::WOFF;
 #pragma unroll
             for (int m = 0; m < NIT; ++m) {
+                if (m == NIT / 2) ahead();
                 const int ch = 4 * m + kq;
                 const int tap = ch < NCH ? ch / CH8 : 4;          // padding chunks have zero weights
                 const int c0 = ch < NCH ? (ch - (ch / CH8) * CH8) * 8 : 0;
@@ -635,6 +649,7 @@ k_conv(ConvArgs a, Geometry geo)
                         acc[nb][p] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
                             av[nb], bv[p], acc[nb][p], 0, 0, 0, 0x7F7F7F7F, 0, sb[p]);
             }
+            ahead();                         // after the (not unrolled) K loop: no branch inside it
         }
 
         // epilogue: D row = output channel 16 nb + 4 kq + r, column = pixel j.
@@ -771,12 +786,6 @@ k_conv(ConvArgs a, Geometry geo)
                 const uint32_t sc2 = *reinterpret_cast<const uint16_t *>(sO + L::OSOFF + lane * 2);
                 __builtin_amdgcn_raw_buffer_store_b16((unsigned short)sc2, osc, row_ok && xo < W ? out_point(xo) * 2 : BUF_OOB, 0, 0);
             }
-        }
-        // wave 0: the tile the next iteration prefetches (or that tile again
-        // when it is the last), into the slot the next iteration reads
-        if (wave == 0 && ti + nslot < t1) {
-            const int64_t t2 = ti + 2 * nslot;
-            publish(par ^ 1, decode(t2 < t1 ? t2 : ti + nslot));
         }
     }
 }
