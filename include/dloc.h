@@ -55,6 +55,18 @@ typedef enum {
     DL_ERR_CAPACITY = -6       /* more emitters than the output capacity      */
 } dl_status;
 
+/* Arithmetic of the 3x3 block convolutions (preprocessing, stem, head,
+ * sigmoid and detection are FP32 in every form):
+ *   DL_FP32  FP32 weights, activations and accumulation (the exact form);
+ *   DL_BF16  BF16 weights and stored activations (round to nearest even),
+ *            FP32 accumulation, bias, residual and ReLU;
+ *   DL_FP8   OCP e4m3 weights with one scale per output channel, and stored
+ *            activations as e4m3 codes with one power-of-two scale per
+ *            32-channel group of each pixel; FP32 accumulation, bias,
+ *            residual and ReLU; the last block's output reaches the head
+ *            unrounded.
+ * None is part of the paper's method; they are the reduced-precision forms
+ * measured against the FP32 path. */
 typedef enum { DL_FP32 = 0, DL_BF16 = 1, DL_FP8 = 2 } dl_precision;
 
 /* flags */
