@@ -467,24 +467,33 @@ k_conv(ConvArgs a, Geometry geo)
                 }
             }
         };
-        if constexpr (EARLY_RES) load_res(0);
-        __builtin_amdgcn_sched_barrier(0);   // residual loads stay ahead of the prefetch
-        // the next tile's input.  Past the last tile the current one is read
-        // again (and not used), so no branch separates the residual loads from
-        // the prefetch and the wait for them stays exact.  FP32 with weights
-        // in L2 (4-row tiles, no register room for that) skips the read.
-        if constexpr (GW) {
-            if (ti + nslot < t1) {
-                n = pickup(par);
+        // FP32 with weights and tile in LDS and the register budget of two
+        // waves per SIMD (see its MFMA loop below)
+        constexpr bool PREF = P == DL_FP32 && !GW && min_waves<P, TR_>() == 2;
+        // the residual (early forms) and the next tile's input.  Past the
+        // last tile the current one is read again (and not used), so no branch
+        // separates the residual loads from the prefetch and the wait for them
+        // stays exact.  FP32 with weights in L2 (4-row tiles, no register room
+        // for that) skips the read.  PREF issues these after the first K step's
+        // MFMAs, so the matrix unit works while they go out; the other forms
+        // issue them before their K loop.
+        auto pre_loads = [&]() {
+            if constexpr (EARLY_RES) load_res(0);
+            __builtin_amdgcn_sched_barrier(0);   // residual loads stay ahead of the prefetch
+            if constexpr (GW) {
+                if (ti + nslot < t1) {
+                    n = pickup(par);
+                    issue(n);
+                }
+            } else {
+                n = pickup(par);                 // the next tile, or this one again past the last
                 issue(n);
             }
-        } else {
-            n = pickup(par);                 // the next tile, or this one again past the last
-            issue(n);
-        }
-        // keep the scheduler from sinking these loads below the MFMAs they
-        // are meant to overlap
-        __builtin_amdgcn_sched_barrier(0);
+            // keep the scheduler from sinking these loads below the MFMAs they
+            // are meant to overlap
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        if constexpr (!PREF) pre_loads();
 
 
         v4f acc[NB][PB];
@@ -506,12 +515,9 @@ k_conv(ConvArgs a, Geometry geo)
                 publish(par ^ 1, decode(t2 < t1 ? t2 : ti + nslot));
             }
         };
-        // FP32 with weights and tile in LDS and the register budget of two
-        // waves per SIMD: the operands of K step it + 1 are read while the
-        // MFMAs of step it run (the reads past the last step fetch step 0
-        // again and are not used), so the MFMAs wait only for reads issued one
-        // step earlier
-        constexpr bool PREF = P == DL_FP32 && !GW && min_waves<P, TR_>() == 2;
+        // PREF: the operands of K step it + 1 are read while the MFMAs of step
+        // it run (the reads past the last step fetch step 0 again and are not
+        // used), so the MFMAs wait only for reads issued one step earlier
         if constexpr (PREF) {
             constexpr int G = C / 16, NIT = KPlan<C, P>::NIT;
             const v4f *sW = reinterpret_cast<const v4f *>(sT + L::WOFF);
@@ -538,6 +544,7 @@ k_conv(ConvArgs a, Geometry geo)
 #pragma unroll
                         for (int p = 0; p < PB; ++p)
                             acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[nb][s], bv[p][s], acc[nb][p], 0, 0, 0);
+                if (it == 0) pre_loads();
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) aw[nb] = an[nb];
 #pragma unroll
