@@ -123,6 +123,7 @@ def main():
         cpu, ref = cpu_baseline(args, spec, w, frames, head["net"], dev, head["records"])
         for f, r in results.items():
             r["accuracy_vs_oracle"] = accuracy_on_sample(r["records"], ref)
+            r["accuracy_vs_oracle"].update(map_errors_on_sample(r["net"], d_frames, ref, torch, dev))
 
     def public(r):
         return {k: v for k, v in r.items() if k not in ("net", "records")}
@@ -247,6 +248,25 @@ def accuracy_on_sample(recs, ref):
     return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in m.items()}
 
 
+def map_errors_on_sample(net, d_frames, ref, torch, dev):
+    """The form's maps of frame 0 against the FP64 oracle's on the region where
+    the oracle's maps are exact: max and RMS absolute logit error, RMS error of
+    the dx, dy (px) and dz (units of the dz map) planes."""
+    side = d_frames.shape[1]
+    maps = torch.empty((1, 5, side, d_frames.shape[2]), dtype=torch.float32, device=dev)
+    net.maps_device(d_frames[:1], maps)
+    torch.cuda.synchronize()
+    e = ref["map_extent"]
+    g = maps[0, :, :e, :e].cpu().numpy().astype(np.float64)
+    d = g - ref["maps"]
+    return {"max_logit_err": round(float(np.max(np.abs(d[0]))), 6),
+            "rms_logit_err": round(float(np.sqrt(np.mean(d[0] ** 2))), 6),
+            "rms_dx_map_err_px": round(float(np.sqrt(np.mean(d[1] ** 2))), 6),
+            "rms_dy_map_err_px": round(float(np.sqrt(np.mean(d[2] ** 2))), 6),
+            "rms_dz_map_err": round(float(np.sqrt(np.mean(d[3] ** 2))), 6),
+            "map_region": f"{e}x{e}"}
+
+
 def conv_source_sha256():
     """Hash of the sources that decide the conv kernel's memory traffic (the
     kernel and the tile order / layouts it includes)."""
@@ -305,7 +325,7 @@ def cpu_baseline(args, spec, w, frames, net, dev, recs):
     mism = int(np.sum((ref_det != got_det) & ~ex))
     matched = int(np.sum(ref_det & got_det))
     rsel = (rec["row"] < lim) & (rec["col"] < lim)
-    ref = {"records": rec[rsel], "limit": lim}
+    ref = {"records": rec[rsel], "limit": lim, "maps": ref_maps[0, :, :e, :e], "map_extent": e}
     what = "frame 0" if whole else f"frame 0 crop {s}x{s}"
     return {"value": round(s * s / dt / 1e6, 4), "unit": "Mpixel/s", "cores": cpu_threads(), "kind": "oracle",
             "sample": f"{what} of the same workload, FP64 oracle (net + detection + records), {dt:.1f} s",
