@@ -174,10 +174,15 @@ int dl_localize(dl_net *net, const uint16_t *frames, int n, int h, int w,
 
 /* Pipelined host localization of `nbatch` consecutive batches of n frames
  * (frames host uint16 [nbatch][n][h][w]): batch k+1 is copied host->device on
- * a side stream while batch k is processed (Sec. 2.2 preloading and
+ * a side stream while batch k is processed, and the records of batch k are
+ * copied back while batch k+1 is processed (Sec. 2.2 preloading and
  * pipelining).  Records of all batches are concatenated in order, with
- * `frame` counted across batches.  overlap = 0 runs copy and compute
- * serially (the reference workflow, for comparison). */
+ * `frame` counted across batches.  overlap = 0 copies, processes and collects
+ * each batch before the next starts (the serial workflow, for comparison).
+ * The handle keeps two device frame slots of n*h*w*2 bytes, two record slots
+ * of min(cap, n*h*w) records and, for unpinned frames, two pinned staging
+ * slots; they grow to the largest call and are freed by dl_destroy_net.
+ * Synchronous; returns DL_ERR_CAPACITY as dl_localize does. */
 int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w,
                           int overlap, dl_emitter *out, size_t cap, size_t *count);
 

@@ -73,6 +73,17 @@ struct dl_net {
     struct Ev { int stage; hipEvent_t a, b; };
     std::vector<Ev> prof_pending;
     std::vector<hipEvent_t> ev_pool;
+
+    // host-frame pipeline (dl_localize, dl_localize_pipelined): two slots of
+    // frames, pinned staging, records and counts; grow-only, freed with the net
+    uint16_t *pl_frames[2] = {};
+    uint16_t *pl_stage[2] = {};
+    dl_emitter *pl_out[2] = {};
+    uint32_t *pl_dcounts = nullptr;   // device [2][n + 1]
+    uint32_t *pl_hcounts = nullptr;   // pinned [2][n + 1]
+    size_t pl_frame_bytes = 0, pl_stage_bytes = 0, pl_out_cap = 0;
+    int pl_counts_n = 0;
+    hipEvent_t pl_copied[2] = {}, pl_used[2] = {}, pl_counted[2] = {};
 };
 
 namespace {
@@ -759,6 +770,15 @@ void dl_destroy_net(dl_net *net)
     if (net->d_desc) (void)hipFree(net->d_desc);
     for (int i = 0; i < DESC_SLOTS; ++i)
         if (net->desc_ev[i]) (void)hipEventDestroy(net->desc_ev[i]);
+    for (int i = 0; i < 2; ++i) {
+        if (net->pl_frames[i]) (void)hipFree(net->pl_frames[i]);
+        if (net->pl_stage[i]) (void)hipHostFree(net->pl_stage[i]);
+        if (net->pl_out[i]) (void)hipFree(net->pl_out[i]);
+        for (hipEvent_t e : {net->pl_copied[i], net->pl_used[i], net->pl_counted[i]})
+            if (e) (void)hipEventDestroy(e);
+    }
+    if (net->pl_dcounts) (void)hipFree(net->pl_dcounts);
+    if (net->pl_hcounts) (void)hipHostFree(net->pl_hcounts);
     if (net->copy_stream) (void)hipStreamDestroy(net->copy_stream);
     if (net->compute_stream) (void)hipStreamDestroy(net->compute_stream);
     delete net;
@@ -894,6 +914,74 @@ static bool is_pinned(const void *p)
     return at.type == hipMemoryTypeHost;
 }
 
+// Grow the pipeline's slot buffers to hold batches of `fbytes` frame bytes,
+// `out_cap` records and n + 1 counts.  Waits for all work on the device before
+// it frees anything.
+static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_cap, int n)
+{
+    const bool grow = fbytes > net->pl_frame_bytes || (staged && fbytes > net->pl_stage_bytes) ||
+                      out_cap > net->pl_out_cap || n + 1 > net->pl_counts_n;
+    if (!grow && net->pl_copied[0]) return DL_OK;
+    HIPCHK(net, hipDeviceSynchronize());
+    for (int i = 0; i < 2; ++i) {
+        if (!net->pl_copied[i]) {
+            HIPCHK(net, hipEventCreateWithFlags(&net->pl_copied[i], hipEventDisableTiming));
+            HIPCHK(net, hipEventCreateWithFlags(&net->pl_used[i], hipEventDisableTiming));
+            HIPCHK(net, hipEventCreateWithFlags(&net->pl_counted[i], hipEventDisableTiming));
+        }
+    }
+    if (fbytes > net->pl_frame_bytes) {
+        for (auto &p : net->pl_frames) {
+            if (p) HIPCHK(net, hipFree(p));
+            p = nullptr;
+        }
+        net->pl_frame_bytes = 0;
+        for (auto &p : net->pl_frames)
+            if (hipMalloc(&p, fbytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(net, DL_ERR_OOM, "hipMalloc(%zu) for a frame slot failed", fbytes);
+            }
+        net->pl_frame_bytes = fbytes;
+    }
+    if (staged && fbytes > net->pl_stage_bytes) {
+        for (auto &p : net->pl_stage) {
+            if (p) HIPCHK(net, hipHostFree(p));
+            p = nullptr;
+        }
+        net->pl_stage_bytes = 0;
+        for (auto &p : net->pl_stage)
+            if (hipHostMalloc((void **)&p, fbytes, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(net, DL_ERR_OOM, "hipHostMalloc(%zu) for a staging slot failed", fbytes);
+            }
+        net->pl_stage_bytes = fbytes;
+    }
+    if (out_cap > net->pl_out_cap) {
+        for (auto &p : net->pl_out) {
+            if (p) HIPCHK(net, hipFree(p));
+            p = nullptr;
+        }
+        net->pl_out_cap = 0;
+        for (auto &p : net->pl_out)
+            if (hipMalloc(&p, out_cap * sizeof(dl_emitter)) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(net, DL_ERR_OOM, "hipMalloc for %zu records failed", out_cap);
+            }
+        net->pl_out_cap = out_cap;
+    }
+    if (n + 1 > net->pl_counts_n) {
+        if (net->pl_dcounts) HIPCHK(net, hipFree(net->pl_dcounts));
+        if (net->pl_hcounts) HIPCHK(net, hipHostFree(net->pl_hcounts));
+        net->pl_dcounts = nullptr;
+        net->pl_hcounts = nullptr;
+        net->pl_counts_n = 0;
+        HIPCHK(net, hipMalloc(&net->pl_dcounts, (size_t)2 * (n + 1) * 4));
+        HIPCHK(net, hipHostMalloc((void **)&net->pl_hcounts, (size_t)2 * (n + 1) * 4, hipHostMallocDefault));
+        net->pl_counts_n = n + 1;
+    }
+    return DL_OK;
+}
+
 int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w, int overlap,
                           dl_emitter *out, size_t cap, size_t *count)
 {
@@ -906,82 +994,84 @@ int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n
     *count = 0;
     const size_t fbytes = (size_t)n * h * w * 2;
     const bool pinned = is_pinned(frames);
-    // two device frame buffers + two pinned staging buffers (when needed),
-    // device outputs per batch
-    uint16_t *d_frames[2] = {nullptr, nullptr};
-    uint16_t *h_stage[2] = {nullptr, nullptr};
-    dl_emitter *d_out = nullptr;
-    uint32_t *d_counts = nullptr;
-    hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_used[2] = {nullptr, nullptr};
-    const size_t cap_dev = std::max<size_t>(cap, 1);
-    std::vector<uint32_t> h_counts((size_t)(n + 1) * nbatch);
+    // a batch yields at most one record per pixel
+    const size_t slot_cap = std::max<size_t>(1, std::min<size_t>(cap, (size_t)n * h * w));
+    if ((rc = ensure_pipeline(net, fbytes, !pinned, slot_cap, n))) return rc;
+
+    // Slot k & 1 holds batch k's frames, records and counts.  With overlap the
+    // copy of batch k (copy stream) waits on the device for the compute that
+    // last read its slot, the compute of batch k waits for that copy, and the
+    // host collects batch k - 1 only after batch k is queued, so the compute
+    // stream never waits for the host.  Without overlap every batch is copied,
+    // processed and collected before the next one starts.
+    hipStream_t cs = net->compute_stream, xs = overlap ? net->copy_stream : net->compute_stream;
+    const size_t cn = (size_t)n + 1;
+    size_t written = 0;        // records copied to `out` so far
+    size_t total = 0;
     int result = DL_OK;
-    auto cleanup = [&]() {
-        (void)hipDeviceSynchronize();
-        for (int i = 0; i < 2; ++i) {
-            if (d_frames[i]) (void)hipFree(d_frames[i]);
-            if (h_stage[i]) (void)hipHostFree(h_stage[i]);
-            if (ev_copied[i]) (void)hipEventDestroy(ev_copied[i]);
-            if (ev_used[i]) (void)hipEventDestroy(ev_used[i]);
-        }
-        if (d_out) (void)hipFree(d_out);
-        if (d_counts) (void)hipFree(d_counts);
+    auto drain = [&]() {
+        (void)hipStreamSynchronize(cs);
+        (void)hipStreamSynchronize(xs);
     };
 #define PCHK(expr)                                                                                  \
     do {                                                                                            \
         hipError_t e_ = (expr);                                                                     \
         if (e_ != hipSuccess) {                                                                     \
             result = fail(net, DL_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
-            cleanup();                                                                              \
+            drain();                                                                                \
             return result;                                                                          \
         }                                                                                           \
     } while (0)
-    for (int i = 0; i < 2; ++i) {
-        PCHK(hipMalloc(&d_frames[i], fbytes));
-        if (!pinned) PCHK(hipHostMalloc((void **)&h_stage[i], fbytes, hipHostMallocDefault));
-        PCHK(hipEventCreateWithFlags(&ev_copied[i], hipEventDisableTiming));
-        PCHK(hipEventCreateWithFlags(&ev_used[i], hipEventDisableTiming));
-    }
-    PCHK(hipMalloc(&d_out, cap_dev * sizeof(dl_emitter)));
-    PCHK(hipMalloc(&d_counts, h_counts.size() * 4));
-    hipStream_t cs = net->compute_stream, xs = overlap ? net->copy_stream : net->compute_stream;
-    size_t written = 0;
-    uint32_t *hc = h_counts.data();
-    std::vector<dl_emitter> tmp;
-    for (int k = 0; k < nbatch; ++k) {
-        const int buf = k & 1;
-        const uint16_t *src = frames + (size_t)k * n * h * w;
-        PCHK(hipEventSynchronize(ev_used[buf]));     // the compute that read this buffer is done
-        if (!pinned) {
-            std::memcpy(h_stage[buf], src, fbytes);
-            src = h_stage[buf];
-        }
-        PCHK(hipMemcpyAsync(d_frames[buf], src, fbytes, hipMemcpyHostToDevice, xs));
-        PCHK(hipEventRecord(ev_copied[buf], xs));
-        PCHK(hipStreamWaitEvent(cs, ev_copied[buf], 0));
-        std::vector<FrameDesc> fd;
-        Geometry g;
-        uniform_geometry(net, d_frames[buf], n, h, w, fd, g);
-        const size_t room = written < cap ? cap - written : 0;
-        rc = localize_geom(net, fd, g, cs, room ? d_out : nullptr, room, d_counts + (size_t)k * (n + 1), nullptr,
-                           d_frames[buf], n, h, w);
-        if (rc) { cleanup(); return rc; }
-        PCHK(hipEventRecord(ev_used[buf], cs));
-        // results of this batch: counts then records (compute stream order)
-        PCHK(hipMemcpyAsync(hc + (size_t)k * (n + 1), d_counts + (size_t)k * (n + 1), (n + 1) * 4, hipMemcpyDeviceToHost, cs));
-        PCHK(hipStreamSynchronize(cs));
-        const uint32_t tot = hc[(size_t)k * (n + 1) + n];
-        const size_t take = std::min<size_t>(tot, room);
+    // Copy batch j's records to the host: the counts are in pinned memory once
+    // its compute has finished; the first min(total, room) records are the
+    // same whatever room the kernels were given (they are placed by prefix).
+    auto collect = [&](int j) -> int {
+        const int sl = j & 1;
+        PCHK(hipEventSynchronize(net->pl_counted[sl]));
+        const uint32_t tot = net->pl_hcounts[sl * cn + n];
+        const size_t take = std::min<size_t>(tot, cap - written);
         if (take) {
-            PCHK(hipMemcpy(out + written, d_out, take * sizeof(dl_emitter), hipMemcpyDeviceToHost));
-            for (size_t r = 0; r < take; ++r) out[written + r].frame += k * n;
+            PCHK(hipMemcpyAsync(out + written, net->pl_out[sl], take * sizeof(dl_emitter), hipMemcpyDeviceToHost, xs));
+            PCHK(hipStreamSynchronize(xs));
+            for (size_t r = 0; r < take; ++r) out[written + r].frame += j * n;
         }
         written += take;
-        *count += tot;
+        total += tot;
+        return DL_OK;
+    };
+    for (int k = 0; k < nbatch; ++k) {
+        const int sl = k & 1;
+        const uint16_t *src = frames + (size_t)k * n * h * w;
+        if (!pinned) {
+            PCHK(hipEventSynchronize(net->pl_copied[sl]));   // batch k - 2's copy out of this stage is done
+            std::memcpy(net->pl_stage[sl], src, fbytes);
+            src = net->pl_stage[sl];
+        }
+        if (xs != cs) PCHK(hipStreamWaitEvent(xs, net->pl_used[sl], 0));
+        PCHK(hipMemcpyAsync(net->pl_frames[sl], src, fbytes, hipMemcpyHostToDevice, xs));
+        PCHK(hipEventRecord(net->pl_copied[sl], xs));
+        if (xs != cs) PCHK(hipStreamWaitEvent(cs, net->pl_copied[sl], 0));
+        std::vector<FrameDesc> fd;
+        Geometry g;
+        uniform_geometry(net, net->pl_frames[sl], n, h, w, fd, g);
+        // an upper bound on the room left: batches not yet collected take none
+        const size_t room = std::min(slot_cap, cap - std::min(cap, written));
+        rc = localize_geom(net, fd, g, cs, room ? net->pl_out[sl] : nullptr, room, net->pl_dcounts + sl * cn,
+                           nullptr, net->pl_frames[sl], n, h, w);
+        if (rc) { drain(); return rc; }
+        PCHK(hipEventRecord(net->pl_used[sl], cs));
+        PCHK(hipMemcpyAsync(net->pl_hcounts + sl * cn, net->pl_dcounts + sl * cn, cn * 4, hipMemcpyDeviceToHost, cs));
+        PCHK(hipEventRecord(net->pl_counted[sl], cs));
+        if (!overlap) {
+            if ((rc = collect(k))) return rc;
+        } else if (k > 0) {
+            if ((rc = collect(k - 1))) return rc;
+        }
     }
-    cleanup();
+    if (overlap && (rc = collect(nbatch - 1))) return rc;
 #undef PCHK
-    if (*count > cap) return fail(net, DL_ERR_CAPACITY, "%zu emitters exceed capacity %zu", *count, cap);
+    *count = total;
+    if (total > cap) return fail(net, DL_ERR_CAPACITY, "%zu emitters exceed capacity %zu", total, cap);
     return DL_OK;
 }
 

@@ -65,3 +65,41 @@ def test_host_capacity_protocol():
     rc = dl.lib().dl_localize(net.handle, F.ctypes.data, 2, 128, 128, out.ctypes.data, 5, ctypes.byref(cnt))
     assert rc == dl.DL_ERR_CAPACITY and cnt.value == len(full)
     assert np.array_equal(out, full[:5])
+
+
+@pytest.mark.parametrize("overlap", [1, 0])
+def test_pipelined_capacity_inside_a_later_batch(overlap):
+    """The capacity runs out inside batch 2 while batch 1 is still being
+    collected (overlap on): the first `cap` records and the total count are
+    those of the uncapped call."""
+    spec, w = S.make_net("A", 1)
+    net = dl.Net(S.serialize_weights(spec, w))
+    frames = S.render_frames(6, 128, 192, "tiny", 64).reshape(3, 2, 128, 192)
+    full = net.localize_pipelined(frames, overlap=bool(overlap))
+    per = [len(net.localize(frames[k])) for k in range(3)]
+    assert sum(per) == len(full) and per[0] > 0 and per[2] > 1
+    cap = per[0] + per[1] + per[2] // 2
+    out = np.empty(cap, dl.EMITTER_DTYPE)
+    cnt = ctypes.c_size_t()
+    F = np.ascontiguousarray(frames)
+    rc = dl.lib().dl_localize_pipelined(net.handle, F.ctypes.data, 3, 2, 128, 192, overlap, out.ctypes.data,
+                                        cap, ctypes.byref(cnt))
+    assert rc == dl.DL_ERR_CAPACITY and cnt.value == len(full)
+    assert np.array_equal(out, full[:cap])
+
+
+def test_pipelined_slots_grow_then_serve_smaller_batches():
+    """The handle's frame and record slots grow for a larger call and are
+    reused by a smaller one; each call equals its own device-path result."""
+    spec, w = S.make_net("A", 1)
+    net = dl.Net(S.serialize_weights(spec, w))
+    for n, h, wd, seed in ((1, 96, 128, 65), (3, 256, 320, 66), (2, 64, 80, 67)):
+        frames = S.render_frames(2 * n, h, wd, "tiny", seed).reshape(2, n, h, wd)
+        ref = []
+        for k in range(2):
+            r, _ = gpu_localize(net, frames[k])
+            r = r.copy()
+            r["frame"] += n * k
+            ref.append(r)
+        got = net.localize_pipelined(frames, overlap=True)
+        assert np.array_equal(got, np.concatenate(ref)), (n, h, wd)
