@@ -99,10 +99,20 @@ def rois(args, S):
     conv_ms, conv_n = prof["conv"]
     flop = 2.0 * 9 * spec.C * spec.C * px
     ach = flop / (conv_ms / conv_n * 1e-3) / 1e12
-    _line(args, px / (ms * 1e-3) / 1e6, ms,
+    # load balance: the same net on a uniform batch of about the same pixel
+    # count (16 x 2048^2 frames of the same emitter model) in one launch per layer
+    uni = S.render_frames(16, 2048, 2048, "rois", 1004, workers=args.gen_workers or None)
+    d_uni = torch.from_numpy(uni).to(dev)
+    u_out = torch.empty((uni.size // 32, 8), dtype=torch.int32, device=dev)
+    u_counts = torch.zeros(17, dtype=torch.int32, device=dev)
+    ms_uni = _timed(lambda: net.localize_device(d_uni, u_out, u_counts, st), args.steps, args.warmup, st)
+    mpx, mpx_uni = px / (ms * 1e-3) / 1e6, uni.size / (ms_uni * 1e-3) / 1e6
+    del d_uni, u_out
+    _line(args, mpx, ms,
           {"workload": f"256 uneven ROIs (sides 128..1024), {px / 1e6:.1f} Mpx, net A", "net": "A",
            "precision": args.precision, "frames": 256, "pixels": px},
           {"graph_ms_per_step": round(ms_graph, 3), "emitters_per_step": int(counts[256].item()),
+           "uniform_16x2048sq_mpx_s": round(mpx_uni, 2), "load_balance_efficiency": round(mpx / mpx_uni, 4),
            "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAKS[args.precision],
                         "unit": "TFLOP/s", "frac": round(ach / PEAKS[args.precision], 4), "traffic": None}})
     g.close()

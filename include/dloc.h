@@ -304,6 +304,21 @@ int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int 
 int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, float tau,
                     void *stream, uint8_t *d_det);
 
+/* ---- measured ceilings ----
+ * Sustained rates of the current device, quoted beside the published peaks
+ * in rooflines.  what:
+ *   DL_RATE_MFMA_FP32 / _BF16 / _FP8  dense MFMA rate in TFLOP/s: every SIMD
+ *       runs register-resident chains of the MFMA each form's convolution
+ *       uses (16x16x4 f32, 16x16x32 bf16, 16x16x128 scaled e4m3); `bytes`
+ *       is ignored;
+ *   DL_RATE_HBM_COPY  GB/s read plus written by a device-to-device copy
+ *       kernel of `bytes` (a multiple of 16) each way.
+ * *value = the best of `reps` timed launches (after one untimed launch).
+ * Synchronous; allocates and frees its own buffers and stream.  Returns
+ * DL_ERR_INVALID_ARG or DL_ERR_DEVICE; no handle records the text. */
+enum { DL_RATE_MFMA_FP32 = 0, DL_RATE_MFMA_BF16 = 1, DL_RATE_MFMA_FP8 = 2, DL_RATE_HBM_COPY = 3 };
+int dl_measure_rate(int what, size_t bytes, int reps, double *value);
+
 #ifdef __cplusplus
 }
 #endif

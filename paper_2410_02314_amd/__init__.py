@@ -87,6 +87,7 @@ def _load():
         "dl_localize_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P, Z, P]),
         "dl_maps_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P]),
         "dl_host_alloc": (I, [Z, ctypes.POINTER(P)]),
+        "dl_measure_rate": (I, [I, Z, I, ctypes.POINTER(ctypes.c_double)]),
         "dl_host_free": (None, [P]),
         "dl_debug_conv_layer": (I, [P, P, P, I, I, I, I, I, P, P]),
         "dl_debug_detect": (I, [P, P, I, I, I, ctypes.c_float, P, P]),
@@ -397,3 +398,14 @@ def host_alloc(nbytes: int) -> int:
 
 def host_free(p: int):
     _lib.dl_host_free(p)
+
+
+RATE_KINDS = {"fp32": 0, "bf16": 1, "fp8": 2, "hbm_copy": 3}
+
+
+def measure_rate(kind: str, nbytes: int = 1 << 30, reps: int = 3) -> float:
+    """Sustained rate of the current device: dense MFMA TFLOP/s of a form
+    ("fp32", "bf16", "fp8") or device copy GB/s ("hbm_copy", read + written)."""
+    v = ctypes.c_double()
+    _check(_lib.dl_measure_rate(RATE_KINDS[kind], nbytes, reps, ctypes.byref(v)))
+    return v.value

@@ -1,0 +1,146 @@
+// Sustained-rate probes of the current device: the dense MFMA rate of each
+// precision form and the device-to-device copy bandwidth.  Rooflines are
+// quoted against the published peaks; these measured rates sit beside them,
+// as the ceiling a kernel can reach at the clock the chip holds under load.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "dloc.h"
+
+namespace {
+
+typedef float rp_f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 rp_bf8 __attribute__((ext_vector_type(8)));
+typedef int rp_i8 __attribute__((ext_vector_type(8)));
+
+constexpr int RP_CHAINS = 4;      // independent accumulators per wave
+constexpr int RP_THREADS = 256;   // four waves per workgroup
+
+// Each wave runs RP_CHAINS independent MFMA accumulation chains of `iters`
+// steps on register operands: no memory traffic, so the launch measures the
+// matrix units alone.  `flag` is 0 at run time; the store it guards keeps the
+// chains live.
+template <int KIND>
+__global__ __launch_bounds__(RP_THREADS) void k_mfma_rate(int iters, int flag, float *sink)
+{
+    const int t = threadIdx.x;
+    rp_f4 acc[RP_CHAINS];
+#pragma unroll
+    for (int c = 0; c < RP_CHAINS; ++c) acc[c] = rp_f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (KIND == DL_FP32) {
+        const float a = 1e-3f * (t & 7), b = 1e-3f * ((t >> 3) & 7);
+        for (int i = 0; i < iters; ++i)
+#pragma unroll
+            for (int c = 0; c < RP_CHAINS; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+    } else if constexpr (KIND == DL_BF16) {
+        rp_bf8 a, b;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a[k] = (__bf16)(1e-3f * ((t + k) & 7));
+            b[k] = (__bf16)(1e-3f * ((t >> 3) + k & 7));
+        }
+        for (int i = 0; i < iters; ++i)
+#pragma unroll
+            for (int c = 0; c < RP_CHAINS; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+    } else {
+        // e4m3 codes 0x30 (0.25) and 0x28 (0.125); unit E8M0 block scales (127)
+        rp_i8 a, b;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a[k] = 0x30303030 ^ ((t & 1) << k);
+            b[k] = 0x28282828;
+        }
+        for (int i = 0; i < iters; ++i)
+#pragma unroll
+            for (int c = 0; c < RP_CHAINS; ++c)
+                acc[c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[c], 0, 0, 0, 0x7F7F7F7F, 0,
+                                                                          0x7F7F7F7F);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < RP_CHAINS; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    if (flag) sink[blockIdx.x * RP_THREADS + t] = s;
+}
+
+// Plain grid-stride copy of n 16-byte words.
+__global__ __launch_bounds__(RP_THREADS) void k_copy_rate(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                          size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * RP_THREADS;
+    for (size_t i = (size_t)blockIdx.x * RP_THREADS + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+extern "C" int dl_measure_rate(int what, size_t bytes, int reps, double *value)
+{
+    if (!value || reps <= 0) return DL_ERR_INVALID_ARG;
+    if (what < DL_RATE_MFMA_FP32 || what > DL_RATE_HBM_COPY) return DL_ERR_INVALID_ARG;
+    if (what == DL_RATE_HBM_COPY && (bytes < 16 || bytes % 16)) return DL_ERR_INVALID_ARG;
+    *value = 0.0;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return DL_ERR_DEVICE;
+    const int blocks = prop.multiProcessorCount * 4;   // sixteen waves per CU
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    void *a = nullptr, *b = nullptr;
+    int rc = DL_OK;
+    auto ok = [&](hipError_t e) {
+        if (e != hipSuccess && rc == DL_OK) rc = DL_ERR_DEVICE;
+        return rc == DL_OK;
+    };
+    double best_ms = 0.0;
+    if (ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) && ok(hipEventCreate(&e0)) && ok(hipEventCreate(&e1))) {
+        if (what == DL_RATE_HBM_COPY) {
+            if (ok(hipMalloc(&a, bytes)) && ok(hipMalloc(&b, bytes)) && ok(hipMemsetAsync(a, 0, bytes, s))) {
+                const size_t n = bytes / 16;
+                const int grid = (int)std::min<size_t>((size_t)prop.multiProcessorCount * 16, (n + RP_THREADS - 1) / RP_THREADS);
+                for (int r = 0; r <= reps && rc == DL_OK; ++r) {   // launch 0 warms up
+                    ok(hipEventRecord(e0, s));
+                    k_copy_rate<<<grid, RP_THREADS, 0, s>>>((const uint4 *)a, (uint4 *)b, n);
+                    ok(hipGetLastError());
+                    ok(hipEventRecord(e1, s));
+                    float ms = 0.f;
+                    if (ok(hipEventSynchronize(e1)) && ok(hipEventElapsedTime(&ms, e0, e1)) && r > 0)
+                        best_ms = best_ms == 0.0 ? ms : std::min<double>(best_ms, ms);
+                }
+                if (rc == DL_OK && best_ms > 0.0) *value = 2.0 * (double)bytes / (best_ms * 1e-3) / 1e9;
+            }
+        } else {
+            // about 8 ms per launch at the published rates
+            const int iters = what == DL_RATE_MFMA_BF16 ? 80000 : 40000;
+            const double flop_mfma = what == DL_RATE_MFMA_FP32 ? 2.0 * 16 * 16 * 4
+                                   : what == DL_RATE_MFMA_BF16 ? 2.0 * 16 * 16 * 32
+                                                               : 2.0 * 16 * 16 * 128;
+            if (ok(hipMalloc(&a, (size_t)blocks * RP_THREADS * sizeof(float)))) {
+                for (int r = 0; r <= reps && rc == DL_OK; ++r) {
+                    ok(hipEventRecord(e0, s));
+                    if (what == DL_RATE_MFMA_FP32)
+                        k_mfma_rate<DL_FP32><<<blocks, RP_THREADS, 0, s>>>(iters, 0, (float *)a);
+                    else if (what == DL_RATE_MFMA_BF16)
+                        k_mfma_rate<DL_BF16><<<blocks, RP_THREADS, 0, s>>>(iters, 0, (float *)a);
+                    else
+                        k_mfma_rate<DL_FP8><<<blocks, RP_THREADS, 0, s>>>(iters, 0, (float *)a);
+                    ok(hipGetLastError());
+                    ok(hipEventRecord(e1, s));
+                    float ms = 0.f;
+                    if (ok(hipEventSynchronize(e1)) && ok(hipEventElapsedTime(&ms, e0, e1)) && r > 0)
+                        best_ms = best_ms == 0.0 ? ms : std::min<double>(best_ms, ms);
+                }
+                const double flop = (double)blocks * (RP_THREADS / 64) * iters * RP_CHAINS * flop_mfma;
+                if (rc == DL_OK && best_ms > 0.0) *value = flop / (best_ms * 1e-3) / 1e12;
+            }
+        }
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (rc != DL_OK) (void)hipGetLastError();
+    return rc;
+}

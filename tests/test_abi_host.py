@@ -129,3 +129,14 @@ def test_create_without_gpu_reports_device_error():
         pytest.skip("a GPU is present")
     _, _, b = blob("B")
     assert _create(b) == dl.DL_ERR_DEVICE
+
+
+def test_measure_rate_rejects_bad_requests_before_any_hip_call():
+    v = ctypes.c_double()
+    L = dl.lib()
+    assert L.dl_measure_rate(7, 0, 1, ctypes.byref(v)) == dl.DL_ERR_INVALID_ARG      # unknown kind
+    assert L.dl_measure_rate(-1, 0, 1, ctypes.byref(v)) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_measure_rate(3, 100, 1, ctypes.byref(v)) == dl.DL_ERR_INVALID_ARG    # copy size not 16-aligned
+    assert L.dl_measure_rate(3, 0, 1, ctypes.byref(v)) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_measure_rate(0, 0, 0, ctypes.byref(v)) == dl.DL_ERR_INVALID_ARG      # no repetition
+    assert L.dl_measure_rate(0, 0, 1, None) == dl.DL_ERR_INVALID_ARG
