@@ -66,6 +66,9 @@ def _L():
         _lib.or_conv3x3.argtypes = [P, i, i, i, P, P, i, i, P]
         _lib.or_net_maps.restype = i
         _lib.or_net_maps.argtypes = [P, i, i, d, d, d, P, i, i, P, i, P]
+        _lib.or_preprocess_maps.argtypes = [P, l, P, P, d, P]
+        _lib.or_net_maps_cam.restype = i
+        _lib.or_net_maps_cam.argtypes = [P, i, i, P, P, d, P, i, i, P, i, P]
         _lib.or_detect.argtypes = [P, i, i, d, P]
         _lib.or_gate_pool.argtypes = [P, i, i, i, P]
         _lib.or_gate_forward.argtypes = [P, i, i, i, P, P]
@@ -109,9 +112,31 @@ def store_fp8_groups(a: np.ndarray) -> np.ndarray:
 
 
 # ----------------------------------------------------------- preprocessing
-def preprocess(frames: np.ndarray, gain: float, offset: float, in_scale: float) -> np.ndarray:
+def _is_map(v) -> bool:
+    return np.ndim(v) > 0
+
+
+def _camera_maps(gain, offset, shape):
+    """Per-pixel (sCMOS) gain and offset maps of `shape` as FP64 arrays (a
+    scalar beside a map is broadcast)."""
+    g = np.ascontiguousarray(np.broadcast_to(np.asarray(gain, np.float64), shape), np.float64)
+    o = np.ascontiguousarray(np.broadcast_to(np.asarray(offset, np.float64), shape), np.float64)
+    return g, o
+
+
+def preprocess(frames: np.ndarray, gain, offset, in_scale: float) -> np.ndarray:
+    """x = (ADU - offset) * gain * in_scale; gain and offset are scalars or
+    per-pixel maps of one frame's shape (sCMOS)."""
     F = np.ascontiguousarray(frames, np.uint16)
     x = np.empty(F.shape, np.float64)
+    if _is_map(gain) or _is_map(offset):
+        g, o = _camera_maps(gain, offset, F.shape[-2:])
+        for k in range(F.size // g.size):
+            Fk = np.ascontiguousarray(F.reshape(-1, *g.shape)[k])
+            xk = np.empty(g.shape, np.float64)
+            _L().or_preprocess_maps(_p(Fk), g.size, _p(g), _p(o), in_scale, _p(xk))
+            x.reshape(-1, *g.shape)[k] = xk
+        return x
     _L().or_preprocess(_p(F), F.size, gain, offset, in_scale, _p(x))
     return x
 
@@ -139,16 +164,22 @@ def _flat(spec, weights: Dict[str, np.ndarray]) -> np.ndarray:
     return np.ascontiguousarray(flat_weights(spec, weights), np.float32)
 
 
-def net_maps(frame: np.ndarray, spec, weights: Dict[str, np.ndarray], gain: float = 0.5,
-             offset: float = 100.0, quant: str = "exact") -> np.ndarray:
-    """Maps [5][h][w] (logit, dx, dy, dz, photons) of one uint16 frame, FP64."""
+def net_maps(frame: np.ndarray, spec, weights: Dict[str, np.ndarray], gain=0.5,
+             offset=100.0, quant: str = "exact") -> np.ndarray:
+    """Maps [5][h][w] (logit, dx, dy, dz, photons) of one uint16 frame, FP64.
+    gain and offset are scalars or per-pixel [h][w] maps (sCMOS)."""
     F = np.ascontiguousarray(frame, np.uint16)
     h, w = F.shape
     params = _flat(spec, weights)
     dil = np.asarray(spec.dilations, np.int32)
     maps = np.empty((5, h, w), np.float64)
-    rc = _L().or_net_maps(_p(F), h, w, gain, offset, spec.in_scale, _p(params), spec.C,
-                          len(spec.dilations), _p(dil), QUANT[quant], _p(maps))
+    if _is_map(gain) or _is_map(offset):
+        g, o = _camera_maps(gain, offset, (h, w))
+        rc = _L().or_net_maps_cam(_p(F), h, w, _p(g), _p(o), spec.in_scale, _p(params), spec.C,
+                                  len(spec.dilations), _p(dil), QUANT[quant], _p(maps))
+    else:
+        rc = _L().or_net_maps(_p(F), h, w, gain, offset, spec.in_scale, _p(params), spec.C,
+                              len(spec.dilations), _p(dil), QUANT[quant], _p(maps))
     if rc != 0:
         raise RuntimeError("oracle net failed")
     return maps
@@ -171,6 +202,10 @@ def net_maps_window(frame: np.ndarray, spec, weights, y0: int, x0: int, hh: int,
     cy0, cx0 = max(0, y0 - R), max(0, x0 - R)
     cy1, cx1 = min(H, y0 + hh + R), min(W, x0 + ww + R)
     crop = frame[cy0:cy1, cx0:cx1]
+    if _is_map(gain):
+        gain = np.asarray(gain)[cy0:cy1, cx0:cx1]
+    if _is_map(offset):
+        offset = np.asarray(offset)[cy0:cy1, cx0:cx1]
     m = net_maps(crop, spec, weights, gain, offset, quant)
     return m[:, y0 - cy0:y0 - cy0 + hh, x0 - cx0:x0 - cx0 + ww]
 
@@ -209,7 +244,8 @@ def records(maps: np.ndarray, det: np.ndarray, spec, frame: int = 0) -> np.ndarr
 
 def localize(frames: np.ndarray, spec, weights, gain=0.5, offset=100.0, threshold=0.3,
              quant="exact", return_maps=False):
-    """Whole path: frames -> maps -> detections -> records (frame, row, col order)."""
+    """Whole path: frames -> maps -> detections -> records (frame, row, col order).
+    gain and offset are scalars or per-pixel [h][w] maps shared by all frames."""
     tau = math.log(threshold / (1.0 - threshold))
     recs, allmaps = [], []
     for f, F in enumerate(frames):

@@ -12,6 +12,7 @@
  * offsets, as in DECODE; Sec. 3.2.1: dilated 3x3 convolutions):
  *
  *   x      = (ADU - offset) * gain * in_scale                       preprocessing
+ *            (scalar gain/offset, or per-pixel sCMOS maps)
  *   a      = ReLU(conv_1(x; stem))                                  stem, 1 -> C
  *   per block k with dilation d_k:
  *     t    = ReLU(conv_dk(a; W_k1, b_k1))
@@ -142,6 +143,15 @@ void or_preprocess(const uint16_t *F, long npx, double gain, double offset,
         x[p] = ((double)F[p] - offset) * gain * in_scale;
 }
 
+/* sCMOS cameras: every pixel has its own offset (ADU) and gain (photons per
+ * ADU); gain[p] and offset[p] replace the scalars in the same formula. */
+void or_preprocess_maps(const uint16_t *F, long npx, const double *gain, const double *offset,
+                        double in_scale, double *x)
+{
+    for (long p = 0; p < npx; ++p)
+        x[p] = ((double)F[p] - offset[p]) * gain[p] * in_scale;
+}
+
 /* ------------------------------------------------------------- convolution */
 
 /* One 3x3 dilated convolution, planar [cin][h][w] -> [cout][h][w], zero padding
@@ -205,26 +215,23 @@ static void quant_weights_fp8(double *W, int cout, long per_out)
     }
 }
 
-int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
-                double in_scale, const float *params, int C, int nblocks,
-                const int *dil, int quant, double *maps /* [5][h][w] */)
+/* The network on the preprocessed input x [h][w]. */
+static int net_maps_from_input(const double *x, int h, int w, const float *params, int C, int nblocks,
+                               const int *dil, int quant, double *maps /* [5][h][w] */)
 {
     if (h <= 0 || w <= 0 || C <= 0 || nblocks < 0 || quant < 0 || quant > 2) return OR_ERR;
     long hw = (long)h * w;
     long nconv = (long)C * C * 9;
-    double *x = malloc(sizeof(double) * hw);
     double *a = malloc(sizeof(double) * hw * C);
     double *t = malloc(sizeof(double) * hw * C);
     double *u = malloc(sizeof(double) * hw * C);
     double *Wd = malloc(sizeof(double) * nconv);
     double *bd = malloc(sizeof(double) * (C > 5 ? C : 5));
-    if (!x || !a || !t || !u || !Wd || !bd) {
-        free(x); free(a); free(t); free(u); free(Wd); free(bd);
+    if (!a || !t || !u || !Wd || !bd) {
+        free(a); free(t); free(u); free(Wd); free(bd);
         return OR_ERR;
     }
     const float *p = params;
-
-    or_preprocess(F, hw, gain, offset, in_scale, x);
 
     /* stem: 1 -> C, dilation 1, FP32-exact weights in every mode */
     promote(p, (long)C * 9, Wd); p += (long)C * 9;
@@ -270,8 +277,35 @@ int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
             for (long k = 0; k < hw; ++k) m[k] += wt * ac[k];
         }
     }
-    free(x); free(a); free(t); free(u); free(Wd); free(bd);
+    free(a); free(t); free(u); free(Wd); free(bd);
     return OR_OK;
+}
+
+int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
+                double in_scale, const float *params, int C, int nblocks,
+                const int *dil, int quant, double *maps /* [5][h][w] */)
+{
+    if (h <= 0 || w <= 0) return OR_ERR;
+    double *x = malloc(sizeof(double) * (long)h * w);
+    if (!x) return OR_ERR;
+    or_preprocess(F, (long)h * w, gain, offset, in_scale, x);
+    int rc = net_maps_from_input(x, h, w, params, C, nblocks, dil, quant, maps);
+    free(x);
+    return rc;
+}
+
+/* As or_net_maps with per-pixel camera maps gain [h][w] and offset [h][w]. */
+int or_net_maps_cam(const uint16_t *F, int h, int w, const double *gain, const double *offset,
+                    double in_scale, const float *params, int C, int nblocks,
+                    const int *dil, int quant, double *maps /* [5][h][w] */)
+{
+    if (h <= 0 || w <= 0) return OR_ERR;
+    double *x = malloc(sizeof(double) * (long)h * w);
+    if (!x) return OR_ERR;
+    or_preprocess_maps(F, (long)h * w, gain, offset, in_scale, x);
+    int rc = net_maps_from_input(x, h, w, params, C, nblocks, dil, quant, maps);
+    free(x);
+    return rc;
 }
 
 /* --------------------------------------------------------------- detection */
