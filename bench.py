@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--sparse-layout", default="iid", choices=["iid", "cell"],
                     help="sparse workload: empty 256^2 tiles chosen independently (iid) or around one "
                          "compact occupied region (cell)")
+    ap.add_argument("--camera", default="scmos", choices=["scmos", "scalar"],
+                    help="full and pipeline workloads: frames from a seeded sCMOS sensor whose per-pixel gain "
+                         "and offset maps the net is given (scmos), or the scalar camera model (scalar)")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes rendering the frames (0 = automatic; 1 under profilers)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -93,8 +96,9 @@ def main():
     spec, w = S.make_net("B", 2)
     n, side = args.frames, args.size
     t0 = time.time()
-    frames = S.render_frames(n, side, side, "full", 1002, workers=args.gen_workers or None)
-    log(f"generated {n} x {side}^2 frames in {time.time() - t0:.1f}s")
+    cam = S.scmos_camera(side, side, 1002) if args.camera == "scmos" else None
+    frames = S.render_frames(n, side, side, "full", 1002, workers=args.gen_workers or None, camera=cam)
+    log(f"generated {n} x {side}^2 frames in {time.time() - t0:.1f}s ({args.camera} camera)")
 
     import torch
     import paper_2410_02314_amd as dl
@@ -115,7 +119,7 @@ def main():
         del src, dst
 
     forms = [args.precision] + [f for f in args.forms.split(",") if f and f != args.precision]
-    results = {f: measure_form(args, f, spec, w, d_frames, dl, torch, dev) for f in forms}
+    results = {f: measure_form(args, f, spec, w, d_frames, dl, torch, dev, cam) for f in forms}
     head = results[args.precision]
     # each roofline against the rate this device sustains as well as the published peak
     rates = {}
@@ -130,7 +134,7 @@ def main():
 
     cpu, ref = None, None
     if args.cpu_sample > 0:
-        cpu, ref = cpu_baseline(args, spec, w, frames, head["net"], dev, head["records"])
+        cpu, ref = cpu_baseline(args, spec, w, frames, head["net"], dev, head["records"], cam)
         for f, r in results.items():
             r["accuracy_vs_oracle"] = accuracy_on_sample(r["records"], ref)
             r["accuracy_vs_oracle"].update(map_errors_on_sample(r["net"], d_frames, ref, torch, dev))
@@ -153,6 +157,8 @@ def main():
         "config": {"workload": f"{n} x {side}x{side} uint16 frames, astigmatic 3D PSF, net B "
                                f"(C=48, d=1,2,4,8,16), {args.precision}",
                    "frames": n, "height": side, "width": side, "net": "B", "precision": args.precision,
+                   "camera": ("sCMOS per-pixel gain/offset maps (sensor seed 1002)" if cam is not None
+                              else "scalar gain 0.5, offset 100"),
                    "parallelism": "single GPU"},
         "roofline": head["roofline"], "stage_ms_per_step": head["stage_ms_per_step"],
         "emitters_per_step": head["emitters_per_step"],
@@ -165,7 +171,7 @@ def main():
         r["net"].close()
 
 
-def measure_form(args, precision, spec, w, d_frames, dl, torch, dev):
+def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
     """Time `steps` passes of the whole path in one form on the resident frames;
     returns throughput, per-stage HIP-event times and the dominant kernel's
     roofline (the 3x3 block convolution; its launches are bracketed by HIP
@@ -173,6 +179,8 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev):
     import smlm_synth as S
     n, side = args.frames, args.size
     net = dl.Net(S.serialize_weights(spec, w), precision=precision, tile_rows=args.tile_rows)
+    if cam is not None:
+        net.set_camera_maps(cam.gain, cam.offset)
     cap = n * side * side // 64
     d_out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
     d_counts = torch.zeros(n + 1, dtype=torch.int32, device=dev)
@@ -307,7 +315,7 @@ def measured_traffic(key):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(args, spec, w, frames, net, dev, recs):
+def cpu_baseline(args, spec, w, frames, net, dev, recs, cam=None):
     """FP64 oracle on a bounded sample: the top-left s x s crop of frame 0
     (1536^2 by default, about 20 s on 16 host threads).  Also checks the GPU maps and detections where the
     oracle's result is exact: all of a whole frame; in a smaller crop, the part
@@ -319,7 +327,8 @@ def cpu_baseline(args, spec, w, frames, net, dev, recs):
     s = min(args.cpu_sample, args.size)
     crop = np.ascontiguousarray(frames[0, :s, :s])
     t0 = time.perf_counter()
-    rec, ref_maps = oracle.localize(crop[None], spec, w, return_maps=True)
+    camera = {} if cam is None else {"gain": cam.gain[:s, :s], "offset": cam.offset[:s, :s]}
+    rec, ref_maps = oracle.localize(crop[None], spec, w, return_maps=True, **camera)
     dt = time.perf_counter() - t0
     whole = s == args.size
     R = 1 + 2 * sum(spec.dilations)

@@ -229,12 +229,15 @@ def pipeline(args, S):
     """Host frames: batches copied host->device on a side stream while the
     previous batch is processed, against the serial copy-then-compute order."""
     nb = 4
-    frames = S.render_frames(args.frames * nb, args.size, args.size, "full", 1002,
-                             workers=args.gen_workers or None).reshape(nb, args.frames, args.size, args.size)
+    cam = S.scmos_camera(args.size, args.size, 1002) if args.camera == "scmos" else None
+    frames = S.render_frames(args.frames * nb, args.size, args.size, "full", 1002, workers=args.gen_workers or None,
+                             camera=cam).reshape(nb, args.frames, args.size, args.size)
     import torch
     import paper_2410_02314_amd as dl
     spec, w = S.make_net("B", 2)
     net = dl.Net(S.serialize_weights(spec, w), precision=args.precision)
+    if cam is not None:
+        net.set_camera_maps(cam.gain, cam.offset)
     import ctypes
     pin = dl.host_alloc(frames.nbytes)               # pinned: copied to the GPU without staging
     buf = (ctypes.c_char * frames.nbytes).from_address(pin)
@@ -250,6 +253,7 @@ def pipeline(args, S):
     px = frames.size
     _line(args, px / out[1][0] / 1e6, out[1][0] * 1e3 / nb,
           {"workload": f"{nb} batches of {args.frames} x {args.size}^2 host frames (pinned), net B, "
-                       f"H2D on a side stream overlapped with compute", "net": "B", "precision": args.precision},
+                       f"H2D on a side stream overlapped with compute", "net": "B", "precision": args.precision,
+           "camera": args.camera},
           {"serial_mpx_s": round(px / out[0][0] / 1e6, 2), "overlap_speedup": round(out[0][0] / out[1][0], 3),
            "emitters": out[1][1]})

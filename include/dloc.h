@@ -162,6 +162,19 @@ int dl_localize_device(dl_net *net, const uint16_t *d_frames, int n, int h, int 
 int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
                    void *stream, float *d_maps);
 
+/* Per-pixel camera maps of an sCMOS sensor (host float [h][w] each, row-major,
+ * copied into the handle): preprocessing becomes
+ * x = (ADU - offset[y][x]) * gain[y][x] * in_scale in place of the config's
+ * scalar gain and offset, in the stem and in the tile gate's pooling.  Every
+ * frame of a uniform batch must then be h x w (else DL_ERR_INVALID_ARG); ROI
+ * lists are refused with DL_ERR_UNSUPPORTED.  gain and offset both NULL
+ * clears the maps (the scalars apply again).  gain must be finite and > 0,
+ * offset finite.  Waits for all work on the device before it changes the
+ * maps.  Graphs captured before the maps were set, cleared or given another
+ * shape refuse to launch (DL_ERR_INVALID_ARG); new values of the same shape
+ * are used by existing graphs. */
+int dl_set_camera_maps(dl_net *net, const float *gain, const float *offset, int h, int w);
+
 /* Localize host frames (synchronous).  The frames are copied host->device on
  * the handle's copy stream (from the caller's buffer directly when it is
  * pinned memory from dl_host_alloc, else through a pinned staging buffer),

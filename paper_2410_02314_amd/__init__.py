@@ -88,6 +88,7 @@ def _load():
         "dl_maps_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P]),
         "dl_host_alloc": (I, [Z, ctypes.POINTER(P)]),
         "dl_measure_rate": (I, [I, Z, I, ctypes.POINTER(ctypes.c_double)]),
+        "dl_set_camera_maps": (I, [P, P, P, I, I]),
         "dl_host_free": (None, [P]),
         "dl_debug_conv_layer": (I, [P, P, P, I, I, I, I, I, P, P]),
         "dl_debug_detect": (I, [P, P, I, I, I, ctypes.c_float, P, P]),
@@ -314,6 +315,18 @@ class Net:
         th = np.ascontiguousarray(theta, np.float32)
         assert th.size == GATE_NPARAM
         self._rc(_lib.dl_set_gate(self.handle, th.ctypes.data, float(threshold)))
+
+    def set_camera_maps(self, gain, offset):
+        """Per-pixel sCMOS gain and offset maps (host arrays [h][w]), or None
+        and None to return to the config's scalars."""
+        if gain is None and offset is None:
+            self._rc(_lib.dl_set_camera_maps(self.handle, None, None, 0, 0))
+            return
+        g = np.ascontiguousarray(gain, np.float32)
+        o = np.ascontiguousarray(offset, np.float32)
+        if g.ndim != 2 or g.shape != o.shape:
+            raise ValueError("gain and offset must be 2-D maps of one shape")
+        self._rc(_lib.dl_set_camera_maps(self.handle, g.ctypes.data, o.ctypes.data, g.shape[0], g.shape[1]))
 
     def gate_keep_map(self, keep, stream=None) -> int:
         n = ctypes.c_size_t()

@@ -84,6 +84,13 @@ struct dl_net {
     size_t pl_frame_bytes = 0, pl_stage_bytes = 0, pl_out_cap = 0;
     int pl_counts_n = 0;
     hipEvent_t pl_copied[2] = {}, pl_used[2] = {}, pl_counted[2] = {};
+
+    // per-pixel camera maps (sCMOS): {offset, gain * in_scale} per pixel of
+    // a cam_h x cam_w sensor; null = the scalar gain and offset of the config.
+    // cam_gen counts every change of shape or presence (graphs check it).
+    float2 *d_cam = nullptr;
+    int cam_h = 0, cam_w = 0;
+    uint64_t cam_gen = 0;
 };
 
 namespace {
@@ -360,7 +367,7 @@ int run_gate(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     float *pooled = reinterpret_cast<float *>(p.ws + p.pooled);
     float *glog = reinterpret_cast<float *>(p.ws + p.glog);
     uint8_t *keep = reinterpret_cast<uint8_t *>(p.ws + p.keep);
-    HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * net->in_scale, pooled, s));
+    HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * net->in_scale, net->d_cam, pooled, s));
     HIPCHK(net, launch_gate(pooled, (int)g.gate_tiles, net->d_gate_theta, glog, nullptr, nullptr, s));
     HIPCHK(net, launch_gate_keep(glog, g.gate_tiles, net->gate_tau, keep, s));
     HIPCHK(net, launch_active_lists(d_fd, g, keep, net->d_radius + 1, net->d_dil, 2 * net->nb,
@@ -385,8 +392,8 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
     for (int b = 0; b < net->nb; ++b) stem_r += 2 * net->dil[b];
     {
         StageTimer t(net, DL_STAGE_STEM, s);
-        HIPCHK(net, launch_stem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset, scale, a0,
-                                net->cfg.precision, keep, stem_r, s));
+        HIPCHK(net, launch_stem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset, scale, net->d_cam,
+                                a0, net->cfg.precision, keep, stem_r, s));
     }
     const int maxg = conv_max_grid(C, net->cfg.precision, g.tr, net->ncu);
     void *x = a0, *xn = p.ws + p.act2;      // block input, block output (alternating)
@@ -486,11 +493,24 @@ int uniform_geometry(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
     return DL_OK;
 }
 
+// Camera maps cover one sensor: they apply to uniform batches of frames of
+// exactly that shape and not to ROI lists.
+int check_camera(dl_net *net, bool uniform, int h, int w)
+{
+    if (!net->d_cam) return DL_OK;
+    if (!uniform) return fail(net, DL_ERR_UNSUPPORTED, "camera maps apply to uniform batches of sensor frames, not ROI lists");
+    if (h != net->cam_h || w != net->cam_w)
+        return fail(net, DL_ERR_INVALID_ARG, "frames are %d x %d but the camera maps are %d x %d", h, w, net->cam_h,
+                    net->cam_w);
+    return DL_OK;
+}
+
 int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g, hipStream_t s,
                   dl_emitter *d_out, size_t cap, uint32_t *d_counts, float *ext_maps,
                   const uint16_t *d_frames = nullptr, int n = 0, int h = 0, int w = 0)
 {
     int rc;
+    if ((rc = check_camera(net, d_frames != nullptr, h, w))) return rc;
     if ((rc = set_device(net))) return rc;
     if ((rc = ensure_packed(net))) return rc;
     if (gated_run(net)) {
@@ -524,6 +544,7 @@ struct dl_graph {
     FrameDesc *d_fd = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t cam_gen = 0;           // the handle's camera-map generation at capture
 };
 
 static int check_rois(dl_net *net, const dl_roi *rois, int nroi);
@@ -541,6 +562,7 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
     dl_graph *gr = new (std::nothrow) dl_graph();
     if (!gr) return fail(net, DL_ERR_OOM, "out of host memory");
     gr->net = net;
+    gr->cam_gen = net->cam_gen;
     auto bail = [&](int code) {
         if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
         if (gr->graph) (void)hipGraphDestroy(gr->graph);
@@ -779,6 +801,7 @@ void dl_destroy_net(dl_net *net)
     }
     if (net->pl_dcounts) (void)hipFree(net->pl_dcounts);
     if (net->pl_hcounts) (void)hipHostFree(net->pl_hcounts);
+    if (net->d_cam) (void)hipFree(net->d_cam);
     if (net->copy_stream) (void)hipStreamDestroy(net->copy_stream);
     if (net->compute_stream) (void)hipStreamDestroy(net->compute_stream);
     delete net;
@@ -799,6 +822,53 @@ int dl_set_config(dl_net *net, const dl_config *cfg)
             net->cfg.precision = old;
             return rc;
         }
+    }
+    return DL_OK;
+}
+
+int dl_set_camera_maps(dl_net *net, const float *gain, const float *offset, int h, int w)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (!gain != !offset) return fail(net, DL_ERR_INVALID_ARG, "give both camera maps or neither");
+    if (gain && (h <= 0 || w <= 0 || (int64_t)h * w > ((int64_t)1 << 28)))
+        return fail(net, DL_ERR_INVALID_ARG, "camera maps must be h x w with 0 < h * w <= 2^28 (got %d x %d)", h, w);
+    int rc;
+    if ((rc = set_device(net))) return rc;
+    auto clear = [&]() {
+        if (net->d_cam) (void)hipFree(net->d_cam);
+        net->d_cam = nullptr;
+        net->cam_h = net->cam_w = 0;
+        ++net->cam_gen;
+    };
+    if (!gain) {
+        if (net->d_cam) {
+            HIPCHK(net, hipDeviceSynchronize());
+            clear();
+        }
+        return DL_OK;
+    }
+    const size_t npx = (size_t)h * w;
+    std::vector<float2> host(npx);
+    for (size_t p = 0; p < npx; ++p) {
+        if (!std::isfinite(gain[p]) || !(gain[p] > 0.f) || !std::isfinite(offset[p]))
+            return fail(net, DL_ERR_INVALID_ARG, "camera map pixel %zu: gain must be finite and > 0, offset finite", p);
+        host[p] = make_float2(offset[p], gain[p] * net->in_scale);   // the scalar path's FP32 product
+    }
+    HIPCHK(net, hipDeviceSynchronize());        // nothing in flight still reads the old maps
+    if (!net->d_cam || h != net->cam_h || w != net->cam_w) {
+        clear();
+        if (hipMalloc(&net->d_cam, npx * sizeof(float2)) != hipSuccess) {
+            (void)hipGetLastError();
+            net->d_cam = nullptr;
+            return fail(net, DL_ERR_OOM, "hipMalloc for %d x %d camera maps failed", h, w);
+        }
+        net->cam_h = h;
+        net->cam_w = w;
+    }
+    hipError_t e = hipMemcpy(net->d_cam, host.data(), npx * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        clear();
+        return fail(net, DL_ERR_DEVICE, "camera map upload failed: %s", hipGetErrorString(e));
     }
     return DL_OK;
 }
@@ -1155,6 +1225,7 @@ int dl_graph_create(dl_net *net, const uint16_t *d_frames, int n, int h, int w, 
     if (rc) return rc;
     if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
     if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    if ((rc = check_camera(net, true, h, w))) return rc;
     std::vector<FrameDesc> fd;
     Geometry g;
     uniform_geometry(net, d_frames, n, h, w, fd, g);
@@ -1170,6 +1241,7 @@ int dl_graph_create_rois(dl_net *net, const dl_roi *rois, int nroi, dl_emitter *
     if (rc) return rc;
     if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
     if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    if ((rc = check_camera(net, false, 0, 0))) return rc;
     std::vector<FrameDesc> fd;
     Geometry g;
     roi_geometry(net, rois, nroi, fd, g);
@@ -1181,6 +1253,8 @@ int dl_graph_launch(dl_graph *g, void *stream)
     if (!g) return fail(nullptr, DL_ERR_INVALID_ARG, "graph is NULL");
     dl_net *net = g->net;
     int rc;
+    if (g->cam_gen != net->cam_gen)
+        return fail(net, DL_ERR_INVALID_ARG, "the camera maps were set, cleared or reshaped after this graph was captured");
     if ((rc = set_device(net))) return rc;
     HIPCHK(net, hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
     return DL_OK;
@@ -1329,7 +1403,7 @@ int dl_gate_pool(const uint16_t *d_frames, int n, int h, int w, float gain, floa
         return fail(nullptr, DL_ERR_UNSUPPORTED, "gate tiles need h and w multiples of %d", DL_GATE_TILE);
     if (!std::isfinite(gain) || !std::isfinite(offset) || !std::isfinite(in_scale) || !(gain > 0.f) || !(in_scale > 0.f))
         return fail(nullptr, DL_ERR_INVALID_ARG, "bad gain/offset/in_scale");
-    GCHK(launch_gate_pool(d_frames, n, h, w, offset, gain * in_scale, d_pooled, static_cast<hipStream_t>(stream)));
+    GCHK(launch_gate_pool(d_frames, n, h, w, offset, gain * in_scale, nullptr, d_pooled, static_cast<hipStream_t>(stream)));
     return DL_OK;
 }
 

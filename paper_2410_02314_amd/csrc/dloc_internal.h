@@ -187,9 +187,11 @@ __device__ __forceinline__ v4f fp8_unpack4(uint32_t codes, float s)
 // all return hipError_t of the launch
 // precision: storage of the output activations (FP32, BF16, or FP8 codes
 // and group scales)
+// cam: per-pixel {offset, gain * in_scale} of the sensor (every frame of
+// the batch is sensor-sized), or null for the scalar offset and scale
 hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                       float offset, float scale, void *act, int precision, const uint8_t *keep,
-                       int radius, hipStream_t s);
+                       float offset, float scale, const float2 *cam, void *act, int precision,
+                       const uint8_t *keep, int radius, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // gated runs: keep[t] = logit[t] > tau_gate; then one compacted list of conv
 // tiles per layer (tiles within radius[l] of a kept gate tile)
@@ -240,7 +242,7 @@ hipError_t launch_mask_to_u8(const uint64_t *mask, const FrameDesc *fd, const Ge
 // tile gate (kernels_gate.hip)
 size_t gate_smem_bytes();
 hipError_t launch_gate_pool(const uint16_t *frames, int n, int h, int w, float offset, float scale,
-                            float *pooled, hipStream_t s);
+                            const float2 *cam, float *pooled, hipStream_t s);
 hipError_t launch_gate(const float *pooled, int ntiles, const float *theta, float *logits,
                        const float *dlogits, float *gpart, hipStream_t s);
 hipError_t launch_gate_reduce(const float *gpart, int ntiles, float *grad, hipStream_t s);

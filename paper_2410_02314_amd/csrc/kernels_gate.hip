@@ -47,7 +47,7 @@ __device__ __forceinline__ float wave_sum(float v)
 // grid: one workgroup per tile (frame-major, then tile row, tile column).
 __global__ void __launch_bounds__(256)
 k_gate_pool(const uint16_t *__restrict__ frames, int n, int h, int w, float offset, float scale,
-            float *__restrict__ pooled)
+            const float2 *__restrict__ cam, float *__restrict__ pooled)
 {
     const int tiles_x = w / GT, tiles_y = h / GT;
     const int tile = blockIdx.x;
@@ -62,8 +62,16 @@ k_gate_pool(const uint16_t *__restrict__ frames, int n, int h, int w, float offs
 #pragma unroll
         for (int u = 0; u < GPOOL; ++u)
 #pragma unroll
-            for (int v = 0; v < GPOOL; ++v)
-                s += ((float)src[(int64_t)(i * GPOOL + u) * w + j * GPOOL + v] - offset) * scale;
+            for (int v = 0; v < GPOOL; ++v) {
+                const int64_t q2 = (int64_t)(i * GPOOL + u) * w + j * GPOOL + v;
+                const float adu = (float)src[q2];
+                if (cam) {               // sCMOS: this pixel's offset and gain
+                    const float2 cm = cam[(int64_t)(ty * GT) * w + tx * GT + q2];
+                    s += (adu - cm.x) * cm.y;
+                } else {
+                    s += (adu - offset) * scale;
+                }
+            }
         dst[q] = s * (1.f / (GPOOL * GPOOL));
     }
 }
@@ -314,10 +322,10 @@ k_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v, 
 size_t gate_smem_bytes() { return sizeof(GateSmem); }
 
 hipError_t launch_gate_pool(const uint16_t *frames, int n, int h, int w, float offset, float scale,
-                            float *pooled, hipStream_t s)
+                            const float2 *cam, float *pooled, hipStream_t s)
 {
     const int nt = n * (h / GT) * (w / GT);
-    hipLaunchKernelGGL(k_gate_pool, dim3(nt), dim3(256), 0, s, frames, n, h, w, offset, scale, pooled);
+    hipLaunchKernelGGL(k_gate_pool, dim3(nt), dim3(256), 0, s, frames, n, h, w, offset, scale, cam, pooled);
     return hipGetLastError();
 }
 

@@ -28,8 +28,8 @@ constexpr int SSEG = 1024;
 template <int C, int P>
 __global__ void __launch_bounds__(256)
 k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__restrict__ w,
-       const float *__restrict__ b, float offset, float scale, void *__restrict__ act, int64_t scale_off,
-       const uint8_t *__restrict__ keep, int radius)
+       const float *__restrict__ b, float offset, float scale, const float2 *__restrict__ cam,
+       void *__restrict__ act, int64_t scale_off, const uint8_t *__restrict__ keep, int radius)
 {
     constexpr int CQ = P == DL_FP8 ? 16 : P == DL_BF16 ? 8 : 4;   // channels per item
     constexpr int IPX = P == DL_FP8 ? 4 : C / CQ;                  // items per pixel
@@ -62,7 +62,17 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__
                 const int r = i / (SSEG + 2), c = i - r * (SSEG + 2);
                 const int yy = y + r - 1, xx = x0 + c - 1;
                 const bool ok = c < n + 2 && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
-                sx[r][c] = ok ? ((float)fd.data[(int64_t)yy * fd.stride + xx] - offset) * scale : 0.f;
+                float v = 0.f;
+                if (ok) {
+                    const float adu = (float)fd.data[(int64_t)yy * fd.stride + xx];
+                    if (cam) {               // sCMOS: this pixel's offset and gain (frames are sensor-sized)
+                        const float2 cm = cam[(int64_t)yy * W + xx];
+                        v = (adu - cm.x) * cm.y;
+                    } else {
+                        v = (adu - offset) * scale;
+                    }
+                }
+                sx[r][c] = v;
             }
             // gated runs: which 64-pixel pieces of the segment are needed
             if (threadIdx.x < SSEG / 64) {
@@ -121,19 +131,20 @@ k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__
 
 template <int C>
 hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const float *b, float offset,
-                  float scale, void *act, int precision, const uint8_t *keep, int radius, hipStream_t s)
+                  float scale, const float2 *cam, void *act, int precision, const uint8_t *keep, int radius,
+                  hipStream_t s)
 {
     const unsigned grid = (unsigned)std::min<int64_t>(g.total_rows, 8192);
     const int64_t soff = g.total_act * C;        // FP8: byte offset of the group scales
     if (precision == DL_FP8)
         hipLaunchKernelGGL((k_stem<C, DL_FP8>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
-                           scale, act, soff, keep, radius);
+                           scale, cam, act, soff, keep, radius);
     else if (precision == DL_BF16)
         hipLaunchKernelGGL((k_stem<C, DL_BF16>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
-                           scale, act, soff, keep, radius);
+                           scale, cam, act, soff, keep, radius);
     else
         hipLaunchKernelGGL((k_stem<C, DL_FP32>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
-                           scale, act, soff, keep, radius);
+                           scale, cam, act, soff, keep, radius);
     return hipGetLastError();
 }
 
@@ -376,14 +387,14 @@ hipError_t launch_active_lists(const FrameDesc *fd, const Geometry &g, const uin
 }
 
 hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b,
-                       float offset, float scale, void *act, int precision, const uint8_t *keep,
-                       int radius, hipStream_t s)
+                       float offset, float scale, const float2 *cam, void *act, int precision,
+                       const uint8_t *keep, int radius, hipStream_t s)
 {
     switch (C) {
-    case 16: return stem_c<16>(fd, g, w, b, offset, scale, act, precision, keep, radius, s);
-    case 32: return stem_c<32>(fd, g, w, b, offset, scale, act, precision, keep, radius, s);
-    case 48: return stem_c<48>(fd, g, w, b, offset, scale, act, precision, keep, radius, s);
-    case 64: return stem_c<64>(fd, g, w, b, offset, scale, act, precision, keep, radius, s);
+    case 16: return stem_c<16>(fd, g, w, b, offset, scale, cam, act, precision, keep, radius, s);
+    case 32: return stem_c<32>(fd, g, w, b, offset, scale, cam, act, precision, keep, radius, s);
+    case 48: return stem_c<48>(fd, g, w, b, offset, scale, cam, act, precision, keep, radius, s);
+    case 64: return stem_c<64>(fd, g, w, b, offset, scale, cam, act, precision, keep, radius, s);
     default: return hipErrorInvalidValue;
     }
 }

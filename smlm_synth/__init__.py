@@ -36,7 +36,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 __all__ = [
-    "FrameModel", "NetSpec", "NET_A", "NET_B", "CONFIG_MODELS",
+    "FrameModel", "Camera", "scmos_camera", "NetSpec", "NET_A", "NET_B", "CONFIG_MODELS",
     "render_frames", "render_rois", "he_normal_weights", "make_net",
     "serialize_weights", "param_count", "net_flops_per_px", "receptive_radius",
     "TAU_LOGIT", "DLW_MAGIC",
@@ -105,6 +105,30 @@ CONFIG_MODELS: Dict[str, FrameModel] = {
 ROI_SIDES = (128, 256, 384, 512, 768, 1024)
 
 
+@dataclass(frozen=True)
+class Camera:
+    """Per-pixel sCMOS calibration of one sensor, float32 [h][w] maps."""
+    gain: np.ndarray       # photons per ADU
+    offset: np.ndarray     # ADU
+    read_sd: np.ndarray    # read noise, ADU
+
+
+def scmos_camera(h: int, w: int, seed: int, gain: float = 0.5, offset: float = 100.0, gain_cv: float = 0.05,
+                 offset_sd: float = 3.0, read_sd: float = 1.5, read_log_sd: float = 0.3) -> Camera:
+    """Seeded sCMOS sensor: gain = gain (1 + gain_cv N) clipped to +-4 gain_cv,
+    offset = offset + offset_sd N, read noise sd = read_sd exp(read_log_sd N)
+    (N independent standard normals per pixel and map)."""
+    rng = np.random.default_rng([seed, 0x5C])
+    g = gain * (1.0 + gain_cv * np.clip(rng.standard_normal((h, w)), -4.0, 4.0))
+    o = offset + offset_sd * rng.standard_normal((h, w))
+    r = read_sd * np.exp(read_log_sd * rng.standard_normal((h, w)))
+    return Camera(g.astype(np.float32), o.astype(np.float32), r.astype(np.float32))
+
+
+# the camera of the render in progress (inherited by forked workers)
+_CAMERA: Optional[Camera] = None
+
+
 def _phi(t: np.ndarray) -> np.ndarray:
     """Standard normal CDF (used only to integrate the simulated PSF over a pixel)."""
     from scipy.special import ndtr
@@ -137,8 +161,9 @@ def _occupancy(nty: int, ntx: int, q: float, layout: str, rng: np.random.Generat
     return occ.reshape(nty, ntx)
 
 
-def _render_one(h: int, w: int, model: FrameModel, rng: np.random.Generator):
-    """Render one frame; returns (uint16 frame, truth dict)."""
+def _render_one(h: int, w: int, model: FrameModel, rng: np.random.Generator, camera: Optional[Camera] = None):
+    """Render one frame; returns (uint16 frame, truth dict).  With a camera,
+    its per-pixel gain, offset and read noise replace the model's scalars."""
     area_um2 = h * w * (model.pixel_nm / 1000.0) ** 2
     rho = rng.uniform(*model.density)
     bg = rng.uniform(*model.background)
@@ -203,7 +228,12 @@ def _render_one(h: int, w: int, model: FrameModel, rng: np.random.Generator):
             idx = (pyc[:, :, None] * w + pxc[:, None, :]).ravel()
             mu += np.bincount(idx, weights=val, minlength=h * w)
     counts = rng.poisson(mu).astype(np.float64)
-    adu = counts / model.gain + model.offset + model.read_sd_adu * rng.standard_normal(h * w)
+    if camera is not None:
+        assert camera.gain.shape == (h, w), "the camera maps must cover the frame"
+        adu = (counts / camera.gain.ravel().astype(np.float64) + camera.offset.ravel().astype(np.float64)
+               + camera.read_sd.ravel().astype(np.float64) * rng.standard_normal(h * w))
+    else:
+        adu = counts / model.gain + model.offset + model.read_sd_adu * rng.standard_normal(h * w)
     frame = np.clip(np.rint(adu), 0, 65535).astype(np.uint16).reshape(h, w)
     truth = {"x": xs, "y": ys, "z_nm": z, "photons": nph, "background": bg, "density": rho,
              "tile_occupied": tile_occupied}
@@ -212,13 +242,16 @@ def _render_one(h: int, w: int, model: FrameModel, rng: np.random.Generator):
 
 def render_frames(n: int, h: int, w: int, model: FrameModel | str, seed: int,
                   frame_ids: Optional[Sequence[int]] = None, with_truth: bool = False,
-                  workers: Optional[int] = None):
+                  workers: Optional[int] = None, camera: Optional[Camera] = None):
     """Render ``n`` frames of ``h x w`` uint16 (frame k seeded by ``(seed, k)``).
 
     ``frame_ids`` selects which frame indices of the seeded sequence to render
     (default ``range(n)``), so any frame can be regenerated on its own.
     ``workers`` > 1 renders frames in forked processes (default: automatic).
+    ``camera`` (an sCMOS sensor of h x w) gives per-pixel gain, offset and
+    read noise.
     """
+    global _CAMERA
     if isinstance(model, str):
         model = CONFIG_MODELS[model]
     ids = list(range(n)) if frame_ids is None else list(frame_ids)
@@ -227,12 +260,16 @@ def render_frames(n: int, h: int, w: int, model: FrameModel | str, seed: int,
     jobs = [(h, w, model, int(seed), int(fid)) for fid in ids]
     if workers is None:
         workers = min(len(ids), _pool_size()) if len(ids) * h * w >= (1 << 22) else 1
-    if workers > 1:
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers) as pool:
-            res = pool.map(_render_job, jobs)
-    else:
-        res = [_render_job(j) for j in jobs]
+    _CAMERA = camera
+    try:
+        if workers > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(workers) as pool:
+                res = pool.map(_render_job, jobs)
+        else:
+            res = [_render_job(j) for j in jobs]
+    finally:
+        _CAMERA = None
     for i, (f, t) in enumerate(res):
         out[i] = f
         truths.append(t)
@@ -249,7 +286,7 @@ def _pool_size() -> int:
 
 def _render_job(job):
     h, w, model, seed, fid = job
-    return _render_one(h, w, model, np.random.default_rng([seed, fid]))
+    return _render_one(h, w, model, np.random.default_rng([seed, fid]), _CAMERA)
 
 
 def roi_shapes(n: int, seed: int, sides: Sequence[int] = ROI_SIDES) -> List[Tuple[int, int]]:

@@ -140,3 +140,8 @@ def test_measure_rate_rejects_bad_requests_before_any_hip_call():
     assert L.dl_measure_rate(3, 0, 1, ctypes.byref(v)) == dl.DL_ERR_INVALID_ARG
     assert L.dl_measure_rate(0, 0, 0, ctypes.byref(v)) == dl.DL_ERR_INVALID_ARG      # no repetition
     assert L.dl_measure_rate(0, 0, 1, None) == dl.DL_ERR_INVALID_ARG
+
+
+def test_set_camera_maps_rejects_a_null_handle():
+    g = np.full((4, 4), 0.5, np.float32)
+    assert dl.lib().dl_set_camera_maps(None, g.ctypes.data, g.ctypes.data, 4, 4) == dl.DL_ERR_INVALID_ARG

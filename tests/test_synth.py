@@ -52,3 +52,37 @@ def test_emitters_only_in_occupied_tiles(model):
         ty = (np.asarray(t["y"]) // 256).astype(int)
         tx = (np.asarray(t["x"]) // 256).astype(int)
         assert occ[ty, tx].all()
+
+
+def test_scmos_camera_is_seeded_and_plausible():
+    a, b = S.scmos_camera(64, 96, 7), S.scmos_camera(64, 96, 7)
+    assert all(np.array_equal(getattr(a, k), getattr(b, k)) for k in ("gain", "offset", "read_sd"))
+    c = S.scmos_camera(64, 96, 8)
+    assert not np.array_equal(a.offset, c.offset)
+    assert a.gain.dtype == np.float32 and a.gain.shape == (64, 96)
+    assert np.all(a.gain > 0.5 * 0.79) and np.all(a.gain < 0.5 * 1.21) and abs(a.gain.mean() - 0.5) < 0.005
+    assert abs(a.offset.mean() - 100.0) < 0.2 and 2.5 < a.offset.std() < 3.5
+    assert np.all(a.read_sd > 0)
+
+
+def test_constant_camera_renders_the_scalar_model():
+    """A camera whose maps equal the model's scalars draws the same random
+    numbers in the same order: the frames are identical."""
+    h, w = 48, 80
+    cam = S.Camera(np.full((h, w), 0.5, np.float32), np.full((h, w), 100.0, np.float32),
+                   np.full((h, w), 1.5, np.float32))
+    a = S.render_frames(2, h, w, "tiny", 5)
+    b = S.render_frames(2, h, w, "tiny", 5, camera=cam)
+    assert np.array_equal(a, b)
+
+
+def test_camera_offset_shows_in_dark_frames():
+    """Background only (no emitters): each pixel's mean ADU over many frames
+    approaches offset + background / gain of that pixel."""
+    import dataclasses
+    h, w = 8, 12
+    cam = S.scmos_camera(h, w, 3, offset_sd=20.0)
+    dark = dataclasses.replace(S.CONFIG_MODELS["tiny"], density=(0.0, 0.0), background=(10.0, 10.0))
+    fr = S.render_frames(400, h, w, dark, 9, camera=cam, workers=1).astype(np.float64)
+    expect = cam.offset + 10.0 / cam.gain
+    assert np.abs(fr.mean(axis=0) - expect).max() < 1.5
