@@ -15,14 +15,13 @@ typedef float rp_f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 rp_bf8 __attribute__((ext_vector_type(8)));
 typedef int rp_i8 __attribute__((ext_vector_type(8)));
 
-constexpr int RP_CHAINS = 4;      // independent accumulators per wave
 constexpr int RP_THREADS = 256;   // four waves per workgroup
 
-// Each wave runs RP_CHAINS independent MFMA accumulation chains of `iters`
-// steps on register operands: no memory traffic, so the launch measures the
-// matrix units alone.  `flag` is 0 at run time; the store it guards keeps the
-// chains live.
-template <int KIND>
+// Each wave runs CH independent MFMA accumulation chains of `iters` steps on
+// register operands: no memory traffic, so the launch measures the matrix
+// units alone.  `flag` is 0 at run time; the store it guards keeps the chains
+// live.
+template <int KIND, int RP_CHAINS>
 __global__ __launch_bounds__(RP_THREADS) void k_mfma_rate(int iters, int flag, float *sink)
 {
     const int t = threadIdx.x;
@@ -64,12 +63,25 @@ __global__ __launch_bounds__(RP_THREADS) void k_mfma_rate(int iters, int flag, f
     if (flag) sink[blockIdx.x * RP_THREADS + t] = s;
 }
 
-// Plain grid-stride copy of n 16-byte words.
+// Copy of n 16-byte words: each workgroup moves one contiguous chunk of
+// RP_COPY_UNROLL * RP_THREADS words, with all its loads issued before its
+// stores.
+constexpr int RP_COPY_UNROLL = 8;
 __global__ __launch_bounds__(RP_THREADS) void k_copy_rate(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                                           size_t n)
 {
-    const size_t stride = (size_t)gridDim.x * RP_THREADS;
-    for (size_t i = (size_t)blockIdx.x * RP_THREADS + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    const size_t base = (size_t)blockIdx.x * RP_COPY_UNROLL * RP_THREADS + threadIdx.x;
+    uint4 v[RP_COPY_UNROLL];
+#pragma unroll
+    for (int k = 0; k < RP_COPY_UNROLL; ++k) {
+        const size_t i = base + (size_t)k * RP_THREADS;
+        if (i < n) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < RP_COPY_UNROLL; ++k) {
+        const size_t i = base + (size_t)k * RP_THREADS;
+        if (i < n) dst[i] = v[k];
+    }
 }
 
 }  // namespace
@@ -83,7 +95,8 @@ extern "C" int dl_measure_rate(int what, size_t bytes, int reps, double *value)
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return DL_ERR_DEVICE;
-    const int blocks = prop.multiProcessorCount * 4;   // sixteen waves per CU
+    // many short workgroups, so the dispatcher keeps every SIMD busy to the end
+    const int blocks = prop.multiProcessorCount * 64;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     void *a = nullptr, *b = nullptr;
@@ -97,7 +110,8 @@ extern "C" int dl_measure_rate(int what, size_t bytes, int reps, double *value)
         if (what == DL_RATE_HBM_COPY) {
             if (ok(hipMalloc(&a, bytes)) && ok(hipMalloc(&b, bytes)) && ok(hipMemsetAsync(a, 0, bytes, s))) {
                 const size_t n = bytes / 16;
-                const int grid = (int)std::min<size_t>((size_t)prop.multiProcessorCount * 16, (n + RP_THREADS - 1) / RP_THREADS);
+                const size_t per = (size_t)RP_COPY_UNROLL * RP_THREADS;
+                const int grid = (int)((n + per - 1) / per);
                 for (int r = 0; r <= reps && rc == DL_OK; ++r) {   // launch 0 warms up
                     ok(hipEventRecord(e0, s));
                     k_copy_rate<<<grid, RP_THREADS, 0, s>>>((const uint4 *)a, (uint4 *)b, n);
@@ -110,28 +124,37 @@ extern "C" int dl_measure_rate(int what, size_t bytes, int reps, double *value)
                 if (rc == DL_OK && best_ms > 0.0) *value = 2.0 * (double)bytes / (best_ms * 1e-3) / 1e9;
             }
         } else {
-            // about 8 ms per launch at the published rates
-            const int iters = what == DL_RATE_MFMA_BF16 ? 80000 : 40000;
+            // about 8 ms per launch at the published rates (64 workgroups per CU,
+            // four of them resident at a time)
+            const int iters = what == DL_RATE_MFMA_BF16 ? 5000 : 2500;
             const double flop_mfma = what == DL_RATE_MFMA_FP32 ? 2.0 * 16 * 16 * 4
                                    : what == DL_RATE_MFMA_BF16 ? 2.0 * 16 * 16 * 32
                                                                : 2.0 * 16 * 16 * 128;
+            // the best of four and eight independent chains per wave
             if (ok(hipMalloc(&a, (size_t)blocks * RP_THREADS * sizeof(float)))) {
-                for (int r = 0; r <= reps && rc == DL_OK; ++r) {
-                    ok(hipEventRecord(e0, s));
-                    if (what == DL_RATE_MFMA_FP32)
-                        k_mfma_rate<DL_FP32><<<blocks, RP_THREADS, 0, s>>>(iters, 0, (float *)a);
-                    else if (what == DL_RATE_MFMA_BF16)
-                        k_mfma_rate<DL_BF16><<<blocks, RP_THREADS, 0, s>>>(iters, 0, (float *)a);
-                    else
-                        k_mfma_rate<DL_FP8><<<blocks, RP_THREADS, 0, s>>>(iters, 0, (float *)a);
-                    ok(hipGetLastError());
-                    ok(hipEventRecord(e1, s));
-                    float ms = 0.f;
-                    if (ok(hipEventSynchronize(e1)) && ok(hipEventElapsedTime(&ms, e0, e1)) && r > 0)
-                        best_ms = best_ms == 0.0 ? ms : std::min<double>(best_ms, ms);
+                for (int chains = 4; chains <= 8 && rc == DL_OK; chains += 4) {
+                    const int it = iters * 4 / chains;    // the same work either way
+                    best_ms = 0.0;
+                    for (int r = 0; r <= reps && rc == DL_OK; ++r) {
+                        ok(hipEventRecord(e0, s));
+                        if (what == DL_RATE_MFMA_FP32)
+                            (chains == 4 ? k_mfma_rate<DL_FP32, 4> : k_mfma_rate<DL_FP32, 8>)
+                                <<<blocks, RP_THREADS, 0, s>>>(it, 0, (float *)a);
+                        else if (what == DL_RATE_MFMA_BF16)
+                            (chains == 4 ? k_mfma_rate<DL_BF16, 4> : k_mfma_rate<DL_BF16, 8>)
+                                <<<blocks, RP_THREADS, 0, s>>>(it, 0, (float *)a);
+                        else
+                            (chains == 4 ? k_mfma_rate<DL_FP8, 4> : k_mfma_rate<DL_FP8, 8>)
+                                <<<blocks, RP_THREADS, 0, s>>>(it, 0, (float *)a);
+                        ok(hipGetLastError());
+                        ok(hipEventRecord(e1, s));
+                        float ms = 0.f;
+                        if (ok(hipEventSynchronize(e1)) && ok(hipEventElapsedTime(&ms, e0, e1)) && r > 0)
+                            best_ms = best_ms == 0.0 ? ms : std::min<double>(best_ms, ms);
+                    }
+                    const double flop = (double)blocks * (RP_THREADS / 64) * it * chains * flop_mfma;
+                    if (rc == DL_OK && best_ms > 0.0) *value = std::max(*value, flop / (best_ms * 1e-3) / 1e12);
                 }
-                const double flop = (double)blocks * (RP_THREADS / 64) * iters * RP_CHAINS * flop_mfma;
-                if (rc == DL_OK && best_ms > 0.0) *value = flop / (best_ms * 1e-3) / 1e12;
             }
         }
     }
