@@ -65,10 +65,10 @@ def _L():
         _lib.or_preprocess.argtypes = [P, l, d, d, d, P]
         _lib.or_conv3x3.argtypes = [P, i, i, i, P, P, i, i, P]
         _lib.or_net_maps.restype = i
-        _lib.or_net_maps.argtypes = [P, i, i, d, d, d, P, i, i, P, i, P]
+        _lib.or_net_maps.argtypes = [P, i, i, d, d, d, P, i, i, P, i, i, P]
         _lib.or_preprocess_maps.argtypes = [P, l, P, P, d, P]
         _lib.or_net_maps_cam.restype = i
-        _lib.or_net_maps_cam.argtypes = [P, i, i, P, P, d, P, i, i, P, i, P]
+        _lib.or_net_maps_cam.argtypes = [P, i, i, P, P, d, P, i, i, P, i, i, P]
         _lib.or_detect.argtypes = [P, i, i, d, P]
         _lib.or_gate_pool.argtypes = [P, i, i, i, P]
         _lib.or_gate_forward.argtypes = [P, i, i, i, P, P]
@@ -166,20 +166,23 @@ def _flat(spec, weights: Dict[str, np.ndarray]) -> np.ndarray:
 
 def net_maps(frame: np.ndarray, spec, weights: Dict[str, np.ndarray], gain=0.5,
              offset=100.0, quant: str = "exact") -> np.ndarray:
-    """Maps [5][h][w] (logit, dx, dy, dz, photons) of one uint16 frame, FP64.
-    gain and offset are scalars or per-pixel [h][w] maps (sCMOS)."""
+    """Maps [nh][h][w] of one uint16 frame, FP64: logit, dx, dy, dz, photons
+    (nh = 5), then the raw uncertainties of x, y, z, photons and the raw
+    background (nh = 10).  gain and offset are scalars or per-pixel [h][w]
+    maps (sCMOS)."""
     F = np.ascontiguousarray(frame, np.uint16)
     h, w = F.shape
     params = _flat(spec, weights)
     dil = np.asarray(spec.dilations, np.int32)
-    maps = np.empty((5, h, w), np.float64)
+    nh = spec.head_outputs
+    maps = np.empty((nh, h, w), np.float64)
     if _is_map(gain) or _is_map(offset):
         g, o = _camera_maps(gain, offset, (h, w))
         rc = _L().or_net_maps_cam(_p(F), h, w, _p(g), _p(o), spec.in_scale, _p(params), spec.C,
-                                  len(spec.dilations), _p(dil), QUANT[quant], _p(maps))
+                                  len(spec.dilations), _p(dil), QUANT[quant], nh, _p(maps))
     else:
         rc = _L().or_net_maps(_p(F), h, w, gain, offset, spec.in_scale, _p(params), spec.C,
-                              len(spec.dilations), _p(dil), QUANT[quant], _p(maps))
+                              len(spec.dilations), _p(dil), QUANT[quant], nh, _p(maps))
     if rc != 0:
         raise RuntimeError("oracle net failed")
     return maps
@@ -242,19 +245,58 @@ def records(maps: np.ndarray, det: np.ndarray, spec, frame: int = 0) -> np.ndarr
     return out
 
 
+UNCERTAINTY_DTYPE = np.dtype([("sigma_x", "<f8"), ("sigma_y", "<f8"), ("sigma_z", "<f8"),
+                               ("sigma_photons", "<f8"), ("background", "<f8")])
+
+
+def softplus(u):
+    """log(1 + e^u), in the form that neither overflows nor loses small values:
+    max(u, 0) + log1p(e^-|u|)."""
+    u = np.asarray(u, np.float64)
+    return np.maximum(u, 0.0) + np.log1p(np.exp(-np.abs(u)))
+
+
+def uncertainties(maps: np.ndarray, det: np.ndarray, spec) -> np.ndarray:
+    """Uncertainties of one frame's detections (raster order) from a 10-plane
+    map: each is softplus of its raw plane (positive by construction) times its
+    unit -- sigma_x, sigma_y in px, sigma_z * z_scale (nm), sigma_photons *
+    ph_scale, background / in_scale (photons per pixel, the units the input
+    scaling divides out)."""
+    assert maps.shape[0] == 10, "the uncertainty head has 10 planes"
+    rows, cols = np.nonzero(det)
+    out = np.empty(rows.size, UNCERTAINTY_DTYPE)
+    sp = [softplus(maps[5 + q, rows, cols]) for q in range(5)]
+    out["sigma_x"] = sp[0]
+    out["sigma_y"] = sp[1]
+    out["sigma_z"] = sp[2] * spec.z_scale
+    out["sigma_photons"] = sp[3] * spec.ph_scale
+    out["background"] = sp[4] / spec.in_scale
+    return out
+
+
 def localize(frames: np.ndarray, spec, weights, gain=0.5, offset=100.0, threshold=0.3,
-             quant="exact", return_maps=False):
+             quant="exact", return_maps=False, with_uncertainty=False):
     """Whole path: frames -> maps -> detections -> records (frame, row, col order).
-    gain and offset are scalars or per-pixel [h][w] maps shared by all frames."""
+    gain and offset are scalars or per-pixel [h][w] maps shared by all frames.
+    with_uncertainty (10-output heads): also the records' uncertainties, in
+    the same order; returns (records, uncertainties[, maps])."""
     tau = math.log(threshold / (1.0 - threshold))
-    recs, allmaps = [], []
+    recs, uncs, allmaps = [], [], []
     for f, F in enumerate(frames):
         m = net_maps(F, spec, weights, gain, offset, quant)
-        recs.append(records(m, detect(m[0], tau), spec, f))
+        det = detect(m[0], tau)
+        recs.append(records(m, det, spec, f))
+        if with_uncertainty:
+            uncs.append(uncertainties(m, det, spec))
         if return_maps:
             allmaps.append(m)
     r = np.concatenate(recs) if recs else np.empty(0, EMITTER_DTYPE)
-    return (r, np.stack(allmaps)) if return_maps else r
+    out = [r]
+    if with_uncertainty:
+        out.append(np.concatenate(uncs) if uncs else np.empty(0, UNCERTAINTY_DTYPE))
+    if return_maps:
+        out.append(np.stack(allmaps))
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 # -------------------------------------------------------------------- gate

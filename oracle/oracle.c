@@ -18,6 +18,8 @@
  *     t    = ReLU(conv_dk(a; W_k1, b_k1))
  *     a    = ReLU(a + conv_dk(t; W_k2, b_k2))                       residual block
  *   maps   = head(a), 1x1, C -> 5: logit, dx, dy, dz, photons
+ *            (C -> 10: then the raw uncertainties of x, y, z and photons and
+ *            the background, Sec. 3.2's per-pixel position uncertainty)
  *
  * conv_d is a cross-correlation with taps spaced d pixels apart and zero
  * "same" padding applied at the true frame border at every layer:
@@ -215,18 +217,19 @@ static void quant_weights_fp8(double *W, int cout, long per_out)
     }
 }
 
-/* The network on the preprocessed input x [h][w]. */
+/* The network on the preprocessed input x [h][w]; nh head outputs. */
 static int net_maps_from_input(const double *x, int h, int w, const float *params, int C, int nblocks,
-                               const int *dil, int quant, double *maps /* [5][h][w] */)
+                               const int *dil, int quant, int nh, double *maps /* [nh][h][w] */)
 {
     if (h <= 0 || w <= 0 || C <= 0 || nblocks < 0 || quant < 0 || quant > 2) return OR_ERR;
+    if (nh != 5 && nh != 10) return OR_ERR;
     long hw = (long)h * w;
     long nconv = (long)C * C * 9;
     double *a = malloc(sizeof(double) * hw * C);
     double *t = malloc(sizeof(double) * hw * C);
     double *u = malloc(sizeof(double) * hw * C);
     double *Wd = malloc(sizeof(double) * nconv);
-    double *bd = malloc(sizeof(double) * (C > 5 ? C : 5));
+    double *bd = malloc(sizeof(double) * (C > nh ? C : nh));
     if (!a || !t || !u || !Wd || !bd) {
         free(a); free(t); free(u); free(Wd); free(bd);
         return OR_ERR;
@@ -264,11 +267,11 @@ static int net_maps_from_input(const double *x, int h, int w, const float *param
         if (quant == 2 && blk + 1 < nblocks) or_store_fp8_groups(a, C, hw);
     }
 
-    /* head: 1x1, C -> 5, FP32 weights in every mode */
-    promote(p, 5L * C, Wd); p += 5L * C;
-    promote(p, 5, bd); p += 5;
+    /* head: 1x1, C -> nh, FP32 weights in every mode */
+    promote(p, (long)nh * C, Wd); p += (long)nh * C;
+    promote(p, nh, bd); p += nh;
 #pragma omp parallel for schedule(static)
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < nh; ++q) {
         double *m = maps + (long)q * hw;
         for (long k = 0; k < hw; ++k) m[k] = bd[q];
         for (int c = 0; c < C; ++c) {
@@ -283,13 +286,13 @@ static int net_maps_from_input(const double *x, int h, int w, const float *param
 
 int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
                 double in_scale, const float *params, int C, int nblocks,
-                const int *dil, int quant, double *maps /* [5][h][w] */)
+                const int *dil, int quant, int nh, double *maps /* [nh][h][w] */)
 {
     if (h <= 0 || w <= 0) return OR_ERR;
     double *x = malloc(sizeof(double) * (long)h * w);
     if (!x) return OR_ERR;
     or_preprocess(F, (long)h * w, gain, offset, in_scale, x);
-    int rc = net_maps_from_input(x, h, w, params, C, nblocks, dil, quant, maps);
+    int rc = net_maps_from_input(x, h, w, params, C, nblocks, dil, quant, nh, maps);
     free(x);
     return rc;
 }
@@ -297,13 +300,13 @@ int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,
 /* As or_net_maps with per-pixel camera maps gain [h][w] and offset [h][w]. */
 int or_net_maps_cam(const uint16_t *F, int h, int w, const double *gain, const double *offset,
                     double in_scale, const float *params, int C, int nblocks,
-                    const int *dil, int quant, double *maps /* [5][h][w] */)
+                    const int *dil, int quant, int nh, double *maps /* [nh][h][w] */)
 {
     if (h <= 0 || w <= 0) return OR_ERR;
     double *x = malloc(sizeof(double) * (long)h * w);
     if (!x) return OR_ERR;
     or_preprocess_maps(F, (long)h * w, gain, offset, in_scale, x);
-    int rc = net_maps_from_input(x, h, w, params, C, nblocks, dil, quant, maps);
+    int rc = net_maps_from_input(x, h, w, params, C, nblocks, dil, quant, nh, maps);
     free(x);
     return rc;
 }

@@ -317,18 +317,24 @@ def render_rois(n: int, model: FrameModel | str, seed: int, sides: Sequence[int]
 @dataclass(frozen=True)
 class NetSpec:
     """Residual dilated localization network: stem 3x3 (1->C), blocks of two 3x3
-    convolutions at one dilation each, 1x1 head C->5 (logit, dx, dy, dz, photons)."""
+    convolutions at one dilation each, 1x1 head C->5 (logit, dx, dy, dz, photons)
+    or C->10 (those, then the raw uncertainties of x, y, z and photons and the
+    background)."""
     name: str
     C: int
     dilations: Tuple[int, ...]
     in_scale: float = 0.01      # photons -> network input units (background 100 -> 1.0)
     z_scale: float = 700.0      # nm per unit of the dz map
     ph_scale: float = 1000.0    # photons per unit of the photon map
+    head_outputs: int = 5       # 5, or 10 with the uncertainty planes
 
 
 NET_A = NetSpec("A", 32, (1, 2, 4))
 NET_B = NetSpec("B", 48, (1, 2, 4, 8, 16))
-NETS = {"A": NET_A, "B": NET_B}
+# the same networks with the uncertainty head (planes 5-9)
+NET_AU = NetSpec("AU", 32, (1, 2, 4), head_outputs=10)
+NET_BU = NetSpec("BU", 48, (1, 2, 4, 8, 16), head_outputs=10)
+NETS = {"A": NET_A, "B": NET_B, "AU": NET_AU, "BU": NET_BU}
 
 
 def tensor_layout(spec: NetSpec) -> List[Tuple[str, Tuple[int, ...]]]:
@@ -338,7 +344,8 @@ def tensor_layout(spec: NetSpec) -> List[Tuple[str, Tuple[int, ...]]]:
     for k in range(len(spec.dilations)):
         lay += [(f"blk{k}.w1", (C, C, 3, 3)), (f"blk{k}.b1", (C,)),
                 (f"blk{k}.w2", (C, C, 3, 3)), (f"blk{k}.b2", (C,))]
-    lay += [("head.w", (5, C)), ("head.b", (5,))]
+    nh = spec.head_outputs
+    lay += [("head.w", (nh, C)), ("head.b", (nh,))]
     return lay
 
 
@@ -349,7 +356,7 @@ def param_count(spec: NetSpec) -> int:
 def net_flops_per_px(spec: NetSpec) -> int:
     """Algorithmic FLOP per output pixel (2 per multiply-add; stem + blocks + head)."""
     C, B = spec.C, len(spec.dilations)
-    macs = 9 * C + B * 2 * 9 * C * C + 5 * C
+    macs = 9 * C + B * 2 * 9 * C * C + spec.head_outputs * C
     return 2 * macs
 
 
@@ -390,15 +397,22 @@ def load_calibration(spec: NetSpec, seed: int) -> Optional[dict]:
         return None
     with open(path) as f:
         table = json.load(f)
-    return table.get(f"{spec.name}:{seed}")
+    return table.get(f"{spec.name[:1]}:{seed}")
 
 
 def apply_calibration(weights: Dict[str, np.ndarray], calib: dict) -> Dict[str, np.ndarray]:
-    """Replace the 1x1 head by the stored calibrated head (linear probe of the
-    final features; see ``make_calibration.py``)."""
+    """Replace the 1x1 head's first five rows by the stored calibrated head
+    (linear probe of the final features; see ``make_calibration.py``).  The
+    uncertainty rows of a 10-output head keep their He-normal draws scaled by
+    0.05, with bias -1 (raw values near -1: uncertainties near softplus(-1),
+    0.31 units)."""
     w = {k: v.copy() for k, v in weights.items()}
-    w["head.w"] = np.asarray(calib["head_w"], np.float32).reshape(w["head.w"].shape)
-    w["head.b"] = np.asarray(calib["head_b"], np.float32).reshape(w["head.b"].shape)
+    C = w["head.w"].shape[1]
+    w["head.w"][:5] = np.asarray(calib["head_w"], np.float32).reshape(5, C)
+    w["head.b"][:5] = np.asarray(calib["head_b"], np.float32).reshape(5)
+    if w["head.w"].shape[0] > 5:
+        w["head.w"][5:] *= np.float32(0.05)
+        w["head.b"][5:] = np.float32(-1.0)
     return w
 
 
@@ -418,15 +432,18 @@ def serialize_weights(spec: NetSpec, weights: Dict[str, np.ndarray]) -> bytes:
     """Little-endian ``DLW1`` blob.
 
     Header (64 bytes): magic 'DLW1', u32 version, u32 C, u32 nblocks,
-    u32 dilation[8], f32 in_scale, f32 z_scale, f32 ph_scale, u32 reserved(0),
+    u32 dilation[8], f32 in_scale, f32 z_scale, f32 ph_scale, u32 head outputs
+    (0 = 5),
     then the FP32 tensors of ``tensor_layout`` in order, C-contiguous.
     """
     nb = len(spec.dilations)
     if nb > DLW_MAX_BLOCKS:
         raise ValueError("too many blocks")
     dil = list(spec.dilations) + [0] * (DLW_MAX_BLOCKS - nb)
+    # the last header word: 0 for the 5-output head, else the head's outputs
     head = DLW_MAGIC + struct.pack("<III8IfffI", DLW_VERSION, spec.C, nb, *dil,
-                                   spec.in_scale, spec.z_scale, spec.ph_scale, 0)
+                                   spec.in_scale, spec.z_scale, spec.ph_scale,
+                                   0 if spec.head_outputs == 5 else spec.head_outputs)
     assert len(head) == 64
     body = b"".join(np.ascontiguousarray(weights[name], dtype="<f4").tobytes()
                     for name, _ in tensor_layout(spec))
