@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--sparse-layout", default="iid", choices=["iid", "cell"],
                     help="sparse workload: empty 256^2 tiles chosen independently (iid) or around one "
                          "compact occupied region (cell)")
+    ap.add_argument("--net", default="B", choices=["B", "BU"],
+                    help="full workload: net B with the 5-output head, or BU, the same net with the "
+                         "10-output head (per-pixel uncertainties and background)")
     ap.add_argument("--camera", default="scmos", choices=["scmos", "scalar"],
                     help="full and pipeline workloads: frames from a seeded sCMOS sensor whose per-pixel gain "
                          "and offset maps the net is given (scmos), or the scalar camera model (scalar)")
@@ -93,7 +96,7 @@ def main():
         return
 
     # inputs first, before anything touches the GPU (workers are forked)
-    spec, w = S.make_net("B", 2)
+    spec, w = S.make_net(args.net, 2)
     n, side = args.frames, args.size
     t0 = time.time()
     cam = S.scmos_camera(side, side, 1002) if args.camera == "scmos" else None
@@ -154,9 +157,9 @@ def main():
         "ms_per_step_median": head["ms_per_step_median"], "ms_per_step_min": head["ms_per_step_min"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
         "data": "synthetic (seeded astigmatic-PSF SMLM frames; random-init calibrated net)",
-        "config": {"workload": f"{n} x {side}x{side} uint16 frames, astigmatic 3D PSF, net B "
-                               f"(C=48, d=1,2,4,8,16), {args.precision}",
-                   "frames": n, "height": side, "width": side, "net": "B", "precision": args.precision,
+        "config": {"workload": f"{n} x {side}x{side} uint16 frames, astigmatic 3D PSF, net {args.net} "
+                               f"(C=48, d=1,2,4,8,16, {spec.head_outputs}-output head), {args.precision}",
+                   "frames": n, "height": side, "width": side, "net": args.net, "precision": args.precision,
                    "camera": ("sCMOS per-pixel gain/offset maps (sensor seed 1002)" if cam is not None
                               else "scalar gain 0.5, offset 100"),
                    "parallelism": "single GPU"},
@@ -185,8 +188,13 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
     d_out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
     d_counts = torch.zeros(n + 1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
+    if net.head_outputs == 10:               # records and their uncertainties
+        d_unc = torch.empty((cap * 5,), dtype=torch.float32, device=dev)
+        run = lambda: net.localize_device_unc(d_frames, d_out, d_unc, d_counts, stream)  # noqa: E731
+    else:
+        run = lambda: net.localize_device(d_frames, d_out, d_counts, stream)  # noqa: E731
     for _ in range(args.warmup):
-        net.localize_device(d_frames, d_out, d_counts, stream)
+        run()
     torch.cuda.synchronize()
     net.profile(True)
     net.profile_read()
@@ -195,7 +203,7 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
     evs[0].record(stream)
     wall0 = time.perf_counter()
     for k in range(args.steps):
-        net.localize_device(d_frames, d_out, d_counts, stream)
+        run()
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -275,7 +283,7 @@ def map_errors_on_sample(net, d_frames, ref, torch, dev):
     the oracle's maps are exact: max and RMS absolute logit error, RMS error of
     the dx, dy (px) and dz (units of the dz map) planes."""
     side = d_frames.shape[1]
-    maps = torch.empty((1, 5, side, d_frames.shape[2]), dtype=torch.float32, device=dev)
+    maps = torch.empty((1, net.head_outputs, side, d_frames.shape[2]), dtype=torch.float32, device=dev)
     net.maps_device(d_frames[:1], maps)
     torch.cuda.synchronize()
     e = ref["map_extent"]
@@ -334,7 +342,7 @@ def cpu_baseline(args, spec, w, frames, net, dev, recs, cam=None):
     R = 1 + 2 * sum(spec.dilations)
     e = s if whole else s - R                 # exact maps on [0, e)^2
     lim = e if whole else e - 1               # exact detections on [0, lim)^2
-    maps = torch.empty((1, 5, args.size, args.size), dtype=torch.float32, device=dev)
+    maps = torch.empty((1, net.head_outputs, args.size, args.size), dtype=torch.float32, device=dev)
     net.maps_device(torch.from_numpy(np.ascontiguousarray(frames[:1])).to(dev), maps)
     torch.cuda.synchronize()
     g = maps[0, :, :e, :e].cpu().numpy()

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DL_ABI_VERSION 1u
+#define DL_ABI_VERSION 2u
 
 typedef enum {
     DL_OK = 0,
@@ -92,6 +92,16 @@ typedef struct {
     float x_px, y_px, z_nm, photons, prob;
 } dl_emitter;
 
+/* Uncertainties of one emitter, 20 bytes, from a network with the 10-output
+ * head (Sec. 3.2: each pixel also gives the uncertainty of the position).
+ * With u the raw head value and softplus(u) = log(1 + e^u) > 0:
+ * sigma_x_px = softplus(u5), sigma_y_px = softplus(u6), sigma_z_nm =
+ * softplus(u7) * z_scale, sigma_photons = softplus(u8) * ph_scale,
+ * background = softplus(u9) / in_scale (photons per pixel). */
+typedef struct {
+    float sigma_x_px, sigma_y_px, sigma_z_nm, sigma_photons, background;
+} dl_uncertainty;
+
 /* One region of interest of an uneven batch (device data). */
 typedef struct {
     const uint16_t *data;       /* device pointer to the ROI's first pixel */
@@ -108,6 +118,8 @@ typedef struct {
     float in_scale, z_scale, ph_scale;
     int32_t receptive_radius;   /* 1 + 2 * sum(dilation): halo a tile needs     */
     int64_t nparams;            /* FP32 values after the 64-byte header          */
+    int32_t head_outputs;       /* 5, or 10 with the uncertainty planes          */
+    int32_t reserved_;
 } dl_net_info;
 
 /* Library ABI version (DL_ABI_VERSION). */
@@ -118,9 +130,11 @@ int dl_default_config(dl_config *cfg);
 
 /* Create a network from a little-endian "DLW1" weights blob:
  *   header (64 B): char magic[4] = "DLW1"; u32 version = 1; u32 C; u32 nblocks;
- *   u32 dilation[8]; f32 in_scale; f32 z_scale; f32 ph_scale; u32 reserved;
+ *   u32 dilation[8]; f32 in_scale; f32 z_scale; f32 ph_scale; u32 nh (the head's
+ *   outputs: 0 or 5 = logit, dx, dy, dz, photons; 10 = those, then the raw
+ *   uncertainties of x, y, z and photons and the raw background);
  *   then FP32 tensors: stem.w [C][1][3][3], stem.b [C], for each block
- *   w1 [C][C][3][3], b1 [C], w2 [C][C][3][3], b2 [C]; head.w [5][C], head.b [5].
+ *   w1 [C][C][3][3], b1 [C], w2 [C][C][3][3], b2 [C]; head.w [nh][C], head.b [nh].
  * Network (Sec. 3.2, Sec. 3.2.1): x = (ADU - offset) * gain * in_scale;
  * a = ReLU(conv_1(x)); per block with dilation d: t = ReLU(conv_d(a)),
  * a = ReLU(a + conv_d(t)); maps = head(a).  Supported: C in {16, 32, 48, 64},
@@ -157,8 +171,17 @@ int dl_set_config(dl_net *net, const dl_config *cfg);
 int dl_localize_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
                        void *stream, dl_emitter *d_out, size_t cap, uint32_t *d_counts);
 
-/* Per-pixel maps of the network, device-resident: d_maps float [n][5][h][w]
- * (logit, dx, dy, dz, photons before scaling).  For parity checks. */
+/* dl_localize_device for a network with the 10-output head, also writing
+ * each record's uncertainties: d_unc device dl_uncertainty[cap], entry i
+ * belongs to d_out[i] (4-byte aligned; may be NULL only when cap is 0).
+ * DL_ERR_UNSUPPORTED for a 5-output network. */
+int dl_localize_device_unc(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
+                           void *stream, dl_emitter *d_out, dl_uncertainty *d_unc, size_t cap,
+                           uint32_t *d_counts);
+
+/* Per-pixel maps of the network, device-resident: d_maps float [n][nh][h][w]
+ * with nh the head's outputs (5: logit, dx, dy, dz, photons before scaling;
+ * 10: then the raw uncertainty and background planes).  For parity checks. */
 int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
                    void *stream, float *d_maps);
 
@@ -204,8 +227,8 @@ int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n
 int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream,
                             dl_emitter *d_out, size_t cap, uint32_t *d_counts);
 
-/* Maps of an uneven ROI batch: ROI k's maps [5][h_k][w_k] start at
- * d_maps + 5 * sum_{j<k} h_j * w_j. */
+/* Maps of an uneven ROI batch: ROI k's maps [nh][h_k][w_k] start at
+ * d_maps + nh * sum_{j<k} h_j * w_j. */
 int dl_maps_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, float *d_maps);
 
 /* ---- autotuning ----

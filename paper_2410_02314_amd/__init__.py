@@ -35,6 +35,9 @@ NSTAGES = 8
 EMITTER_DTYPE = np.dtype([("frame", "<i4"), ("row", "<i4"), ("col", "<i4"), ("x_px", "<f4"),
                           ("y_px", "<f4"), ("z_nm", "<f4"), ("photons", "<f4"), ("prob", "<f4")])
 assert EMITTER_DTYPE.itemsize == 32
+UNCERTAINTY_DTYPE = np.dtype([("sigma_x_px", "<f4"), ("sigma_y_px", "<f4"), ("sigma_z_nm", "<f4"),
+                              ("sigma_photons", "<f4"), ("background", "<f4")])
+assert UNCERTAINTY_DTYPE.itemsize == 20
 
 
 class DLConfig(ctypes.Structure):
@@ -52,7 +55,8 @@ class DLRoi(ctypes.Structure):
 class DLNetInfo(ctypes.Structure):
     _fields_ = [("C", ctypes.c_int32), ("nblocks", ctypes.c_int32), ("dilation", ctypes.c_int32 * 8),
                 ("in_scale", ctypes.c_float), ("z_scale", ctypes.c_float), ("ph_scale", ctypes.c_float),
-                ("receptive_radius", ctypes.c_int32), ("nparams", ctypes.c_int64)]
+                ("receptive_radius", ctypes.c_int32), ("nparams", ctypes.c_int64),
+                ("head_outputs", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class DlocError(RuntimeError):
@@ -81,6 +85,7 @@ def _load():
         "dl_last_error": (ctypes.c_char_p, [P]),
         "dl_set_config": (I, [P, ctypes.POINTER(DLConfig)]),
         "dl_localize_device": (I, [P, P, I, I, I, P, P, Z, P]),
+        "dl_localize_device_unc": (I, [P, P, I, I, I, P, P, P, Z, P]),
         "dl_maps_device": (I, [P, P, I, I, I, P, P]),
         "dl_localize": (I, [P, P, I, I, I, P, Z, ctypes.POINTER(Z)]),
         "dl_localize_pipelined": (I, [P, P, I, I, I, I, I, P, Z, ctypes.POINTER(Z)]),
@@ -178,7 +183,7 @@ def inspect_weights(weights: bytes) -> dict:
     _check(_lib.dl_inspect_weights(buf, len(weights), ctypes.byref(info)))
     return {"C": info.C, "nblocks": info.nblocks, "dilations": tuple(info.dilation[:info.nblocks]),
             "in_scale": info.in_scale, "z_scale": info.z_scale, "ph_scale": info.ph_scale,
-            "receptive_radius": info.receptive_radius, "nparams": info.nparams}
+            "receptive_radius": info.receptive_radius, "nparams": info.nparams, "head_outputs": info.head_outputs}
 
 
 def create_net(weights: bytes, **cfg) -> "Net":
@@ -194,6 +199,9 @@ class Net:
         buf = ctypes.create_string_buffer(bytes(weights), len(weights))
         _check(_lib.dl_create_net(buf, len(weights), ctypes.byref(self.config), ctypes.byref(h)))
         self.handle = h
+        info = DLNetInfo()
+        _check(_lib.dl_inspect_weights(buf, len(weights), ctypes.byref(info)))
+        self.head_outputs = int(info.head_outputs)     # planes of the maps: 5, or 10 with uncertainties
 
     def close(self):
         if getattr(self, "handle", None):
@@ -224,6 +232,16 @@ class Net:
         cap = out.numel() * out.element_size() // 32
         return self._rc(_lib.dl_localize_device(self.handle, _ptr(frames), n, h, w, _stream(stream),
                                                 _ptr(out), cap, _ptr(counts)))
+
+    def localize_device_unc(self, frames, out, unc, counts, stream=None) -> int:
+        """localize_device for a 10-output network, also filling unc (cuda
+        tensor of cap * 20 bytes, one dl_uncertainty per record)."""
+        n, h, w = frames.shape
+        cap = out.numel() * out.element_size() // 32
+        if unc.numel() * unc.element_size() < cap * 20:
+            raise ValueError("unc holds fewer records than out")
+        return self._rc(_lib.dl_localize_device_unc(self.handle, _ptr(frames), n, h, w, _stream(stream),
+                                                    _ptr(out), _ptr(unc), cap, _ptr(counts)))
 
     def maps_device(self, frames, maps, stream=None) -> int:
         n, h, w = frames.shape
@@ -367,6 +385,12 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def uncertainties_from_device(unc, counts_total: int) -> np.ndarray:
+    """Copy the first ``counts_total`` dl_uncertainty entries to a numpy structured array."""
+    raw = unc.reshape(-1).view(__import__("torch").uint8)[: counts_total * 20].cpu().numpy()
+    return raw.view(UNCERTAINTY_DTYPE).copy()
 
 
 def emitters_from_device(out, counts_total: int) -> np.ndarray:

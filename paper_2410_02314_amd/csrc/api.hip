@@ -27,7 +27,10 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 thread_local std::string g_err;   // errors with no handle
 
-size_t param_count(int C, int nb) { return (size_t)C * 9 + C + (size_t)nb * 2 * ((size_t)C * C * 9 + C) + 5 * (size_t)C + 5; }
+size_t param_count(int C, int nb, int nh)
+{
+    return (size_t)C * 9 + C + (size_t)nb * 2 * ((size_t)C * C * 9 + C) + (size_t)nh * C + nh;
+}
 
 }  // namespace
 
@@ -35,6 +38,7 @@ struct dl_net {
     dl_config cfg{};
     int dev = 0, ncu = 256;
     int C = 0, nb = 0;
+    int nh = 5;                     // head outputs: 5, or 10 with the uncertainty planes
     int dil[8] = {0};
     float in_scale = 0.f, z_scale = 0.f, ph_scale = 0.f;
     std::vector<float> params;
@@ -226,7 +230,7 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     p.act0 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
     p.act1 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
     p.act2 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
-    p.maps = o; if (!ext_maps) o = align_up(o + (size_t)g.total_px * 5 * 4);
+    p.maps = o; if (!ext_maps) o = align_up(o + (size_t)g.total_px * net->nh * 4);
     p.mask = o; o = align_up(o + (size_t)g.total_words * 8);
     p.rc = o; o = align_up(o + (size_t)g.total_rows * 4);
     p.roff = o; o = align_up(o + (size_t)(g.total_rows + 1) * 4);
@@ -436,6 +440,7 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         if (b == net->nb - 1) {
             a.head = net->d_head;
             a.maps = maps;
+            a.nh = net->nh;
             a.out = nullptr;
         }
         StageTimer t(net, b == net->nb - 1 ? DL_STAGE_CONV_HEAD : DL_STAGE_CONV, s);
@@ -446,7 +451,7 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
 }
 
 int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, const float *maps,
-             dl_emitter *d_out, size_t cap, uint32_t *d_counts, hipStream_t s)
+             dl_emitter *d_out, size_t cap, uint32_t *d_counts, hipStream_t s, dl_uncertainty *d_unc = nullptr)
 {
     const float thr = net->cfg.threshold;
     const float tau = (float)std::log((double)thr / (1.0 - (double)thr));
@@ -456,7 +461,7 @@ int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     {
         StageTimer t(net, DL_STAGE_DETECT, s);
         const uint8_t *keep = p.gated ? reinterpret_cast<const uint8_t *>(p.ws + p.keep) : nullptr;
-        HIPCHK(net, launch_detect_mask(maps, 5, d_fd, g, tau, keep, mask, rc, s));
+        HIPCHK(net, launch_detect_mask(maps, net->nh, d_fd, g, tau, keep, mask, rc, s));
     }
     {
         StageTimer t(net, DL_STAGE_SCAN, s);
@@ -464,7 +469,8 @@ int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     }
     {
         StageTimer t(net, DL_STAGE_EMIT, s);
-        HIPCHK(net, launch_emit(maps, mask, roff, d_fd, g, net->z_scale, net->ph_scale, d_out, cap, s));
+        HIPCHK(net, launch_emit(maps, net->nh, mask, roff, d_fd, g, net->z_scale, net->ph_scale, 1.f / net->in_scale,
+                                d_out, d_unc, cap, s));
     }
     return DL_OK;
 }
@@ -507,7 +513,8 @@ int check_camera(dl_net *net, bool uniform, int h, int w)
 
 int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g, hipStream_t s,
                   dl_emitter *d_out, size_t cap, uint32_t *d_counts, float *ext_maps,
-                  const uint16_t *d_frames = nullptr, int n = 0, int h = 0, int w = 0)
+                  const uint16_t *d_frames = nullptr, int n = 0, int h = 0, int w = 0,
+                  dl_uncertainty *d_unc = nullptr)
 {
     int rc;
     if ((rc = check_camera(net, d_frames != nullptr, h, w))) return rc;
@@ -528,7 +535,7 @@ int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry 
     if (p.gated && (rc = run_gate(net, d_fd, g, p, d_frames, n, h, w, s))) return rc;
     if ((rc = run_net(net, d_fd, g, p, maps, s))) return rc;
     if (d_out || d_counts)
-        if ((rc = run_post(net, d_fd, g, p, maps, d_out, cap, d_counts, s))) return rc;
+        if ((rc = run_post(net, d_fd, g, p, maps, d_out, cap, d_counts, s, d_unc))) return rc;
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
     return DL_OK;
 }
@@ -635,20 +642,24 @@ static int parse_weights(const void *weights, size_t nbytes, dl_net_info *info, 
     const unsigned char *b = static_cast<const unsigned char *>(weights);
     if (std::memcmp(b, "DLW1", 4) != 0) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "bad magic (expected DLW1)");
     // header: magic, u32 version, u32 C, u32 nblocks, u32 dilation[8], f32 in_scale,
-    // f32 z_scale, f32 ph_scale, u32 reserved
+    // f32 z_scale, f32 ph_scale, u32 head outputs (0 = 5)
     uint32_t hdr[11];
     std::memcpy(hdr, b + 4, sizeof hdr);
     const uint32_t version = hdr[0], C = hdr[1], nb = hdr[2];
     float sc[3];
     std::memcpy(sc, b + 4 + 11 * 4, sizeof sc);
     if (version != 1) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "unsupported weights version %u", version);
+    uint32_t nh_word;                                  // the header's last word (byte 60)
+    std::memcpy(&nh_word, b + 60, 4);
+    const uint32_t nh = nh_word == 0 ? 5u : nh_word;
+    if (nh != 5 && nh != 10) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "head outputs %u: 5 or 10 supported", nh);
     if (nb < 1 || nb > 8) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "nblocks %u outside 1..8", nb);
     if (!(C == 16 || C == 32 || C == 48 || C == 64))
         return fail(nullptr, DL_ERR_UNSUPPORTED, "C = %u not supported (16, 32, 48 or 64)", C);
     for (uint32_t k = 0; k < nb; ++k)
         if (hdr[3 + k] < 1 || hdr[3 + k] > 64) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "dilation %u of block %u outside 1..64", hdr[3 + k], k);
     if (!finite_all(sc, 3) || !(sc[0] > 0.f)) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "bad in_scale/z_scale/ph_scale");
-    const size_t np = param_count((int)C, (int)nb);
+    const size_t np = param_count((int)C, (int)nb, (int)nh);
     if (nbytes != 64 + np * 4)
         return fail(nullptr, DL_ERR_BAD_WEIGHTS, "blob is %zu bytes, expected %zu for C=%u, %u blocks", nbytes, 64 + np * 4, C, nb);
     std::vector<float> tmp(np);
@@ -663,6 +674,7 @@ static int parse_weights(const void *weights, size_t nbytes, dl_net_info *info, 
         info->z_scale = sc[1];
         info->ph_scale = sc[2];
         info->nparams = (int64_t)np;
+        info->head_outputs = (int32_t)nh;
         int R = 1;
         for (uint32_t k = 0; k < nb; ++k) R += 2 * (int)hdr[3 + k];
         info->receptive_radius = R;
@@ -690,7 +702,7 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     dl_net_info info;
     std::vector<float> params;
     if ((rc = parse_weights(weights, nbytes, &info, &params))) return rc;
-    if (!conv_supported(info.C, c.precision))
+    if (!conv_supported(info.C, c.precision, info.head_outputs))
         return fail(nullptr, DL_ERR_UNSUPPORTED, "C = %d does not fit the %s conv kernel's LDS", info.C,
                     c.precision == DL_FP32 ? "FP32" : c.precision == DL_BF16 ? "BF16" : "FP8");
     const uint32_t C = (uint32_t)info.C, nb = (uint32_t)info.nblocks;
@@ -711,6 +723,7 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     net->in_scale = info.in_scale;
     net->z_scale = info.z_scale;
     net->ph_scale = info.ph_scale;
+    net->nh = info.head_outputs;
     net->params = std::move(params);
 
     auto bail = [&](int code) {
@@ -722,7 +735,7 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, net->dev) == hipSuccess) net->ncu = prop.multiProcessorCount;
     const float *p = net->params.data();
-    const size_t nstem = (size_t)C * 9 + C, nhead = 5 * (size_t)C + 5;
+    const size_t nstem = (size_t)C * 9 + C, nhead = (size_t)net->nh * C + net->nh;
     if (hipMalloc(&net->d_stem, nstem * 4) != hipSuccess || hipMalloc(&net->d_head, nhead * 4) != hipSuccess ||
         hipMalloc(&net->d_bias, (size_t)nb * 2 * C * 4) != hipSuccess)
         return bail(fail(net, DL_ERR_OOM, "hipMalloc of weights failed"));
@@ -814,6 +827,8 @@ int dl_set_config(dl_net *net, const dl_config *cfg)
     int rc = check_config(net, cfg);
     if (rc) return rc;
     if (cfg->device != net->cfg.device) return fail(net, DL_ERR_INVALID_ARG, "device cannot change");
+    if (!conv_supported(net->C, cfg->precision, net->nh))
+        return fail(net, DL_ERR_UNSUPPORTED, "C = %d does not fit this form's conv kernel", net->C);
     const int old = net->cfg.precision;
     net->cfg = *cfg;
     if (cfg->precision != old) {
@@ -886,6 +901,24 @@ int dl_localize_device(dl_net *net, const uint16_t *d_frames, int n, int h, int 
     Geometry g;
     uniform_geometry(net, d_frames, n, h, w, fd, g);
     return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr, d_frames, n, h, w);
+}
+
+int dl_localize_device_unc(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream,
+                           dl_emitter *d_out, dl_uncertainty *d_unc, size_t cap, uint32_t *d_counts)
+{
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (net->nh != 10) return fail(net, DL_ERR_UNSUPPORTED, "the network has no uncertainty head (%d outputs)", net->nh);
+    if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
+    if (cap > 0 && (!d_out || !d_unc)) return fail(net, DL_ERR_INVALID_ARG, "d_out or d_unc is NULL with cap > 0");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_counts) % 4 ||
+        reinterpret_cast<uintptr_t>(d_unc) % 4)
+        return fail(net, DL_ERR_INVALID_ARG, "d_out must be 16-byte, d_unc and d_counts 4-byte aligned");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, d_frames, n, h, w, fd, g);
+    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr, d_frames, n, h, w,
+                         cap ? d_unc : nullptr);
 }
 
 int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, float *d_maps)

@@ -206,8 +206,9 @@ struct ConvArgs {
     const void *wpk;         // packed weights
     const float *bias;       // [C]
     const float *wscale;     // FP8: per-output-channel weight scale [C]
-    const float *head;       // fused head: w [5][C] then b [5]; null = no head
-    float *maps;             // fused head output, planar [5][h][w] per frame
+    const float *head;       // fused head: w [nh][C] then b [nh]; null = no head
+    float *maps;             // fused head output, planar [nh][h][w] per frame
+    int nh;                  // head outputs: 5, or 10 with the uncertainty planes
     const FrameDesc *fd;
     int d;
     int blk;                 // block index: selects the frame's tile numbering
@@ -222,7 +223,7 @@ hipError_t launch_conv(int C, int precision, const ConvArgs &a, const Geometry &
 void conv_tile_shape(int C, int precision, int rows, int *tr, int *tc);
 int conv_max_grid(int C, int precision, int tr, int ncu);
 // does the conv kernel of this channel count and form fit in LDS (both tile heights)?
-bool conv_supported(int C, int precision);
+bool conv_supported(int C, int precision, int nh);
 size_t conv_packed_bytes(int C, int precision);
 // pack one 3x3 C->C layer W [C][C][3][3]; FP8 also writes scale[C]
 void pack_conv_weights(int C, int precision, const float *W, void *dst, float *scale);
@@ -233,9 +234,11 @@ hipError_t launch_detect_mask(const float *maps, int planes, const FrameDesc *fd
                               const uint8_t *keep, uint64_t *mask, uint32_t *row_counts, hipStream_t s);
 hipError_t launch_scan(const uint32_t *row_counts, const FrameDesc *fd, const Geometry &g,
                        uint32_t *row_off, uint32_t *counts, hipStream_t s);
-hipError_t launch_emit(const float *maps, const uint64_t *mask, const uint32_t *row_off,
+// maps has `planes` planes per frame; with unc (10 planes) each record's
+// uncertainties go to unc[i] beside out[i]
+hipError_t launch_emit(const float *maps, int planes, const uint64_t *mask, const uint32_t *row_off,
                        const FrameDesc *fd, const Geometry &g, float z_scale, float ph_scale,
-                       dl_emitter *out, uint64_t cap, hipStream_t s);
+                       float bg_scale, dl_emitter *out, dl_uncertainty *unc, uint64_t cap, hipStream_t s);
 hipError_t launch_mask_to_u8(const uint64_t *mask, const FrameDesc *fd, const Geometry &g,
                              uint8_t *det, hipStream_t s);
 

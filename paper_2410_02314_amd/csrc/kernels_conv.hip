@@ -167,7 +167,8 @@ template <> struct TileShape<DL_FP8> { static constexpr int TC = 64; };
 // waves per SIMD
 template <int P, int TR> constexpr int min_waves() { return P == DL_FP32 && TR == 4 ? 3 : 2; }
 
-template <int C, int P, int TR_>
+// NHL: head outputs the LDS holds weights for (5, or 10 with uncertainties)
+template <int C, int P, int TR_, int NHL = 5>
 struct Lds {
     static constexpr int TR = TR_, TC = TileShape<P>::TC;
     // bytes per point; FP8 points hold the tap's padded CT codes (the padding
@@ -178,15 +179,15 @@ struct Lds {
     static constexpr int PW = TC + 2;
     static constexpr int NPT = (TR + 2) * PW;
     static constexpr int TBYTES = align16(NPT * PS);
-    static constexpr int EXTRA = C * 4 + (5 * C + 5) * 4 + C * 4 + 64;  // bias, head, scales, alignment
+    static constexpr int EXTRA = C * 4 + (NHL * C + NHL) * 4 + C * 4 + 64;  // bias, head, scales, alignment
     // FP32 keeps its weights in LDS when they fit beside the tile (C <= 48 at
     // 8 rows); otherwise each K iteration reads them from L2, one ahead
     static constexpr bool LDSW_FP32 = TBYTES + KPlan<C, P>::BYTES + EXTRA <= 160 * 1024;
     static constexpr int LDSW = P == DL_FP32 ? (LDSW_FP32 ? KPlan<C, P>::BYTES : 0) : KPlan<C, P>::LDS_W;
     static constexpr int WOFF = TBYTES;
     static constexpr int BOFF = WOFF + LDSW;                           // bias [C]
-    static constexpr int HOFF = BOFF + C * 4;                          // head [5C + 5]
-    static constexpr int SOFF = HOFF + (5 * C + 5) * 4;                // FP8 weight scales [C]
+    static constexpr int HOFF = BOFF + C * 4;                          // head [NHL C + NHL]
+    static constexpr int SOFF = HOFF + (NHL * C + NHL) * 4;            // FP8 weight scales [C]
     // BF16 and FP8 stage each wave's output row (TC pixels x C BF16 values or
     // e4m3 codes, pixel-major) so it leaves in whole 16-byte lanes; FP8 adds
     // the row's residual scales and output scales (2 bytes per pixel each)
@@ -209,11 +210,14 @@ struct TileDec {
 };
 
 // --------------------------------------------------------------- kernel
-template <int C, int P, int TR_, bool RES, bool HEAD>
+// NH: outputs of the fused 1x1 head (0: no head, the layer's activations are
+// stored; 5 or 10: the head's maps are stored instead)
+template <int C, int P, int TR_, bool RES, int NH>
 __global__ void __launch_bounds__(TR_ * 64, (min_waves<P, TR_>()))
 k_conv(ConvArgs a, Geometry geo)
 {
-    using L = Lds<C, P, TR_>;
+    constexpr bool HEAD = NH > 0;
+    using L = Lds<C, P, TR_, (NH > 5 ? NH : 5)>;
     constexpr int TR = L::TR, TC = L::TC, PS = L::PS, PW = L::PW, NPT = L::NPT;
     constexpr int NB = C / 16, PB = TC / 16, NT = TR * 64;
     extern __shared__ v4f smem[];
@@ -234,7 +238,7 @@ k_conv(ConvArgs a, Geometry geo)
     }
     for (int i = tid; i < C; i += NT) sB[i] = a.bias[i];
     if (HEAD)
-        for (int i = tid; i < 5 * C + 5; i += NT) sH[i] = a.head[i];
+        for (int i = tid; i < NH * C + NH; i += NT) sH[i] = a.head[i];
     if constexpr (P == DL_FP8) {
         for (int i = tid; i < C; i += NT) sS[i] = a.wscale[i];
         // the channel padding of every point must read as e4m3 zero (never
@@ -687,7 +691,9 @@ k_conv(ConvArgs a, Geometry geo)
             const int xo = X0 + dd * (16 * p + j);
             const bool ok = xo < W;
             const int spx = 16 * p + j;                      // this lane's pixel in the staged row
-            float h0 = 0.f, h1 = 0.f, h2 = 0.f, h3 = 0.f, h4 = 0.f;
+            float hh[NH > 0 ? NH : 1];                        // head partial sums of this lane's channels
+#pragma unroll
+            for (int q = 0; q < (NH > 0 ? NH : 1); ++q) hh[q] = 0.f;
             v4f vs[P == DL_FP8 && STAGE ? NB : 1];           // FP8: quantised once all NB are known
             if constexpr (RES && !STAGE && !EARLY_RES) load_res(p);
 #pragma unroll
@@ -728,13 +734,9 @@ k_conv(ConvArgs a, Geometry geo)
                     Store<P>::bstore4(orow, ok && row_ok ? (out_point(xo) * C + oc) * ESZ : BUF_OOB, v);
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        h0 += sH[0 * C + oc + r] * v[r];
-                        h1 += sH[1 * C + oc + r] * v[r];
-                        h2 += sH[2 * C + oc + r] * v[r];
-                        h3 += sH[3 * C + oc + r] * v[r];
-                        h4 += sH[4 * C + oc + r] * v[r];
-                    }
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int q = 0; q < NH; ++q) hh[q] += sH[q * C + oc + r] * v[r];
                 }
             }
             if constexpr (STAGE && P == DL_FP8) {
@@ -760,17 +762,19 @@ k_conv(ConvArgs a, Geometry geo)
                 if (kq == 0) *reinterpret_cast<uint16_t *>(sO + L::OSOFF + spx * 2) = (uint16_t)(sbyte[0] | (sbyte[1] << 8));
             }
             if constexpr (HEAD) {
-                h0 += __shfl_xor(h0, 16); h0 += __shfl_xor(h0, 32);
-                h1 += __shfl_xor(h1, 16); h1 += __shfl_xor(h1, 32);
-                h2 += __shfl_xor(h2, 16); h2 += __shfl_xor(h2, 32);
-                h3 += __shfl_xor(h3, 16); h3 += __shfl_xor(h3, 32);
-                h4 += __shfl_xor(h4, 16); h4 += __shfl_xor(h4, 32);
+                // the four lane groups hold disjoint channel subsets of the pixel
+#pragma unroll
+                for (int q = 0; q < NH; ++q) {
+                    hh[q] += __shfl_xor(hh[q], 16);
+                    hh[q] += __shfl_xor(hh[q], 32);
+                }
                 if (ok && row_ok) {
                     const int64_t plane = (int64_t)H * W;
-                    float *mp = a.maps + 5 * px_off + (int64_t)yo * W + xo;
-                    const float mine = kq == 0 ? h0 : kq == 1 ? h1 : kq == 2 ? h2 : h3;
-                    mp[kq * plane] = mine + sH[5 * C + kq];
-                    if (kq == 0) mp[4 * plane] = h4 + sH[5 * C + 4];
+                    float *mp = a.maps + NH * px_off + (int64_t)yo * W + xo;
+                    // lane group kq writes planes kq, kq + 4, kq + 8
+#pragma unroll
+                    for (int q = 0; q < NH; ++q)
+                        if ((q & 3) == kq) mp[q * plane] = hh[q] + sH[NH * C + q];
                 }
             }
         }
@@ -798,14 +802,15 @@ k_conv(ConvArgs a, Geometry geo)
 }
 
 // ------------------------------------------------------------- launchers
-template <int C, int P, int TR, bool RES, bool HEAD>
+template <int C, int P, int TR, bool RES, int NH>
 hipError_t launch_t(const ConvArgs &a, const Geometry &g, int grid, hipStream_t s)
 {
-    if constexpr (!Lds<C, P, TR>::FITS) {
+    using L = Lds<C, P, TR, (NH > 5 ? NH : 5)>;
+    if constexpr (!L::FITS) {
         return hipErrorInvalidValue;
     } else {
-        auto kern = k_conv<C, P, TR, RES, HEAD>;
-        constexpr size_t sh = Lds<C, P, TR>::TOTAL;
+        auto kern = k_conv<C, P, TR, RES, NH>;
+        constexpr size_t sh = L::TOTAL;
         static bool attr = false;
         if (!attr) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -821,9 +826,9 @@ hipError_t launch_t(const ConvArgs &a, const Geometry &g, int grid, hipStream_t 
 template <int C, int P, int TR>
 hipError_t launch_ct(const ConvArgs &a, const Geometry &g, int grid, hipStream_t s)
 {
-    if (a.head) return launch_t<C, P, TR, true, true>(a, g, grid, s);
-    if (a.res) return launch_t<C, P, TR, true, false>(a, g, grid, s);
-    return launch_t<C, P, TR, false, false>(a, g, grid, s);
+    if (a.head) return a.nh == 10 ? launch_t<C, P, TR, true, 10>(a, g, grid, s) : launch_t<C, P, TR, true, 5>(a, g, grid, s);
+    if (a.res) return launch_t<C, P, TR, true, 0>(a, g, grid, s);
+    return launch_t<C, P, TR, false, 0>(a, g, grid, s);
 }
 
 template <int C, int P>
@@ -841,7 +846,7 @@ int blocks_per_cu()
         return 1;
     } else {
         int nb = 0;
-        auto kern = k_conv<C, P, TR, true, false>;
+        auto kern = k_conv<C, P, TR, true, 0>;
         constexpr size_t sh = Lds<C, P, TR>::TOTAL;
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)sh);
@@ -850,16 +855,22 @@ int blocks_per_cu()
     }
 }
 
-template <int P>
-bool fits_p(int C)
+template <int P, int NHL>
+bool fits_pn(int C)
 {
     switch (C) {
-    case 16: return Lds<16, P, 4>::FITS && Lds<16, P, 8>::FITS;
-    case 32: return Lds<32, P, 4>::FITS && Lds<32, P, 8>::FITS;
-    case 48: return Lds<48, P, 4>::FITS && Lds<48, P, 8>::FITS;
-    case 64: return Lds<64, P, 4>::FITS && Lds<64, P, 8>::FITS;
+    case 16: return Lds<16, P, 4, NHL>::FITS && Lds<16, P, 8, NHL>::FITS;
+    case 32: return Lds<32, P, 4, NHL>::FITS && Lds<32, P, 8, NHL>::FITS;
+    case 48: return Lds<48, P, 4, NHL>::FITS && Lds<48, P, 8, NHL>::FITS;
+    case 64: return Lds<64, P, 4, NHL>::FITS && Lds<64, P, 8, NHL>::FITS;
     default: return false;
     }
+}
+
+template <int P>
+bool fits_p(int C, int nh)
+{
+    return nh == 10 ? fits_pn<P, 10>(C) : fits_pn<P, 5>(C);
 }
 
 template <int P>
@@ -939,11 +950,11 @@ void conv_tile_shape(int C, int precision, int rows, int *tr, int *tc)
     }
 }
 
-bool conv_supported(int C, int precision)
+bool conv_supported(int C, int precision, int nh)
 {
-    if (precision == DL_FP32) return fits_p<DL_FP32>(C);
-    if (precision == DL_BF16) return fits_p<DL_BF16>(C);
-    if (precision == DL_FP8) return fits_p<DL_FP8>(C);
+    if (precision == DL_FP32) return fits_p<DL_FP32>(C, nh);
+    if (precision == DL_BF16) return fits_p<DL_BF16>(C, nh);
+    if (precision == DL_FP8) return fits_p<DL_FP8>(C, nh);
     return false;
 }
 

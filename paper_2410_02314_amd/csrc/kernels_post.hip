@@ -247,9 +247,10 @@ k_scan(const uint32_t *__restrict__ rc, int64_t R, const FrameDesc *__restrict__
 // row_off[row] + (detections before it in raster order).  Records beyond
 // `cap` are dropped (the total is still reported by the scan).
 __global__ void __launch_bounds__(256)
-k_emit(const float *__restrict__ maps, const uint64_t *__restrict__ mask,
+k_emit(const float *__restrict__ maps, int planes, const uint64_t *__restrict__ mask,
        const uint32_t *__restrict__ row_off, const FrameDesc *__restrict__ fdp, int nf,
-       float z_scale, float ph_scale, dl_emitter *__restrict__ out, uint64_t cap)
+       float z_scale, float ph_scale, float bg_scale, dl_emitter *__restrict__ out,
+       dl_uncertainty *__restrict__ unc, uint64_t cap)
 {
     const int64_t row = blockIdx.x;
     const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
@@ -257,7 +258,7 @@ k_emit(const float *__restrict__ maps, const uint64_t *__restrict__ mask,
     const int y = (int)(row - fd.row_start);
     const int W = fd.w;
     const int64_t plane = (int64_t)fd.h * W;
-    const float *M = maps + 5 * fd.px_off + (int64_t)y * W;
+    const float *M = maps + planes * fd.px_off + (int64_t)y * W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ uint32_t sc[4];
     uint32_t base = row_off[row];
@@ -286,6 +287,17 @@ k_emit(const float *__restrict__ maps, const uint64_t *__restrict__ mask,
                 e.photons = M[4 * plane + x] * ph_scale;
                 e.prob = 1.f / (1.f + expf(-lg));
                 out[idx] = e;
+                if (unc) {
+                    // softplus(u) = max(u, 0) + log1p(exp(-|u|)): positive, no overflow
+                    auto sp = [](float u) { return fmaxf(u, 0.f) + log1pf(expf(-fabsf(u))); };
+                    dl_uncertainty q;
+                    q.sigma_x_px = sp(M[5 * plane + x]);
+                    q.sigma_y_px = sp(M[6 * plane + x]);
+                    q.sigma_z_nm = sp(M[7 * plane + x]) * z_scale;
+                    q.sigma_photons = sp(M[8 * plane + x]) * ph_scale;
+                    q.background = sp(M[9 * plane + x]) * bg_scale;
+                    unc[idx] = q;
+                }
             }
         }
         base += tot;
@@ -414,12 +426,12 @@ hipError_t launch_scan(const uint32_t *row_counts, const FrameDesc *fd, const Ge
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const float *maps, const uint64_t *mask, const uint32_t *row_off,
+hipError_t launch_emit(const float *maps, int planes, const uint64_t *mask, const uint32_t *row_off,
                        const FrameDesc *fd, const Geometry &g, float z_scale, float ph_scale,
-                       dl_emitter *out, uint64_t cap, hipStream_t s)
+                       float bg_scale, dl_emitter *out, dl_uncertainty *unc, uint64_t cap, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, mask, row_off, fd, g.nf,
-                       z_scale, ph_scale, out, cap);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, mask, row_off, fd, g.nf,
+                       z_scale, ph_scale, bg_scale, out, unc, cap);
     return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_defaults():
-    assert dl.abi_version() == 1
+    assert dl.abi_version() == 2
     c = dl.DLConfig()
     assert dl.lib().dl_default_config(ctypes.byref(c)) == 0
     assert (c.precision, c.device, c.flags, c.tile_rows) == (0, 0, 0, 0)
@@ -44,12 +44,13 @@ def blob(name="A", seed=1):
     return spec, w, S.serialize_weights(spec, w)
 
 
-@pytest.mark.parametrize("name", ["A", "B"])
+@pytest.mark.parametrize("name", ["A", "B", "AU", "BU"])
 def test_inspect_weights_reads_header(name):
-    spec, w, b = blob(name)
+    spec, w, b = blob(name, 1 if name[0] == "A" else 2)
     info = dl.inspect_weights(b)
     assert info["C"] == spec.C and info["dilations"] == spec.dilations
     assert info["nparams"] == S.param_count(spec)
+    assert info["head_outputs"] == spec.head_outputs
     assert info["receptive_radius"] == S.receptive_radius(spec)
     assert math.isclose(info["in_scale"], spec.in_scale, rel_tol=1e-7)
     assert info["z_scale"] == spec.z_scale and info["ph_scale"] == spec.ph_scale
@@ -81,6 +82,12 @@ def test_bad_blobs_are_rejected():
     bad = bytearray(b); bad[100:104] = struct.pack("<f", float("nan"))
     assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS                           # NaN weight
     assert "NaN" in dl.last_error()
+    bad = bytearray(b); bad[60:64] = struct.pack("<I", 7)
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS                           # head outputs not 5 or 10
+    bad = bytearray(b); bad[60:64] = struct.pack("<I", 10)
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS                           # 10 outputs: blob too short
+    bad = bytearray(b); bad[60:64] = struct.pack("<I", 5)
+    assert _code(bad) == 0                                               # 5 written out
     assert dl.lib().dl_inspect_weights(None, 10, ctypes.byref(dl.DLNetInfo())) == dl.DL_ERR_INVALID_ARG
 
 

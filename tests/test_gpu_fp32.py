@@ -32,7 +32,7 @@ def make(name="A", seed=1, bias_std=0.0, **cfg):
 def gpu_maps(net, frames):
     n, h, w = frames.shape
     fr = torch.from_numpy(np.ascontiguousarray(frames)).to(DEV)
-    maps = torch.full((n, 5, h, w), float("nan"), dtype=torch.float32, device=DEV)
+    maps = torch.full((n, net.head_outputs, h, w), float("nan"), dtype=torch.float32, device=DEV)
     net.maps_device(fr, maps)
     torch.cuda.synchronize()
     return maps.cpu().numpy()
@@ -52,7 +52,7 @@ def gpu_localize(net, frames, cap=None):
 
 
 def test_abi_version():
-    assert dl.abi_version() == 1
+    assert dl.abi_version() == 2
 
 
 def test_tiny_config_maps_and_emitters():
