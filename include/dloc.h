@@ -347,8 +347,9 @@ int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, floa
  *       runs register-resident chains of the MFMA each form's convolution
  *       uses (16x16x4 f32, 16x16x32 bf16, 16x16x128 scaled e4m3); `bytes`
  *       is ignored;
- *   DL_RATE_HBM_COPY  GB/s read plus written by a device-to-device copy
- *       kernel of `bytes` (a multiple of 16) each way.
+ *   DL_RATE_HBM_COPY  GB/s read plus written by the best of three
+ *       device-to-device copies of `bytes` (a multiple of 16) each way: the
+ *       runtime's copy, a grid-stride kernel and a chunked kernel.
  * *value = the best of `reps` timed launches (after one untimed launch).
  * Synchronous; allocates and frees its own buffers and stream.  Returns
  * DL_ERR_INVALID_ARG or DL_ERR_DEVICE; no handle records the text. */

@@ -63,6 +63,14 @@ __global__ __launch_bounds__(RP_THREADS) void k_mfma_rate(int iters, int flag, f
     if (flag) sink[blockIdx.x * RP_THREADS + t] = s;
 }
 
+// Grid-stride copy of n 16-byte words.
+__global__ __launch_bounds__(RP_THREADS) void k_copy_stride(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                            size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * RP_THREADS;
+    for (size_t i = (size_t)blockIdx.x * RP_THREADS + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 // Copy of n 16-byte words: each workgroup moves one contiguous chunk of
 // RP_COPY_UNROLL * RP_THREADS words, with all its loads issued before its
 // stores.
@@ -108,20 +116,33 @@ extern "C" int dl_measure_rate(int what, size_t bytes, int reps, double *value)
     double best_ms = 0.0;
     if (ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) && ok(hipEventCreate(&e0)) && ok(hipEventCreate(&e1))) {
         if (what == DL_RATE_HBM_COPY) {
+            // the best of three copies: the runtime's device-to-device copy, a
+            // grid-stride kernel and a chunked kernel with eight loads in flight
             if (ok(hipMalloc(&a, bytes)) && ok(hipMalloc(&b, bytes)) && ok(hipMemsetAsync(a, 0, bytes, s))) {
                 const size_t n = bytes / 16;
                 const size_t per = (size_t)RP_COPY_UNROLL * RP_THREADS;
-                const int grid = (int)((n + per - 1) / per);
-                for (int r = 0; r <= reps && rc == DL_OK; ++r) {   // launch 0 warms up
-                    ok(hipEventRecord(e0, s));
-                    k_copy_rate<<<grid, RP_THREADS, 0, s>>>((const uint4 *)a, (uint4 *)b, n);
-                    ok(hipGetLastError());
-                    ok(hipEventRecord(e1, s));
-                    float ms = 0.f;
-                    if (ok(hipEventSynchronize(e1)) && ok(hipEventElapsedTime(&ms, e0, e1)) && r > 0)
-                        best_ms = best_ms == 0.0 ? ms : std::min<double>(best_ms, ms);
+                const int grid_chunk = (int)((n + per - 1) / per);
+                const int grid_stride = (int)std::min<size_t>((size_t)prop.multiProcessorCount * 16,
+                                                              (n + RP_THREADS - 1) / RP_THREADS);
+                for (int variant = 0; variant < 3 && rc == DL_OK; ++variant) {
+                    best_ms = 0.0;
+                    for (int r = 0; r <= reps && rc == DL_OK; ++r) {   // launch 0 warms up
+                        ok(hipEventRecord(e0, s));
+                        if (variant == 0)
+                            ok(hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, s));
+                        else if (variant == 1)
+                            k_copy_stride<<<grid_stride, RP_THREADS, 0, s>>>((const uint4 *)a, (uint4 *)b, n);
+                        else
+                            k_copy_rate<<<grid_chunk, RP_THREADS, 0, s>>>((const uint4 *)a, (uint4 *)b, n);
+                        ok(hipGetLastError());
+                        ok(hipEventRecord(e1, s));
+                        float ms = 0.f;
+                        if (ok(hipEventSynchronize(e1)) && ok(hipEventElapsedTime(&ms, e0, e1)) && r > 0)
+                            best_ms = best_ms == 0.0 ? ms : std::min<double>(best_ms, ms);
+                    }
+                    if (rc == DL_OK && best_ms > 0.0)
+                        *value = std::max(*value, 2.0 * (double)bytes / (best_ms * 1e-3) / 1e9);
                 }
-                if (rc == DL_OK && best_ms > 0.0) *value = 2.0 * (double)bytes / (best_ms * 1e-3) / 1e9;
             }
         } else {
             // about 8 ms per launch at the published rates (64 workgroups per CU,
