@@ -279,6 +279,11 @@ void dl_host_free(void *p);
  * [n * (h/256) * (w/256)][64][64], tiles frame-major then row-major. */
 int dl_gate_pool(const uint16_t *d_frames, int n, int h, int w, float gain, float offset, float in_scale,
                  void *stream, float *d_pooled);
+/* dl_gate_pool with the handle's own preprocessing: its config's gain and
+ * offset and its weights' in_scale, or its camera maps when set (then the
+ * frames must be sensor-sized) -- the tiles a gated run of this handle
+ * pools, for training its gate. */
+int dl_gate_pool_net(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, float *d_pooled);
 /* d_logits[ntiles] = g of every pooled tile. */
 int dl_gate_forward(const float *d_pooled, int ntiles, const float *d_theta, void *stream, float *d_logits);
 /* Forward plus the gradient of sum_b d_dlogits[b] * g_b with respect to theta:

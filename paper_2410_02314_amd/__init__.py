@@ -94,6 +94,7 @@ def _load():
         "dl_host_alloc": (I, [Z, ctypes.POINTER(P)]),
         "dl_measure_rate": (I, [I, Z, I, ctypes.POINTER(ctypes.c_double)]),
         "dl_set_camera_maps": (I, [P, P, P, I, I]),
+        "dl_gate_pool_net": (I, [P, P, I, I, I, P, P]),
         "dl_host_free": (None, [P]),
         "dl_debug_conv_layer": (I, [P, P, P, I, I, I, I, I, P, P]),
         "dl_debug_detect": (I, [P, P, I, I, I, ctypes.c_float, P, P]),
@@ -345,6 +346,12 @@ class Net:
         if g.ndim != 2 or g.shape != o.shape:
             raise ValueError("gain and offset must be 2-D maps of one shape")
         self._rc(_lib.dl_set_camera_maps(self.handle, g.ctypes.data, o.ctypes.data, g.shape[0], g.shape[1]))
+
+    def gate_pool(self, frames, pooled, stream=None):
+        """Pool frames into gate tiles with this handle's preprocessing (its
+        scalars or camera maps): the tiles its gated runs see."""
+        n, h, w = frames.shape
+        self._rc(_lib.dl_gate_pool_net(self.handle, _ptr(frames), n, h, w, _stream(stream), _ptr(pooled)))
 
     def gate_keep_map(self, keep, stream=None) -> int:
         n = ctypes.c_size_t()

@@ -1427,6 +1427,20 @@ int dl_profile_read(dl_net *net, double *ms, int64_t *launches)
         if (e_ != hipSuccess) return fail(nullptr, DL_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+int dl_gate_pool_net(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, float *d_pooled)
+{
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (!d_pooled) return fail(net, DL_ERR_INVALID_ARG, "d_pooled is NULL");
+    if (h % GATE_TILE || w % GATE_TILE)
+        return fail(net, DL_ERR_UNSUPPORTED, "the tile gate needs h and w multiples of %d (got %d x %d)", GATE_TILE, h, w);
+    if ((rc = check_camera(net, true, h, w))) return rc;
+    if ((rc = set_device(net))) return rc;
+    HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * net->in_scale, net->d_cam, d_pooled,
+                                 static_cast<hipStream_t>(stream)));
+    return DL_OK;
+}
+
 int dl_gate_pool(const uint16_t *d_frames, int n, int h, int w, float gain, float offset, float in_scale,
                  void *stream, float *d_pooled)
 {

@@ -1,9 +1,10 @@
 """Training and evaluation of the tile-occupancy gate on the GPU.
 
-Every arithmetic step runs in libdloc's kernels: 4x4 pooling
-(``dl_gate_pool``), forward (``dl_gate_forward``), binary cross-entropy
-(``dl_gate_bce``, paper Sec. 3.3), backward (``dl_gate_backward``, fixed-order
-reductions) and Adam (``dl_gate_adam``).  This module only moves data:
+Every arithmetic step runs in libdloc's kernels: 4x4 pooling with the
+handle's own preprocessing (``dl_gate_pool_net``), forward
+(``dl_gate_forward``), binary cross-entropy (``dl_gate_bce``, paper Sec. 3.3),
+backward (``dl_gate_backward``, fixed-order reductions) and Adam
+(``dl_gate_adam``).  This module only moves data:
 generating labelled tiles, shuffling mini-batches and bookkeeping.
 
 Labels: a 256^2 tile is positive iff the ungated localization network emits at
@@ -20,7 +21,7 @@ from typing import Dict, List, Optional, Tuple
 import numpy as np
 
 from . import GATE_NPARAM, GATE_TILE, Net, emitters_from_device, gate_adam, gate_backward, gate_bce, \
-    gate_forward, gate_pool
+    gate_forward
 
 
 def tile_counts(rec: np.ndarray, n: int, h: int, w: int) -> np.ndarray:
@@ -39,10 +40,12 @@ def tile_labels(rec: np.ndarray, n: int, h: int, w: int) -> np.ndarray:
     return (tile_counts(rec, n, h, w) > 0).astype(np.float32)
 
 
-def labelled_tiles(net: Net, frames_iter, device, gain=0.5, offset=100.0, in_scale=0.01, with_counts=False):
-    """Pool every frame batch into gate tiles and label them with ``net``'s own
-    (ungated) detections.  frames_iter yields uint16 numpy batches [n][h][w].
-    with_counts: also return the number of detections per tile."""
+def labelled_tiles(net: Net, frames_iter, device, with_counts=False):
+    """Pool every frame batch into gate tiles with ``net``'s own preprocessing
+    (its scalars or camera maps, as its gated runs pool them) and label them
+    with its own (ungated) detections.  frames_iter yields uint16 numpy
+    batches [n][h][w].  with_counts: also return the number of detections per
+    tile."""
     import torch
     pooled, labels, counts_ = [], [], []
     for frames in frames_iter:
@@ -53,7 +56,7 @@ def labelled_tiles(net: Net, frames_iter, device, gain=0.5, offset=100.0, in_sca
         counts = torch.zeros(n + 1, dtype=torch.int32, device=device)
         net.localize_device(d, out, counts)
         p = torch.empty((n * (h // GATE_TILE) * (w // GATE_TILE), 64, 64), dtype=torch.float32, device=device)
-        gate_pool(d, p, gain, offset, in_scale)
+        net.gate_pool(d, p)
         torch.cuda.synchronize()
         total = int(counts[n].item())
         rec = emitters_from_device(out, min(total, cap))

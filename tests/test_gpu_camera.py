@@ -7,7 +7,9 @@
   emitter sets equal outside the exempt pixels), on non-square and ragged
   frames, and differ from the scalar-path result;
 * the tile gate's pooling reads the maps: its keep decisions equal the
-  oracle gate's on pooled tiles preprocessed with the maps;
+  oracle gate's on pooled tiles preprocessed with the maps, and the handle's
+  own pooling entry point (what gate training uses) matches the oracle's
+  pooling with the scalars and then with the maps;
 * frames of another shape and ROI lists are refused; graphs captured under
   another camera state refuse to launch, and graphs see new values of the
   same shape.
@@ -144,3 +146,31 @@ def test_graphs_follow_the_camera_state():
         assert np.array_equal(dl.emitters_from_device(out, int(c[-1])), ref)
     g0.close()
     g1.close()
+
+
+def test_handle_gate_pool_uses_the_handle_preprocessing():
+    """dl_gate_pool_net pools with the handle's scalars, or its camera maps once
+    set: against the oracle's pooling of the preprocessed frames."""
+    h, w = 256, 512
+    cam = S.scmos_camera(h, w, 27, offset_sd=8.0)
+    frames = S.render_frames(2, h, w, "sparse", 4045, camera=cam)
+    spec, wts = S.make_net("A", 1)
+    net = dl.Net(S.serialize_weights(spec, wts))
+    fr = torch.from_numpy(frames).to(DEV)
+    for maps in (False, True):
+        if maps:
+            net.set_camera_maps(cam.gain, cam.offset)
+        p = torch.full((4, 64, 64), float("nan"), dtype=torch.float32, device=DEV)
+        net.gate_pool(fr, p)
+        torch.cuda.synchronize()
+        got = p.cpu().numpy()
+        ref = []
+        for F in frames:
+            x = oracle.preprocess(F, cam.gain if maps else 0.5, cam.offset if maps else 100.0, spec.in_scale)
+            for tx in range(2):
+                ref.append(oracle.gate_pool(x[:, tx * 256:(tx + 1) * 256], 4))
+        ref = np.stack(ref)
+        assert np.allclose(got, ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max()), maps
+    with pytest.raises(dl.DlocError) as e:
+        net.gate_pool(fr[:, :, :256].contiguous(), torch.empty((2, 64, 64), dtype=torch.float32, device=DEV))
+    assert e.value.code == dl.DL_ERR_INVALID_ARG      # not the sensor's shape
