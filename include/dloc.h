@@ -81,7 +81,9 @@ typedef struct {
     uint32_t flags;             /* DL_FLAG_*                                       */
     uint64_t max_workspace_bytes; /* device workspace cap, 0 = no cap             */
     int32_t tile_rows;          /* conv tile rows 4 or 8; 0 = the form's default   */
-    int32_t reserved[7];
+    float max_sigma_px;         /* 10-output nets: drop a detection whose sigma_x  */
+                                /* or sigma_y exceeds this (px); 0 = keep all      */
+    int32_t reserved[6];
 } dl_config;
 
 /* One detected emitter, 32 bytes.  x_px = col + 0.5 + dx, y_px = row + 0.5 + dy

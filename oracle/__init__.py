@@ -274,17 +274,29 @@ def uncertainties(maps: np.ndarray, det: np.ndarray, spec) -> np.ndarray:
     return out
 
 
+def sigma_filter(maps: np.ndarray, det: np.ndarray, max_sigma_px: float) -> np.ndarray:
+    """Uncertainty-aware post-processing of a 10-plane map: a detection is kept
+    only if sigma_x = softplus(plane 5) and sigma_y = softplus(plane 6) are both
+    <= max_sigma_px.  Applied after the local-maximum test, so a dropped
+    maximum does not promote a neighbour."""
+    assert maps.shape[0] == 10, "the uncertainty filter needs the 10-output head"
+    return det & (softplus(maps[5]) <= max_sigma_px) & (softplus(maps[6]) <= max_sigma_px)
+
+
 def localize(frames: np.ndarray, spec, weights, gain=0.5, offset=100.0, threshold=0.3,
-             quant="exact", return_maps=False, with_uncertainty=False):
+             quant="exact", return_maps=False, with_uncertainty=False, max_sigma_px=0.0):
     """Whole path: frames -> maps -> detections -> records (frame, row, col order).
     gain and offset are scalars or per-pixel [h][w] maps shared by all frames.
     with_uncertainty (10-output heads): also the records' uncertainties, in
-    the same order; returns (records, uncertainties[, maps])."""
+    the same order; returns (records, uncertainties[, maps]).  max_sigma_px > 0
+    (10-output heads): drop detections whose sigma_x or sigma_y exceeds it."""
     tau = math.log(threshold / (1.0 - threshold))
     recs, uncs, allmaps = [], [], []
     for f, F in enumerate(frames):
         m = net_maps(F, spec, weights, gain, offset, quant)
         det = detect(m[0], tau)
+        if max_sigma_px > 0:
+            det = sigma_filter(m, det, max_sigma_px)
         recs.append(records(m, det, spec, f))
         if with_uncertainty:
             uncs.append(uncertainties(m, det, spec))

@@ -44,7 +44,7 @@ class DLConfig(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("threshold", ctypes.c_float), ("gain", ctypes.c_float),
                 ("offset", ctypes.c_float), ("device", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("max_workspace_bytes", ctypes.c_uint64), ("tile_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("max_sigma_px", ctypes.c_float), ("reserved", ctypes.c_int32 * 6)]
 
 
 class DLRoi(ctypes.Structure):
@@ -143,7 +143,8 @@ def _check(rc: int, handle=None):
 
 
 def make_config(precision: str = "fp32", threshold: float = 0.3, gain: float = 0.5, offset: float = 100.0,
-                device: int = 0, flags: int = 0, max_workspace_bytes: int = 0, tile_rows: int = 0) -> DLConfig:
+                device: int = 0, flags: int = 0, max_workspace_bytes: int = 0, tile_rows: int = 0,
+                max_sigma_px: float = 0.0) -> DLConfig:
     c = DLConfig()
     _lib.dl_default_config(ctypes.byref(c))
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -154,6 +155,7 @@ def make_config(precision: str = "fp32", threshold: float = 0.3, gain: float = 0
     c.flags = flags
     c.max_workspace_bytes = max_workspace_bytes
     c.tile_rows = tile_rows
+    c.max_sigma_px = max_sigma_px
     return c
 
 

@@ -133,6 +133,8 @@ int check_config(dl_net *net, const dl_config *c)
     if (!std::isfinite(c->gain) || !(c->gain > 0.f))
         return fail(net, DL_ERR_INVALID_ARG, "gain must be finite and > 0");
     if (!std::isfinite(c->offset)) return fail(net, DL_ERR_INVALID_ARG, "offset must be finite");
+    if (!std::isfinite(c->max_sigma_px) || c->max_sigma_px < 0.f)
+        return fail(net, DL_ERR_INVALID_ARG, "max_sigma_px must be finite and >= 0");
     if (c->device < 0) return fail(net, DL_ERR_INVALID_ARG, "device must be >= 0");
     if (!(c->tile_rows == 0 || c->tile_rows == 4 || c->tile_rows == 8))
         return fail(net, DL_ERR_INVALID_ARG, "tile_rows must be 0, 4 or 8");
@@ -450,6 +452,16 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
     return DL_OK;
 }
 
+// The uncertainty filter as a bound on the raw sigma planes: sigma =
+// softplus(u) <= s iff u <= log(e^s - 1) (softplus is increasing); +inf when
+// the filter is off or the net has no uncertainty planes.
+float sigma_limit_raw(const dl_net *net)
+{
+    const double s = net->cfg.max_sigma_px;
+    if (net->nh != 10 || !(s > 0.0)) return INFINITY;
+    return (float)(s > 30.0 ? s : std::log(std::expm1(s)));
+}
+
 int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, const float *maps,
              dl_emitter *d_out, size_t cap, uint32_t *d_counts, hipStream_t s, dl_uncertainty *d_unc = nullptr)
 {
@@ -461,7 +473,7 @@ int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     {
         StageTimer t(net, DL_STAGE_DETECT, s);
         const uint8_t *keep = p.gated ? reinterpret_cast<const uint8_t *>(p.ws + p.keep) : nullptr;
-        HIPCHK(net, launch_detect_mask(maps, net->nh, d_fd, g, tau, keep, mask, rc, s));
+        HIPCHK(net, launch_detect_mask(maps, net->nh, d_fd, g, tau, sigma_limit_raw(net), keep, mask, rc, s));
     }
     {
         StageTimer t(net, DL_STAGE_SCAN, s);
@@ -702,6 +714,8 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     dl_net_info info;
     std::vector<float> params;
     if ((rc = parse_weights(weights, nbytes, &info, &params))) return rc;
+    if (c.max_sigma_px > 0.f && info.head_outputs != 10)
+        return fail(nullptr, DL_ERR_UNSUPPORTED, "max_sigma_px needs a network with the uncertainty head");
     if (!conv_supported(info.C, c.precision, info.head_outputs))
         return fail(nullptr, DL_ERR_UNSUPPORTED, "C = %d does not fit the %s conv kernel's LDS", info.C,
                     c.precision == DL_FP32 ? "FP32" : c.precision == DL_BF16 ? "BF16" : "FP8");
@@ -827,6 +841,8 @@ int dl_set_config(dl_net *net, const dl_config *cfg)
     int rc = check_config(net, cfg);
     if (rc) return rc;
     if (cfg->device != net->cfg.device) return fail(net, DL_ERR_INVALID_ARG, "device cannot change");
+    if (cfg->max_sigma_px > 0.f && net->nh != 10)
+        return fail(net, DL_ERR_UNSUPPORTED, "max_sigma_px needs a network with the uncertainty head");
     if (!conv_supported(net->C, cfg->precision, net->nh))
         return fail(net, DL_ERR_UNSUPPORTED, "C = %d does not fit this form's conv kernel", net->C);
     const int old = net->cfg.precision;
@@ -1243,7 +1259,7 @@ int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, floa
     if (slot < 0) return slot;
     uint64_t *mask = reinterpret_cast<uint64_t *>(p.ws + p.mask);
     uint32_t *rcnt = reinterpret_cast<uint32_t *>(p.ws + p.rc);
-    HIPCHK(net, launch_detect_mask(d_logit, 1, d_fd, g, tau, nullptr, mask, rcnt, s));
+    HIPCHK(net, launch_detect_mask(d_logit, 1, d_fd, g, tau, INFINITY, nullptr, mask, rcnt, s));
     HIPCHK(net, launch_mask_to_u8(mask, d_fd, g, d_det, s));
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
     return DL_OK;

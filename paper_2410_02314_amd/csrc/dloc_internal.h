@@ -230,8 +230,11 @@ void pack_conv_weights(int C, int precision, const float *W, void *dst, float *s
 
 // maps: `planes` planes per frame, the logit plane first (5 for the head
 // output, 1 for a plain logit stack)
+// u_max: with 10 planes, a candidate is kept only if its raw sigma_x and
+// sigma_y values (planes 5, 6) are <= u_max (+inf keeps all)
 hipError_t launch_detect_mask(const float *maps, int planes, const FrameDesc *fd, const Geometry &g, float tau,
-                              const uint8_t *keep, uint64_t *mask, uint32_t *row_counts, hipStream_t s);
+                              float u_max, const uint8_t *keep, uint64_t *mask, uint32_t *row_counts,
+                              hipStream_t s);
 hipError_t launch_scan(const uint32_t *row_counts, const FrameDesc *fd, const Geometry &g,
                        uint32_t *row_off, uint32_t *counts, hipStream_t s);
 // maps has `planes` planes per frame; with unc (10 planes) each record's

@@ -154,10 +154,13 @@ hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const 
 // then smaller raster index) -- a strict local maximum with a deterministic
 // tie-break, so a plateau yields exactly one detection.  Each wave turns 64
 // decisions into one 64-bit mask word (ballot); the row's count goes to
-// row_counts for the scan.
+// row_counts for the scan.  With the uncertainty planes and a finite u_max, a
+// local maximum whose raw sigma_x or sigma_y exceeds u_max is dropped (its
+// neighbours are not promoted): softplus is increasing, so this is
+// sigma <= softplus(u_max) without evaluating softplus.
 __global__ void __launch_bounds__(256)
 k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__restrict__ fdp, int nf,
-              float tau, const uint8_t *__restrict__ keep, uint64_t *__restrict__ mask,
+              float tau, float u_max, const uint8_t *__restrict__ keep, uint64_t *__restrict__ mask,
               uint32_t *__restrict__ row_counts)
 {
     const int64_t row = blockIdx.x;
@@ -192,6 +195,10 @@ k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__res
                         const bool earlier = di < 0 || (di == 0 && dj < 0);
                         if (nv > v || (nv == v && earlier)) det = false;
                     }
+                if (det && planes == 10 && u_max < INFINITY) {
+                    const int64_t plane = (int64_t)H * W;
+                    det = L[5 * plane + idx] <= u_max && L[6 * plane + idx] <= u_max;
+                }
             }
         }
         const uint64_t m = __ballot(det);
@@ -412,10 +419,11 @@ hipError_t launch_stem(int C, const FrameDesc *fd, const Geometry &g, const floa
 }
 
 hipError_t launch_detect_mask(const float *maps, int planes, const FrameDesc *fd, const Geometry &g, float tau,
-                              const uint8_t *keep, uint64_t *mask, uint32_t *row_counts, hipStream_t s)
+                              float u_max, const uint8_t *keep, uint64_t *mask, uint32_t *row_counts,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_detect_mask, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, fd, g.nf, tau, keep,
-                       mask, row_counts);
+    hipLaunchKernelGGL(k_detect_mask, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, fd, g.nf, tau, u_max,
+                       keep, mask, row_counts);
     return hipGetLastError();
 }
 

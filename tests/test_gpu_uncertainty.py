@@ -9,7 +9,8 @@ background) on the GPU:
   the same weights, in every precision form;
 * dl_localize_device on the 10-output net gives the same records; the
   capacity limit cuts records and uncertainties alike; a 5-output net refuses
-  dl_localize_device_unc.
+  dl_localize_device_unc;
+* the uncertainty filter (max_sigma_px) keeps the oracle's filtered set.
 """
 import numpy as np
 import pytest
@@ -115,4 +116,35 @@ def test_plain_entry_point_capacity_and_refusal():
     _, _, n5 = make("A")
     with pytest.raises(dl.DlocError) as e:
         localize_unc(n5, frames)
+    assert e.value.code == dl.DL_ERR_UNSUPPORTED
+
+
+def test_sigma_filter_matches_oracle():
+    """max_sigma_px: the GPU keeps exactly the oracle's filtered detections,
+    except pixels exempt under the usual threshold rules or whose sigma lies
+    within 1e-4 (relative) of the limit; records and uncertainties stay
+    aligned; a 5-output net refuses the setting."""
+    from tests.parity import exempt_mask
+    spec, wts = S.make_net("AU", 1)
+    frames = S.render_frames(2, 128, 160, "tiny", 84)
+    base, unc, maps = oracle.localize(frames, spec, wts, with_uncertainty=True, return_maps=True)
+    sig = np.maximum(unc["sigma_x"], unc["sigma_y"])
+    lim = float(np.median(sig))
+    ref = oracle.localize(frames, spec, wts, max_sigma_px=lim)
+    assert 0 < len(ref) < len(base)
+    net = dl.Net(S.serialize_weights(spec, wts), max_sigma_px=lim)
+    rec, u, counts = localize_unc(net, frames)
+    keys = lambda r: set(zip(r["frame"].tolist(), r["row"].tolist(), r["col"].tolist()))  # noqa: E731
+    base_keys = zip(base["frame"].tolist(), base["row"].tolist(), base["col"].tolist())
+    near = {k for k, s in zip(base_keys, sig) if abs(s - lim) <= 1e-4 * lim}
+    ex = [exempt_mask(maps[f, 0]) for f in range(len(frames))]
+    diff = keys(rec) ^ keys(ref)
+    bad = [k for k in diff if k not in near and not ex[k[0]][k[1], k[2]]]
+    assert not bad, bad[:10]
+    assert counts[-1] == len(rec) == len(u)
+    assert np.all(np.maximum(u["sigma_x_px"], u["sigma_y_px"]) <= lim * (1 + 1e-4))
+    plain, _ = gpu_localize(net, frames)
+    assert np.array_equal(plain, rec)
+    with pytest.raises(dl.DlocError) as e:
+        make("A")[2].set_config(max_sigma_px=0.5)
     assert e.value.code == dl.DL_ERR_UNSUPPORTED

@@ -89,3 +89,29 @@ def test_localize_returns_matching_uncertainties():
     # the 5-output net's records are those of the 10-output net
     s5, w5 = S.make_net("A", 1)
     assert np.array_equal(oracle.localize(frames, s5, w5), rec)
+
+
+def test_sigma_filter_invariants():
+    """The uncertainty filter only removes detections, the removed set grows as
+    the limit falls (nested), nothing survives a limit below every sigma, a
+    limit above every sigma changes nothing, and a removed maximum does not
+    promote a neighbour (the survivors are a subset of the local maxima)."""
+    spec, w = S.make_net("AU", 1)
+    frames = S.render_frames(2, 96, 120, "tiny", 11)
+    base, unc, maps = oracle.localize(frames, spec, w, with_uncertainty=True, return_maps=True)
+    assert len(base) > 10
+    sig = np.maximum(unc["sigma_x"], unc["sigma_y"])
+    keys = lambda r: set(zip(r["frame"].tolist(), r["row"].tolist(), r["col"].tolist()))  # noqa: E731
+    kb = keys(base)
+    prev = kb
+    for lim in sorted(set(np.quantile(sig, [0.9, 0.6, 0.3]).tolist()), reverse=True):
+        r = oracle.localize(frames, spec, w, max_sigma_px=lim)
+        k = keys(r)
+        assert k <= prev and k <= kb
+        # exactly the base detections whose larger lateral sigma is within the limit
+        expect = {kk for kk, s in zip(zip(base["frame"].tolist(), base["row"].tolist(), base["col"].tolist()), sig)
+                  if s <= lim}
+        assert k == expect
+        prev = k
+    assert len(oracle.localize(frames, spec, w, max_sigma_px=0.5 * sig.min())) == 0
+    assert keys(oracle.localize(frames, spec, w, max_sigma_px=2.0 * sig.max())) == kb
