@@ -229,6 +229,11 @@ int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n
 int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream,
                             dl_emitter *d_out, size_t cap, uint32_t *d_counts);
 
+/* dl_localize_rois_device for a network with the 10-output head, with each
+ * record's uncertainties in d_unc (as dl_localize_device_unc). */
+int dl_localize_rois_device_unc(dl_net *net, const dl_roi *rois, int nroi, void *stream,
+                                dl_emitter *d_out, dl_uncertainty *d_unc, size_t cap, uint32_t *d_counts);
+
 /* Maps of an uneven ROI batch: ROI k's maps [nh][h_k][w_k] start at
  * d_maps + nh * sum_{j<k} h_j * w_j. */
 int dl_maps_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, float *d_maps);

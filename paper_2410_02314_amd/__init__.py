@@ -86,6 +86,7 @@ def _load():
         "dl_set_config": (I, [P, ctypes.POINTER(DLConfig)]),
         "dl_localize_device": (I, [P, P, I, I, I, P, P, Z, P]),
         "dl_localize_device_unc": (I, [P, P, I, I, I, P, P, P, Z, P]),
+        "dl_localize_rois_device_unc": (I, [P, ctypes.POINTER(DLRoi), I, P, P, P, Z, P]),
         "dl_maps_device": (I, [P, P, I, I, I, P, P]),
         "dl_localize": (I, [P, P, I, I, I, P, Z, ctypes.POINTER(Z)]),
         "dl_localize_pipelined": (I, [P, P, I, I, I, I, I, P, Z, ctypes.POINTER(Z)]),
@@ -257,6 +258,15 @@ class Net:
         return self._rc(_lib.dl_localize_rois_device(self.handle, arr, len(rois), _stream(stream), _ptr(out),
                                                      cap, _ptr(counts)))
 
+    def localize_rois_device_unc(self, rois: Sequence, out, unc, counts, stream=None) -> int:
+        """localize_rois_device for a 10-output network, with uncertainties."""
+        arr = self._roi_array(rois)
+        cap = out.numel() * out.element_size() // 32
+        if unc.numel() * unc.element_size() < cap * 20:
+            raise ValueError("unc holds fewer records than out")
+        return self._rc(_lib.dl_localize_rois_device_unc(self.handle, arr, len(rois), _stream(stream), _ptr(out),
+                                                         _ptr(unc), cap, _ptr(counts)))
+
     def maps_rois_device(self, rois: Sequence, maps, stream=None) -> int:
         arr = self._roi_array(rois)
         return self._rc(_lib.dl_maps_rois_device(self.handle, arr, len(rois), _stream(stream), _ptr(maps)))
@@ -300,7 +310,7 @@ class Net:
         if rc == DL_ERR_CAPACITY:
             return self.localize_pipelined(frames, overlap, cap=int(cnt.value))
         _check(rc, self.handle)
-        return out[:cnt.value].copy()
+        return out[:cnt.value]          # a view: only the filled records were touched
 
     def graph(self, frames, out, counts) -> "Graph":
         """Capture localization of this fixed frame buffer into a HIP graph."""

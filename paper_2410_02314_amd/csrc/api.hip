@@ -994,6 +994,22 @@ int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *str
     return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr);
 }
 
+int dl_localize_rois_device_unc(dl_net *net, const dl_roi *rois, int nroi, void *stream, dl_emitter *d_out,
+                                dl_uncertainty *d_unc, size_t cap, uint32_t *d_counts)
+{
+    int rc = check_rois(net, rois, nroi);
+    if (rc) return rc;
+    if (net->nh != 10) return fail(net, DL_ERR_UNSUPPORTED, "the network has no uncertainty head (%d outputs)", net->nh);
+    if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
+    if (cap > 0 && (!d_out || !d_unc)) return fail(net, DL_ERR_INVALID_ARG, "d_out or d_unc is NULL with cap > 0");
+    if (reinterpret_cast<uintptr_t>(d_unc) % 4) return fail(net, DL_ERR_INVALID_ARG, "d_unc must be 4-byte aligned");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    roi_geometry(net, rois, nroi, fd, g);
+    return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr, nullptr, 0, 0, 0,
+                         cap ? d_unc : nullptr);
+}
+
 int dl_maps_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, float *d_maps)
 {
     int rc = check_rois(net, rois, nroi);

@@ -174,3 +174,22 @@ def test_handle_gate_pool_uses_the_handle_preprocessing():
     with pytest.raises(dl.DlocError) as e:
         net.gate_pool(fr[:, :, :256].contiguous(), torch.empty((2, 64, 64), dtype=torch.float32, device=DEV))
     assert e.value.code == dl.DL_ERR_INVALID_ARG      # not the sensor's shape
+
+
+def test_host_entry_points_use_the_maps():
+    """dl_localize and the pipelined host path with camera maps set give the
+    device path's records (pageable frames, overlap on)."""
+    spec, w, net = make("A", 1)
+    h, wd = 96, 144
+    cam = S.scmos_camera(h, wd, 28, offset_sd=10.0)
+    net.set_camera_maps(cam.gain, cam.offset)
+    frames = S.render_frames(4, h, wd, "tiny", 76, camera=cam)
+    ref = []
+    for k in range(2):
+        r, _ = gpu_localize(net, frames[2 * k:2 * k + 2])
+        r = r.copy()
+        r["frame"] += 2 * k
+        ref.append(r)
+    ref = np.concatenate(ref)
+    assert np.array_equal(net.localize(frames[:2]), ref[ref["frame"] < 2])
+    assert np.array_equal(net.localize_pipelined(frames.reshape(2, 2, h, wd), overlap=True), ref)

@@ -10,7 +10,10 @@ background) on the GPU:
 * dl_localize_device on the 10-output net gives the same records; the
   capacity limit cuts records and uncertainties alike; a 5-output net refuses
   dl_localize_device_unc;
-* the uncertainty filter (max_sigma_px) keeps the oracle's filtered set.
+* the uncertainty filter (max_sigma_px) keeps the oracle's filtered set;
+* uneven ROI batches: ten maps per ROI against the oracle, records with
+  uncertainties equal to the per-ROI runs; a graph of the 10-output net
+  replays the eager records.
 """
 import numpy as np
 import pytest
@@ -148,3 +151,51 @@ def test_sigma_filter_matches_oracle():
     with pytest.raises(dl.DlocError) as e:
         make("A")[2].set_config(max_sigma_px=0.5)
     assert e.value.code == dl.DL_ERR_UNSUPPORTED
+
+
+def test_uneven_rois_with_uncertainties():
+    """ROI batches of a 10-output net: each ROI's ten maps against the oracle,
+    and the ROI records with uncertainties equal the per-ROI device runs."""
+    shapes = [(64, 96), (128, 64), (33, 200), (1, 130), (17, 5)]
+    rois = S.render_rois(len(shapes), "rois", 1006, shapes=shapes)
+    spec, wts, net = make("AU")
+    d = [torch.from_numpy(r).to(DEV) for r in rois]
+    px = sum(r.size for r in rois)
+    maps = torch.full((10 * px,), float("nan"), dtype=torch.float32, device=DEV)
+    net.maps_rois_device(d, maps)
+    cap = 4096
+    out = torch.zeros((cap, 8), dtype=torch.int32, device=DEV)
+    unc = torch.zeros((cap * 5,), dtype=torch.float32, device=DEV)
+    counts = torch.zeros(len(rois) + 1, dtype=torch.int32, device=DEV)
+    net.localize_rois_device_unc(d, out, unc, counts)
+    torch.cuda.synchronize()
+    m, off = maps.cpu().numpy(), 0
+    c = counts.cpu().numpy()
+    rec = dl.emitters_from_device(out, int(c[-1]))
+    u = dl.uncertainties_from_device(unc, int(c[-1]))
+    for k, r in enumerate(rois):
+        mk = m[off:off + 10 * r.size].reshape(10, *r.shape)
+        off += 10 * r.size
+        assert map_rel_err(mk, oracle.net_maps(r, spec, wts)).max() <= TOL, k
+        rk, uk, _ = localize_unc(net, r[None])
+        sel = rec["frame"] == k
+        g = rec[sel].copy()
+        g["frame"] = 0
+        assert np.array_equal(g, rk) and np.array_equal(u[sel], uk), k
+
+
+def test_graph_of_the_ten_output_net():
+    spec, wts, net = make("AU")
+    frames = S.render_frames(2, 96, 128, "tiny", 85)
+    fr = torch.from_numpy(frames).to(DEV)
+    out = torch.zeros((4096, 8), dtype=torch.int32, device=DEV)
+    counts = torch.zeros(3, dtype=torch.int32, device=DEV)
+    g = net.graph(fr, out, counts)
+    ref, rc = gpu_localize(net, frames)
+    for _ in range(3):
+        counts.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        c = counts.cpu().numpy()
+        assert np.array_equal(c, rc) and np.array_equal(dl.emitters_from_device(out, int(c[-1])), ref)
+    g.close()
