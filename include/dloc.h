@@ -230,7 +230,9 @@ int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *str
                             dl_emitter *d_out, size_t cap, uint32_t *d_counts);
 
 /* dl_localize_rois_device for a network with the 10-output head, with each
- * record's uncertainties in d_unc (as dl_localize_device_unc). */
+ * record's uncertainties in d_unc (as dl_localize_device_unc: device
+ * dl_uncertainty[cap], entry i beside d_out[i], 4-byte aligned).  Errors as
+ * dl_localize_rois_device, plus DL_ERR_UNSUPPORTED for a 5-output network. */
 int dl_localize_rois_device_unc(dl_net *net, const dl_roi *rois, int nroi, void *stream,
                                 dl_emitter *d_out, dl_uncertainty *d_unc, size_t cap, uint32_t *d_counts);
 
@@ -289,7 +291,9 @@ int dl_gate_pool(const uint16_t *d_frames, int n, int h, int w, float gain, floa
 /* dl_gate_pool with the handle's own preprocessing: its config's gain and
  * offset and its weights' in_scale, or its camera maps when set (then the
  * frames must be sensor-sized) -- the tiles a gated run of this handle
- * pools, for training its gate. */
+ * pools, for training its gate.  Same layouts as dl_gate_pool; work is
+ * queued on `stream`.  Errors: DL_ERR_INVALID_ARG (NULL pointers, frames not
+ * the camera maps' shape), DL_ERR_UNSUPPORTED (h or w not a multiple of 256). */
 int dl_gate_pool_net(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, float *d_pooled);
 /* d_logits[ntiles] = g of every pooled tile. */
 int dl_gate_forward(const float *d_pooled, int ntiles, const float *d_theta, void *stream, float *d_logits);
