@@ -257,8 +257,12 @@ int dl_autotune(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void
  * Refill the frame buffer in place and replay with dl_graph_launch: one
  * launch per batch instead of ~20 kernel launches (Sec. 2.2: the network reads
  * preloaded frames from fixed memory locations).  Outputs as for
- * dl_localize_device.  The graph holds the handle's weights and precision at
- * creation; destroy graphs before their handle.  Not available with the gate. */
+ * dl_localize_device.  The graph holds the handle's weights, precision,
+ * threshold, gain, offset and max_sigma_px at creation; after a change of
+ * precision (the packed weights move) or of the camera maps' presence or
+ * shape, dl_graph_launch refuses with DL_ERR_INVALID_ARG and the graph must
+ * be created again.  Destroy graphs before their handle.  Not available with
+ * the gate. */
 typedef struct dl_graph dl_graph;
 int dl_graph_create(dl_net *net, const uint16_t *d_frames, int n, int h, int w, dl_emitter *d_out, size_t cap,
                     uint32_t *d_counts, dl_graph **out);

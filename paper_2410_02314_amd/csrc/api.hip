@@ -51,6 +51,7 @@ struct dl_net {
     int *d_dil = nullptr;           // dilations [nb]
     size_t wpk_stride = 0;
     int packed_precision = -1;
+    uint64_t packed_gen = 0;        // counts repacks (graphs check it: they hold d_wpk)
 
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -326,6 +327,7 @@ int ensure_packed(dl_net *net)
     HIPCHK(net, hipMemcpy(net->d_wpk, host.data(), host.size(), hipMemcpyHostToDevice));
     net->wpk_stride = stride;
     net->packed_precision = net->cfg.precision;
+    ++net->packed_gen;
     return DL_OK;
 }
 
@@ -564,6 +566,7 @@ struct dl_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t cam_gen = 0;           // the handle's camera-map generation at capture
+    uint64_t packed_gen = 0;        // and its weight-packing generation
 };
 
 static int check_rois(dl_net *net, const dl_roi *rois, int nroi);
@@ -582,6 +585,7 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
     if (!gr) return fail(net, DL_ERR_OOM, "out of host memory");
     gr->net = net;
     gr->cam_gen = net->cam_gen;
+    gr->packed_gen = net->packed_gen;       // ensure_packed ran above
     auto bail = [&](int code) {
         if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
         if (gr->graph) (void)hipGraphDestroy(gr->graph);
@@ -1320,6 +1324,8 @@ int dl_graph_launch(dl_graph *g, void *stream)
     int rc;
     if (g->cam_gen != net->cam_gen)
         return fail(net, DL_ERR_INVALID_ARG, "the camera maps were set, cleared or reshaped after this graph was captured");
+    if (g->packed_gen != net->packed_gen)
+        return fail(net, DL_ERR_INVALID_ARG, "the handle's precision changed after this graph was captured (its weights moved)");
     if ((rc = set_device(net))) return rc;
     HIPCHK(net, hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
     return DL_OK;

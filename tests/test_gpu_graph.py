@@ -84,3 +84,35 @@ def test_autotune_picks_a_candidate_and_keeps_results():
     assert ms[rows] == min(ms.values())
     got, _ = eager(net, d, 1 << 14)
     assert torch.equal(got, ref)              # the tile shape never changes results
+
+
+def test_graph_refuses_to_launch_after_a_precision_change():
+    """A precision change repacks (moves) the weights a graph points at: the
+    graph refuses to launch instead of reading freed memory; a graph captured
+    after the change replays the eager result, and a threshold change leaves
+    an existing graph valid (it keeps its own threshold)."""
+    spec, w = S.make_net("A", 1)
+    net = dl.Net(S.serialize_weights(spec, w), precision="fp32")
+    frames = S.render_frames(2, 96, 128, "tiny", 1004)
+    buf = torch.from_numpy(frames).to(DEV)
+    out = torch.zeros((2048, 8), dtype=torch.int32, device=DEV)
+    counts = torch.zeros(3, dtype=torch.int32, device=DEV)
+    g = net.graph(buf, out, counts)
+    ref_out, ref_counts = eager(net, buf, 2048)
+    net.set_config(precision="fp32", threshold=0.5)   # same precision: no repack
+    g.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(counts, ref_counts)            # the graph's own threshold (0.3)
+    net.set_config(precision="bf16")
+    with pytest.raises(dl.DlocError) as e:
+        g.launch()
+    assert e.value.code == dl.DL_ERR_INVALID_ARG
+    g.close()
+    g2 = net.graph(buf, out, counts)
+    ref2_out, ref2_counts = eager(net, buf, 2048)
+    counts.zero_()
+    g2.launch()
+    torch.cuda.synchronize()
+    n = int(counts[-1].item())
+    assert torch.equal(counts, ref2_counts) and torch.equal(out[:n], ref2_out)
+    g2.close()
