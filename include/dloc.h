@@ -323,9 +323,11 @@ int dl_gate_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, in
  * test.  Other shapes return DL_ERR_UNSUPPORTED while the flag is set. */
 int dl_set_gate(dl_net *net, const float *theta, float threshold);
 
-/* Copy the keep flags (uint8, 1 = kept) of the last gated run, frame-major
- * then row-major over 256^2 tiles, to device memory d_keep (cap bytes);
- * *ntiles = number of flags.  DL_ERR_CAPACITY if cap is too small. */
+/* Copy the keep flags (uint8, 1 = kept) of the handle's most recent run,
+ * which must have been gated (a later run reuses the workspace they live in;
+ * else DL_ERR_INVALID_ARG), frame-major then row-major over 256^2 tiles, to
+ * device memory d_keep (cap bytes), queued on `stream`; *ntiles = number of
+ * flags.  DL_ERR_CAPACITY if cap is too small. */
 int dl_gate_keep_map(dl_net *net, void *stream, uint8_t *d_keep, size_t cap, size_t *ntiles);
 
 /* ---- stage timing ----

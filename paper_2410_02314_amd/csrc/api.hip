@@ -262,6 +262,7 @@ int ensure_workspace(dl_net *net, size_t bytes, hipStream_t s)
         HIPCHK(net, hipFree(net->ws));
         net->ws = nullptr;
         net->ws_bytes = 0;
+        net->last_gate_tiles = 0;           // the keep map lived in the old workspace
     }
     hipError_t e = hipMalloc(&net->ws, bytes);
     if (e != hipSuccess) {
@@ -546,6 +547,7 @@ int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry 
     const int slot = upload_desc(net, fd, s, &d_fd);
     if (slot < 0) return slot;
     float *maps = ext_maps ? ext_maps : reinterpret_cast<float *>(p.ws + p.maps);
+    net->last_gate_tiles = 0;               // this run reuses the workspace
     if (p.gated && (rc = run_gate(net, d_fd, g, p, d_frames, n, h, w, s))) return rc;
     if ((rc = run_net(net, d_fd, g, p, maps, s))) return rc;
     if (d_out || d_counts)
@@ -1415,7 +1417,7 @@ int dl_gate_keep_map(dl_net *net, void *stream, uint8_t *d_keep, size_t cap, siz
     if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
     if (!ntiles) return fail(net, DL_ERR_INVALID_ARG, "ntiles is NULL");
     *ntiles = (size_t)net->last_gate_tiles;
-    if (net->last_gate_tiles == 0) return fail(net, DL_ERR_INVALID_ARG, "no gated run yet");
+    if (net->last_gate_tiles == 0) return fail(net, DL_ERR_INVALID_ARG, "the handle's most recent run was not gated");
     if (!d_keep || cap < *ntiles) return fail(net, DL_ERR_CAPACITY, "keep map needs %zu bytes", *ntiles);
     int rc;
     if ((rc = set_device(net))) return rc;

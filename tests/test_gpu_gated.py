@@ -114,3 +114,24 @@ def test_mixed_keep_map(name):
     for (a, b, c) in k1 - k0:                                        # extras sit next to a skipped tile
         nb = pix_keep[a, max(0, b - 1):b + 2, max(0, c - 1):c + 2]
         assert not nb.all()
+
+
+def test_keep_map_belongs_to_the_most_recent_gated_run():
+    """The keep flags live in the workspace the next run reuses: after an
+    ungated run the keep map is refused rather than read stale."""
+    frames = S.render_frames(1, 512, 512, "sparse", 4046)
+    spec, w = S.make_net("A", 1)
+    net = dl.Net(S.serialize_weights(spec, w), flags=dl.DL_FLAG_GATE)
+    th = np.zeros(673, np.float32)
+    th[672] = 20.0                                        # keeps every tile
+    net.set_gate(th, 0.05)
+    gpu_localize(net, frames)
+    k = torch.zeros(4, dtype=torch.uint8, device=DEV)
+    assert net.gate_keep_map(k) == 4                     # four 256^2 tiles
+    torch.cuda.synchronize()
+    assert k.cpu().numpy().all()
+    net.set_gate(None)                                    # the next run is ungated
+    gpu_localize(net, frames)
+    with pytest.raises(dl.DlocError) as e:
+        net.gate_keep_map(k)
+    assert e.value.code == dl.DL_ERR_INVALID_ARG
