@@ -63,7 +63,7 @@ def tiny(args, S):
     out = torch.empty((8192, 8), dtype=torch.int32, device=dev)
     counts = torch.zeros(5, dtype=torch.int32, device=dev)
     st = torch.cuda.current_stream()
-    steps = max(args.steps, 200)
+    steps = max(args.steps, 1000)               # latency-scale: a 1000-iteration replay
     ms_eager = _timed(lambda: net.localize_device(d, out, counts, st), steps, max(args.warmup, 20), st)
     g = net.graph(d, out, counts)
     ms_graph = _timed(lambda: g.launch(st), steps, max(args.warmup, 20), st)
