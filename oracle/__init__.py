@@ -11,8 +11,9 @@ order of the definition).  This module compiles it with gcc and wraps it with
 ctypes, plus the few steps that are plain bookkeeping (record assembly).
 
 Definitions followed (paper Sec. 2.2, Sec. 3.2, Sec. 3.2.1, Sec. 3.3):
-see the header of ``oracle.c``.  Readings where the paper is silent are listed
-in DESIGN.md ("Readings of the paper").
+see the header of ``oracle.c``, which also states the choices made where the
+paper is silent (network shape, preprocessing, head outputs, emulated
+rounding).
 """
 from __future__ import annotations
 

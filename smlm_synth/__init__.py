@@ -86,7 +86,7 @@ class FrameModel:
         raise ValueError(f"unknown psf {self.psf!r}")
 
 
-#: frame models of the five workloads (see the design doc for the recipe table)
+#: frame models of the workloads: tiny (4 x 128^2), full (16 x 2048^2), uneven ROIs and sparse frames
 CONFIG_MODELS: Dict[str, FrameModel] = {
     # 4 x 128^2, 2D Gaussian sigma 1.3, density 1/um^2, photons U(1000,5000), bg 100
     "tiny": FrameModel(),

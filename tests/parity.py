@@ -1,6 +1,6 @@
 """Comparison helpers for GPU-vs-oracle parity (shared by the tests, smoke and bench).
 
-Readings used (listed in the design doc):
+Readings used:
 * maps: |gpu - oracle| <= tol * (|oracle| + rms of that map over the frame),
   a relative error that stays defined where a map crosses zero;
 * emitter sets: identical except pixels the FP64 oracle puts within 1e-3 of the
