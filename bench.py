@@ -164,6 +164,7 @@ def main():
                               else "scalar gain 0.5, offset 100"),
                    "parallelism": "single GPU"},
         "roofline": head["roofline"], "stage_ms_per_step": head["stage_ms_per_step"],
+        "bandwidth_kernels": head["bandwidth_kernels"],
         "emitters_per_step": head["emitters_per_step"],
         "accuracy_vs_oracle": head.get("accuracy_vs_oracle"),
         "forms": others,
@@ -243,11 +244,23 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
                      "kernel": f"k_conv {precision} (3x3 dilated conv, C={C}; mean of the {n_conv} non-head launches)",
                      "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_launch": flop_launch,
                      "algorithmic_bytes_per_launch": round(bytes_launch)})
+    # the bandwidth-bound stages against the HBM peak, from their algorithmic
+    # bytes: the stem reads the uint16 frame (+ the 8-byte camera map per pixel
+    # with sCMOS maps) and writes one stored point per pixel; detection reads
+    # the logit plane and writes one mask bit per pixel
+    bw = {}
+    for stage, nbytes in (("stem", total_px * (2 + (8 if cam is not None else 0) + pt_bytes)),
+                          ("detect", total_px * (4 + 1 / 8))):
+        if prof.get(stage, (0, 0))[1]:
+            t = prof[stage][0] / prof[stage][1] * 1e-3
+            bw[stage] = {"gb_s": round(nbytes / t / 1e9, 1), "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 3),
+                         "algorithmic_bytes": round(nbytes), "avg_ms": round(t * 1e3, 3)}
     recs = dl.emitters_from_device(d_out, min(int(counts[n]), cap))
     return {"value": round(value, 2), "ms_per_step": round(ms_step, 3),
             "ms_per_step_median": round(float(np.median(step_ms)), 3), "ms_per_step_min": round(min(step_ms), 3),
             "roofline": roofline,
             "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]},
+            "bandwidth_kernels": bw,
             "emitters_per_step": int(counts[n]), "net": net, "records": recs}
 
 

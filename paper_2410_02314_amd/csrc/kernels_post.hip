@@ -170,17 +170,29 @@ k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__res
     const int H = fd.h, W = fd.w;
     const float *L = maps + planes * fd.px_off;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // gated runs: pixels of skipped gate tiles are neither detected nor neighbours
+    const uint8_t *kp = keep ? keep + fd.keep_start : nullptr;
+    auto kept = [&](int yy, int xx) { return !kp || kp[(yy / GATE_TILE) * fd.gtx + xx / GATE_TILE]; };
+    const float *Lrow = L + (int64_t)y * W;
     uint32_t cnt = 0;
-    for (int xb = wave * 64; xb < W; xb += 256) {
-        const int x = xb + lane;
-        bool det = false;
-        // gated runs: pixels of skipped gate tiles are neither detected nor neighbours
-        const uint8_t *kp = keep ? keep + fd.keep_start : nullptr;
-        auto kept = [&](int yy, int xx) { return !kp || kp[(yy / GATE_TILE) * fd.gtx + xx / GATE_TILE]; };
-        if (x < W && kept(y, x)) {
-            const int64_t idx = (int64_t)y * W + x;
-            const float v = L[idx];
-            det = v > tau;
+    // The row in passes of DCH 256-pixel chunks: all of a pass's logit loads
+    // are issued before any decision, so each lane has DCH loads in flight
+    // (one load per decision left the kernel latency-bound).
+    constexpr int DCH = 8;
+    for (int base = 0; base < W; base += 256 * DCH) {
+        float vv[DCH];
+#pragma unroll
+        for (int c = 0; c < DCH; ++c) {
+            const int x = base + c * 256 + wave * 64 + lane;
+            vv[c] = x < W ? Lrow[x] : 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < DCH; ++c) {
+            const int xb = base + c * 256 + wave * 64;
+            if (xb >= W) break;                              // uniform across the wave
+            const int x = xb + lane;
+            const float v = vv[c];
+            bool det = x < W && v > tau && kept(y, x);
             if (det) {
 #pragma unroll
                 for (int di = -1; di <= 1; ++di)
@@ -196,14 +208,14 @@ k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__res
                         if (nv > v || (nv == v && earlier)) det = false;
                     }
                 if (det && planes == 10 && u_max < INFINITY) {
-                    const int64_t plane = (int64_t)H * W;
+                    const int64_t plane = (int64_t)H * W, idx = (int64_t)y * W + x;
                     det = L[5 * plane + idx] <= u_max && L[6 * plane + idx] <= u_max;
                 }
             }
+            const uint64_t m = __ballot(det);
+            if (lane == 0) mask[fd.mask_start + (int64_t)y * fd.words + (xb >> 6)] = m;
+            cnt += (uint32_t)__popcll(m);
         }
-        const uint64_t m = __ballot(det);
-        if (lane == 0) mask[fd.mask_start + (int64_t)y * fd.words + (xb >> 6)] = m;
-        cnt += (uint32_t)__popcll(m);
     }
     __shared__ uint32_t sc[4];
     if (lane == 0) sc[wave] = cnt;
