@@ -159,7 +159,7 @@ def main():
         "data": "synthetic (seeded astigmatic-PSF SMLM frames; random-init calibrated net)",
         "config": {"workload": f"{n} x {side}x{side} uint16 frames, astigmatic 3D PSF, net {args.net} "
                                f"(C=48, d=1,2,4,8,16, {spec.head_outputs}-output head), {args.precision}",
-                   "frames": n, "height": side, "width": side, "net": args.net, "precision": args.precision,
+                   "frames": n, "height": side, "width": side, "precision": args.precision,
                    "camera": ("sCMOS per-pixel gain/offset maps (sensor seed 1002)" if cam is not None
                               else "scalar gain 0.5, offset 100"),
                    "parallelism": "single GPU"},

@@ -69,7 +69,7 @@ def tiny(args, S):
     ms_graph = _timed(lambda: g.launch(st), steps, max(args.warmup, 20), st)
     px = 4 * 128 * 128
     _line(args, px / (ms_graph * 1e-3) / 1e6, ms_graph,
-          {"workload": "4 x 128x128 uint16 frames, 2D Gaussian PSF, net A (C=32, d=1,2,4)", "net": "A",
+          {"workload": "4 x 128x128 uint16 frames, 2D Gaussian PSF, net A (C=32, d=1,2,4)",
            "precision": args.precision, "frames": 4, "height": 128, "width": 128},
           {"eager_ms_per_step": round(ms_eager, 4), "graph_ms_per_step": round(ms_graph, 4),
            "eager_mpx_s": round(px / (ms_eager * 1e-3) / 1e6, 3), "emitters_per_step": int(counts[4].item())})
@@ -109,7 +109,7 @@ def rois(args, S):
     mpx, mpx_uni = px / (ms * 1e-3) / 1e6, uni.size / (ms_uni * 1e-3) / 1e6
     del d_uni, u_out
     _line(args, mpx, ms,
-          {"workload": f"256 uneven ROIs (sides 128..1024), {px / 1e6:.1f} Mpx, net A", "net": "A",
+          {"workload": f"256 uneven ROIs (sides 128..1024), {px / 1e6:.1f} Mpx, net A",
            "precision": args.precision, "frames": 256, "pixels": px},
           {"graph_ms_per_step": round(ms_graph, 3), "emitters_per_step": int(counts[256].item()),
            "uniform_16x2048sq_mpx_s": round(mpx_uni, 2), "load_balance_efficiency": round(mpx / mpx_uni, 4),
@@ -202,7 +202,7 @@ def sparse(args, S):
           {"workload": f"{n_eval} x {side}x{side} sparse frames (30-70% empty 256^2 tiles, "
                        f"{'independent' if args.sparse_layout == 'iid' else 'around one compact occupied region'})"
                        f", gated BF16 net B",
-           "net": "B", "precision": "bf16",
+           "precision": "bf16",
            "gate": f"2 conv x 8 ch + global max pool, threshold {thr:.4f} (99.9% of held-out detections kept)",
            "frames": n_eval},
           {"ungated_ms_per_step": round(ms0, 3), "ungated_mpx_s": round(px / (ms0 * 1e-3) / 1e6, 2),
@@ -253,7 +253,7 @@ def pipeline(args, S):
     px = frames.size
     _line(args, px / out[1][0] / 1e6, out[1][0] * 1e3 / nb,
           {"workload": f"{nb} batches of {args.frames} x {args.size}^2 host frames (pinned), net B, "
-                       f"H2D on a side stream overlapped with compute", "net": "B", "precision": args.precision,
+                       f"H2D on a side stream overlapped with compute", "precision": args.precision,
            "camera": args.camera},
           {"serial_mpx_s": round(px / out[0][0] / 1e6, 2), "overlap_speedup": round(out[0][0] / out[1][0], 3),
            "emitters": out[1][1]})
