@@ -48,6 +48,17 @@ def cpu_threads() -> int:
     return min(n, int(omp)) if omp and omp.isdigit() else n
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), for the baseline's record."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,6 +383,7 @@ def cpu_baseline(args, spec, w, frames, net, dev, recs, cam=None):
     ref = {"records": rec[rsel], "limit": lim, "maps": ref_maps[0, :, :e, :e], "map_extent": e}
     what = "frame 0" if whole else f"frame 0 crop {s}x{s}"
     return {"value": round(s * s / dt / 1e6, 4), "unit": "Mpixel/s", "cores": cpu_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{what} of the same workload, FP64 oracle (net + detection + records), {dt:.1f} s",
             "sample_check": {"max_map_rel_err": float(err.max()), "oracle_detections": int(ref_det.sum()),
                              "gpu_detections": int(got_det.sum()), "matched": matched,
