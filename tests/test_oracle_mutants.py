@@ -1,0 +1,69 @@
+"""The oracle's pins catch plausible mistakes: each case plants one mistake in
+a copy of oracle.c (a transposed kernel, a dropped dilation, a dropped bias or
+residual, a wrong sign, a reversed tie-break, swapped camera maps, a dropped
+head bias), builds it with the oracle's own flags, points the oracle module at
+it, and checks that at least one of the named pins fails.  The planted copy
+lives in a temporary directory; the real oracle is restored afterwards."""
+import subprocess
+
+import pytest
+
+import oracle
+import smlm_synth as S
+from tests import test_oracle_camera as CAM
+from tests import test_oracle_pins as PINS
+from tests import test_oracle_uncertainty as UNC
+
+MUTANTS = [
+    ("transposed 3x3 kernel",
+     "double wt = W[(((long)o * cin + c) * 3 + (u + 1)) * 3 + (v + 1)];",
+     "double wt = W[(((long)o * cin + c) * 3 + (v + 1)) * 3 + (u + 1)];",
+     [(PINS.test_conv_delta_input_reproduces_weights, (2,))]),
+    ("row dilation dropped",
+     "int ii = i + d * u;",
+     "int ii = i + u;",
+     [(PINS.test_conv_matches_torch_float64, (4,))]),
+    ("conv bias dropped",
+     "for (long p = 0; p < hw; ++p) y[p] = b ? b[o] : 0.0;",
+     "for (long p = 0; p < hw; ++p) y[p] = 0.0;",
+     [(PINS.test_conv_linearity_and_bias, ())]),
+    ("offset sign flipped",
+     "x[p] = ((double)F[p] - offset) * gain * in_scale;",
+     "x[p] = ((double)F[p] + offset) * gain * in_scale;",
+     [(PINS.test_preprocess_closed_form, ())]),
+    ("tie-break reversed",
+     "if (!(v > nv || (v == nv && idx < nidx))) keep = 0;",
+     "if (!(v > nv || (v == nv && idx > nidx))) keep = 0;",
+     [(PINS.test_detect_exhaustive_3x3, ())]),
+    ("residual dropped",
+     "double s = a[k] + u[k];",
+     "double s = u[k];",
+     [(PINS.test_net_matches_torch_composition, ("A",))]),
+    ("head bias dropped",
+     "for (long k = 0; k < hw; ++k) m[k] = bd[q];",
+     "for (long k = 0; k < hw; ++k) m[k] = 0.0;",
+     [(UNC.test_head_closed_form, ("AU",))]),
+    ("camera gain and offset swapped",
+     "x[p] = ((double)F[p] - offset[p]) * gain[p] * in_scale;",
+     "x[p] = ((double)F[p] - gain[p]) * offset[p] * in_scale;",
+     [(CAM.test_per_pixel_maps_equal_rescaled_frame, (S.make_net("A", 1),))]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_reject_a_planted_mistake(name, old, new, pins, tmp_path, monkeypatch):
+    src = open(oracle._SRC).read()
+    assert src.count(old) == 1, "the planted mistake's target text must occur once"
+    mutant = tmp_path / "oracle_mutant.c"
+    mutant.write_text(src.replace(old, new))
+    lib = tmp_path / "liboracle_mutant.so"
+    subprocess.check_call(["gcc", *oracle.GCC_FLAGS, str(mutant), "-o", str(lib), "-lm"])
+    monkeypatch.setattr(oracle, "build", lambda force=False: str(lib))
+    monkeypatch.setattr(oracle, "_lib", None)
+    failed = []
+    for pin, args in pins:
+        try:
+            pin(*args)
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"no pin caught: {name}"
