@@ -1,9 +1,11 @@
-"""The oracle's pins catch plausible mistakes: each case plants one mistake in
-a copy of oracle.c (a transposed kernel, a dropped dilation, a dropped bias or
-residual, a wrong sign, a reversed tie-break, swapped camera maps, a dropped
-head bias), builds it with the oracle's own flags, points the oracle module at
-it, and checks that at least one of the named pins fails.  The planted copy
-lives in a temporary directory; the real oracle is restored afterwards."""
+"""The oracle's pins catch plausible mistakes.  Each case plants one mistake
+in a copy of oracle.c: a transposed kernel, a dropped dilation, a dropped bias
+or residual, a wrong sign, a reversed tie-break, truncating BF16 rounding, an
+FP8 scale one power of two off, the gate's gradient sent to the last maximum,
+swapped camera maps, a dropped head bias.  It builds the copy with the
+oracle's own flags, points the oracle module at it, and checks that at least
+one of the named pins fails.  The planted copy lives in a temporary directory;
+the real oracle is restored afterwards."""
 import subprocess
 
 import pytest
@@ -43,6 +45,18 @@ MUTANTS = [
      "for (long k = 0; k < hw; ++k) m[k] = bd[q];",
      "for (long k = 0; k < hw; ++k) m[k] = 0.0;",
      [(UNC.test_head_closed_form, ("AU",))]),
+    ("BF16 rounding truncates",
+     "u += 0x7FFFu + lsb;",
+     "u += 0u * lsb;",
+     [(PINS.test_bf16_rounding_matches_torch, ())]),
+    ("FP8 group exponent one too small",
+     "int k = (e - 1) - (f <= 1.75 ? 8 : 7);",
+     "int k = (e - 1) - (f <= 1.75 ? 9 : 8);",
+     [(PINS.test_fp8_group_exponent_is_smallest_fitting_power_of_two, ())]),
+    ("gate pool takes the last maximum",
+     "if (h2[(long)c * hw + k] > h2[(long)c * hw + a]) a = k;",
+     "if (h2[(long)c * hw + k] >= h2[(long)c * hw + a]) a = k;",
+     [(PINS.test_gate_max_gradient_goes_to_first_maximum, ())]),
     ("camera gain and offset swapped",
      "x[p] = ((double)F[p] - offset[p]) * gain[p] * in_scale;",
      "x[p] = ((double)F[p] - gain[p]) * offset[p] * in_scale;",
