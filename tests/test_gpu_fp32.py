@@ -177,17 +177,24 @@ def test_debug_detect_bit_exact_with_plateaus():
         assert np.array_equal(got[f], oracle.detect(L[f].astype(np.float64), 0.5))
 
 
-def test_full_size_sampled_windows():
-    """Full-size frames (2048 x 2048, net B) on the GPU, compared with the oracle on
-    sampled windows it computes exactly (window + receptive-radius margin)."""
-    spec, wts, net = make("B", 2)
-    frames = S.render_frames(2, 2048, 2048, "full", 1002)
+@pytest.mark.parametrize("name,scmos", [("B", False), ("BU", True)])
+def test_full_size_sampled_windows(name, scmos):
+    """Full-size frames (2048 x 2048, net B; and the 10-output net on sCMOS
+    frames with the sensor's camera maps, as the benchmark runs it) on the
+    GPU, compared with the oracle on sampled windows it computes exactly
+    (window + receptive-radius margin)."""
+    spec, wts, net = make(name, 2)
+    cam = S.scmos_camera(2048, 2048, 1002) if scmos else None
+    frames = S.render_frames(2, 2048, 2048, "full", 1002, camera=cam)
+    camera = {} if cam is None else {"gain": cam.gain, "offset": cam.offset}
+    if cam is not None:
+        net.set_camera_maps(cam.gain, cam.offset)
     got = gpu_maps(net, frames)
     rec, counts = gpu_localize(net, frames)
     wins = [(0, 0, 0), (0, 2048 - 40, 2048 - 48), (1, 1000, 517), (1, 0, 1500), (0, 1731, 0)]
     for f, y0, x0 in wins:
         hh, ww = 40, 48
-        ref = oracle.net_maps_window(frames[f], spec, wts, y0, x0, hh, ww)
+        ref = oracle.net_maps_window(frames[f], spec, wts, y0, x0, hh, ww, **camera)
         err = map_rel_err(got[f, :, y0:y0 + hh, x0:x0 + ww], ref)
         assert err.max() <= TOL, (f, y0, x0, err)
         # detections strictly inside the window (neighbours known) must agree
