@@ -210,3 +210,27 @@ def test_full_size_sampled_windows(name, scmos):
     assert np.all(np.diff(keys[:, 0] * 2048 * 2048 + keys[:, 1] * 2048 + keys[:, 2]) > 0)
     lg = got[rec["frame"], 0, rec["row"], rec["col"]]
     assert np.all(lg > math.log(0.3 / 0.7))
+
+
+def test_tiny_workload_against_the_stored_oracle_records():
+    """The library's records for the tiny workload against the oracle's stored
+    records (tests/golden): the same emitters except pixels whose decision
+    rounding may flip, coordinates within 1e-3 px, photons and z within 1e-4
+    relative, probabilities within 1e-5."""
+    from tests.golden_records import load
+    gold, near, counts = load()
+    spec, w, net = make("A", 1)
+    frames = S.render_frames(4, 128, 128, "tiny", 1001)
+    rec, c = gpu_localize(net, frames)
+    gk = {(int(a), int(b), int(d)): i for i, (a, b, d) in enumerate(zip(gold["frame"], gold["row"], gold["col"]))}
+    rk = {(int(a), int(b), int(d)): i for i, (a, b, d) in enumerate(zip(rec["frame"], rec["row"], rec["col"]))}
+    assert not [k for k in set(gk) ^ set(rk) if k not in near]
+    both = [k for k in rk if k in gk]
+    assert len(both) >= len(gold) - len(near)
+    r = rec[[rk[k] for k in both]]
+    g = gold[[gk[k] for k in both]]
+    assert np.max(np.abs(r["x_px"] - g["x"])) < 1e-3 and np.max(np.abs(r["y_px"] - g["y"])) < 1e-3
+    assert np.allclose(r["photons"], g["photons"], rtol=1e-4, atol=1e-2)
+    assert np.allclose(r["z_nm"], g["z"], rtol=1e-4, atol=1e-2)
+    assert np.max(np.abs(r["prob"] - g["prob"])) < 1e-5
+    assert list(c[:4]) == list(np.bincount(rec["frame"], minlength=4))
