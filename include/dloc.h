@@ -2,10 +2,11 @@
  * dloc.h -- C ABI of the MI355X localization library (libdloc.so).
  *
  * The library turns raw uint16 SMLM camera frames into an emitter list on the
- * GPU: gain/offset preprocessing, a residual network of 3x3 dilated
- * convolutions, a 1x1 head giving per-pixel detection logit and sub-pixel
- * offsets, then thresholding, 3x3 local-maximum suppression and an ordered
- * compaction into emitter records.
+ * GPU: gain/offset preprocessing (scalar or per-pixel sCMOS maps), a residual
+ * network of 3x3 dilated convolutions, a 1x1 head giving per-pixel detection
+ * logit, sub-pixel offsets and photons (and, with 10 outputs, their
+ * uncertainties and the background), then thresholding, 3x3 local-maximum
+ * suppression and an ordered compaction into emitter records.
  *
  * Paper passages the calls follow (An Efficient Inference Frame for Single
  * Molecule Localization Microscopy):
@@ -13,7 +14,8 @@
  *     from fixed locations (preloading); post-processing is kept in GPU memory
  *     and only the post-processed coordinates leave the device.
  *   - Sec. 3.2: the network's output follows DECODE: per pixel a detection
- *     probability plus the emitter's offset relative to that pixel.
+ *     probability plus the emitter's offset relative to that pixel and the
+ *     uncertainty of that position.
  *   - Sec. 3.2.1: feature extraction with dilated 3x3 convolutions whose
  *     dilation sets the receptive field.
  *   - Sec. 3.3: binary cross-entropy (used here to train the tile gate).
@@ -29,9 +31,10 @@
  *   - Work queued by the *_device calls runs on the caller's HIP stream
  *     (hipStream_t passed as void*, NULL = the null stream) and is not
  *     synchronised: results are valid once that stream has completed.
- *   - Frames are uint16 [n][h][w] row-major; maps are float [n][5][h][w]
- *     (planes: logit, dx, dy, dz, photons); emitter records are ordered by
- *     (frame, row, col).
+ *   - Frames are uint16 [n][h][w] row-major; maps are float [n][nh][h][w]
+ *     (planes: logit, dx, dy, dz, photons; with nh = 10 then the raw
+ *     uncertainties of x, y, z, photons and the background); emitter records
+ *     are ordered by (frame, row, col).
  */
 #ifndef DLOC_H
 #define DLOC_H
