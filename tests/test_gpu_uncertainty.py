@@ -13,7 +13,9 @@ background) on the GPU:
 * the uncertainty filter (max_sigma_px) keeps the oracle's filtered set;
 * uneven ROI batches: ten maps per ROI against the oracle, records with
   uncertainties equal to the per-ROI runs; a graph of the 10-output net
-  replays the eager records.
+  replays the eager records;
+* a keep-all gate on sCMOS frames with camera maps gives the ungated records
+  and uncertainties bit for bit.
 """
 import numpy as np
 import pytest
@@ -199,3 +201,25 @@ def test_graph_of_the_ten_output_net():
         c = counts.cpu().numpy()
         assert np.array_equal(c, rc) and np.array_equal(dl.emitters_from_device(out, int(c[-1])), ref)
     g.close()
+
+
+def test_gate_camera_maps_and_uncertainties_together():
+    """A gate that keeps every tile, on sCMOS frames with camera maps, through
+    the 10-output head: records and uncertainties equal the ungated run bit for
+    bit."""
+    spec, wts = S.make_net("AU", 1)
+    h = w = 512
+    cam = S.scmos_camera(h, w, 29)
+    frames = S.render_frames(2, h, w, "sparse", 4047, camera=cam)
+    blob = S.serialize_weights(spec, wts)
+    plain = dl.Net(blob)
+    plain.set_camera_maps(cam.gain, cam.offset)
+    r0, u0, c0 = localize_unc(plain, frames)
+    gated = dl.Net(blob, flags=dl.DL_FLAG_GATE)
+    gated.set_camera_maps(cam.gain, cam.offset)
+    th = np.zeros(673, np.float32)
+    th[672] = 20.0                                        # keeps every tile
+    gated.set_gate(th, 0.05)
+    r1, u1, c1 = localize_unc(gated, frames)
+    assert len(r0) > 0
+    assert np.array_equal(r0, r1) and np.array_equal(u0, u1) and np.array_equal(c0, c1)
