@@ -227,6 +227,16 @@ int dl_localize(dl_net *net, const uint16_t *frames, int n, int h, int w,
 int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w,
                           int overlap, dl_emitter *out, size_t cap, size_t *count);
 
+/* dl_localize and dl_localize_pipelined for a network with the 10-output head,
+ * also writing each record's uncertainties to the host array unc[cap] (entry
+ * i beside out[i]; may be NULL only when cap is 0).  The handle then also
+ * keeps two device slots of min(cap, n*h*w) dl_uncertainty.  Errors as the
+ * plain calls, plus DL_ERR_UNSUPPORTED for a 5-output network. */
+int dl_localize_unc(dl_net *net, const uint16_t *frames, int n, int h, int w,
+                    dl_emitter *out, dl_uncertainty *unc, size_t cap, size_t *count);
+int dl_localize_pipelined_unc(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w,
+                              int overlap, dl_emitter *out, dl_uncertainty *unc, size_t cap, size_t *count);
+
 /* Uneven batch of ROIs (device data; the dl_roi array itself is host memory).
  * Same outputs as dl_localize_device with n = nroi. */
 int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream,

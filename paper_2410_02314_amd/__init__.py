@@ -90,6 +90,8 @@ def _load():
         "dl_maps_device": (I, [P, P, I, I, I, P, P]),
         "dl_localize": (I, [P, P, I, I, I, P, Z, ctypes.POINTER(Z)]),
         "dl_localize_pipelined": (I, [P, P, I, I, I, I, I, P, Z, ctypes.POINTER(Z)]),
+        "dl_localize_pipelined_unc": (I, [P, P, I, I, I, I, I, P, P, Z, ctypes.POINTER(Z)]),
+        "dl_localize_unc": (I, [P, P, I, I, I, P, P, Z, ctypes.POINTER(Z)]),
         "dl_localize_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P, Z, P]),
         "dl_maps_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P]),
         "dl_host_alloc": (I, [Z, ctypes.POINTER(P)]),
@@ -311,6 +313,27 @@ class Net:
             return self.localize_pipelined(frames, overlap, cap=int(cnt.value))
         _check(rc, self.handle)
         return out[:cnt.value]          # a view: only the filled records were touched
+
+    def localize_pipelined_unc(self, frames: np.ndarray, overlap: bool = True, cap: Optional[int] = None):
+        """localize_pipelined for a 10-output network: (records, uncertainties),
+        structured arrays of EMITTER_DTYPE and UNCERTAINTY_DTYPE."""
+        F = np.ascontiguousarray(frames, np.uint16)
+        nb, n, h, w = F.shape
+        if cap is None:
+            cap = max(1024, F.size // 16)
+        out = np.empty(cap, EMITTER_DTYPE)
+        unc = np.empty(cap, UNCERTAINTY_DTYPE)
+        cnt = ctypes.c_size_t()
+        rc = _lib.dl_localize_pipelined_unc(self.handle, F.ctypes.data, nb, n, h, w, int(bool(overlap)),
+                                            out.ctypes.data, unc.ctypes.data, cap, ctypes.byref(cnt))
+        if rc == DL_ERR_CAPACITY:
+            return self.localize_pipelined_unc(frames, overlap, cap=int(cnt.value))
+        _check(rc, self.handle)
+        return out[:cnt.value], unc[:cnt.value]
+
+    def localize_unc(self, frames: np.ndarray, cap: Optional[int] = None):
+        """Host frames [n, h, w] of a 10-output network -> (records, uncertainties)."""
+        return self.localize_pipelined_unc(frames[None], overlap=False, cap=cap)
 
     def graph(self, frames, out, counts) -> "Graph":
         """Capture localization of this fixed frame buffer into a HIP graph."""

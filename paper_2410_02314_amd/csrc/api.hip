@@ -84,9 +84,10 @@ struct dl_net {
     uint16_t *pl_frames[2] = {};
     uint16_t *pl_stage[2] = {};
     dl_emitter *pl_out[2] = {};
+    dl_uncertainty *pl_unc[2] = {};   // record uncertainties (10-output nets, on demand)
     uint32_t *pl_dcounts = nullptr;   // device [2][n + 1]
     uint32_t *pl_hcounts = nullptr;   // pinned [2][n + 1]
-    size_t pl_frame_bytes = 0, pl_stage_bytes = 0, pl_out_cap = 0;
+    size_t pl_frame_bytes = 0, pl_stage_bytes = 0, pl_out_cap = 0, pl_unc_cap = 0;
     int pl_counts_n = 0;
     hipEvent_t pl_copied[2] = {}, pl_used[2] = {}, pl_counted[2] = {};
 
@@ -829,6 +830,7 @@ void dl_destroy_net(dl_net *net)
         if (net->pl_frames[i]) (void)hipFree(net->pl_frames[i]);
         if (net->pl_stage[i]) (void)hipHostFree(net->pl_stage[i]);
         if (net->pl_out[i]) (void)hipFree(net->pl_out[i]);
+        if (net->pl_unc[i]) (void)hipFree(net->pl_unc[i]);
         for (hipEvent_t e : {net->pl_copied[i], net->pl_used[i], net->pl_counted[i]})
             if (e) (void)hipEventDestroy(e);
     }
@@ -1058,10 +1060,10 @@ static bool is_pinned(const void *p)
 // Grow the pipeline's slot buffers to hold batches of `fbytes` frame bytes,
 // `out_cap` records and n + 1 counts.  Waits for all work on the device before
 // it frees anything.
-static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_cap, int n)
+static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_cap, int n, bool unc)
 {
     const bool grow = fbytes > net->pl_frame_bytes || (staged && fbytes > net->pl_stage_bytes) ||
-                      out_cap > net->pl_out_cap || n + 1 > net->pl_counts_n;
+                      out_cap > net->pl_out_cap || n + 1 > net->pl_counts_n || (unc && out_cap > net->pl_unc_cap);
     if (!grow && net->pl_copied[0]) return DL_OK;
     HIPCHK(net, hipDeviceSynchronize());
     for (int i = 0; i < 2; ++i) {
@@ -1110,6 +1112,19 @@ static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_c
             }
         net->pl_out_cap = out_cap;
     }
+    if (unc && out_cap > net->pl_unc_cap) {
+        for (auto &p : net->pl_unc) {
+            if (p) HIPCHK(net, hipFree(p));
+            p = nullptr;
+        }
+        net->pl_unc_cap = 0;
+        for (auto &p : net->pl_unc)
+            if (hipMalloc(&p, out_cap * sizeof(dl_uncertainty)) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(net, DL_ERR_OOM, "hipMalloc for %zu record uncertainties failed", out_cap);
+            }
+        net->pl_unc_cap = out_cap;
+    }
     if (n + 1 > net->pl_counts_n) {
         if (net->pl_dcounts) HIPCHK(net, hipFree(net->pl_dcounts));
         if (net->pl_hcounts) HIPCHK(net, hipHostFree(net->pl_hcounts));
@@ -1123,8 +1138,10 @@ static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_c
     return DL_OK;
 }
 
-int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w, int overlap,
-                          dl_emitter *out, size_t cap, size_t *count)
+// Host-frame localization of nbatch batches (unc: the records'
+// uncertainties too, for 10-output nets; else null).
+static int localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w, int overlap,
+                              dl_emitter *out, dl_uncertainty *unc, size_t cap, size_t *count)
 {
     int rc = check_uniform(net, frames, n, h, w);
     if (rc) return rc;
@@ -1137,7 +1154,7 @@ int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n
     const bool pinned = is_pinned(frames);
     // a batch yields at most one record per pixel
     const size_t slot_cap = std::max<size_t>(1, std::min<size_t>(cap, (size_t)n * h * w));
-    if ((rc = ensure_pipeline(net, fbytes, !pinned, slot_cap, n))) return rc;
+    if ((rc = ensure_pipeline(net, fbytes, !pinned, slot_cap, n, unc != nullptr))) return rc;
 
     // Slot k & 1 holds batch k's frames, records and counts.  With overlap the
     // copy of batch k (copy stream) waits on the device for the compute that
@@ -1173,6 +1190,9 @@ int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n
         const size_t take = std::min<size_t>(tot, cap - written);
         if (take) {
             PCHK(hipMemcpyAsync(out + written, net->pl_out[sl], take * sizeof(dl_emitter), hipMemcpyDeviceToHost, xs));
+            if (unc)
+                PCHK(hipMemcpyAsync(unc + written, net->pl_unc[sl], take * sizeof(dl_uncertainty),
+                                    hipMemcpyDeviceToHost, xs));
             PCHK(hipStreamSynchronize(xs));
             for (size_t r = 0; r < take; ++r) out[written + r].frame += j * n;
         }
@@ -1198,7 +1218,7 @@ int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n
         // an upper bound on the room left: batches not yet collected take none
         const size_t room = std::min(slot_cap, cap - std::min(cap, written));
         rc = localize_geom(net, fd, g, cs, room ? net->pl_out[sl] : nullptr, room, net->pl_dcounts + sl * cn,
-                           nullptr, net->pl_frames[sl], n, h, w);
+                           nullptr, net->pl_frames[sl], n, h, w, unc && room ? net->pl_unc[sl] : nullptr);
         if (rc) { drain(); return rc; }
         PCHK(hipEventRecord(net->pl_used[sl], cs));
         PCHK(hipMemcpyAsync(net->pl_hcounts + sl * cn, net->pl_dcounts + sl * cn, cn * 4, hipMemcpyDeviceToHost, cs));
@@ -1216,9 +1236,30 @@ int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n
     return DL_OK;
 }
 
+int dl_localize_pipelined(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w, int overlap,
+                          dl_emitter *out, size_t cap, size_t *count)
+{
+    return localize_pipelined(net, frames, nbatch, n, h, w, overlap, out, nullptr, cap, count);
+}
+
+int dl_localize_pipelined_unc(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w, int overlap,
+                              dl_emitter *out, dl_uncertainty *unc, size_t cap, size_t *count)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (net->nh != 10) return fail(net, DL_ERR_UNSUPPORTED, "the network has no uncertainty head (%d outputs)", net->nh);
+    if (cap > 0 && !unc) return fail(net, DL_ERR_INVALID_ARG, "unc is NULL with cap > 0");
+    return localize_pipelined(net, frames, nbatch, n, h, w, overlap, out, cap ? unc : nullptr, cap, count);
+}
+
 int dl_localize(dl_net *net, const uint16_t *frames, int n, int h, int w, dl_emitter *out, size_t cap, size_t *count)
 {
-    return dl_localize_pipelined(net, frames, 1, n, h, w, 0, out, cap, count);
+    return localize_pipelined(net, frames, 1, n, h, w, 0, out, nullptr, cap, count);
+}
+
+int dl_localize_unc(dl_net *net, const uint16_t *frames, int n, int h, int w, dl_emitter *out, dl_uncertainty *unc,
+                    size_t cap, size_t *count)
+{
+    return dl_localize_pipelined_unc(net, frames, 1, n, h, w, 0, out, unc, cap, count);
 }
 
 int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int n, int h, int w, int blk,

@@ -15,7 +15,8 @@ background) on the GPU:
   uncertainties equal to the per-ROI runs; a graph of the 10-output net
   replays the eager records;
 * a keep-all gate on sCMOS frames with camera maps gives the ungated records
-  and uncertainties bit for bit.
+  and uncertainties bit for bit;
+* the host entry points return the device path's records and uncertainties.
 """
 import numpy as np
 import pytest
@@ -223,3 +224,27 @@ def test_gate_camera_maps_and_uncertainties_together():
     r1, u1, c1 = localize_unc(gated, frames)
     assert len(r0) > 0
     assert np.array_equal(r0, r1) and np.array_equal(u0, u1) and np.array_equal(c0, c1)
+
+
+@pytest.mark.parametrize("overlap", [True, False])
+def test_host_entry_points_with_uncertainties(overlap):
+    """dl_localize_unc and dl_localize_pipelined_unc give the device path's
+    records and uncertainties (records of later batches counted across
+    batches); a 5-output net refuses them."""
+    spec, wts, net = make("AU")
+    frames = S.render_frames(6, 96, 128, "tiny", 86).reshape(3, 2, 96, 128)
+    ref_r, ref_u = [], []
+    for k in range(3):
+        r, u, _ = localize_unc(net, frames[k])
+        r = r.copy()
+        r["frame"] += 2 * k
+        ref_r.append(r)
+        ref_u.append(u)
+    got_r, got_u = net.localize_pipelined_unc(frames, overlap=overlap)
+    assert np.array_equal(got_r, np.concatenate(ref_r)) and np.array_equal(got_u, np.concatenate(ref_u))
+    r1, u1 = net.localize_unc(frames[1])
+    assert np.array_equal(u1, ref_u[1])
+    _, _, n5 = make("A")
+    with pytest.raises(dl.DlocError) as e:
+        n5.localize_unc(frames[0])
+    assert e.value.code == dl.DL_ERR_UNSUPPORTED
