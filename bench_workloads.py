@@ -63,6 +63,8 @@ def tiny(args, S):
     out = torch.empty((8192, 8), dtype=torch.int32, device=dev)
     counts = torch.zeros(5, dtype=torch.int32, device=dev)
     st = torch.cuda.current_stream()
+    # the autotuner times both conv tile shapes on this batch and keeps the faster
+    rows, tune_ms = net.autotune(d, reps=50, stream=st) if not args.tile_rows else (args.tile_rows, {})
     steps = max(args.steps, 1000)               # latency-scale: a 1000-iteration replay
     ms_eager = _timed(lambda: net.localize_device(d, out, counts, st), steps, max(args.warmup, 20), st)
     g = net.graph(d, out, counts)
@@ -72,6 +74,7 @@ def tiny(args, S):
           {"workload": "4 x 128x128 uint16 frames, 2D Gaussian PSF, net A (C=32, d=1,2,4)",
            "precision": args.precision, "frames": 4, "height": 128, "width": 128},
           {"eager_ms_per_step": round(ms_eager, 4), "graph_ms_per_step": round(ms_graph, 4),
+           "conv_tile_rows": rows, "autotune_ms": {k: round(v, 4) for k, v in tune_ms.items()},
            "eager_mpx_s": round(px / (ms_eager * 1e-3) / 1e6, 3), "emitters_per_step": int(counts[4].item())})
     g.close()
 
