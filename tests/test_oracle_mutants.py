@@ -5,8 +5,17 @@ FP8 scale one power of two off, the gate's gradient sent to the last maximum,
 swapped camera maps, a dropped head bias.  It builds the copy with the
 oracle's own flags, points the oracle module at it, and checks that at least
 one of the named pins fails.  The planted copy lives in a temporary directory;
-the real oracle is restored afterwards."""
+the real oracle is restored afterwards.
+
+The post-processing written in Python (records, softplus, uncertainties, the
+sigma filter, the threshold's logit) gets the same treatment: a mistake is
+planted in one function's source, the changed function replaces the oracle's
+for the duration of the test, and a named pin must fail."""
+import inspect
 import subprocess
+import textwrap
+
+import numpy as np
 
 import pytest
 
@@ -80,4 +89,53 @@ def test_pins_reject_a_planted_mistake(name, old, new, pins, tmp_path, monkeypat
             pin(*args)
         except AssertionError:
             failed.append(pin.__name__)
+    assert failed, f"no pin caught: {name}"
+
+
+PY_MUTANTS = [
+    ("pixel centre half dropped", "records",
+     'out["x"] = cols + 0.5 + maps[1, rows, cols]',
+     'out["x"] = cols + maps[1, rows, cols]',
+     [(PINS.test_records_coordinates, ())]),
+    ("x takes the y offset plane", "records",
+     "cols + 0.5 + maps[1, rows, cols]",
+     "cols + 0.5 + maps[2, rows, cols]",
+     [(PINS.test_records_coordinates, ())]),
+    ("softplus loses its small values", "softplus",
+     "np.maximum(u, 0.0) + np.log1p(np.exp(-np.abs(u)))",
+     "np.maximum(u, 0.0)",
+     [(UNC.test_softplus_special_values, ())]),
+    ("softplus in the overflowing form", "softplus",
+     "np.maximum(u, 0.0) + np.log1p(np.exp(-np.abs(u)))",
+     "np.log1p(np.exp(u))",
+     [(UNC.test_softplus_special_values, ())]),
+    ("background scaled the wrong way", "uncertainties",
+     "sp[4] / spec.in_scale",
+     "sp[4] * spec.in_scale",
+     [(UNC.test_uncertainty_units_at_zero_raw_value, ())]),
+    ("sigma filter reads the z plane", "sigma_filter",
+     "(softplus(maps[6]) <= max_sigma_px)",
+     "(softplus(maps[7]) <= max_sigma_px)",
+     [(UNC.test_sigma_filter_invariants, ())]),
+    ("threshold turned into a logit with the wrong odds", "localize",
+     "math.log(threshold / (1.0 - threshold))",
+     "math.log(threshold / (1.0 + threshold))",
+     [(PINS.test_localize_threshold_is_a_probability, (0.3,))]),
+]
+
+
+@pytest.mark.parametrize("name,fname,old,new,pins", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_pins_reject_a_planted_python_mistake(name, fname, old, new, pins, monkeypatch):
+    src = textwrap.dedent(inspect.getsource(getattr(oracle, fname)))
+    assert src.count(old) == 1, "the planted mistake's target text must occur once"
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), f"<planted mistake in oracle.{fname}>", "exec"), ns)
+    monkeypatch.setattr(oracle, fname, ns[fname])
+    failed = []
+    with np.errstate(all="ignore"):
+        for pin, args in pins:
+            try:
+                pin(*args)
+            except AssertionError:
+                failed.append(pin.__name__)
     assert failed, f"no pin caught: {name}"

@@ -234,6 +234,20 @@ def test_threshold_is_probability_0_3():
     assert abs(oracle.TAU - (-0.8472978603872037)) < 1e-15
 
 
+@pytest.mark.parametrize("threshold", [0.3, 0.7])
+def test_localize_threshold_is_a_probability(threshold):
+    """The whole path keeps exactly the local maxima (found with no threshold)
+    whose probability 1 / (1 + e^-logit) exceeds the threshold, at any threshold."""
+    spec, w = S.make_net("A", 1)
+    fr = S.render_frames(1, 64, 64, "tiny", 12)
+    rec, maps = oracle.localize(fr, spec, w, threshold=threshold, return_maps=True)
+    L = maps[0, 0]
+    expect = oracle.detect(L, -np.inf) & (1.0 / (1.0 + np.exp(-L)) > threshold)
+    assert len(rec) == expect.sum() > 0
+    assert np.array_equal(np.stack([rec["row"], rec["col"]], 1), np.argwhere(expect))
+    assert np.all(rec["prob"] > threshold)
+
+
 def test_records_coordinates():
     spec = S.NET_A
     h, w = 4, 5
