@@ -171,6 +171,9 @@ int dl_set_config(dl_net *net, const dl_config *cfg);
  *   d_out     device dl_emitter[cap]; records in (frame, row, col) order; only
  *             the first cap records are written
  *   d_counts  device uint32[n + 1]: emitters per frame, then the total
+ * n, h and w must be >= 1: an empty batch or a zero-sized frame is
+ * DL_ERR_INVALID_ARG, returned before anything is queued (this holds for every
+ * entry point that takes n, h, w).
  * Work is queued on `stream`.  Overflow (total > cap) is visible as
  * d_counts[n] > cap once the stream completes; the call itself returns DL_OK. */
 int dl_localize_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w,

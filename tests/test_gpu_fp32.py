@@ -115,6 +115,29 @@ def test_tiny_and_degenerate_shapes(h, w):
     assert compare_emitters(rec, ref, ref_maps)["non_exempt_mismatch"] == 0
 
 
+def test_empty_batch_and_zero_sized_frames_are_refused():
+    """n = 0, h = 0 or w = 0 is DL_ERR_INVALID_ARG from the localize and maps
+    entry points, before any work is queued; the handle then works as before."""
+    spec, wts, net = make("A", 1)
+    out = torch.zeros((64, 8), dtype=torch.int32, device=DEV)
+    counts = torch.full((3,), -1, dtype=torch.int32, device=DEV)
+    maps = torch.zeros(8, dtype=torch.float32, device=DEV)
+    for shape in [(0, 32, 32), (2, 0, 32), (2, 32, 0)]:
+        fr = torch.from_numpy(np.zeros(shape, np.uint16)).to(DEV)
+        with pytest.raises(dl.DlocError) as e:
+            net.localize_device(fr, out, counts)
+        assert e.value.code == dl.DL_ERR_INVALID_ARG
+        with pytest.raises(dl.DlocError) as e:
+            net.maps_device(fr, maps)
+        assert e.value.code == dl.DL_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert counts.cpu().tolist() == [-1, -1, -1]          # nothing was written
+    frames = S.render_frames(2, 48, 56, "tiny", 13)
+    ref, ref_maps = oracle.localize(frames, spec, wts, return_maps=True)
+    rec, c = gpu_localize(net, frames)
+    assert compare_emitters(rec, ref, ref_maps)["non_exempt_mismatch"] == 0 and c[-1] == len(rec)
+
+
 def test_no_detections_frame():
     """A frame at the camera offset everywhere (zero photons) gives no emitters."""
     spec, wts, net = make("A", 1)
