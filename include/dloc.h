@@ -173,7 +173,13 @@ int dl_set_config(dl_net *net, const dl_config *cfg);
  *   d_counts  device uint32[n + 1]: emitters per frame, then the total
  * n, h and w must be >= 1: an empty batch or a zero-sized frame is
  * DL_ERR_INVALID_ARG, returned before anything is queued (this holds for every
- * entry point that takes n, h, w).
+ * entry point that takes n, h, w).  A frame larger than the kernels address is
+ * DL_ERR_UNSUPPORTED, also before anything is queued: h * w <= 2^28, n * h <=
+ * 2^30, and the frame's stored activations (C values per point, 4 / 2 / 1
+ * bytes in FP32 / BF16 / FP8, both sides rounded up to the net's largest
+ * phase layout, 16 for dilations up to 16) under 2 GiB.  For C = 48 and
+ * dilations up to 16 the largest square frames are 3344 (FP32), 4720 (BF16)
+ * and 6688 (FP8) pixels a side; larger images go in as ROIs or tiles.
  * Work is queued on `stream`.  Overflow (total > cap) is visible as
  * d_counts[n] > cap once the stream completes; the call itself returns DL_OK. */
 int dl_localize_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w,

@@ -138,6 +138,32 @@ def test_empty_batch_and_zero_sized_frames_are_refused():
     assert compare_emitters(rec, ref, ref_maps)["non_exempt_mismatch"] == 0 and c[-1] == len(rec)
 
 
+@pytest.mark.parametrize("precision,h,w", [("fp32", 3345, 3344), ("fp32", 3344, 3345), ("bf16", 4721, 4721),
+                                           ("fp8", 6689, 6688), ("fp8", 6688, 6689)])
+def test_frames_past_the_activation_limit_are_refused(precision, h, w):
+    """A frame's stored activations must stay under 2 GiB (the conv kernels
+    address a frame with 32-bit byte offsets).  For net B, whose largest phase
+    layout rounds both sides up to multiples of 16, these frames are just past
+    it (largest accepted squares: 3344 FP32, 4720 BF16, 6688 FP8): the call is
+    DL_ERR_UNSUPPORTED before anything is queued, and the handle stays usable."""
+    spec, wts, net = make("B", 2, precision=precision)
+    esz = {"fp32": 4, "bf16": 2, "fp8": 1}[precision]
+    side = {"fp32": 3344, "bf16": 4720, "fp8": 6688}[precision]
+    assert side % 16 == 0 and side * side * spec.C * esz < 2 ** 31
+    assert 256 * -(-h // 16) * -(-w // 16) * spec.C * esz >= 2 ** 31 and h * w <= 2 ** 28
+    fr = torch.zeros((1, h, w), dtype=torch.int16, device=DEV)
+    out = torch.zeros((64, 8), dtype=torch.int32, device=DEV)
+    counts = torch.full((2,), -1, dtype=torch.int32, device=DEV)
+    with pytest.raises(dl.DlocError) as e:
+        net.localize_device(fr, out, counts)
+    assert e.value.code == dl.DL_ERR_UNSUPPORTED
+    torch.cuda.synchronize()
+    assert counts.cpu().tolist() == [-1, -1]
+    frames = S.render_frames(1, 64, 80, "full", 14)
+    rec, c = gpu_localize(net, frames)
+    assert c[-1] == len(rec)
+
+
 def test_no_detections_frame():
     """A frame at the camera offset everywhere (zero photons) gives no emitters."""
     spec, wts, net = make("A", 1)
