@@ -63,6 +63,7 @@ def _L():
         _lib.or_fp8_group_exp.restype = i
         _lib.or_fp8_group_exp.argtypes = [d]
         _lib.or_store_fp8_groups.argtypes = [P, i, l]
+        _lib.or_quant_weights_fp8.argtypes = [P, i, l]
         _lib.or_preprocess.argtypes = [P, l, d, d, d, P]
         _lib.or_conv3x3.argtypes = [P, i, i, i, P, P, i, i, P]
         _lib.or_net_maps.restype = i
@@ -109,6 +110,16 @@ def store_fp8_groups(a: np.ndarray) -> np.ndarray:
     out = np.ascontiguousarray(a, np.float64).copy()
     C = out.shape[0]
     _L().or_store_fp8_groups(_p(out), C, out.size // C)
+    return out
+
+
+def quant_weights_fp8(W: np.ndarray) -> np.ndarray:
+    """FP8 e4m3 quantisation of a convolution weight tensor [cout][...] with one
+    scale per output channel, max|W[o]| / 448 (FP32); returns the dequantised
+    FP64 values the FP8 emulation multiplies with."""
+    out = np.ascontiguousarray(W, np.float64).copy()
+    cout = out.shape[0]
+    _L().or_quant_weights_fp8(_p(out), cout, out.size // cout)
     return out
 
 

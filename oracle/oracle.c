@@ -200,8 +200,9 @@ static void promote(const float *src, long n, double *dst)
 }
 
 /* per-output-channel e4m3 weight quantisation: ws[o] = max|W[o]| / 448 (FP32),
- * Wq = e4m3(W * fl32(448 / max|W[o]|)) * ws[o], i.e. the dequantised value. */
-static void quant_weights_fp8(double *W, int cout, long per_out)
+ * Wq = e4m3(W * fl32(448 / max|W[o]|)) * ws[o], i.e. the dequantised value.
+ * W is [cout][per_out], quantised in place. */
+void or_quant_weights_fp8(double *W, int cout, long per_out)
 {
     for (int o = 0; o < cout; ++o) {
         double *wo = W + (long)o * per_out;
@@ -249,7 +250,7 @@ static int net_maps_from_input(const double *x, int h, int w, const float *param
         promote(p, nconv, Wd); p += nconv;
         promote(p, C, bd); p += C;
         if (quant == 1) for (long k = 0; k < nconv; ++k) Wd[k] = or_round_bf16(Wd[k]);
-        if (quant == 2) quant_weights_fp8(Wd, C, (long)C * 9);
+        if (quant == 2) or_quant_weights_fp8(Wd, C, (long)C * 9);
         or_conv3x3(a, C, h, w, Wd, bd, C, d, t);
         for (long k = 0; k < hw * C; ++k) t[k] = store_round(t[k] > 0 ? t[k] : 0.0, quant);
         if (quant == 2) or_store_fp8_groups(t, C, hw);
@@ -257,7 +258,7 @@ static int net_maps_from_input(const double *x, int h, int w, const float *param
         promote(p, nconv, Wd); p += nconv;
         promote(p, C, bd); p += C;
         if (quant == 1) for (long k = 0; k < nconv; ++k) Wd[k] = or_round_bf16(Wd[k]);
-        if (quant == 2) quant_weights_fp8(Wd, C, (long)C * 9);
+        if (quant == 2) or_quant_weights_fp8(Wd, C, (long)C * 9);
         or_conv3x3(t, C, h, w, Wd, bd, C, d, u);
         for (long k = 0; k < hw * C; ++k) {
             double s = a[k] + u[k];

@@ -1,8 +1,10 @@
 """The oracle's pins catch plausible mistakes.  Each case plants one mistake
 in a copy of oracle.c: a transposed kernel, a dropped dilation, a dropped bias
 or residual, a wrong sign, a reversed tie-break, truncating BF16 rounding, an
-FP8 scale one power of two off, the gate's gradient sent to the last maximum,
-swapped camera maps, a dropped head bias.  It builds the copy with the
+FP8 group scale one power of two off, an FP8 weight scale taken over the
+whole tensor or applied the wrong way, an FP8 rounding point dropped or
+added, the gate's gradient sent to the last maximum, swapped camera maps, a
+dropped head bias.  It builds the copy with the
 oracle's own flags, points the oracle module at it, and checks that at least
 one of the named pins fails.  The planted copy lives in a temporary directory;
 the real oracle is restored afterwards.
@@ -22,6 +24,7 @@ import pytest
 import oracle
 import smlm_synth as S
 from tests import test_oracle_camera as CAM
+from tests import test_oracle_fp8 as FP8
 from tests import test_oracle_pins as PINS
 from tests import test_oracle_uncertainty as UNC
 
@@ -62,6 +65,26 @@ MUTANTS = [
      "int k = (e - 1) - (f <= 1.75 ? 8 : 7);",
      "int k = (e - 1) - (f <= 1.75 ? 9 : 8);",
      [(PINS.test_fp8_group_exponent_is_smallest_fitting_power_of_two, ())]),
+    ("FP8 weight scale from the whole tensor's maximum",
+     "for (long k = 0; k < per_out; ++k) if (fabs(wo[k]) > mx) mx = fabs(wo[k]);",
+     "for (long k = 0; k < per_out * cout; ++k) if (fabs(W[k]) > mx) mx = fabs(W[k]);",
+     [(FP8.test_fp8_weight_quant_closed_form, ()), (FP8.test_fp8_weight_quant_per_channel_properties, ())]),
+    ("FP8 weights multiplied by the scale instead of its inverse",
+     "float inv = (float)(448.0 / mx);",
+     "float inv = (float)(mx / 448.0);",
+     [(FP8.test_fp8_weight_quant_closed_form, ())]),
+    ("FP8 stem output left unrounded",
+     "if (quant == 2 && nblocks > 0) or_store_fp8_groups(a, C, hw);",
+     ";",
+     [(FP8.test_fp8_emulation_matches_torch_composition, (48, (1, 2, 4)))]),
+    ("FP8 block intermediate left unrounded",
+     "if (quant == 2) or_store_fp8_groups(t, C, hw);",
+     ";",
+     [(FP8.test_fp8_emulation_matches_torch_composition, (48, (1, 2, 4)))]),
+    ("FP8 last block output rounded before the head",
+     "if (quant == 2 && blk + 1 < nblocks) or_store_fp8_groups(a, C, hw);",
+     "if (quant == 2) or_store_fp8_groups(a, C, hw);",
+     [(FP8.test_fp8_emulation_matches_torch_composition, (48, (1, 2, 4)))]),
     ("gate pool takes the last maximum",
      "if (h2[(long)c * hw + k] > h2[(long)c * hw + a]) a = k;",
      "if (h2[(long)c * hw + k] >= h2[(long)c * hw + a]) a = k;",
