@@ -1,15 +1,18 @@
-"""Reduced-precision form: BF16 block convolutions with FP32 accumulation.
+"""Reduced-precision forms (BF16 and FP8 block convolutions, FP32
+accumulation) on realistic networks: accuracy reports.
 
-* Quantisation logic, pinned bit for bit: with small-integer weights and
-  inputs every product and sum is exact in FP32 and FP64, so the GPU's BF16
-  form must equal the oracle's BF16 emulation exactly -- including the rounding
-  of stored integers above 256, which bfloat16 cannot all represent.
-* Realistic weights: the GPU stays as close to the emulation as bfloat16
-  noise allows (differences start where FP32 and FP64 accumulation land on
-  opposite sides of a bfloat16 rounding boundary and then propagate).
-* Accuracy against the exact FP64 oracle (tiny workload): emitters matched
-  one-to-one within 1 px; recall, precision and RMS offset differences are
-  printed and held to the measured level of the oracle's own BF16 emulation.
+Their parity is pinned bit for bit in ``test_gpu_exact.py`` (integer-valued
+networks on which every sum is exact, so the only rounding is the form's
+own).  On real weights the FP32 and FP64 accumulations of the GPU and the
+emulation land on opposite sides of some rounding boundaries and the
+differences propagate, so these tests report how close the GPU stays to the
+oracle's emulation and to the exact FP64 oracle, and guard that level:
+
+* maps: the GPU's error against the emulation is no more than twice the
+  emulation's own error against the exact oracle;
+* emitters (matched one-to-one within 1 px): recall, precision and RMS offset
+  differences against the exact oracle, held to the level of the oracle's own
+  emulation of the form.
 """
 import numpy as np
 import pytest
