@@ -156,11 +156,19 @@ def main():
     def public(r):
         return {k: v for k, v in r.items() if k not in ("net", "records")}
 
+    for r in results.values():
+        if r.get("accuracy_vs_oracle"):
+            r["accuracy_target"] = accuracy_target(r["accuracy_vs_oracle"])
     n, side = args.frames, args.size
     others = {}
     for f in forms[1:]:
         r = public(results[f])
-        r["speedup_vs_" + args.precision] = round(r["value"] / head["value"], 3)
+        sp = round(r["value"] / head["value"], 3)
+        r["speedup_vs_" + args.precision] = sp
+        # a speedup counts as "at oracle-matched recall" only where the form
+        # meets the accuracy target on the oracle's sample
+        met = bool(r.get("accuracy_target", {}).get("met"))
+        r["speedup_at_matched_recall"] = sp if met else None
         others[f] = r
     res = {
         "metric": METRIC, "value": head["value"], "unit": "Mpixel/s", "n_gpus": 1,
@@ -178,7 +186,9 @@ def main():
         "bandwidth_kernels": head["bandwidth_kernels"],
         "emitters_per_step": head["emitters_per_step"],
         "accuracy_vs_oracle": head.get("accuracy_vs_oracle"),
+        "accuracy_target": head.get("accuracy_target"),
         "forms": others,
+        "gated_form": "measured by --workload sparse (sparse frames; the gate is trained first), not in this line",
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
@@ -273,6 +283,24 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
             "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]},
             "bandwidth_kernels": bw,
             "emitters_per_step": int(counts[n]), "net": net, "records": recs}
+
+
+RECALL_TARGET = 0.995
+OFFSET_RMS_TARGET_PX = 0.01
+
+
+def accuracy_target(acc):
+    """The accuracy bar a form's speedup is judged at: recall >= 0.995 against
+    the FP64 oracle's detections (one-to-one within 1 px) and RMS offset error
+    <= 0.01 px, taken as the larger of the x and y RMS differences of the
+    detections both put at the same pixel (the offset heads' own error; a
+    maximum that moves to a neighbour pixel is a recall question)."""
+    off = max(acc.get("same_pixel_rms_dx_px", math.inf), acc.get("same_pixel_rms_dy_px", math.inf))
+    rec = acc.get("recall", 0.0)
+    return {"recall": rec, "recall_min": RECALL_TARGET, "offset_rms_px": round(off, 6),
+            "offset_rms_max_px": OFFSET_RMS_TARGET_PX,
+            "offset_rms_used": "max(same_pixel_rms_dx_px, same_pixel_rms_dy_px)",
+            "met": bool(rec >= RECALL_TARGET and off <= OFFSET_RMS_TARGET_PX)}
 
 
 def accuracy_on_sample(recs, ref):

@@ -173,6 +173,29 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+def _frames_arg(frames, ndim: int = 3):
+    """A device frame batch as the C ABI reads it: dense rows of 16-bit
+    pixels.  A sliced, transposed or wrongly typed tensor would be read from
+    the wrong addresses, so it is refused here."""
+    import torch
+    if frames.dim() != ndim:
+        raise ValueError(f"frames must have {ndim} dimensions, got shape {tuple(frames.shape)}")
+    if frames.dtype not in (torch.uint16, torch.int16):
+        raise ValueError(f"frames must hold 16-bit pixels (torch.uint16), got {frames.dtype}")
+    if not frames.is_contiguous():
+        raise ValueError("frames must be contiguous (call .contiguous() first)")
+    return frames
+
+
+def _host_frames(frames, ndim: int) -> np.ndarray:
+    F = np.asarray(frames)
+    if F.dtype != np.uint16:
+        raise ValueError(f"host frames must be uint16, got {F.dtype}")
+    if F.ndim != ndim:
+        raise ValueError(f"host frames must have {ndim} dimensions, got shape {F.shape}")
+    return np.ascontiguousarray(F)
+
+
 def _stream(stream) -> Optional[int]:
     if stream is None:
         import torch
@@ -234,7 +257,7 @@ class Net:
     # ---- device-resident ----
     def localize_device(self, frames, out, counts, stream=None) -> int:
         """frames: cuda uint16 [n, h, w]; out: cuda tensor of cap*32 bytes; counts: cuda int32 [n+1]."""
-        n, h, w = frames.shape
+        n, h, w = _frames_arg(frames).shape
         cap = out.numel() * out.element_size() // 32
         return self._rc(_lib.dl_localize_device(self.handle, _ptr(frames), n, h, w, _stream(stream),
                                                 _ptr(out), cap, _ptr(counts)))
@@ -242,7 +265,7 @@ class Net:
     def localize_device_unc(self, frames, out, unc, counts, stream=None) -> int:
         """localize_device for a 10-output network, also filling unc (cuda
         tensor of cap * 20 bytes, one dl_uncertainty per record)."""
-        n, h, w = frames.shape
+        n, h, w = _frames_arg(frames).shape
         cap = out.numel() * out.element_size() // 32
         if unc.numel() * unc.element_size() < cap * 20:
             raise ValueError("unc holds fewer records than out")
@@ -250,7 +273,7 @@ class Net:
                                                     _ptr(out), _ptr(unc), cap, _ptr(counts)))
 
     def maps_device(self, frames, maps, stream=None) -> int:
-        n, h, w = frames.shape
+        n, h, w = _frames_arg(frames).shape
         return self._rc(_lib.dl_maps_device(self.handle, _ptr(frames), n, h, w, _stream(stream), _ptr(maps)))
 
     def localize_rois_device(self, rois: Sequence, out, counts, stream=None) -> int:
@@ -275,8 +298,13 @@ class Net:
 
     @staticmethod
     def _roi_array(rois):
+        import torch
         arr = (DLRoi * len(rois))()
         for k, r in enumerate(rois):
+            if r.dim() != 2 or r.stride(1) != 1 or r.stride(0) < r.shape[1]:
+                raise ValueError(f"roi {k}: rows must be dense (stride(1) == 1, stride(0) >= w)")
+            if r.dtype not in (torch.uint16, torch.int16):
+                raise ValueError(f"roi {k}: pixels must be 16-bit (torch.uint16), got {r.dtype}")
             arr[k].data = _ptr(r)
             arr[k].h = r.shape[0]
             arr[k].w = r.shape[1]
@@ -301,7 +329,7 @@ class Net:
     def localize_pipelined(self, frames: np.ndarray, overlap: bool = True, cap: Optional[int] = None) -> np.ndarray:
         """Host frames uint16 [nbatch, n, h, w]; batches are copied on a side stream
         while the previous batch is processed (overlap=True)."""
-        F = np.ascontiguousarray(frames, np.uint16)
+        F = _host_frames(frames, 4)
         nb, n, h, w = F.shape
         if cap is None:
             cap = max(1024, F.size // 16)
@@ -317,7 +345,7 @@ class Net:
     def localize_pipelined_unc(self, frames: np.ndarray, overlap: bool = True, cap: Optional[int] = None):
         """localize_pipelined for a 10-output network: (records, uncertainties),
         structured arrays of EMITTER_DTYPE and UNCERTAINTY_DTYPE."""
-        F = np.ascontiguousarray(frames, np.uint16)
+        F = _host_frames(frames, 4)
         nb, n, h, w = F.shape
         if cap is None:
             cap = max(1024, F.size // 16)
@@ -337,7 +365,7 @@ class Net:
 
     def graph(self, frames, out, counts) -> "Graph":
         """Capture localization of this fixed frame buffer into a HIP graph."""
-        n, h, w = frames.shape
+        n, h, w = _frames_arg(frames).shape
         cap = out.numel() * out.element_size() // 32
         g = ctypes.c_void_p()
         self._rc(_lib.dl_graph_create(self.handle, _ptr(frames), n, h, w, _ptr(out), cap, _ptr(counts),
@@ -355,7 +383,7 @@ class Net:
     def autotune(self, frames, reps: int = 3, stream=None):
         """Pick the fastest convolution tile shape for this batch shape; returns
         (rows, {rows: ms per pass})."""
-        n, h, w = frames.shape
+        n, h, w = _frames_arg(frames).shape
         best = ctypes.c_int32()
         ms = (ctypes.c_float * 2)()
         self._rc(_lib.dl_autotune(self.handle, _ptr(frames), n, h, w, _stream(stream), reps, ctypes.byref(best), ms))
@@ -447,7 +475,7 @@ GATE_NPARAM = 673
 
 
 def gate_pool(frames, pooled, gain=0.5, offset=100.0, in_scale=0.01, stream=None):
-    n, h, w = frames.shape
+    n, h, w = _frames_arg(frames).shape
     _check(_lib.dl_gate_pool(_ptr(frames), n, h, w, gain, offset, in_scale, _stream(stream), _ptr(pooled)))
 
 

@@ -55,6 +55,12 @@ struct dl_net {
 
     char *ws = nullptr;
     size_t ws_bytes = 0;
+    // Ordering of runs that share the workspace: ws_ev is recorded on the
+    // stream of the last run that used it (ws_stream); a run on another
+    // stream first waits for it on the device.
+    hipEvent_t ws_ev = nullptr;
+    hipStream_t ws_stream = nullptr;
+    bool ws_used = false;
 
     FrameDesc *h_desc = nullptr;    // pinned, DESC_SLOTS * desc_cap
     FrameDesc *d_desc = nullptr;    // device, DESC_SLOTS * desc_cap
@@ -251,6 +257,32 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     return p;
 }
 
+// A run on stream s that uses the handle's workspace is ordered after the
+// previous such run: when that one was queued on another stream, s waits
+// for it on the device (no host synchronisation).  Skipped while s is being
+// captured into a graph, where an event recorded outside the capture cannot
+// be waited on.
+int ws_acquire(dl_net *net, hipStream_t s)
+{
+    if (!net->ws_used || net->ws_stream == s) return DL_OK;
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    HIPCHK(net, hipStreamIsCapturing(s, &cst));
+    if (cst != hipStreamCaptureStatusNone) return DL_OK;
+    HIPCHK(net, hipStreamWaitEvent(s, net->ws_ev, 0));
+    return DL_OK;
+}
+
+int ws_release(dl_net *net, hipStream_t s)
+{
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    HIPCHK(net, hipStreamIsCapturing(s, &cst));
+    if (cst != hipStreamCaptureStatusNone) return DL_OK;
+    HIPCHK(net, hipEventRecord(net->ws_ev, s));
+    net->ws_stream = s;
+    net->ws_used = true;
+    return DL_OK;
+}
+
 int ensure_workspace(dl_net *net, size_t bytes, hipStream_t s)
 {
     if (bytes <= net->ws_bytes) return DL_OK;
@@ -318,10 +350,11 @@ int ensure_packed(dl_net *net)
                               wscale.data() + (size_t)(b * 2 + k) * C);
             p += (size_t)C * C * 9 + C;
         }
+    // kernels still queued on any stream may read the old weights and scales
+    HIPCHK(net, hipDeviceSynchronize());
     if (!net->d_wscale) HIPCHK(net, hipMalloc(&net->d_wscale, wscale.size() * sizeof(float)));
     HIPCHK(net, hipMemcpy(net->d_wscale, wscale.data(), wscale.size() * sizeof(float), hipMemcpyHostToDevice));
     if (net->d_wpk) {
-        HIPCHK(net, hipDeviceSynchronize());
         HIPCHK(net, hipFree(net->d_wpk));
         net->d_wpk = nullptr;
     }
@@ -543,6 +576,7 @@ int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry 
     }
     Plan p = make_plan(net, g, ext_maps != nullptr);
     if ((rc = ensure_workspace(net, p.total, s))) return rc;
+    if ((rc = ws_acquire(net, s))) return rc;
     p.ws = net->ws;
     FrameDesc *d_fd = nullptr;
     const int slot = upload_desc(net, fd, s, &d_fd);
@@ -554,7 +588,7 @@ int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry 
     if (d_out || d_counts)
         if ((rc = run_post(net, d_fd, g, p, maps, d_out, cap, d_counts, s, d_unc))) return rc;
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
-    return DL_OK;
+    return ws_release(net, s);
 }
 
 }  // namespace
@@ -778,6 +812,8 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     for (int i = 0; i < DESC_SLOTS; ++i)
         if (hipEventCreateWithFlags(&net->desc_ev[i], hipEventDisableTiming) != hipSuccess)
             return bail(fail(net, DL_ERR_DEVICE, "hipEventCreate failed"));
+    if (hipEventCreateWithFlags(&net->ws_ev, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(net, DL_ERR_DEVICE, "hipEventCreate failed"));
     if (hipStreamCreateWithFlags(&net->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&net->compute_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(net, DL_ERR_DEVICE, "hipStreamCreate failed"));
@@ -826,6 +862,7 @@ void dl_destroy_net(dl_net *net)
     if (net->d_desc) (void)hipFree(net->d_desc);
     for (int i = 0; i < DESC_SLOTS; ++i)
         if (net->desc_ev[i]) (void)hipEventDestroy(net->desc_ev[i]);
+    if (net->ws_ev) (void)hipEventDestroy(net->ws_ev);
     for (int i = 0; i < 2; ++i) {
         if (net->pl_frames[i]) (void)hipFree(net->pl_frames[i]);
         if (net->pl_stage[i]) (void)hipHostFree(net->pl_stage[i]);
@@ -1316,6 +1353,7 @@ int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, floa
     uniform_geometry(net, nullptr, n, h, w, fd, g);
     Plan p = make_plan(net, g, true);
     if ((rc = ensure_workspace(net, p.total, s))) return rc;
+    if ((rc = ws_acquire(net, s))) return rc;
     p.ws = net->ws;
     FrameDesc *d_fd = nullptr;
     const int slot = upload_desc(net, fd, s, &d_fd);
@@ -1325,7 +1363,7 @@ int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, floa
     HIPCHK(net, launch_detect_mask(d_logit, 1, d_fd, g, tau, INFINITY, nullptr, mask, rcnt, s));
     HIPCHK(net, launch_mask_to_u8(mask, d_fd, g, d_det, s));
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
-    return DL_OK;
+    return ws_release(net, s);
 }
 
 int dl_graph_create(dl_net *net, const uint16_t *d_frames, int n, int h, int w, dl_emitter *d_out, size_t cap,
@@ -1462,9 +1500,10 @@ int dl_gate_keep_map(dl_net *net, void *stream, uint8_t *d_keep, size_t cap, siz
     if (!d_keep || cap < *ntiles) return fail(net, DL_ERR_CAPACITY, "keep map needs %zu bytes", *ntiles);
     int rc;
     if ((rc = set_device(net))) return rc;
-    HIPCHK(net, hipMemcpyAsync(d_keep, net->ws + net->last_keep_off, *ntiles, hipMemcpyDeviceToDevice,
-                               static_cast<hipStream_t>(stream)));
-    return DL_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = ws_acquire(net, s))) return rc;
+    HIPCHK(net, hipMemcpyAsync(d_keep, net->ws + net->last_keep_off, *ntiles, hipMemcpyDeviceToDevice, s));
+    return ws_release(net, s);
 }
 
 int dl_profile_enable(dl_net *net, int on)

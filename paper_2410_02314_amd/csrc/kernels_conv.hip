@@ -37,9 +37,10 @@
 //         E8M0 scale byte per 32-channel group of each point (dloc_internal.h),
 //         which is exactly the MFMA's per-lane block scale of the activation
 //         operand; weights carry a per-output-channel scale applied in the
-//         epilogue.  The epilogue rounds its output to BF16, takes each group's
-//         max over the four lanes holding the pixel, and stores codes and
-//         scale bytes.
+//         epilogue.  The epilogue takes each 32-channel group's max of the
+//         FP32 outputs over the four lanes holding the pixel, and stores the
+//         e4m3 codes of the FP32 values (scaled by the group's power of two)
+//         and the scale bytes.
 // K is padded with zero-weight chunks when 9 C is not a multiple of the MFMA's K.
 // BF16 and FP8 pass each wave's output row (and residual) through LDS so they
 // move in whole 16-byte lanes; every store is a buffer store whose offset is

@@ -120,3 +120,39 @@ def match_by_distance(got, ref, radius: float = 1.0):
             "rms_dx_px": float(np.sqrt(np.mean(dx ** 2))) if m else 0.0,
             "rms_dy_px": float(np.sqrt(np.mean(dy ** 2))) if m else 0.0,
             "rms_dz_nm": float(np.sqrt(np.mean(dz ** 2))) if m else 0.0}
+
+
+def record_field_errors(got, ref, ref_maps, spec, keys=None):
+    """Worst error of each record field over the emitters both lists hold,
+    each divided by the bound the FP32 map tolerance (1e-4 of |value| + the
+    map's rms) implies for it; a value <= 1 is within tolerance.
+
+    x, y: 1e-3 px (the offsets' 1e-4 bound plus FP32 rounding of
+    col + 0.5 + dx at columns up to 2^12); z and photons: 1e-4 (|dz| + rms dz)
+    times z_scale, likewise ph_scale; prob: the logit bound times the
+    sigmoid's slope (at most 1/4) plus 1e-6.  ``ref_maps`` is [n][planes][h][w]
+    for the frames the records index; ``keys`` restricts the comparison."""
+    gk = {(int(a), int(b), int(c)): i for i, (a, b, c) in enumerate(zip(got["frame"], got["row"], got["col"]))}
+    rk = {(int(a), int(b), int(c)): i for i, (a, b, c) in enumerate(zip(ref["frame"], ref["row"], ref["col"]))}
+    both = [k for k in gk if k in rk and (keys is None or k in keys)]
+    out = {"n": len(both), "x": 0.0, "y": 0.0, "z": 0.0, "photons": 0.0, "prob": 0.0}
+    if not both:
+        return out
+    gi = np.array([gk[k] for k in both])
+    ri = np.array([rk[k] for k in both])
+    fr = np.array([k[0] for k in both])
+    rms = {q: np.array([np.sqrt(np.mean(np.asarray(ref_maps[f, q], np.float64) ** 2)) for f in range(ref_maps.shape[0])])
+           for q in (0, 3, 4)}
+    gx = got["x_px"] if "x_px" in got.dtype.names else got["x"]
+    gy = got["y_px"] if "y_px" in got.dtype.names else got["y"]
+    gz = got["z_nm"] if "z_nm" in got.dtype.names else got["z"]
+    out["x"] = float(np.max(np.abs(gx[gi] - ref["x"][ri])) / 1e-3)
+    out["y"] = float(np.max(np.abs(gy[gi] - ref["y"][ri])) / 1e-3)
+    zb = 1e-4 * (np.abs(ref["z"][ri]) + rms[3][fr] * spec.z_scale) + 1e-6
+    out["z"] = float(np.max(np.abs(gz[gi] - ref["z"][ri]) / zb))
+    pb = 1e-4 * (np.abs(ref["photons"][ri]) + rms[4][fr] * spec.ph_scale) + 1e-6
+    out["photons"] = float(np.max(np.abs(got["photons"][gi] - ref["photons"][ri]) / pb))
+    lg = np.array([ref_maps[k[0], 0, k[1], k[2]] for k in both], np.float64)   # the oracle's logits
+    qb = 0.25 * 1e-4 * (np.abs(lg) + rms[0][fr]) + 1e-6
+    out["prob"] = float(np.max(np.abs(got["prob"][gi] - ref["prob"][ri]) / qb))
+    return out

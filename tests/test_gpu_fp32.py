@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import smlm_synth as S
-from tests.parity import compare_emitters, exempt_mask, map_rel_err
+from tests.parity import compare_emitters, exempt_mask, map_rel_err, record_field_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -241,6 +241,7 @@ def test_full_size_sampled_windows(name, scmos):
     got = gpu_maps(net, frames)
     rec, counts = gpu_localize(net, frames)
     wins = [(0, 0, 0), (0, 2048 - 40, 2048 - 48), (1, 1000, 517), (1, 0, 1500), (0, 1731, 0)]
+    n_fields = 0
     for f, y0, x0 in wins:
         hh, ww = 40, 48
         ref = oracle.net_maps_window(frames[f], spec, wts, y0, x0, hh, ww, **camera)
@@ -253,6 +254,23 @@ def test_full_size_sampled_windows(name, scmos):
         gdet = np.zeros_like(ref_det)
         gdet[rec["row"][sel] - y0 - 1, rec["col"][sel] - x0 - 1] = True
         assert not np.any((gdet != ref_det) & ~ex)
+        # every field of the records both hold (net B's z and photon rows
+        # are non-zero), within the bound the map tolerance implies
+        full_det = np.zeros((hh, ww), bool)
+        full_det[1:-1, 1:-1] = ref_det
+        loc = oracle.records(ref, full_det, spec, f)          # window coordinates
+        win = np.zeros((f + 1,) + ref.shape, np.float64)
+        win[f] = ref
+        shifted = rec[sel].copy()
+        shifted["row"] -= y0
+        shifted["col"] -= x0
+        shifted["x_px"] -= x0
+        shifted["y_px"] -= y0
+        err = record_field_errors(shifted, loc, win, spec)
+        if err["n"]:
+            assert max(err[k] for k in ("x", "y", "z", "photons", "prob")) <= 1.0, (f, y0, x0, err)
+        n_fields += err["n"]
+    assert n_fields >= 5
     # whole-frame properties at full size: ordering, counts, records inside the frame
     assert counts[2] == len(rec)
     keys = np.stack([rec["frame"], rec["row"], rec["col"]], 1)
