@@ -193,6 +193,27 @@ int dl_localize_device_unc(dl_net *net, const uint16_t *d_frames, int n, int h, 
                            void *stream, dl_emitter *d_out, dl_uncertainty *d_unc, size_t cap,
                            uint32_t *d_counts);
 
+/* Allocation-free form of dl_localize_device, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and stream semantics as
+ * dl_localize_device, and the same kernels; the activations, maps, masks and
+ * row offsets live in one fixed device array of DL_NOALLOC_SCRATCH_BYTES per
+ * device (set up by dl_create_net; held until the process ends) instead of
+ * the handle's workspace, and the frame descriptors in a ring the handle
+ * allocated at creation, so the call performs no allocation.  Limits
+ * (DL_ERR_UNSUPPORTED, before anything is queued): n <= DL_NOALLOC_MAX_FRAMES
+ * (more if an earlier call on the handle grew its ring), a batch whose
+ * workspace exceeds the array (net A in FP32: about 150k pixels, e.g. 4 x
+ * 128 x 128 frames fit; net B in FP32: about 100k pixels), and gated runs.
+ * Nothing in the array needs to start at zero: every kernel writes what the
+ * next one reads.  Every call on a device shares that device's array, from any
+ * handle: calls whose work overlaps on one device (other streams, other host
+ * threads) race and give wrong results; order them on one stream. */
+#define DL_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define DL_NOALLOC_MAX_FRAMES 64
+int dl_localize_device_noalloc(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
+                               void *stream, dl_emitter *d_out, size_t cap, uint32_t *d_counts);
+
 /* Per-pixel maps of the network, device-resident: d_maps float [n][nh][h][w]
  * with nh the head's outputs (5: logit, dx, dy, dz, photons before scaling;
  * 10: then the raw uncertainty and background planes).  For parity checks. */

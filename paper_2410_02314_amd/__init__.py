@@ -29,6 +29,8 @@ STATUS_NAMES = {0: "DL_OK", -1: "DL_ERR_INVALID_ARG", -2: "DL_ERR_BAD_WEIGHTS", 
                 -4: "DL_ERR_OOM", -5: "DL_ERR_DEVICE", -6: "DL_ERR_CAPACITY"}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 DL_FLAG_GATE = 1
+NOALLOC_SCRATCH_BYTES = 64 << 20      # DL_NOALLOC_SCRATCH_BYTES
+NOALLOC_MAX_FRAMES = 64               # DL_NOALLOC_MAX_FRAMES
 STAGES = ("stem", "conv", "conv_head", "detect", "scan", "emit", "gate")
 NSTAGES = 8
 
@@ -86,6 +88,7 @@ def _load():
         "dl_set_config": (I, [P, ctypes.POINTER(DLConfig)]),
         "dl_localize_device": (I, [P, P, I, I, I, P, P, Z, P]),
         "dl_localize_device_unc": (I, [P, P, I, I, I, P, P, P, Z, P]),
+        "dl_localize_device_noalloc": (I, [P, P, I, I, I, P, P, Z, P]),
         "dl_localize_rois_device_unc": (I, [P, ctypes.POINTER(DLRoi), I, P, P, P, Z, P]),
         "dl_maps_device": (I, [P, P, I, I, I, P, P]),
         "dl_localize": (I, [P, P, I, I, I, P, Z, ctypes.POINTER(Z)]),
@@ -261,6 +264,16 @@ class Net:
         cap = out.numel() * out.element_size() // 32
         return self._rc(_lib.dl_localize_device(self.handle, _ptr(frames), n, h, w, _stream(stream),
                                                 _ptr(out), cap, _ptr(counts)))
+
+    def localize_device_noalloc(self, frames, out, counts, stream=None) -> int:
+        """localize_device without any allocation: the work runs in the
+        device's fixed scratch array (at most NOALLOC_MAX_FRAMES frames and
+        NOALLOC_SCRATCH_BYTES of workspace; calls that overlap on one device
+        race)."""
+        n, h, w = _frames_arg(frames).shape
+        cap = out.numel() * out.element_size() // 32
+        return self._rc(_lib.dl_localize_device_noalloc(self.handle, _ptr(frames), n, h, w, _stream(stream),
+                                                        _ptr(out), cap, _ptr(counts)))
 
     def localize_device_unc(self, frames, out, unc, counts, stream=None) -> int:
         """localize_device for a 10-output network, also filling unc (cuda

@@ -13,15 +13,28 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace dloc;
 
+// Workspace of dl_localize_device_noalloc: a fixed array in device memory,
+// one copy per device the library runs on, held until the process ends.  In
+// host code `scratch` names a host-side stand-in, not the device address:
+// host code only ever uses the address hipGetSymbolAddress returns for it on
+// each device (scratch_ptr below).
+static __device__ __align__(256) char scratch[DL_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int DESC_SLOTS = 8;
 constexpr size_t ALIGN = 256;
+constexpr int MAX_DEVICES = 64;
+
+// device address of `scratch` on each device, looked up once per device
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -55,6 +68,7 @@ struct dl_net {
 
     char *ws = nullptr;
     size_t ws_bytes = 0;
+    char *scratch = nullptr;        // this device's `scratch` (dl_localize_device_noalloc)
     // Ordering of runs that share the workspace: ws_ev is recorded on the
     // stream of the last run that used it (ws_stream); a run on another
     // stream first waits for it on the device.
@@ -307,23 +321,32 @@ int ensure_workspace(dl_net *net, size_t bytes, hipStream_t s)
     return DL_OK;
 }
 
+// Grow the descriptor ring (pinned host + device, DESC_SLOTS slots) to hold
+// batches of n frames; waits for the slots' last uploads first.
+int grow_desc(dl_net *net, int n)
+{
+    if (n <= net->desc_cap) return DL_OK;
+    for (int i = 0; i < DESC_SLOTS; ++i)
+        if (net->desc_ev[i]) HIPCHK(net, hipEventSynchronize(net->desc_ev[i]));
+    if (net->h_desc) HIPCHK(net, hipHostFree(net->h_desc));
+    if (net->d_desc) HIPCHK(net, hipFree(net->d_desc));
+    net->h_desc = nullptr;
+    net->d_desc = nullptr;
+    net->desc_cap = 0;
+    int cap = DL_NOALLOC_MAX_FRAMES;
+    while (cap < n) cap *= 2;
+    HIPCHK(net, hipHostMalloc((void **)&net->h_desc, sizeof(FrameDesc) * cap * DESC_SLOTS, hipHostMallocDefault));
+    HIPCHK(net, hipMalloc((void **)&net->d_desc, sizeof(FrameDesc) * cap * DESC_SLOTS));
+    net->desc_cap = cap;
+    return DL_OK;
+}
+
 // Upload descriptors into the next ring slot; returns the device pointer.
 int upload_desc(dl_net *net, const std::vector<FrameDesc> &fd, hipStream_t s, FrameDesc **out)
 {
     const int n = (int)fd.size();
-    if (n > net->desc_cap) {
-        for (int i = 0; i < DESC_SLOTS; ++i)
-            if (net->desc_ev[i]) HIPCHK(net, hipEventSynchronize(net->desc_ev[i]));
-        if (net->h_desc) HIPCHK(net, hipHostFree(net->h_desc));
-        if (net->d_desc) HIPCHK(net, hipFree(net->d_desc));
-        net->h_desc = nullptr;
-        net->d_desc = nullptr;
-        int cap = 64;
-        while (cap < n) cap *= 2;
-        HIPCHK(net, hipHostMalloc((void **)&net->h_desc, sizeof(FrameDesc) * cap * DESC_SLOTS, hipHostMallocDefault));
-        HIPCHK(net, hipMalloc((void **)&net->d_desc, sizeof(FrameDesc) * cap * DESC_SLOTS));
-        net->desc_cap = cap;
-    }
+    int rc;
+    if ((rc = grow_desc(net, n))) return rc;
     const int slot = net->desc_next;
     net->desc_next = (slot + 1) % DESC_SLOTS;
     HIPCHK(net, hipEventSynchronize(net->desc_ev[slot]));
@@ -560,10 +583,13 @@ int check_camera(dl_net *net, bool uniform, int h, int w)
     return DL_OK;
 }
 
+// fixed_ws (fixed_cap bytes): run in this memory instead of the handle's
+// workspace, which is then neither grown nor touched (the allocation-free
+// entry point; ungated runs only)
 int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g, hipStream_t s,
                   dl_emitter *d_out, size_t cap, uint32_t *d_counts, float *ext_maps,
                   const uint16_t *d_frames = nullptr, int n = 0, int h = 0, int w = 0,
-                  dl_uncertainty *d_unc = nullptr)
+                  dl_uncertainty *d_unc = nullptr, char *fixed_ws = nullptr, size_t fixed_cap = 0)
 {
     int rc;
     if ((rc = check_camera(net, d_frames != nullptr, h, w))) return rc;
@@ -575,9 +601,17 @@ int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry 
             return fail(net, DL_ERR_UNSUPPORTED, "the tile gate needs h and w multiples of %d (got %d x %d)", GATE_TILE, h, w);
     }
     Plan p = make_plan(net, g, ext_maps != nullptr);
-    if ((rc = ensure_workspace(net, p.total, s))) return rc;
-    if ((rc = ws_acquire(net, s))) return rc;
-    p.ws = net->ws;
+    if (fixed_ws) {
+        if (p.gated) return fail(net, DL_ERR_UNSUPPORTED, "gated runs need the handle's workspace");
+        if (p.total > fixed_cap)
+            return fail(net, DL_ERR_UNSUPPORTED, "the batch needs %zu bytes of workspace; the allocation-free entry "
+                        "point has %zu", p.total, fixed_cap);
+        p.ws = fixed_ws;
+    } else {
+        if ((rc = ensure_workspace(net, p.total, s))) return rc;
+        if ((rc = ws_acquire(net, s))) return rc;
+        p.ws = net->ws;
+    }
     FrameDesc *d_fd = nullptr;
     const int slot = upload_desc(net, fd, s, &d_fd);
     if (slot < 0) return slot;
@@ -588,7 +622,26 @@ int localize_geom(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry 
     if (d_out || d_counts)
         if ((rc = run_post(net, d_fd, g, p, maps, d_out, cap, d_counts, s, d_unc))) return rc;
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
-    return ws_release(net, s);
+    return fixed_ws ? DL_OK : ws_release(net, s);
+}
+
+// This device's `scratch`: its address is looked up once per device (with
+// that device current) and kept; every handle on the device shares it.
+int scratch_init(dl_net *net)
+{
+    if (net->dev >= MAX_DEVICES) return fail(net, DL_ERR_UNSUPPORTED, "device ordinal %d >= %d", net->dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[net->dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(net, DL_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[net->dev] = static_cast<char *>(p);
+    }
+    net->scratch = g_scratch_ptr[net->dev];
+    return DL_OK;
 }
 
 }  // namespace
@@ -814,6 +867,10 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
             return bail(fail(net, DL_ERR_DEVICE, "hipEventCreate failed"));
     if (hipEventCreateWithFlags(&net->ws_ev, hipEventDisableTiming) != hipSuccess)
         return bail(fail(net, DL_ERR_DEVICE, "hipEventCreate failed"));
+    // the allocation-free entry point's memory: the device's scratch array
+    // and a descriptor ring for DL_NOALLOC_MAX_FRAMES frames
+    if ((rc = scratch_init(net))) return bail(rc);
+    if ((rc = grow_desc(net, DL_NOALLOC_MAX_FRAMES))) return bail(rc);
     if (hipStreamCreateWithFlags(&net->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&net->compute_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(net, DL_ERR_DEVICE, "hipStreamCreate failed"));
@@ -980,6 +1037,31 @@ int dl_localize_device_unc(dl_net *net, const uint16_t *d_frames, int n, int h, 
     uniform_geometry(net, d_frames, n, h, w, fd, g);
     return localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr, d_frames, n, h, w,
                          cap ? d_unc : nullptr);
+}
+
+int dl_localize_device_noalloc(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream,
+                               dl_emitter *d_out, size_t cap, uint32_t *d_counts)
+{
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
+    if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_counts) % 4)
+        return fail(net, DL_ERR_INVALID_ARG, "d_out must be 16-byte and d_counts 4-byte aligned");
+    if (n > net->desc_cap)
+        return fail(net, DL_ERR_UNSUPPORTED, "at most %d frames per allocation-free call (got %d)", net->desc_cap, n);
+    if (gated_run(net)) return fail(net, DL_ERR_UNSUPPORTED, "gated runs need the handle's workspace");
+    if (net->packed_precision != net->cfg.precision || !net->scratch)
+        return fail(net, DL_ERR_DEVICE, "the handle's weights or scratch memory are not set up");
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, d_frames, n, h, w, fd, g);
+    const bool prof = net->profiling;
+    net->profiling = false;            // timing events may need creating
+    rc = localize_geom(net, fd, g, static_cast<hipStream_t>(stream), d_out, cap, d_counts, nullptr, d_frames, n, h, w,
+                       nullptr, net->scratch, DL_NOALLOC_SCRATCH_BYTES);
+    net->profiling = prof;
+    return rc;
 }
 
 int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, float *d_maps)

@@ -122,6 +122,7 @@ def test_calls_on_null_handle_fail_cleanly():
     L = dl.lib()
     assert L.dl_localize_device(None, 16, 1, 8, 8, None, 16, 4, 16) == dl.DL_ERR_INVALID_ARG
     assert L.dl_maps_device(None, 16, 1, 8, 8, None, 16) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_localize_device_noalloc(None, 16, 1, 8, 8, None, 16, 4, 16) == dl.DL_ERR_INVALID_ARG
     assert L.dl_set_config(None, None) == dl.DL_ERR_INVALID_ARG
     assert L.dl_profile_enable(None, 1) == dl.DL_ERR_INVALID_ARG
     assert L.dl_host_alloc(0, ctypes.byref(ctypes.c_void_p())) == dl.DL_ERR_INVALID_ARG
