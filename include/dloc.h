@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define DL_ABI_VERSION 2u
+#define DL_ABI_VERSION 3u
 
 typedef enum {
     DL_OK = 0,
@@ -86,7 +86,12 @@ typedef struct {
     int32_t tile_rows;          /* conv tile rows 4 or 8; 0 = the form's default   */
     float max_sigma_px;         /* 10-output nets: drop a detection whose sigma_x  */
                                 /* or sigma_y exceeds this (px); 0 = keep all      */
-    int32_t reserved[6];
+    float in_scale_override;    /* > 0: network input units per photon in place of */
+                                /* the weights' in_scale; 0 = the weights' value   */
+    int32_t tile_w;             /* conv tile lattice columns; 0 = the form's own   */
+                                /* (32 FP32, 64 BF16/FP8); other widths are        */
+                                /* DL_ERR_UNSUPPORTED                              */
+    int32_t reserved[4];        /* must be 0                                       */
 } dl_config;
 
 /* One detected emitter, 32 bytes.  x_px = col + 0.5 + dx, y_px = row + 0.5 + dy
@@ -214,9 +219,13 @@ int dl_localize_device_unc(dl_net *net, const uint16_t *d_frames, int n, int h, 
 int dl_localize_device_noalloc(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
                                void *stream, dl_emitter *d_out, size_t cap, uint32_t *d_counts);
 
-/* Per-pixel maps of the network, device-resident: d_maps float [n][nh][h][w]
+/* Per-pixel maps of the network, device-resident (Sec. 3.2: the DECODE-style
+ * output, per pixel a detection logit, the emitter's offset relative to the
+ * pixel and, with 10 outputs, the uncertainties): d_maps float [n][nh][h][w]
  * with nh the head's outputs (5: logit, dx, dy, dz, photons before scaling;
- * 10: then the raw uncertainty and background planes).  For parity checks. */
+ * 10: then the raw uncertainty and background planes), 4-byte aligned,
+ * caller-owned.  Queued on `stream`; errors as dl_localize_device.  For parity
+ * checks. */
 int dl_maps_device(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
                    void *stream, float *d_maps);
 
@@ -267,8 +276,29 @@ int dl_localize_unc(dl_net *net, const uint16_t *frames, int n, int h, int w,
 int dl_localize_pipelined_unc(dl_net *net, const uint16_t *frames, int nbatch, int n, int h, int w,
                               int overlap, dl_emitter *out, dl_uncertainty *unc, size_t cap, size_t *count);
 
-/* Uneven batch of ROIs (device data; the dl_roi array itself is host memory).
- * Same outputs as dl_localize_device with n = nroi. */
+/* dl_localize_rois_device for ROIs in host memory (Sec. 2.2: frames read from
+ * fixed memory locations; only the post-processed coordinates come back):
+ * each ROI's rows (h rows of w pixels, row_stride apart, host memory read
+ * before the call returns) are copied into one device slot of the handle,
+ * localized in one launch per layer on the handle's compute stream, and the
+ * records copied into out[cap] (host).  *count = total emitters; the first
+ * cap are written and DL_ERR_CAPACITY returned when the total exceeds cap.
+ * Synchronous.  Errors otherwise as dl_localize_rois_device. */
+int dl_localize_rois(dl_net *net, const dl_roi *rois, int nroi, dl_emitter *out, size_t cap, size_t *count);
+
+/* The network's maps of host frames, into host memory: frames host uint16
+ * [n][h][w] -> maps host float [n][nh][h][w] (as dl_maps_device).  The handle
+ * keeps a device maps buffer, grown to the largest call.  Synchronous; errors
+ * as dl_localize.  For parity checks. */
+int dl_localize_maps(dl_net *net, const uint16_t *frames, int n, int h, int w, float *maps);
+
+/* Uneven batch of ROIs (Sec. 4.2.1 and 4.2.2 run frames in batches; here the
+ * frames of one batch may differ in shape): device data, the dl_roi array
+ * itself host memory (read before the call returns).  All ROIs go through one
+ * launch per layer.  Same outputs as dl_localize_device with n = nroi and
+ * `frame` = the ROI's index; DL_ERR_INVALID_ARG for a NULL or misaligned ROI,
+ * h or w < 1 or row_stride < w, DL_ERR_UNSUPPORTED for an ROI past the frame
+ * limits of dl_localize_device or with camera maps set. */
 int dl_localize_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream,
                             dl_emitter *d_out, size_t cap, uint32_t *d_counts);
 
@@ -284,7 +314,8 @@ int dl_localize_rois_device_unc(dl_net *net, const dl_roi *rois, int nroi, void 
 int dl_maps_rois_device(dl_net *net, const dl_roi *rois, int nroi, void *stream, float *d_maps);
 
 /* ---- autotuning ----
- * Time the network (no post-processing) on the given batch for every
+ * (Not from the paper, which fixes no tiling: the conv tile shape is this
+ * library's choice.)  Time the network (no post-processing) on the given batch for every
  * candidate convolution tile shape (lattice rows per workgroup: 8, then 4),
  * `reps` times each after one warm-up, with HIP events on `stream`; keep the
  * fastest on the handle (as cfg.tile_rows) and return it in *best_rows.
@@ -393,17 +424,33 @@ int dl_profile_read(dl_net *net, double *ms /*[DL_NSTAGES]*/, int64_t *launches 
 
 /* ---- debug / parity entry points (device pointers, queued on stream) ---- */
 
-/* One 3x3 convolution layer of the handle's precision on an NHWC FP32 tensor:
- * d_in float [n][h][w][C] -> d_out float [n][h][w][C],
- * out = ReLU(conv_d(in; block `blk` conv `which` (0 or 1)) + (d_res ? res : 0)). */
+/* One 3x3 dilated convolution layer (Sec. 3.2.1) of an FP32 handle on NHWC
+ * FP32 tensors: d_in float [n][h][w][C] -> d_out float [n][h][w][C] (16-byte
+ * aligned, caller-owned; d_res optional, same layout),
+ * out = ReLU(conv_d(in; block `blk` conv `which` (0 or 1)) + (d_res ? res : 0)),
+ * zero padding at the frame border.  DL_ERR_UNSUPPORTED unless the handle's
+ * precision is DL_FP32; DL_ERR_INVALID_ARG for a bad blk / which. */
 int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int n, int h, int w,
                         int blk, int which, void *stream, float *d_out);
 
-/* Threshold + 3x3 local-maximum test on a logit plane stack: d_logit float
- * [n][h][w] -> d_det uint8 [n][h][w] (1 = detected).  tau is the logit
- * threshold (ln(p / (1 - p))). */
+/* Threshold + 3x3 local-maximum test (the post-processing Sec. 2.2 keeps on
+ * the GPU) on a logit plane stack: d_logit float [n][h][w] (4-byte aligned)
+ * -> d_det uint8 [n][h][w] (1 = detected; caller-owned).  tau is the logit
+ * threshold (ln(p / (1 - p))), finite; ties between neighbours go to the
+ * earlier pixel in raster order. */
 int dl_debug_detect(dl_net *net, const float *d_logit, int n, int h, int w, float tau,
                     void *stream, uint8_t *d_det);
+
+/* Compaction alone (Sec. 2.2 post-processing; Sec. 4.2.1: converting the
+ * offsets to coordinates is part of the cost): detection flags d_det uint8
+ * [n][h][w] (non-zero = detected) and maps d_maps float [n][nh][h][w] (nh =
+ * the handle's head outputs) -> records d_out (16-byte aligned, cap entries)
+ * in (frame, row, col) order and d_counts uint32 [n + 1] (per frame, then the
+ * total), exactly as the last stages of dl_localize_device produce them
+ * (uncertainties are not written).  Records past cap are dropped; the counts
+ * still hold the totals. */
+int dl_debug_compact(dl_net *net, const uint8_t *d_det, const float *d_maps, int n, int h, int w,
+                     void *stream, dl_emitter *d_out, size_t cap, uint32_t *d_counts);
 
 /* ---- measured ceilings ----
  * Sustained rates of the current device, quoted beside the published peaks

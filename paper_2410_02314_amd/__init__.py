@@ -46,7 +46,8 @@ class DLConfig(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("threshold", ctypes.c_float), ("gain", ctypes.c_float),
                 ("offset", ctypes.c_float), ("device", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("max_workspace_bytes", ctypes.c_uint64), ("tile_rows", ctypes.c_int32),
-                ("max_sigma_px", ctypes.c_float), ("reserved", ctypes.c_int32 * 6)]
+                ("max_sigma_px", ctypes.c_float), ("in_scale_override", ctypes.c_float),
+                ("tile_w", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class DLRoi(ctypes.Structure):
@@ -96,6 +97,9 @@ def _load():
         "dl_localize_pipelined_unc": (I, [P, P, I, I, I, I, I, P, P, Z, ctypes.POINTER(Z)]),
         "dl_localize_unc": (I, [P, P, I, I, I, P, P, Z, ctypes.POINTER(Z)]),
         "dl_localize_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P, Z, P]),
+        "dl_localize_rois": (I, [P, ctypes.POINTER(DLRoi), I, P, Z, ctypes.POINTER(Z)]),
+        "dl_localize_maps": (I, [P, P, I, I, I, P]),
+        "dl_debug_compact": (I, [P, P, P, I, I, I, P, P, Z, P]),
         "dl_maps_rois_device": (I, [P, ctypes.POINTER(DLRoi), I, P, P]),
         "dl_host_alloc": (I, [Z, ctypes.POINTER(P)]),
         "dl_measure_rate": (I, [I, Z, I, ctypes.POINTER(ctypes.c_double)]),
@@ -150,7 +154,7 @@ def _check(rc: int, handle=None):
 
 def make_config(precision: str = "fp32", threshold: float = 0.3, gain: float = 0.5, offset: float = 100.0,
                 device: int = 0, flags: int = 0, max_workspace_bytes: int = 0, tile_rows: int = 0,
-                max_sigma_px: float = 0.0) -> DLConfig:
+                max_sigma_px: float = 0.0, in_scale_override: float = 0.0, tile_w: int = 0) -> DLConfig:
     c = DLConfig()
     _lib.dl_default_config(ctypes.byref(c))
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -162,6 +166,8 @@ def make_config(precision: str = "fp32", threshold: float = 0.3, gain: float = 0
     c.max_workspace_bytes = max_workspace_bytes
     c.tile_rows = tile_rows
     c.max_sigma_px = max_sigma_px
+    c.in_scale_override = in_scale_override
+    c.tile_w = tile_w
     return c
 
 
@@ -329,6 +335,16 @@ class Net:
         return self._rc(_lib.dl_debug_conv_layer(self.handle, _ptr(x), _ptr(res), n, h, w, blk, which,
                                                  _stream(stream), _ptr(out)))
 
+    def debug_compact(self, det, maps, out, counts, stream=None) -> int:
+        """Compaction alone: det cuda uint8 [n, h, w], maps cuda float
+        [n, nh, h, w] -> records in out (cap * 32 bytes), counts int32 [n + 1]."""
+        n, h, w = det.shape
+        if tuple(maps.shape) != (n, self.head_outputs, h, w) or not maps.is_contiguous() or not det.is_contiguous():
+            raise ValueError("det must be [n, h, w] and maps [n, nh, h, w], both contiguous")
+        cap = out.numel() * out.element_size() // 32
+        return self._rc(_lib.dl_debug_compact(self.handle, _ptr(det), _ptr(maps), n, h, w, _stream(stream),
+                                              _ptr(out), cap, _ptr(counts)))
+
     def debug_detect(self, logit, tau: float, det, stream=None) -> int:
         n, h, w = logit.shape
         return self._rc(_lib.dl_debug_detect(self.handle, _ptr(logit), n, h, w, float(tau), _stream(stream),
@@ -371,6 +387,36 @@ class Net:
             return self.localize_pipelined_unc(frames, overlap, cap=int(cnt.value))
         _check(rc, self.handle)
         return out[:cnt.value], unc[:cnt.value]
+
+    def localize_rois(self, rois: Sequence[np.ndarray], cap: Optional[int] = None) -> np.ndarray:
+        """Host ROIs (2-D uint16 arrays, rows may be strided views) -> records
+        with `frame` = the ROI's index (dl_localize_rois)."""
+        arr = (DLRoi * len(rois))()
+        for k, r in enumerate(rois):
+            if not isinstance(r, np.ndarray) or r.dtype != np.uint16 or r.ndim != 2:
+                raise ValueError(f"roi {k}: a 2-D uint16 numpy array is required")
+            if r.strides[1] != 2 or r.strides[0] % 2 or r.strides[0] < 2 * r.shape[1]:
+                raise ValueError(f"roi {k}: rows must be dense (element stride 1, row stride >= w)")
+            arr[k].data = r.ctypes.data
+            arr[k].h, arr[k].w = r.shape
+            arr[k].row_stride = r.strides[0] // 2
+        if cap is None:
+            cap = max(1024, sum(r.size for r in rois) // 16)
+        out = np.empty(cap, EMITTER_DTYPE)
+        cnt = ctypes.c_size_t()
+        rc = _lib.dl_localize_rois(self.handle, arr, len(rois), out.ctypes.data, cap, ctypes.byref(cnt))
+        if rc == DL_ERR_CAPACITY:
+            return self.localize_rois(rois, cap=int(cnt.value))
+        _check(rc, self.handle)
+        return out[:cnt.value]
+
+    def localize_maps(self, frames: np.ndarray) -> np.ndarray:
+        """Host frames uint16 [n, h, w] -> host maps float32 [n, nh, h, w]."""
+        F = _host_frames(frames, 3)
+        n, h, w = F.shape
+        maps = np.empty((n, self.head_outputs, h, w), np.float32)
+        self._rc(_lib.dl_localize_maps(self.handle, F.ctypes.data, n, h, w, maps.ctypes.data))
+        return maps
 
     def localize_unc(self, frames: np.ndarray, cap: Optional[int] = None):
         """Host frames [n, h, w] of a 10-output network -> (records, uncertainties)."""

@@ -107,6 +107,8 @@ struct dl_net {
     dl_uncertainty *pl_unc[2] = {};   // record uncertainties (10-output nets, on demand)
     uint32_t *pl_dcounts = nullptr;   // device [2][n + 1]
     uint32_t *pl_hcounts = nullptr;   // pinned [2][n + 1]
+    float *pl_maps = nullptr;         // device maps of dl_localize_maps (grow-only)
+    size_t pl_maps_bytes = 0;
     size_t pl_frame_bytes = 0, pl_stage_bytes = 0, pl_out_cap = 0, pl_unc_cap = 0;
     int pl_counts_n = 0;
     hipEvent_t pl_copied[2] = {}, pl_used[2] = {}, pl_counted[2] = {};
@@ -120,6 +122,12 @@ struct dl_net {
 };
 
 namespace {
+
+// the input scaling in use: the config's override when set, else the blob's
+float in_scale_of(const dl_net *net)
+{
+    return net->cfg.in_scale_override > 0.f ? net->cfg.in_scale_override : net->in_scale;
+}
 
 int fail(dl_net *net, int code, const char *fmt, ...)
 {
@@ -161,6 +169,18 @@ int check_config(dl_net *net, const dl_config *c)
     if (!(c->tile_rows == 0 || c->tile_rows == 4 || c->tile_rows == 8))
         return fail(net, DL_ERR_INVALID_ARG, "tile_rows must be 0, 4 or 8");
     if (c->flags & ~DL_FLAG_GATE) return fail(net, DL_ERR_INVALID_ARG, "unknown flag bits");
+    if (!std::isfinite(c->in_scale_override) || c->in_scale_override < 0.f)
+        return fail(net, DL_ERR_INVALID_ARG, "in_scale_override must be finite and >= 0 (0 = the weights' in_scale)");
+    if (c->tile_w < 0) return fail(net, DL_ERR_INVALID_ARG, "tile_w must be >= 0");
+    if (c->tile_w) {
+        int tr = 0, tc = 0;
+        conv_tile_shape(48, c->precision, 0, &tr, &tc);
+        if (c->tile_w != tc)
+            return fail(net, DL_ERR_UNSUPPORTED, "tile_w %d: this form's conv kernel is built for %d lattice columns",
+                        c->tile_w, tc);
+    }
+    for (int k = 0; k < 4; ++k)
+        if (c->reserved[k]) return fail(net, DL_ERR_INVALID_ARG, "reserved config fields must be 0");
     return DL_OK;
 }
 
@@ -433,7 +453,7 @@ int run_gate(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     float *pooled = reinterpret_cast<float *>(p.ws + p.pooled);
     float *glog = reinterpret_cast<float *>(p.ws + p.glog);
     uint8_t *keep = reinterpret_cast<uint8_t *>(p.ws + p.keep);
-    HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * net->in_scale, net->d_cam, pooled, s));
+    HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * in_scale_of(net), net->d_cam, pooled, s));
     HIPCHK(net, launch_gate(pooled, (int)g.gate_tiles, net->d_gate_theta, glog, nullptr, nullptr, s));
     HIPCHK(net, launch_gate_keep(glog, g.gate_tiles, net->gate_tau, keep, s));
     HIPCHK(net, launch_active_lists(d_fd, g, keep, net->d_radius + 1, net->d_dil, 2 * net->nb,
@@ -450,7 +470,7 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
     const int C = net->C;
     void *a0 = p.ws + p.act0;
     void *a1 = p.ws + p.act1;
-    const float scale = net->cfg.gain * net->in_scale;
+    const float scale = net->cfg.gain * in_scale_of(net);
     const uint8_t *keep = p.gated ? reinterpret_cast<const uint8_t *>(p.ws + p.keep) : nullptr;
     const int32_t *lists = p.gated ? reinterpret_cast<const int32_t *>(p.ws + p.lists) : nullptr;
     const uint32_t *lcount = p.gated ? reinterpret_cast<const uint32_t *>(p.ws + p.lcount) : nullptr;
@@ -541,7 +561,7 @@ int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     }
     {
         StageTimer t(net, DL_STAGE_EMIT, s);
-        HIPCHK(net, launch_emit(maps, net->nh, mask, roff, d_fd, g, net->z_scale, net->ph_scale, 1.f / net->in_scale,
+        HIPCHK(net, launch_emit(maps, net->nh, mask, roff, d_fd, g, net->z_scale, net->ph_scale, 1.f / in_scale_of(net),
                                 d_out, d_unc, cap, s));
     }
     return DL_OK;
@@ -929,6 +949,7 @@ void dl_destroy_net(dl_net *net)
             if (e) (void)hipEventDestroy(e);
     }
     if (net->pl_dcounts) (void)hipFree(net->pl_dcounts);
+    if (net->pl_maps) (void)hipFree(net->pl_maps);
     if (net->pl_hcounts) (void)hipHostFree(net->pl_hcounts);
     if (net->d_cam) (void)hipFree(net->d_cam);
     if (net->copy_stream) (void)hipStreamDestroy(net->copy_stream);
@@ -947,6 +968,9 @@ int dl_set_config(dl_net *net, const dl_config *cfg)
         return fail(net, DL_ERR_UNSUPPORTED, "max_sigma_px needs a network with the uncertainty head");
     if (!conv_supported(net->C, cfg->precision, net->nh))
         return fail(net, DL_ERR_UNSUPPORTED, "C = %d does not fit this form's conv kernel", net->C);
+    const float new_scale = cfg->in_scale_override > 0.f ? cfg->in_scale_override : net->in_scale;
+    if (net->d_cam && new_scale != in_scale_of(net))
+        return fail(net, DL_ERR_INVALID_ARG, "the input scaling cannot change while camera maps are set (clear them first)");
     const int old = net->cfg.precision;
     net->cfg = *cfg;
     if (cfg->precision != old) {
@@ -985,7 +1009,7 @@ int dl_set_camera_maps(dl_net *net, const float *gain, const float *offset, int 
     for (size_t p = 0; p < npx; ++p) {
         if (!std::isfinite(gain[p]) || !(gain[p] > 0.f) || !std::isfinite(offset[p]))
             return fail(net, DL_ERR_INVALID_ARG, "camera map pixel %zu: gain must be finite and > 0, offset finite", p);
-        host[p] = make_float2(offset[p], gain[p] * net->in_scale);   // the scalar path's FP32 product
+        host[p] = make_float2(offset[p], gain[p] * in_scale_of(net));   // the scalar path's FP32 product
     }
     HIPCHK(net, hipDeviceSynchronize());        // nothing in flight still reads the old maps
     if (!net->d_cam || h != net->cam_h || w != net->cam_w) {
@@ -1381,6 +1405,113 @@ int dl_localize_unc(dl_net *net, const uint16_t *frames, int n, int h, int w, dl
     return dl_localize_pipelined_unc(net, frames, 1, n, h, w, 0, out, unc, cap, count);
 }
 
+int dl_localize_rois(dl_net *net, const dl_roi *rois, int nroi, dl_emitter *out, size_t cap, size_t *count)
+{
+    int rc = check_rois(net, rois, nroi);
+    if (rc) return rc;
+    if (!count) return fail(net, DL_ERR_INVALID_ARG, "count is NULL");
+    if (cap > 0 && !out) return fail(net, DL_ERR_INVALID_ARG, "out is NULL with cap > 0");
+    if ((rc = check_camera(net, false, 0, 0))) return rc;
+    if ((rc = set_device(net))) return rc;
+    *count = 0;
+    size_t px = 0;
+    for (int k = 0; k < nroi; ++k) px += (size_t)rois[k].h * rois[k].w;
+    const size_t slot_cap = std::max<size_t>(1, std::min(cap, px));
+    if ((rc = ensure_pipeline(net, px * 2, false, slot_cap, nroi, false))) return rc;
+    hipStream_t cs = net->compute_stream;
+    // the ROIs, packed densely one after another into the frame slot
+    std::vector<dl_roi> dev(nroi);
+    size_t off = 0;
+    for (int k = 0; k < nroi; ++k) {
+        const dl_roi &r = rois[k];
+        uint16_t *dst = net->pl_frames[0] + off;
+        HIPCHK(net, hipMemcpy2DAsync(dst, (size_t)r.w * 2, r.data, (size_t)r.row_stride * 2, (size_t)r.w * 2, r.h,
+                                     hipMemcpyHostToDevice, cs));
+        dev[k] = dl_roi{dst, r.h, r.w, r.w};
+        off += (size_t)r.h * r.w;
+    }
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    roi_geometry(net, dev.data(), nroi, fd, g);
+    uint32_t *dc = net->pl_dcounts;
+    if ((rc = localize_geom(net, fd, g, cs, cap ? net->pl_out[0] : nullptr, cap ? slot_cap : 0, dc, nullptr))) return rc;
+    HIPCHK(net, hipMemcpyAsync(net->pl_hcounts, dc, (size_t)(nroi + 1) * 4, hipMemcpyDeviceToHost, cs));
+    HIPCHK(net, hipStreamSynchronize(cs));
+    const size_t total = net->pl_hcounts[nroi];
+    const size_t take = std::min(total, cap);
+    if (take) {
+        HIPCHK(net, hipMemcpyAsync(out, net->pl_out[0], take * sizeof(dl_emitter), hipMemcpyDeviceToHost, cs));
+        HIPCHK(net, hipStreamSynchronize(cs));
+    }
+    *count = total;
+    if (total > cap) return fail(net, DL_ERR_CAPACITY, "%zu emitters exceed capacity %zu", total, cap);
+    return DL_OK;
+}
+
+int dl_localize_maps(dl_net *net, const uint16_t *frames, int n, int h, int w, float *maps)
+{
+    int rc = check_uniform(net, frames, n, h, w);
+    if (rc) return rc;
+    if (!maps) return fail(net, DL_ERR_INVALID_ARG, "maps is NULL");
+    if ((rc = set_device(net))) return rc;
+    const size_t fbytes = (size_t)n * h * w * 2, mbytes = (size_t)n * net->nh * h * w * 4;
+    if ((rc = ensure_pipeline(net, fbytes, false, 1, n, false))) return rc;
+    hipStream_t cs = net->compute_stream;
+    if (mbytes > net->pl_maps_bytes) {
+        HIPCHK(net, hipStreamSynchronize(cs));
+        if (net->pl_maps) HIPCHK(net, hipFree(net->pl_maps));
+        net->pl_maps = nullptr;
+        net->pl_maps_bytes = 0;
+        if (hipMalloc(&net->pl_maps, mbytes) != hipSuccess) {
+            (void)hipGetLastError();
+            net->pl_maps = nullptr;
+            return fail(net, DL_ERR_OOM, "hipMalloc(%zu) for the maps failed", mbytes);
+        }
+        net->pl_maps_bytes = mbytes;
+    }
+    HIPCHK(net, hipMemcpyAsync(net->pl_frames[0], frames, fbytes, hipMemcpyHostToDevice, cs));
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, net->pl_frames[0], n, h, w, fd, g);
+    if ((rc = localize_geom(net, fd, g, cs, nullptr, 0, nullptr, net->pl_maps, net->pl_frames[0], n, h, w))) return rc;
+    HIPCHK(net, hipMemcpyAsync(maps, net->pl_maps, mbytes, hipMemcpyDeviceToHost, cs));
+    HIPCHK(net, hipStreamSynchronize(cs));
+    return DL_OK;
+}
+
+int dl_debug_compact(dl_net *net, const uint8_t *d_det, const float *d_maps, int n, int h, int w, void *stream,
+                     dl_emitter *d_out, size_t cap, uint32_t *d_counts)
+{
+    int rc = check_uniform(net, d_det, n, h, w);
+    if (rc) return rc;
+    if (!d_maps || !d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_maps or d_counts is NULL");
+    if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    if (reinterpret_cast<uintptr_t>(d_maps) % 4 || reinterpret_cast<uintptr_t>(d_out) % 16 ||
+        reinterpret_cast<uintptr_t>(d_counts) % 4)
+        return fail(net, DL_ERR_INVALID_ARG, "d_maps and d_counts must be 4-byte, d_out 16-byte aligned");
+    if ((rc = set_device(net))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<FrameDesc> fd;
+    Geometry g;
+    uniform_geometry(net, nullptr, n, h, w, fd, g);
+    Plan p = make_plan(net, g, true);
+    if ((rc = ensure_workspace(net, p.total, s))) return rc;
+    if ((rc = ws_acquire(net, s))) return rc;
+    p.ws = net->ws;
+    FrameDesc *d_fd = nullptr;
+    const int slot = upload_desc(net, fd, s, &d_fd);
+    if (slot < 0) return slot;
+    uint64_t *mask = reinterpret_cast<uint64_t *>(p.ws + p.mask);
+    uint32_t *rcnt = reinterpret_cast<uint32_t *>(p.ws + p.rc);
+    uint32_t *roff = reinterpret_cast<uint32_t *>(p.ws + p.roff);
+    HIPCHK(net, launch_mask_from_u8(d_det, d_fd, g, mask, rcnt, s));
+    HIPCHK(net, launch_scan(rcnt, d_fd, g, roff, d_counts, s));
+    HIPCHK(net, launch_emit(d_maps, net->nh, mask, roff, d_fd, g, net->z_scale, net->ph_scale, 1.f / in_scale_of(net),
+                            d_out, nullptr, cap, s));
+    HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
+    return ws_release(net, s);
+}
+
 int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int n, int h, int w, int blk,
                         int which, void *stream, float *d_out)
 {
@@ -1638,7 +1769,7 @@ int dl_gate_pool_net(dl_net *net, const uint16_t *d_frames, int n, int h, int w,
         return fail(net, DL_ERR_UNSUPPORTED, "the tile gate needs h and w multiples of %d (got %d x %d)", GATE_TILE, h, w);
     if ((rc = check_camera(net, true, h, w))) return rc;
     if ((rc = set_device(net))) return rc;
-    HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * net->in_scale, net->d_cam, d_pooled,
+    HIPCHK(net, launch_gate_pool(d_frames, n, h, w, net->cfg.offset, net->cfg.gain * in_scale_of(net), net->d_cam, d_pooled,
                                  static_cast<hipStream_t>(stream)));
     return DL_OK;
 }

@@ -244,6 +244,9 @@ hipError_t launch_emit(const float *maps, int planes, const uint64_t *mask, cons
                        float bg_scale, dl_emitter *out, dl_uncertainty *unc, uint64_t cap, hipStream_t s);
 hipError_t launch_mask_to_u8(const uint64_t *mask, const FrameDesc *fd, const Geometry &g,
                              uint8_t *det, hipStream_t s);
+// detection flags (u8 per pixel, planar per frame from px_off) -> mask words + row counts
+hipError_t launch_mask_from_u8(const uint8_t *det, const FrameDesc *fd, const Geometry &g, uint64_t *mask,
+                               uint32_t *row_counts, hipStream_t s);
 
 // tile gate (kernels_gate.hip)
 size_t gate_smem_bytes();

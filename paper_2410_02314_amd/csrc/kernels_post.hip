@@ -337,6 +337,32 @@ k_mask_to_u8(const uint64_t *__restrict__ mask, const FrameDesc *__restrict__ fd
     }
 }
 
+// detection flags (one byte per pixel, non-zero = detected) -> the mask
+// words and per-row counts the scan and emit kernels read: one workgroup per
+// global row, one 64-bit ballot per wave and 64 pixels
+__global__ void __launch_bounds__(256)
+k_mask_from_u8(const uint8_t *__restrict__ det, const FrameDesc *__restrict__ fdp, int nf,
+               uint64_t *__restrict__ mask, uint32_t *__restrict__ row_counts)
+{
+    const int64_t row = blockIdx.x;
+    const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
+    const FrameDesc fd = fdp[f];
+    const int y = (int)(row - fd.row_start);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t cnt = 0;
+    for (int xb = wave * 64; xb < fd.w; xb += 256) {
+        const int x = xb + lane;
+        const bool d = x < fd.w && det[fd.px_off + (int64_t)y * fd.w + x] != 0;
+        const uint64_t m = __ballot(d);
+        if (lane == 0) mask[fd.mask_start + (int64_t)y * fd.words + (xb >> 6)] = m;
+        cnt += (uint32_t)__popcll(m);
+    }
+    __shared__ uint32_t sc[4];
+    if (lane == 0) sc[wave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) row_counts[row] = sc[0] + sc[1] + sc[2] + sc[3];
+}
+
 // ----------------------------------------------------------- gated runs
 __global__ void __launch_bounds__(256)
 k_gate_keep(const float *__restrict__ logits, int64_t n, float tau, uint8_t *__restrict__ keep)
@@ -452,6 +478,13 @@ hipError_t launch_emit(const float *maps, int planes, const uint64_t *mask, cons
 {
     hipLaunchKernelGGL(k_emit, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, mask, row_off, fd, g.nf,
                        z_scale, ph_scale, bg_scale, out, unc, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_from_u8(const uint8_t *det, const FrameDesc *fd, const Geometry &g, uint64_t *mask,
+                               uint32_t *row_counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mask_from_u8, dim3((unsigned)g.total_rows), dim3(256), 0, s, det, fd, g.nf, mask, row_counts);
     return hipGetLastError();
 }
 

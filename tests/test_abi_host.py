@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_defaults():
-    assert dl.abi_version() == 2
+    assert dl.abi_version() == 3
     c = dl.DLConfig()
     assert dl.lib().dl_default_config(ctypes.byref(c)) == 0
     assert (c.precision, c.device, c.flags, c.tile_rows) == (0, 0, 0, 0)
@@ -103,10 +103,18 @@ def _create(b, **cfg):
 
 @pytest.mark.parametrize("cfg", [dict(precision=7), dict(threshold=0.0), dict(threshold=1.0),
                                  dict(gain=0.0), dict(gain=float("nan")), dict(offset=float("inf")),
-                                 dict(device=-1), dict(tile_rows=5), dict(flags=0x80)])
+                                 dict(device=-1), dict(tile_rows=5), dict(flags=0x80),
+                                 dict(in_scale_override=-0.01), dict(in_scale_override=float("inf")),
+                                 dict(tile_w=-1)])
 def test_create_rejects_bad_config_before_device(cfg):
     _, _, b = blob("A")
     assert _create(b, **cfg) == dl.DL_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("prec,tw", [("fp32", 64), ("bf16", 32), ("fp8", 48)])
+def test_create_refuses_tile_widths_not_built(prec, tw):
+    _, _, b = blob("A")
+    assert _create(b, precision=prec, tile_w=tw) == dl.DL_ERR_UNSUPPORTED
 
 
 def test_create_rejects_bad_blob_and_null_pointers():
@@ -123,6 +131,9 @@ def test_calls_on_null_handle_fail_cleanly():
     assert L.dl_localize_device(None, 16, 1, 8, 8, None, 16, 4, 16) == dl.DL_ERR_INVALID_ARG
     assert L.dl_maps_device(None, 16, 1, 8, 8, None, 16) == dl.DL_ERR_INVALID_ARG
     assert L.dl_localize_device_noalloc(None, 16, 1, 8, 8, None, 16, 4, 16) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_debug_compact(None, 16, 16, 1, 8, 8, None, 16, 4, 16) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_localize_maps(None, 16, 1, 8, 8, 16) == dl.DL_ERR_INVALID_ARG
+    assert L.dl_localize_rois(None, None, 1, None, 0, None) == dl.DL_ERR_INVALID_ARG
     assert L.dl_set_config(None, None) == dl.DL_ERR_INVALID_ARG
     assert L.dl_profile_enable(None, 1) == dl.DL_ERR_INVALID_ARG
     assert L.dl_host_alloc(0, ctypes.byref(ctypes.c_void_p())) == dl.DL_ERR_INVALID_ARG

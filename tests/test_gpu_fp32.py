@@ -52,7 +52,7 @@ def gpu_localize(net, frames, cap=None):
 
 
 def test_abi_version():
-    assert dl.abi_version() == 2
+    assert dl.abi_version() == 3
 
 
 def test_tiny_config_maps_and_emitters():
