@@ -64,7 +64,7 @@ def test_c_program_uses_the_abi(tmp_path):
     out = subprocess.run([str(exe), str(blob)], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0, out.stderr
     fields = dict(kv.split("=") for kv in out.stdout.split())
-    assert fields["abi"] == "2" and fields["precision"] == "0" and fields["threshold"] == "0.30"
+    assert fields["abi"] == "3" and fields["precision"] == "0" and fields["threshold"] == "0.30"
     assert (fields["C"], fields["nblocks"], fields["head"], fields["radius"]) == ("48", "5", "10", "63")
     assert int(fields["bad_rate"]) == dl.DL_ERR_INVALID_ARG
     assert int(fields["bad_info"]) == dl.DL_ERR_BAD_WEIGHTS
