@@ -64,6 +64,7 @@ def _L():
         _lib.or_fp8_group_exp.argtypes = [d]
         _lib.or_store_fp8_groups.argtypes = [P, i, l]
         _lib.or_quant_weights_fp8.argtypes = [P, i, l]
+        _lib.or_split_bf16.argtypes = [P, P, l]
         _lib.or_preprocess.argtypes = [P, l, d, d, d, P]
         _lib.or_conv3x3.argtypes = [P, i, i, i, P, P, i, i, P]
         _lib.or_net_maps.restype = i
@@ -111,6 +112,14 @@ def store_fp8_groups(a: np.ndarray) -> np.ndarray:
     C = out.shape[0]
     _L().or_store_fp8_groups(_p(out), C, out.size // C)
     return out
+
+
+def split_bf16(v: np.ndarray):
+    """(hi, lo) BF16 halves of the FP32 values v: hi = bf16(v), lo = bf16(v - hi)."""
+    hi = np.ascontiguousarray(v, np.float64).copy()
+    lo = np.empty_like(hi)
+    _L().or_split_bf16(_p(hi), _p(lo), hi.size)
+    return hi, lo
 
 
 def quant_weights_fp8(W: np.ndarray) -> np.ndarray:
@@ -168,7 +177,7 @@ def conv3x3(x: np.ndarray, W: np.ndarray, b: Optional[np.ndarray], d: int) -> np
 
 
 # ------------------------------------------------------------- the network
-QUANT = {"fp32": 0, "fp64": 0, "exact": 0, "bf16": 1, "fp8": 2}
+QUANT = {"fp32": 0, "fp64": 0, "exact": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
 
 
 def _flat(spec, weights: Dict[str, np.ndarray]) -> np.ndarray:

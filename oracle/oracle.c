@@ -36,7 +36,12 @@
  * activation tensor that a block convolution reads as e4m3 codes with one
  * power-of-two scale per 32-channel group of each pixel (the last block's
  * output goes to the head unrounded); the block-convolution weights carry one
- * scale per output channel.
+ * scale per output channel.  quant = 3 (split BF16) stores activations in
+ * FP32 and forms each product of a block convolution from BF16 halves:
+ * v = hi + lo with hi = bf16(v), lo = bf16(v - hi) for the FP32 activation and
+ * the weight alike, and w * x is taken as wh xh + wh xl + wl xh (the wl xl
+ * term is left out); bias, residual and ReLU are exact, stem and head as in
+ * the other modes.
  *
  * Pins (tests/test_oracle_*.py): delta input reproduces the kernel weights;
  * linearity; constant field; torch-CPU float64 conv2d(dilation=d); residual
@@ -98,8 +103,24 @@ double or_round_e4m3(double v)
 static double store_round(double v, int quant)
 {
     if (quant == 1) return or_round_bf16(v);
+    if (quant == 3) return (double)(float)v;   /* split BF16 stores FP32 */
     return v;   /* FP8 storage is applied per tensor (or_store_fp8_groups) */
 }
+
+/* Split of an FP32 value into its BF16 halves: hi = bf16(v), lo = bf16(v - hi)
+ * (v - hi is exact in FP32: hi is v rounded to 8 significant bits).
+ * n values in place: v -> hi, and lo into lo[]. */
+void or_split_bf16(double *v, double *lo, long n)
+{
+    for (long k = 0; k < n; ++k) {
+        double f = (double)(float)v[k];
+        double hi = or_round_bf16(f);
+        lo[k] = or_round_bf16(f - hi);
+        v[k] = hi;
+    }
+}
+
+
 
 /* Exponent k of the FP8 group scale 2^k: the smallest k with amax <= 448 2^k,
  * kept to normal float scales (k in -126..127, E8M0 byte k + 127 in 1..254);
@@ -187,6 +208,34 @@ void or_conv3x3(const double *in, int cin, int h, int w, const double *W,
     }
 }
 
+/* Block convolution of the split-BF16 form: y = b + sum (Wh xh + Wh xl + Wl xh)
+ * over the same terms as or_conv3x3, with x and W split by or_split_bf16.
+ * Written as three convolutions of the halves (every product of two BF16
+ * values is exact in double).  tmp: scratch of cout * h * w doubles. */
+static int conv3x3_split3(const double *in, int cin, int h, int w, const double *W, const double *b, int cout,
+                          int d, double *out)
+{
+    long hw = (long)h * w, nin = (long)cin * hw, nw = (long)cout * cin * 9;
+    double *xh = malloc(sizeof(double) * nin), *xl = malloc(sizeof(double) * nin);
+    double *wh = malloc(sizeof(double) * nw), *wl = malloc(sizeof(double) * nw);
+    double *tmp = malloc(sizeof(double) * (long)cout * hw);
+    if (!xh || !xl || !wh || !wl || !tmp) {
+        free(xh); free(xl); free(wh); free(wl); free(tmp);
+        return OR_ERR;
+    }
+    memcpy(xh, in, sizeof(double) * nin);
+    or_split_bf16(xh, xl, nin);
+    memcpy(wh, W, sizeof(double) * nw);
+    or_split_bf16(wh, wl, nw);
+    or_conv3x3(xh, cin, h, w, wh, b, cout, d, out);          /* b + Wh xh */
+    or_conv3x3(xl, cin, h, w, wh, NULL, cout, d, tmp);       /* Wh xl */
+    for (long k = 0; k < (long)cout * hw; ++k) out[k] += tmp[k];
+    or_conv3x3(xh, cin, h, w, wl, NULL, cout, d, tmp);       /* Wl xh */
+    for (long k = 0; k < (long)cout * hw; ++k) out[k] += tmp[k];
+    free(xh); free(xl); free(wh); free(wl); free(tmp);
+    return OR_OK;
+}
+
 /* -------------------------------------------------------------- the network */
 
 /* Parameters arrive as the FP32 blob tensors in order:
@@ -222,7 +271,7 @@ void or_quant_weights_fp8(double *W, int cout, long per_out)
 static int net_maps_from_input(const double *x, int h, int w, const float *params, int C, int nblocks,
                                const int *dil, int quant, int nh, double *maps /* [nh][h][w] */)
 {
-    if (h <= 0 || w <= 0 || C <= 0 || nblocks < 0 || quant < 0 || quant > 2) return OR_ERR;
+    if (h <= 0 || w <= 0 || C <= 0 || nblocks < 0 || quant < 0 || quant > 3) return OR_ERR;
     if (nh != 5 && nh != 10) return OR_ERR;
     long hw = (long)h * w;
     long nconv = (long)C * C * 9;
@@ -251,7 +300,11 @@ static int net_maps_from_input(const double *x, int h, int w, const float *param
         promote(p, C, bd); p += C;
         if (quant == 1) for (long k = 0; k < nconv; ++k) Wd[k] = or_round_bf16(Wd[k]);
         if (quant == 2) or_quant_weights_fp8(Wd, C, (long)C * 9);
-        or_conv3x3(a, C, h, w, Wd, bd, C, d, t);
+        if (quant == 3) {
+            if (conv3x3_split3(a, C, h, w, Wd, bd, C, d, t) != OR_OK) goto fail;
+        } else {
+            or_conv3x3(a, C, h, w, Wd, bd, C, d, t);
+        }
         for (long k = 0; k < hw * C; ++k) t[k] = store_round(t[k] > 0 ? t[k] : 0.0, quant);
         if (quant == 2) or_store_fp8_groups(t, C, hw);
         /* a = ReLU(a + conv_d(t; W2, b2)) */
@@ -259,7 +312,11 @@ static int net_maps_from_input(const double *x, int h, int w, const float *param
         promote(p, C, bd); p += C;
         if (quant == 1) for (long k = 0; k < nconv; ++k) Wd[k] = or_round_bf16(Wd[k]);
         if (quant == 2) or_quant_weights_fp8(Wd, C, (long)C * 9);
-        or_conv3x3(t, C, h, w, Wd, bd, C, d, u);
+        if (quant == 3) {
+            if (conv3x3_split3(t, C, h, w, Wd, bd, C, d, u) != OR_OK) goto fail;
+        } else {
+            or_conv3x3(t, C, h, w, Wd, bd, C, d, u);
+        }
         for (long k = 0; k < hw * C; ++k) {
             double s = a[k] + u[k];
             a[k] = store_round(s > 0 ? s : 0.0, quant);
@@ -283,6 +340,9 @@ static int net_maps_from_input(const double *x, int h, int w, const float *param
     }
     free(a); free(t); free(u); free(Wd); free(bd);
     return OR_OK;
+fail:
+    free(a); free(t); free(u); free(Wd); free(bd);
+    return OR_ERR;
 }
 
 int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset,

@@ -93,7 +93,7 @@ def integer_frames(n: int, h: int, wd: int, seed: int, top: int = 24) -> np.ndar
     return (100 + r.integers(0, top, size=(n, h, wd))).astype(np.uint16)
 
 
-def max_intermediate(frame: np.ndarray, spec, w) -> float:
+def max_intermediate(frame: np.ndarray, spec, w, include_head: bool = True) -> float:
     """Largest magnitude of any pre-activation sum of the exact (unquantised)
     network on one frame: stem, each block's two convolutions (the second
     with its residual), head.  Rounding to BF16 or e4m3 changes a stored value
@@ -111,6 +111,8 @@ def max_intermediate(frame: np.ndarray, spec, w) -> float:
         u = a + oracle.conv3x3(t, w[f"blk{k}.w2"].astype(np.float64), w[f"blk{k}.b2"].astype(np.float64), d)
         m = max(m, np.abs(u).max())
         a = np.maximum(u, 0)
+    if not include_head:
+        return float(m)
     hw = w["head.w"].astype(np.float64)
     maps = np.tensordot(hw, a, axes=(1, 0)) + w["head.b"].astype(np.float64)[:, None, None]
     return float(max(m, np.abs(maps).max()))

@@ -23,6 +23,7 @@ import pytest
 
 import oracle
 import smlm_synth as S
+from tests import test_oracle_bf16x3 as B3
 from tests import test_oracle_camera as CAM
 from tests import test_oracle_fp8 as FP8
 from tests import test_oracle_pins as PINS
@@ -85,6 +86,18 @@ MUTANTS = [
      "if (quant == 2 && blk + 1 < nblocks) or_store_fp8_groups(a, C, hw);",
      "if (quant == 2) or_store_fp8_groups(a, C, hw);",
      [(FP8.test_fp8_emulation_matches_torch_composition, (48, (1, 2, 4)))]),
+    ("split BF16: the wl xh term dropped",
+     "    or_conv3x3(xh, cin, h, w, wl, NULL, cout, d, tmp);       /* Wl xh */\n    for (long k = 0; k < (long)cout * hw; ++k) out[k] += tmp[k];",
+     "    or_conv3x3(xh, cin, h, w, wl, NULL, cout, d, tmp);       /* Wl xh */",
+     [(B3.test_bf16x3_emulation_matches_torch_composition, (32, (1, 2, 4)))]),
+    ("split BF16: lo taken without rounding",
+     "        lo[k] = or_round_bf16(f - hi);",
+     "        lo[k] = f - hi;",
+     [(B3.test_split_matches_torch_casts_and_error_bound, ())]),
+    ("split BF16: activations stored unrounded",
+     "    if (quant == 3) return (double)(float)v;   /* split BF16 stores FP32 */",
+     "    if (quant == 3) return v;",
+     [(B3.test_bf16x3_emulation_matches_torch_composition, (32, (1, 2, 4)))]),
     ("gate pool takes the last maximum",
      "if (h2[(long)c * hw + k] > h2[(long)c * hw + a]) a = k;",
      "if (h2[(long)c * hw + k] >= h2[(long)c * hw + a]) a = k;",
