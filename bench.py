@@ -31,7 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Mpixel/s frame->emitter list: FP32 vs BF16/FP8/gated at oracle-matched recall"
-PEAKS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}     # dense MFMA TFLOP/s, MI355X
+PEAKS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "bf16x3": 2500.0}   # dense MFMA TFLOP/s, MI355X
+# BF16 MFMA products per algorithmic product: the split-BF16 form takes three
+MFMA_PER_PRODUCT = {"fp32": 1, "bf16": 1, "fp8": 1, "bf16x3": 3}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -64,9 +66,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"],
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "bf16x3"],
                     help="the headline form (value, roofline, dtype)")
-    ap.add_argument("--forms", default="bf16,fp8",
+    ap.add_argument("--forms", default="bf16x3,bf16,fp8",
                     help="further forms measured on the same frames and reported under 'forms' ('' = none)")
     ap.add_argument("--frames", type=int, default=16)
     ap.add_argument("--size", type=int, default=2048)
@@ -246,7 +248,7 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
     flop_launch = 2.0 * 9 * C * C * total_px
     tflops = flop_launch / avg_s / 1e12
     # bytes per activation point: FP32 / BF16 values, FP8 codes + 2 group scale bytes
-    pt_bytes = {"fp32": 4 * C, "bf16": 2 * C, "fp8": C + 2}[precision]
+    pt_bytes = {"fp32": 4 * C, "bf16": 2 * C, "fp8": C + 2, "bf16x3": 4 * C}[precision]
     # algorithmic HBM bytes of the mean non-head conv launch: input + output for
     # all nine, + the residual for the four second convolutions of blocks 1-4
     nb = len(spec.dilations)
@@ -260,7 +262,7 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
     else:
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "mfma_frac": round(tflops / PEAKS[precision], 4)}
+                    "mfma_frac": round(MFMA_PER_PRODUCT[precision] * tflops / PEAKS[precision], 4)}
     roofline.update({"traffic": measured_traffic(key),
                      "kernel": f"k_conv {precision} (3x3 dilated conv, C={C}; mean of the {n_conv} non-head launches)",
                      "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_launch": flop_launch,

@@ -67,10 +67,14 @@ typedef enum {
  *            activations as e4m3 codes with one power-of-two scale per
  *            32-channel group of each pixel; FP32 accumulation, bias,
  *            residual and ReLU; the last block's output reaches the head
- *            unrounded.
+ *            unrounded;
+ *   DL_BF16X3 split BF16: FP32 weights and stored activations, each product
+ *            formed on the BF16 matrix cores from BF16 halves (v = hi + lo,
+ *            hi = bf16(v), lo = bf16(v - hi)) as wh xh + wh xl + wl xh, FP32
+ *            accumulation (about 16 significant bits per product).
  * None is part of the paper's method; they are the reduced-precision forms
  * measured against the FP32 path. */
-typedef enum { DL_FP32 = 0, DL_BF16 = 1, DL_FP8 = 2 } dl_precision;
+typedef enum { DL_FP32 = 0, DL_BF16 = 1, DL_FP8 = 2, DL_BF16X3 = 3 } dl_precision;
 
 /* flags */
 #define DL_FLAG_GATE 1u        /* skip tiles the tile gate predicts empty */
@@ -89,7 +93,7 @@ typedef struct {
     float in_scale_override;    /* > 0: network input units per photon in place of */
                                 /* the weights' in_scale; 0 = the weights' value   */
     int32_t tile_w;             /* conv tile lattice columns; 0 = the form's own   */
-                                /* (32 FP32, 64 BF16/FP8); other widths are        */
+                                /* (32 FP32/BF16X3, 64 BF16/FP8); other widths are */
                                 /* DL_ERR_UNSUPPORTED                              */
     int32_t reserved[4];        /* must be 0                                       */
 } dl_config;
@@ -424,12 +428,13 @@ int dl_profile_read(dl_net *net, double *ms /*[DL_NSTAGES]*/, int64_t *launches 
 
 /* ---- debug / parity entry points (device pointers, queued on stream) ---- */
 
-/* One 3x3 dilated convolution layer (Sec. 3.2.1) of an FP32 handle on NHWC
+/* One 3x3 dilated convolution layer (Sec. 3.2.1) of an FP32 or BF16X3 handle on NHWC
  * FP32 tensors: d_in float [n][h][w][C] -> d_out float [n][h][w][C] (16-byte
  * aligned, caller-owned; d_res optional, same layout),
  * out = ReLU(conv_d(in; block `blk` conv `which` (0 or 1)) + (d_res ? res : 0)),
  * zero padding at the frame border.  DL_ERR_UNSUPPORTED unless the handle's
- * precision is DL_FP32; DL_ERR_INVALID_ARG for a bad blk / which. */
+ * precision is DL_FP32 or DL_BF16X3 (the forms that store FP32 activations);
+ * DL_ERR_INVALID_ARG for a bad blk / which. */
 int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int n, int h, int w,
                         int blk, int which, void *stream, float *d_out);
 

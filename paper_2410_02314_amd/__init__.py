@@ -27,7 +27,7 @@ DL_ERR_DEVICE = -5
 DL_ERR_CAPACITY = -6
 STATUS_NAMES = {0: "DL_OK", -1: "DL_ERR_INVALID_ARG", -2: "DL_ERR_BAD_WEIGHTS", -3: "DL_ERR_UNSUPPORTED",
                 -4: "DL_ERR_OOM", -5: "DL_ERR_DEVICE", -6: "DL_ERR_CAPACITY"}
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
 DL_FLAG_GATE = 1
 NOALLOC_SCRATCH_BYTES = 64 << 20      # DL_NOALLOC_SCRATCH_BYTES
 NOALLOC_MAX_FRAMES = 64               # DL_NOALLOC_MAX_FRAMES

@@ -156,8 +156,9 @@ bool finite_all(const float *p, size_t n)
 
 int check_config(dl_net *net, const dl_config *c)
 {
-    if (c->precision < DL_FP32 || c->precision > DL_FP8)
-        return fail(net, DL_ERR_INVALID_ARG, "precision %d is not one of DL_FP32/DL_BF16/DL_FP8", c->precision);
+    if (c->precision < DL_FP32 || c->precision > DL_BF16X3)
+        return fail(net, DL_ERR_INVALID_ARG, "precision %d is not one of DL_FP32/DL_BF16/DL_FP8/DL_BF16X3",
+                    c->precision);
     if (!(c->threshold > 0.f && c->threshold < 1.f))
         return fail(net, DL_ERR_INVALID_ARG, "threshold must lie in (0, 1)");
     if (!std::isfinite(c->gain) || !(c->gain > 0.f))
@@ -207,7 +208,8 @@ int64_t frame_act_points(const dl_net *net, int h, int w)
 bool frame_act_fits(const dl_net *net, int h, int w)
 {
     // FP32 4, BF16 2, FP8 1 byte per value (FP8 scales: 2 bytes per point, also within range)
-    const int64_t esz = net->cfg.precision == DL_FP32 ? 4 : net->cfg.precision == DL_BF16 ? 2 : 1;
+    const int pr = net->cfg.precision;
+    const int64_t esz = pr == DL_FP32 || pr == DL_BF16X3 ? 4 : pr == DL_BF16 ? 2 : 1;
     return frame_act_points(net, h, w) * net->C * esz < ((int64_t)1 << 31);
 }
 
@@ -268,7 +270,9 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     // bytes per activation point: FP32 / BF16 values, or FP8 codes plus two
     // group scale bytes (the scales follow all codes of the buffer)
     const int prec = net->cfg.precision;
-    const size_t pt_bytes = prec == DL_FP32 ? 4 * (size_t)net->C : prec == DL_BF16 ? 2 * (size_t)net->C : net->C + 2;
+    const size_t pt_bytes = prec == DL_FP32 || prec == DL_BF16X3 ? 4 * (size_t)net->C
+                            : prec == DL_BF16                     ? 2 * (size_t)net->C
+                                                                  : net->C + 2;
     Plan p;
     size_t o = 0;
     p.act0 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
@@ -832,7 +836,8 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
         return fail(nullptr, DL_ERR_UNSUPPORTED, "max_sigma_px needs a network with the uncertainty head");
     if (!conv_supported(info.C, c.precision, info.head_outputs))
         return fail(nullptr, DL_ERR_UNSUPPORTED, "C = %d does not fit the %s conv kernel's LDS", info.C,
-                    c.precision == DL_FP32 ? "FP32" : c.precision == DL_BF16 ? "BF16" : "FP8");
+                    c.precision == DL_FP32 ? "FP32" : c.precision == DL_BF16 ? "BF16" : c.precision == DL_FP8 ? "FP8"
+                                                                                                           : "BF16X3");
     const uint32_t C = (uint32_t)info.C, nb = (uint32_t)info.nblocks;
 
     // ---- arguments are valid; device work starts here ----
@@ -1519,7 +1524,8 @@ int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int 
     if (rc) return rc;
     if (!d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL");
     if (blk < 0 || blk >= net->nb || which < 0 || which > 1) return fail(net, DL_ERR_INVALID_ARG, "bad blk/which");
-    if (net->cfg.precision != DL_FP32) return fail(net, DL_ERR_UNSUPPORTED, "debug conv layer takes FP32 tensors; set precision FP32");
+    if (net->cfg.precision != DL_FP32 && net->cfg.precision != DL_BF16X3)
+        return fail(net, DL_ERR_UNSUPPORTED, "debug conv layer takes FP32 tensors; set precision FP32 or BF16X3");
     if (reinterpret_cast<uintptr_t>(d_in) % 16 || reinterpret_cast<uintptr_t>(d_out) % 16 ||
         reinterpret_cast<uintptr_t>(d_res) % 16)
         return fail(net, DL_ERR_INVALID_ARG, "tensors must be 16-byte aligned");

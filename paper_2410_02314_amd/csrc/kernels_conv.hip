@@ -41,6 +41,12 @@
 //         FP32 outputs over the four lanes holding the pixel, and stores the
 //         e4m3 codes of the FP32 values (scaled by the group's power of two)
 //         and the scale bytes.
+//   BF16X3 (split BF16) the BF16 MFMA on both halves of FP32 operands: the
+//         tile is staged from FP32 activations as BF16 pairs (hi = bf16(v),
+//         lo = bf16(v - hi); per point C hi values then C lo values), the
+//         weights are packed as a hi block and a lo block, and each K chunk
+//         takes three MFMAs, wh xh + wh xl + wl xh, into one FP32 accumulator.
+//         Storage, residual, epilogue and fused head are those of FP32.
 // K is padded with zero-weight chunks when 9 C is not a multiple of the MFMA's K.
 // BF16 and FP8 pass each wave's output row (and residual) through LDS so they
 // move in whole 16-byte lanes; every store is a buffer store whose offset is
@@ -131,6 +137,9 @@ template <> struct Store<DL_FP32> {
     }
 };
 
+// split BF16 stores FP32 activations
+template <> struct Store<DL_BF16X3> : Store<DL_FP32> {};
+
 // K plan and packed-weight bytes per precision
 template <int C, int P> struct KPlan;
 template <int C> struct KPlan<C, DL_FP32> {
@@ -145,6 +154,15 @@ template <int C> struct KPlan<C, DL_BF16> {
     static constexpr int BYTES = NIT * (C / 16) * 64 * 16;
     static constexpr int LDS_W = BYTES;
     static constexpr int LESZ = 2;
+};
+template <int C> struct KPlan<C, DL_BF16X3> {
+    // the BF16 K plan, with a hi and a lo block of weights
+    static constexpr int CH8 = C / 8, NCH = 9 * CH8;
+    static constexpr int NIT = (NCH + 3) / 4;
+    static constexpr int HALF = NIT * (C / 16) * 64 * 16;
+    static constexpr int BYTES = 2 * HALF;
+    static constexpr int LDS_W = BYTES;
+    static constexpr int LESZ = 4;                // hi and lo BF16 per channel
 };
 template <int C> struct KPlan<C, DL_FP8> {
     // K runs tap by tap, each tap's channels padded to CT (a multiple of 32):
@@ -162,6 +180,7 @@ template <int P> struct TileShape;
 template <> struct TileShape<DL_FP32> { static constexpr int TC = 32; };
 template <> struct TileShape<DL_BF16> { static constexpr int TC = 64; };
 template <> struct TileShape<DL_FP8> { static constexpr int TC = 64; };
+template <> struct TileShape<DL_BF16X3> { static constexpr int TC = 32; };
 // waves per SIMD the register budget is sized for: FP32 4-row tiles fit three
 // workgroups per CU in LDS (one wave per SIMD each); every other shape is
 // limited to one or two workgroups by LDS and gets the larger budget of two
@@ -195,7 +214,7 @@ struct Lds {
     static constexpr int OPX = P == DL_FP8 ? C : C * 2;                // staging bytes per pixel
     static constexpr int RSOFF = TC * OPX;                             // FP8: residual scales
     static constexpr int OSOFF = RSOFF + TC * 2;                       // FP8: output scales
-    static constexpr int OWAVE = P == DL_FP32 ? 0 : P == DL_FP8 ? align16(OSOFF + TC * 2) : TC * OPX;
+    static constexpr int OWAVE = P == DL_FP32 || P == DL_BF16X3 ? 0 : P == DL_FP8 ? align16(OSOFF + TC * 2) : TC * OPX;
     static constexpr int OOFF = align16(SOFF + C * 4);
     static constexpr int DOFF = align16(OOFF + TR * OWAVE);            // two decoded-tile slots
     static constexpr int TOTAL = DOFF + 2 * 64;
@@ -394,7 +413,20 @@ k_conv(ConvArgs a, Geometry geo)
             const int q = tid + k * NT;
             if (q < NQ) {
                 const int pt = q / SCH, ch = q - (q / SCH) * SCH;
-                *reinterpret_cast<v4f *>(sT + pt * PS + ch * 16) = pf[k];
+                if constexpr (P == DL_BF16X3) {
+                    // four FP32 channels -> their BF16 halves: hi at byte 8 ch of
+                    // the point, lo at 2 C + 8 ch (v - hi is exact in FP32)
+                    const v4f v = pf[k];
+                    const uint32_t h01 = bf16_pack2(v[0], v[1]), h23 = bf16_pack2(v[2], v[3]);
+                    const uint32_t l01 = bf16_pack2(v[0] - __uint_as_float(h01 << 16),
+                                                    v[1] - __uint_as_float(h01 & 0xFFFF0000u));
+                    const uint32_t l23 = bf16_pack2(v[2] - __uint_as_float(h23 << 16),
+                                                    v[3] - __uint_as_float(h23 & 0xFFFF0000u));
+                    *reinterpret_cast<uint2 *>(sT + pt * PS + ch * 8) = uint2{h01, h23};
+                    *reinterpret_cast<uint2 *>(sT + pt * PS + 2 * C + ch * 8) = uint2{l01, l23};
+                } else {
+                    *reinterpret_cast<v4f *>(sT + pt * PS + ch * 16) = pf[k];
+                }
             }
         }
         if constexpr (P == DL_FP8) {
@@ -424,8 +456,9 @@ k_conv(ConvArgs a, Geometry geo)
         // MFMA layout before the next tile's input (EARLY_RES); FP32 with
         // weights in L2 has no registers to spare and loads it in the
         // epilogue, one pixel block at a time.
-        constexpr bool STAGE = P != DL_FP32 && !HEAD;
-        constexpr bool EARLY_RES = RES && (P != DL_FP32 ? HEAD : L::LDSW_FP32);
+        constexpr bool F32IO = P == DL_FP32 || P == DL_BF16X3;      // FP32 activations in HBM
+        constexpr bool STAGE = !F32IO && !HEAD;
+        constexpr bool EARLY_RES = RES && (!F32IO ? HEAD : P == DL_BF16X3 || L::LDSW_FP32);
         constexpr int CPX = L::OPX / 16;                    // 16-byte chunks per staged pixel
         constexpr int NRC = STAGE ? TC * CPX / 64 : 1;      // chunks per lane
         static_assert(!STAGE || (TC * CPX) % 64 == 0, "staging chunks per lane");
@@ -610,6 +643,46 @@ k_conv(ConvArgs a, Geometry geo)
                     for (int p = 0; p < PB; ++p)
                         acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                             __builtin_bit_cast(v8bf, av[nb]), __builtin_bit_cast(v8bf, bv[p]), acc[nb][p], 0, 0, 0);
+            }
+        } else if constexpr (P == DL_BF16X3) {
+            // as BF16, with both halves of every operand; the operands of step
+            // m + 1 are read while the MFMAs of step m run (past the last step
+            // step 0 is read again and not used)
+            constexpr int CH8 = KPlan<C, P>::CH8, NCH = KPlan<C, P>::NCH, NIT = KPlan<C, P>::NIT;
+            constexpr int HALF = KPlan<C, P>::HALF;
+            const char *sW = sT + L::WOFF;
+            auto operands = [&](int m, v4f (&ah)[NB], v4f (&al)[NB], v4f (&bh)[PB], v4f (&bl)[PB]) {
+                const int ch = 4 * m + kq;
+                const int tap = ch < NCH ? ch / CH8 : 4;          // padding chunks have zero weights
+                const int c0 = ch < NCH ? (ch - (ch / CH8) * CH8) * 8 : 0;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int wo = ((m * NB + nb) * 64 + lane) * 16;
+                    ah[nb] = *reinterpret_cast<const v4f *>(sW + wo);
+                    al[nb] = *reinterpret_cast<const v4f *>(sW + HALF + wo);
+                }
+#pragma unroll
+                for (int p = 0; p < PB; ++p) {
+                    const char *pa = pt_addr(p, tap) + c0 * 2;
+                    bh[p] = *reinterpret_cast<const v4f *>(pa);
+                    bl[p] = *reinterpret_cast<const v4f *>(pa + 2 * C);
+                }
+            };
+#pragma unroll
+            for (int m = 0; m < NIT; ++m) {
+                v4f ah[NB], al[NB], bh[PB], bl[PB];
+                operands(m, ah, al, bh, bl);
+                if (m == NIT / 2) ahead();
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int p = 0; p < PB; ++p) {
+                        const v8bf wh = __builtin_bit_cast(v8bf, ah[nb]), wl = __builtin_bit_cast(v8bf, al[nb]);
+                        const v8bf xh = __builtin_bit_cast(v8bf, bh[p]), xl = __builtin_bit_cast(v8bf, bl[p]);
+                        acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xh, acc[nb][p], 0, 0, 0);
+                        acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xl, acc[nb][p], 0, 0, 0);
+                        acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, xh, acc[nb][p], 0, 0, 0);
+                    }
             }
         } else {
             constexpr int HPT = KPlan<C, P>::HPT, NIT = KPlan<C, P>::NIT;
@@ -947,6 +1020,7 @@ void conv_tile_shape(int C, int precision, int rows, int *tr, int *tc)
     switch (precision) {
     case DL_FP32: *tc = TileShape<DL_FP32>::TC; break;
     case DL_BF16: *tc = TileShape<DL_BF16>::TC; break;
+    case DL_BF16X3: *tc = TileShape<DL_BF16X3>::TC; break;
     default: *tc = TileShape<DL_FP8>::TC; break;
     }
 }
@@ -956,6 +1030,7 @@ bool conv_supported(int C, int precision, int nh)
     if (precision == DL_FP32) return fits_p<DL_FP32>(C, nh);
     if (precision == DL_BF16) return fits_p<DL_BF16>(C, nh);
     if (precision == DL_FP8) return fits_p<DL_FP8>(C, nh);
+    if (precision == DL_BF16X3) return fits_p<DL_BF16X3>(C, nh);
     return false;
 }
 
@@ -964,6 +1039,7 @@ size_t conv_packed_bytes(int C, int precision)
     const int NB = C / 16, NCH = 9 * (C / 8);
     if (precision == DL_FP32) return (size_t)9 * C * C * 4;
     if (precision == DL_BF16) return (size_t)((NCH + 3) / 4) * NB * 64 * 16;
+    if (precision == DL_BF16X3) return 2 * (size_t)((NCH + 3) / 4) * NB * 64 * 16;
     const int HPT = (C + 31) / 32;
     return (size_t)((9 * HPT + 3) / 4) * NB * 64 * 32;
 }
@@ -987,9 +1063,12 @@ void pack_conv_weights(int C, int precision, const float *W, void *dst, float *s
         return;
     }
     const int CH8 = C / 8, NCH = 9 * CH8;
-    if (precision == DL_BF16) {
-        // step m, block nb, lane (i, kq): 8 bf16 of chunk 4 m + kq
+    if (precision == DL_BF16 || precision == DL_BF16X3) {
+        // step m, block nb, lane (i, kq): 8 bf16 of chunk 4 m + kq; split BF16
+        // follows with a second block of the same layout holding the lo
+        // halves bf16(w - hi)
         const int NIT = (NCH + 3) / 4;
+        const size_t half = (size_t)NIT * NB * 64 * 8;
         uint16_t *o = static_cast<uint16_t *>(dst);
         for (int m = 0; m < NIT; ++m)
             for (int nb = 0; nb < NB; ++nb)
@@ -997,7 +1076,15 @@ void pack_conv_weights(int C, int precision, const float *W, void *dst, float *s
                     const int oc = nb * 16 + (lane & 15), ch = 4 * m + (lane >> 4);
                     for (int e = 0; e < 8; ++e) {
                         const float v = ch < NCH ? wt(oc, (ch % CH8) * 8 + e, ch / CH8) : 0.f;
-                        o[((size_t)(m * NB + nb) * 64 + lane) * 8 + e] = host_bf16(v);
+                        const size_t i = ((size_t)(m * NB + nb) * 64 + lane) * 8 + e;
+                        const uint16_t hb = host_bf16(v);
+                        o[i] = hb;
+                        if (precision == DL_BF16X3) {
+                            const uint32_t hu = (uint32_t)hb << 16;
+                            float hf;
+                            std::memcpy(&hf, &hu, 4);
+                            o[half + i] = host_bf16(v - hf);
+                        }
                     }
                 }
         return;
@@ -1037,6 +1124,7 @@ int conv_max_grid(int C, int precision, int tr, int ncu)
     int b = 1;
     if (precision == DL_FP32) b = bpc_p<DL_FP32>(C, tr);
     else if (precision == DL_BF16) b = bpc_p<DL_BF16>(C, tr);
+    else if (precision == DL_BF16X3) b = bpc_p<DL_BF16X3>(C, tr);
     else b = bpc_p<DL_FP8>(C, tr);
     return b * ncu;
 }
@@ -1046,6 +1134,7 @@ hipError_t launch_conv(int C, int precision, const ConvArgs &a, const Geometry &
     if (precision == DL_FP32) return launch_p<DL_FP32>(C, a, g, grid, s);
     if (precision == DL_BF16) return launch_p<DL_BF16>(C, a, g, grid, s);
     if (precision == DL_FP8) return launch_p<DL_FP8>(C, a, g, grid, s);
+    if (precision == DL_BF16X3) return launch_p<DL_BF16X3>(C, a, g, grid, s);
     return hipErrorInvalidValue;
 }
 

@@ -32,6 +32,9 @@ DIL = (1, 2, 4, 8, 16)
 def _net(kind, C):
     if kind == "fp8":
         return X.fp8_exact_net(C, DIL, seed=21 + C)
+    # split BF16 on integers: hi and lo are integers and every product of the
+    # three terms is exact, so only the split's own rounding (the dropped lo
+    # bits of values above 2^16 and the lo xl term) separates it from exact
     return X.bf16_integer_net(C, DIL, seed=15 + C)
 
 
@@ -42,7 +45,8 @@ def _make(spec, w, prec, **cfg):
 
 # every channel count each form's kernel is built for (BF16 with C = 64 does
 # not fit its tile and weights in LDS; dl_create_net refuses it)
-CASES = [("bf16", 16), ("bf16", 32), ("bf16", 48), ("fp8", 16), ("fp8", 32), ("fp8", 48), ("fp8", 64)]
+CASES = [("bf16", 16), ("bf16", 32), ("bf16", 48), ("fp8", 16), ("fp8", 32), ("fp8", 48), ("fp8", 64),
+         ("bf16x3", 16), ("bf16x3", 32), ("bf16x3", 48)]
 
 
 @pytest.mark.parametrize("kind,C", CASES)
@@ -55,7 +59,7 @@ def test_integer_net_bit_exact_vs_emulation(kind, C):
     got = gpu_maps(net, frames)
     emu = np.stack([oracle.net_maps(f, spec, w, gain=1.0, offset=100.0, quant=kind) for f in frames])
     ex = np.stack([oracle.net_maps(f, spec, w, gain=1.0, offset=100.0) for f in frames])
-    assert not np.array_equal(emu, ex)               # the stored values really round
+    assert not np.array_equal(emu, ex)               # the form's rounding really happens
     bad = np.argwhere(got != emu)
     assert bad.size == 0, (len(bad), bad[:5], got[tuple(bad[0])], emu[tuple(bad[0])])
     # detections: the same set as the oracle's on the same maps
@@ -77,7 +81,7 @@ def test_bf16_c64_is_refused():
     assert e.value.code == dl.DL_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "bf16x3"])
 def test_integer_net_tile_shapes_agree(kind):
     """4-row and 8-row conv tiles give the same bits (and both equal the
     emulation, by the test above)."""
@@ -88,7 +92,7 @@ def test_integer_net_tile_shapes_agree(kind):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "bf16x3"])
 def test_integer_net_uneven_rois_bit_exact(kind):
     """Uneven ROI lists (one launch per layer over all ROIs, some strided out
     of a larger frame) equal the emulation ROI by ROI."""
