@@ -249,6 +249,7 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         g.total_rows += d.h;
         g.total_words += (int64_t)d.h * d.words;
         if (d.w > g.maxw) g.maxw = d.w;
+        if (d.h > g.maxh) g.maxh = d.h;
     }
     for (int b = 0; b < net->nb; ++b) g.max_tiles = std::max(g.max_tiles, g.tiles[b]);
 }

@@ -66,7 +66,7 @@ struct Geometry {
     int64_t max_tiles = 0;
     int64_t max_frame_tiles = 0;   // most conv tiles of one frame in one block
     int tr = 8, tc = 64;           // conv tile shape on the sub-lattice
-    int maxw = 0;
+    int maxw = 0, maxh = 0;
     int minor_blk = -1;            // block whose tiles run phase-minor (see decode_tile)
 };
 

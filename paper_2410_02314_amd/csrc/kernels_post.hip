@@ -149,78 +149,139 @@ hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const 
 }
 
 // ------------------------------------------------------------ detection
-// One workgroup (4 waves) per global row.  Pixel (y, x) is detected iff its
-// logit exceeds tau and beats every in-frame 8-neighbour in the order (value,
-// then smaller raster index) -- a strict local maximum with a deterministic
-// tie-break, so a plateau yields exactly one detection.  Each wave turns 64
-// decisions into one 64-bit mask word (ballot); the row's count goes to
-// row_counts for the scan.  With the uncertainty planes and a finite u_max, a
-// local maximum whose raw sigma_x or sigma_y exceeds u_max is dropped (its
+// Pixel (y, x) is detected iff its logit exceeds tau and beats every in-frame
+// 8-neighbour in the order (value, then smaller raster index) -- a strict
+// local maximum with a deterministic tie-break, so a plateau yields exactly
+// one detection.  With the uncertainty planes and a finite u_max, a local
+// maximum whose raw sigma_x or sigma_y exceeds u_max is dropped (its
 // neighbours are not promoted): softplus is increasing, so this is
 // sigma <= softplus(u_max) without evaluating softplus.
+//
+// A workgroup (4 waves) takes a band of DBAND rows of one frame.  A wave
+// works on chunks of 256 columns (chunk k of the band goes to wave k mod 4),
+// as four groups of 64: lane l holds columns x0 + l + 64 e, e = 0..3, so each
+// group's decisions form one 64-bit mask word by a ballot.  The wave loads
+// the chunk's DBAND + 2 rows (the band and one row above and below) at once,
+// 4 (DBAND + 2) logits per lane in flight, plus one halo column per row (the
+// pixel left of the chunk in lane 0, right of it in lane 63).  Left and right
+// neighbours come from the adjacent lanes (lane shuffles; across a group
+// boundary from the neighbouring group's end lane), the rows above and below
+// from the registers: each logit is read from HBM once per band (the band's
+// two halo rows aside), with no LDS staging and no barrier until the per-row
+// counts are summed.  Neighbours off the frame or in a gate tile that was
+// skipped are -inf (absent).  The row's count goes to row_counts for the scan.
+constexpr int DBAND = 8, DROWS = DBAND + 2;
+
+// GATED: keep is a gate keep map; SIGMA: the uncertainty filter is on
+template <bool GATED, bool SIGMA>
 __global__ void __launch_bounds__(256)
-k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__restrict__ fdp, int nf,
-              float tau, float u_max, const uint8_t *__restrict__ keep, uint64_t *__restrict__ mask,
+k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__restrict__ fdp, int bands, float tau,
+              float u_max, const uint8_t *__restrict__ keep, uint64_t *__restrict__ mask,
               uint32_t *__restrict__ row_counts)
 {
-    const int64_t row = blockIdx.x;
-    const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
+    __shared__ uint32_t wcnt[DBAND][4];
+    // workgroup = (frame, band): bands per frame from the batch's tallest frame
+    const int f = blockIdx.x / bands, band = blockIdx.x - f * bands;
     const FrameDesc fd = fdp[f];
-    const int y = (int)(row - fd.row_start);
     const int H = fd.h, W = fd.w;
+    const int y0 = band * DBAND;
+    if (y0 >= H) return;                                  // uniform over the workgroup
+    const int y1 = min(H, y0 + DBAND);
     const float *L = maps + planes * fd.px_off;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // gated runs: pixels of skipped gate tiles are neither detected nor neighbours
-    const uint8_t *kp = keep ? keep + fd.keep_start : nullptr;
-    auto kept = [&](int yy, int xx) { return !kp || kp[(yy / GATE_TILE) * fd.gtx + xx / GATE_TILE]; };
-    const float *Lrow = L + (int64_t)y * W;
-    uint32_t cnt = 0;
-    // The row in passes of DCH 256-pixel chunks: all of a pass's logit loads
-    // are issued before any decision, so each lane has DCH loads in flight
-    // (one load per decision left the kernel latency-bound).
-    constexpr int DCH = 8;
-    for (int base = 0; base < W; base += 256 * DCH) {
-        float vv[DCH];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const uint8_t *kp = GATED ? keep + fd.keep_start : nullptr;
+    const int64_t plane = (int64_t)H * W;
+    if (lane == 0)
+        for (int r = 0; r < DBAND; ++r) wcnt[r][wave] = 0;
+    // is (yy, xx) a present pixel: in the frame and in a kept gate tile
+    // (branch-free: the keep byte is read at clamped coordinates)
+    auto present = [&](int yy, int xx) -> bool {
+        const bool in = ((unsigned)yy < (unsigned)H) & ((unsigned)xx < (unsigned)W);
+        if constexpr (!GATED) return in;
+        const int yc = min(max(yy, 0), H - 1), xc = min(max(xx, 0), W - 1);
+        return in & (kp[(yc / GATE_TILE) * fd.gtx + xc / GATE_TILE] != 0);
+    };
+    // the logit plane as a buffer resource: each load is a per-lane column
+    // offset plus the row's offset (uniform) plus the group's immediate, so the
+    // many loads in flight cost few address registers; a load past the plane
+    // reads zero, and every position off the frame is replaced by -inf below
+    const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(L), (short)0, (int)min<int64_t>(plane * 4, 0x7FFFFFFF), (int)0x00020000);
+    for (int x0 = wave * 256; x0 < W; x0 += 1024) {
+        const int hx = lane == 0 ? x0 - 1 : x0 + 256;     // halo column (lanes 0 and 63)
+        const int vo = (x0 + lane) * 4, ho = min(max(hx, 0), W - 1) * 4;
+        v4f v[DROWS];
+        float h[DROWS];
 #pragma unroll
-        for (int c = 0; c < DCH; ++c) {
-            const int x = base + c * 256 + wave * 64 + lane;
-            vv[c] = x < W ? Lrow[x] : 0.f;
+        for (int r = 0; r < DROWS; ++r) {
+            const int ro = __builtin_amdgcn_readfirstlane(min(max(y0 - 1 + r, 0), H - 1) * W * 4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[r][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rl, vo + 256 * e, ro, 0));
+            h[r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rl, ho, ro, 0));
         }
 #pragma unroll
-        for (int c = 0; c < DCH; ++c) {
-            const int xb = base + c * 256 + wave * 64;
-            if (xb >= W) break;                              // uniform across the wave
-            const int x = xb + lane;
-            const float v = vv[c];
-            bool det = x < W && v > tau && kept(y, x);
-            if (det) {
+        for (int r = 0; r < DROWS; ++r) {
+            const int yy = y0 - 1 + r;
 #pragma unroll
-                for (int di = -1; di <= 1; ++di)
+            for (int e = 0; e < 4; ++e) v[r][e] = present(yy, x0 + lane + 64 * e) ? v[r][e] : -INFINITY;
+            h[r] = present(yy, hx) ? h[r] : -INFINITY;
+        }
+        // left / right neighbours of row r's values (a sliding window of three rows)
+        // (DPP whole-wave shifts by one lane: wave_shr1 gives lane i the value
+        // of lane i - 1, wave_shl1 that of lane i + 1)
+        auto shr1 = [](float x) {
+            return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, false));
+        };
+        auto shl1 = [](float x) {
+            return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xF, 0xF, false));
+        };
+        auto lane_val = [](float x, int l) {
+            return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+        };
+        auto sides = [&](int r, v4f &lf, v4f &rt) {
 #pragma unroll
-                    for (int dj = -1; dj <= 1; ++dj) {
-                        if (di == 0 && dj == 0) continue;
-                        const int yy = y + di, xx = x + dj;
-                        if ((unsigned)yy >= (unsigned)H || (unsigned)xx >= (unsigned)W) continue;
-                        if (!kept(yy, xx)) continue;
-                        const float nv = L[(int64_t)yy * W + xx];
-                        // neighbours before (y, x) in raster order win ties
-                        const bool earlier = di < 0 || (di == 0 && dj < 0);
-                        if (nv > v || (nv == v && earlier)) det = false;
-                    }
-                if (det && planes == 10 && u_max < INFINITY) {
-                    const int64_t plane = (int64_t)H * W, idx = (int64_t)y * W + x;
+            for (int e = 0; e < 4; ++e) {
+                const float up = shr1(v[r][e]), dn = shl1(v[r][e]);
+                // across a group boundary: the neighbouring group's end lane
+                const float pl = e > 0 ? lane_val(v[r][e > 0 ? e - 1 : 0], 63) : h[r];
+                const float nx = e < 3 ? lane_val(v[r][e < 3 ? e + 1 : 3], 0) : lane_val(h[r], 63);
+                lf[e] = lane == 0 ? pl : up;
+                rt[e] = lane == 63 ? nx : dn;
+            }
+        };
+        v4f lf0, rt0, lf1, rt1, lf2, rt2;
+        sides(0, lf0, rt0);
+        sides(1, lf1, rt1);
+#pragma unroll
+        for (int r = 0; r < DBAND; ++r) {
+            const int yy = y0 + r;
+            if (yy >= y1) break;                          // uniform
+            sides(r + 2, lf2, rt2);
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float c = v[r + 1][e];
+                // neighbours earlier in raster order must be strictly smaller;
+                // later ones may tie
+                bool det = c > tau && c > lf0[e] && c > v[r][e] && c > rt0[e] && c > lf1[e] && c >= rt1[e] &&
+                           c >= lf2[e] && c >= v[r + 2][e] && c >= rt2[e];
+                if (SIGMA && det) {
+                    const int64_t idx = (int64_t)yy * W + x0 + lane + 64 * e;
                     det = L[5 * plane + idx] <= u_max && L[6 * plane + idx] <= u_max;
                 }
+                const uint64_t m = __ballot(det);
+                const int xb = x0 + 64 * e;
+                if (lane == 0 && xb < W) mask[fd.mask_start + (int64_t)yy * fd.words + (xb >> 6)] = m;
+                cnt += (uint32_t)__popcll(m);
             }
-            const uint64_t m = __ballot(det);
-            if (lane == 0) mask[fd.mask_start + (int64_t)y * fd.words + (xb >> 6)] = m;
-            cnt += (uint32_t)__popcll(m);
+            if (lane == 0) wcnt[r][wave] += cnt;
+            lf0 = lf1; rt0 = rt1; lf1 = lf2; rt1 = rt2;
         }
     }
-    __shared__ uint32_t sc[4];
-    if (lane == 0) sc[wave] = cnt;
     __syncthreads();
-    if (threadIdx.x == 0) row_counts[row] = sc[0] + sc[1] + sc[2] + sc[3];
+    for (int i = tid; i < y1 - y0; i += 256)
+        row_counts[fd.row_start + y0 + i] = wcnt[i][0] + wcnt[i][1] + wcnt[i][2] + wcnt[i][3];
 }
 
 // ----------------------------------------------------------------- scan
@@ -460,8 +521,14 @@ hipError_t launch_detect_mask(const float *maps, int planes, const FrameDesc *fd
                               float u_max, const uint8_t *keep, uint64_t *mask, uint32_t *row_counts,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_detect_mask, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, fd, g.nf, tau, u_max,
-                       keep, mask, row_counts);
+    const int bands = (g.maxh + DBAND - 1) / DBAND;
+    const int64_t blocks = (int64_t)bands * g.nf;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const bool sigma = planes == 10 && u_max < INFINITY;
+    auto kern = keep ? (sigma ? k_detect_mask<true, true> : k_detect_mask<true, false>)
+                     : (sigma ? k_detect_mask<false, true> : k_detect_mask<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, maps, planes, fd, bands, tau, u_max, keep, mask,
+                       row_counts);
     return hipGetLastError();
 }
 
