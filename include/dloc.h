@@ -347,6 +347,29 @@ int dl_graph_create(dl_net *net, const uint16_t *d_frames, int n, int h, int w, 
 int dl_graph_create_rois(dl_net *net, const dl_roi *rois, int nroi, dl_emitter *d_out, size_t cap,
                          uint32_t *d_counts, dl_graph **out);
 int dl_graph_launch(dl_graph *g, void *stream);
+
+/* A graph that localizes ANY uneven ROI batch within a capacity (Sec. 4.2.1
+ * and 4.2.2 run fixed-size batches; here one capture serves every batch that
+ * fits): at most max_rois ROIs, each at most max_h x max_w, at most max_pixels
+ * pixels in all.  The graph owns a workspace sized for the capacity, a pinned
+ * host slot for the ROI list, and device descriptor buffers; its first nodes
+ * copy the slot to the device and build the frame descriptors there (prefix
+ * sums over the ROIs), and every kernel reads the batch's frame count, rows
+ * and tiles from device memory, so nothing is re-captured.  d_out / cap /
+ * d_counts as dl_graph_create_rois, except that d_counts must hold
+ * max_rois + 1 entries: a replay over n ROIs writes counts[0..n-1] and the
+ * total at counts[n].  Gated handles and camera maps are refused
+ * (DL_ERR_UNSUPPORTED); max_rois is at most DL_GRAPH_MAX_ROIS.
+ * dl_graph_launch_rois: queue one replay on `stream` for the ROI list `rois`
+ * (device data; the array is host memory, copied into the graph's slot
+ * before the call returns).  It first waits (on the host) until the previous
+ * replay has copied the slot.  ROIs past the capacity return DL_ERR_CAPACITY
+ * before anything is queued; other errors as dl_localize_rois_device.
+ * dl_graph_launch refuses such a graph, and dl_graph_launch_rois a fixed one. */
+#define DL_GRAPH_MAX_ROIS 65536
+int dl_graph_create_rois_dynamic(dl_net *net, int max_rois, int max_h, int max_w, int64_t max_pixels,
+                                 dl_emitter *d_out, size_t cap, uint32_t *d_counts, dl_graph **out);
+int dl_graph_launch_rois(dl_graph *g, const dl_roi *rois, int nroi, void *stream);
 void dl_graph_destroy(dl_graph *g);
 
 /* Pinned host memory for frames (Sec. 2.2 "specified memory locations"). */

@@ -113,6 +113,8 @@ def _load():
         "dl_graph_create": (I, [P, P, I, I, I, P, Z, P, ctypes.POINTER(P)]),
         "dl_graph_create_rois": (I, [P, ctypes.POINTER(DLRoi), I, P, Z, P, ctypes.POINTER(P)]),
         "dl_graph_launch": (I, [P, P]),
+        "dl_graph_create_rois_dynamic": (I, [P, I, I, I, ctypes.c_int64, P, Z, P, ctypes.POINTER(P)]),
+        "dl_graph_launch_rois": (I, [P, ctypes.POINTER(DLRoi), I, P]),
         "dl_autotune": (I, [P, P, I, I, I, P, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]),
         "dl_graph_destroy": (None, [P]),
         "dl_gate_keep_map": (I, [P, P, P, Z, ctypes.POINTER(Z)]),
@@ -439,6 +441,17 @@ class Net:
                                            ctypes.byref(g)))
         return Graph(self, g, (rois, out, counts))
 
+    def graph_rois_dynamic(self, max_rois: int, max_h: int, max_w: int, max_pixels: int, out, counts) -> "Graph":
+        """Capture one graph that localizes any ROI list within the capacity
+        (dl_graph_create_rois_dynamic); replay it with Graph.launch_rois."""
+        if counts.numel() < max_rois + 1:
+            raise ValueError("counts must hold max_rois + 1 entries")
+        cap = out.numel() * out.element_size() // 32
+        g = ctypes.c_void_p()
+        self._rc(_lib.dl_graph_create_rois_dynamic(self.handle, max_rois, max_h, max_w, max_pixels, _ptr(out), cap,
+                                                   _ptr(counts), ctypes.byref(g)))
+        return Graph(self, g, (out, counts))
+
     def autotune(self, frames, reps: int = 3, stream=None):
         """Pick the fastest convolution tile shape for this batch shape; returns
         (rows, {rows: ms per pass})."""
@@ -503,6 +516,14 @@ class Graph:
 
     def launch(self, stream=None):
         _check(_lib.dl_graph_launch(self.handle, _stream(stream)), self.net.handle)
+
+    def launch_rois(self, rois: Sequence, stream=None):
+        """One replay of a capacity graph over this ROI list (cuda uint16
+        [h, w] tensors, rows may be strided); the tensors must stay alive
+        until the replay has run."""
+        arr = Net._roi_array(rois)
+        self._live = list(rois)
+        _check(_lib.dl_graph_launch_rois(self.handle, arr, len(rois), _stream(stream)), self.net.handle)
 
     def close(self):
         if getattr(self, "handle", None):

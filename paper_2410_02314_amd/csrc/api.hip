@@ -682,6 +682,15 @@ struct dl_graph {
     hipGraphExec_t exec = nullptr;
     uint64_t cam_gen = 0;           // the handle's camera-map generation at capture
     uint64_t packed_gen = 0;        // and its weight-packing generation
+    // ROI graphs of any batch within a capacity: the ROI list goes into a
+    // pinned slot the graph's first node copies to the device, where a kernel
+    // builds the descriptors and the frame counts (dyn)
+    bool dynamic = false;
+    int cap_rois = 0, cap_h = 0, cap_w = 0;
+    int64_t cap_px = 0, cap_act = 0, cap_rows = 0, cap_words = 0;
+    char *h_slot = nullptr, *d_slot = nullptr;   // [int64 n][dl_roi x cap_rois]
+    int64_t *d_dyn = nullptr;
+    hipEvent_t copied = nullptr;    // recorded in the graph after the slot's copy
 };
 
 static int check_rois(dl_net *net, const dl_roi *rois, int nroi);
@@ -690,7 +699,7 @@ static void roi_geometry(dl_net *net, const dl_roi *rois, int nroi, std::vector<
 namespace {
 
 int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g, dl_emitter *d_out, size_t cap,
-                uint32_t *d_counts, dl_graph **out)
+                uint32_t *d_counts, dl_graph **out, dl_graph *dyn_proto = nullptr)
 {
     int rc;
     if ((rc = set_device(net))) return rc;
@@ -698,6 +707,7 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
     if (gated_run(net)) return fail(net, DL_ERR_UNSUPPORTED, "graph capture of gated runs is not supported");
     dl_graph *gr = new (std::nothrow) dl_graph();
     if (!gr) return fail(net, DL_ERR_OOM, "out of host memory");
+    if (dyn_proto) *gr = *dyn_proto;        // capacity fields of a dynamic ROI graph
     gr->net = net;
     gr->cam_gen = net->cam_gen;
     gr->packed_gen = net->packed_gen;       // ensure_packed ran above
@@ -706,6 +716,10 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
         if (gr->graph) (void)hipGraphDestroy(gr->graph);
         if (gr->ws) (void)hipFree(gr->ws);
         if (gr->d_fd) (void)hipFree(gr->d_fd);
+        if (gr->d_slot) (void)hipFree(gr->d_slot);
+        if (gr->d_dyn) (void)hipFree(gr->d_dyn);
+        if (gr->h_slot) (void)hipHostFree(gr->h_slot);
+        if (gr->copied) (void)hipEventDestroy(gr->copied);
         delete gr;
         return code;
     };
@@ -716,9 +730,24 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
         (void)hipGetLastError();
         return bail(fail(net, DL_ERR_OOM, "hipMalloc(%zu) for the graph workspace failed", p.total));
     }
-    if (hipMalloc(&gr->d_fd, sizeof(FrameDesc) * fd.size()) != hipSuccess ||
-        hipMemcpy(gr->d_fd, fd.data(), sizeof(FrameDesc) * fd.size(), hipMemcpyHostToDevice) != hipSuccess)
+    Geometry gg = g;
+    const size_t slot_bytes = 8 + sizeof(dl_roi) * (size_t)gr->cap_rois;
+    if (gr->dynamic) {
+        if (hipMalloc(&gr->d_fd, sizeof(FrameDesc) * gr->cap_rois) != hipSuccess ||
+            hipMalloc(&gr->d_slot, slot_bytes) != hipSuccess ||
+            hipMalloc(&gr->d_dyn, sizeof(int64_t) * DYN_WORDS) != hipSuccess ||
+            hipHostMalloc((void **)&gr->h_slot, slot_bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(net, DL_ERR_OOM, "allocation of the graph's ROI slots failed"));
+        }
+        std::memset(gr->h_slot, 0, slot_bytes);
+        if (hipEventCreateWithFlags(&gr->copied, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(net, DL_ERR_DEVICE, "hipEventCreate failed"));
+        gg.dyn = gr->d_dyn;
+    } else if (hipMalloc(&gr->d_fd, sizeof(FrameDesc) * fd.size()) != hipSuccess ||
+               hipMemcpy(gr->d_fd, fd.data(), sizeof(FrameDesc) * fd.size(), hipMemcpyHostToDevice) != hipSuccess) {
         return bail(fail(net, DL_ERR_DEVICE, "descriptor upload failed"));
+    }
     p.ws = gr->ws;
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
@@ -728,8 +757,28 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         float *maps = reinterpret_cast<float *>(p.ws + p.maps);
-        rc = run_net(net, gr->d_fd, g, p, maps, cs);
-        if (!rc) rc = run_post(net, gr->d_fd, g, p, maps, d_out, cap, d_counts, cs);
+        rc = DL_OK;
+        if (gr->dynamic) {
+            // the ROI list of this replay: pinned slot -> device, then the
+            // descriptors and frame counts built on the device
+            EnumArgs ea{};
+            ea.nb = net->nb;
+            ea.tr = g.tr;
+            ea.tc = g.tc;
+            ea.layouts[ea.nl++] = 1;
+            for (int b = 0; b < net->nb; ++b) {
+                ea.dil[b] = net->dil[b];
+                const int l = block_layout(net, b);
+                bool seen = false;
+                for (int i = 0; i < ea.nl; ++i) seen |= ea.layouts[i] == l;
+                if (!seen) ea.layouts[ea.nl++] = l;
+            }
+            if (hipMemcpyAsync(gr->d_slot, gr->h_slot, slot_bytes, hipMemcpyHostToDevice, cs) != hipSuccess ||
+                hipEventRecord(gr->copied, cs) != hipSuccess || launch_enumerate(gr->d_slot, ea, gr->d_fd, gr->d_dyn, cs) != hipSuccess)
+                rc = fail(net, DL_ERR_DEVICE, "capturing the ROI list's copy and enumeration failed");
+        }
+        if (!rc) rc = run_net(net, gr->d_fd, gg, p, maps, cs);
+        if (!rc) rc = run_post(net, gr->d_fd, gg, p, maps, d_out, cap, d_counts, cs);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         gr->graph = graph;
@@ -1618,10 +1667,92 @@ int dl_graph_create_rois(dl_net *net, const dl_roi *rois, int nroi, dl_emitter *
     return graph_build(net, fd, g, d_out, cap, d_counts, out);
 }
 
+int dl_graph_create_rois_dynamic(dl_net *net, int max_rois, int max_h, int max_w, int64_t max_pixels,
+                                 dl_emitter *d_out, size_t cap, uint32_t *d_counts, dl_graph **out)
+{
+    if (!out) return fail(net, DL_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (max_rois < 1 || max_rois > DL_GRAPH_MAX_ROIS || max_h < 1 || max_w < 1 || max_pixels < 1)
+        return fail(net, DL_ERR_INVALID_ARG, "capacity: 1 <= max_rois <= %d, max_h, max_w, max_pixels >= 1",
+                    DL_GRAPH_MAX_ROIS);
+    if ((int64_t)max_h * max_w > (int64_t)1 << 28 || !frame_act_fits(net, max_h, max_w))
+        return fail(net, DL_ERR_UNSUPPORTED, "an ROI of %d x %d pixels is too large", max_h, max_w);
+    if (!d_counts) return fail(net, DL_ERR_INVALID_ARG, "d_counts is NULL");
+    if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
+    int rc;
+    if ((rc = check_camera(net, false, 0, 0))) return rc;
+    dl_graph proto;
+    proto.dynamic = true;
+    proto.cap_rois = max_rois;
+    proto.cap_h = max_h;
+    proto.cap_w = max_w;
+    proto.cap_px = std::min<int64_t>(max_pixels, (int64_t)max_rois * max_h * max_w);
+    proto.cap_rows = std::min<int64_t>((int64_t)max_rois * max_h, proto.cap_px);
+    const int64_t cols = std::min<int64_t>((int64_t)max_rois * max_w, proto.cap_px);
+    int L = 1;
+    for (int b = 0; b < net->nb; ++b) L = std::max(L, block_layout(net, b));
+    // a frame's largest layout holds at most (h + L - 1)(w + L - 1) points
+    proto.cap_act = proto.cap_px + (int64_t)(L - 1) * (proto.cap_rows + cols) + (int64_t)max_rois * (L - 1) * (L - 1);
+    proto.cap_words = (proto.cap_px + 63) / 64 + proto.cap_rows;
+    if (proto.cap_rows > (int64_t)1 << 30) return fail(net, DL_ERR_UNSUPPORTED, "capacity has too many rows");
+    Geometry g;
+    g.nf = max_rois;
+    conv_tile_shape(net->C, net->cfg.precision, tile_rows_of(net), &g.tr, &g.tc);
+    g.minor_blk = net->nb - 1;
+    g.total_px = proto.cap_px;
+    g.total_act = proto.cap_act;
+    g.total_rows = proto.cap_rows;
+    g.total_words = proto.cap_words;
+    for (int b = 0; b < net->nb; ++b) g.tiles[b] = (int64_t)1 << 40;   // persistent grids: the full chip
+    g.max_tiles = 0;
+    g.maxh = max_h;
+    g.maxw = max_w;
+    std::vector<FrameDesc> none;
+    return graph_build(net, none, g, d_out, cap, d_counts, out, &proto);
+}
+
+int dl_graph_launch_rois(dl_graph *g, const dl_roi *rois, int nroi, void *stream)
+{
+    if (!g) return fail(nullptr, DL_ERR_INVALID_ARG, "graph is NULL");
+    dl_net *net = g->net;
+    if (!g->dynamic) return fail(net, DL_ERR_INVALID_ARG, "this graph was captured for one fixed batch (dl_graph_launch)");
+    int rc = check_rois(net, rois, nroi);
+    if (rc) return rc;
+    if (nroi > g->cap_rois) return fail(net, DL_ERR_CAPACITY, "%d ROIs exceed the graph's capacity of %d", nroi, g->cap_rois);
+    int64_t px = 0, act = 0, rows = 0, words = 0;
+    for (int k = 0; k < nroi; ++k) {
+        const dl_roi &r = rois[k];
+        if (r.h > g->cap_h || r.w > g->cap_w)
+            return fail(net, DL_ERR_CAPACITY, "roi %d is %d x %d; the graph holds ROIs up to %d x %d", k, r.h, r.w,
+                        g->cap_h, g->cap_w);
+        px += (int64_t)r.h * r.w;
+        act += frame_act_points(net, r.h, r.w);
+        rows += r.h;
+        words += (int64_t)r.h * ((r.w + 63) / 64);
+    }
+    if (px > g->cap_px || act > g->cap_act || rows > g->cap_rows || words > g->cap_words)
+        return fail(net, DL_ERR_CAPACITY, "the ROIs' %lld pixels exceed the graph's capacity of %lld", (long long)px,
+                    (long long)g->cap_px);
+    if (g->cam_gen != net->cam_gen)
+        return fail(net, DL_ERR_INVALID_ARG, "the camera maps were set, cleared or reshaped after this graph was captured");
+    if (g->packed_gen != net->packed_gen)
+        return fail(net, DL_ERR_INVALID_ARG, "the handle's precision changed after this graph was captured (its weights moved)");
+    if ((rc = set_device(net))) return rc;
+    // the previous replay has copied the slot once this event has passed
+    HIPCHK(net, hipEventSynchronize(g->copied));
+    const int64_t n64 = nroi;
+    std::memcpy(g->h_slot, &n64, 8);
+    std::memcpy(g->h_slot + 8, rois, sizeof(dl_roi) * (size_t)nroi);
+    HIPCHK(net, hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return DL_OK;
+}
+
 int dl_graph_launch(dl_graph *g, void *stream)
 {
     if (!g) return fail(nullptr, DL_ERR_INVALID_ARG, "graph is NULL");
     dl_net *net = g->net;
+    if (g->dynamic) return fail(net, DL_ERR_INVALID_ARG, "this graph takes a ROI list at each launch (dl_graph_launch_rois)");
     int rc;
     if (g->cam_gen != net->cam_gen)
         return fail(net, DL_ERR_INVALID_ARG, "the camera maps were set, cleared or reshaped after this graph was captured");
@@ -1641,6 +1772,10 @@ void dl_graph_destroy(dl_graph *g)
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->ws) (void)hipFree(g->ws);
     if (g->d_fd) (void)hipFree(g->d_fd);
+    if (g->d_slot) (void)hipFree(g->d_slot);
+    if (g->d_dyn) (void)hipFree(g->d_dyn);
+    if (g->h_slot) (void)hipHostFree(g->h_slot);
+    if (g->copied) (void)hipEventDestroy(g->copied);
     delete g;
 }
 

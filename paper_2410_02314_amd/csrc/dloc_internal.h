@@ -68,7 +68,15 @@ struct Geometry {
     int tr = 8, tc = 64;           // conv tile shape on the sub-lattice
     int maxw = 0, maxh = 0;
     int minor_blk = -1;            // block whose tiles run phase-minor (see decode_tile)
+    // Batches whose frame list is only known on the device (a graph replayed
+    // over any ROI set within its capacity): dyn points to DYN_WORDS int64 in
+    // device memory -- the frame count, the total rows, then the conv tiles of
+    // each block -- which the kernels read in place of nf, total_rows and
+    // tiles[].  The other fields then hold capacity bounds (grid sizes,
+    // workspace offsets such as the FP8 scale region at total_act * C).
+    const int64_t *dyn = nullptr;
 };
+constexpr int DYN_NF = 0, DYN_ROWS = 1, DYN_TILES = 2, DYN_WORDS = 2 + MAXBLK;
 
 // Order of one frame's conv tiles for one block.  Phase-major: the d*d phase
 // sub-lattices one after another, and within a phase its ry x rx regions in
@@ -182,6 +190,18 @@ __device__ __forceinline__ v4f fp8_unpack4(uint32_t codes, float s)
     const f32x2_t hi = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(codes, s, true);
     return v4f{lo[0], lo[1], hi[0], hi[1]};
 }
+
+// The frame descriptors of a ROI list on the device (one workgroup): from
+// in = [int64 n][dl_roi x n] (device copy of a pinned slot), fd[k] of ROI k
+// with every offset a prefix sum over the ROIs before it, and dyn (see
+// Geometry::dyn).  layouts: the activation layouts the net uses (a frame
+// reserves the largest); dil: the blocks' dilations; tr x tc: the conv tile.
+struct EnumArgs {
+    int nl, nb, tr, tc;
+    int layouts[MAXBLK + 1];
+    int dil[MAXBLK];
+};
+hipError_t launch_enumerate(const void *in, const EnumArgs &e, FrameDesc *fd, int64_t *dyn, hipStream_t s);
 
 // ---- launchers (kernels_*.hip) ----
 // all return hipError_t of the launch

@@ -273,7 +273,9 @@ k_conv(ConvArgs a, Geometry geo)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) awn[nb] = static_cast<const v4f *>(a.wpk)[nb * 64 + lane];
 
-    const int64_t T = a.list ? (int64_t)ld_const(a.list_count) : geo.tiles[blk];
+    const int64_t T = a.list ? (int64_t)ld_const(a.list_count)
+                      : geo.dyn ? ld_const(geo.dyn + DYN_TILES + blk) : geo.tiles[blk];
+    const int nfr = geo.dyn ? (int)ld_const(geo.dyn + DYN_NF) : geo.nf;
     const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD, nslot = gridDim.x / NXCD;
     const int64_t chunk = (T + NXCD - 1) / NXCD;
     const int64_t t0 = (int64_t)xcd * chunk;
@@ -307,7 +309,7 @@ k_conv(ConvArgs a, Geometry geo)
     auto decode = [&](int64_t ti) {
         TileDec r;
         const int64_t t = a.list ? (int64_t)ld_const(a.list + ti) : ti;
-        const int f = find_frame(a.fd, geo.nf, t, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
+        const int f = find_frame(a.fd, nfr, t, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
         const FrameDesc *fd = a.fd + f;      // fields read in place: tile_start is indexed by the block
         r.h = ld_const(&fd->h);
         r.w = ld_const(&fd->w);

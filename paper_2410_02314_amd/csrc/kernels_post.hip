@@ -27,10 +27,15 @@ constexpr int SSEG = 1024;
 
 template <int C, int P>
 __global__ void __launch_bounds__(256)
-k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const float *__restrict__ w,
-       const float *__restrict__ b, float offset, float scale, const float2 *__restrict__ cam,
-       void *__restrict__ act, int64_t scale_off, const uint8_t *__restrict__ keep, int radius)
+k_stem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const int64_t *__restrict__ dyn,
+       const float *__restrict__ w, const float *__restrict__ b, float offset, float scale,
+       const float2 *__restrict__ cam, void *__restrict__ act, int64_t scale_off, const uint8_t *__restrict__ keep,
+       int radius)
 {
+    if (dyn) {                       // frame count and rows known on the device only
+        nf = (int)dyn[DYN_NF];
+        nrows = dyn[DYN_ROWS];
+    }
     constexpr int CQ = P == DL_FP8 ? 16 : P == DL_BF16 ? 8 : 4;   // channels per item
     constexpr int IPX = P == DL_FP8 ? 4 : C / CQ;                  // items per pixel
     static_assert(P != DL_FP8 || C <= 64, "FP8 stem: at most four 16-channel items");
@@ -137,13 +142,13 @@ hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const 
     const unsigned grid = (unsigned)std::min<int64_t>(g.total_rows, 8192);
     const int64_t soff = g.total_act * C;        // FP8: byte offset of the group scales
     if (precision == DL_FP8)
-        hipLaunchKernelGGL((k_stem<C, DL_FP8>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
+        hipLaunchKernelGGL((k_stem<C, DL_FP8>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, g.dyn, w, b, offset,
                            scale, cam, act, soff, keep, radius);
     else if (precision == DL_BF16)
-        hipLaunchKernelGGL((k_stem<C, DL_BF16>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
+        hipLaunchKernelGGL((k_stem<C, DL_BF16>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, g.dyn, w, b, offset,
                            scale, cam, act, soff, keep, radius);
     else
-        hipLaunchKernelGGL((k_stem<C, DL_FP32>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, w, b, offset,
+        hipLaunchKernelGGL((k_stem<C, DL_FP32>), dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, g.dyn, w, b, offset,
                            scale, cam, act, soff, keep, radius);
     return hipGetLastError();
 }
@@ -175,13 +180,14 @@ constexpr int DBAND = 8, DROWS = DBAND + 2;
 // GATED: keep is a gate keep map; SIGMA: the uncertainty filter is on
 template <bool GATED, bool SIGMA>
 __global__ void __launch_bounds__(256)
-k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__restrict__ fdp, int bands, float tau,
-              float u_max, const uint8_t *__restrict__ keep, uint64_t *__restrict__ mask,
-              uint32_t *__restrict__ row_counts)
+k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__restrict__ fdp, int bands,
+              const int64_t *__restrict__ dyn, float tau, float u_max, const uint8_t *__restrict__ keep,
+              uint64_t *__restrict__ mask, uint32_t *__restrict__ row_counts)
 {
     __shared__ uint32_t wcnt[DBAND][4];
     // workgroup = (frame, band): bands per frame from the batch's tallest frame
     const int f = blockIdx.x / bands, band = blockIdx.x - f * bands;
+    if (dyn && f >= dyn[DYN_NF]) return;                  // past the frames of this batch
     const FrameDesc fd = fdp[f];
     const int H = fd.h, W = fd.w;
     const int y0 = band * DBAND;
@@ -290,8 +296,12 @@ k_detect_mask(const float *__restrict__ maps, int planes, const FrameDesc *__res
 // each thread writes its chunk's offsets), then per-frame counts and total.
 __global__ void __launch_bounds__(1024)
 k_scan(const uint32_t *__restrict__ rc, int64_t R, const FrameDesc *__restrict__ fdp, int nf,
-       uint32_t *__restrict__ row_off, uint32_t *__restrict__ counts)
+       const int64_t *__restrict__ dyn, uint32_t *__restrict__ row_off, uint32_t *__restrict__ counts)
 {
+    if (dyn) {
+        nf = (int)dyn[DYN_NF];
+        R = dyn[DYN_ROWS];
+    }
     __shared__ uint32_t sh[1024];
     const int tid = threadIdx.x;
     const int64_t per = (R + 1023) / 1024;
@@ -329,10 +339,14 @@ k_scan(const uint32_t *__restrict__ rc, int64_t R, const FrameDesc *__restrict__
 __global__ void __launch_bounds__(256)
 k_emit(const float *__restrict__ maps, int planes, const uint64_t *__restrict__ mask,
        const uint32_t *__restrict__ row_off, const FrameDesc *__restrict__ fdp, int nf,
-       float z_scale, float ph_scale, float bg_scale, dl_emitter *__restrict__ out,
+       const int64_t *__restrict__ dyn, float z_scale, float ph_scale, float bg_scale, dl_emitter *__restrict__ out,
        dl_uncertainty *__restrict__ unc, uint64_t cap)
 {
     const int64_t row = blockIdx.x;
+    if (dyn) {
+        if (row >= dyn[DYN_ROWS]) return;                 // past the rows of this batch
+        nf = (int)dyn[DYN_NF];
+    }
     const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
     const FrameDesc fd = fdp[f];
     const int y = (int)(row - fd.row_start);
@@ -422,6 +436,89 @@ k_mask_from_u8(const uint8_t *__restrict__ det, const FrameDesc *__restrict__ fd
     if (lane == 0) sc[wave] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) row_counts[row] = sc[0] + sc[1] + sc[2] + sc[3];
+}
+
+// ------------------------------------------------ descriptors on the device
+// One workgroup turns a ROI list ([int64 n][dl_roi x n], copied from a pinned
+// slot by a graph's first node) into the batch's frame descriptors: per ROI
+// its pixels, activation points (the largest layout the net uses), rows,
+// detection words and conv tiles of every block; each descriptor offset is
+// the exclusive prefix sum of that quantity over the ROIs before it (each
+// thread sums a contiguous chunk of ROIs, the chunk sums are scanned in
+// LDS).  dyn receives the frame count, the total rows and each block's tiles.
+constexpr int ENQ = 4 + MAXBLK;      // pixels, activation points, rows, words, tiles per block
+
+__device__ int64_t enum_quantity(int q, int h, int w, const EnumArgs &e)
+{
+    if (q == 0) return (int64_t)h * w;
+    if (q == 1) {
+        int64_t m = 0;
+        for (int i = 0; i < e.nl; ++i) m = max(m, act_points(h, w, e.layouts[i]));
+        return m;
+    }
+    if (q == 2) return h;
+    if (q == 3) return (int64_t)h * ((w + 63) / 64);
+    return conv_tiles(h, w, e.dil[q - 4], e.tr, e.tc);
+}
+
+__global__ void __launch_bounds__(1024)
+k_enumerate(const char *__restrict__ in, EnumArgs e, FrameDesc *__restrict__ fd, int64_t *__restrict__ dyn)
+{
+    __shared__ int64_t sh[1024];
+    const int64_t n = *reinterpret_cast<const int64_t *>(in);
+    const dl_roi *r = reinterpret_cast<const dl_roi *>(in + 8);
+    const int tid = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t k0 = min(n, (int64_t)tid * per), k1 = min(n, k0 + per);
+    int64_t base[ENQ];
+#pragma unroll
+    for (int q = 0; q < ENQ; ++q) {
+        base[q] = 0;
+        if (q >= 4 + e.nb) continue;                       // uniform
+        int64_t sum = 0;
+        for (int64_t k = k0; k < k1; ++k) sum += enum_quantity(q, r[k].h, r[k].w, e);
+        sh[tid] = sum;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t v = tid >= o ? sh[tid - o] : 0;
+            __syncthreads();
+            sh[tid] += v;
+            __syncthreads();
+        }
+        base[q] = sh[tid] - sum;
+        if (tid == 1023) {
+            if (q == 2) dyn[DYN_ROWS] = sh[1023];
+            if (q >= 4) dyn[DYN_TILES + q - 4] = sh[1023];
+        }
+        __syncthreads();
+    }
+    for (int64_t k = k0; k < k1; ++k) {
+        const int h = r[k].h, w = r[k].w;
+        FrameDesc d;
+        d.data = r[k].data;
+        d.stride = r[k].row_stride;
+        d.px_off = base[0];
+        d.act_off = base[1];
+        d.row_start = base[2];
+        d.mask_start = base[3];
+        d.keep_start = 0;
+#pragma unroll
+        for (int b = 0; b < MAXBLK; ++b) d.tile_start[b] = b < e.nb ? base[4 + b] : 0;
+        d.h = h;
+        d.w = w;
+        d.words = (w + 63) / 64;
+        d.gtx = w / GATE_TILE;
+        d.gty = h / GATE_TILE;
+        d.pad_ = 0;
+        fd[k] = d;
+#pragma unroll
+        for (int q = 0; q < ENQ; ++q)
+            if (q < 4 + e.nb) base[q] += enum_quantity(q, h, w, e);
+    }
+    if (tid == 0) {
+        dyn[DYN_NF] = n;
+        for (int b = e.nb; b < MAXBLK; ++b) dyn[DYN_TILES + b] = 0;
+    }
 }
 
 // ----------------------------------------------------------- gated runs
@@ -527,15 +624,15 @@ hipError_t launch_detect_mask(const float *maps, int planes, const FrameDesc *fd
     const bool sigma = planes == 10 && u_max < INFINITY;
     auto kern = keep ? (sigma ? k_detect_mask<true, true> : k_detect_mask<true, false>)
                      : (sigma ? k_detect_mask<false, true> : k_detect_mask<false, false>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, maps, planes, fd, bands, tau, u_max, keep, mask,
-                       row_counts);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, maps, planes, fd, bands, g.dyn, tau, u_max, keep,
+                       mask, row_counts);
     return hipGetLastError();
 }
 
 hipError_t launch_scan(const uint32_t *row_counts, const FrameDesc *fd, const Geometry &g,
                        uint32_t *row_off, uint32_t *counts, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, row_counts, g.total_rows, fd, g.nf, row_off, counts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, row_counts, g.total_rows, fd, g.nf, g.dyn, row_off, counts);
     return hipGetLastError();
 }
 
@@ -543,8 +640,14 @@ hipError_t launch_emit(const float *maps, int planes, const uint64_t *mask, cons
                        const FrameDesc *fd, const Geometry &g, float z_scale, float ph_scale,
                        float bg_scale, dl_emitter *out, dl_uncertainty *unc, uint64_t cap, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, mask, row_off, fd, g.nf,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)g.total_rows), dim3(256), 0, s, maps, planes, mask, row_off, fd, g.nf, g.dyn,
                        z_scale, ph_scale, bg_scale, out, unc, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_enumerate(const void *in, const EnumArgs &e, FrameDesc *fd, int64_t *dyn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_enumerate, dim3(1), dim3(1024), 0, s, static_cast<const char *>(in), e, fd, dyn);
     return hipGetLastError();
 }
 
