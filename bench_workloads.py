@@ -93,12 +93,40 @@ def rois(args, S):
     out = torch.empty((cap, 8), dtype=torch.int32, device=dev)
     counts = torch.zeros(257, dtype=torch.int32, device=dev)
     st = torch.cuda.current_stream()
+    # the autotuner (strip width, per-block tile rows) on a uniform batch of the
+    # ROIs' typical size; its choice is used for everything below
+    import tempfile
+    tune = None
+    if not args.tile_rows:
+        probe = torch.from_numpy(S.render_frames(8, 512, 512, "rois", 1004)).to(dev)
+        tune = net.autotune_ex(probe, reps=3, cache_path=os.path.join(tempfile.gettempdir(), "dloc_tune.jsonl"),
+                               stream=st)
+        del probe
+        log(f"autotuner: {tune}")
     net.profile(True)
     ms = _timed(lambda: net.localize_rois_device(d, out, counts, st), args.steps, args.warmup, st)
     prof = net.profile_read()
     net.profile(False)
     g = net.graph_rois(d, out, counts)
     ms_graph = _timed(lambda: g.launch(st), args.steps, args.warmup, st)
+    g.close()
+    # one capacity graph serving any ROI batch that fits: replayed alternately
+    # over this ROI set and a second, differently seeded one
+    rois2_np = S.render_rois(256, "rois", 1005)
+    d2 = [torch.from_numpy(r).to(dev) for r in rois2_np]
+    px_cap = max(px, sum(r.size for r in rois2_np))
+    gd = net.graph_rois_dynamic(256, 1024, 1024, px_cap, out, counts)
+    sets = [d, d2]
+    it = [0]
+
+    def dyn_step():
+        gd.launch_rois(sets[it[0] & 1], st)
+        it[0] += 1
+
+    ms_dyn = _timed(dyn_step, 2 * (args.steps // 2 + 1), args.warmup, st)
+    gd.close()
+    torch.cuda.synchronize()
+    net.localize_rois_device(d, out, counts, st)          # counts of the headline ROI set again
     conv_ms, conv_n = prof["conv"]
     flop = 2.0 * 9 * spec.C * spec.C * px
     ach = flop / (conv_ms / conv_n * 1e-3) / 1e12
@@ -114,11 +142,14 @@ def rois(args, S):
     _line(args, mpx, ms,
           {"workload": f"256 uneven ROIs (sides 128..1024), {px / 1e6:.1f} Mpx, net A",
            "precision": args.precision, "frames": 256, "pixels": px},
-          {"graph_ms_per_step": round(ms_graph, 3), "emitters_per_step": int(counts[256].item()),
+          {"graph_ms_per_step": round(ms_graph, 3),
+           "capacity_graph_ms_per_step": round(ms_dyn, 3),
+           "capacity_graph": "one capture (256 ROIs up to 1024 x 1024) replayed alternately over two ROI sets",
+           "autotune": tune,
+           "emitters_per_step": int(counts[256].item()),
            "uniform_16x2048sq_mpx_s": round(mpx_uni, 2), "load_balance_efficiency": round(mpx / mpx_uni, 4),
            "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAKS[args.precision],
                         "unit": "TFLOP/s", "frac": round(ach / PEAKS[args.precision], 4), "traffic": None}})
-    g.close()
 
 
 def sparse(args, S):

@@ -431,6 +431,32 @@ int dl_set_gate(dl_net *net, const float *theta, float threshold);
  * flags.  DL_ERR_CAPACITY if cap is too small. */
 int dl_gate_keep_map(dl_net *net, void *stream, uint8_t *d_keep, size_t cap, size_t *ntiles);
 
+/* Autotuner over the conv tiling, with a cache (the tiling is this library's
+ * choice; the paper fixes none).  Starting from the form's default (8-row
+ * tiles, tile order in column strips 8 regions wide) it times the network on
+ * the caller's batch (`reps` passes after one warm-up, HIP events on
+ * `stream`) for strip widths 4, 16 and 32, keeping one only when 1% faster,
+ * then toggles each block's tile rows between 8 and 4 in turn under the same
+ * rule, and applies the result to the handle (per-block rows; cfg.tile_rows
+ * is reset to 0).  cache_path (may be NULL): a text file of JSON lines
+ * {"key": ..., "rows": [...], "strip": s, "ms": t}; the key names the device
+ * architecture, its CU count, the net (C, dilations, head outputs), the
+ * precision and the batch shape.  A line with this key is applied without
+ * timing (res->from_cache = 1); otherwise the result is appended.  res
+ * receives the chosen rows and strip, the number of tilings timed and the
+ * mean ms per pass of the default and of the chosen tiling.  Synchronous.
+ * DL_ERR_INVALID_ARG if the cache cannot be appended to (the tuned tiling is
+ * still applied). */
+typedef struct {
+    int32_t rows[8];         /* tile rows of each block's convolutions (4 or 8) */
+    int32_t strip;           /* strip width of the tile order, in regions        */
+    int32_t from_cache;      /* 1: taken from the cache, nothing timed           */
+    int32_t configs_timed;
+    float ms_default, ms_best;
+} dl_tune_result;
+int dl_autotune_ex(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, int reps,
+                   const char *cache_path, dl_tune_result *res);
+
 /* ---- stage timing ----
  * With profiling on, every kernel launch of the path is bracketed by two HIP
  * events recorded on the stream it runs on.  dl_profile_read waits for the

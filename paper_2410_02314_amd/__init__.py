@@ -62,6 +62,11 @@ class DLNetInfo(ctypes.Structure):
                 ("head_outputs", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
+class DLTuneResult(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32 * 8), ("strip", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("configs_timed", ctypes.c_int32), ("ms_default", ctypes.c_float), ("ms_best", ctypes.c_float)]
+
+
 class DlocError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
@@ -117,6 +122,7 @@ def _load():
         "dl_graph_launch_rois": (I, [P, ctypes.POINTER(DLRoi), I, P]),
         "dl_autotune": (I, [P, P, I, I, I, P, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]),
         "dl_graph_destroy": (None, [P]),
+        "dl_autotune_ex": (I, [P, P, I, I, I, P, I, ctypes.c_char_p, ctypes.POINTER(DLTuneResult)]),
         "dl_gate_keep_map": (I, [P, P, P, Z, ctypes.POINTER(Z)]),
         "dl_gate_pool": (I, [P, I, I, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P]),
         "dl_gate_forward": (I, [P, I, P, P, P]),
@@ -242,6 +248,7 @@ class Net:
         info = DLNetInfo()
         _check(_lib.dl_inspect_weights(buf, len(weights), ctypes.byref(info)))
         self.head_outputs = int(info.head_outputs)     # planes of the maps: 5, or 10 with uncertainties
+        self.nblocks = int(info.nblocks)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -460,6 +467,18 @@ class Net:
         ms = (ctypes.c_float * 2)()
         self._rc(_lib.dl_autotune(self.handle, _ptr(frames), n, h, w, _stream(stream), reps, ctypes.byref(best), ms))
         return int(best.value), {8: float(ms[0]), 4: float(ms[1])}
+
+    def autotune_ex(self, frames, reps: int = 3, cache_path: Optional[str] = None, stream=None) -> dict:
+        """Tune strip width and per-block tile rows on this batch (dl_autotune_ex);
+        with cache_path, reuse or record the result."""
+        n, h, w = _frames_arg(frames).shape
+        r = DLTuneResult()
+        path = cache_path.encode() if cache_path else None
+        self._rc(_lib.dl_autotune_ex(self.handle, _ptr(frames), n, h, w, _stream(stream), reps, path,
+                                     ctypes.byref(r)))
+        nb = self.nblocks
+        return {"rows": list(r.rows[:nb]), "strip": int(r.strip), "from_cache": bool(r.from_cache),
+                "configs_timed": int(r.configs_timed), "ms_default": float(r.ms_default), "ms_best": float(r.ms_best)}
 
     def set_gate(self, theta, threshold: float = 0.05):
         """Attach gate parameters (host array of 673 floats, or None to detach)."""

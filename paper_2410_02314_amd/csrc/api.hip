@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -119,6 +120,12 @@ struct dl_net {
     float2 *d_cam = nullptr;
     int cam_h = 0, cam_w = 0;
     uint64_t cam_gen = 0;
+
+    // conv tiling chosen by the autotuner: tile rows per block (0 = the form's
+    // default) and the strip width of the tile order (0 = 8); cfg.tile_rows,
+    // when set, overrides the rows of every block
+    int tune_rows[MAXBLK] = {0};
+    uint32_t tune_strip = 0;
 };
 
 namespace {
@@ -187,6 +194,20 @@ int check_config(dl_net *net, const dl_config *c)
 
 int tile_rows_of(const dl_net *net) { return net->cfg.tile_rows ? net->cfg.tile_rows : 0; }
 
+// The conv tiling of a batch: the form's tile (its default rows in g.tr), each
+// block's rows (config override, else the autotuner's choice, else the
+// default) and the strip width of the tile order.
+void set_tiling(const dl_net *net, Geometry &g)
+{
+    conv_tile_shape(net->C, net->cfg.precision, tile_rows_of(net), &g.tr, &g.tc);
+    for (int b = 0; b < MAXBLK; ++b) {
+        const int rows = net->cfg.tile_rows ? net->cfg.tile_rows : b < net->nb ? net->tune_rows[b] : 0;
+        int tc = 0;
+        conv_tile_shape(net->C, net->cfg.precision, rows, &g.trb[b], &tc);
+    }
+    g.strip = net->tune_strip ? net->tune_strip : 8;
+}
+
 // Activation layout of block b's layers (input, intermediate and residual):
 // the phase layout of its dilation when that is a power of two, plain NHWC
 // for the first block (the stem writes plain rows) and other dilations.
@@ -220,7 +241,7 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
     fd.resize(n);
     g = Geometry{};
     g.nf = n;
-    conv_tile_shape(net->C, net->cfg.precision, tile_rows_of(net), &g.tr, &g.tc);
+    set_tiling(net, g);
     g.minor_blk = net->nb - 1;        // its head writes plain planar maps
     for (int f = 0; f < n; ++f) {
         FrameDesc &d = fd[f];
@@ -239,7 +260,7 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         d.keep_start = g.gate_tiles;
         for (int b = 0; b < net->nb; ++b) {
             d.tile_start[b] = g.tiles[b];
-            const int64_t nt = conv_tiles(d.h, d.w, net->dil[b], g.tr, g.tc);
+            const int64_t nt = conv_tiles(d.h, d.w, net->dil[b], g.trb[b], g.tc);
             g.tiles[b] += nt;
             g.max_frame_tiles = std::max(g.max_frame_tiles, nt);
         }
@@ -486,9 +507,9 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         HIPCHK(net, launch_stem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset, scale, net->d_cam,
                                 a0, net->cfg.precision, keep, stem_r, s));
     }
-    const int maxg = conv_max_grid(C, net->cfg.precision, g.tr, net->ncu);
     void *x = a0, *xn = p.ws + p.act2;      // block input, block output (alternating)
     for (int b = 0; b < net->nb; ++b) {
+        const int maxg = conv_max_grid(C, net->cfg.precision, g.trb[b], net->ncu);
         int grid = (int)std::min<int64_t>(g.tiles[b], maxg);
         grid = std::max(8, grid / 8 * 8);
         const int lay = block_layout(net, b);
@@ -497,6 +518,7 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
         a.fd = d_fd;
         a.d = net->dil[b];
         a.blk = b;
+        a.tr = g.trb[b];
         a.in_phase = lay == net->dil[b] && lay > 1;
         a.out_shift = __builtin_ctz((unsigned)lay);
         if (net->cfg.precision == DL_FP8) a.wscale = net->d_wscale + (size_t)(b * 2) * C;
@@ -763,7 +785,7 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
             // descriptors and frame counts built on the device
             EnumArgs ea{};
             ea.nb = net->nb;
-            ea.tr = g.tr;
+            for (int b = 0; b < MAXBLK; ++b) ea.tr[b] = g.trb[b];
             ea.tc = g.tc;
             ea.layouts[ea.nl++] = 1;
             for (int b = 0; b < net->nb; ++b) {
@@ -793,6 +815,56 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
     if (rc) return bail(rc);
     *out = gr;
     return DL_OK;
+}
+
+}  // namespace
+
+// ---- autotuner with a cache ----
+namespace {
+
+std::string tune_key(dl_net *net, int n, int h, int w)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, net->dev) == hipSuccess) arch = prop.gcnArchName;
+    std::string k = "arch=" + arch + ";cu=" + std::to_string(net->ncu) + ";C=" + std::to_string(net->C) + ";dil=";
+    for (int b = 0; b < net->nb; ++b) k += (b ? "," : "") + std::to_string(net->dil[b]);
+    k += ";nh=" + std::to_string(net->nh) + ";prec=" + std::to_string(net->cfg.precision) + ";batch=" +
+         std::to_string(n) + "x" + std::to_string(h) + "x" + std::to_string(w);
+    return k;
+}
+
+// one cache line: {"key": "<key>", "rows": [r0, r1, ...], "strip": s, "ms": t}
+bool tune_cache_find(const char *path, const std::string &key, int nb, int *rows, int *strip)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    const std::string want = "{\"key\": \"" + key + "\", \"rows\": [";
+    while (!found && std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
+        const char *q = line + want.size();
+        int r[MAXBLK], k = 0;
+        bool ok = true;
+        for (; k < nb && ok; ++k) {
+            char *end = nullptr;
+            const long v = std::strtol(q, &end, 10);
+            ok = end != q && (v == 4 || v == 8);
+            r[k] = (int)v;
+            q = end;
+            while (*q == ',' || *q == ' ') ++q;
+        }
+        const char *sp = std::strstr(q, "\"strip\": ");
+        if (!ok || *q != ']' || !sp) continue;
+        const long sv = std::strtol(sp + 9, nullptr, 10);
+        if (sv < 1 || sv > 64) continue;
+        for (int b = 0; b < nb; ++b) rows[b] = r[b];
+        *strip = (int)sv;
+        found = true;
+    }
+    std::fclose(f);
+    return found;
 }
 
 }  // namespace
@@ -1600,7 +1672,8 @@ int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int 
     a.out = d_out;
     a.wpk = static_cast<char *>(net->d_wpk) + (size_t)(blk * 2 + which) * net->wpk_stride;
     a.bias = net->d_bias + (size_t)(blk * 2 + which) * net->C;
-    const int maxg = conv_max_grid(net->C, net->cfg.precision, g.tr, net->ncu);
+    a.tr = g.trb[blk];
+    const int maxg = conv_max_grid(net->C, net->cfg.precision, g.trb[blk], net->ncu);
     int grid = (int)std::min<int64_t>(g.tiles[blk], maxg);
     grid = std::max(8, grid / 8 * 8);
     HIPCHK(net, launch_conv(net->C, net->cfg.precision, a, g, grid, s));
@@ -1698,7 +1771,7 @@ int dl_graph_create_rois_dynamic(dl_net *net, int max_rois, int max_h, int max_w
     if (proto.cap_rows > (int64_t)1 << 30) return fail(net, DL_ERR_UNSUPPORTED, "capacity has too many rows");
     Geometry g;
     g.nf = max_rois;
-    conv_tile_shape(net->C, net->cfg.precision, tile_rows_of(net), &g.tr, &g.tc);
+    set_tiling(net, g);
     g.minor_blk = net->nb - 1;
     g.total_px = proto.cap_px;
     g.total_act = proto.cap_act;
@@ -1825,6 +1898,106 @@ int dl_autotune(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void
     net->cfg.tile_rows = rc ? saved : pick;
     if (!rc && best_rows) *best_rows = pick;
     return rc;
+}
+
+
+int dl_autotune_ex(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, int reps,
+                   const char *cache_path, dl_tune_result *res)
+{
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (!res) return fail(net, DL_ERR_INVALID_ARG, "res is NULL");
+    if (reps <= 0 || reps > 1000) return fail(net, DL_ERR_INVALID_ARG, "reps must lie in 1..1000");
+    if ((rc = set_device(net))) return rc;
+    std::memset(res, 0, sizeof *res);
+    const std::string key = tune_key(net, n, h, w);
+    int rows[MAXBLK], strip = 8;
+    if (cache_path && tune_cache_find(cache_path, key, net->nb, rows, &strip)) {
+        net->cfg.tile_rows = 0;
+        for (int b = 0; b < net->nb; ++b) net->tune_rows[b] = res->rows[b] = rows[b];
+        net->tune_strip = (uint32_t)(res->strip = strip);
+        res->from_cache = 1;
+        return DL_OK;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int saved_rows = net->cfg.tile_rows;
+    int saved_tune[MAXBLK];
+    std::memcpy(saved_tune, net->tune_rows, sizeof saved_tune);
+    const uint32_t saved_strip = net->tune_strip;
+    const bool prof = net->profiling;
+    net->profiling = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(net, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(net, DL_ERR_DEVICE, "hipEventCreate failed");
+    }
+    // mean time of one pass of the network (no post-processing) with this tiling
+    auto time_cfg = [&](const int *r, int st, float *ms) -> int {
+        net->cfg.tile_rows = 0;
+        for (int b = 0; b < net->nb; ++b) net->tune_rows[b] = r[b];
+        net->tune_strip = (uint32_t)st;
+        std::vector<FrameDesc> fd;
+        Geometry g;
+        uniform_geometry(net, d_frames, n, h, w, fd, g);
+        int e = localize_geom(net, fd, g, s, nullptr, 0, nullptr, nullptr, d_frames, n, h, w);   // warm-up
+        if (!e && hipEventRecord(e0, s) != hipSuccess) e = fail(net, DL_ERR_DEVICE, "hipEventRecord failed");
+        for (int k = 0; k < reps && !e; ++k) e = localize_geom(net, fd, g, s, nullptr, 0, nullptr, nullptr, d_frames, n, h, w);
+        float t = 0.f;
+        if (!e && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                   hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+            e = fail(net, DL_ERR_DEVICE, "event timing failed");
+        *ms = t / (float)reps;
+        ++res->configs_timed;
+        return e;
+    };
+    // start from the form's default rows and strip 8; pick the strip width,
+    // then each block's rows in turn (kept only when 1% faster)
+    for (int b = 0; b < net->nb; ++b) {
+        int tr = 0, tc = 0;
+        conv_tile_shape(net->C, net->cfg.precision, 0, &tr, &tc);
+        rows[b] = tr;
+    }
+    float best = 0.f, t = 0.f;
+    rc = time_cfg(rows, strip, &best);
+    res->ms_default = best;
+    static const int strips[] = {4, 16, 32};
+    for (int k = 0; k < 3 && !rc; ++k) {
+        rc = time_cfg(rows, strips[k], &t);
+        if (!rc && t < 0.99f * best) {
+            best = t;
+            strip = strips[k];
+        }
+    }
+    for (int b = 0; b < net->nb && !rc; ++b) {
+        const int old = rows[b];
+        rows[b] = old == 8 ? 4 : 8;
+        rc = time_cfg(rows, strip, &t);
+        if (!rc && t < 0.99f * best) best = t;
+        else rows[b] = old;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    net->profiling = prof;
+    if (rc) {
+        net->cfg.tile_rows = saved_rows;
+        std::memcpy(net->tune_rows, saved_tune, sizeof saved_tune);
+        net->tune_strip = saved_strip;
+        return rc;
+    }
+    net->cfg.tile_rows = 0;
+    for (int b = 0; b < net->nb; ++b) net->tune_rows[b] = res->rows[b] = rows[b];
+    net->tune_strip = (uint32_t)(res->strip = strip);
+    res->ms_best = best;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "a");
+        if (!f) return fail(net, DL_ERR_INVALID_ARG, "cannot append to the tuning cache %s", cache_path);
+        std::fprintf(f, "{\"key\": \"%s\", \"rows\": [", key.c_str());
+        for (int b = 0; b < net->nb; ++b) std::fprintf(f, "%s%d", b ? ", " : "", rows[b]);
+        std::fprintf(f, "], \"strip\": %d, \"ms\": %.4f}\n", strip, best);
+        std::fclose(f);
+    }
+    return DL_OK;
 }
 
 int dl_set_gate(dl_net *net, const float *theta, float threshold)

@@ -65,7 +65,9 @@ struct Geometry {
     int64_t tiles[MAXBLK] = {0};   // conv tiles of each block's layers
     int64_t max_tiles = 0;
     int64_t max_frame_tiles = 0;   // most conv tiles of one frame in one block
-    int tr = 8, tc = 64;           // conv tile shape on the sub-lattice
+    int tr = 8, tc = 64;           // conv tile shape on the sub-lattice (tr: the form's default rows)
+    int trb[MAXBLK] = {8, 8, 8, 8, 8, 8, 8, 8};   // tile rows of each block's layers
+    uint32_t strip = 8;            // tile order: column strips of this many regions (see decode_tile)
     int maxw = 0, maxh = 0;
     int minor_blk = -1;            // block whose tiles run phase-minor (see decode_tile)
     // Batches whose frame list is only known on the device (a graph replayed
@@ -80,15 +82,15 @@ constexpr int DYN_NF = 0, DYN_ROWS = 1, DYN_TILES = 2, DYN_WORDS = 2 + MAXBLK;
 
 // Order of one frame's conv tiles for one block.  Phase-major: the d*d phase
 // sub-lattices one after another, and within a phase its ry x rx regions in
-// column strips TSTRIP regions wide, row by row inside a strip, so the tile
-// below a tile comes at most TSTRIP tiles later and finds the halo rows they
+// column strips `strip` regions wide, row by row inside a strip, so the tile
+// below a tile comes at most `strip` tiles later and finds the halo rows they
 // share still in L2 (tiles are handed out in order to the resident
-// workgroups of an XCD).  Phase-minor (the last block, whose head writes
-// plain planar maps): the d*d phases of one region in a row, regions row by
-// row, so the map pixels a region's phases write are written together.
-constexpr uint32_t TSTRIP = 8;
+// workgroups of an XCD; the strip width is a tuning choice, 8 by default).
+// Phase-minor (the last block, whose head writes plain planar maps): the d*d
+// phases of one region in a row, regions row by row, so the map pixels a
+// region's phases write are written together.
 __device__ __forceinline__ void decode_tile(int h, int w, int64_t local, int d, int tr, int tc, bool phase_minor,
-                                            int &Y0, int &X0)
+                                            uint32_t strip, int &Y0, int &X0)
 {
     // a frame has fewer than 2^32 tiles: 32-bit arithmetic suffices
     const uint32_t l = (uint32_t)local, ud = (uint32_t)d;
@@ -103,11 +105,11 @@ __device__ __forceinline__ void decode_tile(int h, int w, int64_t local, int d, 
         const uint32_t nreg = ryn * rxn;
         ph = l / nreg;
         const uint32_t r = l - ph * nreg;
-        const uint32_t sfull = ryn * TSTRIP;                  // tiles of a full strip
+        const uint32_t sfull = ryn * strip;                   // tiles of a full strip
         const uint32_t st = r / sfull, in = r - st * sfull;
-        const uint32_t sw = min(TSTRIP, rxn - st * TSTRIP);   // width of this strip
+        const uint32_t sw = min(strip, rxn - st * strip);     // width of this strip
         ry = in / sw;
-        rx = st * TSTRIP + (in - ry * sw);
+        rx = st * strip + (in - ry * sw);
     }
     const uint32_t py = ph / ud, px = ph - py * ud;
     Y0 = (int)(ry * (uint32_t)(tr * d) + py);
@@ -197,9 +199,10 @@ __device__ __forceinline__ v4f fp8_unpack4(uint32_t codes, float s)
 // Geometry::dyn).  layouts: the activation layouts the net uses (a frame
 // reserves the largest); dil: the blocks' dilations; tr x tc: the conv tile.
 struct EnumArgs {
-    int nl, nb, tr, tc;
+    int nl, nb, tc;
     int layouts[MAXBLK + 1];
     int dil[MAXBLK];
+    int tr[MAXBLK];          // tile rows of each block
 };
 hipError_t launch_enumerate(const void *in, const EnumArgs &e, FrameDesc *fd, int64_t *dyn, hipStream_t s);
 
@@ -236,6 +239,7 @@ struct ConvArgs {
     const uint32_t *list_count;
     int in_phase;            // input and residual in phase layout d (1) or plain NHWC (0)
     int out_shift;           // output in phase layout 1 << out_shift (0: plain NHWC)
+    int tr;                  // tile rows of this layer (4 or 8)
 };
 hipError_t launch_conv(int C, int precision, const ConvArgs &a, const Geometry &g, int grid, hipStream_t s);
 // tile shape of the conv kernel: rows = 4 or 8; 0 picks the form's default

@@ -315,7 +315,8 @@ k_conv(ConvArgs a, Geometry geo)
         r.w = ld_const(&fd->w);
         r.px = ld_const(&fd->px_off);
         r.act = ld_const(&fd->act_off);
-        decode_tile(r.h, r.w, t - ld_const(&fd->tile_start[blk]), dd, TR, TC, blk == geo.minor_blk, r.y0, r.x0);
+        decode_tile(r.h, r.w, t - ld_const(&fd->tile_start[blk]), dd, TR, TC, blk == geo.minor_blk, geo.strip, r.y0,
+                    r.x0);
         if (a.in_phase) {
             const int hd = (r.h + dd - 1) / dd, wd = (r.w + dd - 1) / dd;
             const int py = r.y0 % dd, px = r.x0 % dd;
@@ -910,8 +911,8 @@ hipError_t launch_ct(const ConvArgs &a, const Geometry &g, int grid, hipStream_t
 template <int C, int P>
 hipError_t launch_cp(const ConvArgs &a, const Geometry &g, int grid, hipStream_t s)
 {
-    if (g.tr == 4) return launch_ct<C, P, 4>(a, g, grid, s);
-    if (g.tr == 8) return launch_ct<C, P, 8>(a, g, grid, s);
+    if (a.tr == 4) return launch_ct<C, P, 4>(a, g, grid, s);
+    if (a.tr == 8) return launch_ct<C, P, 8>(a, g, grid, s);
     return hipErrorInvalidValue;
 }
 

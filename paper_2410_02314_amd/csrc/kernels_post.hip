@@ -458,7 +458,7 @@ __device__ int64_t enum_quantity(int q, int h, int w, const EnumArgs &e)
     }
     if (q == 2) return h;
     if (q == 3) return (int64_t)h * ((w + 63) / 64);
-    return conv_tiles(h, w, e.dil[q - 4], e.tr, e.tc);
+    return conv_tiles(h, w, e.dil[q - 4], e.tr[q - 4], e.tc);
 }
 
 __global__ void __launch_bounds__(1024)
@@ -557,9 +557,9 @@ k_active_lists(const FrameDesc *__restrict__ fdp, Geometry geo, const uint8_t *_
     if (t < end) {
         const int d = dil[b];
         int Y0, X0;
-        decode_tile(fd.h, fd.w, l, d, geo.tr, geo.tc, b == geo.minor_blk, Y0, X0);
+        decode_tile(fd.h, fd.w, l, d, geo.trb[b], geo.tc, b == geo.minor_blk, geo.strip, Y0, X0);
         if (Y0 < fd.h && X0 < fd.w) {
-            const int y1 = min(fd.h - 1, Y0 + d * (geo.tr - 1)), x1 = min(fd.w - 1, X0 + d * (geo.tc - 1));
+            const int y1 = min(fd.h - 1, Y0 + d * (geo.trb[b] - 1)), x1 = min(fd.w - 1, X0 + d * (geo.tc - 1));
             for (int k = 0; k < 2; ++k) act[k] = near_kept(keep, fd, Y0, y1, X0, x1, radius[2 * b + k]);
         }
     }
