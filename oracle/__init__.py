@@ -65,6 +65,8 @@ def _L():
         _lib.or_store_fp8_groups.argtypes = [P, i, l]
         _lib.or_quant_weights_fp8.argtypes = [P, i, l]
         _lib.or_split_bf16.argtypes = [P, P, l]
+        _lib.or_dense_maps.restype = i
+        _lib.or_dense_maps.argtypes = [P, i, i, d, d, d, P, i, i, i, i, P, i, P]
         _lib.or_preprocess.argtypes = [P, l, d, d, d, P]
         _lib.or_conv3x3.argtypes = [P, i, i, i, P, P, i, i, P]
         _lib.or_net_maps.restype = i
@@ -197,6 +199,17 @@ def net_maps(frame: np.ndarray, spec, weights: Dict[str, np.ndarray], gain=0.5,
     dil = np.asarray(spec.dilations, np.int32)
     nh = spec.head_outputs
     maps = np.empty((nh, h, w), np.float64)
+    if hasattr(spec, "growth"):
+        # the dense-connection network (FP64 only, scalar camera model)
+        if quant != "exact" and QUANT[quant] != 0:
+            raise ValueError("the dense-connection network has no emulation modes")
+        if _is_map(gain) or _is_map(offset):
+            raise ValueError("camera maps are not supported for the dense-connection network")
+        rc = _L().or_dense_maps(_p(F), h, w, gain, offset, spec.in_scale, _p(params), spec.C, len(spec.dilations),
+                                spec.layers, spec.growth, _p(dil), nh, _p(maps))
+        if rc != 0:
+            raise RuntimeError("oracle net failed")
+        return maps
     if _is_map(gain) or _is_map(offset):
         g, o = _camera_maps(gain, offset, (h, w))
         rc = _L().or_net_maps_cam(_p(F), h, w, _p(g), _p(o), spec.in_scale, _p(params), spec.C,

@@ -372,6 +372,97 @@ int or_net_maps_cam(const uint16_t *F, int h, int w, const double *gain, const d
     return rc;
 }
 
+/* ------------------------------------------------ dense-connection network */
+
+/* The dense-connection dilated network (paper Sec. 3.2 / 3.2.1: dense
+ * connections let each layer use the outputs of all layers before it in its
+ * block; Sec. 4.1.2: dilations 2, 4, 8, 16), on the preprocessed input x:
+ *   a      = ReLU(conv_1(x; stem))                                   1 -> C
+ *   per block k at dilation d_k, on the block input a (C channels):
+ *     cat  = [a]
+ *     for i in 0 .. L-1:  y_i = ReLU(conv_dk(cat; W_ki, b_ki)),      cat = [cat, y_i]
+ *                         (C + i G -> G channels)
+ *     a    = ReLU(W_kt . cat + b_kt)                                  1x1, C + L G -> C
+ *   maps   = head(a), 1x1, C -> nh
+ * Parameters in blob order: stem w [C][1][3][3], b [C]; per block: per layer
+ * w [G][C + i G][3][3], b [G]; transition w [C][C + L G], b [C]; head w
+ * [nh][C], b [nh].  The concatenation is kept planar: channel c of cat is
+ * plane c, so layer i reads planes 0 .. C + i G - 1 and writes the next G. */
+static void pointwise(const double *in, int cin, long hw, const double *W, const double *b, int cout, int relu,
+                      double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int o = 0; o < cout; ++o) {
+        double *y = out + (long)o * hw;
+        for (long p = 0; p < hw; ++p) y[p] = b[o];
+        for (int c = 0; c < cin; ++c) {
+            const double wt = W[(long)o * cin + c];
+            const double *xc = in + (long)c * hw;
+            for (long p = 0; p < hw; ++p) y[p] += wt * xc[p];
+        }
+        if (relu)
+            for (long p = 0; p < hw; ++p) y[p] = y[p] > 0 ? y[p] : 0.0;
+    }
+}
+
+static int dense_maps_from_input(const double *x, int h, int w, const float *params, int C, int nblocks, int L,
+                                 int G, const int *dil, int nh, double *maps)
+{
+    if (h <= 0 || w <= 0 || C <= 0 || G <= 0 || L < 0 || nblocks < 0 || nh <= 0) return OR_ERR;
+    const long hw = (long)h * w;
+    const int CT = C + L * G;
+    double *cat = malloc(sizeof(double) * hw * CT);
+    double *Wd = malloc(sizeof(double) * (long)CT * 9 * (G > C ? G : C));
+    double *bd = malloc(sizeof(double) * (CT > nh ? CT : nh));
+    if (!cat || !Wd || !bd) {
+        free(cat); free(Wd); free(bd);
+        return OR_ERR;
+    }
+    const float *p = params;
+    promote(p, (long)C * 9, Wd); p += (long)C * 9;
+    promote(p, C, bd); p += C;
+    or_conv3x3(x, 1, h, w, Wd, bd, C, 1, cat);
+    for (long k = 0; k < hw * C; ++k) cat[k] = cat[k] > 0 ? cat[k] : 0.0;
+    for (int blk = 0; blk < nblocks; ++blk) {
+        for (int i = 0; i < L; ++i) {
+            const int cin = C + i * G;
+            promote(p, (long)G * cin * 9, Wd); p += (long)G * cin * 9;
+            promote(p, G, bd); p += G;
+            double *y = cat + (long)cin * hw;
+            or_conv3x3(cat, cin, h, w, Wd, bd, G, dil[blk], y);
+            for (long k = 0; k < hw * G; ++k) y[k] = y[k] > 0 ? y[k] : 0.0;
+        }
+        promote(p, (long)C * CT, Wd); p += (long)C * CT;
+        promote(p, C, bd); p += C;
+        /* the transition's output becomes the next block's input (planes 0 .. C-1) */
+        double *t = malloc(sizeof(double) * hw * C);
+        if (!t) {
+            free(cat); free(Wd); free(bd);
+            return OR_ERR;
+        }
+        pointwise(cat, CT, hw, Wd, bd, C, 1, t);
+        memcpy(cat, t, sizeof(double) * hw * C);
+        free(t);
+    }
+    promote(p, (long)nh * C, Wd); p += (long)nh * C;
+    promote(p, nh, bd); p += nh;
+    pointwise(cat, C, hw, Wd, bd, nh, 0, maps);
+    free(cat); free(Wd); free(bd);
+    return OR_OK;
+}
+
+int or_dense_maps(const uint16_t *F, int h, int w, double gain, double offset, double in_scale, const float *params,
+                  int C, int nblocks, int L, int G, const int *dil, int nh, double *maps)
+{
+    if (h <= 0 || w <= 0) return OR_ERR;
+    double *x = malloc(sizeof(double) * (long)h * w);
+    if (!x) return OR_ERR;
+    or_preprocess(F, (long)h * w, gain, offset, in_scale, x);
+    int rc = dense_maps_from_input(x, h, w, params, C, nblocks, L, G, dil, nh, maps);
+    free(x);
+    return rc;
+}
+
 /* --------------------------------------------------------------- detection */
 
 /* Pixel (i, j) is detected iff logit > tau and it beats every in-frame

@@ -47,6 +47,7 @@ TAU_LOGIT = math.log(0.3 / 0.7)
 DLW_MAGIC = b"DLW1"
 DLW_VERSION = 1
 DLW_MAX_BLOCKS = 8
+DLD_MAGIC = b"DLD1"          # dense-connection networks
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -329,18 +330,53 @@ class NetSpec:
     head_outputs: int = 5       # 5, or 10 with the uncertainty planes
 
 
+@dataclass(frozen=True)
+class DenseSpec:
+    """Dense-connection dilated network: stem 3x3 (1->C), then one dense block
+    per dilation.  Block k at dilation d: ``layers`` 3x3 convolutions at
+    dilation d, layer i reading the concatenation of the block input (C
+    channels) and the i earlier layers' outputs (``growth`` channels each) and
+    giving ``growth`` channels (+ bias, ReLU); a 1x1 transition over the whole
+    concatenation (C + layers * growth -> C, + bias, ReLU) gives the block's
+    output.  Then the 1x1 head C -> head_outputs."""
+    name: str
+    C: int
+    dilations: Tuple[int, ...]
+    layers: int = 4
+    growth: int = 16
+    in_scale: float = 0.01
+    z_scale: float = 700.0
+    ph_scale: float = 1000.0
+    head_outputs: int = 5
+
+
 NET_A = NetSpec("A", 32, (1, 2, 4))
 NET_B = NetSpec("B", 48, (1, 2, 4, 8, 16))
 # the same networks with the uncertainty head (planes 5-9)
 NET_AU = NetSpec("AU", 32, (1, 2, 4), head_outputs=10)
 NET_BU = NetSpec("BU", 48, (1, 2, 4, 8, 16), head_outputs=10)
-NETS = {"A": NET_A, "B": NET_B, "AU": NET_AU, "BU": NET_BU}
+# the paper's feature extractor as read here: one coarse-grained and three
+# context dense blocks at dilations 2, 4, 8, 16
+NET_D = DenseSpec("D", 32, (2, 4, 8, 16))
+NETS = {"A": NET_A, "B": NET_B, "AU": NET_AU, "BU": NET_BU, "D": NET_D}
 
 
-def tensor_layout(spec: NetSpec) -> List[Tuple[str, Tuple[int, ...]]]:
+def is_dense(spec) -> bool:
+    return isinstance(spec, DenseSpec)
+
+
+def tensor_layout(spec) -> List[Tuple[str, Tuple[int, ...]]]:
     """Names and shapes of the weight tensors, in blob order."""
     C = spec.C
     lay = [("stem.w", (C, 1, 3, 3)), ("stem.b", (C,))]
+    if is_dense(spec):
+        G, L = spec.growth, spec.layers
+        for k in range(len(spec.dilations)):
+            for i in range(L):
+                lay += [(f"blk{k}.l{i}.w", (G, C + i * G, 3, 3)), (f"blk{k}.l{i}.b", (G,))]
+            lay += [(f"blk{k}.t.w", (C, C + L * G)), (f"blk{k}.t.b", (C,))]
+        nh = spec.head_outputs
+        return lay + [("head.w", (nh, C)), ("head.b", (nh,))]
     for k in range(len(spec.dilations)):
         lay += [(f"blk{k}.w1", (C, C, 3, 3)), (f"blk{k}.b1", (C,)),
                 (f"blk{k}.w2", (C, C, 3, 3)), (f"blk{k}.b2", (C,))]
@@ -353,9 +389,13 @@ def param_count(spec: NetSpec) -> int:
     return int(sum(np.prod(s) for _, s in tensor_layout(spec)))
 
 
-def net_flops_per_px(spec: NetSpec) -> int:
+def net_flops_per_px(spec) -> int:
     """Algorithmic FLOP per output pixel (2 per multiply-add; stem + blocks + head)."""
     C, B = spec.C, len(spec.dilations)
+    if is_dense(spec):
+        G, L = spec.growth, spec.layers
+        blk = sum(9 * (C + i * G) * G for i in range(L)) + (C + L * G) * C
+        return 2 * (9 * C + B * blk + spec.head_outputs * C)
     macs = 9 * C + B * 2 * 9 * C * C + spec.head_outputs * C
     return 2 * macs
 
@@ -365,7 +405,9 @@ def block_flops_per_px(spec: NetSpec) -> int:
     return 2 * 9 * spec.C * spec.C
 
 
-def receptive_radius(spec: NetSpec) -> int:
+def receptive_radius(spec) -> int:
+    if is_dense(spec):
+        return 1 + spec.layers * sum(spec.dilations)
     return 1 + 2 * sum(spec.dilations)
 
 
@@ -377,7 +419,7 @@ def he_normal_weights(spec: NetSpec, seed: int, bias_std: float = 0.0) -> Dict[s
     out: Dict[str, np.ndarray] = {}
     for name, shape in tensor_layout(spec):
         if name.endswith(".w"):
-            fan_in = int(np.prod(shape[1:]))
+            fan_in = int(np.prod(shape[1:]))   # (1x1 transitions: their input channels)
             out[name] = (rng.standard_normal(shape) * math.sqrt(2.0 / fan_in)).astype(np.float32)
         elif name.endswith(("w1", "w2")):
             fan_in = int(np.prod(shape[1:]))
@@ -428,7 +470,7 @@ def make_net(spec: NetSpec | str, seed: int, calibrated: bool = True, bias_std: 
     return spec, w
 
 
-def serialize_weights(spec: NetSpec, weights: Dict[str, np.ndarray]) -> bytes:
+def serialize_weights(spec, weights: Dict[str, np.ndarray]) -> bytes:
     """Little-endian ``DLW1`` blob.
 
     Header (64 bytes): magic 'DLW1', u32 version, u32 C, u32 nblocks,
@@ -440,13 +482,21 @@ def serialize_weights(spec: NetSpec, weights: Dict[str, np.ndarray]) -> bytes:
     if nb > DLW_MAX_BLOCKS:
         raise ValueError("too many blocks")
     dil = list(spec.dilations) + [0] * (DLW_MAX_BLOCKS - nb)
+    body = b"".join(np.ascontiguousarray(weights[name], dtype="<f4").tobytes()
+                    for name, _ in tensor_layout(spec))
+    if is_dense(spec):
+        # 'DLD1' (80 bytes): magic, u32 version, u32 C, u32 nblocks, u32 layers,
+        # u32 growth, u32 dilation[8], f32 in_scale, f32 z_scale, f32 ph_scale,
+        # u32 head outputs, 8 zero bytes
+        head = DLD_MAGIC + struct.pack("<IIIII8IfffI8x", 1, spec.C, nb, spec.layers, spec.growth, *dil,
+                                       spec.in_scale, spec.z_scale, spec.ph_scale, spec.head_outputs)
+        assert len(head) == 80
+        return head + body
     # the last header word: 0 for the 5-output head, else the head's outputs
     head = DLW_MAGIC + struct.pack("<III8IfffI", DLW_VERSION, spec.C, nb, *dil,
                                    spec.in_scale, spec.z_scale, spec.ph_scale,
                                    0 if spec.head_outputs == 5 else spec.head_outputs)
     assert len(head) == 64
-    body = b"".join(np.ascontiguousarray(weights[name], dtype="<f4").tobytes()
-                    for name, _ in tensor_layout(spec))
     return head + body
 
 

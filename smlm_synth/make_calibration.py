@@ -19,7 +19,7 @@ sparse emitters with known positions):
 The final features are read through the head itself (five unit rows at a
 time), so only the oracle's own network function is used.
 
-Run:  python -m smlm_synth.make_calibration
+Run:  python -m smlm_synth.make_calibration [net ...]
 """
 from __future__ import annotations
 
@@ -32,7 +32,7 @@ import numpy as np
 import oracle
 import smlm_synth as S
 
-CAL_SEEDS = {"A": 1, "B": 2}
+CAL_SEEDS = {"A": 1, "B": 2, "D": 3}
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "calibration.json")
 
 
@@ -104,9 +104,17 @@ def calibrate(name: str, seed: int) -> dict:
                       "em_above_bg_max": float(np.mean(em_sc > bg_max))}}
 
 
-def main():
+def main(argv=None):
+    """Calibrate every (net, seed), or only the nets named on the command line
+    (the other entries of the existing file are kept)."""
+    import sys
+    names = (argv if argv is not None else sys.argv[1:]) or list(CAL_SEEDS)
     table = {}
-    for name, seed in CAL_SEEDS.items():
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            table = json.load(f)
+    for name in names:
+        seed = CAL_SEEDS[name]
         table[f"{name}:{seed}"] = calibrate(name, seed)
         print(name, seed, json.dumps(table[f"{name}:{seed}"]["stats"]))
     with open(OUT, "w") as f:

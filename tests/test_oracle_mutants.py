@@ -25,6 +25,7 @@ import oracle
 import smlm_synth as S
 from tests import test_oracle_bf16x3 as B3
 from tests import test_oracle_camera as CAM
+from tests import test_oracle_dense as DN
 from tests import test_oracle_fp8 as FP8
 from tests import test_oracle_pins as PINS
 from tests import test_oracle_uncertainty as UNC
@@ -98,6 +99,14 @@ MUTANTS = [
      "    if (quant == 3) return (double)(float)v;   /* split BF16 stores FP32 */",
      "    if (quant == 3) return v;",
      [(B3.test_bf16x3_emulation_matches_torch_composition, (32, (1, 2, 4)))]),
+    ("dense layer reads one growth group too few",
+     "            const int cin = C + i * G;",
+     "            const int cin = C + (i > 0 ? i - 1 : 0) * G;",
+     [(DN.test_dense_net_matches_torch_composition, (S.NET_D,))]),
+    ("dense transition without ReLU",
+     "        pointwise(cat, CT, hw, Wd, bd, C, 1, t);",
+     "        pointwise(cat, CT, hw, Wd, bd, C, 0, t);",
+     [(DN.test_dense_net_matches_torch_composition, (S.NET_D,))]),
     ("gate pool takes the last maximum",
      "if (h2[(long)c * hw + k] > h2[(long)c * hw + a]) a = k;",
      "if (h2[(long)c * hw + k] >= h2[(long)c * hw + a]) a = k;",
