@@ -83,9 +83,10 @@ def main():
     ap.add_argument("--sparse-layout", default="iid", choices=["iid", "cell"],
                     help="sparse workload: empty 256^2 tiles chosen independently (iid) or around one "
                          "compact occupied region (cell)")
-    ap.add_argument("--net", default="B", choices=["B", "BU"],
-                    help="full workload: net B with the 5-output head, or BU, the same net with the "
-                         "10-output head (per-pixel uncertainties and background)")
+    ap.add_argument("--net", default="B", choices=["B", "BU", "D"],
+                    help="full workload: net B with the 5-output head, BU, the same net with the "
+                         "10-output head (per-pixel uncertainties and background), or D, the "
+                         "dense-connection network (FP32, scalar camera model)")
     ap.add_argument("--camera", default="scmos", choices=["scmos", "scalar"],
                     help="full and pipeline workloads: frames from a seeded sCMOS sensor whose per-pixel gain "
                          "and offset maps the net is given (scmos), or the scalar camera model (scalar)")
@@ -108,8 +109,14 @@ def main():
         run_workload(args)
         return
 
+    if args.net == "D":
+        # the dense kernels run FP32 with the scalar camera model only
+        if args.precision != "fp32" or args.camera != "scalar":
+            print("--net D runs with --precision fp32 --camera scalar", file=sys.stderr)
+            sys.exit(2)
+        args.forms = ""
     # inputs first, before anything touches the GPU (workers are forked)
-    spec, w = S.make_net(args.net, 2)
+    spec, w = S.make_net(args.net, 3 if args.net == "D" else 2)
     n, side = args.frames, args.size
     t0 = time.time()
     cam = S.scmos_camera(side, side, 1002) if args.camera == "scmos" else None
@@ -179,7 +186,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
         "data": "synthetic (seeded astigmatic-PSF SMLM frames; random-init calibrated net)",
         "config": {"workload": f"{n} x {side}x{side} uint16 frames, astigmatic 3D PSF, net {args.net} "
-                               f"(C=48, d=1,2,4,8,16, {spec.head_outputs}-output head), {args.precision}",
+                               f"({net_text(spec)}, {spec.head_outputs}-output head), {args.precision}",
                    "frames": n, "height": side, "width": side, "precision": args.precision,
                    "camera": ("sCMOS per-pixel gain/offset maps (sensor seed 1002)" if cam is not None
                               else "scalar gain 0.5, offset 100"),
@@ -196,6 +203,53 @@ def main():
     print(json.dumps(res), flush=True)
     for r in results.values():
         r["net"].close()
+
+
+def net_text(spec):
+    import smlm_synth as S
+    d = ",".join(str(x) for x in spec.dilations)
+    if S.is_dense(spec):
+        return (f"dense blocks: C={spec.C}, {spec.layers} 3x3 layers of growth {spec.growth} + 1x1 transition "
+                f"per block, d={d}")
+    return f"C={spec.C}, d={d}"
+
+
+def dense_roofline(spec, prof, total_px, steps):
+    """Roofline of the dense network's dominant kernel, the 3x3 dense layer
+    (k_dconv, taps 9): layer i of a block reads C + i G channels and writes G,
+    so its FLOP and bytes per pixel grow with i; achieved = the mean
+    algorithmic FLOP of the nblocks x L launches / their mean duration.  The
+    1x1 transitions (k_dconv, taps 1) are reported beside it."""
+    C, G, L, nb = spec.C, spec.growth, spec.layers, len(spec.dilations)
+    cins = [C + i * G for i in range(L)]
+    conv_ms, conv_n = prof["conv"]
+    assert conv_n == nb * L * steps, (conv_n, nb, L, steps)
+    avg_s = conv_ms / conv_n * 1e-3
+    flop_launch = 2.0 * 9 * G * (sum(cins) / L) * total_px
+    bytes_launch = 4.0 * (sum(cins) / L + G) * total_px
+    tflops = flop_launch / avg_s / 1e12
+    roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAKS["fp32"], "unit": "TFLOP/s",
+            "frac": round(tflops / PEAKS["fp32"], 4),
+            "traffic": measured_traffic(dense_traffic_key(spec, total_px), DENSE_SOURCES),
+            "kernel": f"k_dconv fp32 (3x3 dilated dense layer, growth {G} over {cins[0]}..{cins[-1]} input channels; "
+                      f"mean of the {nb * L} launches)",
+            "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_launch": flop_launch,
+            "algorithmic_bytes_per_launch": round(bytes_launch),
+            "hbm_gb_s": round(bytes_launch / avg_s / 1e9, 1)}
+    t_ms, t_n = prof["conv_1x1"]
+    if t_n:
+        ts = t_ms / t_n * 1e-3
+        CT = C + L * G
+        tf = 2.0 * CT * C * total_px
+        tb = 4.0 * (CT + C) * total_px
+        roof["transition"] = {"kernel": f"k_dconv fp32 (1x1 transition {CT} -> {C})", "avg_launch_ms": round(ts * 1e3, 3),
+                              "tflop_s": round(tf / ts / 1e12, 2), "mfma_frac": round(tf / ts / 1e12 / PEAKS["fp32"], 4),
+                              "gb_s": round(tb / ts / 1e9, 1), "hbm_frac": round(tb / ts / 1e9 / HBM_PEAK_GBS, 4)}
+    return roof
+
+
+def dense_traffic_key(spec, total_px):
+    return f"k_dconv fp32 taps=9 net {spec.name} {total_px}px"
 
 
 def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
@@ -243,6 +297,35 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
     log(f"[{precision}] stages: " + ", ".join(f"{k} {v[0] / max(1, v[1]):.3f} ms x{v[1]}" for k, v in prof.items() if v[1]))
 
     C = spec.C
+    if S.is_dense(spec):
+        roofline = dense_roofline(spec, prof, total_px, args.steps)
+        pt_bytes = 4 * C                      # the stem writes C channels of each point
+    else:
+        roofline, pt_bytes = conv_roofline(args, precision, spec, prof, total_px)
+    # the bandwidth-bound stages against the HBM peak, from their algorithmic
+    # bytes: the stem reads the uint16 frame (+ the 8-byte camera map per pixel
+    # with sCMOS maps) and writes one stored point per pixel; detection reads
+    # the logit plane and writes one mask bit per pixel
+    bw = {}
+    for stage, nbytes in (("stem", total_px * (2 + (8 if cam is not None else 0) + pt_bytes)),
+                          ("detect", total_px * (4 + 1 / 8))):
+        if prof.get(stage, (0, 0))[1]:
+            t = prof[stage][0] / prof[stage][1] * 1e-3
+            bw[stage] = {"gb_s": round(nbytes / t / 1e9, 1), "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 3),
+                         "algorithmic_bytes": round(nbytes), "avg_ms": round(t * 1e3, 3)}
+    recs = dl.emitters_from_device(d_out, min(int(counts[n]), cap))
+    return {"value": round(value, 2), "ms_per_step": round(ms_step, 3),
+            "ms_per_step_median": round(float(np.median(step_ms)), 3), "ms_per_step_min": round(min(step_ms), 3),
+            "roofline": roofline,
+            "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]},
+            "bandwidth_kernels": bw,
+            "emitters_per_step": int(counts[n]), "net": net, "records": recs}
+
+
+def conv_roofline(args, precision, spec, prof, total_px):
+    """Roofline of the residual network's dominant kernel, the 3x3 block
+    convolution (mean of its non-head launches)."""
+    n, side, C = args.frames, args.size, spec.C
     conv_ms, conv_n = prof["conv"]
     avg_s = conv_ms / conv_n * 1e-3
     flop_launch = 2.0 * 9 * C * C * total_px
@@ -267,24 +350,7 @@ def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
                      "kernel": f"k_conv {precision} (3x3 dilated conv, C={C}; mean of the {n_conv} non-head launches)",
                      "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_launch": flop_launch,
                      "algorithmic_bytes_per_launch": round(bytes_launch)})
-    # the bandwidth-bound stages against the HBM peak, from their algorithmic
-    # bytes: the stem reads the uint16 frame (+ the 8-byte camera map per pixel
-    # with sCMOS maps) and writes one stored point per pixel; detection reads
-    # the logit plane and writes one mask bit per pixel
-    bw = {}
-    for stage, nbytes in (("stem", total_px * (2 + (8 if cam is not None else 0) + pt_bytes)),
-                          ("detect", total_px * (4 + 1 / 8))):
-        if prof.get(stage, (0, 0))[1]:
-            t = prof[stage][0] / prof[stage][1] * 1e-3
-            bw[stage] = {"gb_s": round(nbytes / t / 1e9, 1), "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 3),
-                         "algorithmic_bytes": round(nbytes), "avg_ms": round(t * 1e3, 3)}
-    recs = dl.emitters_from_device(d_out, min(int(counts[n]), cap))
-    return {"value": round(value, 2), "ms_per_step": round(ms_step, 3),
-            "ms_per_step_median": round(float(np.median(step_ms)), 3), "ms_per_step_min": round(min(step_ms), 3),
-            "roofline": roofline,
-            "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]},
-            "bandwidth_kernels": bw,
-            "emitters_per_step": int(counts[n]), "net": net, "records": recs}
+    return roofline, pt_bytes
 
 
 RECALL_TARGET = 0.995
@@ -351,17 +417,21 @@ def map_errors_on_sample(net, d_frames, ref, torch, dev):
             "map_region": f"{e}x{e}"}
 
 
-def conv_source_sha256():
-    """Hash of the sources that decide the conv kernel's memory traffic (the
+CONV_SOURCES = ("kernels_conv.hip", "dloc_internal.h")
+DENSE_SOURCES = ("kernels_dense.hip", "dloc_internal.h")
+
+
+def conv_source_sha256(sources=CONV_SOURCES):
+    """Hash of the sources that decide a conv kernel's memory traffic (the
     kernel and the tile order / layouts it includes)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels_conv.hip", "dloc_internal.h"):
+    for name in sources:
         h.update(open(os.path.join(ROOT, "paper_2410_02314_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic(key):
+def measured_traffic(key, sources=CONV_SOURCES):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (scaled by a plain copy kernel), or None if
     there is no record for this kernel/workload or the kernel source changed
@@ -369,7 +439,7 @@ def measured_traffic(key):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path)).get(key)
-        sha = conv_source_sha256()
+        sha = conv_source_sha256(sources)
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_source_sha256") != sha:
@@ -385,6 +455,7 @@ def cpu_baseline(args, spec, w, frames, net, dev, recs, cam=None):
     detections, whose neighbours must be exact too)."""
     import torch
     import oracle
+    import smlm_synth as S
     from tests.parity import exempt_mask, map_rel_err
     s = min(args.cpu_sample, args.size)
     crop = np.ascontiguousarray(frames[0, :s, :s])
@@ -393,7 +464,7 @@ def cpu_baseline(args, spec, w, frames, net, dev, recs, cam=None):
     rec, ref_maps = oracle.localize(crop[None], spec, w, return_maps=True, **camera)
     dt = time.perf_counter() - t0
     whole = s == args.size
-    R = 1 + 2 * sum(spec.dilations)
+    R = S.receptive_radius(spec)
     e = s if whole else s - R                 # exact maps on [0, e)^2
     lim = e if whole else e - 1               # exact detections on [0, lim)^2
     maps = torch.empty((1, net.head_outputs, args.size, args.size), dtype=torch.float32, device=dev)

@@ -130,10 +130,11 @@ typedef struct {
     int32_t C, nblocks;
     int32_t dilation[8];
     float in_scale, z_scale, ph_scale;
-    int32_t receptive_radius;   /* 1 + 2 * sum(dilation): halo a tile needs     */
-    int64_t nparams;            /* FP32 values after the 64-byte header          */
+    int32_t receptive_radius;   /* 1 + 2 * sum(dilation) (DLD1: 1 + L * sum(dilation)): halo a tile needs */
+    int64_t nparams;            /* FP32 values after the header                  */
     int32_t head_outputs;       /* 5, or 10 with the uncertainty planes          */
-    int32_t reserved_;
+    int16_t dense_layers;       /* DLD1: 3x3 layers per block; 0 for DLW1        */
+    int16_t dense_growth;       /* DLD1: channels each layer adds; 0 for DLW1    */
 } dl_net_info;
 
 /* Library ABI version (DL_ABI_VERSION). */
@@ -153,6 +154,20 @@ int dl_default_config(dl_config *cfg);
  * a = ReLU(conv_1(x)); per block with dilation d: t = ReLU(conv_d(a)),
  * a = ReLU(a + conv_d(t)); maps = head(a).  Supported: C in {16, 32, 48, 64},
  * 1 <= nblocks <= 8, dilations 1..64.
+ * Or from a "DLD1" blob, the dense-connection network (Sec. 3.2: within a
+ * block every layer takes the outputs of all layers before it; Sec. 3.2.1 /
+ * Sec. 4.1.2: one dilation per block):
+ *   header (80 B): char magic[4] = "DLD1"; u32 version = 1; u32 C; u32 nblocks;
+ *   u32 L (3x3 layers per block); u32 G (growth); u32 dilation[8]; f32 in_scale;
+ *   f32 z_scale; f32 ph_scale; u32 nh (5 or 10); 8 bytes ignored;
+ *   then FP32 tensors: stem.w [C][1][3][3], stem.b [C]; for each block, for
+ *   i = 0 .. L-1: w [G][C + i G][3][3], b [G]; then the transition w [C][C + L G],
+ *   b [C]; head.w [nh][C], head.b [nh].
+ * Network: a = ReLU(conv_1(x)); per block with dilation d, cat = [a] and for
+ * each layer cat = [cat, ReLU(conv_d(cat))], then a = ReLU(1x1(cat));
+ * maps = head(a).  Supported: C and G in {16, 32}, 1 <= L <= 8, 1 <= nblocks
+ * <= 7, dilations 1..64; FP32 only (other precisions, the tile gate, camera
+ * maps, the autotuner and dl_debug_conv_layer are DL_ERR_UNSUPPORTED).
  * The blob is copied; the caller keeps ownership.  cfg may be NULL (defaults).
  * *out receives a handle the caller frees with dl_destroy_net.
  * Errors: DL_ERR_INVALID_ARG, DL_ERR_BAD_WEIGHTS, DL_ERR_UNSUPPORTED,
@@ -465,11 +480,14 @@ int dl_autotune_ex(dl_net *net, const uint16_t *d_frames, int n, int h, int w, v
 enum {
     DL_STAGE_STEM = 0,       /* preprocessing + stem convolution              */
     DL_STAGE_CONV = 1,       /* 3x3 block convolutions without the head       */
+                             /* (DLD1 networks: the dense layers)             */
     DL_STAGE_CONV_HEAD = 2,  /* last block convolution with the fused head    */
+                             /* (DLD1 networks: the 1x1 head)                 */
     DL_STAGE_DETECT = 3,     /* threshold + 3x3 local maximum, masks + counts */
     DL_STAGE_SCAN = 4,       /* row offsets and per-frame counts              */
     DL_STAGE_EMIT = 5,       /* ordered emitter records                       */
     DL_STAGE_GATE = 6,       /* tile gate inference and tile selection        */
+    DL_STAGE_CONV_1X1 = 7,   /* DLD1 networks: the blocks' 1x1 transitions    */
     DL_NSTAGES = 8
 };
 int dl_profile_enable(dl_net *net, int on);

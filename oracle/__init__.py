@@ -230,12 +230,15 @@ def net_maps_window(frame: np.ndarray, spec, weights, y0: int, x0: int, hh: int,
                     gain=0.5, offset=100.0, quant="exact", margin: Optional[int] = None) -> np.ndarray:
     """Exact maps of the output window [y0, y0+hh) x [x0, x0+ww) of a large frame.
 
-    The net reads at most ``R = 1 + 2 * sum(dilations)`` pixels away, so running
-    it on the frame cropped to the window plus an R-pixel margin gives exact
-    values inside the window (the crop edge coincides with the frame edge where
-    the margin is clipped, and is at least R away elsewhere)."""
+    The net reads at most ``R = 1 + 2 * sum(dilations)`` pixels away (two
+    convolutions per residual block; ``1 + L * sum(dilations)`` for the
+    dense-connection network, L convolutions per block), so running it on the
+    frame cropped to the window plus an R-pixel margin gives exact values
+    inside the window (the crop edge coincides with the frame edge where the
+    margin is clipped, and is at least R away elsewhere)."""
     H, W = frame.shape
-    R = 1 + 2 * sum(spec.dilations) if margin is None else margin
+    per_block = spec.layers if hasattr(spec, "growth") else 2
+    R = 1 + per_block * sum(spec.dilations) if margin is None else margin
     cy0, cx0 = max(0, y0 - R), max(0, x0 - R)
     cy1, cx1 = min(H, y0 + hh + R), min(W, x0 + ww + R)
     crop = frame[cy0:cy1, cx0:cx1]

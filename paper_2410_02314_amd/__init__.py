@@ -31,7 +31,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
 DL_FLAG_GATE = 1
 NOALLOC_SCRATCH_BYTES = 64 << 20      # DL_NOALLOC_SCRATCH_BYTES
 NOALLOC_MAX_FRAMES = 64               # DL_NOALLOC_MAX_FRAMES
-STAGES = ("stem", "conv", "conv_head", "detect", "scan", "emit", "gate")
+STAGES = ("stem", "conv", "conv_head", "detect", "scan", "emit", "gate", "conv_1x1")
 NSTAGES = 8
 
 EMITTER_DTYPE = np.dtype([("frame", "<i4"), ("row", "<i4"), ("col", "<i4"), ("x_px", "<f4"),
@@ -59,7 +59,8 @@ class DLNetInfo(ctypes.Structure):
     _fields_ = [("C", ctypes.c_int32), ("nblocks", ctypes.c_int32), ("dilation", ctypes.c_int32 * 8),
                 ("in_scale", ctypes.c_float), ("z_scale", ctypes.c_float), ("ph_scale", ctypes.c_float),
                 ("receptive_radius", ctypes.c_int32), ("nparams", ctypes.c_int64),
-                ("head_outputs", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("head_outputs", ctypes.c_int32), ("dense_layers", ctypes.c_int16),
+                ("dense_growth", ctypes.c_int16)]
 
 
 class DLTuneResult(ctypes.Structure):
@@ -223,13 +224,14 @@ def _stream(stream) -> Optional[int]:
 
 
 def inspect_weights(weights: bytes) -> dict:
-    """Validate a DLW1 blob on the host and describe the network (no GPU needed)."""
+    """Validate a DLW1 or DLD1 blob on the host and describe the network (no GPU needed)."""
     info = DLNetInfo()
     buf = ctypes.create_string_buffer(bytes(weights), len(weights))
     _check(_lib.dl_inspect_weights(buf, len(weights), ctypes.byref(info)))
     return {"C": info.C, "nblocks": info.nblocks, "dilations": tuple(info.dilation[:info.nblocks]),
             "in_scale": info.in_scale, "z_scale": info.z_scale, "ph_scale": info.ph_scale,
-            "receptive_radius": info.receptive_radius, "nparams": info.nparams, "head_outputs": info.head_outputs}
+            "receptive_radius": info.receptive_radius, "nparams": info.nparams, "head_outputs": info.head_outputs,
+            "dense_layers": info.dense_layers, "dense_growth": info.dense_growth}
 
 
 def create_net(weights: bytes, **cfg) -> "Net":

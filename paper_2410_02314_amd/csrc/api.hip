@@ -46,6 +46,16 @@ size_t param_count(int C, int nb, int nh)
     return (size_t)C * 9 + C + (size_t)nb * 2 * ((size_t)C * C * 9 + C) + (size_t)nh * C + nh;
 }
 
+// dense-connection network: stem, per block L layers (G x (C + i G) x 3 x 3 + G)
+// and a transition (C x (C + L G) + C), head
+size_t dense_param_count(int C, int nb, int L, int G, int nh)
+{
+    size_t blk = 0;
+    for (int i = 0; i < L; ++i) blk += (size_t)G * (C + i * G) * 9 + G;
+    blk += (size_t)C * (C + L * G) + C;
+    return (size_t)C * 9 + C + (size_t)nb * blk + (size_t)nh * C + nh;
+}
+
 }  // namespace
 
 struct dl_net {
@@ -126,6 +136,14 @@ struct dl_net {
     // when set, overrides the rows of every block
     int tune_rows[MAXBLK] = {0};
     uint32_t tune_strip = 0;
+
+    // dense-connection networks (DLD1 blobs): layers per block and growth
+    // (0 for the residual network), the packed weights and biases of every
+    // conv in run order ([block][layer 0 .. L-1, transition]) at float
+    // offsets dense_w / dense_b of d_dense
+    int dL = 0, dG = 0;
+    float *d_dense = nullptr;
+    std::vector<size_t> dense_w, dense_b;
 };
 
 namespace {
@@ -192,6 +210,19 @@ int check_config(dl_net *net, const dl_config *c)
     return DL_OK;
 }
 
+// What the dense-connection kernels support of a config: FP32, their fixed
+// tile, no tile gate.
+int check_dense_config(dl_net *net, const dl_config *c)
+{
+    if (c->precision != DL_FP32)
+        return fail(net, DL_ERR_UNSUPPORTED, "the dense-connection network runs in FP32 only");
+    if (c->tile_rows || c->tile_w)
+        return fail(net, DL_ERR_UNSUPPORTED, "the dense-connection kernels have a fixed tile: tile_rows and tile_w must be 0");
+    if (c->flags & DL_FLAG_GATE)
+        return fail(net, DL_ERR_UNSUPPORTED, "the tile gate does not run with the dense-connection network");
+    return DL_OK;
+}
+
 int tile_rows_of(const dl_net *net) { return net->cfg.tile_rows ? net->cfg.tile_rows : 0; }
 
 // The conv tiling of a batch: the form's tile (its default rows in g.tr), each
@@ -199,6 +230,13 @@ int tile_rows_of(const dl_net *net) { return net->cfg.tile_rows ? net->cfg.tile_
 // default) and the strip width of the tile order.
 void set_tiling(const dl_net *net, Geometry &g)
 {
+    if (net->dL) {                      // the dense kernels' fixed tile
+        g.tr = dense_tile_rows();
+        g.tc = dense_tile_cols();
+        for (int b = 0; b < MAXBLK; ++b) g.trb[b] = g.tr;
+        g.strip = 8;
+        return;
+    }
     conv_tile_shape(net->C, net->cfg.precision, tile_rows_of(net), &g.tr, &g.tc);
     for (int b = 0; b < MAXBLK; ++b) {
         const int rows = net->cfg.tile_rows ? net->cfg.tile_rows : b < net->nb ? net->tune_rows[b] : 0;
@@ -213,6 +251,7 @@ void set_tiling(const dl_net *net, Geometry &g)
 // for the first block (the stem writes plain rows) and other dilations.
 int block_layout(const dl_net *net, int b)
 {
+    if (net->dL) return 1;              // dense networks: plain NHWC throughout
     const int d = net->dil[b];
     return b > 0 && d > 1 && (d & (d - 1)) == 0 ? d : 1;
 }
@@ -228,11 +267,17 @@ int64_t frame_act_points(const dl_net *net, int h, int w)
 // the conv kernels address a frame's activations with 32-bit byte offsets
 bool frame_act_fits(const dl_net *net, int h, int w)
 {
+    if (net->dL) return true;           // the dense kernels address with 64-bit offsets
     // FP32 4, BF16 2, FP8 1 byte per value (FP8 scales: 2 bytes per point, also within range)
     const int pr = net->cfg.precision;
     const int64_t esz = pr == DL_FP32 || pr == DL_BF16X3 ? 4 : pr == DL_BF16 ? 2 : 1;
     return frame_act_points(net, h, w) * net->C * esz < ((int64_t)1 << 31);
 }
+
+// Conv tile numberings of a net: one per block, and for dense networks one
+// more (slot nblocks) for the 1x1 transitions, which run at d = 1.
+int tile_slots(const dl_net *net) { return net->dL ? net->nb + 1 : net->nb; }
+int slot_dilation(const dl_net *net, int b) { return b < net->nb ? net->dil[b] : 1; }
 
 // Build the frame descriptors of a uniform batch or a ROI list.
 void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, const uint16_t *const *data,
@@ -258,9 +303,9 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         d.gtx = d.w / GATE_TILE;
         d.gty = d.h / GATE_TILE;
         d.keep_start = g.gate_tiles;
-        for (int b = 0; b < net->nb; ++b) {
+        for (int b = 0; b < tile_slots(net); ++b) {
             d.tile_start[b] = g.tiles[b];
-            const int64_t nt = conv_tiles(d.h, d.w, net->dil[b], g.trb[b], g.tc);
+            const int64_t nt = conv_tiles(d.h, d.w, slot_dilation(net, b), g.trb[b], g.tc);
             g.tiles[b] += nt;
             g.max_frame_tiles = std::max(g.max_frame_tiles, nt);
         }
@@ -272,7 +317,7 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         if (d.w > g.maxw) g.maxw = d.w;
         if (d.h > g.maxh) g.maxh = d.h;
     }
-    for (int b = 0; b < net->nb; ++b) g.max_tiles = std::max(g.max_tiles, g.tiles[b]);
+    for (int b = 0; b < tile_slots(net); ++b) g.max_tiles = std::max(g.max_tiles, g.tiles[b]);
 }
 
 struct Plan {
@@ -291,14 +336,16 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
 {
     // bytes per activation point: FP32 / BF16 values, or FP8 codes plus two
     // group scale bytes (the scales follow all codes of the buffer)
+    // (dense networks: FP32 concatenations of C + L G channels, two buffers)
     const int prec = net->cfg.precision;
-    const size_t pt_bytes = prec == DL_FP32 || prec == DL_BF16X3 ? 4 * (size_t)net->C
+    const size_t pt_bytes = net->dL                               ? 4 * (size_t)(net->C + net->dL * net->dG)
+                            : prec == DL_FP32 || prec == DL_BF16X3 ? 4 * (size_t)net->C
                             : prec == DL_BF16                     ? 2 * (size_t)net->C
                                                                   : net->C + 2;
     Plan p;
     size_t o = 0;
     p.act0 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
-    p.act1 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
+    p.act1 = o; if (!net->dL) o = align_up(o + (size_t)g.total_act * pt_bytes);
     p.act2 = o; o = align_up(o + (size_t)g.total_act * pt_bytes);
     p.maps = o; if (!ext_maps) o = align_up(o + (size_t)g.total_px * net->nh * 4);
     p.mask = o; o = align_up(o + (size_t)g.total_words * 8);
@@ -404,9 +451,43 @@ int upload_desc(dl_net *net, const std::vector<FrameDesc> &fd, hipStream_t s, Fr
     return slot;
 }
 
+// Dense networks: every conv's weights in the k_dconv layout and its bias,
+// in run order, in one device buffer (FP32; packed once).
+int pack_dense(dl_net *net)
+{
+    const int C = net->C, L = net->dL, G = net->dG, CT = C + L * G;
+    std::vector<float> host;
+    net->dense_w.clear();
+    net->dense_b.clear();
+    const float *p = net->params.data() + (size_t)C * 9 + C;
+    auto put = [&](int cout, int cin, int taps) {
+        const size_t nw = (size_t)cout * cin * taps;
+        const size_t ow = (host.size() + 63) / 64 * 64;
+        host.resize(ow + nw);
+        pack_dense_weights(cout, cin, taps, p, host.data() + ow);
+        p += nw;
+        const size_t ob = (host.size() + 63) / 64 * 64;
+        host.resize(ob + cout);
+        std::memcpy(host.data() + ob, p, sizeof(float) * cout);
+        p += cout;
+        net->dense_w.push_back(ow);
+        net->dense_b.push_back(ob);
+    };
+    for (int b = 0; b < net->nb; ++b) {
+        for (int i = 0; i < L; ++i) put(G, C + i * G, 9);
+        put(C, CT, 1);
+    }
+    HIPCHK(net, hipMalloc(&net->d_dense, host.size() * sizeof(float)));
+    HIPCHK(net, hipMemcpy(net->d_dense, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
+    net->packed_precision = DL_FP32;
+    ++net->packed_gen;
+    return DL_OK;
+}
+
 int ensure_packed(dl_net *net)
 {
     if (net->packed_precision == net->cfg.precision) return DL_OK;
+    if (net->dL) return pack_dense(net);
     const int C = net->C;
     const size_t per = conv_packed_bytes(C, net->cfg.precision);
     const size_t stride = align_up(per);
@@ -490,9 +571,49 @@ int run_gate(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     return DL_OK;
 }
 
+// Dense networks: stem into channels 0 .. C-1 of buffer A; per block, each
+// layer appends its G channels to A, the transition writes the next block's
+// input into B (channels 0 .. C-1), and A and B swap; the head reads A.
+int run_dense(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, float *maps, hipStream_t s)
+{
+    const int C = net->C, L = net->dL, G = net->dG, CT = C + L * G;
+    float *A = reinterpret_cast<float *>(p.ws + p.act0), *B = reinterpret_cast<float *>(p.ws + p.act2);
+    {
+        StageTimer t(net, DL_STAGE_STEM, s);
+        HIPCHK(net, launch_dstem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset,
+                                 net->cfg.gain * in_scale_of(net), A, CT, s));
+    }
+    size_t k = 0;                       // conv index in run order
+    for (int b = 0; b < net->nb; ++b) {
+        for (int i = 0; i <= L; ++i, ++k) {
+            const bool tr = i == L;
+            DenseConvArgs a{};
+            a.in = A;
+            a.csi = CT;
+            a.cin = tr ? CT : C + i * G;
+            a.out = tr ? B : A;
+            a.cso = CT;
+            a.co = tr ? 0 : C + i * G;
+            a.w = net->d_dense + net->dense_w[k];
+            a.bias = net->d_dense + net->dense_b[k];
+            a.fd = d_fd;
+            a.d = tr ? 1 : net->dil[b];
+            a.blk = tr ? net->nb : b;
+            a.relu = 1;
+            StageTimer t(net, tr ? DL_STAGE_CONV_1X1 : DL_STAGE_CONV, s);
+            HIPCHK(net, launch_dconv(tr ? C / 16 : G / 16, tr ? 1 : 9, a, g, net->ncu, s));
+        }
+        std::swap(A, B);
+    }
+    StageTimer t(net, DL_STAGE_CONV_HEAD, s);
+    HIPCHK(net, launch_dhead(C, d_fd, g, A, CT, net->d_head, net->nh, maps, s));
+    return DL_OK;
+}
+
 // Run stem + blocks (+ fused head into maps).
 int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, float *maps, hipStream_t s)
 {
+    if (net->dL) return run_dense(net, d_fd, g, p, maps, s);
     const int C = net->C;
     void *a0 = p.ws + p.act0;
     void *a1 = p.ws + p.act1;
@@ -784,12 +905,12 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
             // the ROI list of this replay: pinned slot -> device, then the
             // descriptors and frame counts built on the device
             EnumArgs ea{};
-            ea.nb = net->nb;
+            ea.nb = tile_slots(net);
             for (int b = 0; b < MAXBLK; ++b) ea.tr[b] = g.trb[b];
             ea.tc = g.tc;
             ea.layouts[ea.nl++] = 1;
+            for (int b = 0; b < ea.nb; ++b) ea.dil[b] = slot_dilation(net, b);
             for (int b = 0; b < net->nb; ++b) {
-                ea.dil[b] = net->dil[b];
                 const int l = block_layout(net, b);
                 bool seen = false;
                 for (int i = 0; i < ea.nl; ++i) seen |= ea.layouts[i] == l;
@@ -887,12 +1008,62 @@ int dl_default_config(dl_config *cfg)
 
 const char *dl_last_error(const dl_net *net) { return net ? net->err.c_str() : g_err.c_str(); }
 
+// "DLD1": the dense-connection network (header of 80 bytes, see dl_create_net)
+static int parse_dense(const unsigned char *b, size_t nbytes, dl_net_info *info, std::vector<float> *params)
+{
+    if (nbytes < 80) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "weights blob of %zu bytes is shorter than its header", nbytes);
+    uint32_t hdr[13];
+    std::memcpy(hdr, b + 4, sizeof hdr);
+    const uint32_t version = hdr[0], C = hdr[1], nb = hdr[2], L = hdr[3], G = hdr[4];
+    float sc[3];
+    std::memcpy(sc, b + 56, sizeof sc);
+    uint32_t nh;
+    std::memcpy(&nh, b + 68, 4);
+    if (version != 1) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "unsupported weights version %u", version);
+    if (nh != 5 && nh != 10) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "head outputs %u: 5 or 10 supported", nh);
+    if (nb < 1 || nb > MAXBLK - 1) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "nblocks %u outside 1..%d", nb, MAXBLK - 1);
+    if (L < 1 || L > 8) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "layers per block %u outside 1..8", L);
+    if (!(C == 16 || C == 32)) return fail(nullptr, DL_ERR_UNSUPPORTED, "dense network with C = %u (16 or 32)", C);
+    if (!(G == 16 || G == 32)) return fail(nullptr, DL_ERR_UNSUPPORTED, "dense network with growth %u (16 or 32)", G);
+    for (uint32_t k = 0; k < nb; ++k)
+        if (hdr[5 + k] < 1 || hdr[5 + k] > 64) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "dilation %u of block %u outside 1..64", hdr[5 + k], k);
+    if (!finite_all(sc, 3) || !(sc[0] > 0.f)) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "bad in_scale/z_scale/ph_scale");
+    const size_t np = dense_param_count((int)C, (int)nb, (int)L, (int)G, (int)nh);
+    if (nbytes != 80 + np * 4)
+        return fail(nullptr, DL_ERR_BAD_WEIGHTS, "blob is %zu bytes, expected %zu for a dense network with C=%u, %u "
+                    "blocks of %u layers, growth %u", nbytes, 80 + np * 4, C, nb, L, G);
+    std::vector<float> tmp(np);
+    std::memcpy(tmp.data(), b + 80, np * 4);
+    if (!finite_all(tmp.data(), np)) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "weights contain NaN or Inf");
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->C = (int32_t)C;
+        info->nblocks = (int32_t)nb;
+        int R = 1;
+        for (uint32_t k = 0; k < nb; ++k) {
+            info->dilation[k] = (int32_t)hdr[5 + k];
+            R += (int)L * (int)hdr[5 + k];
+        }
+        info->in_scale = sc[0];
+        info->z_scale = sc[1];
+        info->ph_scale = sc[2];
+        info->nparams = (int64_t)np;
+        info->head_outputs = (int32_t)nh;
+        info->receptive_radius = R;
+        info->dense_layers = (int16_t)L;
+        info->dense_growth = (int16_t)G;
+    }
+    if (params) *params = std::move(tmp);
+    return DL_OK;
+}
+
 static int parse_weights(const void *weights, size_t nbytes, dl_net_info *info, std::vector<float> *params)
 {
     if (!weights) return fail(nullptr, DL_ERR_INVALID_ARG, "weights is NULL");
-    if (nbytes < 64) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "weights blob of %zu bytes is shorter than its header", nbytes);
     const unsigned char *b = static_cast<const unsigned char *>(weights);
-    if (std::memcmp(b, "DLW1", 4) != 0) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "bad magic (expected DLW1)");
+    if (nbytes >= 4 && std::memcmp(b, "DLD1", 4) == 0) return parse_dense(b, nbytes, info, params);
+    if (nbytes < 64) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "weights blob of %zu bytes is shorter than its header", nbytes);
+    if (std::memcmp(b, "DLW1", 4) != 0) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "bad magic (expected DLW1 or DLD1)");
     // header: magic, u32 version, u32 C, u32 nblocks, u32 dilation[8], f32 in_scale,
     // f32 z_scale, f32 ph_scale, u32 head outputs (0 = 5)
     uint32_t hdr[11];
@@ -956,7 +1127,9 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     if ((rc = parse_weights(weights, nbytes, &info, &params))) return rc;
     if (c.max_sigma_px > 0.f && info.head_outputs != 10)
         return fail(nullptr, DL_ERR_UNSUPPORTED, "max_sigma_px needs a network with the uncertainty head");
-    if (!conv_supported(info.C, c.precision, info.head_outputs))
+    const bool dense = info.dense_layers > 0;
+    if (dense && (rc = check_dense_config(nullptr, &c))) return rc;
+    if (!dense && !conv_supported(info.C, c.precision, info.head_outputs))
         return fail(nullptr, DL_ERR_UNSUPPORTED, "C = %d does not fit the %s conv kernel's LDS", info.C,
                     c.precision == DL_FP32 ? "FP32" : c.precision == DL_BF16 ? "BF16" : c.precision == DL_FP8 ? "FP8"
                                                                                                            : "BF16X3");
@@ -979,6 +1152,8 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     net->z_scale = info.z_scale;
     net->ph_scale = info.ph_scale;
     net->nh = info.head_outputs;
+    net->dL = info.dense_layers;
+    net->dG = info.dense_growth;
     net->params = std::move(params);
 
     auto bail = [&](int code) {
@@ -992,12 +1167,12 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     const float *p = net->params.data();
     const size_t nstem = (size_t)C * 9 + C, nhead = (size_t)net->nh * C + net->nh;
     if (hipMalloc(&net->d_stem, nstem * 4) != hipSuccess || hipMalloc(&net->d_head, nhead * 4) != hipSuccess ||
-        hipMalloc(&net->d_bias, (size_t)nb * 2 * C * 4) != hipSuccess)
+        (!dense && hipMalloc(&net->d_bias, (size_t)nb * 2 * C * 4) != hipSuccess))
         return bail(fail(net, DL_ERR_OOM, "hipMalloc of weights failed"));
     if (hipMemcpy(net->d_stem, p, nstem * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(net->d_head, p + net->params.size() - nhead, nhead * 4, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(net, DL_ERR_DEVICE, "weight upload failed"));
-    {
+    if (!dense) {
         std::vector<float> bias((size_t)nb * 2 * C);
         const float *q = p + nstem;
         for (uint32_t k = 0; k < nb; ++k)
@@ -1058,6 +1233,7 @@ void dl_destroy_net(dl_net *net)
     if (net->d_head) (void)hipFree(net->d_head);
     if (net->d_bias) (void)hipFree(net->d_bias);
     if (net->d_wpk) (void)hipFree(net->d_wpk);
+    if (net->d_dense) (void)hipFree(net->d_dense);
     if (net->d_gate_theta) (void)hipFree(net->d_gate_theta);
     if (net->d_radius) (void)hipFree(net->d_radius);
     if (net->d_dil) (void)hipFree(net->d_dil);
@@ -1093,7 +1269,8 @@ int dl_set_config(dl_net *net, const dl_config *cfg)
     if (cfg->device != net->cfg.device) return fail(net, DL_ERR_INVALID_ARG, "device cannot change");
     if (cfg->max_sigma_px > 0.f && net->nh != 10)
         return fail(net, DL_ERR_UNSUPPORTED, "max_sigma_px needs a network with the uncertainty head");
-    if (!conv_supported(net->C, cfg->precision, net->nh))
+    if (net->dL && (rc = check_dense_config(net, cfg))) return rc;
+    if (!net->dL && !conv_supported(net->C, cfg->precision, net->nh))
         return fail(net, DL_ERR_UNSUPPORTED, "C = %d does not fit this form's conv kernel", net->C);
     const float new_scale = cfg->in_scale_override > 0.f ? cfg->in_scale_override : net->in_scale;
     if (net->d_cam && new_scale != in_scale_of(net))
@@ -1116,6 +1293,8 @@ int dl_set_camera_maps(dl_net *net, const float *gain, const float *offset, int 
     if (!gain != !offset) return fail(net, DL_ERR_INVALID_ARG, "give both camera maps or neither");
     if (gain && (h <= 0 || w <= 0 || (int64_t)h * w > ((int64_t)1 << 28)))
         return fail(net, DL_ERR_INVALID_ARG, "camera maps must be h x w with 0 < h * w <= 2^28 (got %d x %d)", h, w);
+    if (gain && net->dL)
+        return fail(net, DL_ERR_UNSUPPORTED, "camera maps do not apply to the dense-connection network");
     int rc;
     if ((rc = set_device(net))) return rc;
     auto clear = [&]() {
@@ -1645,6 +1824,7 @@ int dl_debug_conv_layer(dl_net *net, const float *d_in, const float *d_res, int 
     int rc = check_uniform(net, d_in, n, h, w);
     if (rc) return rc;
     if (!d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL");
+    if (net->dL) return fail(net, DL_ERR_UNSUPPORTED, "dl_debug_conv_layer runs the residual network's layers");
     if (blk < 0 || blk >= net->nb || which < 0 || which > 1) return fail(net, DL_ERR_INVALID_ARG, "bad blk/which");
     if (net->cfg.precision != DL_FP32 && net->cfg.precision != DL_BF16X3)
         return fail(net, DL_ERR_UNSUPPORTED, "debug conv layer takes FP32 tensors; set precision FP32 or BF16X3");
@@ -1777,7 +1957,7 @@ int dl_graph_create_rois_dynamic(dl_net *net, int max_rois, int max_h, int max_w
     g.total_act = proto.cap_act;
     g.total_rows = proto.cap_rows;
     g.total_words = proto.cap_words;
-    for (int b = 0; b < net->nb; ++b) g.tiles[b] = (int64_t)1 << 40;   // persistent grids: the full chip
+    for (int b = 0; b < tile_slots(net); ++b) g.tiles[b] = (int64_t)1 << 40;   // persistent grids: the full chip
     g.max_tiles = 0;
     g.maxh = max_h;
     g.maxw = max_w;
@@ -1858,6 +2038,7 @@ int dl_autotune(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void
     int rc = check_uniform(net, d_frames, n, h, w);
     if (rc) return rc;
     if (reps <= 0 || reps > 1000) return fail(net, DL_ERR_INVALID_ARG, "reps must lie in 1..1000");
+    if (net->dL) return fail(net, DL_ERR_UNSUPPORTED, "the dense-connection kernels have a fixed tile (nothing to tune)");
     if ((rc = set_device(net))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     static const int cand[DL_TUNE_CANDIDATES] = {8, 4};
@@ -1908,6 +2089,7 @@ int dl_autotune_ex(dl_net *net, const uint16_t *d_frames, int n, int h, int w, v
     if (rc) return rc;
     if (!res) return fail(net, DL_ERR_INVALID_ARG, "res is NULL");
     if (reps <= 0 || reps > 1000) return fail(net, DL_ERR_INVALID_ARG, "reps must lie in 1..1000");
+    if (net->dL) return fail(net, DL_ERR_UNSUPPORTED, "the dense-connection kernels have a fixed tile (nothing to tune)");
     if ((rc = set_device(net))) return rc;
     std::memset(res, 0, sizeof *res);
     const std::string key = tune_key(net, n, h, w);

@@ -91,6 +91,46 @@ def test_bad_blobs_are_rejected():
     assert dl.lib().dl_inspect_weights(None, 10, ctypes.byref(dl.DLNetInfo())) == dl.DL_ERR_INVALID_ARG
 
 
+def test_inspect_dense_blob_reads_header():
+    spec, w, b = blob("D", 3)
+    assert b[:4] == b"DLD1" and len(b) == 80 + 4 * S.param_count(spec)
+    info = dl.inspect_weights(b)
+    assert info["C"] == 32 and info["dilations"] == (2, 4, 8, 16) and info["head_outputs"] == 5
+    assert info["dense_layers"] == 4 and info["dense_growth"] == 16
+    assert info["nparams"] == S.param_count(spec) == 142181
+    assert info["receptive_radius"] == S.receptive_radius(spec) == 121
+    assert math.isclose(info["in_scale"], spec.in_scale, rel_tol=1e-7)
+    r = blob("A")[2]
+    assert dl.inspect_weights(r)["dense_layers"] == 0 and dl.inspect_weights(r)["dense_growth"] == 0
+
+
+def test_bad_dense_blobs_are_rejected():
+    """DLD1 header: magic, version @4, C @8, nblocks @12, layers @16, growth @20,
+    dilation[8] @24, in_scale @56, z_scale @60, ph_scale @64, head outputs @68."""
+    spec, w, b = blob("D", 3)
+    assert _code(b) == 0
+    assert _code(b[:-4]) == dl.DL_ERR_BAD_WEIGHTS
+    assert _code(b + b"\0" * 4) == dl.DL_ERR_BAD_WEIGHTS
+    assert _code(b[:70]) == dl.DL_ERR_BAD_WEIGHTS
+    for off, val, code in [(4, 2, dl.DL_ERR_BAD_WEIGHTS),            # version
+                           (8, 48, dl.DL_ERR_UNSUPPORTED),           # C
+                           (12, 0, dl.DL_ERR_BAD_WEIGHTS),           # no blocks
+                           (12, 8, dl.DL_ERR_BAD_WEIGHTS),           # one slot is the transitions'
+                           (16, 0, dl.DL_ERR_BAD_WEIGHTS),           # no layers
+                           (16, 9, dl.DL_ERR_BAD_WEIGHTS),
+                           (20, 24, dl.DL_ERR_UNSUPPORTED),          # growth
+                           (24, 0, dl.DL_ERR_BAD_WEIGHTS),           # dilation 0
+                           (68, 7, dl.DL_ERR_BAD_WEIGHTS),           # head outputs
+                           (16, 3, dl.DL_ERR_BAD_WEIGHTS)]:          # other layer count: wrong length
+        bad = bytearray(b)
+        bad[off:off + 4] = struct.pack("<I", val)
+        assert _code(bad) == code, (off, val)
+    bad = bytearray(b); bad[56:60] = struct.pack("<f", 0.0)
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS
+    bad = bytearray(b); bad[200:204] = struct.pack("<f", float("inf"))
+    assert _code(bad) == dl.DL_ERR_BAD_WEIGHTS
+
+
 def _create(b, **cfg):
     c = dl.make_config(**cfg)
     h = ctypes.c_void_p()
@@ -115,6 +155,16 @@ def test_create_rejects_bad_config_before_device(cfg):
 def test_create_refuses_tile_widths_not_built(prec, tw):
     _, _, b = blob("A")
     assert _create(b, precision=prec, tile_w=tw) == dl.DL_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("cfg", [dict(precision="bf16"), dict(precision="fp8"), dict(precision="bf16x3"),
+                                 dict(tile_rows=8), dict(tile_w=32), dict(flags=1)])
+def test_create_refuses_what_the_dense_kernels_do_not_run(cfg):
+    """FP32 only, their fixed tile, no tile gate: refused before any device call."""
+    _, _, b = blob("D", 3)
+    assert _create(b, **cfg) == dl.DL_ERR_UNSUPPORTED
+    if "tile_w" not in cfg:             # (a width no form is built for is refused earlier)
+        assert "dense" in dl.last_error()
 
 
 def test_create_rejects_bad_blob_and_null_pointers():

@@ -7,7 +7,7 @@
 * The library's host side: every HIP source rebuilt with the sanitizers on its
   host code only (``-Xarch_host`` before each flag; device code is unchanged),
   and ``tests/sanitize/abi_driver.c`` run against it: weights parsing over
-  every truncation of a blob and a bad magic, config refusals before any
+  every truncation of a residual and of a dense-connection blob and a bad magic, config refusals before any
   device call, NULL handles, error text.  No GPU is needed (none is used).
 """
 import concurrent.futures as cf
@@ -75,11 +75,12 @@ def test_abi_host_paths_under_sanitizers(tmp_path):
                            "-fsanitize=" + ",".join(SAN), "-I", os.path.join(ROOT, "include"),
                            os.path.join(HERE, "abi_driver.c"), "-o", str(exe), "-L", str(tmp_path), "-ldloc",
                            f"-Wl,-rpath,{tmp_path}", "-Wl,-rpath,/opt/rocm/lib", f"-Wl,-rpath,{rt}"])
-    spec, w = S.make_net("A", 1)
-    blob = tmp_path / "a.dlw"
-    blob.write_bytes(S.serialize_weights(spec, w))
     # leaks are not checked here: the HIP runtime's own allocations would show
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
-    r = subprocess.run([str(exe), str(blob)], capture_output=True, text=True, env=env, timeout=300)
-    assert r.returncode == 0 and "abi driver ok" in r.stdout, r.stderr[-3000:]
+    for name, seed in [("A", 1), ("D", 3)]:          # a residual (DLW1) and a dense (DLD1) blob
+        spec, w = S.make_net(name, seed)
+        blob = tmp_path / f"{name}.blob"
+        blob.write_bytes(S.serialize_weights(spec, w))
+        r = subprocess.run([str(exe), str(blob)], capture_output=True, text=True, env=env, timeout=300)
+        assert r.returncode == 0 and "abi driver ok" in r.stdout, (name, r.stderr[-3000:])
     shutil.rmtree(tmp_path, ignore_errors=True)
