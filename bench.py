@@ -215,36 +215,47 @@ def net_text(spec):
 
 
 def dense_roofline(spec, prof, total_px, steps):
-    """Roofline of the dense network's dominant kernel, the 3x3 dense layer
-    (k_dconv, taps 9): layer i of a block reads C + i G channels and writes G,
-    so its FLOP and bytes per pixel grow with i; achieved = the mean
-    algorithmic FLOP of the nblocks x L launches / their mean duration.  The
-    1x1 transitions (k_dconv, taps 1) are reported beside it."""
-    C, G, L, nb = spec.C, spec.growth, spec.layers, len(spec.dilations)
-    cins = [C + i * G for i in range(L)]
+    """Roofline of the dense network's dominant kernel, the plain 3x3 dense
+    layer (k_dconv without fusion: the first L - 1 layers of each block; layer
+    i reads C + i G channels and writes G, so its FLOP and bytes per pixel grow
+    with i); achieved = the mean algorithmic FLOP of those nblocks x (L - 1)
+    launches / their mean duration.  Each block's last layer runs fused with
+    the block's 1x1 transition (and, in the last block, the head); it is
+    reported beside it."""
+    C, G, L, nb, nh = spec.C, spec.growth, spec.layers, len(spec.dilations), spec.head_outputs
+    CT = C + L * G
+    cins = [C + i * G for i in range(L - 1)]
     conv_ms, conv_n = prof["conv"]
-    assert conv_n == nb * L * steps, (conv_n, nb, L, steps)
+    assert conv_n == nb * (L - 1) * steps, (conv_n, nb, L, steps)
     avg_s = conv_ms / conv_n * 1e-3
-    flop_launch = 2.0 * 9 * G * (sum(cins) / L) * total_px
-    bytes_launch = 4.0 * (sum(cins) / L + G) * total_px
+    flop_launch = 2.0 * 9 * G * (sum(cins) / len(cins)) * total_px
+    bytes_launch = 4.0 * (sum(cins) / len(cins) + G) * total_px
     tflops = flop_launch / avg_s / 1e12
     roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAKS["fp32"], "unit": "TFLOP/s",
             "frac": round(tflops / PEAKS["fp32"], 4),
             "traffic": measured_traffic(dense_traffic_key(spec, total_px), DENSE_SOURCES),
             "kernel": f"k_dconv fp32 (3x3 dilated dense layer, growth {G} over {cins[0]}..{cins[-1]} input channels; "
-                      f"mean of the {nb * L} launches)",
+                      f"mean of the {nb * (L - 1)} unfused launches)",
             "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_launch": flop_launch,
             "algorithmic_bytes_per_launch": round(bytes_launch),
             "hbm_gb_s": round(bytes_launch / avg_s / 1e9, 1)}
-    t_ms, t_n = prof["conv_1x1"]
-    if t_n:
+    # the fused last layers: 3x3 over C + (L - 1) G channels, then the 1x1
+    # transition CT -> C (and the head C -> nh in the last block)
+    cin = C + (L - 1) * G
+    fused = []
+    for stage, head in (("conv_1x1", False), ("conv_head", True)):
+        t_ms, t_n = prof[stage]
+        if not t_n:
+            continue
         ts = t_ms / t_n * 1e-3
-        CT = C + L * G
-        tf = 2.0 * CT * C * total_px
-        tb = 4.0 * (CT + C) * total_px
-        roof["transition"] = {"kernel": f"k_dconv fp32 (1x1 transition {CT} -> {C})", "avg_launch_ms": round(ts * 1e3, 3),
-                              "tflop_s": round(tf / ts / 1e12, 2), "mfma_frac": round(tf / ts / 1e12 / PEAKS["fp32"], 4),
-                              "gb_s": round(tb / ts / 1e9, 1), "hbm_frac": round(tb / ts / 1e9 / HBM_PEAK_GBS, 4)}
+        tf = (2.0 * 9 * G * cin + 2.0 * CT * C + (2.0 * C * nh if head else 0.0)) * total_px
+        tb = (4.0 * (cin + C) + (4.0 * nh - 4.0 * C if head else 0.0)) * total_px
+        fused.append({"kernel": f"k_dconv fp32 fused (3x3 {cin} -> {G}, 1x1 transition {CT} -> {C}"
+                                + (f", head {C} -> {nh})" if head else ")"),
+                      "launches_per_step": t_n // steps, "avg_launch_ms": round(ts * 1e3, 3),
+                      "tflop_s": round(tf / ts / 1e12, 2), "mfma_frac": round(tf / ts / 1e12 / PEAKS["fp32"], 4),
+                      "gb_s": round(tb / ts / 1e9, 1)})
+    roof["fused_last_layers"] = fused
     return roof
 
 

@@ -166,7 +166,7 @@ int dl_default_config(dl_config *cfg);
  * Network: a = ReLU(conv_1(x)); per block with dilation d, cat = [a] and for
  * each layer cat = [cat, ReLU(conv_d(cat))], then a = ReLU(1x1(cat));
  * maps = head(a).  Supported: C and G in {16, 32}, 1 <= L <= 8, 1 <= nblocks
- * <= 7, dilations 1..64; FP32 only (other precisions, the tile gate, camera
+ * <= 8, dilations 1..64; FP32 only (other precisions, the tile gate, camera
  * maps, the autotuner and dl_debug_conv_layer are DL_ERR_UNSUPPORTED).
  * The blob is copied; the caller keeps ownership.  cfg may be NULL (defaults).
  * *out receives a handle the caller frees with dl_destroy_net.
@@ -482,12 +482,13 @@ enum {
     DL_STAGE_CONV = 1,       /* 3x3 block convolutions without the head       */
                              /* (DLD1 networks: the dense layers)             */
     DL_STAGE_CONV_HEAD = 2,  /* last block convolution with the fused head    */
-                             /* (DLD1 networks: the 1x1 head)                 */
+                             /* (DLD1: last layer + transition + head fused)  */
     DL_STAGE_DETECT = 3,     /* threshold + 3x3 local maximum, masks + counts */
     DL_STAGE_SCAN = 4,       /* row offsets and per-frame counts              */
     DL_STAGE_EMIT = 5,       /* ordered emitter records                       */
     DL_STAGE_GATE = 6,       /* tile gate inference and tile selection        */
-    DL_STAGE_CONV_1X1 = 7,   /* DLD1 networks: the blocks' 1x1 transitions    */
+    DL_STAGE_CONV_1X1 = 7,   /* DLD1: a block's last layer fused with its 1x1 */
+                             /* transition (all blocks but the last)          */
     DL_NSTAGES = 8
 };
 int dl_profile_enable(dl_net *net, int on);

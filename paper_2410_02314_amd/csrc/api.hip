@@ -140,10 +140,11 @@ struct dl_net {
     // dense-connection networks (DLD1 blobs): layers per block and growth
     // (0 for the residual network), the packed weights and biases of every
     // conv in run order ([block][layer 0 .. L-1, transition]) at float
-    // offsets dense_w / dense_b of d_dense
+    // offsets dense_w / dense_b of d_dense, then the head's (rows padded to 16)
     int dL = 0, dG = 0;
     float *d_dense = nullptr;
     std::vector<size_t> dense_w, dense_b;
+    size_t dense_head_w = 0;
 };
 
 namespace {
@@ -274,11 +275,6 @@ bool frame_act_fits(const dl_net *net, int h, int w)
     return frame_act_points(net, h, w) * net->C * esz < ((int64_t)1 << 31);
 }
 
-// Conv tile numberings of a net: one per block, and for dense networks one
-// more (slot nblocks) for the 1x1 transitions, which run at d = 1.
-int tile_slots(const dl_net *net) { return net->dL ? net->nb + 1 : net->nb; }
-int slot_dilation(const dl_net *net, int b) { return b < net->nb ? net->dil[b] : 1; }
-
 // Build the frame descriptors of a uniform batch or a ROI list.
 void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, const uint16_t *const *data,
                     const int64_t *strides, std::vector<FrameDesc> &fd, Geometry &g)
@@ -303,9 +299,9 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         d.gtx = d.w / GATE_TILE;
         d.gty = d.h / GATE_TILE;
         d.keep_start = g.gate_tiles;
-        for (int b = 0; b < tile_slots(net); ++b) {
+        for (int b = 0; b < net->nb; ++b) {
             d.tile_start[b] = g.tiles[b];
-            const int64_t nt = conv_tiles(d.h, d.w, slot_dilation(net, b), g.trb[b], g.tc);
+            const int64_t nt = conv_tiles(d.h, d.w, net->dil[b], g.trb[b], g.tc);
             g.tiles[b] += nt;
             g.max_frame_tiles = std::max(g.max_frame_tiles, nt);
         }
@@ -317,7 +313,7 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         if (d.w > g.maxw) g.maxw = d.w;
         if (d.h > g.maxh) g.maxh = d.h;
     }
-    for (int b = 0; b < tile_slots(net); ++b) g.max_tiles = std::max(g.max_tiles, g.tiles[b]);
+    for (int b = 0; b < net->nb; ++b) g.max_tiles = std::max(g.max_tiles, g.tiles[b]);
 }
 
 struct Plan {
@@ -477,6 +473,12 @@ int pack_dense(dl_net *net)
         for (int i = 0; i < L; ++i) put(G, C + i * G, 9);
         put(C, CT, 1);
     }
+    // the head (fused into the last block's last layer) as a 16-row 1x1 conv
+    std::vector<float> head16((size_t)16 * C, 0.f);
+    std::memcpy(head16.data(), p, sizeof(float) * net->nh * C);
+    net->dense_head_w = (host.size() + 63) / 64 * 64;
+    host.resize(net->dense_head_w + head16.size());
+    pack_dense_weights(16, C, 1, head16.data(), host.data() + net->dense_head_w);
     HIPCHK(net, hipMalloc(&net->d_dense, host.size() * sizeof(float)));
     HIPCHK(net, hipMemcpy(net->d_dense, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
     net->packed_precision = DL_FP32;
@@ -572,8 +574,10 @@ int run_gate(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
 }
 
 // Dense networks: stem into channels 0 .. C-1 of buffer A; per block, each
-// layer appends its G channels to A, the transition writes the next block's
-// input into B (channels 0 .. C-1), and A and B swap; the head reads A.
+// layer appends its G channels to A, and the last one, fused with the block's
+// transition, writes the next block's input into B (channels 0 .. C-1), after
+// which A and B swap; in the last block the head is fused after the
+// transition and writes the maps.
 int run_dense(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, float *maps, hipStream_t s)
 {
     const int C = net->C, L = net->dL, G = net->dG, CT = C + L * G;
@@ -583,30 +587,40 @@ int run_dense(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan 
         HIPCHK(net, launch_dstem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset,
                                  net->cfg.gain * in_scale_of(net), A, CT, s));
     }
-    size_t k = 0;                       // conv index in run order
     for (int b = 0; b < net->nb; ++b) {
-        for (int i = 0; i <= L; ++i, ++k) {
-            const bool tr = i == L;
+        const size_t k0 = (size_t)b * (L + 1);          // this block's first conv in run order
+        for (int i = 0; i < L; ++i) {
+            const bool last = i == L - 1;
+            const int fuse = !last ? 0 : b == net->nb - 1 ? 2 : 1;
             DenseConvArgs a{};
             a.in = A;
             a.csi = CT;
-            a.cin = tr ? CT : C + i * G;
-            a.out = tr ? B : A;
+            a.cin = C + i * G;
+            a.out = A;
             a.cso = CT;
-            a.co = tr ? 0 : C + i * G;
-            a.w = net->d_dense + net->dense_w[k];
-            a.bias = net->d_dense + net->dense_b[k];
+            a.co = C + i * G;
+            a.w = net->d_dense + net->dense_w[k0 + i];
+            a.bias = net->d_dense + net->dense_b[k0 + i];
             a.fd = d_fd;
-            a.d = tr ? 1 : net->dil[b];
-            a.blk = tr ? net->nb : b;
-            a.relu = 1;
-            StageTimer t(net, tr ? DL_STAGE_CONV_1X1 : DL_STAGE_CONV, s);
-            HIPCHK(net, launch_dconv(tr ? C / 16 : G / 16, tr ? 1 : 9, a, g, net->ncu, s));
+            a.d = net->dil[b];
+            a.blk = b;
+            if (fuse) {
+                a.wt = net->d_dense + net->dense_w[k0 + L];
+                a.bt = net->d_dense + net->dense_b[k0 + L];
+                a.tout = B;
+                a.cst = CT;
+            }
+            if (fuse == 2) {
+                a.wh = net->d_dense + net->dense_head_w;
+                a.bh = net->d_head + (size_t)net->nh * C;
+                a.nh = net->nh;
+                a.maps = maps;
+            }
+            StageTimer t(net, fuse == 0 ? DL_STAGE_CONV : fuse == 1 ? DL_STAGE_CONV_1X1 : DL_STAGE_CONV_HEAD, s);
+            HIPCHK(net, launch_dconv(G / 16, fuse, C / 16, a, g, net->ncu, s));
         }
         std::swap(A, B);
     }
-    StageTimer t(net, DL_STAGE_CONV_HEAD, s);
-    HIPCHK(net, launch_dhead(C, d_fd, g, A, CT, net->d_head, net->nh, maps, s));
     return DL_OK;
 }
 
@@ -905,12 +919,12 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
             // the ROI list of this replay: pinned slot -> device, then the
             // descriptors and frame counts built on the device
             EnumArgs ea{};
-            ea.nb = tile_slots(net);
+            ea.nb = net->nb;
             for (int b = 0; b < MAXBLK; ++b) ea.tr[b] = g.trb[b];
             ea.tc = g.tc;
             ea.layouts[ea.nl++] = 1;
-            for (int b = 0; b < ea.nb; ++b) ea.dil[b] = slot_dilation(net, b);
             for (int b = 0; b < net->nb; ++b) {
+                ea.dil[b] = net->dil[b];
                 const int l = block_layout(net, b);
                 bool seen = false;
                 for (int i = 0; i < ea.nl; ++i) seen |= ea.layouts[i] == l;
@@ -1021,7 +1035,7 @@ static int parse_dense(const unsigned char *b, size_t nbytes, dl_net_info *info,
     std::memcpy(&nh, b + 68, 4);
     if (version != 1) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "unsupported weights version %u", version);
     if (nh != 5 && nh != 10) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "head outputs %u: 5 or 10 supported", nh);
-    if (nb < 1 || nb > MAXBLK - 1) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "nblocks %u outside 1..%d", nb, MAXBLK - 1);
+    if (nb < 1 || nb > MAXBLK) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "nblocks %u outside 1..%d", nb, MAXBLK);
     if (L < 1 || L > 8) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "layers per block %u outside 1..8", L);
     if (!(C == 16 || C == 32)) return fail(nullptr, DL_ERR_UNSUPPORTED, "dense network with C = %u (16 or 32)", C);
     if (!(G == 16 || G == 32)) return fail(nullptr, DL_ERR_UNSUPPORTED, "dense network with growth %u (16 or 32)", G);
@@ -1957,7 +1971,7 @@ int dl_graph_create_rois_dynamic(dl_net *net, int max_rois, int max_h, int max_w
     g.total_act = proto.cap_act;
     g.total_rows = proto.cap_rows;
     g.total_words = proto.cap_words;
-    for (int b = 0; b < tile_slots(net); ++b) g.tiles[b] = (int64_t)1 << 40;   // persistent grids: the full chip
+    for (int b = 0; b < net->nb; ++b) g.tiles[b] = (int64_t)1 << 40;   // persistent grids: the full chip
     g.max_tiles = 0;
     g.maxh = max_h;
     g.maxw = max_w;

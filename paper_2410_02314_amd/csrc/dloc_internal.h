@@ -255,31 +255,42 @@ void pack_conv_weights(int C, int precision, const float *W, void *dst, float *s
 // ---- dense-connection networks (kernels_dense.hip) ----
 // A block's concatenation lives in one plain NHWC buffer of cs floats per
 // point (block input in channels 0 .. C-1, then each layer's growth channels);
-// a layer reads channels 0 .. cin-1 of `in` and writes cout channels from co
-// of `out`.  Tiles: dense_tile_rows() x dense_tile_cols() points of the
-// layer's d-strided lattice (conv_tiles / decode_tile numbering, phase-major,
-// strip 8); the 1x1 transitions run at d = 1 on the tile numbering of slot
-// `blk` = nblocks.
+// a layer reads channels 0 .. cin-1 of `in` and writes its 16 NB outputs (+
+// bias, ReLU) from channel co of `out`.  A block's last layer runs fused with
+// its 1x1 transition (CT = cin + 16 NB -> 16 NT, + bias, ReLU), which writes
+// channels 0 .. 16 NT - 1 of `tout` (its own outputs are not stored), and in
+// the last block with the 1x1 head after it (16 NT -> nh planar maps).
+// Tiles: dense_tile_rows() x dense_tile_cols() points of the layer's d-strided
+// lattice (conv_tiles / decode_tile numbering, phase-major, strip 8) in the
+// tile numbering of slot `blk`.
 struct DenseConvArgs {
     const float *in;
     int csi, cin;            // floats per input point, input channels read (multiple of 16)
     float *out;
     int cso, co;             // floats per output point, first output channel
-    const float *w;          // packed weights (pack_dense_weights)
-    const float *bias;       // [cout]
+    const float *w;          // packed layer weights (pack_dense_weights, taps 9)
+    const float *bias;       // [16 NB]
     const FrameDesc *fd;
-    int d, blk, relu;
+    int d, blk;
+    // fused transition: packed weights (pack_dense_weights, taps 1, cin + 16 NB
+    // -> 16 NT), bias [16 NT], output points of cst floats
+    const float *wt, *bt;
+    float *tout;
+    int cst;
+    // fused head: packed weights (16 rows, rows >= nh zero; K = 16 NT), bias [nh]
+    const float *wh, *bh;
+    int nh;
+    float *maps;             // planar [nh][h][w] per frame from px_off
 };
 int dense_tile_rows();
 int dense_tile_cols();
-// taps 9 (3x3 at dilation d) or 1 (1x1); cout = 16 nb_out, nb_out 1 or 2
-hipError_t launch_dconv(int nb_out, int taps, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s);
+// nb_out 1 or 2 (16 or 32 layer outputs); fuse 0 (layer), 1 (+ transition),
+// 2 (+ transition + head); nt = transition outputs / 16 (1 or 2)
+hipError_t launch_dconv(int nb_out, int fuse, int nt, const DenseConvArgs &a, const Geometry &g, int ncu,
+                        hipStream_t s);
 // preprocessing + stem 1 -> C (C 16 or 32) + ReLU into channels 0 .. C-1 of points of cs floats
 hipError_t launch_dstem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b, float offset,
                         float scale, float *act, int cs, hipStream_t s);
-// 1x1 head over channels 0 .. C-1 into planar maps [nh][h][w] per frame (nh <= 16)
-hipError_t launch_dhead(int C, const FrameDesc *fd, const Geometry &g, const float *act, int cs, const float *head,
-                        int nh, float *maps, hipStream_t s);
 // W [cout][cin][taps] -> the MFMA layout of k_dconv (cout, cin multiples of 16)
 void pack_dense_weights(int cout, int cin, int taps, const float *W, float *dst);
 

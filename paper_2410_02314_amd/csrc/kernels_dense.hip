@@ -5,18 +5,20 @@
 //
 // A block keeps its concatenation in one NHWC buffer of CT = C + L G channels
 // per point: channels 0 .. C-1 hold the block input, layer i (3x3, dilation d)
-// reads channels 0 .. C + i G - 1 and writes its G channels after them, and
-// the 1x1 transition reads all CT channels and writes the next block's input
-// into channels 0 .. C-1 of the other buffer.  FP32 throughout.
+// reads channels 0 .. C + i G - 1 and writes its G channels after them.  The
+// block's 1x1 transition (CT -> C) is fused into its last layer: that layer's
+// own G outputs feed only the transition, so they never leave registers, and
+// the transition writes the next block's input into channels 0 .. C-1 of the
+// other buffer; in the last block the 1x1 head is fused after it as well.
+// FP32 throughout.
 //
 //   k_dstem   preprocessing + 3x3 conv 1 -> C + ReLU into channels 0 .. C-1
-//   k_dconv   one dense layer (TAPS = 9) or transition (TAPS = 1) as MFMA
-//             implicit GEMM (v_mfma_f32_16x16x4_f32): M = output channels
-//             (NB blocks of 16), N = pixels, K = taps x input channels, the
+//   k_dconv   one dense layer as MFMA implicit GEMM (v_mfma_f32_16x16x4_f32):
+//             M = output channels (NB blocks of 16), N = pixels, K = 9 taps x
 //             input channels taken 16 at a time -- a group's tile and weights
-//             are staged in LDS, the next group's tile is loaded into
-//             registers while the MFMAs run on the current one
-//   k_dhead   1x1 head C -> nh into planar maps
+//             are staged in LDS, the next group's tile and weights are loaded
+//             into registers while the MFMAs run on the current one.  FUSE = 1
+//             adds the transition, FUSE = 2 the transition and the head.
 #include <algorithm>
 
 #include "dloc_internal.h"
@@ -72,77 +74,60 @@ k_dstem(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const int64_t 
     }
 }
 
-// ---------------------------------------------------------------- head
-// one workgroup per global row; a thread per pixel: nh dot products over the
-// first C channels of its point
-template <int C>
-__global__ void __launch_bounds__(256)
-k_dhead(const FrameDesc *__restrict__ fdp, int nf, int64_t nrows, const int64_t *__restrict__ dyn,
-        const float *__restrict__ act, int cs, const float *__restrict__ head, int nh, float *__restrict__ maps)
-{
-    __shared__ float sh[16 * C + 16];
-    for (int i = threadIdx.x; i < nh * C + nh; i += 256) sh[i] = head[i];
-    __syncthreads();
-    if (dyn) {
-        nf = (int)dyn[DYN_NF];
-        nrows = dyn[DYN_ROWS];
-    }
-    const int64_t row = blockIdx.x;
-    if (row >= nrows) return;
-    const int f = find_frame(fdp, nf, row, [](const FrameDesc &d) { return d.row_start; });
-    const FrameDesc fd = fdp[f];
-    const int y = (int)(row - fd.row_start), W = fd.w;
-    const int64_t plane = (int64_t)fd.h * W;
-    for (int x = threadIdx.x; x < W; x += 256) {
-        const float *pt = act + (fd.act_off + (int64_t)y * W + x) * cs;
-        float v[C];
-#pragma unroll
-        for (int c = 0; c < C; c += 4) {
-            const v4f u = *reinterpret_cast<const v4f *>(pt + c);
-            v[c] = u[0]; v[c + 1] = u[1]; v[c + 2] = u[2]; v[c + 3] = u[3];
-        }
-        float *mp = maps + (int64_t)nh * fd.px_off + (int64_t)y * W + x;
-        for (int q = 0; q < nh; ++q) {
-            float s = sh[nh * C + q];
-#pragma unroll
-            for (int c = 0; c < C; ++c) s += sh[q * C + c] * v[c];
-            mp[q * plane] = s;
-        }
-    }
-}
-
 // ---------------------------------------------------------------- conv
 constexpr int DTR = 8, DTC = 32, DPB = DTC / 16;
 constexpr int DPS = 24;                  // LDS floats per point: 16 channels, stride 8 mod 16 dwords
+constexpr int PW = DTC + 2, NPT = (DTR + 2) * PW;   // tile points with the one-point halo
 
-template <int NB, int TAPS>
+// LDS of one workgroup (floats): the group's tile, the group's layer weights,
+// [fused] the group's transition weights, the transition weights of the
+// layer's own outputs, [head] the head weights; then the biases.
+template <int NB, int NT, int FUSE>
 struct DLds {
-    static constexpr int HALO = TAPS == 9 ? 1 : 0;
-    static constexpr int PW = DTC + 2 * HALO, NPT = (DTR + 2 * HALO) * PW;
-    static constexpr int TILE = NPT * DPS;                  // floats
-    static constexpr int W = TAPS * NB * 64 * 4;             // floats of one group's weights
+    static constexpr int TILE = NPT * DPS;
+    static constexpr int W = 9 * NB * 64 * 4;                // one group's layer weights
+    static constexpr int WT = FUSE ? NT * 64 * 4 : 0;        // one group's transition weights
+    static constexpr int WTL = FUSE ? NB * NT * 64 * 4 : 0;  // transition weights of the layer's outputs
+    static constexpr int WH = FUSE == 2 ? NT * 64 * 4 : 0;   // head weights (16 rows, K = 16 NT)
+    static constexpr int BIAS = NB * 16 + (FUSE ? NT * 16 : 0) + (FUSE == 2 ? 16 : 0);
     static constexpr int NQ = NPT * 4;                       // 16-byte chunks of a group's tile
     static constexpr int NPF = (NQ + DTR * 64 - 1) / (DTR * 64);
-    static constexpr int BYTES = (TILE + W + NB * 16) * 4 + 64;
+    static constexpr int NWF = (W / 4 + DTR * 64 - 1) / (DTR * 64);   // weight chunks per thread
+    static constexpr int NTF = (WT / 4 + DTR * 64 - 1) / (DTR * 64);
+    static constexpr int BYTES = (TILE + W + WT + WTL + WH + BIAS) * 4 + 64;
 };
 
-template <int NB, int TAPS>
-__global__ void __launch_bounds__(DTR * 64, 2)
+template <int NB, int NT, int FUSE>
+__global__ void __launch_bounds__(DTR * 64)
 k_dconv(DenseConvArgs a, Geometry geo)
 {
-    using L = DLds<NB, TAPS>;
-    constexpr int HALO = L::HALO, PW = L::PW, NT = DTR * 64;
+    using L = DLds<NB, NT, FUSE>;
+    constexpr int NTH = DTR * 64;
     extern __shared__ v4f dsm[];
     float *sT = reinterpret_cast<float *>(dsm);
     v4f *sW = reinterpret_cast<v4f *>(sT + L::TILE);
-    float *sB = sT + L::TILE + L::W;
-    int *sdec = reinterpret_cast<int *>(sB + NB * 16);
+    v4f *sWT = sW + L::W / 4;
+    v4f *sWTL = sWT + L::WT / 4;
+    v4f *sWH = sWTL + L::WTL / 4;
+    float *sB = reinterpret_cast<float *>(sWH + L::WH / 4);
+    float *sBT = sB + NB * 16;                   // [fused] transition bias
+    float *sBH = sBT + (FUSE ? NT * 16 : 0);     // [head] head bias (nh of 16)
+    int *sdec = reinterpret_cast<int *>(sB + L::BIAS);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = lane & 15, kq = lane >> 4;
     const int dd = a.d, blk = a.blk, ngroups = a.cin / 16;
-    for (int i = tid; i < NB * 16; i += NT) sB[i] = a.bias[i];
+    for (int i = tid; i < NB * 16; i += NTH) sB[i] = a.bias[i];
+    if constexpr (FUSE > 0) {
+        const v4f *wl = reinterpret_cast<const v4f *>(a.wt) + (size_t)ngroups * NT * 64;
+        for (int i = tid; i < L::WTL / 4; i += NTH) sWTL[i] = wl[i];
+        for (int i = tid; i < NT * 16; i += NTH) sBT[i] = a.bt[i];
+    }
+    if constexpr (FUSE == 2) {
+        for (int i = tid; i < L::WH / 4; i += NTH) sWH[i] = reinterpret_cast<const v4f *>(a.wh)[i];
+        for (int i = tid; i < 16; i += NTH) sBH[i] = i < a.nh ? a.bh[i] : 0.f;
+    }
 
     const int64_t T = geo.dyn ? ld_const(geo.dyn + DYN_TILES + blk) : geo.tiles[blk];
     const int nfr = geo.dyn ? (int)ld_const(geo.dyn + DYN_NF) : geo.nf;
@@ -151,7 +136,7 @@ k_dconv(DenseConvArgs a, Geometry geo)
     const int64_t t0 = (int64_t)xcd * chunk, t1 = min(T, t0 + chunk);
 
     for (int64_t ti = t0 + slot; ti < t1; ti += nslot) {
-        // the tile: frame, origin of its phase lattice, frame size and offset
+        // the tile: frame, origin of its phase lattice, frame size and offsets
         __syncthreads();                 // the previous tile's LDS reads are done
         if (tid == 0) {
             const int f = find_frame(a.fd, nfr, ti, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
@@ -159,13 +144,15 @@ k_dconv(DenseConvArgs a, Geometry geo)
             const int h = ld_const(&fd->h), w = ld_const(&fd->w);
             int Y0, X0;
             decode_tile(h, w, ti - ld_const(&fd->tile_start[blk]), dd, DTR, DTC, false, 8u, Y0, X0);
-            const int64_t act = ld_const(&fd->act_off);
+            const int64_t act = ld_const(&fd->act_off), px = ld_const(&fd->px_off);
             sdec[0] = Y0;
             sdec[1] = X0;
             sdec[2] = h;
             sdec[3] = w;
             sdec[4] = (int)(uint32_t)act;
             sdec[5] = (int)(act >> 32);
+            sdec[6] = (int)(uint32_t)px;
+            sdec[7] = (int)(px >> 32);
         }
         __syncthreads();
         const int Y0 = __builtin_amdgcn_readfirstlane(sdec[0]), X0 = __builtin_amdgcn_readfirstlane(sdec[1]);
@@ -174,14 +161,29 @@ k_dconv(DenseConvArgs a, Geometry geo)
                             ((int64_t)__builtin_amdgcn_readfirstlane(sdec[5]) << 32);
         const float *in = a.in + act * a.csi;
 
-        // one input group's tile (16 channels of every tile point) into registers
-        v4f pf[L::NPF];
+        // one input group's tile (16 channels of every tile point) and the
+        // group's weights into registers
+        v4f pf[L::NPF], wf[L::NWF], tf[L::NTF > 0 ? L::NTF : 1];
         auto issue = [&](int g) {
+            const v4f *gw = reinterpret_cast<const v4f *>(a.w) + (size_t)g * (L::W / 4);
+#pragma unroll
+            for (int k = 0; k < L::NWF; ++k) {
+                const int i = tid + k * NTH;
+                if (i < L::W / 4) wf[k] = gw[i];
+            }
+            if constexpr (FUSE > 0) {
+                const v4f *tw = reinterpret_cast<const v4f *>(a.wt) + (size_t)g * (L::WT / 4);
+#pragma unroll
+                for (int k = 0; k < L::NTF; ++k) {
+                    const int i = tid + k * NTH;
+                    if (i < L::WT / 4) tf[k] = tw[i];
+                }
+            }
 #pragma unroll
             for (int k = 0; k < L::NPF; ++k) {
-                const int q = tid + k * NT;
+                const int q = tid + k * NTH;
                 const int pt = q / 4, c4 = q - (q / 4) * 4;
-                const int ii = pt / PW - HALO, jj = pt - (pt / PW) * PW - HALO;
+                const int ii = pt / PW - 1, jj = pt - (pt / PW) * PW - 1;
                 const int y = Y0 + dd * ii, x = X0 + dd * jj;
                 const bool ok = q < L::NQ && (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
                 pf[k] = ok ? *reinterpret_cast<const v4f *>(in + ((int64_t)y * W + x) * a.csi + g * 16 + c4 * 4)
@@ -190,24 +192,38 @@ k_dconv(DenseConvArgs a, Geometry geo)
         };
         issue(0);
         v4f acc[NB][DPB];
+        v4f accT[FUSE ? NT : 1][DPB];    // [fused] transition accumulators
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+        for (int p = 0; p < DPB; ++p) {
 #pragma unroll
-            for (int p = 0; p < DPB; ++p) acc[nb][p] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int nb = 0; nb < NB; ++nb) acc[nb][p] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int nt = 0; nt < (FUSE ? NT : 1); ++nt) accT[nt][p] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
         for (int g = 0; g < ngroups; ++g) {
             __syncthreads();             // the previous group's LDS reads are done
 #pragma unroll
             for (int k = 0; k < L::NPF; ++k) {
-                const int q = tid + k * NT;
+                const int q = tid + k * NTH;
                 if (q < L::NQ) *reinterpret_cast<v4f *>(sT + (q / 4) * DPS + (q % 4) * 4) = pf[k];
             }
-            const v4f *gw = reinterpret_cast<const v4f *>(a.w) + (size_t)g * (L::W / 4);
-            for (int i = tid; i < L::W / 4; i += NT) sW[i] = gw[i];
+#pragma unroll
+            for (int k = 0; k < L::NWF; ++k) {
+                const int i = tid + k * NTH;
+                if (i < L::W / 4) sW[i] = wf[k];
+            }
+            if constexpr (FUSE > 0) {
+#pragma unroll
+                for (int k = 0; k < L::NTF; ++k) {
+                    const int i = tid + k * NTH;
+                    if (i < L::WT / 4) sWT[i] = tf[k];
+                }
+            }
             __syncthreads();
             if (g + 1 < ngroups) issue(g + 1);   // in flight while the MFMAs run
 #pragma unroll
-            for (int tap = 0; tap < TAPS; ++tap) {
-                const int u = TAPS == 9 ? tap / 3 : 0, v = TAPS == 9 ? tap % 3 : 0;
+            for (int tap = 0; tap < 9; ++tap) {
+                const int u = tap / 3, v = tap % 3;
                 v4f aw[NB], bv[DPB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) aw[nb] = sW[(tap * NB + nb) * 64 + lane];
@@ -221,6 +237,19 @@ k_dconv(DenseConvArgs a, Geometry geo)
 #pragma unroll
                         for (int p = 0; p < DPB; ++p)
                             acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[nb][s], bv[p][s], acc[nb][p], 0, 0, 0);
+                if constexpr (FUSE > 0) {
+                    if (tap == 4) {      // the centre tap's operand is this group's 1x1 input
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) {
+                            const v4f awt = sWT[nt * 64 + lane];
+#pragma unroll
+                            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                                for (int p = 0; p < DPB; ++p)
+                                    accT[nt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(awt[s], bv[p][s], accT[nt][p], 0, 0, 0);
+                        }
+                    }
+                }
             }
         }
         // epilogue: lane (j, kq) holds output channels 16 nb + 4 kq + r of pixel j
@@ -228,27 +257,74 @@ k_dconv(DenseConvArgs a, Geometry geo)
 #pragma unroll
         for (int p = 0; p < DPB; ++p) {
             const int xo = X0 + dd * (16 * p + j);
-            if (yo >= H || xo >= W) continue;
-            float *op = a.out + (act + (int64_t)yo * W + xo) * a.cso + a.co;
+            const bool inside = yo < H && xo < W;
+            v4f o[NB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                v4f o = acc[nb][p];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float s = o[r] + sB[nb * 16 + 4 * kq + r];
-                    o[r] = a.relu ? fmaxf(s, 0.f) : s;
+                for (int r = 0; r < 4; ++r) o[nb][r] = fmaxf(acc[nb][p][r] + sB[nb * 16 + 4 * kq + r], 0.f);
+            }
+            if constexpr (FUSE == 0) {
+                if (inside) {
+                    float *op = a.out + (act + (int64_t)yo * W + xo) * a.cso + a.co;
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) *reinterpret_cast<v4f *>(op + nb * 16 + 4 * kq) = o[nb];
                 }
-                *reinterpret_cast<v4f *>(op + nb * 16 + 4 * kq) = o;
+            } else {
+                // the layer's outputs are the transition's last K groups: in the
+                // accumulator layout, lane (j, kq) element s is channel 4 kq + s
+                // of pixel j, which is the B operand's layout for K step s
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const v4f awl = sWTL[(nb * NT + nt) * 64 + lane];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+                            accT[nt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(awl[s], o[nb][s], accT[nt][p], 0, 0, 0);
+                    }
+                v4f t[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) t[nt][r] = fmaxf(accT[nt][p][r] + sBT[nt * 16 + 4 * kq + r], 0.f);
+                if constexpr (FUSE == 1) {
+                    if (inside) {
+                        float *op = a.tout + (act + (int64_t)yo * W + xo) * a.cst;
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) *reinterpret_cast<v4f *>(op + nt * 16 + 4 * kq) = t[nt];
+                    }
+                } else {
+                    // head: outputs q = 4 kq + r of pixel j, K = the 16 NT transition outputs
+                    v4f hq = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const v4f awh = sWH[nt * 64 + lane];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) hq = __builtin_amdgcn_mfma_f32_16x16x4f32(awh[s], t[nt][s], hq, 0, 0, 0);
+                    }
+                    if (inside) {
+                        const int64_t px = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(sdec[6]) |
+                                           ((int64_t)__builtin_amdgcn_readfirstlane(sdec[7]) << 32);
+                        const int64_t plane = (int64_t)H * W;
+                        float *mp = a.maps + a.nh * px + (int64_t)yo * W + xo;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int q = 4 * kq + r;
+                            if (q < a.nh) mp[q * plane] = hq[r] + sBH[q];
+                        }
+                    }
+                }
             }
         }
     }
 }
 
-template <int NB, int TAPS>
+template <int NB, int NT, int FUSE>
 hipError_t launch_dconv_t(const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
 {
-    using L = DLds<NB, TAPS>;
-    auto kern = k_dconv<NB, TAPS>;
+    using L = DLds<NB, NT, FUSE>;
+    auto kern = k_dconv<NB, NT, FUSE>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -265,17 +341,29 @@ hipError_t launch_dconv_t(const DenseConvArgs &a, const Geometry &g, int ncu, hi
     return hipGetLastError();
 }
 
+template <int NB, int FUSE>
+hipError_t launch_nt(int nt, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
+{
+    if (nt == 1) return launch_dconv_t<NB, 1, FUSE>(a, g, ncu, s);
+    if (nt == 2) return launch_dconv_t<NB, 2, FUSE>(a, g, ncu, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 int dense_tile_rows() { return DTR; }
 int dense_tile_cols() { return DTC; }
 
-hipError_t launch_dconv(int nb_out, int taps, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
+hipError_t launch_dconv(int nb_out, int fuse, int nt, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
 {
-    if (taps == 9 && nb_out == 1) return launch_dconv_t<1, 9>(a, g, ncu, s);
-    if (taps == 9 && nb_out == 2) return launch_dconv_t<2, 9>(a, g, ncu, s);
-    if (taps == 1 && nb_out == 1) return launch_dconv_t<1, 1>(a, g, ncu, s);
-    if (taps == 1 && nb_out == 2) return launch_dconv_t<2, 1>(a, g, ncu, s);
+    if (fuse == 0) {
+        if (nb_out == 1) return launch_dconv_t<1, 1, 0>(a, g, ncu, s);
+        if (nb_out == 2) return launch_dconv_t<2, 1, 0>(a, g, ncu, s);
+        return hipErrorInvalidValue;
+    }
+    if (a.nh > 16) return hipErrorInvalidValue;
+    if (nb_out == 1) return fuse == 1 ? launch_nt<1, 1>(nt, a, g, ncu, s) : launch_nt<1, 2>(nt, a, g, ncu, s);
+    if (nb_out == 2) return fuse == 1 ? launch_nt<2, 1>(nt, a, g, ncu, s) : launch_nt<2, 2>(nt, a, g, ncu, s);
     return hipErrorInvalidValue;
 }
 
@@ -289,22 +377,6 @@ hipError_t launch_dstem(int C, const FrameDesc *fd, const Geometry &g, const flo
     else if (C == 16)
         hipLaunchKernelGGL(k_dstem<16>, dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, g.dyn, w, b, offset, scale,
                            act, cs);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
-hipError_t launch_dhead(int C, const FrameDesc *fd, const Geometry &g, const float *act, int cs, const float *head,
-                        int nh, float *maps, hipStream_t s)
-{
-    const unsigned grid = (unsigned)g.total_rows;
-    if (nh > 16) return hipErrorInvalidValue;
-    if (C == 32)
-        hipLaunchKernelGGL(k_dhead<32>, dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, g.dyn, act, cs, head, nh,
-                           maps);
-    else if (C == 16)
-        hipLaunchKernelGGL(k_dhead<16>, dim3(grid), dim3(256), 0, s, fd, g.nf, g.total_rows, g.dyn, act, cs, head, nh,
-                           maps);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -115,7 +115,7 @@ def test_bad_dense_blobs_are_rejected():
     for off, val, code in [(4, 2, dl.DL_ERR_BAD_WEIGHTS),            # version
                            (8, 48, dl.DL_ERR_UNSUPPORTED),           # C
                            (12, 0, dl.DL_ERR_BAD_WEIGHTS),           # no blocks
-                           (12, 8, dl.DL_ERR_BAD_WEIGHTS),           # one slot is the transitions'
+                           (12, 9, dl.DL_ERR_BAD_WEIGHTS),           # more blocks than descriptors hold
                            (16, 0, dl.DL_ERR_BAD_WEIGHTS),           # no layers
                            (16, 9, dl.DL_ERR_BAD_WEIGHTS),
                            (20, 24, dl.DL_ERR_UNSUPPORTED),          # growth
