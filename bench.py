@@ -260,7 +260,7 @@ def dense_roofline(spec, prof, total_px, steps):
 
 
 def dense_traffic_key(spec, total_px):
-    return f"k_dconv fp32 taps=9 net {spec.name} {total_px}px"
+    return f"k_dconv fp32 unfused net {spec.name} {total_px}px"
 
 
 def measure_form(args, precision, spec, w, d_frames, dl, torch, dev, cam=None):
