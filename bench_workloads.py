@@ -80,11 +80,15 @@ def tiny(args, S):
 
 
 def rois(args, S):
-    """256 ROIs with sides from {128, ..., 1024}, net A, one call per step (and a graph)."""
+    """256 ROIs with sides from {128, ..., 1024}, net A (or, with --net D, the
+    dense-connection net), one call per step (and a graph).  With net D the
+    three tile schedules of its conv kernels are timed on the same ROIs:
+    static ranges per XCD, an atomic queue per XCD, one global atomic queue."""
     rois_np = S.render_rois(256, "rois", 1004)
     import torch
     import paper_2410_02314_amd as dl
-    spec, w = S.make_net("A", 1)
+    dense = args.net == "D"
+    spec, w = S.make_net("D", 3) if dense else S.make_net("A", 1)
     net = dl.Net(S.serialize_weights(spec, w), precision=args.precision, tile_rows=args.tile_rows)
     dev = torch.device("cuda:0")
     d = [torch.from_numpy(r).to(dev) for r in rois_np]
@@ -97,7 +101,7 @@ def rois(args, S):
     # ROIs' typical size; its choice is used for everything below
     import tempfile
     tune = None
-    if not args.tile_rows:
+    if not args.tile_rows and not dense:
         probe = torch.from_numpy(S.render_frames(8, 512, 512, "rois", 1004)).to(dev)
         tune = net.autotune_ex(probe, reps=3, cache_path=os.path.join(tempfile.gettempdir(), "dloc_tune.jsonl"),
                                stream=st)
@@ -107,6 +111,24 @@ def rois(args, S):
     ms = _timed(lambda: net.localize_rois_device(d, out, counts, st), args.steps, args.warmup, st)
     prof = net.profile_read()
     net.profile(False)
+    schedules = None
+    if dense:
+        # the same ROIs under each tile schedule (results are identical; only
+        # the order in which workgroups take tiles differs)
+        ref = dl.emitters_from_device(out, int(counts[256].item()))
+        schedules = {"static_xcd_ranges_ms": round(ms, 3)}
+        for q, name in ((1, "atomic_queue_per_xcd_ms"), (2, "atomic_queue_global_ms")):
+            nq = dl.Net(S.serialize_weights(spec, w), precision=args.precision, tile_queue=q)
+            nq.profile(True)
+            msq = _timed(lambda: nq.localize_rois_device(d, out, counts, st), args.steps, args.warmup, st)
+            pq = nq.profile_read()
+            nq.close()
+            got = dl.emitters_from_device(out, int(counts[256].item()))
+            schedules[name] = round(msq, 3)
+            schedules[name.replace("_ms", "_conv_ms")] = round(pq["conv"][0] / max(1, pq["conv"][1]), 4)
+            schedules[name.replace("_ms", "_same_records")] = bool(np.array_equal(got, ref))
+            log(f"tile schedule {q}: {msq:.3f} ms/step (static {ms:.3f})")
+        schedules["static_xcd_ranges_conv_ms"] = round(prof["conv"][0] / max(1, prof["conv"][1]), 4)
     g = net.graph_rois(d, out, counts)
     ms_graph = _timed(lambda: g.launch(st), args.steps, args.warmup, st)
     g.close()
@@ -128,7 +150,11 @@ def rois(args, S):
     torch.cuda.synchronize()
     net.localize_rois_device(d, out, counts, st)          # counts of the headline ROI set again
     conv_ms, conv_n = prof["conv"]
-    flop = 2.0 * 9 * spec.C * spec.C * px
+    if dense:       # the unfused dense layers: mean over layers 0 .. L-2 of each block
+        cins = [spec.C + i * spec.growth for i in range(spec.layers - 1)]
+        flop = 2.0 * 9 * spec.growth * (sum(cins) / len(cins)) * px
+    else:
+        flop = 2.0 * 9 * spec.C * spec.C * px
     ach = flop / (conv_ms / conv_n * 1e-3) / 1e12
     # load balance: the same net on a uniform batch of about the same pixel
     # count (16 x 2048^2 frames of the same emitter model) in one launch per layer
@@ -140,12 +166,13 @@ def rois(args, S):
     mpx, mpx_uni = px / (ms * 1e-3) / 1e6, uni.size / (ms_uni * 1e-3) / 1e6
     del d_uni, u_out
     _line(args, mpx, ms,
-          {"workload": f"256 uneven ROIs (sides 128..1024), {px / 1e6:.1f} Mpx, net A",
+          {"workload": f"256 uneven ROIs (sides 128..1024), {px / 1e6:.1f} Mpx, net {'D' if dense else 'A'}",
            "precision": args.precision, "frames": 256, "pixels": px},
           {"graph_ms_per_step": round(ms_graph, 3),
            "capacity_graph_ms_per_step": round(ms_dyn, 3),
            "capacity_graph": "one capture (256 ROIs up to 1024 x 1024) replayed alternately over two ROI sets",
            "autotune": tune,
+           "tile_schedules": schedules,
            "emitters_per_step": int(counts[256].item()),
            "uniform_16x2048sq_mpx_s": round(mpx_uni, 2), "load_balance_efficiency": round(mpx / mpx_uni, 4),
            "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAKS[args.precision],

@@ -95,7 +95,11 @@ typedef struct {
     int32_t tile_w;             /* conv tile lattice columns; 0 = the form's own   */
                                 /* (32 FP32/BF16X3, 64 BF16/FP8); other widths are */
                                 /* DL_ERR_UNSUPPORTED                              */
-    int32_t reserved[4];        /* must be 0                                       */
+    int32_t tile_queue;         /* dense-connection nets: how conv tiles reach the */
+                                /* persistent workgroups -- 0 static ranges per    */
+                                /* XCD, 1 an atomic queue per XCD, 2 one atomic    */
+                                /* queue; residual nets: 0 only                    */
+    int32_t reserved[3];        /* must be 0                                       */
 } dl_config;
 
 /* One detected emitter, 32 bytes.  x_px = col + 0.5 + dx, y_px = row + 0.5 + dy

@@ -47,7 +47,7 @@ class DLConfig(ctypes.Structure):
                 ("offset", ctypes.c_float), ("device", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("max_workspace_bytes", ctypes.c_uint64), ("tile_rows", ctypes.c_int32),
                 ("max_sigma_px", ctypes.c_float), ("in_scale_override", ctypes.c_float),
-                ("tile_w", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("tile_w", ctypes.c_int32), ("tile_queue", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class DLRoi(ctypes.Structure):
@@ -163,7 +163,8 @@ def _check(rc: int, handle=None):
 
 def make_config(precision: str = "fp32", threshold: float = 0.3, gain: float = 0.5, offset: float = 100.0,
                 device: int = 0, flags: int = 0, max_workspace_bytes: int = 0, tile_rows: int = 0,
-                max_sigma_px: float = 0.0, in_scale_override: float = 0.0, tile_w: int = 0) -> DLConfig:
+                max_sigma_px: float = 0.0, in_scale_override: float = 0.0, tile_w: int = 0,
+                tile_queue: int = 0) -> DLConfig:
     c = DLConfig()
     _lib.dl_default_config(ctypes.byref(c))
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -177,6 +178,7 @@ def make_config(precision: str = "fp32", threshold: float = 0.3, gain: float = 0
     c.max_sigma_px = max_sigma_px
     c.in_scale_override = in_scale_override
     c.tile_w = tile_w
+    c.tile_queue = tile_queue
     return c
 
 

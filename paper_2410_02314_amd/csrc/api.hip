@@ -206,7 +206,8 @@ int check_config(dl_net *net, const dl_config *c)
             return fail(net, DL_ERR_UNSUPPORTED, "tile_w %d: this form's conv kernel is built for %d lattice columns",
                         c->tile_w, tc);
     }
-    for (int k = 0; k < 4; ++k)
+    if (c->tile_queue < 0 || c->tile_queue > 2) return fail(net, DL_ERR_INVALID_ARG, "tile_queue must be 0, 1 or 2");
+    for (int k = 0; k < 3; ++k)
         if (c->reserved[k]) return fail(net, DL_ERR_INVALID_ARG, "reserved config fields must be 0");
     return DL_OK;
 }
@@ -322,6 +323,7 @@ struct Plan {
     // holds the intermediate of a block (a block writes its output in the next
     // block's layout, so it cannot overwrite its own input in place)
     size_t act0 = 0, act1 = 0, act2 = 0, maps = 0, mask = 0, rc = 0, roff = 0, total = 0;
+    size_t queue = 0;               // dense tile queues: 8 counters per conv launch (tile_queue != 0)
     bool gated = false;
     size_t pooled = 0, glog = 0, keep = 0, lists = 0, lcount = 0;
 };
@@ -347,6 +349,9 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     p.mask = o; o = align_up(o + (size_t)g.total_words * 8);
     p.rc = o; o = align_up(o + (size_t)g.total_rows * 4);
     p.roff = o; o = align_up(o + (size_t)(g.total_rows + 1) * 4);
+    if (net->dL && net->cfg.tile_queue) {
+        p.queue = o; o = align_up(o + (size_t)net->nb * net->dL * 8 * 4);
+    }
     if (gated_run(net)) {
         const int L = 2 * net->nb;
         p.gated = true;
@@ -582,6 +587,8 @@ int run_dense(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan 
 {
     const int C = net->C, L = net->dL, G = net->dG, CT = C + L * G;
     float *A = reinterpret_cast<float *>(p.ws + p.act0), *B = reinterpret_cast<float *>(p.ws + p.act2);
+    uint32_t *queue = net->cfg.tile_queue ? reinterpret_cast<uint32_t *>(p.ws + p.queue) : nullptr;
+    if (queue) HIPCHK(net, launch_zero_u32(queue, (int64_t)net->nb * L * 8, s));
     {
         StageTimer t(net, DL_STAGE_STEM, s);
         HIPCHK(net, launch_dstem(C, d_fd, g, net->d_stem, net->d_stem + C * 9, net->cfg.offset,
@@ -604,6 +611,10 @@ int run_dense(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan 
             a.fd = d_fd;
             a.d = net->dil[b];
             a.blk = b;
+            if (queue) {
+                a.queue = queue + ((size_t)b * L + i) * 8;
+                a.queue_mode = net->cfg.tile_queue;
+            }
             if (fuse) {
                 a.wt = net->d_dense + net->dense_w[k0 + L];
                 a.bt = net->d_dense + net->dense_b[k0 + L];
@@ -1143,6 +1154,8 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
         return fail(nullptr, DL_ERR_UNSUPPORTED, "max_sigma_px needs a network with the uncertainty head");
     const bool dense = info.dense_layers > 0;
     if (dense && (rc = check_dense_config(nullptr, &c))) return rc;
+    if (!dense && c.tile_queue)
+        return fail(nullptr, DL_ERR_UNSUPPORTED, "tile_queue applies to the dense-connection kernels only");
     if (!dense && !conv_supported(info.C, c.precision, info.head_outputs))
         return fail(nullptr, DL_ERR_UNSUPPORTED, "C = %d does not fit the %s conv kernel's LDS", info.C,
                     c.precision == DL_FP32 ? "FP32" : c.precision == DL_BF16 ? "BF16" : c.precision == DL_FP8 ? "FP8"
@@ -1284,6 +1297,8 @@ int dl_set_config(dl_net *net, const dl_config *cfg)
     if (cfg->max_sigma_px > 0.f && net->nh != 10)
         return fail(net, DL_ERR_UNSUPPORTED, "max_sigma_px needs a network with the uncertainty head");
     if (net->dL && (rc = check_dense_config(net, cfg))) return rc;
+    if (!net->dL && cfg->tile_queue)
+        return fail(net, DL_ERR_UNSUPPORTED, "tile_queue applies to the dense-connection kernels only");
     if (!net->dL && !conv_supported(net->C, cfg->precision, net->nh))
         return fail(net, DL_ERR_UNSUPPORTED, "C = %d does not fit this form's conv kernel", net->C);
     const float new_scale = cfg->in_scale_override > 0.f ? cfg->in_scale_override : net->in_scale;

@@ -281,6 +281,11 @@ struct DenseConvArgs {
     const float *wh, *bh;
     int nh;
     float *maps;             // planar [nh][h][w] per frame from px_off
+    // tile schedule: null = static ranges per XCD; else 8 zeroed counters, and
+    // queue_mode 1 (one atomic queue per XCD over its range) or 2 (counter 0:
+    // one queue over all tiles)
+    uint32_t *queue;
+    int queue_mode;
 };
 int dense_tile_rows();
 int dense_tile_cols();

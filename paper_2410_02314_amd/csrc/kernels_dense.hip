@@ -97,7 +97,7 @@ struct DLds {
     static constexpr int BYTES = (TILE + W + WT + WTL + WH + BIAS) * 4 + 64;
 };
 
-template <int NB, int NT, int FUSE>
+template <int NB, int NT, int FUSE, bool QUEUE>
 __global__ void __launch_bounds__(DTR * 64)
 k_dconv(DenseConvArgs a, Geometry geo)
 {
@@ -135,26 +135,42 @@ k_dconv(DenseConvArgs a, Geometry geo)
     const int64_t chunk = (T + DXCD - 1) / DXCD;
     const int64_t t0 = (int64_t)xcd * chunk, t1 = min(T, t0 + chunk);
 
-    for (int64_t ti = t0 + slot; ti < t1; ti += nslot) {
+    // tile schedule: static (tile t0 + slot, then every nslot-th of the XCD's
+    // range), or (QUEUE) claimed from an atomic queue -- the XCD's, over its
+    // range (queue_mode 1), or one over all tiles (2); a claim past the end
+    // ends the workgroup
+    const int64_t qb = a.queue_mode == 2 ? 0 : t0, qe = a.queue_mode == 2 ? T : t1;
+    for (int64_t si = t0 + slot; QUEUE || si < t1; si += nslot) {
         // the tile: frame, origin of its phase lattice, frame size and offsets
         __syncthreads();                 // the previous tile's LDS reads are done
         if (tid == 0) {
-            const int f = find_frame(a.fd, nfr, ti, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
-            const FrameDesc *fd = a.fd + f;
-            const int h = ld_const(&fd->h), w = ld_const(&fd->w);
-            int Y0, X0;
-            decode_tile(h, w, ti - ld_const(&fd->tile_start[blk]), dd, DTR, DTC, false, 8u, Y0, X0);
-            const int64_t act = ld_const(&fd->act_off), px = ld_const(&fd->px_off);
-            sdec[0] = Y0;
-            sdec[1] = X0;
-            sdec[2] = h;
-            sdec[3] = w;
-            sdec[4] = (int)(uint32_t)act;
-            sdec[5] = (int)(act >> 32);
-            sdec[6] = (int)(uint32_t)px;
-            sdec[7] = (int)(px >> 32);
+            int64_t ti = si;
+            bool valid = true;
+            if constexpr (QUEUE) {
+                ti = qb + (int64_t)atomicAdd(a.queue + (a.queue_mode == 1 ? xcd : 0), 1u);
+                valid = ti < qe;
+                sdec[8] = valid;
+            }
+            if (valid) {
+                const int f = find_frame(a.fd, nfr, ti, [blk](const FrameDesc &d) { return ld_const(&d.tile_start[blk]); });
+                const FrameDesc *fd = a.fd + f;
+                const int h = ld_const(&fd->h), w = ld_const(&fd->w);
+                int Y0, X0;
+                decode_tile(h, w, ti - ld_const(&fd->tile_start[blk]), dd, DTR, DTC, false, 8u, Y0, X0);
+                const int64_t act = ld_const(&fd->act_off), px = ld_const(&fd->px_off);
+                sdec[0] = Y0;
+                sdec[1] = X0;
+                sdec[2] = h;
+                sdec[3] = w;
+                sdec[4] = (int)(uint32_t)act;
+                sdec[5] = (int)(act >> 32);
+                sdec[6] = (int)(uint32_t)px;
+                sdec[7] = (int)(px >> 32);
+            }
         }
         __syncthreads();
+        if constexpr (QUEUE)
+            if (!__builtin_amdgcn_readfirstlane(sdec[8])) break;   // uniform: every thread reads the same flag
         const int Y0 = __builtin_amdgcn_readfirstlane(sdec[0]), X0 = __builtin_amdgcn_readfirstlane(sdec[1]);
         const int H = __builtin_amdgcn_readfirstlane(sdec[2]), W = __builtin_amdgcn_readfirstlane(sdec[3]);
         const int64_t act = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(sdec[4]) |
@@ -320,11 +336,11 @@ k_dconv(DenseConvArgs a, Geometry geo)
     }
 }
 
-template <int NB, int NT, int FUSE>
-hipError_t launch_dconv_t(const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
+template <int NB, int NT, int FUSE, bool QUEUE>
+hipError_t launch_dconv_q(const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
 {
     using L = DLds<NB, NT, FUSE>;
-    auto kern = k_dconv<NB, NT, FUSE>;
+    auto kern = k_dconv<NB, NT, FUSE, QUEUE>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -339,6 +355,12 @@ hipError_t launch_dconv_t(const DenseConvArgs &a, const Geometry &g, int ncu, hi
     grid = std::max(DXCD, grid / DXCD * DXCD);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(DTR * 64), L::BYTES, s, a, g);
     return hipGetLastError();
+}
+
+template <int NB, int NT, int FUSE>
+hipError_t launch_dconv_t(const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
+{
+    return a.queue ? launch_dconv_q<NB, NT, FUSE, true>(a, g, ncu, s) : launch_dconv_q<NB, NT, FUSE, false>(a, g, ncu, s);
 }
 
 template <int NB, int FUSE>

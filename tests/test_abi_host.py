@@ -145,7 +145,7 @@ def _create(b, **cfg):
                                  dict(gain=0.0), dict(gain=float("nan")), dict(offset=float("inf")),
                                  dict(device=-1), dict(tile_rows=5), dict(flags=0x80),
                                  dict(in_scale_override=-0.01), dict(in_scale_override=float("inf")),
-                                 dict(tile_w=-1)])
+                                 dict(tile_w=-1), dict(tile_queue=3), dict(tile_queue=-1)])
 def test_create_rejects_bad_config_before_device(cfg):
     _, _, b = blob("A")
     assert _create(b, **cfg) == dl.DL_ERR_INVALID_ARG
@@ -165,6 +165,13 @@ def test_create_refuses_what_the_dense_kernels_do_not_run(cfg):
     assert _create(b, **cfg) == dl.DL_ERR_UNSUPPORTED
     if "tile_w" not in cfg:             # (a width no form is built for is refused earlier)
         assert "dense" in dl.last_error()
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_tile_queue_is_refused_for_the_residual_kernels(q):
+    _, _, b = blob("A")
+    assert _create(b, tile_queue=q) == dl.DL_ERR_UNSUPPORTED
+    assert "tile_queue" in dl.last_error()
 
 
 def test_create_rejects_bad_blob_and_null_pointers():

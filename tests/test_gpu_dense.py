@@ -186,6 +186,31 @@ def test_rois_and_capacity_graph():
     g.close()
 
 
+@pytest.mark.parametrize("queue", [1, 2])
+def test_tile_queues_give_the_same_bits(queue):
+    """The atomic tile queues (per XCD, global) only change which workgroup
+    computes a tile: maps and records equal the static schedule's bit for bit,
+    on a batch and on an uneven ROI list, twice in a row (the counters are
+    cleared by every run)."""
+    spec, wts, net = make("D", 3)
+    _, _, netq = make("D", 3, tile_queue=queue)
+    frames = S.render_frames(3, 200, 333, "full", 61)
+    assert np.array_equal(gpu_maps(net, frames), gpu_maps(netq, frames))
+    for _ in range(2):
+        a, ca = gpu_localize(net, frames)
+        b, cb = gpu_localize(netq, frames)
+        assert np.array_equal(a, b) and np.array_equal(ca, cb)
+    rois = [torch.from_numpy(r).to(DEV) for r in S.render_rois(5, "rois", 62, shapes=[(64, 90), (7, 300), (128, 128), (1, 1), (150, 40)])]
+    outs = []
+    for n_ in (net, netq):
+        out = torch.zeros((20000, 8), dtype=torch.int32, device=DEV)
+        counts = torch.full((6,), -1, dtype=torch.int32, device=DEV)
+        n_.localize_rois_device(rois, out, counts)
+        torch.cuda.synchronize()
+        outs.append((dl.emitters_from_device(out, int(counts[-1].item())), counts.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_noalloc_entry_point_matches():
     spec, wts, net = make("D", 3)
     for n, h, w in [(2, 128, 160), (1, 64, 64)]:
