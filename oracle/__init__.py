@@ -66,7 +66,7 @@ def _L():
         _lib.or_quant_weights_fp8.argtypes = [P, i, l]
         _lib.or_split_bf16.argtypes = [P, P, l]
         _lib.or_dense_maps.restype = i
-        _lib.or_dense_maps.argtypes = [P, i, i, d, d, d, P, i, i, i, i, P, i, P]
+        _lib.or_dense_maps.argtypes = [P, i, i, d, d, d, P, i, i, i, i, P, i, i, P]
         _lib.or_preprocess.argtypes = [P, l, d, d, d, P]
         _lib.or_conv3x3.argtypes = [P, i, i, i, P, P, i, i, P]
         _lib.or_net_maps.restype = i
@@ -206,7 +206,7 @@ def net_maps(frame: np.ndarray, spec, weights: Dict[str, np.ndarray], gain=0.5,
         if _is_map(gain) or _is_map(offset):
             raise ValueError("camera maps are not supported for the dense-connection network")
         rc = _L().or_dense_maps(_p(F), h, w, gain, offset, spec.in_scale, _p(params), spec.C, len(spec.dilations),
-                                spec.layers, spec.growth, _p(dil), nh, _p(maps))
+                                spec.layers, spec.growth, _p(dil), getattr(spec, "unet", 0), nh, _p(maps))
         if rc != 0:
             raise RuntimeError("oracle net failed")
         return maps
@@ -226,6 +226,27 @@ def net_maps_batch(frames: np.ndarray, spec, weights, gain=0.5, offset=100.0, qu
     return np.stack([net_maps(f, spec, weights, gain, offset, quant) for f in frames])
 
 
+def unet_reach(spec) -> int:
+    """How far (pixels, per axis) the two-stage U-Net's output at a pixel
+    reaches into its input a0, found by following the stage's row dependencies
+    for every phase of the pixel modulo 4 (0 without a U-Net)."""
+    if not getattr(spec, "unet", 0):
+        return 0
+    reach = 0
+    for y in range(4, 8):
+        rows = set()
+        c0 = range(y - 1, y + 2)                              # final 3x3 conv at level 0
+        rows |= set(c0)                                       # its skip input a0
+        u1 = {r // 2 for r in c0}                             # up(u1) -> u1 rows
+        c1 = {q for r in u1 for q in range(r - 1, r + 2)}     # u1's 3x3 conv at level 1
+        d1 = set(c1) | {q for r in {r // 2 for r in c1} for q in range(2 * (r - 1), 2 * (r + 1) + 2)}
+        # d1 rows come from d1 (skip) and from d2 = conv(pool(d1)); d1 = conv(pool(a0))
+        for r in d1:
+            rows |= set(range(2 * (r - 1), 2 * (r + 1) + 2))
+        reach = max(reach, max(abs(r - y) for r in rows))
+    return reach
+
+
 def net_maps_window(frame: np.ndarray, spec, weights, y0: int, x0: int, hh: int, ww: int,
                     gain=0.5, offset=100.0, quant="exact", margin: Optional[int] = None) -> np.ndarray:
     """Exact maps of the output window [y0, y0+hh) x [x0, x0+ww) of a large frame.
@@ -238,8 +259,11 @@ def net_maps_window(frame: np.ndarray, spec, weights, y0: int, x0: int, hh: int,
     margin is clipped, and is at least R away elsewhere)."""
     H, W = frame.shape
     per_block = spec.layers if hasattr(spec, "growth") else 2
-    R = 1 + per_block * sum(spec.dilations) if margin is None else margin
-    cy0, cx0 = max(0, y0 - R), max(0, x0 - R)
+    R = 1 + per_block * sum(spec.dilations) + unet_reach(spec) if margin is None else margin
+    # a U-Net's pooling windows start at even pixels of every level: the crop
+    # starts at a multiple of 2^levels so they fall where they fall in the frame
+    al = 2 ** getattr(spec, "unet", 0)
+    cy0, cx0 = max(0, y0 - R) // al * al, max(0, x0 - R) // al * al
     cy1, cx1 = min(H, y0 + hh + R), min(W, x0 + ww + R)
     crop = frame[cy0:cy1, cx0:cx1]
     if _is_map(gain):

@@ -405,10 +405,95 @@ static void pointwise(const double *in, int cin, long hw, const double *W, const
     }
 }
 
-static int dense_maps_from_input(const double *x, int h, int w, const float *params, int C, int nblocks, int L,
-                                 int G, const int *dil, int nh, double *maps)
+/* The fine-grained stage read as a two-stage U-Net (paper Sec. 3.2: after
+ * feature extraction a two-stage U-Net refines the features; its sizes are
+ * not given -- the reading here): on the extractor's output a0 (C channels),
+ *   p1 = pool(a0),  d1 = ReLU(conv_1(p1))          level 1, C -> C
+ *   p2 = pool(d1),  d2 = ReLU(conv_1(p2))          level 2, C -> C
+ *   u1 = ReLU(conv_1([d1, up(d2)]))                level 1, 2C -> C
+ *   u0 = ReLU(conv_1([a0, up(u1)]))                level 0, 2C -> C
+ * and the head reads u0.  Level l + 1 of an h x w level is ceil(h/2) x
+ * ceil(w/2); pool = max over the 2 x 2 window's pixels inside the level
+ * (windows at an odd edge hold fewer); up = nearest: up(v)[y][x] = v[y/2][x/2].
+ * [u, v] concatenates channels, u first.  Convolutions zero-pad at each
+ * level's border. */
+static void pool2(const double *in, int C, int h, int w, double *out)
 {
-    if (h <= 0 || w <= 0 || C <= 0 || G <= 0 || L < 0 || nblocks < 0 || nh <= 0) return OR_ERR;
+    const int h2 = (h + 1) / 2, w2 = (w + 1) / 2;
+    for (int c = 0; c < C; ++c)
+        for (int y = 0; y < h2; ++y)
+            for (int x = 0; x < w2; ++x) {
+                double m = -INFINITY;
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const int yy = 2 * y + dy, xx = 2 * x + dx;
+                        if (yy < h && xx < w && in[((long)c * h + yy) * w + xx] > m) m = in[((long)c * h + yy) * w + xx];
+                    }
+                out[((long)c * h2 + y) * w2 + x] = m;
+            }
+}
+
+/* out [C][h][w] = nearest upsampling of in [C][ceil(h/2)][ceil(w/2)] */
+static void up2(const double *in, int C, int h, int w, double *out)
+{
+    const int h2 = (h + 1) / 2, w2 = (w + 1) / 2;
+    for (int c = 0; c < C; ++c)
+        for (int y = 0; y < h; ++y)
+            for (int x = 0; x < w; ++x) out[((long)c * h + y) * w + x] = in[((long)c * h2 + y / 2) * w2 + x / 2];
+}
+
+static void relu_inplace(double *v, long n)
+{
+    for (long k = 0; k < n; ++k) v[k] = v[k] > 0 ? v[k] : 0.0;
+}
+
+/* the U-Net stage on a0 [C][h][w] -> u0 [C][h][w]; p points at its
+ * parameters (d1 w, b; d2 w, b; u1 w, b; u0 w, b); returns the parameters
+ * after them, or NULL when memory runs out */
+static const float *unet_stage(const double *a0, int C, int h, int w, const float *p, double *u0)
+{
+    const int h1 = (h + 1) / 2, w1 = (w + 1) / 2, h2 = (h1 + 1) / 2, w2 = (w1 + 1) / 2;
+    const long n0 = (long)h * w, n1 = (long)h1 * w1, n2 = (long)h2 * w2;
+    double *p1 = malloc(sizeof(double) * C * n1), *c1 = malloc(sizeof(double) * 2 * C * n1);
+    double *p2 = malloc(sizeof(double) * C * n2), *d2 = malloc(sizeof(double) * C * n2);
+    double *u1 = malloc(sizeof(double) * C * n1), *c0 = malloc(sizeof(double) * 2 * C * n0);
+    double *Wd = malloc(sizeof(double) * (long)C * 2 * C * 9), *bd = malloc(sizeof(double) * C);
+    const float *ret = NULL;
+    if (!p1 || !c1 || !p2 || !d2 || !u1 || !c0 || !Wd || !bd) goto done;
+    /* down: d1 goes to the first half of c1, d2 to p2's partner */
+    pool2(a0, C, h, w, p1);
+    promote(p, (long)C * C * 9, Wd); p += (long)C * C * 9;
+    promote(p, C, bd); p += C;
+    or_conv3x3(p1, C, h1, w1, Wd, bd, C, 1, c1);
+    relu_inplace(c1, C * n1);
+    pool2(c1, C, h1, w1, p2);
+    promote(p, (long)C * C * 9, Wd); p += (long)C * C * 9;
+    promote(p, C, bd); p += C;
+    or_conv3x3(p2, C, h2, w2, Wd, bd, C, 1, d2);
+    relu_inplace(d2, C * n2);
+    /* up: c1 = [d1, up(d2)], c0 = [a0, up(u1)] */
+    up2(d2, C, h1, w1, c1 + C * n1);
+    promote(p, (long)C * 2 * C * 9, Wd); p += (long)C * 2 * C * 9;
+    promote(p, C, bd); p += C;
+    or_conv3x3(c1, 2 * C, h1, w1, Wd, bd, C, 1, u1);
+    relu_inplace(u1, C * n1);
+    memcpy(c0, a0, sizeof(double) * C * n0);
+    up2(u1, C, h, w, c0 + C * n0);
+    promote(p, (long)C * 2 * C * 9, Wd); p += (long)C * 2 * C * 9;
+    promote(p, C, bd); p += C;
+    or_conv3x3(c0, 2 * C, h, w, Wd, bd, C, 1, u0);
+    relu_inplace(u0, C * n0);
+    ret = p;
+done:
+    free(p1); free(c1); free(p2); free(d2); free(u1); free(c0); free(Wd); free(bd);
+    return ret;
+}
+
+static int dense_maps_from_input(const double *x, int h, int w, const float *params, int C, int nblocks, int L,
+                                 int G, const int *dil, int unet, int nh, double *maps)
+{
+    if (h <= 0 || w <= 0 || C <= 0 || G <= 0 || L < 0 || nblocks < 0 || nh <= 0 || !(unet == 0 || unet == 2))
+        return OR_ERR;
     const long hw = (long)h * w;
     const int CT = C + L * G;
     double *cat = malloc(sizeof(double) * hw * CT);
@@ -444,6 +529,15 @@ static int dense_maps_from_input(const double *x, int h, int w, const float *par
         memcpy(cat, t, sizeof(double) * hw * C);
         free(t);
     }
+    if (unet) {
+        double *u0 = malloc(sizeof(double) * hw * C);
+        if (!u0 || !(p = unet_stage(cat, C, h, w, p, u0))) {
+            free(u0); free(cat); free(Wd); free(bd);
+            return OR_ERR;
+        }
+        memcpy(cat, u0, sizeof(double) * hw * C);
+        free(u0);
+    }
     promote(p, (long)nh * C, Wd); p += (long)nh * C;
     promote(p, nh, bd); p += nh;
     pointwise(cat, C, hw, Wd, bd, nh, 0, maps);
@@ -451,14 +545,16 @@ static int dense_maps_from_input(const double *x, int h, int w, const float *par
     return OR_OK;
 }
 
+/* unet: 0 (the head reads the extractor's output) or 2 (the two-stage U-Net
+ * above runs first; its parameters follow the blocks') */
 int or_dense_maps(const uint16_t *F, int h, int w, double gain, double offset, double in_scale, const float *params,
-                  int C, int nblocks, int L, int G, const int *dil, int nh, double *maps)
+                  int C, int nblocks, int L, int G, const int *dil, int unet, int nh, double *maps)
 {
     if (h <= 0 || w <= 0) return OR_ERR;
     double *x = malloc(sizeof(double) * (long)h * w);
     if (!x) return OR_ERR;
     or_preprocess(F, (long)h * w, gain, offset, in_scale, x);
-    int rc = dense_maps_from_input(x, h, w, params, C, nblocks, L, G, dil, nh, maps);
+    int rc = dense_maps_from_input(x, h, w, params, C, nblocks, L, G, dil, unet, nh, maps);
     free(x);
     return rc;
 }

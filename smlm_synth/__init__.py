@@ -338,7 +338,11 @@ class DenseSpec:
     channels) and the i earlier layers' outputs (``growth`` channels each) and
     giving ``growth`` channels (+ bias, ReLU); a 1x1 transition over the whole
     concatenation (C + layers * growth -> C, + bias, ReLU) gives the block's
-    output.  Then the 1x1 head C -> head_outputs."""
+    output.  With ``unet`` = 2, a two-stage U-Net follows the blocks (2x2 max
+    pooling, 3x3 convolutions C -> C on the way down at levels 1 and 2,
+    nearest upsampling and 3x3 convolutions over [skip, upsampled] 2C -> C on
+    the way up at levels 1 and 0, each + bias, ReLU).  Then the 1x1 head
+    C -> head_outputs."""
     name: str
     C: int
     dilations: Tuple[int, ...]
@@ -348,6 +352,7 @@ class DenseSpec:
     z_scale: float = 700.0
     ph_scale: float = 1000.0
     head_outputs: int = 5
+    unet: int = 0
 
 
 NET_A = NetSpec("A", 32, (1, 2, 4))
@@ -358,7 +363,13 @@ NET_BU = NetSpec("BU", 48, (1, 2, 4, 8, 16), head_outputs=10)
 # the paper's feature extractor as read here: one coarse-grained and three
 # context dense blocks at dilations 2, 4, 8, 16
 NET_D = DenseSpec("D", 32, (2, 4, 8, 16))
-NETS = {"A": NET_A, "B": NET_B, "AU": NET_AU, "BU": NET_BU, "D": NET_D}
+# ... followed by the fine-grained stage, a two-stage U-Net
+NET_DU = DenseSpec("DU", 32, (2, 4, 8, 16), unet=2)
+NETS = {"A": NET_A, "B": NET_B, "AU": NET_AU, "BU": NET_BU, "D": NET_D, "DU": NET_DU}
+# pixels (per axis) a two-stage U-Net's output reaches into its input: its
+# final 3x3 conv, and through pooling and nearest upsampling the level-1 and
+# level-2 convolutions
+UNET_REACH = 12
 
 
 def is_dense(spec) -> bool:
@@ -375,6 +386,10 @@ def tensor_layout(spec) -> List[Tuple[str, Tuple[int, ...]]]:
             for i in range(L):
                 lay += [(f"blk{k}.l{i}.w", (G, C + i * G, 3, 3)), (f"blk{k}.l{i}.b", (G,))]
             lay += [(f"blk{k}.t.w", (C, C + L * G)), (f"blk{k}.t.b", (C,))]
+        if spec.unet:
+            lay += [("unet.d1.w", (C, C, 3, 3)), ("unet.d1.b", (C,)), ("unet.d2.w", (C, C, 3, 3)), ("unet.d2.b", (C,)),
+                    ("unet.u1.w", (C, 2 * C, 3, 3)), ("unet.u1.b", (C,)), ("unet.u0.w", (C, 2 * C, 3, 3)),
+                    ("unet.u0.b", (C,))]
         nh = spec.head_outputs
         return lay + [("head.w", (nh, C)), ("head.b", (nh,))]
     for k in range(len(spec.dilations)):
@@ -395,7 +410,9 @@ def net_flops_per_px(spec) -> int:
     if is_dense(spec):
         G, L = spec.growth, spec.layers
         blk = sum(9 * (C + i * G) * G for i in range(L)) + (C + L * G) * C
-        return 2 * (9 * C + B * blk + spec.head_outputs * C)
+        # the U-Net per level-0 pixel: level l holds 1/4^l of the pixels
+        unet = (9 * C * C / 4 + 9 * C * C / 16 + 9 * 2 * C * C / 4 + 9 * 2 * C * C) if spec.unet else 0
+        return int(2 * (9 * C + B * blk + unet + spec.head_outputs * C))
     macs = 9 * C + B * 2 * 9 * C * C + spec.head_outputs * C
     return 2 * macs
 
@@ -407,7 +424,7 @@ def block_flops_per_px(spec: NetSpec) -> int:
 
 def receptive_radius(spec) -> int:
     if is_dense(spec):
-        return 1 + spec.layers * sum(spec.dilations)
+        return 1 + spec.layers * sum(spec.dilations) + (UNET_REACH if spec.unet else 0)
     return 1 + 2 * sum(spec.dilations)
 
 
@@ -487,9 +504,9 @@ def serialize_weights(spec, weights: Dict[str, np.ndarray]) -> bytes:
     if is_dense(spec):
         # 'DLD1' (80 bytes): magic, u32 version, u32 C, u32 nblocks, u32 layers,
         # u32 growth, u32 dilation[8], f32 in_scale, f32 z_scale, f32 ph_scale,
-        # u32 head outputs, 8 zero bytes
-        head = DLD_MAGIC + struct.pack("<IIIII8IfffI8x", 1, spec.C, nb, spec.layers, spec.growth, *dil,
-                                       spec.in_scale, spec.z_scale, spec.ph_scale, spec.head_outputs)
+        # u32 head outputs, u32 U-Net levels (0 or 2), 4 zero bytes
+        head = DLD_MAGIC + struct.pack("<IIIII8IfffII4x", 1, spec.C, nb, spec.layers, spec.growth, *dil,
+                                       spec.in_scale, spec.z_scale, spec.ph_scale, spec.head_outputs, spec.unet)
         assert len(head) == 80
         return head + body
     # the last header word: 0 for the 5-output head, else the head's outputs

@@ -32,7 +32,7 @@ import numpy as np
 import oracle
 import smlm_synth as S
 
-CAL_SEEDS = {"A": 1, "B": 2, "D": 3}
+CAL_SEEDS = {"A": 1, "B": 2, "D": 3, "DU": 3}
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "calibration.json")
 
 

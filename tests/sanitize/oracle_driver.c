@@ -22,6 +22,8 @@ int or_net_maps(const uint16_t *F, int h, int w, double gain, double offset, dou
                 int C, int nblocks, const int *dil, int quant, int nh, double *maps);
 int or_net_maps_cam(const uint16_t *F, int h, int w, const double *gain, const double *offset, double in_scale,
                     const float *params, int C, int nblocks, const int *dil, int quant, int nh, double *maps);
+int or_dense_maps(const uint16_t *F, int h, int w, double gain, double offset, double in_scale, const float *params,
+                  int C, int nblocks, int L, int G, const int *dil, int unet, int nh, double *maps);
 void or_detect(const double *logit, int h, int w, double tau, uint8_t *det);
 void or_gate_pool(const double *x, int th, int tw, int pool, double *p);
 void or_gate_forward(const double *pooled, int n, int ph, int pw, const double *theta, double *g);
@@ -78,6 +80,22 @@ int main(void)
         CHECK(finite_all(maps, (long)NH * H * W));
     }
     CHECK(or_net_maps(F, H, W, 0.5, 100.0, 0.01, params, C, NB, dil, 4, NH, maps) != 0);   /* bad mode */
+    {
+        /* dense-connection net, 2 blocks of 2 layers of growth 16, with and
+         * without the two-stage U-Net, on an odd-sized frame */
+        enum { DL = 2, DG = 16, CT = C + DL * DG };
+        long nd = (long)C * 9 + C + (long)NH * C + NH + 4L * C + 2L * C * C * 9 + 2L * C * 2 * C * 9;
+        for (int i = 0; i < DL; ++i) nd += NB * ((long)DG * (C + i * DG) * 9 + DG);
+        nd += NB * ((long)C * CT + C);
+        float *pd = malloc(sizeof(float) * nd);
+        for (long i = 0; i < nd; ++i) pd[i] = (float)(0.3 * (urand() - 0.5));
+        for (int unet = 0; unet <= 2; unet += 2) {
+            CHECK(or_dense_maps(F, H, W, 0.5, 100.0, 0.01, pd, C, NB, DL, DG, dil, unet, NH, maps) == 0);
+            CHECK(finite_all(maps, (long)NH * H * W));
+        }
+        CHECK(or_dense_maps(F, H, W, 0.5, 100.0, 0.01, pd, C, NB, DL, DG, dil, 1, NH, maps) != 0);   /* bad U-Net */
+        free(pd);
+    }
     uint8_t det[H * W];
     or_detect(maps, H, W, -0.5, det);
     double x[H * W], lo[H * W];

@@ -4,7 +4,7 @@ or residual, a wrong sign, a reversed tie-break, truncating BF16 rounding, an
 FP8 group scale one power of two off, an FP8 weight scale taken over the
 whole tensor or applied the wrong way, an FP8 rounding point dropped or
 added, the gate's gradient sent to the last maximum, swapped camera maps, a
-dropped head bias.  It builds the copy with the
+dropped head bias, the dense blocks' and the U-Net's wiring.  It builds the copy with the
 oracle's own flags, points the oracle module at it, and checks that at least
 one of the named pins fails.  The planted copy lives in a temporary directory;
 the real oracle is restored afterwards.
@@ -107,6 +107,18 @@ MUTANTS = [
      "        pointwise(cat, CT, hw, Wd, bd, C, 1, t);",
      "        pointwise(cat, CT, hw, Wd, bd, C, 0, t);",
      [(DN.test_dense_net_matches_torch_composition, (S.NET_D,))]),
+    ("U-Net pooling reads one row of each window",
+     "                for (int dy = 0; dy < 2; ++dy)",
+     "                for (int dy = 0; dy < 1; ++dy)",
+     [(DN.test_unet_matches_torch_composition, (DN.UNET_SMALL, 38, 29))]),
+    ("U-Net upsampling takes the right neighbour",
+     "out[((long)c * h + y) * w + x] = in[((long)c * h2 + y / 2) * w2 + x / 2];",
+     "out[((long)c * h + y) * w + x] = in[((long)c * h2 + y / 2) * w2 + ((x + 1) / 2 < w2 ? (x + 1) / 2 : w2 - 1)];",
+     [(DN.test_unet_matches_torch_composition, (DN.UNET_SMALL, 38, 29))]),
+    ("U-Net skip and upsampled halves swapped",
+     "    memcpy(c0, a0, sizeof(double) * C * n0);\n    up2(u1, C, h, w, c0 + C * n0);",
+     "    memcpy(c0 + C * n0, a0, sizeof(double) * C * n0);\n    up2(u1, C, h, w, c0);",
+     [(DN.test_unet_matches_torch_composition, (DN.UNET_SMALL, 38, 29))]),
     ("gate pool takes the last maximum",
      "if (h2[(long)c * hw + k] > h2[(long)c * hw + a]) a = k;",
      "if (h2[(long)c * hw + k] >= h2[(long)c * hw + a]) a = k;",
