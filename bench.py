@@ -83,10 +83,11 @@ def main():
     ap.add_argument("--sparse-layout", default="iid", choices=["iid", "cell"],
                     help="sparse workload: empty 256^2 tiles chosen independently (iid) or around one "
                          "compact occupied region (cell)")
-    ap.add_argument("--net", default="B", choices=["B", "BU", "D"],
+    ap.add_argument("--net", default="B", choices=["B", "BU", "D", "DU"],
                     help="full workload: net B with the 5-output head, BU, the same net with the "
-                         "10-output head (per-pixel uncertainties and background), or D, the "
-                         "dense-connection network (FP32, scalar camera model)")
+                         "10-output head (per-pixel uncertainties and background), D, the "
+                         "dense-connection network, or DU, D followed by the two-stage U-Net (FP32, scalar "
+                         "camera model)")
     ap.add_argument("--camera", default="scmos", choices=["scmos", "scalar"],
                     help="full and pipeline workloads: frames from a seeded sCMOS sensor whose per-pixel gain "
                          "and offset maps the net is given (scmos), or the scalar camera model (scalar)")
@@ -109,14 +110,14 @@ def main():
         run_workload(args)
         return
 
-    if args.net == "D":
+    if args.net in ("D", "DU"):
         # the dense kernels run FP32 with the scalar camera model only
         if args.precision != "fp32" or args.camera != "scalar":
-            print("--net D runs with --precision fp32 --camera scalar", file=sys.stderr)
+            print("--net D and DU run with --precision fp32 --camera scalar", file=sys.stderr)
             sys.exit(2)
         args.forms = ""
     # inputs first, before anything touches the GPU (workers are forked)
-    spec, w = S.make_net(args.net, 3 if args.net == "D" else 2)
+    spec, w = S.make_net(args.net, 3 if args.net in ("D", "DU") else 2)
     n, side = args.frames, args.size
     t0 = time.time()
     cam = S.scmos_camera(side, side, 1002) if args.camera == "scmos" else None
@@ -210,7 +211,7 @@ def net_text(spec):
     d = ",".join(str(x) for x in spec.dilations)
     if S.is_dense(spec):
         return (f"dense blocks: C={spec.C}, {spec.layers} 3x3 layers of growth {spec.growth} + 1x1 transition "
-                f"per block, d={d}")
+                f"per block, d={d}" + (", then the two-stage U-Net" if spec.unet else ""))
     return f"C={spec.C}, d={d}"
 
 
@@ -248,14 +249,22 @@ def dense_roofline(spec, prof, total_px, steps):
         if not t_n:
             continue
         ts = t_ms / t_n * 1e-3
-        tf = (2.0 * 9 * G * cin + 2.0 * CT * C + (2.0 * C * nh if head else 0.0)) * total_px
-        tb = (4.0 * (cin + C) + (4.0 * nh - 4.0 * C if head else 0.0)) * total_px
-        fused.append({"kernel": f"k_dconv fp32 fused (3x3 {cin} -> {G}, 1x1 transition {CT} -> {C}"
-                                + (f", head {C} -> {nh})" if head else ")"),
-                      "launches_per_step": t_n // steps, "avg_launch_ms": round(ts * 1e3, 3),
+        if head and spec.unet:       # the U-Net's last conv (2C -> C at level 0) with the head
+            tf = (2.0 * 9 * 2 * C * C + 2.0 * C * nh) * total_px
+            tb = (4.0 * 2 * C + 4.0 * nh) * total_px
+            name = f"k_dconv fp32 fused (U-Net 3x3 {2 * C} -> {C}, head {C} -> {nh})"
+        else:
+            tf = (2.0 * 9 * G * cin + 2.0 * CT * C + (2.0 * C * nh if head else 0.0)) * total_px
+            tb = (4.0 * (cin + C) + (4.0 * nh - 4.0 * C if head else 0.0)) * total_px
+            name = (f"k_dconv fp32 fused (3x3 {cin} -> {G}, 1x1 transition {CT} -> {C}"
+                    + (f", head {C} -> {nh})" if head else ")"))
+        fused.append({"kernel": name, "launches_per_step": t_n // steps, "avg_launch_ms": round(ts * 1e3, 3),
                       "tflop_s": round(tf / ts / 1e12, 2), "mfma_frac": round(tf / ts / 1e12 / PEAKS["fp32"], 4),
                       "gb_s": round(tb / ts / 1e9, 1)})
     roof["fused_last_layers"] = fused
+    if spec.unet and prof["unet"][1]:
+        # pooling, upsampling and the level-1 and level-2 convolutions, per step
+        roof["unet_stage_ms_per_step"] = round(prof["unet"][0] / steps, 3)
     return roof
 
 

@@ -139,6 +139,8 @@ typedef struct {
     int32_t head_outputs;       /* 5, or 10 with the uncertainty planes          */
     int16_t dense_layers;       /* DLD1: 3x3 layers per block; 0 for DLW1        */
     int16_t dense_growth;       /* DLD1: channels each layer adds; 0 for DLW1    */
+    int32_t unet_levels;        /* DLD1: 2 with the two-stage U-Net, else 0      */
+    int32_t reserved2_[3];
 } dl_net_info;
 
 /* Library ABI version (DL_ABI_VERSION). */
@@ -163,14 +165,23 @@ int dl_default_config(dl_config *cfg);
  * Sec. 4.1.2: one dilation per block):
  *   header (80 B): char magic[4] = "DLD1"; u32 version = 1; u32 C; u32 nblocks;
  *   u32 L (3x3 layers per block); u32 G (growth); u32 dilation[8]; f32 in_scale;
- *   f32 z_scale; f32 ph_scale; u32 nh (5 or 10); 8 bytes ignored;
+ *   f32 z_scale; f32 ph_scale; u32 nh (5 or 10); u32 U-Net levels (0 or 2);
+ *   4 bytes ignored;
  *   then FP32 tensors: stem.w [C][1][3][3], stem.b [C]; for each block, for
  *   i = 0 .. L-1: w [G][C + i G][3][3], b [G]; then the transition w [C][C + L G],
- *   b [C]; head.w [nh][C], head.b [nh].
+ *   b [C]; with the U-Net: d1.w [C][C][3][3], d1.b [C], d2.w [C][C][3][3],
+ *   d2.b [C], u1.w [C][2C][3][3], u1.b [C], u0.w [C][2C][3][3], u0.b [C];
+ *   head.w [nh][C], head.b [nh].
  * Network: a = ReLU(conv_1(x)); per block with dilation d, cat = [a] and for
- * each layer cat = [cat, ReLU(conv_d(cat))], then a = ReLU(1x1(cat));
- * maps = head(a).  Supported: C and G in {16, 32}, 1 <= L <= 8, 1 <= nblocks
- * <= 8, dilations 1..64; FP32 only (other precisions, the tile gate, camera
+ * each layer cat = [cat, ReLU(conv_d(cat))], then a = ReLU(1x1(cat)).  The
+ * two-stage U-Net (Sec. 3.2: fine-grained processing after the extractor):
+ * d1 = ReLU(conv_1(pool(a))), d2 = ReLU(conv_1(pool(d1))) at levels 1 and 2,
+ * u1 = ReLU(conv_1([d1, up(d2)])), a = ReLU(conv_1([a, up(u1)])), where pool
+ * is a 2 x 2 max (level l + 1 is ceil(h/2) x ceil(w/2) of level l; an edge
+ * window takes the pixels it has), up is nearest (up(v)[y][x] = v[y/2][x/2])
+ * and [u, v] concatenates channels.  maps = head(a).  Supported: C and G in
+ * {16, 32}, 1 <= L <= 8, 1 <= nblocks <= 8 (7 with the U-Net), dilations
+ * 1..64; FP32 only; with the U-Net, no capacity ROI graph (other precisions, the tile gate, camera
  * maps, the autotuner and dl_debug_conv_layer are DL_ERR_UNSUPPORTED).
  * The blob is copied; the caller keeps ownership.  cfg may be NULL (defaults).
  * *out receives a handle the caller frees with dl_destroy_net.
@@ -493,7 +504,9 @@ enum {
     DL_STAGE_GATE = 6,       /* tile gate inference and tile selection        */
     DL_STAGE_CONV_1X1 = 7,   /* DLD1: a block's last layer fused with its 1x1 */
                              /* transition (all blocks but the last)          */
-    DL_NSTAGES = 8
+    DL_STAGE_UNET = 8,       /* DLD1 U-Net: pooling, upsampling and its       */
+                             /* convolutions but the last (which is CONV_HEAD)*/
+    DL_NSTAGES = 10
 };
 int dl_profile_enable(dl_net *net, int on);
 int dl_profile_read(dl_net *net, double *ms /*[DL_NSTAGES]*/, int64_t *launches /*[DL_NSTAGES]*/);

@@ -31,8 +31,8 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
 DL_FLAG_GATE = 1
 NOALLOC_SCRATCH_BYTES = 64 << 20      # DL_NOALLOC_SCRATCH_BYTES
 NOALLOC_MAX_FRAMES = 64               # DL_NOALLOC_MAX_FRAMES
-STAGES = ("stem", "conv", "conv_head", "detect", "scan", "emit", "gate", "conv_1x1")
-NSTAGES = 8
+STAGES = ("stem", "conv", "conv_head", "detect", "scan", "emit", "gate", "conv_1x1", "unet")
+NSTAGES = 10
 
 EMITTER_DTYPE = np.dtype([("frame", "<i4"), ("row", "<i4"), ("col", "<i4"), ("x_px", "<f4"),
                           ("y_px", "<f4"), ("z_nm", "<f4"), ("photons", "<f4"), ("prob", "<f4")])
@@ -60,7 +60,7 @@ class DLNetInfo(ctypes.Structure):
                 ("in_scale", ctypes.c_float), ("z_scale", ctypes.c_float), ("ph_scale", ctypes.c_float),
                 ("receptive_radius", ctypes.c_int32), ("nparams", ctypes.c_int64),
                 ("head_outputs", ctypes.c_int32), ("dense_layers", ctypes.c_int16),
-                ("dense_growth", ctypes.c_int16)]
+                ("dense_growth", ctypes.c_int16), ("unet_levels", ctypes.c_int32), ("reserved2_", ctypes.c_int32 * 3)]
 
 
 class DLTuneResult(ctypes.Structure):
@@ -233,7 +233,7 @@ def inspect_weights(weights: bytes) -> dict:
     return {"C": info.C, "nblocks": info.nblocks, "dilations": tuple(info.dilation[:info.nblocks]),
             "in_scale": info.in_scale, "z_scale": info.z_scale, "ph_scale": info.ph_scale,
             "receptive_radius": info.receptive_radius, "nparams": info.nparams, "head_outputs": info.head_outputs,
-            "dense_layers": info.dense_layers, "dense_growth": info.dense_growth}
+            "dense_layers": info.dense_layers, "dense_growth": info.dense_growth, "unet_levels": info.unet_levels}
 
 
 def create_net(weights: bytes, **cfg) -> "Net":

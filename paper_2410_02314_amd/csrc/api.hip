@@ -48,12 +48,14 @@ size_t param_count(int C, int nb, int nh)
 
 // dense-connection network: stem, per block L layers (G x (C + i G) x 3 x 3 + G)
 // and a transition (C x (C + L G) + C), head
-size_t dense_param_count(int C, int nb, int L, int G, int nh)
+size_t dense_param_count(int C, int nb, int L, int G, int nh, int unet)
 {
     size_t blk = 0;
     for (int i = 0; i < L; ++i) blk += (size_t)G * (C + i * G) * 9 + G;
     blk += (size_t)C * (C + L * G) + C;
-    return (size_t)C * 9 + C + (size_t)nb * blk + (size_t)nh * C + nh;
+    // the U-Net: two C -> C and two 2C -> C 3x3 convolutions
+    const size_t un = unet ? 2 * ((size_t)C * C * 9 + C) + 2 * ((size_t)C * 2 * C * 9 + C) : 0;
+    return (size_t)C * 9 + C + (size_t)nb * blk + un + (size_t)nh * C + nh;
 }
 
 }  // namespace
@@ -142,6 +144,7 @@ struct dl_net {
     // conv in run order ([block][layer 0 .. L-1, transition]) at float
     // offsets dense_w / dense_b of d_dense, then the head's (rows padded to 16)
     int dL = 0, dG = 0;
+    int unet = 0;                   // U-Net levels after the dense blocks: 0 or 2
     float *d_dense = nullptr;
     std::vector<size_t> dense_w, dense_b;
     size_t dense_head_w = 0;
@@ -315,7 +318,35 @@ void build_geometry(const dl_net *net, int n, const int *hs, const int *ws_, con
         if (d.h > g.maxh) g.maxh = d.h;
     }
     for (int b = 0; b < net->nb; ++b) g.max_tiles = std::max(g.max_tiles, g.tiles[b]);
+    if (net->unet) {
+        // the U-Net's last convolution (level 0, d = 1) in tile slot nblocks;
+        // levels 1 and 2 get descriptors of their own after the n frames'
+        const int nb = net->nb;
+        for (int f = 0; f < n; ++f) {
+            fd[f].tile_start[nb] = g.tiles[nb];
+            g.tiles[nb] += conv_tiles(fd[f].h, fd[f].w, 1, g.trb[nb], g.tc);
+        }
+        g.lv_pts[0] = g.total_act;
+        g.lv_tiles[0] = g.tiles[nb];
+        fd.resize((size_t)3 * n);
+        for (int l = 1; l <= 2; ++l)
+            for (int f = 0; f < n; ++f) {
+                const FrameDesc &up = fd[(size_t)(l - 1) * n + f];
+                FrameDesc &d = fd[(size_t)l * n + f];
+                std::memset(&d, 0, sizeof d);
+                d.h = (up.h + 1) / 2;
+                d.w = (up.w + 1) / 2;
+                d.act_off = g.lv_pts[l];
+                d.tile_start[0] = g.lv_tiles[l];
+                g.lv_pts[l] += (int64_t)d.h * d.w;
+                g.lv_tiles[l] += conv_tiles(d.h, d.w, 1, g.tr, g.tc);
+            }
+        for (int l = 0; l <= 2; ++l) g.max_tiles = std::max(g.max_tiles, g.lv_tiles[l]);
+    }
 }
+
+// frame descriptors per frame: the U-Net's levels 1 and 2 have their own
+int desc_per_frame(const dl_net *net) { return net->unet ? 3 : 1; }
 
 struct Plan {
     char *ws = nullptr;             // workspace base the offsets refer to
@@ -324,6 +355,7 @@ struct Plan {
     // block's layout, so it cannot overwrite its own input in place)
     size_t act0 = 0, act1 = 0, act2 = 0, maps = 0, mask = 0, rc = 0, roff = 0, total = 0;
     size_t queue = 0;               // dense tile queues: 8 counters per conv launch (tile_queue != 0)
+    size_t unet = 0;                // U-Net levels 1 and 2: 96 floats per level-1 point, 64 per level-2 point
     bool gated = false;
     size_t pooled = 0, glog = 0, keep = 0, lists = 0, lcount = 0;
 };
@@ -351,6 +383,9 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     p.roff = o; o = align_up(o + (size_t)(g.total_rows + 1) * 4);
     if (net->dL && net->cfg.tile_queue) {
         p.queue = o; o = align_up(o + (size_t)net->nb * net->dL * 8 * 4);
+    }
+    if (net->unet) {
+        p.unet = o; o = align_up(o + ((size_t)96 * g.lv_pts[1] + (size_t)64 * g.lv_pts[2]) * 4);
     }
     if (gated_run(net)) {
         const int L = 2 * net->nb;
@@ -478,6 +513,12 @@ int pack_dense(dl_net *net)
         for (int i = 0; i < L; ++i) put(G, C + i * G, 9);
         put(C, CT, 1);
     }
+    if (net->unet) {                    // d1, d2 (C -> C), u1, u0 (2C -> C)
+        put(C, C, 9);
+        put(C, C, 9);
+        put(C, 2 * C, 9);
+        put(C, 2 * C, 9);
+    }
     // the head (fused into the last block's last layer) as a 16-row 1x1 conv
     std::vector<float> head16((size_t)16 * C, 0.f);
     std::memcpy(head16.data(), p, sizeof(float) * net->nh * C);
@@ -578,6 +619,60 @@ int run_gate(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &
     return DL_OK;
 }
 
+// The two-stage U-Net on the extractor's output a0 (channels 0 .. C-1 of B0,
+// points of 2C floats at level 0).  Level buffers: B1 [d1 | x] (2C floats per
+// level-1 point; x is pool(a0), later up(d2)), B2 [d2 | pool(d1)] (2C per
+// level-2 point), U1 (C per level-1 point); B0's channels C .. 2C-1 take
+// up(u1), and the last convolution reads [a0, up(u1)] with the head fused.
+int run_unet(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, float *B0, float *maps,
+             hipStream_t s)
+{
+    const int C = net->C, n = g.nf, C2 = 2 * C;
+    const FrameDesc *fd0 = d_fd, *fd1 = d_fd + n, *fd2 = d_fd + 2 * (size_t)n;
+    float *B1 = reinterpret_cast<float *>(p.ws + p.unet);
+    float *B2 = B1 + (size_t)C2 * g.lv_pts[1];
+    float *U1 = B2 + (size_t)C2 * g.lv_pts[2];
+    Geometry g1 = g, g2 = g;
+    g1.tiles[0] = g.lv_tiles[1];
+    g2.tiles[0] = g.lv_tiles[2];
+    const size_t k0 = (size_t)net->nb * (net->dL + 1);   // the U-Net's convs in run order
+    auto conv = [&](const FrameDesc *fd, const Geometry &gg, int blk, const float *in, int cin, float *out, int cso,
+                    size_t k, int fuse) {
+        DenseConvArgs a{};
+        a.in = in;
+        a.csi = C2;
+        a.cin = cin;
+        a.out = out;
+        a.cso = cso;
+        a.co = 0;
+        a.w = net->d_dense + net->dense_w[k];
+        a.bias = net->d_dense + net->dense_b[k];
+        a.fd = fd;
+        a.d = 1;
+        a.blk = blk;
+        if (fuse) {
+            a.wh = net->d_dense + net->dense_head_w;
+            a.bh = net->d_head + (size_t)net->nh * C;
+            a.nh = net->nh;
+            a.maps = maps;
+        }
+        return launch_dconv(C / 16, fuse, 1, a, gg, net->ncu, s);
+    };
+    {
+        StageTimer t(net, DL_STAGE_UNET, s);
+        HIPCHK(net, launch_pool2(fd0, fd1, n, g.lv_pts[1], B0, C2, B1 + C, C2, C, s));
+        HIPCHK(net, conv(fd1, g1, 0, B1 + C, C, B1, C2, k0, 0));                  // d1
+        HIPCHK(net, launch_pool2(fd1, fd2, n, g.lv_pts[2], B1, C2, B2 + C, C2, C, s));
+        HIPCHK(net, conv(fd2, g2, 0, B2 + C, C, B2, C2, k0 + 1, 0));              // d2
+        HIPCHK(net, launch_up2(fd2, fd1, n, g.lv_pts[1], B2, C2, B1 + C, C2, C, s));
+        HIPCHK(net, conv(fd1, g1, 0, B1, C2, U1, C, k0 + 2, 0));                  // u1
+        HIPCHK(net, launch_up2(fd1, fd0, n, g.lv_pts[0], U1, C, B0 + C, C2, C, s));
+    }
+    StageTimer t(net, DL_STAGE_CONV_HEAD, s);
+    HIPCHK(net, conv(fd0, g, net->nb, B0, C2, nullptr, 0, k0 + 3, 3));             // u0 + head
+    return DL_OK;
+}
+
 // Dense networks: stem into channels 0 .. C-1 of buffer A; per block, each
 // layer appends its G channels to A, and the last one, fused with the block's
 // transition, writes the next block's input into B (channels 0 .. C-1), after
@@ -598,7 +693,7 @@ int run_dense(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan 
         const size_t k0 = (size_t)b * (L + 1);          // this block's first conv in run order
         for (int i = 0; i < L; ++i) {
             const bool last = i == L - 1;
-            const int fuse = !last ? 0 : b == net->nb - 1 ? 2 : 1;
+            const int fuse = !last ? 0 : b == net->nb - 1 && !net->unet ? 2 : 1;
             DenseConvArgs a{};
             a.in = A;
             a.csi = CT;
@@ -619,7 +714,7 @@ int run_dense(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan 
                 a.wt = net->d_dense + net->dense_w[k0 + L];
                 a.bt = net->d_dense + net->dense_b[k0 + L];
                 a.tout = B;
-                a.cst = CT;
+                a.cst = b == net->nb - 1 ? 2 * C : CT;   // the U-Net's [a0, up(u1)] at level 0
             }
             if (fuse == 2) {
                 a.wh = net->d_dense + net->dense_head_w;
@@ -632,6 +727,7 @@ int run_dense(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan 
         }
         std::swap(A, B);
     }
+    if (net->unet) return run_unet(net, d_fd, g, p, A, maps, s);
     return DL_OK;
 }
 
@@ -1042,18 +1138,22 @@ static int parse_dense(const unsigned char *b, size_t nbytes, dl_net_info *info,
     const uint32_t version = hdr[0], C = hdr[1], nb = hdr[2], L = hdr[3], G = hdr[4];
     float sc[3];
     std::memcpy(sc, b + 56, sizeof sc);
-    uint32_t nh;
+    uint32_t nh, unet;
     std::memcpy(&nh, b + 68, 4);
+    std::memcpy(&unet, b + 72, 4);
     if (version != 1) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "unsupported weights version %u", version);
     if (nh != 5 && nh != 10) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "head outputs %u: 5 or 10 supported", nh);
     if (nb < 1 || nb > MAXBLK) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "nblocks %u outside 1..%d", nb, MAXBLK);
+    if (unet != 0 && unet != 2) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "U-Net levels %u: 0 or 2 supported", unet);
+    if (unet && nb > MAXBLK - 1)    // the U-Net's last convolution takes tile slot nblocks
+        return fail(nullptr, DL_ERR_UNSUPPORTED, "a U-Net after %u blocks (at most %d)", nb, MAXBLK - 1);
     if (L < 1 || L > 8) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "layers per block %u outside 1..8", L);
     if (!(C == 16 || C == 32)) return fail(nullptr, DL_ERR_UNSUPPORTED, "dense network with C = %u (16 or 32)", C);
     if (!(G == 16 || G == 32)) return fail(nullptr, DL_ERR_UNSUPPORTED, "dense network with growth %u (16 or 32)", G);
     for (uint32_t k = 0; k < nb; ++k)
         if (hdr[5 + k] < 1 || hdr[5 + k] > 64) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "dilation %u of block %u outside 1..64", hdr[5 + k], k);
     if (!finite_all(sc, 3) || !(sc[0] > 0.f)) return fail(nullptr, DL_ERR_BAD_WEIGHTS, "bad in_scale/z_scale/ph_scale");
-    const size_t np = dense_param_count((int)C, (int)nb, (int)L, (int)G, (int)nh);
+    const size_t np = dense_param_count((int)C, (int)nb, (int)L, (int)G, (int)nh, (int)unet);
     if (nbytes != 80 + np * 4)
         return fail(nullptr, DL_ERR_BAD_WEIGHTS, "blob is %zu bytes, expected %zu for a dense network with C=%u, %u "
                     "blocks of %u layers, growth %u", nbytes, 80 + np * 4, C, nb, L, G);
@@ -1074,9 +1174,12 @@ static int parse_dense(const unsigned char *b, size_t nbytes, dl_net_info *info,
         info->ph_scale = sc[2];
         info->nparams = (int64_t)np;
         info->head_outputs = (int32_t)nh;
-        info->receptive_radius = R;
+        // the U-Net's output reaches 12 pixels into its input (its last 3x3
+        // conv, and through pooling and upsampling the level-1 and level-2 ones)
+        info->receptive_radius = R + (unet ? 12 : 0);
         info->dense_layers = (int16_t)L;
         info->dense_growth = (int16_t)G;
+        info->unet_levels = (int32_t)unet;
     }
     if (params) *params = std::move(tmp);
     return DL_OK;
@@ -1181,6 +1284,7 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     net->nh = info.head_outputs;
     net->dL = info.dense_layers;
     net->dG = info.dense_growth;
+    net->unet = info.unet_levels;
     net->params = std::move(params);
 
     auto bail = [&](int code) {
@@ -1219,7 +1323,7 @@ int dl_create_net(const void *weights, size_t nbytes, const dl_config *cfg, dl_n
     // the allocation-free entry point's memory: the device's scratch array
     // and a descriptor ring for DL_NOALLOC_MAX_FRAMES frames
     if ((rc = scratch_init(net))) return bail(rc);
-    if ((rc = grow_desc(net, DL_NOALLOC_MAX_FRAMES))) return bail(rc);
+    if ((rc = grow_desc(net, DL_NOALLOC_MAX_FRAMES * desc_per_frame(net)))) return bail(rc);
     if (hipStreamCreateWithFlags(&net->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&net->compute_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(net, DL_ERR_DEVICE, "hipStreamCreate failed"));
@@ -1407,8 +1511,9 @@ int dl_localize_device_noalloc(dl_net *net, const uint16_t *d_frames, int n, int
     if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
     if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_counts) % 4)
         return fail(net, DL_ERR_INVALID_ARG, "d_out must be 16-byte and d_counts 4-byte aligned");
-    if (n > net->desc_cap)
-        return fail(net, DL_ERR_UNSUPPORTED, "at most %d frames per allocation-free call (got %d)", net->desc_cap, n);
+    if ((int64_t)n * desc_per_frame(net) > net->desc_cap)
+        return fail(net, DL_ERR_UNSUPPORTED, "at most %d frames per allocation-free call (got %d)",
+                    net->desc_cap / desc_per_frame(net), n);
     if (gated_run(net)) return fail(net, DL_ERR_UNSUPPORTED, "gated runs need the handle's workspace");
     if (net->packed_precision != net->cfg.precision || !net->scratch)
         return fail(net, DL_ERR_DEVICE, "the handle's weights or scratch memory are not set up");
@@ -1964,6 +2069,8 @@ int dl_graph_create_rois_dynamic(dl_net *net, int max_rois, int max_h, int max_w
     if (cap > 0 && !d_out) return fail(net, DL_ERR_INVALID_ARG, "d_out is NULL with cap > 0");
     int rc;
     if ((rc = check_camera(net, false, 0, 0))) return rc;
+    if (net->unet)
+        return fail(net, DL_ERR_UNSUPPORTED, "the U-Net's level descriptors are built on the host: no capacity graph");
     dl_graph proto;
     proto.dynamic = true;
     proto.cap_rois = max_rois;

@@ -77,6 +77,10 @@ struct Geometry {
     // tiles[].  The other fields then hold capacity bounds (grid sizes,
     // workspace offsets such as the FP8 scale region at total_act * C).
     const int64_t *dyn = nullptr;
+    // dense networks with the two-stage U-Net: points and conv tiles of
+    // levels 1 and 2 (index 1, 2); their frame descriptors follow the n frame
+    // descriptors of the batch, level by level
+    int64_t lv_pts[3] = {0, 0, 0}, lv_tiles[3] = {0, 0, 0};
 };
 constexpr int DYN_NF = 0, DYN_ROWS = 1, DYN_TILES = 2, DYN_WORDS = 2 + MAXBLK;
 
@@ -290,12 +294,21 @@ struct DenseConvArgs {
 int dense_tile_rows();
 int dense_tile_cols();
 // nb_out 1 or 2 (16 or 32 layer outputs); fuse 0 (layer), 1 (+ transition),
-// 2 (+ transition + head); nt = transition outputs / 16 (1 or 2)
+// 2 (+ transition + head), 3 (+ head on the layer's outputs); nt = transition
+// outputs / 16 (1 or 2)
 hipError_t launch_dconv(int nb_out, int fuse, int nt, const DenseConvArgs &a, const Geometry &g, int ncu,
                         hipStream_t s);
 // preprocessing + stem 1 -> C (C 16 or 32) + ReLU into channels 0 .. C-1 of points of cs floats
 hipError_t launch_dstem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b, float offset,
                         float scale, float *act, int cs, hipStream_t s);
+// U-Net levels (src and dst descriptors of the same frames, npts = the dst
+// level's points): 2 x 2 max pooling to the next level, nearest upsampling
+// to the level above; C channels read from points of scs floats, written to
+// points of dcs floats
+hipError_t launch_pool2(const FrameDesc *sfd, const FrameDesc *dfd, int nf, int64_t npts, const float *src, int scs,
+                        float *dst, int dcs, int C, hipStream_t s);
+hipError_t launch_up2(const FrameDesc *sfd, const FrameDesc *dfd, int nf, int64_t npts, const float *src, int scs,
+                      float *dst, int dcs, int C, hipStream_t s);
 // W [cout][cin][taps] -> the MFMA layout of k_dconv (cout, cin multiples of 16)
 void pack_dense_weights(int cout, int cin, int taps, const float *W, float *dst);
 

@@ -82,14 +82,18 @@ constexpr int PW = DTC + 2, NPT = (DTR + 2) * PW;   // tile points with the one-
 // LDS of one workgroup (floats): the group's tile, the group's layer weights,
 // [fused] the group's transition weights, the transition weights of the
 // layer's own outputs, [head] the head weights; then the biases.
+// FUSE: 0 the layer alone; 1 + the block's 1x1 transition; 2 + transition +
+// head; 3 + head (on the layer's own outputs)
 template <int NB, int NT, int FUSE>
 struct DLds {
+    static constexpr bool TR = FUSE == 1 || FUSE == 2, HD = FUSE >= 2;
+    static constexpr int HK = FUSE == 3 ? NB : NT;           // head K groups (16 channels each)
     static constexpr int TILE = NPT * DPS;
     static constexpr int W = 9 * NB * 64 * 4;                // one group's layer weights
-    static constexpr int WT = FUSE ? NT * 64 * 4 : 0;        // one group's transition weights
-    static constexpr int WTL = FUSE ? NB * NT * 64 * 4 : 0;  // transition weights of the layer's outputs
-    static constexpr int WH = FUSE == 2 ? NT * 64 * 4 : 0;   // head weights (16 rows, K = 16 NT)
-    static constexpr int BIAS = NB * 16 + (FUSE ? NT * 16 : 0) + (FUSE == 2 ? 16 : 0);
+    static constexpr int WT = TR ? NT * 64 * 4 : 0;          // one group's transition weights
+    static constexpr int WTL = TR ? NB * NT * 64 * 4 : 0;    // transition weights of the layer's outputs
+    static constexpr int WH = HD ? HK * 64 * 4 : 0;          // head weights (16 rows, K = 16 HK)
+    static constexpr int BIAS = NB * 16 + (TR ? NT * 16 : 0) + (HD ? 16 : 0);
     static constexpr int NQ = NPT * 4;                       // 16-byte chunks of a group's tile
     static constexpr int NPF = (NQ + DTR * 64 - 1) / (DTR * 64);
     static constexpr int NWF = (W / 4 + DTR * 64 - 1) / (DTR * 64);   // weight chunks per thread
@@ -102,6 +106,8 @@ __global__ void __launch_bounds__(DTR * 64)
 k_dconv(DenseConvArgs a, Geometry geo)
 {
     using L = DLds<NB, NT, FUSE>;
+    constexpr bool TR = L::TR, HD = L::HD;
+    constexpr int HK = L::HK;
     constexpr int NTH = DTR * 64;
     extern __shared__ v4f dsm[];
     float *sT = reinterpret_cast<float *>(dsm);
@@ -111,7 +117,7 @@ k_dconv(DenseConvArgs a, Geometry geo)
     v4f *sWH = sWTL + L::WTL / 4;
     float *sB = reinterpret_cast<float *>(sWH + L::WH / 4);
     float *sBT = sB + NB * 16;                   // [fused] transition bias
-    float *sBH = sBT + (FUSE ? NT * 16 : 0);     // [head] head bias (nh of 16)
+    float *sBH = sBT + (TR ? NT * 16 : 0);       // [head] head bias (nh of 16)
     int *sdec = reinterpret_cast<int *>(sB + L::BIAS);
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -119,12 +125,12 @@ k_dconv(DenseConvArgs a, Geometry geo)
     const int j = lane & 15, kq = lane >> 4;
     const int dd = a.d, blk = a.blk, ngroups = a.cin / 16;
     for (int i = tid; i < NB * 16; i += NTH) sB[i] = a.bias[i];
-    if constexpr (FUSE > 0) {
+    if constexpr (TR) {
         const v4f *wl = reinterpret_cast<const v4f *>(a.wt) + (size_t)ngroups * NT * 64;
         for (int i = tid; i < L::WTL / 4; i += NTH) sWTL[i] = wl[i];
         for (int i = tid; i < NT * 16; i += NTH) sBT[i] = a.bt[i];
     }
-    if constexpr (FUSE == 2) {
+    if constexpr (HD) {
         for (int i = tid; i < L::WH / 4; i += NTH) sWH[i] = reinterpret_cast<const v4f *>(a.wh)[i];
         for (int i = tid; i < 16; i += NTH) sBH[i] = i < a.nh ? a.bh[i] : 0.f;
     }
@@ -187,7 +193,7 @@ k_dconv(DenseConvArgs a, Geometry geo)
                 const int i = tid + k * NTH;
                 if (i < L::W / 4) wf[k] = gw[i];
             }
-            if constexpr (FUSE > 0) {
+            if constexpr (TR) {
                 const v4f *tw = reinterpret_cast<const v4f *>(a.wt) + (size_t)g * (L::WT / 4);
 #pragma unroll
                 for (int k = 0; k < L::NTF; ++k) {
@@ -208,13 +214,13 @@ k_dconv(DenseConvArgs a, Geometry geo)
         };
         issue(0);
         v4f acc[NB][DPB];
-        v4f accT[FUSE ? NT : 1][DPB];    // [fused] transition accumulators
+        v4f accT[TR ? NT : 1][DPB];      // [fused] transition accumulators
 #pragma unroll
         for (int p = 0; p < DPB; ++p) {
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[nb][p] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int nt = 0; nt < (FUSE ? NT : 1); ++nt) accT[nt][p] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < (TR ? NT : 1); ++nt) accT[nt][p] = v4f{0.f, 0.f, 0.f, 0.f};
         }
         for (int g = 0; g < ngroups; ++g) {
             __syncthreads();             // the previous group's LDS reads are done
@@ -228,7 +234,7 @@ k_dconv(DenseConvArgs a, Geometry geo)
                 const int i = tid + k * NTH;
                 if (i < L::W / 4) sW[i] = wf[k];
             }
-            if constexpr (FUSE > 0) {
+            if constexpr (TR) {
 #pragma unroll
                 for (int k = 0; k < L::NTF; ++k) {
                     const int i = tid + k * NTH;
@@ -253,7 +259,7 @@ k_dconv(DenseConvArgs a, Geometry geo)
 #pragma unroll
                         for (int p = 0; p < DPB; ++p)
                             acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[nb][s], bv[p][s], acc[nb][p], 0, 0, 0);
-                if constexpr (FUSE > 0) {
+                if constexpr (TR) {
                     if (tap == 4) {      // the centre tap's operand is this group's 1x1 input
 #pragma unroll
                         for (int nt = 0; nt < NT; ++nt) {
@@ -280,44 +286,54 @@ k_dconv(DenseConvArgs a, Geometry geo)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) o[nb][r] = fmaxf(acc[nb][p][r] + sB[nb * 16 + 4 * kq + r], 0.f);
             }
-            if constexpr (FUSE == 0) {
+            if constexpr (!TR && !HD) {
                 if (inside) {
                     float *op = a.out + (act + (int64_t)yo * W + xo) * a.cso + a.co;
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) *reinterpret_cast<v4f *>(op + nb * 16 + 4 * kq) = o[nb];
                 }
             } else {
-                // the layer's outputs are the transition's last K groups: in the
-                // accumulator layout, lane (j, kq) element s is channel 4 kq + s
-                // of pixel j, which is the B operand's layout for K step s
+                v4f hin[HK];                 // the head's input: transition or layer outputs
+                if constexpr (TR) {
+                    // the layer's outputs are the transition's last K groups: in the
+                    // accumulator layout, lane (j, kq) element s is channel 4 kq + s
+                    // of pixel j, which is the B operand's layout for K step s
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
+                    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const v4f awl = sWTL[(nb * NT + nt) * 64 + lane];
+                        for (int nt = 0; nt < NT; ++nt) {
+                            const v4f awl = sWTL[(nb * NT + nt) * 64 + lane];
 #pragma unroll
-                        for (int s = 0; s < 4; ++s)
-                            accT[nt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(awl[s], o[nb][s], accT[nt][p], 0, 0, 0);
-                    }
-                v4f t[NT];
+                            for (int s = 0; s < 4; ++s)
+                                accT[nt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(awl[s], o[nb][s], accT[nt][p], 0, 0, 0);
+                        }
+                    v4f t[NT];
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
+                    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) t[nt][r] = fmaxf(accT[nt][p][r] + sBT[nt * 16 + 4 * kq + r], 0.f);
-                if constexpr (FUSE == 1) {
-                    if (inside) {
-                        float *op = a.tout + (act + (int64_t)yo * W + xo) * a.cst;
+                        for (int r = 0; r < 4; ++r) t[nt][r] = fmaxf(accT[nt][p][r] + sBT[nt * 16 + 4 * kq + r], 0.f);
+                    if constexpr (FUSE == 1) {
+                        if (inside) {
+                            float *op = a.tout + (act + (int64_t)yo * W + xo) * a.cst;
 #pragma unroll
-                        for (int nt = 0; nt < NT; ++nt) *reinterpret_cast<v4f *>(op + nt * 16 + 4 * kq) = t[nt];
+                            for (int nt = 0; nt < NT; ++nt) *reinterpret_cast<v4f *>(op + nt * 16 + 4 * kq) = t[nt];
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < HK; ++k) hin[k] = t[k];
                     }
                 } else {
-                    // head: outputs q = 4 kq + r of pixel j, K = the 16 NT transition outputs
+#pragma unroll
+                    for (int k = 0; k < HK; ++k) hin[k] = o[k];
+                }
+                if constexpr (HD) {
+                    // head: outputs q = 4 kq + r of pixel j, K = the head's 16 HK inputs
                     v4f hq = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const v4f awh = sWH[nt * 64 + lane];
+                    for (int k = 0; k < HK; ++k) {
+                        const v4f awh = sWH[k * 64 + lane];
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) hq = __builtin_amdgcn_mfma_f32_16x16x4f32(awh[s], t[nt][s], hq, 0, 0, 0);
+                        for (int s = 0; s < 4; ++s) hq = __builtin_amdgcn_mfma_f32_16x16x4f32(awh[s], hin[k][s], hq, 0, 0, 0);
                     }
                     if (inside) {
                         const int64_t px = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(sdec[6]) |
@@ -371,7 +387,79 @@ hipError_t launch_nt(int nt, const DenseConvArgs &a, const Geometry &g, int ncu,
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------- U-Net
+// Levels of a frame: level l + 1 of an h x w level is ceil(h/2) x ceil(w/2);
+// each level has its own frame descriptors (h, w, act_off), one per frame in
+// the same order.  One thread per (destination point, 4 channels).
+
+// 2 x 2 max pooling of C channels: src level -> dst (the next level); a
+// window at an odd edge takes the pixels it has
+__global__ void __launch_bounds__(256)
+k_pool2(const FrameDesc *__restrict__ sfd, const FrameDesc *__restrict__ dfd, int nf, int64_t npts,
+        const float *__restrict__ src, int scs, float *__restrict__ dst, int dcs, int C)
+{
+    const int Q = C / 4;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npts * Q; i += (int64_t)gridDim.x * 256) {
+        const int64_t pt = i / Q;
+        const int q = (int)(i - pt * Q);
+        const int f = find_frame(dfd, nf, pt, [](const FrameDesc &d) { return d.act_off; });
+        const FrameDesc D = dfd[f], Sd = sfd[f];
+        const int64_t local = pt - D.act_off;
+        const int y = (int)(local / D.w), x = (int)(local - (int64_t)y * D.w);
+        v4f m = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int yy = 2 * y + dy, xx = 2 * x + dx;
+                if (yy < Sd.h && xx < Sd.w) {
+                    const v4f v = *reinterpret_cast<const v4f *>(src + (Sd.act_off + (int64_t)yy * Sd.w + xx) * scs + 4 * q);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) m[r] = fmaxf(m[r], v[r]);
+                }
+            }
+        *reinterpret_cast<v4f *>(dst + pt * dcs + 4 * q) = m;
+    }
+}
+
+// nearest upsampling of C channels: src level -> dst (the level above):
+// dst(y, x) = src(y / 2, x / 2)
+__global__ void __launch_bounds__(256)
+k_up2(const FrameDesc *__restrict__ sfd, const FrameDesc *__restrict__ dfd, int nf, int64_t npts,
+      const float *__restrict__ src, int scs, float *__restrict__ dst, int dcs, int C)
+{
+    const int Q = C / 4;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npts * Q; i += (int64_t)gridDim.x * 256) {
+        const int64_t pt = i / Q;
+        const int q = (int)(i - pt * Q);
+        const int f = find_frame(dfd, nf, pt, [](const FrameDesc &d) { return d.act_off; });
+        const FrameDesc D = dfd[f], Sd = sfd[f];
+        const int64_t local = pt - D.act_off;
+        const int y = (int)(local / D.w), x = (int)(local - (int64_t)y * D.w);
+        *reinterpret_cast<v4f *>(dst + pt * dcs + 4 * q) =
+            *reinterpret_cast<const v4f *>(src + (Sd.act_off + (int64_t)(y / 2) * Sd.w + x / 2) * scs + 4 * q);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_pool2(const FrameDesc *sfd, const FrameDesc *dfd, int nf, int64_t npts, const float *src, int scs,
+                        float *dst, int dcs, int C, hipStream_t s)
+{
+    const int64_t n = npts * (C / 4);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_pool2, dim3(grid), dim3(256), 0, s, sfd, dfd, nf, npts, src, scs, dst, dcs, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_up2(const FrameDesc *sfd, const FrameDesc *dfd, int nf, int64_t npts, const float *src, int scs,
+                      float *dst, int dcs, int C, hipStream_t s)
+{
+    const int64_t n = npts * (C / 4);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_up2, dim3(grid), dim3(256), 0, s, sfd, dfd, nf, npts, src, scs, dst, dcs, C);
+    return hipGetLastError();
+}
 
 int dense_tile_rows() { return DTR; }
 int dense_tile_cols() { return DTC; }
@@ -384,6 +472,11 @@ hipError_t launch_dconv(int nb_out, int fuse, int nt, const DenseConvArgs &a, co
         return hipErrorInvalidValue;
     }
     if (a.nh > 16) return hipErrorInvalidValue;
+    if (fuse == 3) {             // layer + head (no transition)
+        if (nb_out == 1) return launch_dconv_t<1, 1, 3>(a, g, ncu, s);
+        if (nb_out == 2) return launch_dconv_t<2, 1, 3>(a, g, ncu, s);
+        return hipErrorInvalidValue;
+    }
     if (nb_out == 1) return fuse == 1 ? launch_nt<1, 1>(nt, a, g, ncu, s) : launch_nt<1, 2>(nt, a, g, ncu, s);
     if (nb_out == 2) return fuse == 1 ? launch_nt<2, 1>(nt, a, g, ncu, s) : launch_nt<2, 2>(nt, a, g, ncu, s);
     return hipErrorInvalidValue;

@@ -12,6 +12,14 @@ degenerate frames with random biases, a calibrated batch's emitters, full-size
 lists and a capacity graph, the allocation-free entry point; a second layout
 (C = 16, growth 32, three layers, 10 outputs) for the other kernel
 instances; and the refusals of what the dense kernels do not support.
+
+Net DU adds the two-stage U-Net after the blocks (Sec. 3.2: fine-grained
+processing by a two-stage U-Net; its sizes are a reading): 2 x 2 max pooling,
+3x3 convolutions at levels 1 and 2, nearest upsampling and 3x3 convolutions
+over [skip, upsampled].  It is held to the same bar on odd-sized frames (edge
+pooling windows hold fewer pixels), full-size windows (margin 133, crops
+aligned to 4 pixels), ROI lists, fixed ROI graphs and the allocation-free
+entry point.
 """
 import numpy as np
 import pytest
@@ -244,3 +252,94 @@ def test_unsupported_settings_are_refused():
     ref, ref_maps = oracle.localize(frames, spec, wts, return_maps=True)
     rec, _ = gpu_localize(net, frames)
     assert compare_emitters(rec, ref, ref_maps)["non_exempt_mismatch"] == 0
+
+
+UNET_E = S.DenseSpec("UE", 16, (1, 3), layers=2, growth=32, unet=2, head_outputs=10)
+
+
+def test_inspect_unet_blob():
+    spec, w = S.make_net("DU", 3)
+    info = dl.inspect_weights(S.serialize_weights(spec, w))
+    assert info["unet_levels"] == 2 and info["receptive_radius"] == 133 == S.receptive_radius(spec)
+    assert info["nparams"] == S.param_count(spec)
+    assert dl.inspect_weights(S.serialize_weights(*S.make_net("D", 3)))["unet_levels"] == 0
+
+
+@pytest.mark.parametrize("spec,n,h,w", [("DU", 2, 77, 131), ("DU", 1, 5, 3), ("DU", 2, 1, 1), ("DU", 1, 2, 129),
+                                        (UNET_E, 2, 67, 90)])
+def test_unet_maps_odd_frames_random_biases(spec, n, h, w):
+    """Frames whose sides are odd at some level, so edge pooling windows hold
+    fewer pixels, random biases everywhere."""
+    spec, wts, net = make(spec, 7, bias_std=0.05)
+    frames = S.render_frames(n, h, w, "tiny", 556)
+    ref = oracle.net_maps_batch(frames, spec, wts)
+    got = gpu_maps(net, frames)
+    assert not np.isnan(got).any()
+    err = map_rel_err(got, ref)
+    print(spec.name, (n, h, w), "map rel err", err.max())
+    assert err.max() <= TOL
+    rec, counts = gpu_localize(net, frames)
+    ref_rec = oracle.localize(frames, spec, wts)
+    assert compare_emitters(rec, ref_rec, ref)["non_exempt_mismatch"] == 0 and counts[-1] == len(rec)
+
+
+def test_unet_calibrated_emitters():
+    spec, wts, net = make("DU", 3)
+    frames = S.render_frames(2, 256, 256, "full", 1001)
+    ref, ref_maps = oracle.localize(frames, spec, wts, return_maps=True)
+    assert map_rel_err(gpu_maps(net, frames), ref_maps).max() <= TOL
+    rec, counts = gpu_localize(net, frames)
+    cmp = compare_emitters(rec, ref, ref_maps)
+    print(cmp)
+    assert len(ref) > 10 and cmp["non_exempt_mismatch"] == 0 and cmp["order_ok"] and cmp["max_dxy_px"] < 1e-3
+    rec2, _ = gpu_localize(net, frames)
+    assert np.array_equal(rec, rec2)
+
+
+def test_unet_full_size_sampled_windows():
+    spec, wts, net = make("DU", 3)
+    frames = S.render_frames(1, 2048, 2048, "full", 1003)
+    got = gpu_maps(net, frames)
+    for y0, x0 in [(0, 0), (1001, 517), (2048 - 40, 2048 - 48)]:
+        ref = oracle.net_maps_window(frames[0], spec, wts, y0, x0, 40, 48)
+        err = map_rel_err(got[0, :, y0:y0 + 40, x0:x0 + 48], ref)
+        print("window", y0, x0, err.max(), flush=True)
+        assert err.max() <= TOL
+
+
+def test_unet_rois_graph_and_noalloc():
+    """ROI lists (one a strided view) against the oracle per ROI; a fixed ROI
+    graph replays the eager records; the allocation-free entry point equals
+    the allocating one; a capacity graph is refused."""
+    spec, wts, net = make("DU", 3)
+    big = torch.from_numpy(S.render_frames(1, 200, 260, "rois", 96)[0]).to(DEV)
+    host = S.render_rois(4, "rois", 3100, shapes=[(64, 96), (33, 70), (1, 130), (90, 41)])
+    dev = [torch.from_numpy(np.ascontiguousarray(r)).to(DEV) for r in host]
+    dev[0] = big[11:75, 21:117]
+    host[0] = big[11:75, 21:117].cpu().numpy()
+    out = torch.zeros((20000, 8), dtype=torch.int32, device=DEV)
+    counts = torch.full((5,), -1, dtype=torch.int32, device=DEV)
+    net.localize_rois_device(dev, out, counts)
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy().astype(np.int64)
+    erec = dl.emitters_from_device(out, int(c[-1]))
+    for j, r in enumerate(host):
+        rr, mm = oracle.localize(np.ascontiguousarray(r)[None], spec, wts, return_maps=True)
+        gj = erec[erec["frame"] == j].copy()
+        gj["frame"] = 0
+        assert compare_emitters(gj, rr, mm)["non_exempt_mismatch"] == 0, j
+    g = net.graph_rois(dev, out, counts)
+    for _ in range(2):
+        out.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(dl.emitters_from_device(out, int(c[-1])), erec)
+    g.close()
+    with pytest.raises(dl.DlocError) as e:
+        net.graph_rois_dynamic(4, 100, 130, 20000, out, counts)
+    assert e.value.code == dl.DL_ERR_UNSUPPORTED
+    for n, h, w in [(2, 96, 130), (1, 33, 33)]:
+        frames = S.render_frames(n, h, w, "full", 90 + h)
+        a, ca = gpu_localize(net, frames)
+        b, cb = gpu_localize(net, frames, noalloc=True)
+        assert np.array_equal(a, b) and np.array_equal(ca, cb)
