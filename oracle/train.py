@@ -1,0 +1,167 @@
+"""FP64 oracle of one training step of the localization network -- TEST
+INFRASTRUCTURE ONLY (same rules as the rest of ``oracle``: only tests,
+smoke() and the bench's CPU leg use it; it never touches the product path).
+
+The paper trains its network with DECODE's loss plus a binary cross-entropy
+on the per-pixel detection probability (Sec. 3.3: the cross-entropy of
+predicted and true occupancy, together with the counting loss, constrains the
+whole distribution of molecules).  Written out here for the residual network
+with the 10-output head (probability, offsets, their uncertainties), per
+frame of P = h w pixels with maps m (logit l, dx, dy, dz, ph, raw sigmas
+u_x, u_y, u_z, u_N, background) and its true emitters e = 1 .. E:
+
+  p_k = sigmoid(l_k); y_k = 1 iff a true emitter lies in pixel k
+  L_bce   = (1/P) sum_k [softplus(l_k) - y_k l_k]                 (BCE on l)
+  mu = sum_k p_k,  v = sum_k p_k (1 - p_k) + 1e-4
+  L_count = log(2 pi v) / 2 + (E - mu)^2 / (2 v)       (Gaussian count model)
+  m_k = (col + 0.5 + dx, row + 0.5 + dy, dz, ph),  s_kd = softplus(u_kd)
+  q_ek = log p_k - log mu + sum_d log N(t_ed; m_kd, s_kd^2)
+  L_loc   = -sum_e logsumexp_k q_ek        (mixture over pixels, weights p/mu)
+  L_frame = L_bce + L_count + L_loc;  the batch loss is the mean over frames.
+
+t_e = (x, y, z / z_scale, photons / ph_scale) of emitter e.  Gradients are
+taken by hand, layer by layer, in the order of the definitions (the network's
+backward pass is plain convolutions: the transposed 3x3 convolution is the
+forward one with flipped, transposed weights; weight gradients are sums of
+products over pixels).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+from . import conv3x3, preprocess, softplus
+
+VAR_EPS = 1e-4
+
+
+def _sig(v):
+    return 0.5 * (1.0 + np.tanh(0.5 * v))
+
+
+def _log_sig(v):
+    """log sigmoid(v) = -softplus(-v)."""
+    return -softplus(-v)
+
+
+def occupancy(truth, h: int, w: int) -> np.ndarray:
+    """y[h][w]: 1 where a true emitter's (x, y) falls in the pixel."""
+    y = np.zeros((h, w), np.float64)
+    for t in truth:
+        r, c = int(math.floor(t["y"])), int(math.floor(t["x"]))
+        if 0 <= r < h and 0 <= c < w:
+            y[r, c] = 1.0
+    return y
+
+
+def frame_loss(maps: np.ndarray, truth, spec) -> Tuple[Dict[str, float], np.ndarray]:
+    """Loss of one frame and its gradient with respect to the maps [10][h][w]."""
+    nh, h, w = maps.shape
+    assert nh == 10
+    P = h * w
+    l = maps[0]
+    p = _sig(l)
+    g = np.zeros_like(maps)
+    # binary cross-entropy on the logit
+    yk = occupancy(truth, h, w)
+    L_bce = float(np.sum(softplus(l) - yk * l)) / P
+    g[0] += (p - yk) / P
+    # count
+    E = len(truth)
+    mu = float(np.sum(p))
+    v = float(np.sum(p * (1 - p))) + VAR_EPS
+    L_cnt = 0.5 * math.log(2 * math.pi * v) + (E - mu) ** 2 / (2 * v)
+    dmu = -(E - mu) / v
+    dv = 1 / (2 * v) - (E - mu) ** 2 / (2 * v * v)
+    g[0] += p * (1 - p) * (dmu + (1 - 2 * p) * dv)
+    # localisation: a mixture over pixels
+    L_loc = 0.0
+    if E:
+        rows, cols = np.mgrid[0:h, 0:w].astype(np.float64)
+        mean = [cols + 0.5 + maps[1], rows + 0.5 + maps[2], maps[3], maps[4]]
+        s = [softplus(maps[5 + d]) for d in range(4)]
+        logw = _log_sig(l) - math.log(mu)
+        for t in truth:
+            tv = [t["x"], t["y"], t["z_nm"] / spec.z_scale, t["photons"] / spec.ph_scale]
+            q = logw.copy()
+            for d in range(4):
+                q += -0.5 * math.log(2 * math.pi) - np.log(s[d]) - (tv[d] - mean[d]) ** 2 / (2 * s[d] ** 2)
+            qmax = float(np.max(q))
+            lse = qmax + math.log(float(np.sum(np.exp(q - qmax))))
+            L_loc -= lse
+            r = np.exp(q - lse)
+            # through log p_k and -log mu
+            g[0] += -r * (1 - p) + p * (1 - p) / mu
+            for d in range(4):
+                g[1 + d] += -r * (tv[d] - mean[d]) / s[d] ** 2
+                g[5 + d] += -r * (-1 / s[d] + (tv[d] - mean[d]) ** 2 / s[d] ** 3) * _sig(maps[5 + d])
+    return {"bce": L_bce, "count": L_cnt, "loc": L_loc, "total": L_bce + L_cnt + L_loc}, g
+
+
+def _relu(v):
+    return np.maximum(v, 0.0)
+
+
+def _flip_t(W):
+    """Weights of the transposed 3x3 convolution: W'[ci][co][u][v] = W[co][ci][2-u][2-v]."""
+    return np.ascontiguousarray(W[:, :, ::-1, ::-1].transpose(1, 0, 2, 3))
+
+
+def _wgrad(dy: np.ndarray, x: np.ndarray, d: int) -> np.ndarray:
+    """dW[co][ci][u][v] = sum_ij dy[co][i][j] x[ci][i + d(u-1)][j + d(v-1)] (zero outside)."""
+    cin, h, w = x.shape
+    xp = np.zeros((cin, h + 2 * d, w + 2 * d))
+    xp[:, d:d + h, d:d + w] = x
+    out = np.empty((dy.shape[0], cin, 3, 3))
+    for u in range(3):
+        for v in range(3):
+            xs = xp[:, u * d:u * d + h, v * d:v * d + w]
+            out[:, :, u, v] = np.tensordot(dy, xs, axes=([1, 2], [1, 2]))
+    return out
+
+
+def frame_grads(frame: np.ndarray, truth, spec, wts: Dict[str, np.ndarray], gain=0.5, offset=100.0):
+    """Loss of one frame and the gradient of every weight tensor."""
+    W = {k: np.asarray(v, np.float64) for k, v in wts.items()}
+    x = preprocess(frame[None], gain, offset, spec.in_scale)[0][None]
+    a0 = _relu(conv3x3(x, W["stem.w"], W["stem.b"], 1))
+    acts = []
+    a = a0
+    for k, d in enumerate(spec.dilations):
+        t = _relu(conv3x3(a, W[f"blk{k}.w1"], W[f"blk{k}.b1"], d))
+        an = _relu(conv3x3(t, W[f"blk{k}.w2"], W[f"blk{k}.b2"], d) + a)
+        acts.append((a, t, an))
+        a = an
+    maps = np.tensordot(W["head.w"], a, axes=(1, 0)) + W["head.b"][:, None, None]
+    loss, gm = frame_loss(maps, truth, spec)
+    G = {}
+    G["head.w"] = np.tensordot(gm, a, axes=([1, 2], [1, 2]))
+    G["head.b"] = gm.sum(axis=(1, 2))
+    da = np.tensordot(W["head.w"], gm, axes=(0, 0))
+    for k in reversed(range(len(spec.dilations))):
+        d = spec.dilations[k]
+        ain, t, an = acts[k]
+        du = da * (an > 0)
+        G[f"blk{k}.w2"] = _wgrad(du, t, d)
+        G[f"blk{k}.b2"] = du.sum(axis=(1, 2))
+        ds = conv3x3(du, _flip_t(W[f"blk{k}.w2"]), None, d) * (t > 0)
+        G[f"blk{k}.w1"] = _wgrad(ds, ain, d)
+        G[f"blk{k}.b1"] = ds.sum(axis=(1, 2))
+        da = du + conv3x3(ds, _flip_t(W[f"blk{k}.w1"]), None, d)
+    ds0 = da * (a0 > 0)
+    G["stem.w"] = _wgrad(ds0, x, 1)
+    G["stem.b"] = ds0.sum(axis=(1, 2))
+    return loss, G, maps
+
+
+def batch_grads(frames: np.ndarray, truths: List, spec, wts, gain=0.5, offset=100.0):
+    """Mean loss over the frames and the gradients of the mean."""
+    n = len(frames)
+    tot, G = None, None
+    for f in range(n):
+        L, g, _ = frame_grads(frames[f], truths[f], spec, wts, gain, offset)
+        tot = dict(L) if tot is None else {k: tot[k] + L[k] for k in tot}
+        G = g if G is None else {k: G[k] + g[k] for k in G}
+    return {k: v / n for k, v in tot.items()}, {k: v / n for k, v in G.items()}

@@ -277,6 +277,20 @@ def render_frames(n: int, h: int, w: int, model: FrameModel | str, seed: int,
     return (out, truths) if with_truth else out
 
 
+TRUTH_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("z_nm", "<f8"), ("photons", "<f8")])
+
+
+def truth_array(truth: dict, h: int, w: int) -> np.ndarray:
+    """The true emitters of one rendered frame that lie inside it (0 <= x < w,
+    0 <= y < h, pixel units), as records (x, y, z_nm, photons)."""
+    x, y = np.asarray(truth["x"], np.float64), np.asarray(truth["y"], np.float64)
+    keep = (x >= 0) & (x < w) & (y >= 0) & (y < h)
+    out = np.zeros(int(keep.sum()), TRUTH_DTYPE)
+    for k in TRUTH_DTYPE.names:
+        out[k] = np.asarray(truth[k], np.float64)[keep]
+    return out
+
+
 def _pool_size() -> int:
     try:
         n = len(os.sched_getaffinity(0))

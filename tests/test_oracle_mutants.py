@@ -28,7 +28,9 @@ from tests import test_oracle_camera as CAM
 from tests import test_oracle_dense as DN
 from tests import test_oracle_fp8 as FP8
 from tests import test_oracle_pins as PINS
+from tests import test_oracle_train as TR
 from tests import test_oracle_uncertainty as UNC
+import oracle.train  # noqa: E402,F401
 
 MUTANTS = [
     ("transposed 3x3 kernel",
@@ -178,16 +180,35 @@ PY_MUTANTS = [
      "math.log(threshold / (1.0 - threshold))",
      "math.log(threshold / (1.0 + threshold))",
      [(PINS.test_localize_threshold_is_a_probability, (0.3,))]),
+    ("count variance without the (1 - p) factor", "train.frame_loss",
+     "v = float(np.sum(p * (1 - p))) + VAR_EPS",
+     "v = float(np.sum(p)) + VAR_EPS",
+     [(TR.test_count_term_closed_form, ())]),
+    ("mixture weights not divided by the expected count", "train.frame_loss",
+     "logw = _log_sig(l) - math.log(mu)",
+     "logw = _log_sig(l)",
+     [(TR.test_loss_and_gradients_match_torch_autograd, ())]),
+    ("sigma gradient without the softplus derivative", "train.frame_loss",
+     "(tv[d] - mean[d]) ** 2 / s[d] ** 3) * _sig(maps[5 + d])",
+     "(tv[d] - mean[d]) ** 2 / s[d] ** 3)",
+     [(TR.test_loss_and_gradients_match_torch_autograd, ())]),
+    ("transposed convolution left unflipped", "train._flip_t",
+     "W[:, :, ::-1, ::-1].transpose(1, 0, 2, 3)",
+     "W.transpose(1, 0, 2, 3)",
+     [(TR.test_transposed_conv_is_the_adjoint, ())]),
 ]
 
 
 @pytest.mark.parametrize("name,fname,old,new,pins", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
 def test_pins_reject_a_planted_python_mistake(name, fname, old, new, pins, monkeypatch):
-    src = textwrap.dedent(inspect.getsource(getattr(oracle, fname)))
+    mod = oracle
+    if fname.startswith("train."):
+        mod, fname = oracle.train, fname.split(".", 1)[1]
+    src = textwrap.dedent(inspect.getsource(getattr(mod, fname)))
     assert src.count(old) == 1, "the planted mistake's target text must occur once"
-    ns = dict(vars(oracle))
-    exec(compile(src.replace(old, new), f"<planted mistake in oracle.{fname}>", "exec"), ns)
-    monkeypatch.setattr(oracle, fname, ns[fname])
+    ns = dict(vars(mod))
+    exec(compile(src.replace(old, new), f"<planted mistake in {mod.__name__}.{fname}>", "exec"), ns)
+    monkeypatch.setattr(mod, fname, ns[fname])
     failed = []
     with np.errstate(all="ignore"):
         for pin, args in pins:

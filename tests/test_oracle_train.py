@@ -1,0 +1,159 @@
+"""Pins of the training oracle (``oracle.train``): the loss of Sec. 3.3 (binary
+cross-entropy on the detection probability together with DECODE's count and
+localisation terms) and the gradients of every weight of the residual network
+with the 10-output head.
+
+* the loss and every gradient against an independent torch float64
+  composition differentiated by autograd (conv2d with dilation, logsigmoid,
+  softplus, logsumexp), on frames with emitters, one frame without;
+* central finite differences of the whole loss for sampled weights;
+* closed forms: the count term at p = 1/2 everywhere; the localisation term
+  when one pixel holds all the probability (a Gaussian's negative
+  log-likelihood); the cross-entropy term on a known occupancy;
+* the transposed convolution the backward pass uses against the adjoint
+  identity <conv(x), y> = <x, conv_T(y)>.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.train as T
+import smlm_synth as S
+
+torch = pytest.importorskip("torch")
+F = torch.nn.functional
+
+SPEC = S.NetSpec("t16", 16, (1, 2), head_outputs=10)
+
+
+def data(n=2, h=24, w=28, seed=5, empty_last=True):
+    frames, truths = S.render_frames(n, h, w, "tiny", seed, with_truth=True)
+    truths = [S.truth_array(t, h, w) for t in truths]
+    if empty_last:
+        frames[-1] = 100
+        truths[-1] = truths[-1][:0]
+    return frames, truths
+
+
+def weights(seed=3):
+    w = S.he_normal_weights(SPEC, seed, bias_std=0.05)
+    w["head.w"] = (w["head.w"] * 0.3).astype(np.float32)
+    return w
+
+
+def torch_loss(frames, truths, spec, wts, gain=0.5, offset=100.0):
+    P = {k: torch.tensor(np.asarray(v, np.float64), requires_grad=True) for k, v in wts.items()}
+    total = 0.0
+    for f in range(len(frames)):
+        x = (torch.from_numpy(frames[f].astype(np.float64)) - offset) * gain * spec.in_scale
+        a = F.relu(F.conv2d(x[None, None], P["stem.w"], P["stem.b"], padding=1))
+        for k, d in enumerate(spec.dilations):
+            t = F.relu(F.conv2d(a, P[f"blk{k}.w1"], P[f"blk{k}.b1"], padding=d, dilation=d))
+            a = F.relu(F.conv2d(t, P[f"blk{k}.w2"], P[f"blk{k}.b2"], padding=d, dilation=d) + a)
+        m = F.conv2d(a, P["head.w"][:, :, None, None], P["head.b"])[0]
+        h, w = m.shape[1:]
+        l = m[0]
+        p = torch.sigmoid(l)
+        y = torch.zeros(h, w, dtype=torch.float64)
+        for t in truths[f]:
+            y[int(math.floor(t["y"])), int(math.floor(t["x"]))] = 1.0
+        L = (F.softplus(l) - y * l).mean()
+        E = len(truths[f])
+        mu = p.sum()
+        v = (p * (1 - p)).sum() + T.VAR_EPS
+        L = L + 0.5 * torch.log(2 * math.pi * v) + (E - mu) ** 2 / (2 * v)
+        rows, cols = torch.meshgrid(torch.arange(h, dtype=torch.float64), torch.arange(w, dtype=torch.float64),
+                                    indexing="ij")
+        mean = [cols + 0.5 + m[1], rows + 0.5 + m[2], m[3], m[4]]
+        sd = [F.softplus(m[5 + d]) for d in range(4)]
+        for t in truths[f]:
+            tv = [t["x"], t["y"], t["z_nm"] / spec.z_scale, t["photons"] / spec.ph_scale]
+            q = F.logsigmoid(l) - torch.log(mu)
+            for d in range(4):
+                q = q + torch.distributions.Normal(mean[d], sd[d]).log_prob(torch.tensor(float(tv[d]), dtype=torch.float64))
+            L = L - torch.logsumexp(q.reshape(-1), 0)
+        total = total + L
+    total = total / len(frames)
+    total.backward()
+    return float(total.detach()), {k: v.grad.numpy() for k, v in P.items()}
+
+
+def test_loss_and_gradients_match_torch_autograd():
+    frames, truths = data()
+    wts = weights()
+    assert len(truths[0]) >= 2
+    L, G = T.batch_grads(frames, truths, SPEC, wts)
+    Lt, Gt = torch_loss(frames, truths, SPEC, wts)
+    assert abs(L["total"] - Lt) <= 1e-10 * abs(Lt)
+    for k in G:
+        ref = Gt[k]
+        err = np.linalg.norm(G[k] - ref) / (np.linalg.norm(ref) + 1e-300)
+        assert err <= 1e-9, (k, err)
+
+
+def test_finite_differences():
+    frames, truths = data(n=1, empty_last=False)
+    wts = weights(4)
+    _, G = T.batch_grads(frames, truths, SPEC, wts)
+    r = np.random.default_rng(7)
+    for name in ["stem.w", "blk0.w1", "blk1.w2", "blk1.b1", "head.w", "head.b"]:
+        for _ in range(2):
+            idx = tuple(int(r.integers(0, s)) for s in wts[name].shape)
+            h = 1e-5
+            wp = {k: np.asarray(v, np.float64).copy() for k, v in wts.items()}
+            wm = {k: np.asarray(v, np.float64).copy() for k, v in wts.items()}
+            wp[name][idx] += h
+            wm[name][idx] -= h
+            Lp, _ = T.batch_grads(frames, truths, SPEC, wp)
+            Lm, _ = T.batch_grads(frames, truths, SPEC, wm)
+            fd = (Lp["total"] - Lm["total"]) / (2 * h)
+            assert abs(fd - G[name][idx]) <= 1e-5 * (abs(fd) + 1e-3), (name, idx, fd, G[name][idx])
+
+
+def test_count_term_closed_form():
+    h, w = 6, 7
+    maps = np.zeros((10, h, w))
+    truth = np.zeros(3, S.TRUTH_DTYPE)
+    truth["x"], truth["y"] = [0.5, 3.2, 6.9], [0.5, 2.2, 5.1]
+    L, _ = T.frame_loss(maps, truth, SPEC)
+    P = h * w
+    v = P / 4 + T.VAR_EPS
+    assert abs(L["count"] - (0.5 * math.log(2 * math.pi * v) + (3 - P / 2) ** 2 / (2 * v))) <= 1e-12
+    # BCE at logit 0: log 2 everywhere
+    assert abs(L["bce"] - math.log(2.0)) <= 1e-12
+
+
+def test_localisation_term_with_one_dominant_pixel():
+    h, w = 5, 6
+    maps = np.zeros((10, h, w))
+    maps[0] = -40.0
+    maps[0, 2, 3] = 40.0
+    maps[1, 2, 3], maps[2, 2, 3], maps[3, 2, 3], maps[4, 2, 3] = 0.1, -0.2, 0.3, 2.0
+    maps[5:9, 2, 3] = [0.2, -0.1, 0.5, 1.0]
+    truth = np.zeros(1, S.TRUTH_DTYPE)
+    truth["x"], truth["y"], truth["z_nm"], truth["photons"] = 3.7, 2.1, 140.0, 2500.0
+    L, _ = T.frame_loss(maps, truth, SPEC)
+    t = [3.7, 2.1, 140.0 / SPEC.z_scale, 2500.0 / SPEC.ph_scale]
+    m = [3 + 0.5 + 0.1, 2 + 0.5 - 0.2, 0.3, 2.0]
+    s = oracle.softplus(np.array([0.2, -0.1, 0.5, 1.0]))
+    nll = sum(0.5 * math.log(2 * math.pi) + math.log(s[d]) + (t[d] - m[d]) ** 2 / (2 * s[d] ** 2) for d in range(4))
+    assert abs(L["loc"] - nll) <= 1e-9
+
+
+def test_transposed_conv_is_the_adjoint():
+    r = np.random.default_rng(9)
+    for d in (1, 3):
+        x = r.standard_normal((5, 11, 13))
+        y = r.standard_normal((4, 11, 13))
+        W = r.standard_normal((4, 5, 3, 3))
+        lhs = np.sum(oracle.conv3x3(x, W, None, d) * y)
+        rhs = np.sum(x * oracle.conv3x3(y, T._flip_t(W), None, d))
+        assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+        # the weight gradient is the derivative of <conv(x), y> with respect to W
+        g = T._wgrad(y, x, d)
+        k = (1, 2, 0, 2)
+        Wp = W.copy()
+        Wp[k] += 1.0
+        assert abs(np.sum(oracle.conv3x3(x, Wp, None, d) * y) - lhs - g[k]) <= 1e-9 * (1 + abs(g[k]))
