@@ -487,6 +487,50 @@ typedef struct {
 int dl_autotune_ex(dl_net *net, const uint16_t *d_frames, int n, int h, int w, void *stream, int reps,
                    const char *cache_path, dl_tune_result *res);
 
+/* ---- training (Sec. 3.3) ----
+ * One true emitter of a training frame: position in pixels (the frame spans
+ * [0, w) x [0, h), pixel (row, col) covers [col, col + 1) x [row, row + 1)),
+ * axial position in nm and photon count. */
+typedef struct {
+    float x, y, z_nm, photons;
+} dl_truth;
+
+/* Loss and gradient of one batch at the handle's current weights, on the
+ * device, queued on `stream`.  The network must be a residual (DLW1) net with
+ * the 10-output head and C = 16 or 32; FP32; scalar gain and offset.
+ *   d_frames     device uint16 [n][h][w]
+ *   d_truth      device dl_truth[], the frames' true emitters, frame by frame,
+ *                each inside its frame
+ *   d_truth_off  device int32[n + 1]: frame f's emitters are
+ *                d_truth[d_truth_off[f] .. d_truth_off[f + 1] - 1]; [0] = 0
+ *   ntruth       d_truth_off[n] (the host's copy; sizes the launches)
+ *   d_grad       device float[nparams]: the gradient in blob order (may be NULL)
+ *   d_loss       device float[4]: batch means of the loss and of its three
+ *                terms {total, cross-entropy, count, localisation}
+ * Per frame of P pixels, with p = sigmoid(logit), y = 1 on pixels holding a
+ * true emitter, mu = sum p, v = sum p (1 - p) + 1e-4, E emitters:
+ *   cross-entropy  (1/P) sum [softplus(logit) - y logit]
+ *   count          log(2 pi v) / 2 + (E - mu)^2 / (2 v)
+ *   localisation   -sum_e log sum_k (p_k / mu) prod_d N(t_ed; m_kd, s_kd^2),
+ *                  m_k = (col + 0.5 + dx, row + 0.5 + dy, dz, ph), s = softplus
+ *                  of the raw uncertainty planes, t_e = (x, y, z_nm / z_scale,
+ *                  photons / ph_scale)
+ * and the batch loss is the mean over frames.  Training buffers are the
+ * handle's (grown on demand).  Errors: DL_ERR_INVALID_ARG, DL_ERR_UNSUPPORTED,
+ * DL_ERR_OOM, DL_ERR_DEVICE. */
+int dl_train_grad(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
+                  const int32_t *d_truth_off, int ntruth, void *stream, float *d_grad, float *d_loss);
+
+/* dl_train_grad, then one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, the
+ * handle's own moments and step count) of learning rate lr on the handle's
+ * weights; later localize calls use the updated weights. */
+int dl_train_step(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
+                  const int32_t *d_truth_off, int ntruth, void *stream, float lr, float *d_loss);
+
+/* The handle's current weights, flat in blob order (nparams floats), to the
+ * host; waits for the device. */
+int dl_get_params(dl_net *net, float *params, size_t count);
+
 /* ---- stage timing ----
  * With profiling on, every kernel launch of the path is bracketed by two HIP
  * events recorded on the stream it runs on.  dl_profile_read waits for the

@@ -131,6 +131,9 @@ def _load():
         "dl_gate_bce": (I, [P, P, I, P, P, P]),
         "dl_gate_adam": (I, [P, P, P, P, I, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),
         "dl_profile_read": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+        "dl_train_grad": (I, [P, P, I, I, I, P, P, I, P, P, P]),
+        "dl_train_step": (I, [P, P, I, I, I, P, P, I, P, ctypes.c_float, P]),
+        "dl_get_params": (I, [P, P, Z]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -253,6 +256,7 @@ class Net:
         _check(_lib.dl_inspect_weights(buf, len(weights), ctypes.byref(info)))
         self.head_outputs = int(info.head_outputs)     # planes of the maps: 5, or 10 with uncertainties
         self.nblocks = int(info.nblocks)
+        self.nparams = int(info.nparams)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -483,6 +487,39 @@ class Net:
         nb = self.nblocks
         return {"rows": list(r.rows[:nb]), "strip": int(r.strip), "from_cache": bool(r.from_cache),
                 "configs_timed": int(r.configs_timed), "ms_default": float(r.ms_default), "ms_best": float(r.ms_best)}
+
+    # ---- training ----
+    def train_grad(self, frames, truth, truth_off, grad=None, loss=None, stream=None):
+        """Loss and gradient of one batch (dl_train_grad).  truth: cuda float32
+        [E, 4] (x, y, z_nm, photons per true emitter, frame by frame);
+        truth_off: cuda int32 [n + 1]; grad: cuda float32 [nparams] or None;
+        returns the cuda float32 [4] loss (total, cross-entropy, count, loc)."""
+        import torch
+        n, h, w = _frames_arg(frames).shape
+        if loss is None:
+            loss = torch.zeros(4, dtype=torch.float32, device=frames.device)
+        ntruth = int(truth.shape[0])
+        self._rc(_lib.dl_train_grad(self.handle, _ptr(frames), n, h, w, _ptr(truth) if ntruth else None,
+                                    _ptr(truth_off), ntruth, _stream(stream), _ptr(grad) if grad is not None else None,
+                                    _ptr(loss)))
+        return loss
+
+    def train_step(self, frames, truth, truth_off, lr: float, loss=None, stream=None):
+        """One Adam step of the handle's weights on this batch (dl_train_step)."""
+        import torch
+        n, h, w = _frames_arg(frames).shape
+        if loss is None:
+            loss = torch.zeros(4, dtype=torch.float32, device=frames.device)
+        ntruth = int(truth.shape[0])
+        self._rc(_lib.dl_train_step(self.handle, _ptr(frames), n, h, w, _ptr(truth) if ntruth else None,
+                                    _ptr(truth_off), ntruth, _stream(stream), float(lr), _ptr(loss)))
+        return loss
+
+    def get_params(self) -> np.ndarray:
+        """The handle's current weights, flat in blob order (dl_get_params)."""
+        out = np.empty(self.nparams, np.float32)
+        self._rc(_lib.dl_get_params(self.handle, out.ctypes.data, out.size))
+        return out
 
     def set_gate(self, theta, threshold: float = 0.05):
         """Attach gate parameters (host array of 673 floats, or None to detach)."""

@@ -145,6 +145,16 @@ struct dl_net {
     // offsets dense_w / dense_b of d_dense, then the head's (rows padded to 16)
     int dL = 0, dG = 0;
     int unet = 0;                   // U-Net levels after the dense blocks: 0 or 2
+
+    // training (dl_train_*): the weights being trained (blob order), their
+    // gradient and Adam moments, the packed forward and transposed conv
+    // weights, and the batch buffers (grow-only); t_dirty: the trained
+    // weights have not been handed to the inference path yet
+    float *t_params = nullptr, *t_grad = nullptr, *t_m = nullptr, *t_v = nullptr, *t_pack = nullptr;
+    char *t_ws = nullptr;
+    size_t t_ws_bytes = 0;
+    int t_step = 0;
+    bool t_dirty = false;
     float *d_dense = nullptr;
     std::vector<size_t> dense_w, dense_b;
     size_t dense_head_w = 0;
@@ -487,6 +497,42 @@ int upload_desc(dl_net *net, const std::vector<FrameDesc> &fd, hipStream_t s, Fr
     return slot;
 }
 
+// stem, head and (residual nets) conv biases from net->params to the device
+int upload_small_weights(dl_net *net)
+{
+    const int C = net->C, nb = net->nb;
+    const float *p = net->params.data();
+    const size_t nstem = (size_t)C * 9 + C, nhead = (size_t)net->nh * C + net->nh;
+    HIPCHK(net, hipMemcpy(net->d_stem, p, nstem * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, hipMemcpy(net->d_head, p + net->params.size() - nhead, nhead * 4, hipMemcpyHostToDevice));
+    if (!net->dL) {
+        std::vector<float> bias((size_t)nb * 2 * C);
+        const float *q = p + nstem;
+        for (int k = 0; k < nb; ++k)
+            for (int j = 0; j < 2; ++j) {
+                q += (size_t)C * C * 9;
+                std::memcpy(bias.data() + (size_t)(k * 2 + j) * C, q, C * 4);
+                q += C;
+            }
+        HIPCHK(net, hipMemcpy(net->d_bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice));
+    }
+    return DL_OK;
+}
+
+// Trained weights reach the inference path: copied back into net->params,
+// the small tensors re-uploaded, the conv weights repacked on next use.
+int sync_trained(dl_net *net)
+{
+    if (!net->t_dirty) return DL_OK;
+    HIPCHK(net, hipDeviceSynchronize());
+    HIPCHK(net, hipMemcpy(net->params.data(), net->t_params, net->params.size() * 4, hipMemcpyDeviceToHost));
+    int rc = upload_small_weights(net);
+    if (rc) return rc;
+    net->t_dirty = false;
+    net->packed_precision = -1;
+    return DL_OK;
+}
+
 // Dense networks: every conv's weights in the k_dconv layout and its bias,
 // in run order, in one device buffer (FP32; packed once).
 int pack_dense(dl_net *net)
@@ -534,6 +580,7 @@ int pack_dense(dl_net *net)
 
 int ensure_packed(dl_net *net)
 {
+    if (int rc = sync_trained(net)) return rc;
     if (net->packed_precision == net->cfg.precision) return DL_OK;
     if (net->dL) return pack_dense(net);
     const int C = net->C;
@@ -1061,6 +1108,175 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
 
 }  // namespace
 
+// ---- training ----
+namespace {
+
+// float offsets of a residual net's tensors in blob order
+struct ParamOffsets {
+    size_t stem_w, stem_b, w1[MAXBLK], b1[MAXBLK], w2[MAXBLK], b2[MAXBLK], head_w, head_b, total;
+};
+ParamOffsets param_offsets(const dl_net *net)
+{
+    const size_t C = net->C;
+    ParamOffsets o{};
+    size_t k = 0;
+    o.stem_w = k; k += C * 9;
+    o.stem_b = k; k += C;
+    for (int b = 0; b < net->nb; ++b) {
+        o.w1[b] = k; k += C * C * 9;
+        o.b1[b] = k; k += C;
+        o.w2[b] = k; k += C * C * 9;
+        o.b2[b] = k; k += C;
+    }
+    o.head_w = k; k += (size_t)net->nh * C;
+    o.head_b = k; k += net->nh;
+    o.total = k;
+    return o;
+}
+
+int train_check(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
+                const int32_t *d_off, int ntruth, float *d_loss)
+{
+    int rc = check_uniform(net, d_frames, n, h, w);
+    if (rc) return rc;
+    if (net->dL || net->nh != 10 || !(net->C == 16 || net->C == 32))
+        return fail(net, DL_ERR_UNSUPPORTED, "training runs the residual network with the 10-output head and C = 16 or 32");
+    if (net->d_cam) return fail(net, DL_ERR_UNSUPPORTED, "training uses the scalar gain and offset (clear the camera maps)");
+    if (!d_off || !d_loss || (ntruth > 0 && !d_truth) || ntruth < 0)
+        return fail(net, DL_ERR_INVALID_ARG, "d_truth_off and d_loss must be given, d_truth when ntruth > 0");
+    if ((int64_t)n * h * w > ((int64_t)1 << 26))
+        return fail(net, DL_ERR_UNSUPPORTED, "a training batch holds at most 2^26 pixels");
+    return DL_OK;
+}
+
+// device copies of the weights and the Adam state, made on first use
+int train_init(dl_net *net)
+{
+    if (net->t_params) return DL_OK;
+    const size_t np = net->params.size(), C = net->C;
+    HIPCHK(net, hipMalloc(&net->t_params, np * 4));
+    HIPCHK(net, hipMalloc(&net->t_grad, np * 4));
+    HIPCHK(net, hipMalloc(&net->t_m, np * 4));
+    HIPCHK(net, hipMalloc(&net->t_v, np * 4));
+    HIPCHK(net, hipMalloc(&net->t_pack, (size_t)net->nb * 4 * C * C * 9 * 4));
+    HIPCHK(net, hipMemcpy(net->t_params, net->params.data(), np * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, hipMemset(net->t_m, 0, np * 4));
+    HIPCHK(net, hipMemset(net->t_v, 0, np * 4));
+    net->t_step = 0;
+    return DL_OK;
+}
+
+// Forward with every activation kept, the loss and its gradient, backward.
+// Buffers (P = n h w points of C floats): act[0 .. nb], T[0 .. nb-1], two
+// gradient buffers and ds; maps and gm (10 P); stats, lse; the weight-gradient
+// partials.
+int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
+              const int32_t *d_off, int ntruth, hipStream_t s, float *d_grad, float *d_loss)
+{
+    int rc;
+    if ((rc = set_device(net)) || (rc = train_init(net))) return rc;
+    const int C = net->C, nb = net->nb;
+    const int64_t P = (int64_t)n * h * w;
+    const ParamOffsets o = param_offsets(net);
+    const int nblk = (n * h + wgrad_rows_per_block(n, h) - 1) / wgrad_rows_per_block(n, h);
+    size_t off = 0;
+    auto take = [&](size_t floats) { size_t at = off; off = align_up(off + floats * 4); return at; };
+    size_t act[MAXBLK + 1], T[MAXBLK];
+    for (int b = 0; b <= nb; ++b) act[b] = take((size_t)P * C);
+    for (int b = 0; b < nb; ++b) T[b] = take((size_t)P * C);
+    const size_t g0 = take((size_t)P * C), g1 = take((size_t)P * C), dsb = take((size_t)P * C);
+    const size_t maps = take((size_t)P * 10), gm = take((size_t)P * 10);
+    const size_t stats = take((size_t)3 * n), lse = take((size_t)std::max(ntruth, 1));
+    const size_t part = take((size_t)nblk * 9 * C * C), pb = take((size_t)nblk * C), tmp = take((size_t)9 * C * C);
+    if (off > net->t_ws_bytes) {
+        HIPCHK(net, hipDeviceSynchronize());
+        if (net->t_ws) HIPCHK(net, hipFree(net->t_ws));
+        net->t_ws = nullptr;
+        net->t_ws_bytes = 0;
+        if (hipMalloc(&net->t_ws, off) != hipSuccess) return fail(net, DL_ERR_OOM, "training buffers of %zu bytes", off);
+        net->t_ws_bytes = off;
+    }
+    auto F = [&](size_t at) { return reinterpret_cast<float *>(net->t_ws + at); };
+    float *prm = net->t_params, *grd = d_grad ? d_grad : net->t_grad;
+    // descriptors: frame f's points from f h w, its tiles per block from f times a frame's
+    std::vector<FrameDesc> fd(n);
+    Geometry g;
+    g.nf = n;
+    g.tr = dense_tile_rows();
+    g.tc = dense_tile_cols();
+    for (int f = 0; f < n; ++f) {
+        FrameDesc &d = fd[f];
+        std::memset(&d, 0, sizeof d);
+        d.data = d_frames + (size_t)f * h * w;
+        d.stride = w;
+        d.h = h;
+        d.w = w;
+        d.px_off = d.act_off = (int64_t)f * h * w;
+        d.row_start = (int64_t)f * h;
+        for (int b = 0; b < nb; ++b) d.tile_start[b] = (int64_t)f * conv_tiles(h, w, net->dil[b], g.tr, g.tc);
+    }
+    for (int b = 0; b < nb; ++b) g.tiles[b] = (int64_t)n * conv_tiles(h, w, net->dil[b], g.tr, g.tc);
+    g.total_rows = (int64_t)n * h;
+    g.total_px = g.total_act = P;
+    FrameDesc *d_fd = nullptr;
+    const int slot = upload_desc(net, fd, s, &d_fd);
+    if (slot < 0) return slot;
+    // packed conv weights: [block][conv 1, 2][forward, transposed]
+    auto pk = [&](int b, int k, int tr) { return net->t_pack + ((size_t)(b * 2 + k) * 2 + tr) * C * C * 9; };
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < 2; ++k)
+            for (int tr = 0; tr < 2; ++tr)
+                HIPCHK(net, launch_pack_conv(prm + (k ? o.w2[b] : o.w1[b]), C, C, tr, pk(b, k, tr), s));
+    auto conv = [&](int b, int k, int tr, float *in, float *out, const float *bias, const float *res,
+                    const float *mask, int relu) {
+        DenseConvArgs a{};
+        a.in = in;
+        a.csi = C;
+        a.cin = C;
+        a.out = out;
+        a.cso = C;
+        a.co = 0;
+        a.w = pk(b, k, tr);
+        a.bias = bias;
+        a.fd = d_fd;
+        a.d = net->dil[b];
+        a.blk = b;
+        a.res = res;
+        a.rcs = C;
+        a.mask = mask;
+        a.mcs = C;
+        a.relu = relu;
+        return launch_dconv_train(C / 16, a, g, net->ncu, s);
+    };
+    const float scale = net->cfg.gain * in_scale_of(net);
+    // forward
+    HIPCHK(net, launch_dstem(C, d_fd, g, prm + o.stem_w, prm + o.stem_b, net->cfg.offset, scale, F(act[0]), C, s));
+    for (int b = 0; b < nb; ++b) {
+        HIPCHK(net, conv(b, 0, 0, F(act[b]), F(T[b]), prm + o.b1[b], nullptr, nullptr, 1));
+        HIPCHK(net, conv(b, 1, 0, F(T[b]), F(act[b + 1]), prm + o.b2[b], F(act[b]), nullptr, 1));
+    }
+    HIPCHK(net, launch_train_loss(C, F(act[nb]), prm + o.head_w, prm + o.head_b, n, h, w, d_truth, d_off, ntruth,
+                                  net->z_scale, net->ph_scale, F(maps), F(stats), F(lse), F(gm), d_loss, s));
+    // backward: du is the gradient at the pre-activation of block b's output
+    float *du = F(g0), *dn = F(g1);
+    HIPCHK(net, launch_head_backward(C, F(gm), F(act[nb]), prm + o.head_w, n, h, w, grd + o.head_w, grd + o.head_b,
+                                     du, s));
+    for (int b = nb - 1; b >= 0; --b) {
+        HIPCHK(net, launch_wgrad(C, du, F(T[b]), n, h, w, net->dil[b], F(part), F(pb), F(tmp), grd + o.w2[b],
+                                 grd + o.b2[b], s));
+        HIPCHK(net, conv(b, 1, 1, du, F(dsb), nullptr, nullptr, F(T[b]), 0));            // ds
+        HIPCHK(net, launch_wgrad(C, F(dsb), F(act[b]), n, h, w, net->dil[b], F(part), F(pb), F(tmp), grd + o.w1[b],
+                                 grd + o.b1[b], s));
+        HIPCHK(net, conv(b, 0, 1, F(dsb), dn, nullptr, du, F(act[b]), 0));              // (du + W1^T ds) at a_b > 0
+        std::swap(du, dn);
+    }
+    HIPCHK(net, launch_stem_grad(du, d_frames, n, h, w, net->cfg.offset, scale, C, grd + o.stem_w, grd + o.stem_b, s));
+    HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
+    return DL_OK;
+}
+
+}  // namespace
+
 // ---- autotuner with a cache ----
 namespace {
 
@@ -1365,6 +1581,9 @@ void dl_destroy_net(dl_net *net)
     if (net->d_bias) (void)hipFree(net->d_bias);
     if (net->d_wpk) (void)hipFree(net->d_wpk);
     if (net->d_dense) (void)hipFree(net->d_dense);
+    for (float *q : {net->t_params, net->t_grad, net->t_m, net->t_v, net->t_pack})
+        if (q) (void)hipFree(q);
+    if (net->t_ws) (void)hipFree(net->t_ws);
     if (net->d_gate_theta) (void)hipFree(net->d_gate_theta);
     if (net->d_radius) (void)hipFree(net->d_radius);
     if (net->d_dil) (void)hipFree(net->d_dil);
@@ -2315,6 +2534,40 @@ int dl_autotune_ex(dl_net *net, const uint16_t *d_frames, int n, int h, int w, v
         std::fprintf(f, "], \"strip\": %d, \"ms\": %.4f}\n", strip, best);
         std::fclose(f);
     }
+    return DL_OK;
+}
+
+int dl_train_grad(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
+                  const int32_t *d_truth_off, int ntruth, void *stream, float *d_grad, float *d_loss)
+{
+    int rc = train_check(net, d_frames, n, h, w, d_truth, d_truth_off, ntruth, d_loss);
+    if (rc) return rc;
+    return train_run(net, d_frames, n, h, w, d_truth, d_truth_off, ntruth, static_cast<hipStream_t>(stream), d_grad,
+                     d_loss);
+}
+
+int dl_train_step(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
+                  const int32_t *d_truth_off, int ntruth, void *stream, float lr, float *d_loss)
+{
+    int rc = train_check(net, d_frames, n, h, w, d_truth, d_truth_off, ntruth, d_loss);
+    if (rc) return rc;
+    if (!(lr > 0.f) || !std::isfinite(lr)) return fail(net, DL_ERR_INVALID_ARG, "lr must be finite and > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = train_run(net, d_frames, n, h, w, d_truth, d_truth_off, ntruth, s, nullptr, d_loss))) return rc;
+    HIPCHK(net, launch_adam(net->t_params, net->t_m, net->t_v, net->t_grad, (int)net->params.size(), lr, 0.9f, 0.999f,
+                            1e-8f, ++net->t_step, s));
+    net->t_dirty = true;
+    return DL_OK;
+}
+
+int dl_get_params(dl_net *net, float *params, size_t count)
+{
+    if (!net) return fail(nullptr, DL_ERR_INVALID_ARG, "net is NULL");
+    if (!params || count != net->params.size())
+        return fail(net, DL_ERR_INVALID_ARG, "params must hold exactly %zu floats", net->params.size());
+    int rc;
+    if ((rc = set_device(net)) || (rc = sync_trained(net))) return rc;
+    std::memcpy(params, net->params.data(), count * 4);
     return DL_OK;
 }
 

@@ -290,6 +290,11 @@ struct DenseConvArgs {
     // one queue over all tiles)
     uint32_t *queue;
     int queue_mode;
+    // training passes (launch_dconv_train): bias may be null; res (points of
+    // rcs floats) is added before the optional ReLU; where mask (points of mcs
+    // floats) is <= 0 the output is 0
+    const float *res, *mask;
+    int rcs, mcs, relu;
 };
 int dense_tile_rows();
 int dense_tile_cols();
@@ -298,6 +303,27 @@ int dense_tile_cols();
 // outputs / 16 (1 or 2)
 hipError_t launch_dconv(int nb_out, int fuse, int nt, const DenseConvArgs &a, const Geometry &g, int ncu,
                         hipStream_t s);
+// ---- training (kernels_train.hip) ----
+// a 3x3 conv's flat weights [cout][cin][9] into the conv kernel's layout;
+// flip: the transposed convolution's weights (cout and cin swapped, taps reversed)
+hipError_t launch_pack_conv(const float *W, int cout, int cin, int flip, float *dst, hipStream_t s);
+// head (10 outputs) on the last activations, loss terms, their gradient with
+// respect to the maps (gm, planar like maps), batch means into loss[4]
+hipError_t launch_train_loss(int C, const float *act, const float *hw, const float *hb, int n, int h, int w,
+                             const dl_truth *tr, const int32_t *toff, int ntruth, float zs, float ps, float *maps,
+                             float *stats, float *lse, float *gm, float *loss, hipStream_t s);
+// head weight/bias gradients and the gradient at the last block's pre-activation
+hipError_t launch_head_backward(int C, const float *gm, const float *act, const float *hw, int n, int h, int w,
+                                float *gw, float *gb, float *du, hipStream_t s);
+// 3x3 weight and bias gradients; part holds 256 x 9 C^2 floats, pb 256 C, tmp 9 C^2
+int wgrad_rows_per_block(int n, int h);
+hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, int w, int d, float *part, float *pb,
+                        float *tmp, float *gW, float *gb, hipStream_t s);
+hipError_t launch_stem_grad(const float *ds, const uint16_t *frames, int n, int h, int w, float offset, float scale,
+                            int C, float *gw, float *gb, hipStream_t s);
+
+// one plain dense-kernel layer with the training epilogue (see DenseConvArgs)
+hipError_t launch_dconv_train(int nb_out, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s);
 // preprocessing + stem 1 -> C (C 16 or 32) + ReLU into channels 0 .. C-1 of points of cs floats
 hipError_t launch_dstem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b, float offset,
                         float scale, float *act, int cs, hipStream_t s);

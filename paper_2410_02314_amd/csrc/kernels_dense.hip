@@ -101,7 +101,7 @@ struct DLds {
     static constexpr int BYTES = (TILE + W + WT + WTL + WH + BIAS) * 4 + 64;
 };
 
-template <int NB, int NT, int FUSE, bool QUEUE>
+template <int NB, int NT, int FUSE, bool QUEUE, bool TRAIN>
 __global__ void __launch_bounds__(DTR * 64)
 k_dconv(DenseConvArgs a, Geometry geo)
 {
@@ -124,7 +124,7 @@ k_dconv(DenseConvArgs a, Geometry geo)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = lane & 15, kq = lane >> 4;
     const int dd = a.d, blk = a.blk, ngroups = a.cin / 16;
-    for (int i = tid; i < NB * 16; i += NTH) sB[i] = a.bias[i];
+    for (int i = tid; i < NB * 16; i += NTH) sB[i] = !TRAIN || a.bias ? a.bias[i] : 0.f;
     if constexpr (TR) {
         const v4f *wl = reinterpret_cast<const v4f *>(a.wt) + (size_t)ngroups * NT * 64;
         for (int i = tid; i < L::WTL / 4; i += NTH) sWTL[i] = wl[i];
@@ -281,10 +281,30 @@ k_dconv(DenseConvArgs a, Geometry geo)
             const int xo = X0 + dd * (16 * p + j);
             const bool inside = yo < H && xo < W;
             v4f o[NB];
+            if constexpr (TRAIN) {
+                // training passes: (acc + bias [+ res]) [ReLU] [times (mask > 0)],
+                // res and mask read at the output point
+                const int64_t pt = act + (int64_t)yo * W + xo;
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int c0 = nb * 16 + 4 * kq;
+                    const v4f rv = a.res && inside ? *reinterpret_cast<const v4f *>(a.res + pt * a.rcs + c0)
+                                                   : v4f{0.f, 0.f, 0.f, 0.f};
+                    const v4f mv = a.mask && inside ? *reinterpret_cast<const v4f *>(a.mask + pt * a.mcs + c0)
+                                                    : v4f{1.f, 1.f, 1.f, 1.f};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) o[nb][r] = fmaxf(acc[nb][p][r] + sB[nb * 16 + 4 * kq + r], 0.f);
+                    for (int r = 0; r < 4; ++r) {
+                        float v = acc[nb][p][r] + sB[c0 + r] + rv[r];
+                        if (a.relu) v = fmaxf(v, 0.f);
+                        o[nb][r] = mv[r] > 0.f ? v : 0.f;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o[nb][r] = fmaxf(acc[nb][p][r] + sB[nb * 16 + 4 * kq + r], 0.f);
+                }
             }
             if constexpr (!TR && !HD) {
                 if (inside) {
@@ -352,11 +372,11 @@ k_dconv(DenseConvArgs a, Geometry geo)
     }
 }
 
-template <int NB, int NT, int FUSE, bool QUEUE>
+template <int NB, int NT, int FUSE, bool QUEUE, bool TRAIN = false>
 hipError_t launch_dconv_q(const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
 {
     using L = DLds<NB, NT, FUSE>;
-    auto kern = k_dconv<NB, NT, FUSE, QUEUE>;
+    auto kern = k_dconv<NB, NT, FUSE, QUEUE, TRAIN>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -459,6 +479,13 @@ hipError_t launch_up2(const FrameDesc *sfd, const FrameDesc *dfd, int nf, int64_
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
     hipLaunchKernelGGL(k_up2, dim3(grid), dim3(256), 0, s, sfd, dfd, nf, npts, src, scs, dst, dcs, C);
     return hipGetLastError();
+}
+
+hipError_t launch_dconv_train(int nb_out, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
+{
+    if (nb_out == 1) return launch_dconv_q<1, 1, 0, false, true>(a, g, ncu, s);
+    if (nb_out == 2) return launch_dconv_q<2, 1, 0, false, true>(a, g, ncu, s);
+    return hipErrorInvalidValue;
 }
 
 int dense_tile_rows() { return DTR; }

@@ -536,6 +536,17 @@ def flat_weights(spec: NetSpec, weights: Dict[str, np.ndarray]) -> np.ndarray:
     return np.concatenate([np.asarray(weights[n], np.float32).ravel() for n, _ in tensor_layout(spec)])
 
 
+def unflat_weights(spec, flat: np.ndarray) -> Dict[str, np.ndarray]:
+    """The tensors of a flat blob-order vector (the inverse of flat_weights)."""
+    out, k = {}, 0
+    for name, shape in tensor_layout(spec):
+        n = int(np.prod(shape))
+        out[name] = np.asarray(flat[k:k + n]).reshape(shape)
+        k += n
+    assert k == len(flat)
+    return out
+
+
 # --------------------------------------------------------------------------------------
 # tile-gate network (2 conv layers of 8 channels + global max + linear 8 -> 1)
 # --------------------------------------------------------------------------------------
