@@ -76,10 +76,10 @@ def main():
                     help="side of the oracle's sample: the top-left crop of frame 0 (the frame size = the whole "
                          "frame; 0 = skip)")
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--workload", default="full", choices=["full", "tiny", "rois", "sparse", "pipeline"],
+    ap.add_argument("--workload", default="full", choices=["full", "tiny", "rois", "sparse", "pipeline", "train"],
                     help="full: the headline (16 x 2048^2, net B); tiny: 4 x 128^2 net A; rois: 256 uneven "
                          "ROIs, net A; sparse: gated BF16 net B on 64 x 2048^2 sparse frames; pipeline: "
-                         "host frames with H2D overlapped on a side stream")
+                         "host frames with H2D overlapped on a side stream; train: training steps of net AU")
     ap.add_argument("--sparse-layout", default="iid", choices=["iid", "cell"],
                     help="sparse workload: empty 256^2 tiles chosen independently (iid) or around one "
                          "compact occupied region (cell)")

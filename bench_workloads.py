@@ -48,6 +48,8 @@ def run_workload(args):
         return sparse(args, S)
     if args.workload == "pipeline":
         return pipeline(args, S)
+    if args.workload == "train":
+        return train(args, S)
     raise SystemExit(f"unknown workload {args.workload}")
 
 
@@ -318,3 +320,46 @@ def pipeline(args, S):
            "camera": args.camera},
           {"serial_mpx_s": round(px / out[0][0] / 1e6, 2), "overlap_speedup": round(out[0][0] / out[1][0], 3),
            "emitters": out[1][1]})
+
+
+def train(args, S):
+    """Training steps of the 10-output residual net (net AU: C = 32, d = 1, 2,
+    4) on 16 frames of 128 x 128 with their true emitters: forward with kept
+    activations, the loss, backward and Adam, all on the GPU."""
+    import torch
+    import paper_2410_02314_amd as dl
+    n, side = 16, 128
+    frames, truths = S.render_frames(n, side, side, "tiny", 1006, with_truth=True)
+    truths = [S.truth_array(t, side, side) for t in truths]
+    spec, w = S.make_net("AU", 1)
+    net = dl.Net(S.serialize_weights(spec, w))
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(frames).to(dev)
+    off = np.zeros(n + 1, np.int32)
+    rows = []
+    for f, t in enumerate(truths):
+        off[f + 1] = off[f] + len(t)
+        rows += [[r["x"], r["y"], r["z_nm"], r["photons"]] for r in t]
+    tr = torch.from_numpy(np.asarray(rows, np.float32).reshape(-1, 4)).to(dev)
+    toff = torch.from_numpy(off).to(dev)
+    loss = torch.zeros(4, dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream()
+    first = float(net.train_step(d, tr, toff, 1e-3, loss, st).cpu()[0])
+    ms = _timed(lambda: net.train_step(d, tr, toff, 1e-3, loss, st), args.steps, args.warmup, st)
+    last = float(loss.cpu()[0])
+    px = n * side * side
+    C, nb = spec.C, len(spec.dilations)
+    # conv FLOP of one step: per block two forward convolutions, two transposed
+    # ones and two weight gradients, each 2 9 C^2 per pixel
+    flop = 2.0 * 9 * C * C * px * 6 * nb
+    tflops = flop / (ms * 1e-3) / 1e12
+    _line(args, px / (ms * 1e-3) / 1e6, ms,
+          {"workload": f"training steps, {n} x {side}x{side} frames with their true emitters, net AU "
+                       f"(C=32, d=1,2,4, 10-output head), FP32, Adam lr 1e-3",
+           "precision": "fp32", "frames": n, "height": side, "width": side},
+          {"frames_per_s": round(n / (ms * 1e-3), 1), "emitters_per_batch": int(off[-1]),
+           "loss_first_step": round(first, 4), "loss_after": round(last, 4), "steps_timed": args.steps,
+           "conv_tflop_per_step": round(flop / 1e12, 4),
+           "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAKS["fp32"], "unit": "TFLOP/s",
+                        "frac": round(tflops / PEAKS["fp32"], 4), "traffic": None,
+                        "kernel": "whole training step (convolution FLOP over the step time)"}})

@@ -1187,6 +1187,7 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
     const size_t g0 = take((size_t)P * C), g1 = take((size_t)P * C), dsb = take((size_t)P * C);
     const size_t maps = take((size_t)P * 10), gm = take((size_t)P * 10);
     const size_t stats = take((size_t)3 * n), lse = take((size_t)std::max(ntruth, 1));
+    const size_t term = take((size_t)9 * P + 48 * (size_t)n), occ = take((size_t)(P + 3) / 4);
     const size_t part = take((size_t)nblk * 9 * C * C), pb = take((size_t)nblk * C), tmp = take((size_t)9 * C * C);
     if (off > net->t_ws_bytes) {
         HIPCHK(net, hipDeviceSynchronize());
@@ -1256,7 +1257,8 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
         HIPCHK(net, conv(b, 1, 0, F(T[b]), F(act[b + 1]), prm + o.b2[b], F(act[b]), nullptr, 1));
     }
     HIPCHK(net, launch_train_loss(C, F(act[nb]), prm + o.head_w, prm + o.head_b, n, h, w, d_truth, d_off, ntruth,
-                                  net->z_scale, net->ph_scale, F(maps), F(stats), F(lse), F(gm), d_loss, s));
+                                  net->z_scale, net->ph_scale, F(maps), F(stats), F(lse), F(gm), d_loss, F(term),
+                                  reinterpret_cast<uint8_t *>(net->t_ws + occ), s));
     // backward: du is the gradient at the pre-activation of block b's output
     float *du = F(g0), *dn = F(g1);
     HIPCHK(net, launch_head_backward(C, F(gm), F(act[nb]), prm + o.head_w, n, h, w, grd + o.head_w, grd + o.head_b,

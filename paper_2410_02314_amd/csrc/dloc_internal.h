@@ -308,10 +308,12 @@ hipError_t launch_dconv(int nb_out, int fuse, int nt, const DenseConvArgs &a, co
 // flip: the transposed convolution's weights (cout and cin swapped, taps reversed)
 hipError_t launch_pack_conv(const float *W, int cout, int cin, int flip, float *dst, hipStream_t s);
 // head (10 outputs) on the last activations, loss terms, their gradient with
-// respect to the maps (gm, planar like maps), batch means into loss[4]
+// respect to the maps (gm, planar like maps), batch means into loss[4];
+// term: 9 n h w + 48 n floats, occ: n h w bytes
 hipError_t launch_train_loss(int C, const float *act, const float *hw, const float *hb, int n, int h, int w,
                              const dl_truth *tr, const int32_t *toff, int ntruth, float zs, float ps, float *maps,
-                             float *stats, float *lse, float *gm, float *loss, hipStream_t s);
+                             float *stats, float *lse, float *gm, float *loss, float *term, uint8_t *occ,
+                             hipStream_t s);
 // head weight/bias gradients and the gradient at the last block's pre-activation
 hipError_t launch_head_backward(int C, const float *gm, const float *act, const float *hw, int n, int h, int w,
                                 float *gw, float *gb, float *du, hipStream_t s);

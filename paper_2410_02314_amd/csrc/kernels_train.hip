@@ -9,9 +9,13 @@
 //                   conv kernel's MFMA layout (optionally flipped and
 //                   transposed: the weights of the transposed convolution)
 //   k_head_fwd      1x1 head C -> 10 into planar maps
+//   k_occupancy     the pixels holding a true emitter
+//   k_pix_terms     per pixel: log p - sum_d log s_d - 2 log 2 pi, m_d, 1 / s_d
 //   k_frame_stats   per frame: mu = sum p, v = sum p (1 - p) + eps, BCE sum
+//                   (16 blocks per frame, then summed in order)
 //   k_loc_lse       per true emitter: log-sum-exp over its frame's pixels of
-//                   q_k = log p_k - log mu + sum_d log N(t_d; m_kd, s_kd^2)
+//                   q_k = log p_k - log mu + sum_d log N(t_d; m_kd, s_kd^2), one
+//                   pass with a running maximum
 //   k_loss_grad     per pixel: d loss / d maps (10 planes)
 //   k_loss_total    the batch means of the loss terms
 //   k_head_grad     head weight and bias gradients (one block per output)
@@ -114,99 +118,153 @@ __device__ int find_frame_off(const int32_t *toff, int n, int e)
     return lo;
 }
 
-// the true emitter in pixel k of a frame?  (linear scan over the frame's few emitters)
-__device__ bool occupied(const dl_truth *tr, int e0, int e1, int row, int col)
+// occupancy of every pixel (1 where a true emitter lies), from the truth list
+__global__ void __launch_bounds__(256)
+k_occupancy(const dl_truth *__restrict__ tr, const int32_t *__restrict__ toff, int n, int ntruth, int h, int w,
+            uint8_t *__restrict__ occ)
 {
-    for (int e = e0; e < e1; ++e)
-        if ((int)floorf(tr[e].y) == row && (int)floorf(tr[e].x) == col) return true;
-    return false;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= ntruth) return;
+    const int f = find_frame_off(toff, n, e);
+    const int row = (int)floorf(tr[e].y), col = (int)floorf(tr[e].x);
+    if ((unsigned)row < (unsigned)h && (unsigned)col < (unsigned)w) occ[((int64_t)f * h + row) * w + col] = 1;
 }
 
-// stats[f] = {mu, v, sum of softplus(l) - y l}
+__global__ void __launch_bounds__(256) k_zero_u8(uint8_t *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
+// Per pixel, what the mixture terms need, planar over the batch's pixels:
+// term[0] = log p - sum_d log s_d - 2 log(2 pi), term[1 + d] = m_d,
+// term[5 + d] = 1 / s_d (d = x, y, z, N in the units of the targets)
 __global__ void __launch_bounds__(256)
-k_frame_stats(const float *__restrict__ maps, int h, int w, const dl_truth *__restrict__ tr,
-              const int32_t *__restrict__ toff, float eps, float *__restrict__ stats)
+k_pix_terms(const float *__restrict__ maps, int n, int h, int w, float *__restrict__ term)
+{
+    const int64_t P = (int64_t)h * w, np = (int64_t)n * P;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= np) return;
+    const int64_t f = i / P, k = i - f * P;
+    const int row = (int)(k / w), col = (int)(k - (int64_t)row * w);
+    const float *M = maps + f * 10 * P;
+    float c = -softplusf(-M[k]) - 2.f * logf(TWO_PI);
+    term[np + i] = col + 0.5f + M[P + k];
+    term[2 * np + i] = row + 0.5f + M[2 * P + k];
+    term[3 * np + i] = M[3 * P + k];
+    term[4 * np + i] = M[4 * P + k];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const float sd = softplusf(M[(5 + d) * P + k]);
+        c -= logf(sd);
+        term[(5 + d) * np + i] = 1.f / sd;
+    }
+    term[i] = c;
+}
+
+constexpr int STAT_CHUNKS = 16;   // blocks per frame for the frame statistics
+
+// partial[f][chunk] = {sum p, sum p (1 - p), sum softplus(l) - y l}
+__global__ void __launch_bounds__(256)
+k_frame_stats(const float *__restrict__ maps, int h, int w, const uint8_t *__restrict__ occ, float *__restrict__ partial)
 {
     __shared__ float sh[256];
-    const int f = blockIdx.x;
+    const int f = blockIdx.x / STAT_CHUNKS, ch = blockIdx.x % STAT_CHUNKS;
     const int64_t P = (int64_t)h * w;
     const float *L = maps + (int64_t)f * 10 * P;
-    const int e0 = toff[f], e1 = toff[f + 1];
+    const uint8_t *Y = occ + (int64_t)f * P;
     float mu = 0.f, v = 0.f, b = 0.f;
-    for (int64_t k = threadIdx.x; k < P; k += 256) {
+    for (int64_t k = (int64_t)ch * 256 + threadIdx.x; k < P; k += STAT_CHUNKS * 256) {
         const float l = L[k], p = sigmoidf(l);
-        const int row = (int)(k / w), col = (int)(k - (int64_t)row * w);
         mu += p;
         v += p * (1.f - p);
-        b += softplusf(l) - (occupied(tr, e0, e1, row, col) ? l : 0.f);
+        b += softplusf(l) - (Y[k] ? l : 0.f);
     }
     mu = block_sum(mu, sh);
     v = block_sum(v, sh);
     b = block_sum(b, sh);
     if (threadIdx.x == 0) {
-        stats[3 * f] = mu;
-        stats[3 * f + 1] = v + eps;
-        stats[3 * f + 2] = b;
+        float *o = partial + 3 * (size_t)blockIdx.x;
+        o[0] = mu;
+        o[1] = v;
+        o[2] = b;
     }
 }
 
-// q_k of emitter e at pixel k (log p - log mu + sum_d log N)
-__device__ __forceinline__ float loc_q(const float *M, int64_t P, int64_t k, int row, int col, const dl_truth &t,
-                                       float zs, float ps, float logmu)
+// stats[f] = {mu, v + eps, bce sum}: the chunks summed in order
+__global__ void __launch_bounds__(256)
+k_frame_stats_sum(const float *__restrict__ partial, int n, float eps, float *__restrict__ stats)
 {
-    const float l = M[k];
-    const float lp = -softplusf(-l);
-    const float tv[4] = {t.x, t.y, t.z_nm / zs, t.photons / ps};
-    const float mv[4] = {col + 0.5f + M[P + k], row + 0.5f + M[2 * P + k], M[3 * P + k], M[4 * P + k]};
-    float q = lp - logmu;
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= n) return;
+    float a[3] = {0.f, 0.f, 0.f};
+    for (int c = 0; c < STAT_CHUNKS; ++c)
+        for (int q = 0; q < 3; ++q) a[q] += partial[3 * ((size_t)f * STAT_CHUNKS + c) + q];
+    stats[3 * f] = a[0];
+    stats[3 * f + 1] = a[1] + eps;
+    stats[3 * f + 2] = a[2];
+}
+
+// q of emitter target tv at pixel i, from the pixel terms (without -log mu)
+__device__ __forceinline__ float mix_q(const float *__restrict__ term, int64_t np, int64_t i, const float (&tv)[4])
+{
+    float q = term[i], z2 = 0.f;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        const float s = softplusf(M[(5 + d) * P + k]);
-        const float z = (tv[d] - mv[d]) / s;
-        q += -0.5f * logf(TWO_PI) - logf(s) - 0.5f * z * z;
+        const float z = (tv[d] - term[(1 + d) * np + i]) * term[(5 + d) * np + i];
+        z2 += z * z;
     }
-    return q;
+    return q - 0.5f * z2;
 }
 
-// lse[e] for every true emitter e (one block each)
+// lse[e] = log sum_k exp(q_ek) - log mu over emitter e's frame, one pass with
+// a running maximum per thread, then (max, sum) pairs combined in a fixed order
 __global__ void __launch_bounds__(256)
-k_loc_lse(const float *__restrict__ maps, int n, int h, int w, const dl_truth *__restrict__ tr,
+k_loc_lse(const float *__restrict__ term, int n, int h, int w, const dl_truth *__restrict__ tr,
           const int32_t *__restrict__ toff, const float *__restrict__ stats, float zs, float ps, float *__restrict__ lse)
 {
-    __shared__ float sh[256];
+    __shared__ float smx[256], ssm[256];
     const int e = blockIdx.x;
     const int f = find_frame_off(toff, n, e);
-    const int64_t P = (int64_t)h * w;
-    const float *M = maps + (int64_t)f * 10 * P;
-    const float logmu = logf(stats[3 * f]);
+    const int64_t P = (int64_t)h * w, np = (int64_t)n * P, base = (int64_t)f * P;
     const dl_truth t = tr[e];
-    float mx = -INFINITY;
+    const float tv[4] = {t.x, t.y, t.z_nm / zs, t.photons / ps};
+    float mx = -INFINITY, sm = 0.f;
     for (int64_t k = threadIdx.x; k < P; k += 256) {
-        const int row = (int)(k / w), col = (int)(k - (int64_t)row * w);
-        mx = fmaxf(mx, loc_q(M, P, k, row, col, t, zs, ps, logmu));
+        const float q = mix_q(term, np, base + k, tv);
+        if (q > mx) {
+            sm = sm * expf(mx - q) + 1.f;
+            mx = q;
+        } else {
+            sm += expf(q - mx);
+        }
     }
-    mx = block_max(mx, sh);
-    float s = 0.f;
-    for (int64_t k = threadIdx.x; k < P; k += 256) {
-        const int row = (int)(k / w), col = (int)(k - (int64_t)row * w);
-        s += expf(loc_q(M, P, k, row, col, t, zs, ps, logmu) - mx);
+    const int tid = threadIdx.x;
+    smx[tid] = mx;
+    ssm[tid] = sm;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            const float m1 = smx[tid], m2 = smx[tid + o];
+            const float m = fmaxf(m1, m2);
+            ssm[tid] = (m1 == -INFINITY ? 0.f : ssm[tid] * expf(m1 - m)) + (m2 == -INFINITY ? 0.f : ssm[tid + o] * expf(m2 - m));
+            smx[tid] = m;
+        }
+        __syncthreads();
     }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) lse[e] = mx + logf(s);
+    if (tid == 0) lse[e] = smx[0] + logf(ssm[0]) - logf(stats[3 * f]);
 }
 
 // d (batch mean loss) / d maps, one thread per pixel of the batch
 __global__ void __launch_bounds__(256)
-k_loss_grad(const float *__restrict__ maps, int n, int h, int w, const dl_truth *__restrict__ tr,
-            const int32_t *__restrict__ toff, const float *__restrict__ stats, const float *__restrict__ lse, float zs,
-            float ps, float *__restrict__ gm)
+k_loss_grad(const float *__restrict__ maps, const float *__restrict__ term, const uint8_t *__restrict__ occ, int n,
+            int h, int w, const dl_truth *__restrict__ tr, const int32_t *__restrict__ toff,
+            const float *__restrict__ stats, const float *__restrict__ lse, float zs, float ps, float *__restrict__ gm)
 {
-    const int64_t P = (int64_t)h * w;
+    const int64_t P = (int64_t)h * w, np = (int64_t)n * P;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)n * P) return;
+    if (i >= np) return;
     const int f = (int)(i / P);
     const int64_t k = i - (int64_t)f * P;
-    const int row = (int)(k / w), col = (int)(k - (int64_t)row * w);
     const float *M = maps + (int64_t)f * 10 * P;
     float *G = gm + (int64_t)f * 10 * P;
     const float inv_n = 1.f / (float)n;
@@ -215,33 +273,29 @@ k_loss_grad(const float *__restrict__ maps, int n, int h, int w, const dl_truth 
     const float mu = stats[3 * f], v = stats[3 * f + 1];
     const float l = M[k], p = sigmoidf(l), pq = p * (1.f - p);
     // cross-entropy and count
-    float gl = (p - (occupied(tr, e0, e1, row, col) ? 1.f : 0.f)) / (float)P;
+    float gl = (p - (occ[i] ? 1.f : 0.f)) / (float)P;
     const float dmu = -(E - mu) / v, dv = 0.5f / v - (E - mu) * (E - mu) / (2.f * v * v);
     gl += pq * (dmu + (1.f - 2.f * p) * dv);
-    // localisation: responsibilities of this pixel for each emitter
-    float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const float logmu = logf(mu);
-    float mv[4], sv[4], sg[4];
-    mv[0] = col + 0.5f + M[P + k];
-    mv[1] = row + 0.5f + M[2 * P + k];
-    mv[2] = M[3 * P + k];
-    mv[3] = M[4 * P + k];
+    // localisation: this pixel's responsibility for each emitter of its frame
+    float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float mv[4], is[4], sg[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        const float u = M[(5 + d) * P + k];
-        sv[d] = softplusf(u);
-        sg[d] = sigmoidf(u);
+        mv[d] = term[(1 + d) * np + i];
+        is[d] = term[(5 + d) * np + i];
+        sg[d] = sigmoidf(M[(5 + d) * P + k]);
     }
+    const float logmu = logf(mu);
     for (int e = e0; e < e1; ++e) {
         const dl_truth t = tr[e];
-        const float r = expf(loc_q(M, P, k, row, col, t, zs, ps, logmu) - lse[e]);
         const float tv[4] = {t.x, t.y, t.z_nm / zs, t.photons / ps};
+        const float r = expf(mix_q(term, np, i, tv) - logmu - lse[e]);
         gl += -r * (1.f - p) + pq / mu;
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-            const float dm = tv[d] - mv[d], s = sv[d];
-            g[d] += -r * dm / (s * s);
-            g[4 + d] += -r * (-1.f / s + dm * dm / (s * s * s)) * sg[d];
+            const float dm = tv[d] - mv[d], z = dm * is[d];
+            g[d] += -r * dm * is[d] * is[d];
+            g[4 + d] += -r * (z * z - 1.f) * is[d] * sg[d];
         }
     }
     G[k] = gl * inv_n;
@@ -437,7 +491,8 @@ hipError_t launch_pack_conv(const float *W, int cout, int cin, int flip, float *
 
 hipError_t launch_train_loss(int C, const float *act, const float *hw, const float *hb, int n, int h, int w,
                              const dl_truth *tr, const int32_t *toff, int ntruth, float zs, float ps, float *maps,
-                             float *stats, float *lse, float *gm, float *loss, hipStream_t s)
+                             float *stats, float *lse, float *gm, float *loss, float *term, uint8_t *occ,
+                             hipStream_t s)
 {
     const int64_t hwpx = (int64_t)h * w, npx = (int64_t)n * hwpx;
     const unsigned gp = (unsigned)((npx + 255) / 256);
@@ -447,10 +502,18 @@ hipError_t launch_train_loss(int C, const float *act, const float *hw, const flo
         hipLaunchKernelGGL(k_head_fwd<16>, dim3(gp), dim3(256), 0, s, act, hw, hb, npx, hwpx, maps);
     else
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_frame_stats, dim3(n), dim3(256), 0, s, maps, h, w, tr, toff, 1e-4f, stats);
+    hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)std::min<int64_t>(gp, 4096)), dim3(256), 0, s, occ, npx);
     if (ntruth > 0)
-        hipLaunchKernelGGL(k_loc_lse, dim3(ntruth), dim3(256), 0, s, maps, n, h, w, tr, toff, stats, zs, ps, lse);
-    hipLaunchKernelGGL(k_loss_grad, dim3(gp), dim3(256), 0, s, maps, n, h, w, tr, toff, stats, lse, zs, ps, gm);
+        hipLaunchKernelGGL(k_occupancy, dim3((ntruth + 255) / 256), dim3(256), 0, s, tr, toff, n, ntruth, h, w, occ);
+    hipLaunchKernelGGL(k_pix_terms, dim3(gp), dim3(256), 0, s, maps, n, h, w, term);
+    // the stats' partials sit in lse's place until the per-frame sums are taken
+    float *partial = term + 9 * npx;
+    hipLaunchKernelGGL(k_frame_stats, dim3(n * STAT_CHUNKS), dim3(256), 0, s, maps, h, w, occ, partial);
+    hipLaunchKernelGGL(k_frame_stats_sum, dim3((n + 255) / 256), dim3(256), 0, s, partial, n, 1e-4f, stats);
+    if (ntruth > 0)
+        hipLaunchKernelGGL(k_loc_lse, dim3(ntruth), dim3(256), 0, s, term, n, h, w, tr, toff, stats, zs, ps, lse);
+    hipLaunchKernelGGL(k_loss_grad, dim3(gp), dim3(256), 0, s, maps, term, occ, n, h, w, tr, toff, stats, lse, zs, ps,
+                       gm);
     hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, n, h, w, toff, stats, lse, loss);
     return hipGetLastError();
 }
