@@ -1188,7 +1188,8 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
     const size_t maps = take((size_t)P * 10), gm = take((size_t)P * 10);
     const size_t stats = take((size_t)3 * n), lse = take((size_t)std::max(ntruth, 1));
     const size_t term = take((size_t)9 * P + 48 * (size_t)n), occ = take((size_t)(P + 3) / 4);
-    const size_t part = take((size_t)nblk * 9 * C * C), pb = take((size_t)nblk * C), tmp = take((size_t)9 * C * C);
+    const size_t part = take((size_t)nblk * 9 * C * C), pb = take((size_t)nblk * C), tmp = take((size_t)33 * 9 * C * C);
+    const size_t gpart = take((size_t)grad_chunks(P) * (10 * C + 10));
     if (off > net->t_ws_bytes) {
         HIPCHK(net, hipDeviceSynchronize());
         if (net->t_ws) HIPCHK(net, hipFree(net->t_ws));
@@ -1261,8 +1262,8 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
                                   reinterpret_cast<uint8_t *>(net->t_ws + occ), s));
     // backward: du is the gradient at the pre-activation of block b's output
     float *du = F(g0), *dn = F(g1);
-    HIPCHK(net, launch_head_backward(C, F(gm), F(act[nb]), prm + o.head_w, n, h, w, grd + o.head_w, grd + o.head_b,
-                                     du, s));
+    HIPCHK(net, launch_head_backward(C, F(gm), F(act[nb]), prm + o.head_w, n, h, w, grd + o.head_w, F(gpart),
+                                     F(tmp) + 9 * C * C, du, s));
     for (int b = nb - 1; b >= 0; --b) {
         HIPCHK(net, launch_wgrad(C, du, F(T[b]), n, h, w, net->dil[b], F(part), F(pb), F(tmp), grd + o.w2[b],
                                  grd + o.b2[b], s));
@@ -1272,7 +1273,8 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
         HIPCHK(net, conv(b, 0, 1, F(dsb), dn, nullptr, du, F(act[b]), 0));              // (du + W1^T ds) at a_b > 0
         std::swap(du, dn);
     }
-    HIPCHK(net, launch_stem_grad(du, d_frames, n, h, w, net->cfg.offset, scale, C, grd + o.stem_w, grd + o.stem_b, s));
+    HIPCHK(net, launch_stem_grad(du, d_frames, n, h, w, net->cfg.offset, scale, C, grd + o.stem_w, F(gpart),
+                                 F(tmp) + 9 * C * C, s));
     HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
     return DL_OK;
 }

@@ -314,15 +314,20 @@ hipError_t launch_train_loss(int C, const float *act, const float *hw, const flo
                              const dl_truth *tr, const int32_t *toff, int ntruth, float zs, float ps, float *maps,
                              float *stats, float *lse, float *gm, float *loss, float *term, uint8_t *occ,
                              hipStream_t s);
-// head weight/bias gradients and the gradient at the last block's pre-activation
+// head weight/bias gradients (gwb: head.w then head.b) and the gradient at the
+// last block's pre-activation; part: grad_chunks(n h w) x (10 C + 10) floats,
+// mid: 32 x (10 C + 10)
+int grad_chunks(int64_t npx);
 hipError_t launch_head_backward(int C, const float *gm, const float *act, const float *hw, int n, int h, int w,
-                                float *gw, float *gb, float *du, hipStream_t s);
-// 3x3 weight and bias gradients; part holds 256 x 9 C^2 floats, pb 256 C, tmp 9 C^2
+                                float *gwb, float *part, float *mid, float *du, hipStream_t s);
+// 3x3 weight and bias gradients; part holds nblk x 9 C^2 floats and pb nblk C,
+// nblk = ceil(n h / wgrad_rows_per_block(n, h)); tmp 33 x 9 C^2
 int wgrad_rows_per_block(int n, int h);
 hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, int w, int d, float *part, float *pb,
                         float *tmp, float *gW, float *gb, hipStream_t s);
+// stem weight/bias gradients (gwb: stem.w then stem.b); part: grad_chunks(n h w) x 10 C
 hipError_t launch_stem_grad(const float *ds, const uint16_t *frames, int n, int h, int w, float offset, float scale,
-                            int C, float *gw, float *gb, hipStream_t s);
+                            int C, float *gwb, float *part, float *mid, hipStream_t s);
 
 // one plain dense-kernel layer with the training epilogue (see DenseConvArgs)
 hipError_t launch_dconv_train(int nb_out, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s);

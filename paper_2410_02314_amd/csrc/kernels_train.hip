@@ -18,12 +18,12 @@
 //                   pass with a running maximum
 //   k_loss_grad     per pixel: d loss / d maps (10 planes)
 //   k_loss_total    the batch means of the loss terms
-//   k_head_grad     head weight and bias gradients (one block per output)
+//   k_head_grad_part head weight and bias gradient partials per pixel chunk
 //   k_head_back     d loss / d (last block's pre-activation)
 //   k_wgrad         3x3 weight gradient partial sums per workgroup on MFMA:
 //                   dW[co][ci][tap] = sum_p dy[p][co] x[p + off(tap)][ci]
 //   k_sum_partials  fixed-order sums of per-workgroup partials
-//   k_stem_grad     stem weight and bias gradients
+//   k_stem_grad_part stem weight and bias gradient partials per pixel chunk
 // Reductions run in a fixed order: the gradients do not depend on timing.
 #include <algorithm>
 #include <cmath>
@@ -330,24 +330,28 @@ k_loss_total(int n, int h, int w, const int32_t *__restrict__ toff, const float 
     }
 }
 
-// one block per (q, c): grad[q][c] = sum_p gm[q][p] a[p][c]; c == C: the bias
+constexpr int GCHUNK = 256;   // pixels per workgroup of the head and stem gradient partials
+
+// head gradient partials: workgroup b sums over pixels [b GCHUNK, b GCHUNK + GCHUNK);
+// part[b][q C + c] = sum gm[q][p] a[p][c], part[b][10 C + q] = sum gm[q][p]
 template <int C>
 __global__ void __launch_bounds__(256)
-k_head_grad(const float *__restrict__ gm, const float *__restrict__ act, int64_t npx, int64_t hwpx,
-            float *__restrict__ gw, float *__restrict__ gb)
+k_head_grad_part(const float *__restrict__ gm, const float *__restrict__ act, int64_t npx, int64_t hwpx,
+                 float *__restrict__ part)
 {
-    __shared__ float sh[256];
-    const int q = blockIdx.x / (C + 1), c = blockIdx.x % (C + 1);
-    float s = 0.f;
-    for (int64_t p = threadIdx.x; p < npx; p += 256) {
-        const int64_t f = p / hwpx, k = p - f * hwpx;
-        const float g = gm[(f * 10 + q) * hwpx + k];
-        s += c < C ? g * act[p * C + c] : g;
-    }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) {
-        if (c < C) gw[q * C + c] = s;
-        else gb[q] = s;
+    const int t = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * GCHUNK, p1 = min(npx, p0 + GCHUNK);
+    float *P = part + (size_t)blockIdx.x * (10 * C + 10);
+    for (int o = t; o < 10 * (C + 1); o += 256) {
+        const int q = o / (C + 1), c = o - q * (C + 1);
+        float s = 0.f;
+        for (int64_t p = p0; p < p1; ++p) {
+            const int64_t f = p / hwpx, k = p - f * hwpx;
+            const float g = gm[(f * 10 + q) * hwpx + k];
+            s += c < C ? g * act[p * C + c] : g;
+        }
+        if (c < C) P[q * C + c] = s;
+        else P[10 * C + q] = s;
     }
 }
 
@@ -443,6 +447,21 @@ k_sum_partials(const float *__restrict__ part, int nb, int m, float *__restrict_
     out[j] = s;
 }
 
+// first stage of the same sum for many partials: out[g][j] = sum over
+// b in [g G, g G + G) of part[b][j], G = ceil(nb / ng)
+__global__ void __launch_bounds__(256)
+k_sum_partials_grouped(const float *__restrict__ part, int nb, int m, int ng, float *__restrict__ out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)ng * m) return;
+    const int g = (int)(idx / m), j = (int)(idx - (int64_t)g * m);
+    const int G = (nb + ng - 1) / ng;
+    const int b0 = g * G, b1 = min(nb, b0 + G);
+    float s = 0.f;
+    for (int b = b0; b < b1; ++b) s += part[(size_t)b * m + j];
+    out[idx] = s;
+}
+
 // dW[co][ci][tap] <- part sums laid out [tap][co][ci]
 __global__ void __launch_bounds__(256)
 k_wgrad_layout(const float *__restrict__ t_co_ci, int C, float *__restrict__ W)
@@ -453,31 +472,42 @@ k_wgrad_layout(const float *__restrict__ t_co_ci, int C, float *__restrict__ W)
     W[j] = t_co_ci[((size_t)t * C + co) * C + ci];
 }
 
-// stem: one block per (c, tap), tap 9 = the bias: sum_p ds[p][c] x(p + off)
+// stem gradient partials over pixels [b GCHUNK, b GCHUNK + GCHUNK):
+// part[b][c 9 + tap] = sum ds[p][c] x(p + off(tap)), part[b][9 C + c] = sum ds[p][c]
 __global__ void __launch_bounds__(256)
-k_stem_grad(const float *__restrict__ ds, const uint16_t *__restrict__ frames, int n, int h, int w, float offset,
-            float scale, int C, float *__restrict__ gw, float *__restrict__ gb)
+k_stem_grad_part(const float *__restrict__ ds, const uint16_t *__restrict__ frames, int n, int h, int w,
+                 float offset, float scale, int C, float *__restrict__ part)
 {
-    __shared__ float sh[256];
-    const int c = blockIdx.x / 10, t = blockIdx.x % 10;
-    const int64_t P = (int64_t)n * h * w;
-    float s = 0.f;
-    for (int64_t p = threadIdx.x; p < P; p += 256) {
-        const float g = ds[p * C + c];
-        if (t == 9) {
-            s += g;
-            continue;
+    const int64_t hw = (int64_t)h * w, P = (int64_t)n * hw;
+    const int64_t p0 = (int64_t)blockIdx.x * GCHUNK, p1 = min(P, p0 + GCHUNK);
+    float *O = part + (size_t)blockIdx.x * 10 * C;
+    for (int o = threadIdx.x; o < 10 * C; o += 256) {
+        const int c = o % C, t = o / C;             // consecutive threads: consecutive channels
+        float s = 0.f;
+        for (int64_t p = p0; p < p1; ++p) {
+            const float g = ds[p * C + c];
+            if (t == 9) {
+                s += g;
+                continue;
+            }
+            const int64_t f = p / hw, k = p - f * hw;
+            const int y = (int)(k / w) + t / 3 - 1, xx = (int)(k % w) + t % 3 - 1;
+            if ((unsigned)y < (unsigned)h && (unsigned)xx < (unsigned)w)
+                s += g * (((float)frames[(f * h + y) * w + xx] - offset) * scale);
         }
-        const int64_t f = p / ((int64_t)h * w), k = p - f * h * w;
-        const int y = (int)(k / w) + t / 3 - 1, xx = (int)(k % w) + t % 3 - 1;
-        if ((unsigned)y < (unsigned)h && (unsigned)xx < (unsigned)w)
-            s += g * (((float)frames[(f * h + y) * w + xx] - offset) * scale);
+        if (t < 9) O[c * 9 + t] = s;
+        else O[9 * C + c] = s;
     }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) {
-        if (t < 9) gw[c * 9 + t] = s;
-        else gb[c] = s;
-    }
+}
+
+// the sum over nb partials of m values in two fixed-order stages (groups, then
+// the groups' sums); mid holds 32 m floats
+void reduce_partials(const float *part, int nb, int m, float *mid, float *out, hipStream_t s)
+{
+    const int ng = std::min(32, nb);
+    hipLaunchKernelGGL(k_sum_partials_grouped, dim3((unsigned)(((int64_t)ng * m + 255) / 256)), dim3(256), 0, s, part,
+                       nb, m, ng, mid);
+    hipLaunchKernelGGL(k_sum_partials, dim3((m + 255) / 256), dim3(256), 0, s, mid, ng, m, out);
 }
 
 }  // namespace
@@ -518,24 +548,30 @@ hipError_t launch_train_loss(int C, const float *act, const float *hw, const flo
     return hipGetLastError();
 }
 
+int grad_chunks(int64_t npx) { return (int)((npx + GCHUNK - 1) / GCHUNK); }
+
 hipError_t launch_head_backward(int C, const float *gm, const float *act, const float *hw, int n, int h, int w,
-                                float *gw, float *gb, float *du, hipStream_t s)
+                                float *gwb, float *part, float *mid, float *du, hipStream_t s)
 {
     const int64_t hwpx = (int64_t)h * w, npx = (int64_t)n * hwpx;
     const unsigned gp = (unsigned)((npx + 255) / 256);
+    const int nb = grad_chunks(npx);
     if (C == 32) {
-        hipLaunchKernelGGL(k_head_grad<32>, dim3(10 * 33), dim3(256), 0, s, gm, act, npx, hwpx, gw, gb);
+        hipLaunchKernelGGL(k_head_grad_part<32>, dim3(nb), dim3(256), 0, s, gm, act, npx, hwpx, part);
         hipLaunchKernelGGL(k_head_back<32>, dim3(gp), dim3(256), 0, s, gm, hw, act, npx, hwpx, du);
     } else if (C == 16) {
-        hipLaunchKernelGGL(k_head_grad<16>, dim3(10 * 17), dim3(256), 0, s, gm, act, npx, hwpx, gw, gb);
+        hipLaunchKernelGGL(k_head_grad_part<16>, dim3(nb), dim3(256), 0, s, gm, act, npx, hwpx, part);
         hipLaunchKernelGGL(k_head_back<16>, dim3(gp), dim3(256), 0, s, gm, hw, act, npx, hwpx, du);
     } else {
         return hipErrorInvalidValue;
     }
+    reduce_partials(part, nb, 10 * C + 10, mid, gwb, s);   // head.w then head.b, as in the blob
     return hipGetLastError();
 }
 
-int wgrad_rows_per_block(int n, int h) { return std::max(1, (n * h + 255) / 256); }
+// about 1024 workgroups: four waves each, so enough waves per SIMD to hide the
+// operand loads' latency
+int wgrad_rows_per_block(int n, int h) { return std::max(1, (n * h + 1023) / 1024); }
 
 hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, int w, int d, float *part, float *pb,
                         float *tmp, float *gW, float *gb, hipStream_t s)
@@ -549,16 +585,19 @@ hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, in
     else
         return hipErrorInvalidValue;
     const int m = 9 * C * C;
-    hipLaunchKernelGGL(k_sum_partials, dim3((m + 255) / 256), dim3(256), 0, s, part, nblk, m, tmp);
+    float *mid = tmp + m;
+    reduce_partials(part, nblk, m, mid, tmp, s);
     hipLaunchKernelGGL(k_wgrad_layout, dim3((m + 255) / 256), dim3(256), 0, s, tmp, C, gW);
-    hipLaunchKernelGGL(k_sum_partials, dim3((C + 255) / 256), dim3(256), 0, s, pb, nblk, C, gb);
+    reduce_partials(pb, nblk, C, mid, gb, s);
     return hipGetLastError();
 }
 
 hipError_t launch_stem_grad(const float *ds, const uint16_t *frames, int n, int h, int w, float offset, float scale,
-                            int C, float *gw, float *gb, hipStream_t s)
+                            int C, float *gwb, float *part, float *mid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stem_grad, dim3(C * 10), dim3(256), 0, s, ds, frames, n, h, w, offset, scale, C, gw, gb);
+    const int nb = grad_chunks((int64_t)n * h * w);
+    hipLaunchKernelGGL(k_stem_grad_part, dim3(nb), dim3(256), 0, s, ds, frames, n, h, w, offset, scale, C, part);
+    reduce_partials(part, nb, 10 * C, mid, gwb, s);           // stem.w then stem.b, as in the blob
     return hipGetLastError();
 }
 
