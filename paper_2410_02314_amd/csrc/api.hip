@@ -1186,9 +1186,10 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
     for (int b = 0; b < nb; ++b) T[b] = take((size_t)P * C);
     const size_t g0 = take((size_t)P * C), g1 = take((size_t)P * C), dsb = take((size_t)P * C);
     const size_t maps = take((size_t)P * 10), gm = take((size_t)P * 10);
-    const size_t stats = take((size_t)3 * n), lse = take((size_t)std::max(ntruth, 1));
+    const size_t stats = take((size_t)3 * n), lse = take((size_t)train_lse_floats(h, w, ntruth));
     const size_t term = take((size_t)9 * P + 48 * (size_t)n), occ = take((size_t)(P + 3) / 4);
-    const size_t part = take((size_t)nblk * 9 * C * C), pb = take((size_t)nblk * C), tmp = take((size_t)33 * 9 * C * C);
+    const size_t part = take((size_t)nblk * 9 * C * C), pb = take((size_t)nblk * C);
+    const size_t tmp = take((size_t)32 * (9 * C * C + C));
     const size_t gpart = take((size_t)grad_chunks(P) * (10 * C + 10));
     if (off > net->t_ws_bytes) {
         HIPCHK(net, hipDeviceSynchronize());
@@ -1225,10 +1226,9 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
     if (slot < 0) return slot;
     // packed conv weights: [block][conv 1, 2][forward, transposed]
     auto pk = [&](int b, int k, int tr) { return net->t_pack + ((size_t)(b * 2 + k) * 2 + tr) * C * C * 9; };
-    for (int b = 0; b < nb; ++b)
-        for (int k = 0; k < 2; ++k)
-            for (int tr = 0; tr < 2; ++tr)
-                HIPCHK(net, launch_pack_conv(prm + (k ? o.w2[b] : o.w1[b]), C, C, tr, pk(b, k, tr), s));
+    // (the blob holds w1, b1, w2, b2 of each block in turn: the 3x3 weights
+    // follow one another 9 C^2 + C floats apart)
+    HIPCHK(net, launch_pack_convs(prm + o.w1[0], (int64_t)9 * C * C + C, 2 * nb, C, net->t_pack, s));
     auto conv = [&](int b, int k, int tr, float *in, float *out, const float *bias, const float *res,
                     const float *mask, int relu) {
         DenseConvArgs a{};

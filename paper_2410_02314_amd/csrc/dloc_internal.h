@@ -304,12 +304,16 @@ int dense_tile_cols();
 hipError_t launch_dconv(int nb_out, int fuse, int nt, const DenseConvArgs &a, const Geometry &g, int ncu,
                         hipStream_t s);
 // ---- training (kernels_train.hip) ----
-// a 3x3 conv's flat weights [cout][cin][9] into the conv kernel's layout;
-// flip: the transposed convolution's weights (cout and cin swapped, taps reversed)
-hipError_t launch_pack_conv(const float *W, int cout, int cin, int flip, float *dst, hipStream_t s);
+// count square 3x3 convs' flat weights [C][C][9], the i-th at W0 + i src_stride,
+// into the conv kernel's layout, each as itself (dst + 2 i 9 C^2) and as the
+// transposed convolution (dst + (2 i + 1) 9 C^2: cout and cin swapped, taps reversed)
+hipError_t launch_pack_convs(const float *W0, int64_t src_stride, int count, int C, float *dst, hipStream_t s);
 // head (10 outputs) on the last activations, loss terms, their gradient with
 // respect to the maps (gm, planar like maps), batch means into loss[4];
-// term: 9 n h w + 48 n floats, occ: n h w bytes
+// term: 9 n h w + 48 n floats, occ: n h w bytes, lse: train_lse_floats(h, w,
+// ntruth) floats (the log-sum-exps first, then the emitters' constants and the
+// per-chunk partials)
+int64_t train_lse_floats(int h, int w, int ntruth);
 hipError_t launch_train_loss(int C, const float *act, const float *hw, const float *hb, int n, int h, int w,
                              const dl_truth *tr, const int32_t *toff, int ntruth, float zs, float ps, float *maps,
                              float *stats, float *lse, float *gm, float *loss, float *term, uint8_t *occ,
@@ -321,7 +325,7 @@ int grad_chunks(int64_t npx);
 hipError_t launch_head_backward(int C, const float *gm, const float *act, const float *hw, int n, int h, int w,
                                 float *gwb, float *part, float *mid, float *du, hipStream_t s);
 // 3x3 weight and bias gradients; part holds nblk x 9 C^2 floats and pb nblk C,
-// nblk = ceil(n h / wgrad_rows_per_block(n, h)); tmp 33 x 9 C^2
+// nblk = ceil(n h / wgrad_rows_per_block(n, h)); tmp 32 x (9 C^2 + C)
 int wgrad_rows_per_block(int n, int h);
 hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, int w, int d, float *part, float *pb,
                         float *tmp, float *gW, float *gb, hipStream_t s);

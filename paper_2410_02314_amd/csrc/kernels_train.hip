@@ -13,15 +13,17 @@
 //   k_pix_terms     per pixel: log p - sum_d log s_d - 2 log 2 pi, m_d, 1 / s_d
 //   k_frame_stats   per frame: mu = sum p, v = sum p (1 - p) + eps, BCE sum
 //                   (16 blocks per frame, then summed in order)
-//   k_loc_lse       per true emitter: log-sum-exp over its frame's pixels of
-//                   q_k = log p_k - log mu + sum_d log N(t_d; m_kd, s_kd^2), one
-//                   pass with a running maximum
+//   k_lse_part      per true emitter and pixel chunk of its frame: partial
+//                   log-sum-exp of q_k = log p_k - log mu + sum_d log N(t_d;
+//                   m_kd, s_kd^2) (one lane per emitter, the chunk's pixel terms
+//                   in LDS, a running maximum)
+//   k_lse_fin       per true emitter: the chunks combined in order
 //   k_loss_grad     per pixel: d loss / d maps (10 planes)
 //   k_loss_total    the batch means of the loss terms
 //   k_head_grad_part head weight and bias gradient partials per pixel chunk
 //   k_head_back     d loss / d (last block's pre-activation)
-//   k_wgrad         3x3 weight gradient partial sums per workgroup on MFMA:
-//                   dW[co][ci][tap] = sum_p dy[p][co] x[p + off(tap)][ci]
+//   k_wgrad         3x3 weight and bias gradient partial sums per workgroup on
+//                   MFMA: dW[co][ci][tap] = sum_p dy[p][co] x[p + off(tap)][ci]
 //   k_sum_partials  fixed-order sums of per-workgroup partials
 //   k_stem_grad_part stem weight and bias gradient partials per pixel chunk
 // Reductions run in a fixed order: the gradients do not depend on timing.
@@ -68,21 +70,28 @@ __device__ float block_max(float v, float *sh)
     return r;
 }
 
+// Packs count square 3x3 convolutions (C -> C) into the conv kernel's MFMA
+// layout, each twice: pack (i, fl) at dst + (2 i + fl) 9 C^2, from the flat
+// weights at W + i src_stride.  Within a pack,
 // dst[(((g 9 + t) NB + nb) 64 + lane) 4 + s] = Wp[16 nb + (lane & 15)][16 g + 4 (lane >> 4) + s][t]
-// with Wp = W [cout][cin][9], or (flip) Wp[o][c][t] = W[c][o][8 - t]
+// with Wp = W [C][C][9] (fl = 0), or Wp[o][c][t] = W[c][o][8 - t] (fl = 1: the
+// transposed convolution).
 __global__ void __launch_bounds__(256)
-k_pack_conv(const float *__restrict__ W, int cout, int cin, int flip, float *__restrict__ dst)
+k_pack_conv(const float *__restrict__ W0, int64_t src_stride, int count, int C, float *__restrict__ dst)
 {
-    const int n = cout * cin * 9;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const int NB = cout / 16;
+    const int n = C * C * 9;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)count * 2 * n) return;
+    const int pk = (int)(e / n), i = (int)(e - (int64_t)pk * n);
+    const int fl = pk & 1;
+    const float *W = W0 + (pk >> 1) * src_stride;
+    const int NB = C / 16;
     const int s = i & 3, lane = (i >> 2) & 63;
     const int rest = i >> 8;                 // ((g 9 + t) NB + nb)
     const int nb = rest % NB, gt = rest / NB;
     const int t = gt % 9, g = gt / 9;
     const int o = nb * 16 + (lane & 15), c = g * 16 + 4 * (lane >> 4) + s;
-    dst[i] = flip ? W[((size_t)c * cout + o) * 9 + (8 - t)] : W[((size_t)o * cin + c) * 9 + t];
+    dst[e] = fl ? W[((size_t)c * C + o) * 9 + (8 - t)] : W[((size_t)o * C + c) * 9 + t];
 }
 
 template <int C>
@@ -204,69 +213,156 @@ k_frame_stats_sum(const float *__restrict__ partial, int n, float eps, float *__
     stats[3 * f + 2] = a[2];
 }
 
-// q of emitter target tv at pixel i, from the pixel terms (without -log mu)
-__device__ __forceinline__ float mix_q(const float *__restrict__ term, int64_t np, int64_t i, const float (&tv)[4])
+// The localisation term's log-sum-exp over a frame's pixels, per true emitter,
+// is computed in base 2 (q' = q log2 e): a pixel's q' is
+//   q'_k = log2e term0_k - (log2e / 2) sum_d ((t_d - m_kd) / s_kd)^2.
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr float LN2 = 0.6931471805599453f;
+constexpr int LSE_MAX_CHUNKS = 64;   // pixel chunks per frame whose partials are combined per emitter
+constexpr int EM_STRIDE = 8;         // floats of an emitter's constants
+
+// Emitter constants em[e] = {t_x, t_y, t_z, t_N, lse2_e, -, -, -}: the targets
+// in the maps' units and log2 sum_k 2^(q'_k) over the emitter's frame.
+__device__ __forceinline__ void target_of(const dl_truth &t, float izs, float ips, float (&tv)[4])
 {
-    float q = term[i], z2 = 0.f;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        const float z = (tv[d] - term[(1 + d) * np + i]) * term[(5 + d) * np + i];
-        z2 += z * z;
-    }
-    return q - 0.5f * z2;
+    tv[0] = t.x;
+    tv[1] = t.y;
+    tv[2] = t.z_nm * izs;
+    tv[3] = t.photons * ips;
 }
 
-// lse[e] = log sum_k exp(q_ek) - log mu over emitter e's frame, one pass with
-// a running maximum per thread, then (max, sum) pairs combined in a fixed order
+// the pixel chunks of the log-sum-exp: chunk c of a frame covers the 256-pixel
+// groups [c spc, c spc + spc), spc = ceil(ceil(P / 256) / LSE_MAX_CHUNKS)
+__host__ __device__ __forceinline__ int lse_groups_per_chunk(int64_t P)
+{
+    const int64_t g = (P + 255) / 256;
+    return (int)((g + LSE_MAX_CHUNKS - 1) / LSE_MAX_CHUNKS);
+}
+__host__ __device__ __forceinline__ int lse_chunks(int64_t P)
+{
+    const int64_t g = (P + 255) / 256, spc = lse_groups_per_chunk(P);
+    return (int)((g + spc - 1) / spc);
+}
+
+// Partial log-sum-exp of every true emitter of frame f over one pixel chunk:
+// one lane per emitter, the chunk's pixel terms staged in LDS 256 at a time
+// and read by all lanes at once; a running (max, sum of 2^(q' - max)) per lane
+// updated eight pixels at a time.  part[(e nch + c) 2 + {0, 1}] = (max, sum).
 __global__ void __launch_bounds__(256)
-k_loc_lse(const float *__restrict__ term, int n, int h, int w, const dl_truth *__restrict__ tr,
-          const int32_t *__restrict__ toff, const float *__restrict__ stats, float zs, float ps, float *__restrict__ lse)
+k_lse_part(const float *__restrict__ term, int n, int h, int w, const dl_truth *__restrict__ tr,
+           const int32_t *__restrict__ toff, float izs, float ips, float *__restrict__ part)
 {
-    __shared__ float smx[256], ssm[256];
-    const int e = blockIdx.x;
-    const int f = find_frame_off(toff, n, e);
-    const int64_t P = (int64_t)h * w, np = (int64_t)n * P, base = (int64_t)f * P;
-    const dl_truth t = tr[e];
-    const float tv[4] = {t.x, t.y, t.z_nm / zs, t.photons / ps};
-    float mx = -INFINITY, sm = 0.f;
-    for (int64_t k = threadIdx.x; k < P; k += 256) {
-        const float q = mix_q(term, np, base + k, tv);
-        if (q > mx) {
-            sm = sm * expf(mx - q) + 1.f;
-            mx = q;
-        } else {
-            sm += expf(q - mx);
+    __shared__ __align__(16) float4 sa[256], sb[256];
+    __shared__ float sc[256];
+    const int64_t P = (int64_t)h * w, np = (int64_t)n * P;
+    const int nch = lse_chunks(P), spc = lse_groups_per_chunk(P);
+    const int f = blockIdx.x / nch, c = blockIdx.x - f * nch;
+    const int e0 = toff[f], e1 = toff[f + 1];
+    const int t = threadIdx.x;
+    const int64_t k0 = (int64_t)c * spc * 256, k1 = std::min<int64_t>(P, k0 + (int64_t)spc * 256);
+    const float hz = -0.5f * LOG2E;
+    for (int eg = e0; eg < e1; eg += 256) {
+        const int e = eg + t;
+        float tv[4] = {0.f, 0.f, 0.f, 0.f};
+        if (e < e1) target_of(tr[e], izs, ips, tv);
+        float m = -3.0e38f, s = 0.f;
+        for (int64_t kb = k0; kb < k1; kb += 256) {
+            __syncthreads();
+            {
+                const int64_t k = kb + t;
+                if (k < k1) {
+                    const int64_t i = (int64_t)f * P + k;
+                    sa[t] = make_float4(term[i] * LOG2E, term[np + i], term[2 * np + i], term[3 * np + i]);
+                    sb[t] = make_float4(term[4 * np + i], term[5 * np + i], term[6 * np + i], term[7 * np + i]);
+                    sc[t] = term[8 * np + i];
+                } else {                      // past the frame: q' = -inf
+                    sa[t] = make_float4(-INFINITY, 0.f, 0.f, 0.f);
+                    sb[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    sc[t] = 0.f;
+                }
+            }
+            __syncthreads();
+            if (e >= e1) continue;
+            for (int j0 = 0; j0 < 256; j0 += 8) {
+                float q[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float4 A = sa[j0 + j], B = sb[j0 + j];
+                    const float zx = (tv[0] - A.y) * B.y, zy = (tv[1] - A.z) * B.z;
+                    const float zz = (tv[2] - A.w) * B.w, zn = (tv[3] - B.x) * sc[j0 + j];
+                    q[j] = fmaf(hz, zx * zx + zy * zy + zz * zz + zn * zn, A.x);
+                }
+                float mx = q[0];
+#pragma unroll
+                for (int j = 1; j < 8; ++j) mx = fmaxf(mx, q[j]);
+                const float mn = fmaxf(m, mx);
+                float a = s * __builtin_amdgcn_exp2f(m - mn);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a += __builtin_amdgcn_exp2f(q[j] - mn);
+                s = a;
+                m = mn;
+            }
+        }
+        if (e < e1) {
+            part[((size_t)e * nch + c) * 2] = m;
+            part[((size_t)e * nch + c) * 2 + 1] = s;
         }
     }
-    const int tid = threadIdx.x;
-    smx[tid] = mx;
-    ssm[tid] = sm;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) {
-            const float m1 = smx[tid], m2 = smx[tid + o];
-            const float m = fmaxf(m1, m2);
-            ssm[tid] = (m1 == -INFINITY ? 0.f : ssm[tid] * expf(m1 - m)) + (m2 == -INFINITY ? 0.f : ssm[tid + o] * expf(m2 - m));
-            smx[tid] = m;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) lse[e] = smx[0] + logf(ssm[0]) - logf(stats[3 * f]);
 }
 
-// d (batch mean loss) / d maps, one thread per pixel of the batch
+// Per emitter (a wave each, lane c holding chunk c): the chunks' partials
+// combined by a fixed butterfly; lse[e] = the localisation log-sum-exp
+// (natural log, with -log mu), em[e] its constants.
+__global__ void __launch_bounds__(256)
+k_lse_fin(int n, int h, int w, const dl_truth *__restrict__ tr, const int32_t *__restrict__ toff, int ntruth,
+          const float *__restrict__ stats, float izs, float ips, const float *__restrict__ part, float *__restrict__ lse,
+          float *__restrict__ em)
+{
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (e >= ntruth) return;
+    const int nch = lse_chunks((int64_t)h * w);
+    const float *pp = part + (size_t)e * nch * 2;
+    const float m = lane < nch ? pp[2 * lane] : -3.0e38f;
+    float M = m;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) M = fmaxf(M, __shfl_xor(M, o));
+    float S = lane < nch ? pp[2 * lane + 1] * exp2f(m - M) : 0.f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
+    if (lane != 0) return;
+    const int f = find_frame_off(toff, n, e);
+    const float l2 = M + log2f(S);
+    lse[e] = l2 * LN2 - logf(stats[3 * f]);
+    float tv[4];
+    target_of(tr[e], izs, ips, tv);
+    float *o = em + (size_t)e * EM_STRIDE;
+    o[0] = tv[0];
+    o[1] = tv[1];
+    o[2] = tv[2];
+    o[3] = tv[3];
+    o[4] = l2;
+    o[5] = o[6] = o[7] = 0.f;
+}
+
+// d (batch mean loss) / d maps: workgroup (f, chunk) takes 256 pixels of frame
+// f, one per thread; the frame's emitters are the same for the whole
+// workgroup, so their constants are read once per wave.  r_ek = 2^(q'_ek -
+// lse2_e) is pixel k's responsibility for emitter e; with R = sum_e r_ek, Z_d =
+// sum_e r z_d, Z2_d = sum_e r z_d^2 (z_d = (t_d - m_kd) / s_kd):
+//   d/dl   = (p - y) / P + p(1-p) (dmu + (1 - 2p) dv) - (1 - p) R + E p (1-p) / mu
+//   d/dm_d = -Z_d / s_d,   d/du_d = -(Z2_d - R) sigmoid(u_d) / s_d
 __global__ void __launch_bounds__(256)
 k_loss_grad(const float *__restrict__ maps, const float *__restrict__ term, const uint8_t *__restrict__ occ, int n,
-            int h, int w, const dl_truth *__restrict__ tr, const int32_t *__restrict__ toff,
-            const float *__restrict__ stats, const float *__restrict__ lse, float zs, float ps, float *__restrict__ gm)
+            int h, int w, const int32_t *__restrict__ toff, const float *__restrict__ stats,
+            const float *__restrict__ em, float *__restrict__ gm)
 {
-    const int64_t P = (int64_t)h * w, np = (int64_t)n * P;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= np) return;
-    const int f = (int)(i / P);
-    const int64_t k = i - (int64_t)f * P;
-    const float *M = maps + (int64_t)f * 10 * P;
-    float *G = gm + (int64_t)f * 10 * P;
+    const int P = h * w, np = n * P;
+    const int cpf = (P + 255) / 256;
+    const int f = blockIdx.x / cpf, k = (blockIdx.x - f * cpf) * 256 + threadIdx.x;
+    if (k >= P) return;
+    const int i = f * P + k;
+    const float *M = maps + (size_t)f * 10 * P;
+    float *G = gm + (size_t)f * 10 * P;
     const float inv_n = 1.f / (float)n;
     const int e0 = toff[f], e1 = toff[f + 1];
     const float E = (float)(e1 - e0);
@@ -276,37 +372,44 @@ k_loss_grad(const float *__restrict__ maps, const float *__restrict__ term, cons
     float gl = (p - (occ[i] ? 1.f : 0.f)) / (float)P;
     const float dmu = -(E - mu) / v, dv = 0.5f / v - (E - mu) * (E - mu) / (2.f * v * v);
     gl += pq * (dmu + (1.f - 2.f * p) * dv);
-    // localisation: this pixel's responsibility for each emitter of its frame
-    float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float mv[4], is[4], sg[4];
+    // localisation
+    float mv[4], is[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        mv[d] = term[(1 + d) * np + i];
-        is[d] = term[(5 + d) * np + i];
-        sg[d] = sigmoidf(M[(5 + d) * P + k]);
+        mv[d] = term[(size_t)(1 + d) * np + i];
+        is[d] = term[(size_t)(5 + d) * np + i];
     }
-    const float logmu = logf(mu);
+    const float q0 = term[i] * LOG2E, hz = -0.5f * LOG2E;
+    float R = 0.f, Z[4] = {0.f, 0.f, 0.f, 0.f}, Z2[4] = {0.f, 0.f, 0.f, 0.f};
     for (int e = e0; e < e1; ++e) {
-        const dl_truth t = tr[e];
-        const float tv[4] = {t.x, t.y, t.z_nm / zs, t.photons / ps};
-        const float r = expf(mix_q(term, np, i, tv) - logmu - lse[e]);
-        gl += -r * (1.f - p) + pq / mu;
+        const float *c = em + (size_t)e * EM_STRIDE;
+        float z[4], zz[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-            const float dm = tv[d] - mv[d], z = dm * is[d];
-            g[d] += -r * dm * is[d] * is[d];
-            g[4 + d] += -r * (z * z - 1.f) * is[d] * sg[d];
+            z[d] = (c[d] - mv[d]) * is[d];
+            zz[d] = z[d] * z[d];
+        }
+        const float r = __builtin_amdgcn_exp2f(fmaf(hz, zz[0] + zz[1] + zz[2] + zz[3], q0) - c[4]);
+        R += r;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            Z[d] = fmaf(r, z[d], Z[d]);
+            Z2[d] = fmaf(r, zz[d], Z2[d]);
         }
     }
+    gl += -(1.f - p) * R + E * pq / mu;
     G[k] = gl * inv_n;
 #pragma unroll
-    for (int d = 0; d < 8; ++d) G[(1 + d) * P + k] = g[d] * inv_n;
+    for (int d = 0; d < 4; ++d) {
+        G[(1 + d) * P + k] = -Z[d] * is[d] * inv_n;
+        G[(5 + d) * P + k] = -(Z2[d] - R) * is[d] * sigmoidf(M[(5 + d) * P + k]) * inv_n;
+    }
     G[9 * P + k] = 0.f;
 }
 
 // loss[4] = batch means of {total, bce, count, loc}
 __global__ void __launch_bounds__(256)
-k_loss_total(int n, int h, int w, const int32_t *__restrict__ toff, const float *__restrict__ stats,
+k_loss_total(int n, int h, int w, const int32_t *__restrict__ toff, int ntruth, const float *__restrict__ stats,
              const float *__restrict__ lse, float *__restrict__ loss)
 {
     __shared__ float sh[256];
@@ -317,8 +420,8 @@ k_loss_total(int n, int h, int w, const int32_t *__restrict__ toff, const float 
         const float E = (float)(toff[f + 1] - toff[f]);
         b += stats[3 * f + 2] / P;
         c += 0.5f * logf(TWO_PI * v) + (E - mu) * (E - mu) / (2.f * v);
-        for (int e = toff[f]; e < toff[f + 1]; ++e) l -= lse[e];
     }
+    for (int e = threadIdx.x; e < ntruth; e += 256) l -= lse[e];
     b = block_sum(b, sh);
     c = block_sum(c, sh);
     l = block_sum(l, sh);
@@ -332,191 +435,353 @@ k_loss_total(int n, int h, int w, const int32_t *__restrict__ toff, const float 
 
 constexpr int GCHUNK = 256;   // pixels per workgroup of the head and stem gradient partials
 
-// head gradient partials: workgroup b sums over pixels [b GCHUNK, b GCHUNK + GCHUNK);
-// part[b][q C + c] = sum gm[q][p] a[p][c], part[b][10 C + q] = sum gm[q][p]
+// Head gradient partials: workgroup b sums over pixels [b GCHUNK, b GCHUNK +
+// GCHUNK) of the batch; part[b][q C + c] = sum gm[q][p] a[p][c], part[b][10 C +
+// q] = sum gm[q][p].  The chunk's map gradients are staged in LDS (one pixel
+// per thread); thread (slot, c) then sums channel c over every (256 / C)-th
+// pixel, and the slots are added in order.
 template <int C>
 __global__ void __launch_bounds__(256)
-k_head_grad_part(const float *__restrict__ gm, const float *__restrict__ act, int64_t npx, int64_t hwpx,
+k_head_grad_part(const float *__restrict__ gm, const float *__restrict__ act, int npx, int hwpx,
                  float *__restrict__ part)
 {
-    const int t = threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.x * GCHUNK, p1 = min(npx, p0 + GCHUNK);
-    float *P = part + (size_t)blockIdx.x * (10 * C + 10);
-    for (int o = t; o < 10 * (C + 1); o += 256) {
-        const int q = o / (C + 1), c = o - q * (C + 1);
-        float s = 0.f;
-        for (int64_t p = p0; p < p1; ++p) {
-            const int64_t f = p / hwpx, k = p - f * hwpx;
-            const float g = gm[(f * 10 + q) * hwpx + k];
-            s += c < C ? g * act[p * C + c] : g;
-        }
-        if (c < C) P[q * C + c] = s;
-        else P[10 * C + q] = s;
+    constexpr int NS = 256 / C, NO = 10 * C + 10;
+    __shared__ float sg[10][GCHUNK];
+    __shared__ float red[NS][NO];
+    const int t = threadIdx.x, p0 = blockIdx.x * GCHUNK, np = min(GCHUNK, npx - p0);
+    if (t < np) {
+        const int p = p0 + t, f = p / hwpx, k = p - f * hwpx;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) sg[q][t] = gm[((size_t)f * 10 + q) * hwpx + k];
+    }
+    __syncthreads();
+    const int sl = t / C, c = t - sl * C;
+    float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, bacc = 0.f;
+    for (int j = sl; j < np; j += NS) {
+        const float a = act[(size_t)(p0 + j) * C + c];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[q] = fmaf(sg[q][j], a, acc[q]);
+        if (c < 10) bacc += sg[c][j];
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) red[sl][q * C + c] = acc[q];
+    if (c < 10) red[sl][10 * C + c] = bacc;
+    __syncthreads();
+    for (int o = t; o < NO; o += 256) {
+        float v = 0.f;
+        for (int k = 0; k < NS; ++k) v += red[k][o];
+        part[(size_t)blockIdx.x * NO + o] = v;
     }
 }
 
-// du[p][c] = (sum_q W[q][c] gm[q][p]) where a[p][c] > 0, else 0
+// du[p][c] = (sum_q W[q][c] gm[q][p]) where a[p][c] > 0, else 0: a thread per
+// (pixel, four channels), so a wave reads and writes 64 / (C / 4) whole points
 template <int C>
 __global__ void __launch_bounds__(256)
-k_head_back(const float *__restrict__ gm, const float *__restrict__ hw, const float *__restrict__ act, int64_t npx,
-            int64_t hwpx, float *__restrict__ du)
+k_head_back(const float *__restrict__ gm, const float *__restrict__ hw, const float *__restrict__ act, int npx,
+            int hwpx, float *__restrict__ du)
 {
+    constexpr int QT = C / 4;
     __shared__ float sw[10 * C];
     for (int i = threadIdx.x; i < 10 * C; i += 256) sw[i] = hw[i];
     __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    const int p = gid / QT, c0 = (gid - p * QT) * 4;
     if (p >= npx) return;
-    const int64_t f = p / hwpx, k = p - f * hwpx;
+    const int f = p / hwpx, k = p - f * hwpx;
     float g[10];
 #pragma unroll
-    for (int q = 0; q < 10; ++q) g[q] = gm[(f * 10 + q) * hwpx + k];
+    for (int q = 0; q < 10; ++q) g[q] = gm[((size_t)f * 10 + q) * hwpx + k];
+    const float4 a = *reinterpret_cast<const float4 *>(act + (size_t)p * C + c0);
+    float v[4];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
+    for (int j = 0; j < 4; ++j) {
         float s = 0.f;
 #pragma unroll
-        for (int q = 0; q < 10; ++q) s += sw[q * C + c] * g[q];
-        du[p * C + c] = act[p * C + c] > 0.f ? s : 0.f;
+        for (int q = 0; q < 10; ++q) s += sw[q * C + c0 + j] * g[q];
+        v[j] = s;
     }
+    *reinterpret_cast<float4 *>(du + (size_t)p * C + c0) =
+        make_float4(a.x > 0.f ? v[0] : 0.f, a.y > 0.f ? v[1] : 0.f, a.z > 0.f ? v[2] : 0.f, a.w > 0.f ? v[3] : 0.f);
 }
 
-// Weight gradient of a 3x3 conv at dilation d over NHWC tensors of C floats
-// per point (C = 16 CB): workgroup b takes rows [b R, b R + R) of the batch
-// (a frame's rows are consecutive), wave w the (co block, ci block) pair
-// w % (CB CB) for all 9 taps; v_mfma_f32_16x16x4_f32 with K = 4 pixels:
-// lane (i, kq) gives dy[pixel kq][co 16 cb + i] and x[pixel kq + off][ci 16 cb2 + i].
-// part[b][tap][co][ci] (+ part of the bias: pb[b][co]).
-template <int CB>
-__global__ void __launch_bounds__(256)
-k_wgrad(const float *__restrict__ dy, const float *__restrict__ x, int n, int h, int w, int d, int R,
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// The weight gradient's matrix instruction per channel count.  In both, lane l
+// gives channel l % C of pixel l / C to both operands (A = dy: rows are output
+// channels; B = x: columns are input channels), so K = 64 / C pixels per
+// instruction; C = 32 takes v_mfma_f32_32x32x2f32 (twice the arithmetic per
+// operand of the 16 x 16 x 4 form), C = 16 v_mfma_f32_16x16x4f32.  The
+// accumulator's registers come in groups of four rows of one column (l % C):
+// row0(l, g) is the first row of group g.
+template <int C> struct WgMma;
+template <> struct WgMma<32> {
+    typedef v16f acc_t;
+    static constexpr int NG = 4;
+    __device__ static acc_t mma(float a, float b, const acc_t &c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row0(int l, int g) { return 8 * g + 4 * (l >> 5); }
+};
+template <> struct WgMma<16> {
+    typedef v4f acc_t;
+    static constexpr int NG = 1;
+    __device__ static acc_t mma(float a, float b, const acc_t &c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row0(int l, int) { return 4 * (l >> 4); }
+};
+
+constexpr int WG_WAVES = 8;
+constexpr uint32_t BUF_FLAGS = 0x00020000u;   // raw buffer, 32-bit words
+constexpr int BUF_OOB = (int)0x80000000u;      // an offset past any buffer: reads zero
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float *base, uint32_t nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, (int)nbytes, (int)BUF_FLAGS);
+}
+
+// Weight gradient of a 3x3 conv at dilation d over NHWC tensors of C floats per
+// point: dW[co][ci][tap] = sum_p dy[p][co] x[p + off(tap)][ci] (zero off the
+// frame), db[co] = sum_p dy[p][co].  Wave v of workgroup b takes the batch rows
+// [(8 b + v) rpw, + rpw) (a frame's rows are consecutive), K = 64 / C pixels of
+// a row per step, all 9 taps per step.  Every operand is a buffer load: a
+// row off the frame is a buffer of no bytes and a column off the frame an
+// offset past the buffer, both of which read zero, so the loads carry no
+// branch.  Four register sets rotate: a step's ten loads are issued three
+// steps ahead of its nine matrix instructions.  The eight waves' sums are
+// added in order through LDS, one group of output rows at a time (each wave
+// only stores its accumulators, so they go to LDS without passing through
+// vector registers), and written in the weights' own order:
+// part[b][(co C + ci) 9 + tap], pb[b][co].
+template <int C>
+__global__ void __launch_bounds__(64 * WG_WAVES)
+k_wgrad(const float *__restrict__ dy, const float *__restrict__ x, int n, int h, int w, int d, int rpw,
         float *__restrict__ part, float *__restrict__ pb)
 {
-    constexpr int C = 16 * CB;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = lane & 15, kq = lane >> 4;
-    const int64_t rows = (int64_t)n * h;
-    const int64_t r0 = (int64_t)blockIdx.x * R, r1 = std::min<int64_t>(rows, r0 + R);
+    using M = WgMma<C>;
+    constexpr int PX = 64 / C;
+    constexpr int GR = C / M::NG;              // output rows per group (8 or 16)
+    constexpr int TSR = C * GR + 4;            // LDS floats per (wave, tap), padded against bank conflicts
+    __shared__ __align__(16) float red[WG_WAVES * 9 * TSR];
+    __shared__ float sb[WG_WAVES][C];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ch = lane % C, kp = lane / C;
+    const int rows = n * h;
+    const int gr0 = (blockIdx.x * WG_WAVES + wave) * rpw, gr1 = min(rows, gr0 + rpw);
+    const int steps = (w + PX - 1) / PX;
+    const uint32_t rowbytes = (uint32_t)w * C * 4;
+    typename M::acc_t acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = typename M::acc_t{};
+    float bsum = 0.f;
+    __amdgpu_buffer_rsrc_t rd, rx[3];
+    int gr = gr0, q = 0;
+    auto set_row = [&]() {
+        const int f = gr / h, y = gr - f * h;
+        const float *fx = x + (size_t)f * h * w * C;
+        rd = row_rsrc(dy + ((size_t)f * h + y) * w * C, rowbytes);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int ys = y + d * (u - 1);
+            const bool ok = (unsigned)ys < (unsigned)h;
+            rx[u] = row_rsrc(fx + (size_t)(ok ? ys : y) * w * C, ok ? rowbytes : 0u);
+        }
+    };
+    // loads of step (gr, q), then on to the step after it; past the last row dy
+    // becomes a buffer of no bytes, so a further step adds zeros
+    auto load_next = [&](float &a, float (&b)[9]) {
+        const int xx = q * PX + kp;
+        a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rd, xx < w ? (xx * C + ch) * 4 : BUF_OOB, 0, 0));
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int xs = xx + d * (v - 1);
+            const int o = (unsigned)xs < (unsigned)w ? (xs * C + ch) * 4 : BUF_OOB;
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                b[3 * u + v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx[u], o, 0, 0));
+        }
+        if (++q == steps) {
+            q = 0;
+            if (gr + 1 < gr1) {
+                ++gr;
+                set_row();
+            } else {
+                rd = row_rsrc(dy, 0u);
+            }
+        }
+    };
+    auto step = [&](float a, const float (&b)[9]) {
+        bsum += a;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[t] = M::mma(a, b[t], acc[t]);
+    };
+    if (gr0 < gr1) {
+        const int total = (gr1 - gr0) * steps;
+        set_row();
+        float a0, b0[9], a1, b1[9], a2, b2[9], a3, b3[9];
+        load_next(a0, b0);
+        load_next(a1, b1);
+        load_next(a2, b2);
+        for (int it = 0; it < total; it += 4) {   // a total not a multiple of 4 ends with steps of zeros
+            load_next(a3, b3);
+            step(a0, b0);
+            load_next(a0, b0);
+            step(a1, b1);
+            load_next(a1, b1);
+            step(a2, b2);
+            load_next(a2, b2);
+            step(a3, b3);
+        }
+    }
+    // the bias: the K pixel groups of channel ch
+#pragma unroll
+    for (int o = C; o < 64; o <<= 1) bsum += __shfl_xor(bsum, o);
+    if (lane < C) sb[wave][lane] = bsum;
+    // per group of GR output rows: every wave stores its accumulators, then the
+    // waves' values are added in order; LDS [wave][tap][ci][row in group]
     float *P = part + (size_t)blockIdx.x * 9 * C * C;
-    for (int pair = wave; pair < CB * CB; pair += 4) {
-        const int cb = pair / CB, cb2 = pair % CB;
-        v4f acc[9];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-        float bsum = 0.f;
-        for (int64_t gr = r0; gr < r1; ++gr) {
-            const int f = (int)(gr / h), y = (int)(gr - (int64_t)f * h);
-            const int64_t base = (int64_t)f * h * w;
-            for (int x0 = 0; x0 < w; x0 += 4) {
-                const int xx = x0 + kq;
-                const bool in = xx < w;
-                const float a = in ? dy[(base + (int64_t)y * w + xx) * C + 16 * cb + i] : 0.f;
-                bsum += a;
+    for (int g = 0; g < M::NG; ++g) {
 #pragma unroll
-                for (int t = 0; t < 9; ++t) {
-                    const int ys = y + d * (t / 3 - 1), xs = xx + d * (t % 3 - 1);
-                    const bool ok = in && (unsigned)ys < (unsigned)h && (unsigned)xs < (unsigned)w;
-                    const float b = ok ? x[(base + (int64_t)ys * w + xs) * C + 16 * cb2 + i] : 0.f;
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
-                }
-            }
+        for (int t = 0; t < 9; ++t) {
+            float4 *dst = reinterpret_cast<float4 *>(red + (wave * 9 + t) * TSR + ch * GR + M::row0(lane, g) - g * GR);
+            *dst = make_float4(acc[t][4 * g], acc[t][4 * g + 1], acc[t][4 * g + 2], acc[t][4 * g + 3]);
         }
-        // lane (j, kq) holds D[co 4 kq + r][ci j]
+        __syncthreads();
+        for (int j = threadIdx.x; j < GR * C * 9; j += 64 * WG_WAVES) {
+            const int t = j % 9, ci = (j / 9) % C, r = j / (9 * C);
+            float v = 0.f;
 #pragma unroll
-        for (int t = 0; t < 9; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = 16 * cb + 4 * kq + r, ci = 16 * cb2 + i;
-                P[((size_t)t * C + co) * C + ci] = acc[t][r];
-            }
-        if (cb2 == 0) {
-            // the bias: each lane summed dy of channel 16 cb + i over its pixels kq
-            bsum += __shfl_xor(bsum, 16);
-            bsum += __shfl_xor(bsum, 32);
-            if (kq == 0) pb[(size_t)blockIdx.x * C + 16 * cb + i] = bsum;
+            for (int k = 0; k < WG_WAVES; ++k) v += red[(k * 9 + t) * TSR + ci * GR + r];
+            P[(size_t)g * GR * C * 9 + j] = v;
         }
+        __syncthreads();
+    }
+    if (threadIdx.x < C) {
+        float v = 0.f;
+        for (int k = 0; k < WG_WAVES; ++k) v += sb[k][threadIdx.x];
+        pb[(size_t)blockIdx.x * C + threadIdx.x] = v;
     }
 }
 
-// out[j] = sum_b part[b][j] (b in order), j < m
-__global__ void __launch_bounds__(256)
-k_sum_partials(const float *__restrict__ part, int nb, int m, float *__restrict__ out)
+// Sums over nb partials of two arrays at once (ma values of pa and mb of pb
+// per partial), in two fixed-order stages: groups of G = ceil(nb / ng)
+// partials into mid[g][ma + mb], then the ng groups into oa and ob.  Each
+// thread adds its terms in order, eight loads in flight at a time.
+__device__ __forceinline__ float ordered_sum(const float *__restrict__ src, size_t stride, int cnt)
 {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= m) return;
     float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[(size_t)b * m + j];
-    out[j] = s;
+    int b = 0;
+    for (; b + 8 <= cnt; b += 8) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = src[(size_t)(b + k) * stride];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; b < cnt; ++b) s += src[(size_t)b * stride];
+    return s;
 }
 
-// first stage of the same sum for many partials: out[g][j] = sum over
-// b in [g G, g G + G) of part[b][j], G = ceil(nb / ng)
 __global__ void __launch_bounds__(256)
-k_sum_partials_grouped(const float *__restrict__ part, int nb, int m, int ng, float *__restrict__ out)
+k_sum_partials_grouped(const float *__restrict__ pa, int ma, const float *__restrict__ pbb, int mb, int nb, int ng,
+                       float *__restrict__ mid)
 {
+    const int m = ma + mb;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= (int64_t)ng * m) return;
     const int g = (int)(idx / m), j = (int)(idx - (int64_t)g * m);
     const int G = (nb + ng - 1) / ng;
     const int b0 = g * G, b1 = min(nb, b0 + G);
-    float s = 0.f;
-    for (int b = b0; b < b1; ++b) s += part[(size_t)b * m + j];
-    out[idx] = s;
+    const int stride = j < ma ? ma : mb;
+    const float *src = (j < ma ? pa + j : pbb + (j - ma)) + (size_t)b0 * stride;
+    mid[idx] = ordered_sum(src, stride, b1 - b0);
 }
 
-// dW[co][ci][tap] <- part sums laid out [tap][co][ci]
 __global__ void __launch_bounds__(256)
-k_wgrad_layout(const float *__restrict__ t_co_ci, int C, float *__restrict__ W)
+k_sum_partials(const float *__restrict__ mid, int ng, int ma, int mb, float *__restrict__ oa, float *__restrict__ ob)
 {
+    const int m = ma + mb;
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= 9 * C * C) return;
-    const int t = j % 9, rest = j / 9, ci = rest % C, co = rest / C;
-    W[j] = t_co_ci[((size_t)t * C + co) * C + ci];
+    if (j >= m) return;
+    const float s = ordered_sum(mid + j, m, ng);
+    if (j < ma) oa[j] = s;
+    else ob[j - ma] = s;
 }
 
-// stem gradient partials over pixels [b GCHUNK, b GCHUNK + GCHUNK):
-// part[b][c 9 + tap] = sum ds[p][c] x(p + off(tap)), part[b][9 C + c] = sum ds[p][c]
+// Stem gradient partials over pixels [b GCHUNK, b GCHUNK + GCHUNK): part[b][c 9 +
+// tap] = sum ds[p][c] x(p + off(tap)), part[b][9 C + c] = sum ds[p][c].  The
+// chunk's nine preprocessed inputs per pixel are staged in LDS (one pixel per
+// thread); thread (slot, c) sums channel c over every (256 / C)-th pixel, and
+// the slots are added in order.
+template <int C>
 __global__ void __launch_bounds__(256)
 k_stem_grad_part(const float *__restrict__ ds, const uint16_t *__restrict__ frames, int n, int h, int w,
-                 float offset, float scale, int C, float *__restrict__ part)
+                 float offset, float scale, float *__restrict__ part)
 {
-    const int64_t hw = (int64_t)h * w, P = (int64_t)n * hw;
-    const int64_t p0 = (int64_t)blockIdx.x * GCHUNK, p1 = min(P, p0 + GCHUNK);
-    float *O = part + (size_t)blockIdx.x * 10 * C;
-    for (int o = threadIdx.x; o < 10 * C; o += 256) {
-        const int c = o % C, t = o / C;             // consecutive threads: consecutive channels
-        float s = 0.f;
-        for (int64_t p = p0; p < p1; ++p) {
-            const float g = ds[p * C + c];
-            if (t == 9) {
-                s += g;
-                continue;
-            }
-            const int64_t f = p / hw, k = p - f * hw;
-            const int y = (int)(k / w) + t / 3 - 1, xx = (int)(k % w) + t % 3 - 1;
-            if ((unsigned)y < (unsigned)h && (unsigned)xx < (unsigned)w)
-                s += g * (((float)frames[(f * h + y) * w + xx] - offset) * scale);
+    constexpr int NS = 256 / C, NO = 10 * C;
+    __shared__ float sx[9][GCHUNK];
+    __shared__ float red[NS][NO];
+    const int hw = h * w, P = n * hw;
+    const int t = threadIdx.x, p0 = blockIdx.x * GCHUNK, np = min(GCHUNK, P - p0);
+    if (t < np) {
+        const int p = p0 + t, f = p / hw, k = p - f * hw, y = k / w, xx = k - y * w;
+        const uint16_t *F = frames + (size_t)f * hw;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int yy = y + tap / 3 - 1, xs = xx + tap % 3 - 1;
+            sx[tap][t] = (unsigned)yy < (unsigned)h && (unsigned)xs < (unsigned)w
+                             ? ((float)F[yy * w + xs] - offset) * scale : 0.f;
         }
-        if (t < 9) O[c * 9 + t] = s;
-        else O[9 * C + c] = s;
+    }
+    __syncthreads();
+    const int sl = t / C, c = t - sl * C;
+    float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int j = sl; j < np; j += NS) {
+        const float g = ds[(size_t)(p0 + j) * C + c];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) acc[tap] = fmaf(g, sx[tap][j], acc[tap]);
+        acc[9] += g;
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) red[sl][c * 9 + tap] = acc[tap];
+    red[sl][9 * C + c] = acc[9];
+    __syncthreads();
+    for (int o = t; o < NO; o += 256) {
+        float v = 0.f;
+        for (int k = 0; k < NS; ++k) v += red[k][o];
+        part[(size_t)blockIdx.x * NO + o] = v;
     }
 }
 
-// the sum over nb partials of m values in two fixed-order stages (groups, then
-// the groups' sums); mid holds 32 m floats
-void reduce_partials(const float *part, int nb, int m, float *mid, float *out, hipStream_t s)
+// the sums over nb partials of ma values (into oa) and mb values (into ob) in
+// two fixed-order stages; mid holds 32 (ma + mb) floats
+void reduce_partials(const float *pa, int ma, float *oa, const float *pbb, int mb, float *ob, int nb, float *mid,
+                     hipStream_t s)
 {
-    const int ng = std::min(32, nb);
-    hipLaunchKernelGGL(k_sum_partials_grouped, dim3((unsigned)(((int64_t)ng * m + 255) / 256)), dim3(256), 0, s, part,
-                       nb, m, ng, mid);
-    hipLaunchKernelGGL(k_sum_partials, dim3((m + 255) / 256), dim3(256), 0, s, mid, ng, m, out);
+    const int ng = std::min(32, nb), m = ma + mb;
+    hipLaunchKernelGGL(k_sum_partials_grouped, dim3((unsigned)(((int64_t)ng * m + 255) / 256)), dim3(256), 0, s, pa,
+                       ma, pbb, mb, nb, ng, mid);
+    hipLaunchKernelGGL(k_sum_partials, dim3((m + 255) / 256), dim3(256), 0, s, mid, ng, ma, mb, oa, ob);
 }
 
 }  // namespace
 
-hipError_t launch_pack_conv(const float *W, int cout, int cin, int flip, float *dst, hipStream_t s)
+hipError_t launch_pack_convs(const float *W0, int64_t src_stride, int count, int C, float *dst, hipStream_t s)
 {
-    const int n = cout * cin * 9;
-    hipLaunchKernelGGL(k_pack_conv, dim3((n + 255) / 256), dim3(256), 0, s, W, cout, cin, flip, dst);
+    const int64_t n = (int64_t)count * 2 * C * C * 9;
+    hipLaunchKernelGGL(k_pack_conv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W0, src_stride, count, C, dst);
     return hipGetLastError();
+}
+
+int64_t train_lse_floats(int h, int w, int ntruth)
+{
+    const int64_t e = std::max(ntruth, 1);
+    return e * (1 + EM_STRIDE + 2 * (int64_t)lse_chunks((int64_t)h * w));
 }
 
 hipError_t launch_train_loss(int C, const float *act, const float *hw, const float *hb, int n, int h, int w,
@@ -536,15 +801,24 @@ hipError_t launch_train_loss(int C, const float *act, const float *hw, const flo
     if (ntruth > 0)
         hipLaunchKernelGGL(k_occupancy, dim3((ntruth + 255) / 256), dim3(256), 0, s, tr, toff, n, ntruth, h, w, occ);
     hipLaunchKernelGGL(k_pix_terms, dim3(gp), dim3(256), 0, s, maps, n, h, w, term);
-    // the stats' partials sit in lse's place until the per-frame sums are taken
+    // the stats' partials sit past the pixel terms until the per-frame sums are taken
     float *partial = term + 9 * npx;
     hipLaunchKernelGGL(k_frame_stats, dim3(n * STAT_CHUNKS), dim3(256), 0, s, maps, h, w, occ, partial);
     hipLaunchKernelGGL(k_frame_stats_sum, dim3((n + 255) / 256), dim3(256), 0, s, partial, n, 1e-4f, stats);
-    if (ntruth > 0)
-        hipLaunchKernelGGL(k_loc_lse, dim3(ntruth), dim3(256), 0, s, term, n, h, w, tr, toff, stats, zs, ps, lse);
-    hipLaunchKernelGGL(k_loss_grad, dim3(gp), dim3(256), 0, s, maps, term, occ, n, h, w, tr, toff, stats, lse, zs, ps,
-                       gm);
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, n, h, w, toff, stats, lse, loss);
+    // lse: [ntruth] log-sum-exps, then [ntruth][EM_STRIDE] emitter constants,
+    // then [ntruth][chunks][2] partials
+    const float izs = 1.f / zs, ips = 1.f / ps;
+    float *em = lse + std::max(ntruth, 1);
+    float *lpart = em + (size_t)std::max(ntruth, 1) * EM_STRIDE;
+    if (ntruth > 0) {
+        hipLaunchKernelGGL(k_lse_part, dim3((unsigned)(n * lse_chunks(hwpx))), dim3(256), 0, s, term, n, h, w, tr, toff,
+                           izs, ips, lpart);
+        hipLaunchKernelGGL(k_lse_fin, dim3((ntruth + 3) / 4), dim3(256), 0, s, n, h, w, tr, toff, ntruth, stats,
+                           izs, ips, lpart, lse, em);
+    }
+    hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)(n * ((hwpx + 255) / 256))), dim3(256), 0, s, maps, term, occ, n,
+                       h, w, toff, stats, em, gm);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, n, h, w, toff, ntruth, stats, lse, loss);
     return hipGetLastError();
 }
 
@@ -554,24 +828,26 @@ hipError_t launch_head_backward(int C, const float *gm, const float *act, const 
                                 float *gwb, float *part, float *mid, float *du, hipStream_t s)
 {
     const int64_t hwpx = (int64_t)h * w, npx = (int64_t)n * hwpx;
-    const unsigned gp = (unsigned)((npx + 255) / 256);
     const int nb = grad_chunks(npx);
     if (C == 32) {
-        hipLaunchKernelGGL(k_head_grad_part<32>, dim3(nb), dim3(256), 0, s, gm, act, npx, hwpx, part);
-        hipLaunchKernelGGL(k_head_back<32>, dim3(gp), dim3(256), 0, s, gm, hw, act, npx, hwpx, du);
+        hipLaunchKernelGGL(k_head_grad_part<32>, dim3(nb), dim3(256), 0, s, gm, act, (int)npx, (int)hwpx, part);
+        hipLaunchKernelGGL(k_head_back<32>, dim3((unsigned)((npx * 8 + 255) / 256)), dim3(256), 0, s, gm, hw, act,
+                           (int)npx, (int)hwpx, du);
     } else if (C == 16) {
-        hipLaunchKernelGGL(k_head_grad_part<16>, dim3(nb), dim3(256), 0, s, gm, act, npx, hwpx, part);
-        hipLaunchKernelGGL(k_head_back<16>, dim3(gp), dim3(256), 0, s, gm, hw, act, npx, hwpx, du);
+        hipLaunchKernelGGL(k_head_grad_part<16>, dim3(nb), dim3(256), 0, s, gm, act, (int)npx, (int)hwpx, part);
+        hipLaunchKernelGGL(k_head_back<16>, dim3((unsigned)((npx * 4 + 255) / 256)), dim3(256), 0, s, gm, hw, act,
+                           (int)npx, (int)hwpx, du);
     } else {
         return hipErrorInvalidValue;
     }
-    reduce_partials(part, nb, 10 * C + 10, mid, gwb, s);   // head.w then head.b, as in the blob
+    reduce_partials(part, 10 * C + 10, gwb, nullptr, 0, nullptr, nb, mid, s);   // head.w then head.b, as in the blob
     return hipGetLastError();
 }
 
-// about 1024 workgroups: four waves each, so enough waves per SIMD to hide the
-// operand loads' latency
-int wgrad_rows_per_block(int n, int h) { return std::max(1, (n * h + 1023) / 1024); }
+// rows per workgroup: WG_WAVES waves of rpw rows each, rpw the smallest that
+// keeps the batch within 2048 waves (two per SIMD with the 9 x 16 accumulator
+// registers of C = 32)
+int wgrad_rows_per_block(int n, int h) { return WG_WAVES * std::max(1, (n * h + 2047) / 2048); }
 
 hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, int w, int d, float *part, float *pb,
                         float *tmp, float *gW, float *gb, hipStream_t s)
@@ -579,16 +855,14 @@ hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, in
     const int R = wgrad_rows_per_block(n, h);
     const int nblk = (n * h + R - 1) / R;
     if (C == 32)
-        hipLaunchKernelGGL(k_wgrad<2>, dim3(nblk), dim3(256), 0, s, dy, x, n, h, w, d, R, part, pb);
+        hipLaunchKernelGGL(k_wgrad<32>, dim3(nblk), dim3(64 * WG_WAVES), 0, s, dy, x, n, h, w, d, R / WG_WAVES, part,
+                           pb);
     else if (C == 16)
-        hipLaunchKernelGGL(k_wgrad<1>, dim3(nblk), dim3(256), 0, s, dy, x, n, h, w, d, R, part, pb);
+        hipLaunchKernelGGL(k_wgrad<16>, dim3(nblk), dim3(64 * WG_WAVES), 0, s, dy, x, n, h, w, d, R / WG_WAVES, part,
+                           pb);
     else
         return hipErrorInvalidValue;
-    const int m = 9 * C * C;
-    float *mid = tmp + m;
-    reduce_partials(part, nblk, m, mid, tmp, s);
-    hipLaunchKernelGGL(k_wgrad_layout, dim3((m + 255) / 256), dim3(256), 0, s, tmp, C, gW);
-    reduce_partials(pb, nblk, C, mid, gb, s);
+    reduce_partials(part, 9 * C * C, gW, pb, C, gb, nblk, tmp, s);
     return hipGetLastError();
 }
 
@@ -596,8 +870,13 @@ hipError_t launch_stem_grad(const float *ds, const uint16_t *frames, int n, int 
                             int C, float *gwb, float *part, float *mid, hipStream_t s)
 {
     const int nb = grad_chunks((int64_t)n * h * w);
-    hipLaunchKernelGGL(k_stem_grad_part, dim3(nb), dim3(256), 0, s, ds, frames, n, h, w, offset, scale, C, part);
-    reduce_partials(part, nb, 10 * C, mid, gwb, s);           // stem.w then stem.b, as in the blob
+    if (C == 32)
+        hipLaunchKernelGGL(k_stem_grad_part<32>, dim3(nb), dim3(256), 0, s, ds, frames, n, h, w, offset, scale, part);
+    else if (C == 16)
+        hipLaunchKernelGGL(k_stem_grad_part<16>, dim3(nb), dim3(256), 0, s, ds, frames, n, h, w, offset, scale, part);
+    else
+        return hipErrorInvalidValue;
+    reduce_partials(part, 10 * C, gwb, nullptr, 0, nullptr, nb, mid, s);   // stem.w then stem.b, as in the blob
     return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@ against the FP64 training oracle, through the C ABI.
 * dl_train_grad: the three loss terms and the gradient of every weight tensor
   of the residual network with the 10-output head (C = 32 and 16), within
   1e-4 relative (L2 per tensor, FP32 against FP64), on batches with a frame
-  without emitters; the same bits on a second call;
+  without emitters, ragged widths and tall frames that give the weight
+  gradient's waves several rows; the same bits on a second call;
 * dl_train_step: one step equals the oracle's Adam step on the oracle's
   gradient; forty steps lower the loss; the inference path then runs the
   trained weights (its maps equal the oracle's on dl_get_params' weights);
@@ -64,12 +65,19 @@ def gpu_grads(net, spec, frames, truths):
     return loss.cpu().numpy(), S.unflat_weights(spec, grad.cpu().numpy())
 
 
+# the weight-gradient kernel gives each wave ceil(n h / 2048) rows: the two tall
+# single frames run two rows per wave and end on a wave with one row of an odd
+# number of steps (7 pixel pairs for C = 32, 3 pixel quads for C = 16); the
+# 2201 x 13 frame holds more than 256 true emitters (two emitter groups in the
+# log-sum-exp) and its log-sum-exp chunks span two 256-pixel groups
 @pytest.mark.parametrize("spec,n,h,w", [(S.NetSpec("t32", 32, (1, 2), head_outputs=10), 3, 40, 52),
                                         (S.NetSpec("t16", 16, (1, 3, 2), head_outputs=10), 2, 33, 70),
-                                        (S.NET_AU, 2, 64, 64)])
+                                        (S.NET_AU, 2, 64, 64),
+                                        (S.NetSpec("t32", 32, (1, 2), head_outputs=10), 1, 2201, 13),
+                                        (S.NetSpec("t16", 16, (2, 1), head_outputs=10), 1, 2059, 9)])
 def test_gradients_match_the_oracle(spec, n, h, w):
     wts, net = net_and_weights(spec, 11)
-    frames, truths = batch(n, h, w, 21)
+    frames, truths = batch(n, h, w, 21, empty_last=n > 1)
     L, G = T.batch_grads(frames, truths, spec, wts)
     loss, g = gpu_grads(net, spec, frames, truths)
     print(spec.name, L, loss)
