@@ -23,7 +23,8 @@ t_e = (x, y, z / z_scale, photons / ph_scale) of emitter e.  Gradients are
 taken by hand, layer by layer, in the order of the definitions (the network's
 backward pass is plain convolutions: the transposed 3x3 convolution is the
 forward one with flipped, transposed weights; weight gradients are sums of
-products over pixels).
+products over pixels), for the residual network and for the
+dense-connection network (its backward pass through the concatenation).
 """
 from __future__ import annotations
 
@@ -156,12 +157,70 @@ def frame_grads(frame: np.ndarray, truth, spec, wts: Dict[str, np.ndarray], gain
     return loss, G, maps
 
 
+def dense_frame_grads(frame: np.ndarray, truth, spec, wts: Dict[str, np.ndarray], gain=0.5, offset=100.0):
+    """Loss of one frame and the gradient of every weight tensor of the
+    dense-connection network (Sec. 3.2.1: each layer of a block reads the
+    concatenation of the block input and the earlier layers' outputs; a 1x1
+    transition over the whole concatenation gives the block's output).
+
+    Backward through a block: the transition's pre-activation gradient gives
+    its weight gradient against the concatenation and the concatenation's
+    gradient (the transposed 1x1 map); then, from the last layer to the first,
+    a layer's output channels of that gradient, masked where the layer's ReLU
+    was off, give the layer's weight gradient against its input (the
+    concatenation so far) and add the transposed 3x3 convolution of it to the
+    gradient of that input.  The first C channels are then the gradient at the
+    block's input."""
+    if spec.unet:
+        raise ValueError("the training oracle covers the dense network without the U-Net stage")
+    W = {k: np.asarray(v, np.float64) for k, v in wts.items()}
+    C, Gr, L = spec.C, spec.growth, spec.layers
+    x = preprocess(frame[None], gain, offset, spec.in_scale)[0][None]
+    a0 = _relu(conv3x3(x, W["stem.w"], W["stem.b"], 1))
+    a = a0
+    blocks = []
+    for k, d in enumerate(spec.dilations):
+        cat = a
+        for i in range(L):
+            new = _relu(conv3x3(cat, W[f"blk{k}.l{i}.w"], W[f"blk{k}.l{i}.b"], d))
+            cat = np.concatenate([cat, new], axis=0)
+        t = _relu(np.tensordot(W[f"blk{k}.t.w"], cat, axes=(1, 0)) + W[f"blk{k}.t.b"][:, None, None])
+        blocks.append((cat, t))
+        a = t
+    maps = np.tensordot(W["head.w"], a, axes=(1, 0)) + W["head.b"][:, None, None]
+    loss, gm = frame_loss(maps, truth, spec)
+    G = {}
+    G["head.w"] = np.tensordot(gm, a, axes=([1, 2], [1, 2]))
+    G["head.b"] = gm.sum(axis=(1, 2))
+    da = np.tensordot(W["head.w"], gm, axes=(0, 0))
+    for k in reversed(range(len(spec.dilations))):
+        d = spec.dilations[k]
+        cat, t = blocks[k]
+        gt = da * (t > 0)
+        G[f"blk{k}.t.w"] = np.tensordot(gt, cat, axes=([1, 2], [1, 2]))
+        G[f"blk{k}.t.b"] = gt.sum(axis=(1, 2))
+        gc = np.tensordot(W[f"blk{k}.t.w"], gt, axes=(0, 0))
+        for i in reversed(range(L)):
+            lo = C + i * Gr
+            gl = gc[lo:lo + Gr] * (cat[lo:lo + Gr] > 0)
+            G[f"blk{k}.l{i}.w"] = _wgrad(gl, cat[:lo], d)
+            G[f"blk{k}.l{i}.b"] = gl.sum(axis=(1, 2))
+            gc[:lo] += conv3x3(gl, _flip_t(W[f"blk{k}.l{i}.w"]), None, d)
+        da = gc[:C]
+    ds0 = da * (a0 > 0)
+    G["stem.w"] = _wgrad(ds0, x, 1)
+    G["stem.b"] = ds0.sum(axis=(1, 2))
+    return loss, G, maps
+
+
 def batch_grads(frames: np.ndarray, truths: List, spec, wts, gain=0.5, offset=100.0):
-    """Mean loss over the frames and the gradients of the mean."""
+    """Mean loss over the frames and the gradients of the mean (the residual or
+    the dense-connection network, by the spec's type)."""
     n = len(frames)
     tot, G = None, None
+    fg = dense_frame_grads if hasattr(spec, "growth") else frame_grads
     for f in range(n):
-        L, g, _ = frame_grads(frames[f], truths[f], spec, wts, gain, offset)
+        L, g, _ = fg(frames[f], truths[f], spec, wts, gain, offset)
         tot = dict(L) if tot is None else {k: tot[k] + L[k] for k in tot}
         G = g if G is None else {k: G[k] + g[k] for k in G}
     return {k: v / n for k, v in tot.items()}, {k: v / n for k, v in G.items()}

@@ -196,6 +196,14 @@ PY_MUTANTS = [
      "W[:, :, ::-1, ::-1].transpose(1, 0, 2, 3)",
      "W.transpose(1, 0, 2, 3)",
      [(TR.test_transposed_conv_is_the_adjoint, ())]),
+    ("dense layer gradient without its ReLU mask", "train.dense_frame_grads",
+     "gl = gc[lo:lo + Gr] * (cat[lo:lo + Gr] > 0)",
+     "gl = gc[lo:lo + Gr]",
+     [(TR.test_dense_loss_and_gradients_match_torch_autograd, ())]),
+    ("dense layer's input gradient overwritten instead of added", "train.dense_frame_grads",
+     "gc[:lo] += conv3x3(gl, _flip_t(W[f\"blk{k}.l{i}.w\"]), None, d)",
+     "gc[:lo] = conv3x3(gl, _flip_t(W[f\"blk{k}.l{i}.w\"]), None, d)",
+     [(TR.test_dense_loss_and_gradients_match_torch_autograd, ())]),
 ]
 
 

@@ -11,7 +11,11 @@ with the 10-output head.
   when one pixel holds all the probability (a Gaussian's negative
   log-likelihood); the cross-entropy term on a known occupancy;
 * the transposed convolution the backward pass uses against the adjoint
-  identity <conv(x), y> = <x, conv_T(y)>.
+  identity <conv(x), y> = <x, conv_T(y)>;
+* the dense-connection network (backward through the concatenation and the
+  1x1 transition): loss and gradients against torch autograd of a composition
+  from torch.cat and conv2d, finite differences, and its forward maps against
+  the inference oracle.
 """
 import math
 
@@ -78,6 +82,104 @@ def torch_loss(frames, truths, spec, wts, gain=0.5, offset=100.0):
     total = total / len(frames)
     total.backward()
     return float(total.detach()), {k: v.grad.numpy() for k, v in P.items()}
+
+
+DSPEC = S.DenseSpec("td", 16, (1, 2), layers=2, growth=16, head_outputs=10)
+
+
+def dense_weights(seed=3):
+    w = S.he_normal_weights(DSPEC, seed, bias_std=0.05)
+    w["head.w"] = (w["head.w"] * 0.3).astype(np.float32)
+    return w
+
+
+def torch_dense_loss(frames, truths, spec, wts, gain=0.5, offset=100.0):
+    """The dense-connection network and the same loss, composed from torch
+    ops (cat over channels, conv2d with dilation, a 1x1 conv2d) and
+    differentiated by autograd."""
+    P = {k: torch.tensor(np.asarray(v, np.float64), requires_grad=True) for k, v in wts.items()}
+    total = 0.0
+    for f in range(len(frames)):
+        x = (torch.from_numpy(frames[f].astype(np.float64)) - offset) * gain * spec.in_scale
+        a = F.relu(F.conv2d(x[None, None], P["stem.w"], P["stem.b"], padding=1))
+        for k, d in enumerate(spec.dilations):
+            feats = [a]
+            for i in range(spec.layers):
+                inp = torch.cat(feats, dim=1)
+                feats.append(F.relu(F.conv2d(inp, P[f"blk{k}.l{i}.w"], P[f"blk{k}.l{i}.b"], padding=d, dilation=d)))
+            a = F.relu(F.conv2d(torch.cat(feats, dim=1), P[f"blk{k}.t.w"][:, :, None, None], P[f"blk{k}.t.b"]))
+        m = F.conv2d(a, P["head.w"][:, :, None, None], P["head.b"])[0]
+        total = total + _torch_frame_loss(m, truths[f], spec)
+    total = total / len(frames)
+    total.backward()
+    return float(total.detach()), {k: v.grad.numpy() for k, v in P.items()}
+
+
+def _torch_frame_loss(m, truth, spec):
+    h, w = m.shape[1:]
+    l = m[0]
+    p = torch.sigmoid(l)
+    y = torch.zeros(h, w, dtype=torch.float64)
+    for t in truth:
+        y[int(math.floor(t["y"])), int(math.floor(t["x"]))] = 1.0
+    L = (F.softplus(l) - y * l).mean()
+    E = len(truth)
+    mu = p.sum()
+    v = (p * (1 - p)).sum() + T.VAR_EPS
+    L = L + 0.5 * torch.log(2 * math.pi * v) + (E - mu) ** 2 / (2 * v)
+    rows, cols = torch.meshgrid(torch.arange(h, dtype=torch.float64), torch.arange(w, dtype=torch.float64),
+                                indexing="ij")
+    mean = [cols + 0.5 + m[1], rows + 0.5 + m[2], m[3], m[4]]
+    sd = [F.softplus(m[5 + d]) for d in range(4)]
+    for t in truth:
+        tv = [t["x"], t["y"], t["z_nm"] / spec.z_scale, t["photons"] / spec.ph_scale]
+        q = F.logsigmoid(l) - torch.log(mu)
+        for d in range(4):
+            q = q + torch.distributions.Normal(mean[d], sd[d]).log_prob(torch.tensor(float(tv[d]), dtype=torch.float64))
+        L = L - torch.logsumexp(q.reshape(-1), 0)
+    return L
+
+
+def test_dense_loss_and_gradients_match_torch_autograd():
+    frames, truths = data()
+    wts = dense_weights()
+    assert len(truths[0]) >= 2
+    L, G = T.batch_grads(frames, truths, DSPEC, wts)
+    Lt, Gt = torch_dense_loss(frames, truths, DSPEC, wts)
+    assert set(G) == set(Gt)
+    assert abs(L["total"] - Lt) <= 1e-10 * abs(Lt)
+    for k in G:
+        ref = Gt[k]
+        err = np.linalg.norm(G[k] - ref) / (np.linalg.norm(ref) + 1e-300)
+        assert err <= 1e-9, (k, err)
+
+
+def test_dense_finite_differences():
+    frames, truths = data(n=1, empty_last=False)
+    wts = dense_weights(4)
+    _, G = T.batch_grads(frames, truths, DSPEC, wts)
+    r = np.random.default_rng(8)
+    for name in ["stem.w", "blk0.l0.w", "blk0.l1.w", "blk1.l1.b", "blk0.t.w", "blk1.t.b", "head.w"]:
+        for _ in range(2):
+            idx = tuple(int(r.integers(0, s)) for s in wts[name].shape)
+            h = 1e-5
+            wp = {k: np.asarray(v, np.float64).copy() for k, v in wts.items()}
+            wm = {k: np.asarray(v, np.float64).copy() for k, v in wts.items()}
+            wp[name][idx] += h
+            wm[name][idx] -= h
+            Lp, _ = T.batch_grads(frames, truths, DSPEC, wp)
+            Lm, _ = T.batch_grads(frames, truths, DSPEC, wm)
+            fd = (Lp["total"] - Lm["total"]) / (2 * h)
+            assert abs(fd - G[name][idx]) <= 1e-5 * (abs(fd) + 1e-3), (name, idx, fd, G[name][idx])
+
+
+def test_dense_forward_matches_the_inference_oracle():
+    """The training oracle's maps are the inference oracle's (its C code)."""
+    frames, _ = data(n=1, empty_last=False)
+    wts = dense_weights(5)
+    _, _, maps = T.dense_frame_grads(frames[0], np.zeros(0, S.TRUTH_DTYPE), DSPEC, wts)
+    ref = oracle.net_maps(frames[0], DSPEC, wts)
+    assert np.max(np.abs(maps - ref)) <= 1e-12 * (1 + np.max(np.abs(ref)))
 
 
 def test_loss_and_gradients_match_torch_autograd():
