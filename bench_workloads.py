@@ -323,15 +323,17 @@ def pipeline(args, S):
 
 
 def train(args, S):
-    """Training steps of the 10-output residual net (net AU: C = 32, d = 1, 2,
-    4) on 16 frames of 128 x 128 with their true emitters: forward with kept
-    activations, the loss, backward and Adam, all on the GPU."""
+    """Training steps on 16 frames of 128 x 128 with their true emitters: the
+    10-output residual net (net AU: C = 32, d = 1, 2, 4), or with --net D the
+    dense-connection network with the 10-output head (net DT); forward with
+    kept activations, the loss, backward and Adam, all on the GPU."""
     import torch
     import paper_2410_02314_amd as dl
     n, side = 16, 128
     frames, truths = S.render_frames(n, side, side, "tiny", 1006, with_truth=True)
     truths = [S.truth_array(t, side, side) for t in truths]
-    spec, w = S.make_net("AU", 1)
+    dense = args.net == "D"
+    spec, w = S.make_net("DT", 3) if dense else S.make_net("AU", 1)
     net = dl.Net(S.serialize_weights(spec, w))
     dev = torch.device("cuda:0")
     d = torch.from_numpy(frames).to(dev)
@@ -349,13 +351,22 @@ def train(args, S):
     last = float(loss.cpu()[0])
     px = n * side * side
     C, nb = spec.C, len(spec.dilations)
-    # conv FLOP of one step: per block two forward convolutions, two transposed
-    # ones and two weight gradients, each 2 9 C^2 per pixel
-    flop = 2.0 * 9 * C * C * px * 6 * nb
+    if dense:
+        # per block: each layer's 3x3 conv and the 1x1 transition, each run
+        # forward, transposed (input gradient) and as a weight gradient
+        G, L = spec.growth, spec.layers
+        per_px = sum(2 * 9 * G * (C + i * G) for i in range(L)) + 2 * C * (C + L * G)
+        flop = 3.0 * per_px * px * nb
+        name = "net DT (dense blocks at d=2,4,8,16, C=32, 4 layers of growth 16, 10-output head)"
+    else:
+        # per block two forward convolutions, two transposed ones and two
+        # weight gradients, each 2 9 C^2 per pixel
+        flop = 2.0 * 9 * C * C * px * 6 * nb
+        name = "net AU (C=32, d=1,2,4, 10-output head)"
     tflops = flop / (ms * 1e-3) / 1e12
     _line(args, px / (ms * 1e-3) / 1e6, ms,
-          {"workload": f"training steps, {n} x {side}x{side} frames with their true emitters, net AU "
-                       f"(C=32, d=1,2,4, 10-output head), FP32, Adam lr 1e-3",
+          {"workload": f"training steps, {n} x {side}x{side} frames with their true emitters, {name}, FP32, "
+                       f"Adam lr 1e-3",
            "precision": "fp32", "frames": n, "height": side, "width": side},
           {"frames_per_s": round(n / (ms * 1e-3), 1), "emitters_per_batch": int(off[-1]),
            "loss_first_step": round(first, 4), "loss_after": round(last, 4), "steps_timed": args.steps,

@@ -151,6 +151,9 @@ struct dl_net {
     // weights, and the batch buffers (grow-only); t_dirty: the trained
     // weights have not been handed to the inference path yet
     float *t_params = nullptr, *t_grad = nullptr, *t_m = nullptr, *t_v = nullptr, *t_pack = nullptr;
+    PackJob *t_jobs = nullptr;      // dense networks: the weight packs' job table (device)
+    int t_njobs = 0;
+    int64_t t_jobs_total = 0;
     char *t_ws = nullptr;
     size_t t_ws_bytes = 0;
     int t_step = 0;
@@ -571,6 +574,11 @@ int pack_dense(dl_net *net)
     net->dense_head_w = (host.size() + 63) / 64 * 64;
     host.resize(net->dense_head_w + head16.size());
     pack_dense_weights(16, C, 1, head16.data(), host.data() + net->dense_head_w);
+    if (net->d_dense) {             // a repack (trained weights): kernels still queued may read the old buffer
+        HIPCHK(net, hipDeviceSynchronize());
+        HIPCHK(net, hipFree(net->d_dense));
+        net->d_dense = nullptr;
+    }
     HIPCHK(net, hipMalloc(&net->d_dense, host.size() * sizeof(float)));
     HIPCHK(net, hipMemcpy(net->d_dense, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
     net->packed_precision = DL_FP32;
@@ -1134,13 +1142,87 @@ ParamOffsets param_offsets(const dl_net *net)
     return o;
 }
 
+// float offsets of a dense network's tensors in blob order: stem, per block
+// the L layers' weights and biases then the transition's, the head
+struct DenseOffsets {
+    size_t stem_w = 0, stem_b = 0, head_w = 0, head_b = 0;
+    std::vector<size_t> lw, lb, tw, tb;          // lw/lb [block L + layer]
+};
+DenseOffsets dense_offsets(const dl_net *net)
+{
+    const size_t C = net->C, L = net->dL, G = net->dG, CT = C + L * G;
+    DenseOffsets o;
+    size_t k = 0;
+    o.stem_w = k; k += C * 9;
+    o.stem_b = k; k += C;
+    for (int b = 0; b < net->nb; ++b) {
+        for (size_t i = 0; i < L; ++i) {
+            o.lw.push_back(k); k += G * (C + i * G) * 9;
+            o.lb.push_back(k); k += G;
+        }
+        o.tw.push_back(k); k += C * CT;
+        o.tb.push_back(k); k += C;
+    }
+    o.head_w = k; k += (size_t)net->nh * C;
+    o.head_b = k;
+    return o;
+}
+
+// The dense network's weight packs for training, as pack jobs in a fixed
+// order: per block, each layer's forward pack (16 rows over its C + i G
+// inputs, 9 taps), the transition's (C rows over CT inputs, 1 tap) for the
+// fused last layer, and each layer's transposed convolution (G inputs ->
+// C + i G outputs) in slices of at most 32 output rows, one conv launch each.
+struct DensePackPlan {
+    std::vector<PackJob> jobs;
+    std::vector<int> fw, tw;                      // job index: fw [block L + layer], tw [block]
+    std::vector<std::vector<int>> tr;             // [block L + layer]: the slices' job indices
+    int64_t total = 0;
+};
+DensePackPlan dense_pack_plan(const dl_net *net)
+{
+    const int C = net->C, L = net->dL, G = net->dG, CT = C + L * G;
+    const DenseOffsets o = dense_offsets(net);
+    DensePackPlan pl;
+    auto add = [&](size_t src, int cout, int cin, int taps, int flip, int row0, int nrows) {
+        PackJob j{};
+        j.src = (int64_t)src;
+        j.cout = cout;
+        j.cin = cin;
+        j.taps = taps;
+        j.flip = flip;
+        j.row0 = row0;
+        j.nrows = nrows;
+        j.start = pl.total;
+        j.dst = (pl.total + 63) / 64 * 64;       // 256-byte aligned packs
+        const int64_t n = (int64_t)nrows * (flip ? cout : cin) * taps;
+        j.start = j.dst;
+        pl.total = j.dst + n;
+        pl.jobs.push_back(j);
+        return (int)pl.jobs.size() - 1;
+    };
+    for (int b = 0; b < net->nb; ++b) {
+        for (int i = 0; i < L; ++i) pl.fw.push_back(add(o.lw[(size_t)b * L + i], G, C + i * G, 9, 0, 0, G));
+        pl.tw.push_back(add(o.tw[b], C, CT, 1, 0, 0, C));
+        for (int i = 0; i < L; ++i) {
+            std::vector<int> sl;
+            for (int r = 0; r < C + i * G; r += 32)
+                sl.push_back(add(o.lw[(size_t)b * L + i], G, C + i * G, 9, 1, r, std::min(32, C + i * G - r)));
+            pl.tr.push_back(sl);
+        }
+    }
+    return pl;
+}
+
 int train_check(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
                 const int32_t *d_off, int ntruth, float *d_loss)
 {
     int rc = check_uniform(net, d_frames, n, h, w);
     if (rc) return rc;
-    if (net->dL || net->nh != 10 || !(net->C == 16 || net->C == 32))
-        return fail(net, DL_ERR_UNSUPPORTED, "training runs the residual network with the 10-output head and C = 16 or 32");
+    if (net->nh != 10 || !(net->C == 16 || net->C == 32) || (net->dL && (net->dG != 16 || net->unet)))
+        return fail(net, DL_ERR_UNSUPPORTED,
+                    "training runs the residual or the dense network (growth 16, no U-Net) with the 10-output head "
+                    "and C = 16 or 32");
     if (net->d_cam) return fail(net, DL_ERR_UNSUPPORTED, "training uses the scalar gain and offset (clear the camera maps)");
     if (!d_off || !d_loss || (ntruth > 0 && !d_truth) || ntruth < 0)
         return fail(net, DL_ERR_INVALID_ARG, "d_truth_off and d_loss must be given, d_truth when ntruth > 0");
@@ -1158,11 +1240,171 @@ int train_init(dl_net *net)
     HIPCHK(net, hipMalloc(&net->t_grad, np * 4));
     HIPCHK(net, hipMalloc(&net->t_m, np * 4));
     HIPCHK(net, hipMalloc(&net->t_v, np * 4));
-    HIPCHK(net, hipMalloc(&net->t_pack, (size_t)net->nb * 4 * C * C * 9 * 4));
+    if (net->dL) {
+        const DensePackPlan pl = dense_pack_plan(net);
+        HIPCHK(net, hipMalloc(&net->t_pack, (size_t)pl.total * 4));
+        HIPCHK(net, hipMalloc(&net->t_jobs, pl.jobs.size() * sizeof(PackJob)));
+        HIPCHK(net, hipMemcpy(net->t_jobs, pl.jobs.data(), pl.jobs.size() * sizeof(PackJob), hipMemcpyHostToDevice));
+        net->t_njobs = (int)pl.jobs.size();
+        net->t_jobs_total = pl.total;
+    } else {
+        HIPCHK(net, hipMalloc(&net->t_pack, (size_t)net->nb * 4 * C * C * 9 * 4));
+    }
     HIPCHK(net, hipMemcpy(net->t_params, net->params.data(), np * 4, hipMemcpyHostToDevice));
     HIPCHK(net, hipMemset(net->t_m, 0, np * 4));
     HIPCHK(net, hipMemset(net->t_v, 0, np * 4));
     net->t_step = 0;
+    return DL_OK;
+}
+
+// frame descriptors and conv geometry of a uniform training batch (frame f's
+// points from f h w, its tiles per block from f times a frame's)
+int train_geometry(dl_net *net, const uint16_t *d_frames, int n, int h, int w, hipStream_t s, Geometry &g,
+                   FrameDesc **d_fd)
+{
+    std::vector<FrameDesc> fd(n);
+    g = Geometry{};
+    g.nf = n;
+    g.tr = dense_tile_rows();
+    g.tc = dense_tile_cols();
+    for (int f = 0; f < n; ++f) {
+        FrameDesc &d = fd[f];
+        std::memset(&d, 0, sizeof d);
+        d.data = d_frames + (size_t)f * h * w;
+        d.stride = w;
+        d.h = h;
+        d.w = w;
+        d.px_off = d.act_off = (int64_t)f * h * w;
+        d.row_start = (int64_t)f * h;
+        for (int b = 0; b < net->nb; ++b) d.tile_start[b] = (int64_t)f * conv_tiles(h, w, net->dil[b], g.tr, g.tc);
+    }
+    for (int b = 0; b < net->nb; ++b) g.tiles[b] = (int64_t)n * conv_tiles(h, w, net->dil[b], g.tr, g.tc);
+    g.total_rows = (int64_t)n * h;
+    g.total_px = g.total_act = (int64_t)n * h * w;
+    return upload_desc(net, fd, s, d_fd);
+}
+
+// The dense network: forward with every concatenation kept (block b's in A[b],
+// CT = C + L G channels per point; the last transition's output in tl), the
+// loss, backward.  Backward through block b: the transition's
+// pre-activation gradient gtp (the head's, or the next block's input gradient
+// masked where the transition's ReLU was off) gives the transition's weight
+// gradient and, through the transposed 1x1 map, the concatenation's gradient
+// ga; then from the last layer to the first, the layer's output channels of
+// ga masked where its ReLU was off (gl) give its weight gradient, and the
+// transposed 3x3 convolution of gl is added to ga's channels 0 .. C + i G - 1.
+int train_run_dense(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
+                    const int32_t *d_off, int ntruth, hipStream_t s, float *d_grad, float *d_loss)
+{
+    const int C = net->C, L = net->dL, G = net->dG, CT = C + L * G, nb = net->nb;
+    const int64_t P = (int64_t)n * h * w;
+    const DenseOffsets o = dense_offsets(net);
+    const DensePackPlan pl = dense_pack_plan(net);
+    const int nblk = (n * h + wgrad_rows_per_block(n, h) - 1) / wgrad_rows_per_block(n, h);
+    const size_t wmax = std::max((size_t)G * (C + (L - 1) * G) * 9, (size_t)C * CT);
+    size_t off = 0;
+    auto take = [&](size_t floats) { size_t at = off; off = align_up(off + floats * 4); return at; };
+    std::vector<size_t> A(nb);
+    for (int b = 0; b < nb; ++b) A[b] = take((size_t)P * CT);
+    const size_t tl = take((size_t)P * C), ga = take((size_t)P * CT), gl = take((size_t)P * G), gtp = take((size_t)P * C);
+    const size_t maps = take((size_t)P * 10), gm = take((size_t)P * 10);
+    const size_t stats = take((size_t)3 * n), lse = take((size_t)train_lse_floats(h, w, ntruth));
+    const size_t term = take((size_t)9 * P + 48 * (size_t)n), occ = take((size_t)(P + 3) / 4);
+    const size_t part = take((size_t)nblk * wmax), pb = take((size_t)nblk * 32);
+    const size_t tmp = take((size_t)32 * (wmax + 32) + (size_t)32 * (10 * C + 10));
+    const size_t gpart = take((size_t)grad_chunks(P) * (10 * C + 10));
+    if (off > net->t_ws_bytes) {
+        HIPCHK(net, hipDeviceSynchronize());
+        if (net->t_ws) HIPCHK(net, hipFree(net->t_ws));
+        net->t_ws = nullptr;
+        net->t_ws_bytes = 0;
+        if (hipMalloc(&net->t_ws, off) != hipSuccess) return fail(net, DL_ERR_OOM, "training buffers of %zu bytes", off);
+        net->t_ws_bytes = off;
+    }
+    auto F = [&](size_t at) { return reinterpret_cast<float *>(net->t_ws + at); };
+    float *prm = net->t_params, *grd = d_grad ? d_grad : net->t_grad;
+    Geometry g;
+    FrameDesc *d_fd = nullptr;
+    const int slot = train_geometry(net, d_frames, n, h, w, s, g, &d_fd);
+    if (slot < 0) return slot;
+    HIPCHK(net, launch_pack_jobs(net->t_jobs, net->t_njobs, net->t_jobs_total, prm, net->t_pack, s));
+    auto pk = [&](int job) { return net->t_pack + pl.jobs[job].dst; };
+    auto conv = [&](int b, float *in, int csi, int cin, float *out, int cso, int co, const float *wpk,
+                    const float *bias, const float *res, int relu) {
+        DenseConvArgs a{};
+        a.in = in;
+        a.csi = csi;
+        a.cin = cin;
+        a.out = out;
+        a.cso = cso;
+        a.co = co;
+        a.w = wpk;
+        a.bias = bias;
+        a.fd = d_fd;
+        a.d = net->dil[b];
+        a.blk = b;
+        a.res = res;
+        a.rcs = cso;
+        a.relu = relu;
+        return a;
+    };
+    const float scale = net->cfg.gain * in_scale_of(net);
+    // forward
+    HIPCHK(net, launch_dstem(C, d_fd, g, prm + o.stem_w, prm + o.stem_b, net->cfg.offset, scale, F(A[0]), CT, s));
+    for (int b = 0; b < nb; ++b) {
+        for (int i = 0; i < L; ++i) {
+            const size_t li = (size_t)b * L + i;
+            DenseConvArgs a = conv(b, F(A[b]), CT, C + i * G, F(A[b]), CT, C + i * G, pk(pl.fw[li]), prm + o.lb[li],
+                                   nullptr, 1);
+            if (i < L - 1) {
+                HIPCHK(net, launch_dconv_train(G / 16, a, g, net->ncu, s));
+            } else {
+                a.wt = pk(pl.tw[b]);
+                a.bt = prm + o.tb[b];
+                a.tout = b + 1 < nb ? F(A[b + 1]) : F(tl);
+                a.cst = b + 1 < nb ? CT : C;
+                HIPCHK(net, launch_dconv_train_fused(C / 16, a, g, net->ncu, s));
+            }
+        }
+    }
+    HIPCHK(net, launch_train_loss(C, F(tl), prm + o.head_w, prm + o.head_b, n, h, w, d_truth, d_off, ntruth,
+                                  net->z_scale, net->ph_scale, F(maps), F(stats), F(lse), F(gm), d_loss, F(term),
+                                  reinterpret_cast<uint8_t *>(net->t_ws + occ), s));
+    // backward
+    float *mid = F(tmp);
+    HIPCHK(net, launch_head_backward(C, F(gm), F(tl), prm + o.head_w, n, h, w, grd + o.head_w, F(gpart), mid, F(gtp),
+                                     s));
+    for (int b = nb - 1; b >= 0; --b) {
+        if (b + 1 < nb)   // the next block's input gradient, where this block's transition was on
+            HIPCHK(net, launch_mask_slice(F(ga), CT, 0, F(A[b + 1]), CT, 0, C, P, F(gtp), C, s));
+        // the transition: weight gradient (16-row pieces when CT is not a multiple of C), input gradient
+        if (CT % C == 0) {
+            HIPCHK(net, launch_wgrad_ex(C, 1, F(gtp), C, F(A[b]), CT, CT, n, h, w, 1, F(part), F(pb), mid,
+                                        grd + o.tw[b], grd + o.tb[b], s));
+        } else {
+            for (int r = 0; r < C; r += 16)
+                HIPCHK(net, launch_wgrad_ex(16, 1, F(gtp) + r, C, F(A[b]), CT, CT, n, h, w, 1, F(part), F(pb), mid,
+                                            grd + o.tw[b] + (size_t)r * CT, grd + o.tb[b] + r, s));
+        }
+        HIPCHK(net, launch_1x1_back(C, F(gtp), prm + o.tw[b], CT, P, F(ga), s));
+        for (int i = L - 1; i >= 0; --i) {
+            const size_t li = (size_t)b * L + i;
+            const int lo = C + i * G;
+            HIPCHK(net, launch_mask_slice(F(ga), CT, lo, F(A[b]), CT, lo, G, P, F(gl), G, s));
+            HIPCHK(net, launch_wgrad_ex(G, 9, F(gl), G, F(A[b]), CT, lo, n, h, w, net->dil[b], F(part), F(pb), mid,
+                                        grd + o.lw[li], grd + o.lb[li], s));
+            for (int job : pl.tr[li]) {
+                const PackJob &J = pl.jobs[job];
+                DenseConvArgs a = conv(b, F(gl), G, G, F(ga), CT, J.row0, pk(job), nullptr, F(ga) + J.row0, 0);
+                HIPCHK(net, launch_dconv_train(J.nrows / 16, a, g, net->ncu, s));
+            }
+        }
+    }
+    // the stem: its output's gradient where its ReLU was on
+    HIPCHK(net, launch_mask_slice(F(ga), CT, 0, F(A[0]), CT, 0, C, P, F(gtp), C, s));
+    HIPCHK(net, launch_stem_grad(F(gtp), d_frames, n, h, w, net->cfg.offset, scale, C, grd + o.stem_w, F(gpart), mid,
+                                 s));
+    HIPCHK(net, hipEventRecord(net->desc_ev[slot], s));
     return DL_OK;
 }
 
@@ -1175,6 +1417,7 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
 {
     int rc;
     if ((rc = set_device(net)) || (rc = train_init(net))) return rc;
+    if (net->dL) return train_run_dense(net, d_frames, n, h, w, d_truth, d_off, ntruth, s, d_grad, d_loss);
     const int C = net->C, nb = net->nb;
     const int64_t P = (int64_t)n * h * w;
     const ParamOffsets o = param_offsets(net);
@@ -1587,6 +1830,7 @@ void dl_destroy_net(dl_net *net)
     if (net->d_dense) (void)hipFree(net->d_dense);
     for (float *q : {net->t_params, net->t_grad, net->t_m, net->t_v, net->t_pack})
         if (q) (void)hipFree(q);
+    if (net->t_jobs) (void)hipFree(net->t_jobs);
     if (net->t_ws) (void)hipFree(net->t_ws);
     if (net->d_gate_theta) (void)hipFree(net->d_gate_theta);
     if (net->d_radius) (void)hipFree(net->d_radius);

@@ -329,12 +329,39 @@ hipError_t launch_head_backward(int C, const float *gm, const float *act, const 
 int wgrad_rows_per_block(int n, int h);
 hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, int w, int d, float *part, float *pb,
                         float *tmp, float *gW, float *gb, hipStream_t s);
+// the same for CO (16 or 32) outputs over CI inputs (a multiple of CO) of a
+// 3x3 (taps 9) or 1x1 (taps 1) conv; dy points of dcs floats, x points of xcs
+// floats (channels 0 .. CI-1); gW [CO][CI][taps]; part nblk x CO CI taps, pb
+// nblk CO, tmp 32 x (CO CI taps + CO)
+hipError_t launch_wgrad_ex(int CO, int taps, const float *dy, int dcs, const float *x, int xcs, int CI, int n, int h,
+                           int w, int d, float *part, float *pb, float *tmp, float *gW, float *gb, hipStream_t s);
+// one weight pack: the conv at params + src ([cout][cin][taps]), or (flip) its
+// transposed convolution, rows row0 .. row0 + nrows - 1 (a multiple of 16),
+// into dst .. in the conv kernel's layout; start: the job's first element in
+// the launch (jobs in increasing order; elements between one job's last and
+// the next job's start are skipped)
+struct PackJob {
+    int64_t src, dst, start;
+    int cout, cin, taps, flip, row0, nrows;
+};
+hipError_t launch_pack_jobs(const PackJob *jobs, int njobs, int64_t total, const float *params, float *dst,
+                            hipStream_t s);
+// dst[p][c] = src[p][so + c] where m[p][mo + c] > 0, else 0 (c < nc)
+hipError_t launch_mask_slice(const float *src, int scs, int so, const float *m, int mcs, int mo, int nc, int64_t npx,
+                             float *dst, int dcs, hipStream_t s);
+// out[p][c] = sum_o Wt[o][c] g[p][o]: the 1x1 transition's input gradient (C 16
+// or 32; ct a multiple of 4)
+hipError_t launch_1x1_back(int C, const float *g, const float *Wt, int ct, int64_t npx, float *out, hipStream_t s);
 // stem weight/bias gradients (gwb: stem.w then stem.b); part: grad_chunks(n h w) x 10 C
 hipError_t launch_stem_grad(const float *ds, const uint16_t *frames, int n, int h, int w, float offset, float scale,
                             int C, float *gwb, float *part, float *mid, hipStream_t s);
 
 // one plain dense-kernel layer with the training epilogue (see DenseConvArgs)
 hipError_t launch_dconv_train(int nb_out, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s);
+// a dense block's last layer (16 outputs, written to out at co) fused with the
+// block's 1x1 transition (nt = its outputs / 16) as in inference, for the
+// training forward pass
+hipError_t launch_dconv_train_fused(int nt, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s);
 // preprocessing + stem 1 -> C (C 16 or 32) + ReLU into channels 0 .. C-1 of points of cs floats
 hipError_t launch_dstem(int C, const FrameDesc *fd, const Geometry &g, const float *w, const float *b, float offset,
                         float scale, float *act, int cs, hipStream_t s);

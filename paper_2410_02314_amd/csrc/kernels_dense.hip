@@ -19,6 +19,9 @@
 //             are staged in LDS, the next group's tile and weights are loaded
 //             into registers while the MFMAs run on the current one.  FUSE = 1
 //             adds the transition, FUSE = 2 the transition and the head.
+//             TRAIN: the training passes' epilogue (optional bias, residual,
+//             ReLU and mask); with FUSE = 1 it also stores the last layer's
+//             own outputs, which the backward pass needs.
 #include <algorithm>
 
 #include "dloc_internal.h"
@@ -314,6 +317,14 @@ k_dconv(DenseConvArgs a, Geometry geo)
                 }
             } else {
                 v4f hin[HK];                 // the head's input: transition or layer outputs
+                if constexpr (TRAIN && TR) {
+                    // training keeps the layer's own outputs too
+                    if (inside) {
+                        float *op = a.out + (act + (int64_t)yo * W + xo) * a.cso + a.co;
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb) *reinterpret_cast<v4f *>(op + nb * 16 + 4 * kq) = o[nb];
+                    }
+                }
                 if constexpr (TR) {
                     // the layer's outputs are the transition's last K groups: in the
                     // accumulator layout, lane (j, kq) element s is channel 4 kq + s
@@ -485,6 +496,13 @@ hipError_t launch_dconv_train(int nb_out, const DenseConvArgs &a, const Geometry
 {
     if (nb_out == 1) return launch_dconv_q<1, 1, 0, false, true>(a, g, ncu, s);
     if (nb_out == 2) return launch_dconv_q<2, 1, 0, false, true>(a, g, ncu, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_dconv_train_fused(int nt, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
+{
+    if (nt == 1) return launch_dconv_q<1, 1, 1, false, true>(a, g, ncu, s);
+    if (nt == 2) return launch_dconv_q<1, 2, 1, false, true>(a, g, ncu, s);
     return hipErrorInvalidValue;
 }
 

@@ -94,6 +94,85 @@ k_pack_conv(const float *__restrict__ W0, int64_t src_stride, int count, int C, 
     dst[e] = fl ? W[((size_t)c * C + o) * 9 + (8 - t)] : W[((size_t)o * C + c) * 9 + t];
 }
 
+// Packs of any 3x3 or 1x1 conv weights into the conv kernel's MFMA layout,
+// one job each (see PackJob): element i of job j is
+// dst[j.dst + i] = Wp[row0 + 16 nb + (lane & 15)][16 g + 4 (lane >> 4) + s][t]
+// for i = (((g taps + t) NB + nb) 64 + lane) 4 + s, NB = nrows / 16, where Wp
+// is the job's weights W = params + src ([cout][cin][taps]) or, flipped, the
+// transposed convolution's Wp[o][c][t] = W[c][o][taps - 1 - t].
+__global__ void __launch_bounds__(256)
+k_pack_jobs(const PackJob *__restrict__ jobs, int njobs, int64_t total, const float *__restrict__ params,
+            float *__restrict__ dst)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].start <= e) lo = mid; else hi = mid - 1;
+    }
+    const PackJob J = jobs[lo];
+    const int i = (int)(e - J.start);
+    if (i >= J.nrows * (J.flip ? J.cout : J.cin) * J.taps) return;   // the padding before the next job
+    const int NB = J.nrows / 16;
+    const int s = i & 3, lane = (i >> 2) & 63, rest = i >> 8;
+    const int nb = rest % NB, gt = rest / NB;
+    const int t = gt % J.taps, g = gt / J.taps;
+    const int o = J.row0 + nb * 16 + (lane & 15), c = g * 16 + 4 * (lane >> 4) + s;
+    const float *W = params + J.src;
+    dst[J.dst + i] = J.flip ? W[((size_t)c * J.cin + o) * J.taps + (J.taps - 1 - t)]
+                            : W[((size_t)o * J.cin + c) * J.taps + t];
+}
+
+// dst[p][c] = src[p][so + c] where m[p][mo + c] > 0, else 0, for c < nc (a
+// multiple of 4); points of scs, mcs and dcs floats; a thread per four channels
+__global__ void __launch_bounds__(256)
+k_mask_slice(const float *__restrict__ src, int scs, int so, const float *__restrict__ m, int mcs, int mo, int nc,
+             int64_t npx, float *__restrict__ dst, int dcs)
+{
+    const int q4 = nc / 4;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= npx * q4) return;
+    const int64_t p = i / q4;
+    const int c = (int)(i - p * q4) * 4;
+    const float4 v = *reinterpret_cast<const float4 *>(src + p * scs + so + c);
+    const float4 k = *reinterpret_cast<const float4 *>(m + p * mcs + mo + c);
+    *reinterpret_cast<float4 *>(dst + p * dcs + c) =
+        make_float4(k.x > 0.f ? v.x : 0.f, k.y > 0.f ? v.y : 0.f, k.z > 0.f ? v.z : 0.f, k.w > 0.f ? v.w : 0.f);
+}
+
+// The 1x1 transition's input gradient: out[p][c] = sum_o Wt[o][c] g[p][o] for
+// c < ct (Wt [C][ct] from the flat weights; g: points of C floats; out:
+// points of ct floats), a thread per (point, four channels)
+template <int C>
+__global__ void __launch_bounds__(256)
+k_1x1_back(const float *__restrict__ g, const float *__restrict__ Wt, int ct, int64_t npx, float *__restrict__ out)
+{
+    extern __shared__ float sWt[];
+    for (int i = threadIdx.x; i < C * ct; i += 256) sWt[i] = Wt[i];
+    __syncthreads();
+    const int q4 = ct / 4;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= npx * q4) return;
+    const int64_t p = i / q4;
+    const int c = (int)(i - p * q4) * 4;
+    float gv[C];
+#pragma unroll
+    for (int k = 0; k < C / 4; ++k) {
+        const float4 v = *reinterpret_cast<const float4 *>(g + p * C + 4 * k);
+        gv[4 * k] = v.x;
+        gv[4 * k + 1] = v.y;
+        gv[4 * k + 2] = v.z;
+        gv[4 * k + 3] = v.w;
+    }
+    float r[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o = 0; o < C; ++o)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[j] = fmaf(sWt[o * ct + c + j], gv[o], r[j]);
+    *reinterpret_cast<float4 *>(out + p * ct + c) = make_float4(r[0], r[1], r[2], r[3]);
+}
+
 template <int C>
 __global__ void __launch_bounds__(256)
 k_head_fwd(const float *__restrict__ act, const float *__restrict__ hw, const float *__restrict__ hb, int64_t npx,
@@ -543,66 +622,70 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, (int)nbytes, (int)BUF_FLAGS);
 }
 
-// Weight gradient of a 3x3 conv at dilation d over NHWC tensors of C floats per
-// point: dW[co][ci][tap] = sum_p dy[p][co] x[p + off(tap)][ci] (zero off the
-// frame), db[co] = sum_p dy[p][co].  Wave v of workgroup b takes the batch rows
-// [(8 b + v) rpw, + rpw) (a frame's rows are consecutive), K = 64 / C pixels of
-// a row per step, all 9 taps per step.  Every operand is a buffer load: a
-// row off the frame is a buffer of no bytes and a column off the frame an
-// offset past the buffer, both of which read zero, so the loads carry no
-// branch.  Four register sets rotate: a step's ten loads are issued three
-// steps ahead of its nine matrix instructions.  The eight waves' sums are
-// added in order through LDS, one group of output rows at a time (each wave
-// only stores its accumulators, so they go to LDS without passing through
-// vector registers), and written in the weights' own order:
-// part[b][(co C + ci) 9 + tap], pb[b][co].
-template <int C>
+// Weight gradient of a 3x3 (TAPS = 9) or 1x1 (TAPS = 1) conv at dilation d
+// over NHWC tensors: dW[co][ci][tap] = sum_p dy[p][co] x[p + off(tap)][ci]
+// (zero off the frame), db[co] = sum_p dy[p][co], for CO output channels (dy:
+// points of dcs floats) and CI input channels (x: points of xcs floats,
+// channels 0 .. CI-1), CI a multiple of CO.  Workgroup (b, cb) takes input
+// channels [cb CO, cb CO + CO); its wave v the batch rows [(8 b + v) rpw, +
+// rpw) (a frame's rows are consecutive), K = 64 / CO pixels of a row per step,
+// all taps per step.  Every operand is a buffer load: a row off the frame is
+// a buffer of no bytes and a column off the frame an offset past the buffer,
+// both of which read zero, so the loads carry no branch.  Four register sets
+// rotate: a step's loads are issued three steps ahead of its matrix
+// instructions.  The eight waves' sums are added in order through LDS, one
+// group of output rows at a time (each wave only stores its accumulators, so
+// they go to LDS without passing through vector registers), and written in
+// the weights' own order: part[b][(co CI + ci) TAPS + tap]; pb[b][co] (cb = 0).
+template <int CO, int TAPS>
 __global__ void __launch_bounds__(64 * WG_WAVES)
-k_wgrad(const float *__restrict__ dy, const float *__restrict__ x, int n, int h, int w, int d, int rpw,
-        float *__restrict__ part, float *__restrict__ pb)
+k_wgrad(const float *__restrict__ dy, int dcs, const float *__restrict__ x, int xcs, int CI, int n, int h, int w,
+        int d, int rpw, float *__restrict__ part, float *__restrict__ pb)
 {
-    using M = WgMma<C>;
-    constexpr int PX = 64 / C;
-    constexpr int GR = C / M::NG;              // output rows per group (8 or 16)
-    constexpr int TSR = C * GR + 4;            // LDS floats per (wave, tap), padded against bank conflicts
-    __shared__ __align__(16) float red[WG_WAVES * 9 * TSR];
-    __shared__ float sb[WG_WAVES][C];
+    using M = WgMma<CO>;
+    constexpr int PX = 64 / CO;
+    constexpr int GR = CO / M::NG;             // output rows per group (8 or 16)
+    constexpr int TSR = CO * GR + 4;           // LDS floats per (wave, tap), padded against bank conflicts
+    constexpr int NU = TAPS == 9 ? 3 : 1;      // tap rows (and columns)
+    __shared__ __align__(16) float red[WG_WAVES * TAPS * TSR];
+    __shared__ float sb[WG_WAVES][CO];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ch = lane % C, kp = lane / C;
+    const int ch = lane % CO, kp = lane / CO;
+    const int cb = blockIdx.y, xch = cb * CO + ch;
     const int rows = n * h;
     const int gr0 = (blockIdx.x * WG_WAVES + wave) * rpw, gr1 = min(rows, gr0 + rpw);
     const int steps = (w + PX - 1) / PX;
-    const uint32_t rowbytes = (uint32_t)w * C * 4;
-    typename M::acc_t acc[9];
+    const uint32_t dbytes = (uint32_t)w * dcs * 4, xbytes = (uint32_t)w * xcs * 4;
+    typename M::acc_t acc[TAPS];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) acc[t] = typename M::acc_t{};
+    for (int t = 0; t < TAPS; ++t) acc[t] = typename M::acc_t{};
     float bsum = 0.f;
-    __amdgpu_buffer_rsrc_t rd, rx[3];
+    __amdgpu_buffer_rsrc_t rd, rx[NU];
     int gr = gr0, q = 0;
     auto set_row = [&]() {
         const int f = gr / h, y = gr - f * h;
-        const float *fx = x + (size_t)f * h * w * C;
-        rd = row_rsrc(dy + ((size_t)f * h + y) * w * C, rowbytes);
+        const float *fx = x + (size_t)f * h * w * xcs;
+        rd = row_rsrc(dy + ((size_t)f * h + y) * w * dcs, dbytes);
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const int ys = y + d * (u - 1);
+        for (int u = 0; u < NU; ++u) {
+            const int ys = TAPS == 9 ? y + d * (u - 1) : y;
             const bool ok = (unsigned)ys < (unsigned)h;
-            rx[u] = row_rsrc(fx + (size_t)(ok ? ys : y) * w * C, ok ? rowbytes : 0u);
+            rx[u] = row_rsrc(fx + (size_t)(ok ? ys : y) * w * xcs, ok ? xbytes : 0u);
         }
     };
     // loads of step (gr, q), then on to the step after it; past the last row dy
     // becomes a buffer of no bytes, so a further step adds zeros
-    auto load_next = [&](float &a, float (&b)[9]) {
+    auto load_next = [&](float &a, float (&b)[TAPS]) {
         const int xx = q * PX + kp;
-        a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rd, xx < w ? (xx * C + ch) * 4 : BUF_OOB, 0, 0));
+        a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rd, xx < w ? (xx * dcs + ch) * 4 : BUF_OOB, 0, 0));
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            const int xs = xx + d * (v - 1);
-            const int o = (unsigned)xs < (unsigned)w ? (xs * C + ch) * 4 : BUF_OOB;
+        for (int v = 0; v < NU; ++v) {
+            const int xs = TAPS == 9 ? xx + d * (v - 1) : xx;
+            const int o = (unsigned)xs < (unsigned)w ? (xs * xcs + xch) * 4 : BUF_OOB;
 #pragma unroll
-            for (int u = 0; u < 3; ++u)
-                b[3 * u + v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx[u], o, 0, 0));
+            for (int u = 0; u < NU; ++u)
+                b[NU * u + v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx[u], o, 0, 0));
         }
         if (++q == steps) {
             q = 0;
@@ -614,15 +697,15 @@ k_wgrad(const float *__restrict__ dy, const float *__restrict__ x, int n, int h,
             }
         }
     };
-    auto step = [&](float a, const float (&b)[9]) {
+    auto step = [&](float a, const float (&b)[TAPS]) {
         bsum += a;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc[t] = M::mma(a, b[t], acc[t]);
+        for (int t = 0; t < TAPS; ++t) acc[t] = M::mma(a, b[t], acc[t]);
     };
     if (gr0 < gr1) {
         const int total = (gr1 - gr0) * steps;
         set_row();
-        float a0, b0[9], a1, b1[9], a2, b2[9], a3, b3[9];
+        float a0, b0[TAPS], a1, b1[TAPS], a2, b2[TAPS], a3, b3[TAPS];
         load_next(a0, b0);
         load_next(a1, b1);
         load_next(a2, b2);
@@ -639,32 +722,32 @@ k_wgrad(const float *__restrict__ dy, const float *__restrict__ x, int n, int h,
     }
     // the bias: the K pixel groups of channel ch
 #pragma unroll
-    for (int o = C; o < 64; o <<= 1) bsum += __shfl_xor(bsum, o);
-    if (lane < C) sb[wave][lane] = bsum;
+    for (int o = CO; o < 64; o <<= 1) bsum += __shfl_xor(bsum, o);
+    if (lane < CO) sb[wave][lane] = bsum;
     // per group of GR output rows: every wave stores its accumulators, then the
     // waves' values are added in order; LDS [wave][tap][ci][row in group]
-    float *P = part + (size_t)blockIdx.x * 9 * C * C;
+    float *P = part + (size_t)blockIdx.x * CO * CI * TAPS;
 #pragma unroll
     for (int g = 0; g < M::NG; ++g) {
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            float4 *dst = reinterpret_cast<float4 *>(red + (wave * 9 + t) * TSR + ch * GR + M::row0(lane, g) - g * GR);
+        for (int t = 0; t < TAPS; ++t) {
+            float4 *dst = reinterpret_cast<float4 *>(red + (wave * TAPS + t) * TSR + ch * GR + M::row0(lane, g) - g * GR);
             *dst = make_float4(acc[t][4 * g], acc[t][4 * g + 1], acc[t][4 * g + 2], acc[t][4 * g + 3]);
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < GR * C * 9; j += 64 * WG_WAVES) {
-            const int t = j % 9, ci = (j / 9) % C, r = j / (9 * C);
+        for (int j = threadIdx.x; j < GR * CO * TAPS; j += 64 * WG_WAVES) {
+            const int t = j % TAPS, ci = (j / TAPS) % CO, r = j / (TAPS * CO);
             float v = 0.f;
 #pragma unroll
-            for (int k = 0; k < WG_WAVES; ++k) v += red[(k * 9 + t) * TSR + ci * GR + r];
-            P[(size_t)g * GR * C * 9 + j] = v;
+            for (int k = 0; k < WG_WAVES; ++k) v += red[(k * TAPS + t) * TSR + ci * GR + r];
+            P[((size_t)(g * GR + r) * CI + cb * CO + ci) * TAPS + t] = v;
         }
         __syncthreads();
     }
-    if (threadIdx.x < C) {
+    if (cb == 0 && threadIdx.x < CO) {
         float v = 0.f;
         for (int k = 0; k < WG_WAVES; ++k) v += sb[k][threadIdx.x];
-        pb[(size_t)blockIdx.x * C + threadIdx.x] = v;
+        pb[(size_t)blockIdx.x * CO + threadIdx.x] = v;
     }
 }
 
@@ -771,6 +854,38 @@ void reduce_partials(const float *pa, int ma, float *oa, const float *pbb, int m
 
 }  // namespace
 
+hipError_t launch_pack_jobs(const PackJob *jobs, int njobs, int64_t total, const float *params, float *dst,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_jobs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, jobs, njobs, total, params,
+                       dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_slice(const float *src, int scs, int so, const float *m, int mcs, int mo, int nc, int64_t npx,
+                             float *dst, int dcs, hipStream_t s)
+{
+    if (nc % 4) return hipErrorInvalidValue;
+    const int64_t n = npx * (nc / 4);
+    hipLaunchKernelGGL(k_mask_slice, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, scs, so, m, mcs, mo, nc, npx,
+                       dst, dcs);
+    return hipGetLastError();
+}
+
+hipError_t launch_1x1_back(int C, const float *g, const float *Wt, int ct, int64_t npx, float *out, hipStream_t s)
+{
+    if (ct % 4) return hipErrorInvalidValue;
+    const int64_t n = npx * (ct / 4);
+    const size_t lds = (size_t)C * ct * 4;
+    if (C == 32)
+        hipLaunchKernelGGL(k_1x1_back<32>, dim3((unsigned)((n + 255) / 256)), dim3(256), lds, s, g, Wt, ct, npx, out);
+    else if (C == 16)
+        hipLaunchKernelGGL(k_1x1_back<16>, dim3((unsigned)((n + 255) / 256)), dim3(256), lds, s, g, Wt, ct, npx, out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_convs(const float *W0, int64_t src_stride, int count, int C, float *dst, hipStream_t s)
 {
     const int64_t n = (int64_t)count * 2 * C * C * 9;
@@ -849,21 +964,33 @@ hipError_t launch_head_backward(int C, const float *gm, const float *act, const 
 // registers of C = 32)
 int wgrad_rows_per_block(int n, int h) { return WG_WAVES * std::max(1, (n * h + 2047) / 2048); }
 
+hipError_t launch_wgrad_ex(int CO, int taps, const float *dy, int dcs, const float *x, int xcs, int CI, int n, int h,
+                           int w, int d, float *part, float *pb, float *tmp, float *gW, float *gb, hipStream_t s)
+{
+    if (!(CO == 16 || CO == 32) || !(taps == 1 || taps == 9) || CI < CO || CI % CO) return hipErrorInvalidValue;
+    const int R = wgrad_rows_per_block(n, h);
+    const dim3 grid((n * h + R - 1) / R, CI / CO);
+    const int rpw = R / WG_WAVES;
+    if (CO == 32 && taps == 9)
+        hipLaunchKernelGGL((k_wgrad<32, 9>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, rpw,
+                           part, pb);
+    else if (CO == 32)
+        hipLaunchKernelGGL((k_wgrad<32, 1>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, rpw,
+                           part, pb);
+    else if (taps == 9)
+        hipLaunchKernelGGL((k_wgrad<16, 9>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, rpw,
+                           part, pb);
+    else
+        hipLaunchKernelGGL((k_wgrad<16, 1>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, rpw,
+                           part, pb);
+    reduce_partials(part, CO * CI * taps, gW, pb, CO, gb, (int)grid.x, tmp, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_wgrad(int C, const float *dy, const float *x, int n, int h, int w, int d, float *part, float *pb,
                         float *tmp, float *gW, float *gb, hipStream_t s)
 {
-    const int R = wgrad_rows_per_block(n, h);
-    const int nblk = (n * h + R - 1) / R;
-    if (C == 32)
-        hipLaunchKernelGGL(k_wgrad<32>, dim3(nblk), dim3(64 * WG_WAVES), 0, s, dy, x, n, h, w, d, R / WG_WAVES, part,
-                           pb);
-    else if (C == 16)
-        hipLaunchKernelGGL(k_wgrad<16>, dim3(nblk), dim3(64 * WG_WAVES), 0, s, dy, x, n, h, w, d, R / WG_WAVES, part,
-                           pb);
-    else
-        return hipErrorInvalidValue;
-    reduce_partials(part, 9 * C * C, gW, pb, C, gb, nblk, tmp, s);
-    return hipGetLastError();
+    return launch_wgrad_ex(C, 9, dy, C, x, C, C, n, h, w, d, part, pb, tmp, gW, gb, s);
 }
 
 hipError_t launch_stem_grad(const float *ds, const uint16_t *frames, int n, int h, int w, float offset, float scale,

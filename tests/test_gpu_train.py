@@ -10,6 +10,10 @@ against the FP64 training oracle, through the C ABI.
 * dl_train_step: one step equals the oracle's Adam step on the oracle's
   gradient; forty steps lower the loss; the inference path then runs the
   trained weights (its maps equal the oracle's on dl_get_params' weights);
+* the dense-connection network (backward through the concatenation and the
+  fused 1x1 transition): gradients against the oracle for several widths,
+  depths and dilations, net DT itself, a tall frame; an Adam step and the
+  trained weights in the inference path;
 * refusals: nets the training kernels do not cover.
 """
 import numpy as np
@@ -128,13 +132,72 @@ def test_adam_step_matches_the_oracle_and_training_lowers_the_loss():
     assert map_rel_err(maps.cpu().numpy(), ref).max() <= TOL
 
 
+# the dense-connection network: C = 32 with four layers (CT = 96), C = 32 with
+# three (CT = 80: the transition's weight gradient in 16-row pieces), C = 16,
+# net DT itself (dilations 2 .. 16), and a tall frame (two rows per wave)
+@pytest.mark.parametrize("spec,n,h,w", [(S.DenseSpec("td4", 32, (2, 4), head_outputs=10), 2, 40, 52),
+                                        (S.DenseSpec("td3", 32, (1, 3), layers=3, head_outputs=10), 2, 37, 45),
+                                        (S.DenseSpec("td16", 16, (1, 2), layers=2, head_outputs=10), 2, 33, 70),
+                                        (S.NET_DT, 1, 64, 64),
+                                        (S.DenseSpec("td2", 32, (2,), layers=2, head_outputs=10), 1, 2201, 13)])
+def test_dense_gradients_match_the_oracle(spec, n, h, w):
+    wts, net = net_and_weights(spec, 13)
+    frames, truths = batch(n, h, w, 23, empty_last=n > 1)
+    L, G = T.batch_grads(frames, truths, spec, wts)
+    loss, g = gpu_grads(net, spec, frames, truths)
+    print(spec.name, L, loss)
+    for i, k in enumerate(["total", "bce", "count", "loc"]):
+        assert abs(loss[i] - L[k]) <= TOL * (abs(L[k]) + 1e-3), (k, loss[i], L[k])
+    assert set(g) == set(G)
+    for k in G:
+        ref = np.asarray(G[k])
+        err = np.linalg.norm(g[k] - ref) / (np.linalg.norm(ref) + 1e-30)
+        print(k, err)
+        assert np.isfinite(g[k]).all() and err <= TOL, (k, err)
+    loss2, g2 = gpu_grads(net, spec, frames, truths)
+    assert np.array_equal(loss, loss2) and all(np.array_equal(g[k], g2[k]) for k in g)
+
+
+def test_dense_adam_step_and_the_trained_weights_in_inference():
+    spec = S.DenseSpec("td4", 32, (2, 4), head_outputs=10)
+    wts, net = net_and_weights(spec, 14)
+    frames, truths = batch(4, 48, 48, 24, empty_last=False)
+    fr = torch.from_numpy(frames).to(DEV)
+    tr, off = device_truth(truths)
+    _, G = T.batch_grads(frames, truths, spec, wts)
+    theta = S.flat_weights(spec, wts).astype(np.float64)
+    m, v = np.zeros_like(theta), np.zeros_like(theta)
+    oracle.adam_step(theta, m, v, S.flat_weights(spec, {k: np.asarray(g) for k, g in G.items()}).astype(np.float64), 1,
+                     lr=1e-3)
+    net.train_step(fr, tr, off, 1e-3)
+    moved = net.get_params().astype(np.float64) - S.flat_weights(spec, wts)
+    ref_moved = theta - S.flat_weights(spec, wts)
+    assert np.mean(np.abs(moved - ref_moved) <= 1e-6 + 1e-3 * np.abs(ref_moved)) >= 0.99
+    losses = [float(net.train_step(fr, tr, off, 1e-3).cpu()[0]) for _ in range(30)]
+    print(losses[:3], losses[-3:])
+    assert losses[-1] < losses[0]
+    tw = S.unflat_weights(spec, net.get_params())
+    maps = torch.empty((4, 10, 48, 48), dtype=torch.float32, device=DEV)
+    net.maps_device(fr, maps)
+    torch.cuda.synchronize()
+    ref = oracle.net_maps_batch(frames, spec, tw)
+    assert map_rel_err(maps.cpu().numpy(), ref).max() <= TOL
+
+
 def test_nets_the_training_kernels_do_not_cover_are_refused():
     fr = torch.from_numpy(S.render_frames(1, 32, 32, "tiny", 3)).to(DEV)
     tr = torch.zeros((0, 4), dtype=torch.float32, device=DEV)
     off = torch.zeros(2, dtype=torch.int32, device=DEV)
-    for name in ("B", "BU", "A", "D"):           # C = 48, a 5-output head, a dense net
+    for name in ("B", "BU", "A", "D"):           # C = 48, a 5-output head
         spec, w = S.make_net(name, 2 if name[0] == "B" else 1 if name == "A" else 3)
         net = dl.Net(S.serialize_weights(spec, w))
         with pytest.raises(dl.DlocError) as e:
             net.train_grad(fr, tr, off)
         assert e.value.code == dl.DL_ERR_UNSUPPORTED, name
+    # dense nets with the U-Net stage or a growth other than 16
+    for spec in (S.DenseSpec("dut", 32, (2, 4), head_outputs=10, unet=2),
+                 S.DenseSpec("dg32", 32, (2,), growth=32, head_outputs=10)):
+        net = dl.Net(S.serialize_weights(spec, S.he_normal_weights(spec, 1)))
+        with pytest.raises(dl.DlocError) as e:
+            net.train_grad(fr, tr, off)
+        assert e.value.code == dl.DL_ERR_UNSUPPORTED, spec.name
