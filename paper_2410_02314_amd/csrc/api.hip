@@ -1172,7 +1172,7 @@ DenseOffsets dense_offsets(const dl_net *net)
 // order: per block, each layer's forward pack (16 rows over its C + i G
 // inputs, 9 taps), the transition's (C rows over CT inputs, 1 tap) for the
 // fused last layer, and each layer's transposed convolution (G inputs ->
-// C + i G outputs) in slices of at most 32 output rows, one conv launch each.
+// C + i G outputs) in slices of at most 80 output rows, one conv launch each.
 struct DensePackPlan {
     std::vector<PackJob> jobs;
     std::vector<int> fw, tw;                      // job index: fw [block L + layer], tw [block]
@@ -1206,8 +1206,8 @@ DensePackPlan dense_pack_plan(const dl_net *net)
         pl.tw.push_back(add(o.tw[b], C, CT, 1, 0, 0, C));
         for (int i = 0; i < L; ++i) {
             std::vector<int> sl;
-            for (int r = 0; r < C + i * G; r += 32)
-                sl.push_back(add(o.lw[(size_t)b * L + i], G, C + i * G, 9, 1, r, std::min(32, C + i * G - r)));
+            for (int r = 0; r < C + i * G; r += 80)
+                sl.push_back(add(o.lw[(size_t)b * L + i], G, C + i * G, 9, 1, r, std::min(80, C + i * G - r)));
             pl.tr.push_back(sl);
         }
     }

@@ -350,13 +350,14 @@ hipError_t launch_pack_jobs(const PackJob *jobs, int njobs, int64_t total, const
 hipError_t launch_mask_slice(const float *src, int scs, int so, const float *m, int mcs, int mo, int nc, int64_t npx,
                              float *dst, int dcs, hipStream_t s);
 // out[p][c] = sum_o Wt[o][c] g[p][o]: the 1x1 transition's input gradient (C 16
-// or 32; ct a multiple of 4)
+// or 32; ct a multiple of 16)
 hipError_t launch_1x1_back(int C, const float *g, const float *Wt, int ct, int64_t npx, float *out, hipStream_t s);
 // stem weight/bias gradients (gwb: stem.w then stem.b); part: grad_chunks(n h w) x 10 C
 hipError_t launch_stem_grad(const float *ds, const uint16_t *frames, int n, int h, int w, float offset, float scale,
                             int C, float *gwb, float *part, float *mid, hipStream_t s);
 
-// one plain dense-kernel layer with the training epilogue (see DenseConvArgs)
+// one plain dense-kernel layer with the training epilogue (see DenseConvArgs),
+// nb_out 1 .. 5 blocks of 16 outputs
 hipError_t launch_dconv_train(int nb_out, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s);
 // a dense block's last layer (16 outputs, written to out at co) fused with the
 // block's 1x1 transition (nt = its outputs / 16) as in inference, for the

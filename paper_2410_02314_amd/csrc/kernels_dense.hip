@@ -494,9 +494,14 @@ hipError_t launch_up2(const FrameDesc *sfd, const FrameDesc *dfd, int nf, int64_
 
 hipError_t launch_dconv_train(int nb_out, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)
 {
-    if (nb_out == 1) return launch_dconv_q<1, 1, 0, false, true>(a, g, ncu, s);
-    if (nb_out == 2) return launch_dconv_q<2, 1, 0, false, true>(a, g, ncu, s);
-    return hipErrorInvalidValue;
+    switch (nb_out) {
+    case 1: return launch_dconv_q<1, 1, 0, false, true>(a, g, ncu, s);
+    case 2: return launch_dconv_q<2, 1, 0, false, true>(a, g, ncu, s);
+    case 3: return launch_dconv_q<3, 1, 0, false, true>(a, g, ncu, s);
+    case 4: return launch_dconv_q<4, 1, 0, false, true>(a, g, ncu, s);
+    case 5: return launch_dconv_q<5, 1, 0, false, true>(a, g, ncu, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_dconv_train_fused(int nt, const DenseConvArgs &a, const Geometry &g, int ncu, hipStream_t s)

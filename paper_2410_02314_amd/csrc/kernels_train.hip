@@ -142,35 +142,46 @@ k_mask_slice(const float *__restrict__ src, int scs, int so, const float *__rest
 }
 
 // The 1x1 transition's input gradient: out[p][c] = sum_o Wt[o][c] g[p][o] for
-// c < ct (Wt [C][ct] from the flat weights; g: points of C floats; out:
-// points of ct floats), a thread per (point, four channels)
+// c < ct (Wt [C][ct] from the flat weights, staged in LDS; g: points of C
+// floats; out: points of ct floats, ct a multiple of 16), a GEMM on
+// v_mfma_f32_16x16x4_f32: a wave takes 16 points at a time, rows = points,
+// columns = 16 output channels, K = the C gradient channels with lane (i, kq)
+// giving g[point i][(C / 4) kq + s] at K step s (one or two 16-byte loads per
+// lane).  The output: lane (j, kq) holds channel j of points 4 kq + r.
 template <int C>
 __global__ void __launch_bounds__(256)
 k_1x1_back(const float *__restrict__ g, const float *__restrict__ Wt, int ct, int64_t npx, float *__restrict__ out)
 {
+    constexpr int KS = C / 4;                  // K steps
     extern __shared__ float sWt[];
     for (int i = threadIdx.x; i < C * ct; i += 256) sWt[i] = Wt[i];
     __syncthreads();
-    const int q4 = ct / 4;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= npx * q4) return;
-    const int64_t p = i / q4;
-    const int c = (int)(i - p * q4) * 4;
-    float gv[C];
+    const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+    const int64_t ngrp = (npx + 15) / 16;
+    for (int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); grp < ngrp; grp += (int64_t)gridDim.x * 4) {
+        const int64_t p = grp * 16 + i;
+        float av[KS];
 #pragma unroll
-    for (int k = 0; k < C / 4; ++k) {
-        const float4 v = *reinterpret_cast<const float4 *>(g + p * C + 4 * k);
-        gv[4 * k] = v.x;
-        gv[4 * k + 1] = v.y;
-        gv[4 * k + 2] = v.z;
-        gv[4 * k + 3] = v.w;
+        for (int k = 0; k < KS / 4; ++k) {
+            const float4 v = p < npx ? *reinterpret_cast<const float4 *>(g + p * C + KS * kq + 4 * k)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+            av[4 * k] = v.x;
+            av[4 * k + 1] = v.y;
+            av[4 * k + 2] = v.z;
+            av[4 * k + 3] = v.w;
+        }
+        for (int cb = 0; cb < ct / 16; ++cb) {
+            v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < KS; ++st)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], sWt[(KS * kq + st) * ct + cb * 16 + i], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t q = grp * 16 + 4 * kq + r;
+                if (q < npx) out[q * ct + cb * 16 + i] = acc[r];
+            }
+        }
     }
-    float r[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int o = 0; o < C; ++o)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) r[j] = fmaf(sWt[o * ct + c + j], gv[o], r[j]);
-    *reinterpret_cast<float4 *>(out + p * ct + c) = make_float4(r[0], r[1], r[2], r[3]);
 }
 
 template <int C>
@@ -874,13 +885,14 @@ hipError_t launch_mask_slice(const float *src, int scs, int so, const float *m, 
 
 hipError_t launch_1x1_back(int C, const float *g, const float *Wt, int ct, int64_t npx, float *out, hipStream_t s)
 {
-    if (ct % 4) return hipErrorInvalidValue;
-    const int64_t n = npx * (ct / 4);
+    if (ct % 16) return hipErrorInvalidValue;
+    const int64_t groups = (npx + 15) / 16;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 4096));
     const size_t lds = (size_t)C * ct * 4;
     if (C == 32)
-        hipLaunchKernelGGL(k_1x1_back<32>, dim3((unsigned)((n + 255) / 256)), dim3(256), lds, s, g, Wt, ct, npx, out);
+        hipLaunchKernelGGL(k_1x1_back<32>, dim3(grid), dim3(256), lds, s, g, Wt, ct, npx, out);
     else if (C == 16)
-        hipLaunchKernelGGL(k_1x1_back<16>, dim3((unsigned)((n + 255) / 256)), dim3(256), lds, s, g, Wt, ct, npx, out);
+        hipLaunchKernelGGL(k_1x1_back<16>, dim3(grid), dim3(256), lds, s, g, Wt, ct, npx, out);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
