@@ -157,6 +157,40 @@ def frame_grads(frame: np.ndarray, truth, spec, wts: Dict[str, np.ndarray], gain
     return loss, G, maps
 
 
+def _pool2(a: np.ndarray):
+    """2 x 2 max pooling of [C][h][w] to [C][ceil(h/2)][ceil(w/2)] (a window at
+    an odd edge holds the pixels it has) and each window's argmax: the first
+    maximum in the window's raster order (dy, dx)."""
+    C, h, w = a.shape
+    h2, w2 = (h + 1) // 2, (w + 1) // 2
+    pad = np.full((C, 2 * h2, 2 * w2), -np.inf)
+    pad[:, :h, :w] = a
+    win = pad.reshape(C, h2, 2, w2, 2).transpose(0, 1, 3, 2, 4).reshape(C, h2, w2, 4)
+    return win.max(axis=-1), np.argmax(win, axis=-1)
+
+
+def _pool2_back(g: np.ndarray, idx: np.ndarray, h: int, w: int) -> np.ndarray:
+    """The pooling's gradient: each window's gradient goes to its argmax."""
+    C, h2, w2 = g.shape
+    out = np.zeros((C, 2 * h2, 2 * w2))
+    cc, yy, xx = np.meshgrid(np.arange(C), np.arange(h2), np.arange(w2), indexing="ij")
+    out[cc, 2 * yy + idx // 2, 2 * xx + idx % 2] = g
+    return out[:, :h, :w]
+
+
+def _up2(v: np.ndarray, h: int, w: int) -> np.ndarray:
+    """Nearest upsampling to h x w: out[y][x] = v[y // 2][x // 2]."""
+    return v[:, np.arange(h) // 2][:, :, np.arange(w) // 2]
+
+
+def _up2_back(g: np.ndarray, h2: int, w2: int) -> np.ndarray:
+    """The upsampling's gradient: each coarse pixel sums its (up to) four fine ones."""
+    C, h, w = g.shape
+    pad = np.zeros((C, 2 * h2, 2 * w2))
+    pad[:, :h, :w] = g
+    return pad.reshape(C, h2, 2, w2, 2).sum(axis=(2, 4))
+
+
 def dense_frame_grads(frame: np.ndarray, truth, spec, wts: Dict[str, np.ndarray], gain=0.5, offset=100.0):
     """Loss of one frame and the gradient of every weight tensor of the
     dense-connection network (Sec. 3.2.1: each layer of a block reads the
@@ -170,9 +204,17 @@ def dense_frame_grads(frame: np.ndarray, truth, spec, wts: Dict[str, np.ndarray]
     was off, give the layer's weight gradient against its input (the
     concatenation so far) and add the transposed 3x3 convolution of it to the
     gradient of that input.  The first C channels are then the gradient at the
-    block's input."""
-    if spec.unet:
-        raise ValueError("the training oracle covers the dense network without the U-Net stage")
+    block's input.
+
+    With the two-stage U-Net after the blocks (Sec. 3.2: the fine-grained
+    stage), its backward runs first: through u0's convolution over [a0,
+    up(u1)], the upsampling (each coarse pixel sums the gradients of the fine
+    pixels it fills), u1's convolution over [d1, up(d2)], d2's and d1's
+    convolutions and the max poolings (a window's gradient goes to its first
+    maximum in raster order), and the two paths' gradients at d1 and at a0
+    are added."""
+    if spec.unet not in (0, 2):
+        raise ValueError("the U-Net stage has 0 or 2 levels")
     W = {k: np.asarray(v, np.float64) for k, v in wts.items()}
     C, Gr, L = spec.C, spec.growth, spec.layers
     x = preprocess(frame[None], gain, offset, spec.in_scale)[0][None]
@@ -187,12 +229,41 @@ def dense_frame_grads(frame: np.ndarray, truth, spec, wts: Dict[str, np.ndarray]
         t = _relu(np.tensordot(W[f"blk{k}.t.w"], cat, axes=(1, 0)) + W[f"blk{k}.t.b"][:, None, None])
         blocks.append((cat, t))
         a = t
+    if spec.unet:
+        ua = a
+        h, w = ua.shape[1:]
+        h1, w1 = (h + 1) // 2, (w + 1) // 2
+        h2, w2 = (h1 + 1) // 2, (w1 + 1) // 2
+        p1, i1 = _pool2(ua)
+        d1 = _relu(conv3x3(p1, W["unet.d1.w"], W["unet.d1.b"], 1))
+        p2, i2 = _pool2(d1)
+        d2 = _relu(conv3x3(p2, W["unet.d2.w"], W["unet.d2.b"], 1))
+        c1 = np.concatenate([d1, _up2(d2, h1, w1)], axis=0)
+        u1 = _relu(conv3x3(c1, W["unet.u1.w"], W["unet.u1.b"], 1))
+        c0 = np.concatenate([ua, _up2(u1, h, w)], axis=0)
+        a = _relu(conv3x3(c0, W["unet.u0.w"], W["unet.u0.b"], 1))
     maps = np.tensordot(W["head.w"], a, axes=(1, 0)) + W["head.b"][:, None, None]
     loss, gm = frame_loss(maps, truth, spec)
     G = {}
     G["head.w"] = np.tensordot(gm, a, axes=([1, 2], [1, 2]))
     G["head.b"] = gm.sum(axis=(1, 2))
     da = np.tensordot(W["head.w"], gm, axes=(0, 0))
+    if spec.unet:
+        gu0 = da * (a > 0)
+        G["unet.u0.w"] = _wgrad(gu0, c0, 1)
+        G["unet.u0.b"] = gu0.sum(axis=(1, 2))
+        gc0 = conv3x3(gu0, _flip_t(W["unet.u0.w"]), None, 1)
+        gu1 = _up2_back(gc0[C:], h1, w1) * (u1 > 0)
+        G["unet.u1.w"] = _wgrad(gu1, c1, 1)
+        G["unet.u1.b"] = gu1.sum(axis=(1, 2))
+        gc1 = conv3x3(gu1, _flip_t(W["unet.u1.w"]), None, 1)
+        gd2 = _up2_back(gc1[C:], h2, w2) * (d2 > 0)
+        G["unet.d2.w"] = _wgrad(gd2, p2, 1)
+        G["unet.d2.b"] = gd2.sum(axis=(1, 2))
+        gd1 = (gc1[:C] + _pool2_back(conv3x3(gd2, _flip_t(W["unet.d2.w"]), None, 1), i2, h1, w1)) * (d1 > 0)
+        G["unet.d1.w"] = _wgrad(gd1, p1, 1)
+        G["unet.d1.b"] = gd1.sum(axis=(1, 2))
+        da = gc0[:C] + _pool2_back(conv3x3(gd1, _flip_t(W["unet.d1.w"]), None, 1), i1, h, w)
     for k in reversed(range(len(spec.dilations))):
         d = spec.dilations[k]
         cat, t = blocks[k]

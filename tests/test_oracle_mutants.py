@@ -196,6 +196,14 @@ PY_MUTANTS = [
      "W[:, :, ::-1, ::-1].transpose(1, 0, 2, 3)",
      "W.transpose(1, 0, 2, 3)",
      [(TR.test_transposed_conv_is_the_adjoint, ())]),
+    ("upsampling gradient takes one fine pixel instead of the sum", "train._up2_back",
+     "return pad.reshape(C, h2, 2, w2, 2).sum(axis=(2, 4))",
+     "return pad.reshape(C, h2, 2, w2, 2)[:, :, 0, :, 0]",
+     [(TR.test_pooling_and_upsampling_gradients_are_adjoint, ())]),
+    ("pooling gradient sent to the window's last maximum", "train._pool2",
+     "return win.max(axis=-1), np.argmax(win, axis=-1)",
+     "return win.max(axis=-1), 3 - np.argmax(win[..., ::-1], axis=-1)",
+     [(TR.test_pooling_and_upsampling_gradients_are_adjoint, ())]),
     ("dense layer gradient without its ReLU mask", "train.dense_frame_grads",
      "gl = gc[lo:lo + Gr] * (cat[lo:lo + Gr] > 0)",
      "gl = gc[lo:lo + Gr]",

@@ -154,6 +154,79 @@ def test_dense_loss_and_gradients_match_torch_autograd():
         assert err <= 1e-9, (k, err)
 
 
+USPEC = S.DenseSpec("tu", 16, (1,), layers=2, growth=16, head_outputs=10, unet=2)
+
+
+def torch_unet_loss(frames, truths, spec, wts, gain=0.5, offset=100.0):
+    """The dense network with the two-stage U-Net, composed from torch ops:
+    max_pool2d with ceil_mode (a window at an odd edge holds what it has),
+    nearest interpolation cropped to the level, cat, conv2d."""
+    P = {k: torch.tensor(np.asarray(v, np.float64), requires_grad=True) for k, v in wts.items()}
+    total = 0.0
+    for f in range(len(frames)):
+        x = (torch.from_numpy(frames[f].astype(np.float64)) - offset) * gain * spec.in_scale
+        a = F.relu(F.conv2d(x[None, None], P["stem.w"], P["stem.b"], padding=1))
+        for k, d in enumerate(spec.dilations):
+            feats = [a]
+            for i in range(spec.layers):
+                feats.append(F.relu(F.conv2d(torch.cat(feats, dim=1), P[f"blk{k}.l{i}.w"], P[f"blk{k}.l{i}.b"],
+                                             padding=d, dilation=d)))
+            a = F.relu(F.conv2d(torch.cat(feats, dim=1), P[f"blk{k}.t.w"][:, :, None, None], P[f"blk{k}.t.b"]))
+        h, w = a.shape[2:]
+        d1 = F.relu(F.conv2d(F.max_pool2d(a, 2, ceil_mode=True), P["unet.d1.w"], P["unet.d1.b"], padding=1))
+        d2 = F.relu(F.conv2d(F.max_pool2d(d1, 2, ceil_mode=True), P["unet.d2.w"], P["unet.d2.b"], padding=1))
+        up = F.interpolate(d2, scale_factor=2, mode="nearest")[:, :, :d1.shape[2], :d1.shape[3]]
+        u1 = F.relu(F.conv2d(torch.cat([d1, up], dim=1), P["unet.u1.w"], P["unet.u1.b"], padding=1))
+        up = F.interpolate(u1, scale_factor=2, mode="nearest")[:, :, :h, :w]
+        u0 = F.relu(F.conv2d(torch.cat([a, up], dim=1), P["unet.u0.w"], P["unet.u0.b"], padding=1))
+        m = F.conv2d(u0, P["head.w"][:, :, None, None], P["head.b"])[0]
+        total = total + _torch_frame_loss(m, truths[f], spec)
+    total = total / len(frames)
+    total.backward()
+    return float(total.detach()), {k: v.grad.numpy() for k, v in P.items()}
+
+
+@pytest.mark.parametrize("h,w", [(24, 28), (23, 29)])
+def test_unet_loss_and_gradients_match_torch_autograd(h, w):
+    """Even and odd frame sizes (partial pooling windows at both levels)."""
+    frames, truths = data(h=h, w=w)
+    wts = S.he_normal_weights(USPEC, 6, bias_std=0.05)
+    wts["head.w"] = (wts["head.w"] * 0.3).astype(np.float32)
+    L, G = T.batch_grads(frames, truths, USPEC, wts)
+    Lt, Gt = torch_unet_loss(frames, truths, USPEC, wts)
+    assert set(G) == set(Gt)
+    assert abs(L["total"] - Lt) <= 1e-10 * abs(Lt)
+    for k in G:
+        ref = Gt[k]
+        err = np.linalg.norm(G[k] - ref) / (np.linalg.norm(ref) + 1e-300)
+        assert err <= 1e-9, (k, err)
+    # the training oracle's maps are the inference oracle's
+    _, _, maps = T.dense_frame_grads(frames[0], truths[0], USPEC, wts)
+    ref = oracle.net_maps(frames[0], USPEC, wts)
+    assert np.max(np.abs(maps - ref)) <= 1e-12 * (1 + np.max(np.abs(ref)))
+
+
+def test_pooling_and_upsampling_gradients_are_adjoint():
+    """<pool(a) routed by argmax> and <up(v), g> = <v, up_back(g)> identities,
+    and a tie routed to the window's first maximum."""
+    r = np.random.default_rng(4)
+    for h, w in ((6, 8), (7, 5)):
+        v = r.standard_normal((3, (h + 1) // 2, (w + 1) // 2))
+        g = r.standard_normal((3, h, w))
+        assert abs(np.sum(T._up2(v, h, w) * g) - np.sum(v * T._up2_back(g, *v.shape[1:]))) <= 1e-12
+        a = r.standard_normal((3, h, w))
+        p, idx = T._pool2(a)
+        gp = r.standard_normal(p.shape)
+        back = T._pool2_back(gp, idx, h, w)
+        # each window's gradient lands on a pixel holding the window's maximum
+        assert abs(np.sum(back * a) - np.sum(gp * p)) <= 1e-12
+        assert np.count_nonzero(back) == gp.size
+    a = np.zeros((1, 2, 2))
+    a[0, 1, 0] = a[0, 1, 1] = 5.0
+    _, idx = T._pool2(a)
+    assert T._pool2_back(np.ones((1, 1, 1)), idx, 2, 2)[0].tolist() == [[0.0, 0.0], [1.0, 0.0]]
+
+
 def test_dense_finite_differences():
     frames, truths = data(n=1, empty_last=False)
     wts = dense_weights(4)
