@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--workload", default="full", choices=["full", "tiny", "rois", "sparse", "pipeline", "train"],
                     help="full: the headline (16 x 2048^2, net B); tiny: 4 x 128^2 net A; rois: 256 uneven "
                          "ROIs, net A; sparse: gated BF16 net B on 64 x 2048^2 sparse frames; pipeline: "
-                         "host frames with H2D overlapped on a side stream; train: training steps of net AU (net DT with --net D)")
+                         "host frames with H2D overlapped on a side stream; train: training steps of net AU (DT / DUT with --net D / DU)")
     ap.add_argument("--sparse-layout", default="iid", choices=["iid", "cell"],
                     help="sparse workload: empty 256^2 tiles chosen independently (iid) or around one "
                          "compact occupied region (cell)")
@@ -87,8 +87,8 @@ def main():
                     help="full workload: net B with the 5-output head, BU, the same net with the "
                          "10-output head (per-pixel uncertainties and background), D, the "
                          "dense-connection network, or DU, D followed by the two-stage U-Net (FP32, scalar "
-                         "camera model); train workload: D trains net DT (net D with the 10-output head) instead "
-                         "of net AU")
+                         "camera model); train workload: D or DU trains net DT or DUT (D or DU with the "
+                         "10-output head) instead of net AU")
     ap.add_argument("--camera", default="scmos", choices=["scmos", "scalar"],
                     help="full and pipeline workloads: frames from a seeded sCMOS sensor whose per-pixel gain "
                          "and offset maps the net is given (scmos), or the scalar camera model (scalar)")

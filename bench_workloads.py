@@ -332,8 +332,8 @@ def train(args, S):
     n, side = 16, 128
     frames, truths = S.render_frames(n, side, side, "tiny", 1006, with_truth=True)
     truths = [S.truth_array(t, side, side) for t in truths]
-    dense = args.net == "D"
-    spec, w = S.make_net("DT", 3) if dense else S.make_net("AU", 1)
+    dense = args.net in ("D", "DU")
+    spec, w = S.make_net("DUT" if args.net == "DU" else "DT", 3) if dense else S.make_net("AU", 1)
     net = dl.Net(S.serialize_weights(spec, w))
     dev = torch.device("cuda:0")
     d = torch.from_numpy(frames).to(dev)
@@ -358,6 +358,13 @@ def train(args, S):
         per_px = sum(2 * 9 * G * (C + i * G) for i in range(L)) + 2 * C * (C + L * G)
         flop = 3.0 * per_px * px * nb
         name = "net DT (dense blocks at d=2,4,8,16, C=32, 4 layers of growth 16, 10-output head)"
+        if spec.unet:
+            # the U-Net's convolutions: u0 (2C -> C) at level 0, d1 (C -> C)
+            # and u1 (2C -> C) at level 1, d2 (C -> C) at level 2
+            h1, h2 = (side + 1) // 2, (side + 3) // 4
+            lv = [n * side * side, n * h1 * h1, n * h2 * h2]
+            flop += 3.0 * 2 * 9 * C * (2 * C * lv[0] + 3 * C * lv[1] + C * lv[2])
+            name = "net DUT (net DT followed by the two-stage U-Net)"
     else:
         # per block two forward convolutions, two transposed ones and two
         # weight gradients, each 2 9 C^2 per pixel

@@ -1143,10 +1143,12 @@ ParamOffsets param_offsets(const dl_net *net)
 }
 
 // float offsets of a dense network's tensors in blob order: stem, per block
-// the L layers' weights and biases then the transition's, the head
+// the L layers' weights and biases then the transition's, the U-Net's
+// convolutions (d1, d2, u1, u0), the head
 struct DenseOffsets {
     size_t stem_w = 0, stem_b = 0, head_w = 0, head_b = 0;
     std::vector<size_t> lw, lb, tw, tb;          // lw/lb [block L + layer]
+    size_t uw[4] = {0, 0, 0, 0}, ub[4] = {0, 0, 0, 0};
 };
 DenseOffsets dense_offsets(const dl_net *net)
 {
@@ -1163,6 +1165,11 @@ DenseOffsets dense_offsets(const dl_net *net)
         o.tw.push_back(k); k += C * CT;
         o.tb.push_back(k); k += C;
     }
+    if (net->unet)
+        for (int u = 0; u < 4; ++u) {                // d1, d2: C -> C; u1, u0: 2C -> C
+            o.uw[u] = k; k += C * (u < 2 ? C : 2 * C) * 9;
+            o.ub[u] = k; k += C;
+        }
     o.head_w = k; k += (size_t)net->nh * C;
     o.head_b = k;
     return o;
@@ -1177,6 +1184,7 @@ struct DensePackPlan {
     std::vector<PackJob> jobs;
     std::vector<int> fw, tw;                      // job index: fw [block L + layer], tw [block]
     std::vector<std::vector<int>> tr;             // [block L + layer]: the slices' job indices
+    int ufw[4] = {0, 0, 0, 0}, utr[4] = {0, 0, 0, 0};   // the U-Net's convs, forward and transposed
     int64_t total = 0;
 };
 DensePackPlan dense_pack_plan(const dl_net *net)
@@ -1211,6 +1219,12 @@ DensePackPlan dense_pack_plan(const dl_net *net)
             pl.tr.push_back(sl);
         }
     }
+    if (net->unet)
+        for (int u = 0; u < 4; ++u) {
+            const int cin = u < 2 ? C : 2 * C;
+            pl.ufw[u] = add(o.uw[u], C, cin, 9, 0, 0, C);
+            pl.utr[u] = add(o.uw[u], C, cin, 9, 1, 0, cin);
+        }
     return pl;
 }
 
@@ -1219,10 +1233,10 @@ int train_check(dl_net *net, const uint16_t *d_frames, int n, int h, int w, cons
 {
     int rc = check_uniform(net, d_frames, n, h, w);
     if (rc) return rc;
-    if (net->nh != 10 || !(net->C == 16 || net->C == 32) || (net->dL && (net->dG != 16 || net->unet)))
+    if (net->nh != 10 || !(net->C == 16 || net->C == 32) || (net->dL && net->dG != 16))
         return fail(net, DL_ERR_UNSUPPORTED,
-                    "training runs the residual or the dense network (growth 16, no U-Net) with the 10-output head "
-                    "and C = 16 or 32");
+                    "training runs the residual or the dense network (growth 16) with the 10-output head and C = 16 "
+                    "or 32");
     if (net->d_cam) return fail(net, DL_ERR_UNSUPPORTED, "training uses the scalar gain and offset (clear the camera maps)");
     if (!d_off || !d_loss || (ntruth > 0 && !d_truth) || ntruth < 0)
         return fail(net, DL_ERR_INVALID_ARG, "d_truth_off and d_loss must be given, d_truth when ntruth > 0");
@@ -1258,11 +1272,13 @@ int train_init(dl_net *net)
 }
 
 // frame descriptors and conv geometry of a uniform training batch (frame f's
-// points from f h w, its tiles per block from f times a frame's)
+// points from f h w, its tiles per block from f times a frame's); with the
+// U-Net, the level-0 convolution in tile slot nb and levels 1 and 2 with
+// descriptors of their own after the n frames' (g1, g2: their geometry)
 int train_geometry(dl_net *net, const uint16_t *d_frames, int n, int h, int w, hipStream_t s, Geometry &g,
-                   FrameDesc **d_fd)
+                   FrameDesc **d_fd, Geometry *g1 = nullptr, Geometry *g2 = nullptr)
 {
-    std::vector<FrameDesc> fd(n);
+    std::vector<FrameDesc> fd((size_t)n * desc_per_frame(net));
     g = Geometry{};
     g.nf = n;
     g.tr = dense_tile_rows();
@@ -1281,6 +1297,27 @@ int train_geometry(dl_net *net, const uint16_t *d_frames, int n, int h, int w, h
     for (int b = 0; b < net->nb; ++b) g.tiles[b] = (int64_t)n * conv_tiles(h, w, net->dil[b], g.tr, g.tc);
     g.total_rows = (int64_t)n * h;
     g.total_px = g.total_act = (int64_t)n * h * w;
+    if (net->unet) {
+        const int nb = net->nb;
+        for (int f = 0; f < n; ++f) fd[f].tile_start[nb] = (int64_t)f * conv_tiles(h, w, 1, g.tr, g.tc);
+        g.tiles[nb] = (int64_t)n * conv_tiles(h, w, 1, g.tr, g.tc);
+        int hl = h, wl = w;
+        for (int l = 1; l <= 2; ++l) {
+            hl = (hl + 1) / 2;
+            wl = (wl + 1) / 2;
+            Geometry &gl = l == 1 ? *g1 : *g2;
+            gl = g;
+            gl.tiles[0] = (int64_t)n * conv_tiles(hl, wl, 1, g.tr, g.tc);
+            for (int f = 0; f < n; ++f) {
+                FrameDesc &d = fd[(size_t)l * n + f];
+                std::memset(&d, 0, sizeof d);
+                d.h = hl;
+                d.w = wl;
+                d.act_off = (int64_t)f * hl * wl;
+                d.tile_start[0] = (int64_t)f * conv_tiles(hl, wl, 1, g.tr, g.tc);
+            }
+        }
+    }
     return upload_desc(net, fd, s, d_fd);
 }
 
@@ -1296,12 +1333,17 @@ int train_geometry(dl_net *net, const uint16_t *d_frames, int n, int h, int w, h
 int train_run_dense(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
                     const int32_t *d_off, int ntruth, hipStream_t s, float *d_grad, float *d_loss)
 {
-    const int C = net->C, L = net->dL, G = net->dG, CT = C + L * G, nb = net->nb;
+    const int C = net->C, L = net->dL, G = net->dG, CT = C + L * G, nb = net->nb, C2 = 2 * C;
     const int64_t P = (int64_t)n * h * w;
+    const int h1 = (h + 1) / 2, w1 = (w + 1) / 2, h2 = (h1 + 1) / 2, w2 = (w1 + 1) / 2;
+    const int64_t P1 = net->unet ? (int64_t)n * h1 * w1 : 0, P2 = net->unet ? (int64_t)n * h2 * w2 : 0;
     const DenseOffsets o = dense_offsets(net);
     const DensePackPlan pl = dense_pack_plan(net);
     const int nblk = (n * h + wgrad_rows_per_block(n, h) - 1) / wgrad_rows_per_block(n, h);
-    const size_t wmax = std::max((size_t)G * (C + (L - 1) * G) * 9, (size_t)C * CT);
+    // the largest weight gradient (floats per partial): a layer's, the
+    // transition's, or the U-Net's 2C -> C convolutions'
+    const size_t wmax = std::max({(size_t)G * (C + (L - 1) * G) * 9, (size_t)C * CT,
+                                  net->unet ? (size_t)C * C2 * 9 : (size_t)0});
     size_t off = 0;
     auto take = [&](size_t floats) { size_t at = off; off = align_up(off + floats * 4); return at; };
     std::vector<size_t> A(nb);
@@ -1313,6 +1355,15 @@ int train_run_dense(dl_net *net, const uint16_t *d_frames, int n, int h, int w, 
     const size_t part = take((size_t)nblk * wmax), pb = take((size_t)nblk * 32);
     const size_t tmp = take((size_t)32 * (wmax + 32) + (size_t)32 * (10 * C + 10));
     const size_t gpart = take((size_t)grad_chunks(P) * (10 * C + 10));
+    // the U-Net (level 0 points P, level 1 P1, level 2 P2): c0 = [a0, up(u1)],
+    // p1 = pool(a0), c1 = [d1, up(d2)], p2 = pool(d1), d2, u1, u0, and their
+    // gradients
+    const size_t c0 = take((size_t)P * C2 * !!net->unet), u0 = take((size_t)P * C * !!net->unet);
+    const size_t p1 = take((size_t)P1 * C), c1 = take((size_t)P1 * C2), p2 = take((size_t)P2 * C);
+    const size_t d2 = take((size_t)P2 * C), u1 = take((size_t)P1 * C);
+    const size_t gc0 = take((size_t)P * C2 * !!net->unet), gu1 = take((size_t)P1 * C), gc1 = take((size_t)P1 * C2);
+    const size_t gd2 = take((size_t)P2 * C), gp2 = take((size_t)P2 * C), gd1 = take((size_t)P1 * C);
+    const size_t gp1 = take((size_t)P1 * C);
     if (off > net->t_ws_bytes) {
         HIPCHK(net, hipDeviceSynchronize());
         if (net->t_ws) HIPCHK(net, hipFree(net->t_ws));
@@ -1323,10 +1374,11 @@ int train_run_dense(dl_net *net, const uint16_t *d_frames, int n, int h, int w, 
     }
     auto F = [&](size_t at) { return reinterpret_cast<float *>(net->t_ws + at); };
     float *prm = net->t_params, *grd = d_grad ? d_grad : net->t_grad;
-    Geometry g;
+    Geometry g, g1, g2;
     FrameDesc *d_fd = nullptr;
-    const int slot = train_geometry(net, d_frames, n, h, w, s, g, &d_fd);
+    const int slot = train_geometry(net, d_frames, n, h, w, s, g, &d_fd, &g1, &g2);
     if (slot < 0) return slot;
+    const FrameDesc *fd1 = d_fd + n, *fd2 = d_fd + 2 * (size_t)n;
     HIPCHK(net, launch_pack_jobs(net->t_jobs, net->t_njobs, net->t_jobs_total, prm, net->t_pack, s));
     auto pk = [&](int job) { return net->t_pack + pl.jobs[job].dst; };
     auto conv = [&](int b, float *in, int csi, int cin, float *out, int cso, int co, const float *wpk,
@@ -1361,22 +1413,79 @@ int train_run_dense(dl_net *net, const uint16_t *d_frames, int n, int h, int w, 
             } else {
                 a.wt = pk(pl.tw[b]);
                 a.bt = prm + o.tb[b];
-                a.tout = b + 1 < nb ? F(A[b + 1]) : F(tl);
-                a.cst = b + 1 < nb ? CT : C;
+                a.tout = b + 1 < nb ? F(A[b + 1]) : net->unet ? F(c0) : F(tl);
+                a.cst = b + 1 < nb ? CT : net->unet ? C2 : C;
                 HIPCHK(net, launch_dconv_train_fused(C / 16, a, g, net->ncu, s));
             }
         }
     }
-    HIPCHK(net, launch_train_loss(C, F(tl), prm + o.head_w, prm + o.head_b, n, h, w, d_truth, d_off, ntruth,
+    // a U-Net convolution (3x3, d = 1) at a level: fd, geometry, tile slot
+    auto uconv = [&](const FrameDesc *fd, const Geometry &gg, int blk, float *in, int csi, int cin, float *out,
+                     int cso, int nbo, const float *wpk, const float *bias, int relu) {
+        DenseConvArgs a{};
+        a.in = in;
+        a.csi = csi;
+        a.cin = cin;
+        a.out = out;
+        a.cso = cso;
+        a.w = wpk;
+        a.bias = bias;
+        a.fd = fd;
+        a.d = 1;
+        a.blk = blk;
+        a.relu = relu;
+        return launch_dconv_train(nbo, a, gg, net->ncu, s);
+    };
+    if (net->unet) {
+        const int nbc = C / 16, nbc2 = C2 / 16;
+        HIPCHK(net, launch_pool2(d_fd, fd1, n, P1, F(c0), C2, F(p1), C, C, s));
+        HIPCHK(net, uconv(fd1, g1, 0, F(p1), C, C, F(c1), C2, nbc, pk(pl.ufw[0]), prm + o.ub[0], 1));     // d1
+        HIPCHK(net, launch_pool2(fd1, fd2, n, P2, F(c1), C2, F(p2), C, C, s));
+        HIPCHK(net, uconv(fd2, g2, 0, F(p2), C, C, F(d2), C, nbc, pk(pl.ufw[1]), prm + o.ub[1], 1));       // d2
+        HIPCHK(net, launch_up2(fd2, fd1, n, P1, F(d2), C, F(c1) + C, C2, C, s));
+        HIPCHK(net, uconv(fd1, g1, 0, F(c1), C2, C2, F(u1), C, nbc, pk(pl.ufw[2]), prm + o.ub[2], 1));     // u1
+        HIPCHK(net, launch_up2(fd1, d_fd, n, P, F(u1), C, F(c0) + C, C2, C, s));
+        HIPCHK(net, uconv(d_fd, g, nb, F(c0), C2, C2, F(u0), C, nbc, pk(pl.ufw[3]), prm + o.ub[3], 1));    // u0
+        (void)nbc2;
+    }
+    float *last = net->unet ? F(u0) : F(tl);
+    HIPCHK(net, launch_train_loss(C, last, prm + o.head_w, prm + o.head_b, n, h, w, d_truth, d_off, ntruth,
                                   net->z_scale, net->ph_scale, F(maps), F(stats), F(lse), F(gm), d_loss, F(term),
                                   reinterpret_cast<uint8_t *>(net->t_ws + occ), s));
     // backward
     float *mid = F(tmp);
-    HIPCHK(net, launch_head_backward(C, F(gm), F(tl), prm + o.head_w, n, h, w, grd + o.head_w, F(gpart), mid, F(gtp),
+    HIPCHK(net, launch_head_backward(C, F(gm), last, prm + o.head_w, n, h, w, grd + o.head_w, F(gpart), mid, F(gtp),
                                      s));
+    if (net->unet) {
+        // gtp: u0's pre-activation gradient
+        const int nbc = C / 16, nbc2 = C2 / 16;
+        HIPCHK(net, launch_wgrad_ex(C, 9, F(gtp), C, F(c0), C2, C2, n, h, w, 1, F(part), F(pb), mid, grd + o.uw[3],
+                                    grd + o.ub[3], s));
+        HIPCHK(net, uconv(d_fd, g, nb, F(gtp), C, C, F(gc0), C2, nbc2, pk(pl.utr[3]), nullptr, 0));
+        HIPCHK(net, launch_up2_back(F(gc0) + C, C2, F(gu1), C, n, h, w, C, s));
+        HIPCHK(net, launch_mask_slice(F(gu1), C, 0, F(u1), C, 0, C, P1, F(gu1), C, s));
+        HIPCHK(net, launch_wgrad_ex(C, 9, F(gu1), C, F(c1), C2, C2, n, h1, w1, 1, F(part), F(pb), mid, grd + o.uw[2],
+                                    grd + o.ub[2], s));
+        HIPCHK(net, uconv(fd1, g1, 0, F(gu1), C, C, F(gc1), C2, nbc2, pk(pl.utr[2]), nullptr, 0));
+        HIPCHK(net, launch_up2_back(F(gc1) + C, C2, F(gd2), C, n, h1, w1, C, s));
+        HIPCHK(net, launch_mask_slice(F(gd2), C, 0, F(d2), C, 0, C, P2, F(gd2), C, s));
+        HIPCHK(net, launch_wgrad_ex(C, 9, F(gd2), C, F(p2), C, C, n, h2, w2, 1, F(part), F(pb), mid, grd + o.uw[1],
+                                    grd + o.ub[1], s));
+        HIPCHK(net, uconv(fd2, g2, 0, F(gd2), C, C, F(gp2), C, nbc, pk(pl.utr[1]), nullptr, 0));
+        // d1's output gradient: from u1 (gc1's first C channels) and through the pooling from d2
+        HIPCHK(net, launch_pool2_back(F(c1), C2, F(gp2), C, F(gc1), C2, n, h1, w1, C, s));
+        HIPCHK(net, launch_mask_slice(F(gc1), C2, 0, F(c1), C2, 0, C, P1, F(gd1), C, s));
+        HIPCHK(net, launch_wgrad_ex(C, 9, F(gd1), C, F(p1), C, C, n, h1, w1, 1, F(part), F(pb), mid, grd + o.uw[0],
+                                    grd + o.ub[0], s));
+        HIPCHK(net, uconv(fd1, g1, 0, F(gd1), C, C, F(gp1), C, nbc, pk(pl.utr[0]), nullptr, 0));
+        // a0's gradient: from u0 (gc0's first C channels) and through the pooling from d1
+        HIPCHK(net, launch_pool2_back(F(c0), C2, F(gp1), C, F(gc0), C2, n, h, w, C, s));
+    }
     for (int b = nb - 1; b >= 0; --b) {
         if (b + 1 < nb)   // the next block's input gradient, where this block's transition was on
             HIPCHK(net, launch_mask_slice(F(ga), CT, 0, F(A[b + 1]), CT, 0, C, P, F(gtp), C, s));
+        else if (net->unet)   // the U-Net's input gradient, where the last transition was on
+            HIPCHK(net, launch_mask_slice(F(gc0), C2, 0, F(c0), C2, 0, C, P, F(gtp), C, s));
         // the transition: weight gradient (16-row pieces when CT is not a multiple of C), input gradient
         if (CT % C == 0) {
             HIPCHK(net, launch_wgrad_ex(C, 1, F(gtp), C, F(A[b]), CT, CT, n, h, w, 1, F(part), F(pb), mid,

@@ -349,6 +349,14 @@ hipError_t launch_pack_jobs(const PackJob *jobs, int njobs, int64_t total, const
 // dst[p][c] = src[p][so + c] where m[p][mo + c] > 0, else 0 (c < nc)
 hipError_t launch_mask_slice(const float *src, int scs, int so, const float *m, int mcs, int mo, int nc, int64_t npx,
                              float *dst, int dcs, hipStream_t s);
+// U-Net gradients over n uniform frames of h x w at the fine level (coarse:
+// ceil(h/2) x ceil(w/2)): pooling -- each window's gradient g (coarse) added
+// into out (fine) at the window's first maximum of a (the pooling's input,
+// channels 0 .. C-1); upsampling -- out (coarse) = the sum of g (fine) over
+// the pixels each coarse pixel fills; points of *cs floats each
+hipError_t launch_pool2_back(const float *a, int acs, const float *g, int gcs, float *out, int ocs, int n, int h, int w,
+                             int C, hipStream_t s);
+hipError_t launch_up2_back(const float *g, int gcs, float *out, int ocs, int n, int h, int w, int C, hipStream_t s);
 // out[p][c] = sum_o Wt[o][c] g[p][o]: the 1x1 transition's input gradient (C 16
 // or 32; ct a multiple of 16)
 hipError_t launch_1x1_back(int C, const float *g, const float *Wt, int ct, int64_t npx, float *out, hipStream_t s);

@@ -26,6 +26,10 @@
 //                   MFMA: dW[co][ci][tap] = sum_p dy[p][co] x[p + off(tap)][ci]
 //   k_sum_partials  fixed-order sums of per-workgroup partials
 //   k_stem_grad_part stem weight and bias gradient partials per pixel chunk
+//   k_pack_jobs, k_mask_slice, k_1x1_back, k_pool2_back, k_up2_back: the
+//                   dense network's weight packs, ReLU masks of channel slices,
+//                   the transition's input gradient, the U-Net's pooling and
+//                   upsampling gradients
 // Reductions run in a fixed order: the gradients do not depend on timing.
 #include <algorithm>
 #include <cmath>
@@ -182,6 +186,84 @@ k_1x1_back(const float *__restrict__ g, const float *__restrict__ Wt, int ct, in
             }
         }
     }
+}
+
+// U-Net backward over a batch of n uniform frames of h x w at the fine level
+// (the coarse level is ceil(h/2) x ceil(w/2); frame f's points from f h w and
+// f h2 w2).  A thread per (coarse point, four channels).
+//
+// k_pool2_back: the 2 x 2 max pooling's gradient.  Each window's argmax is
+// taken again from the pooling's input a (points of acs floats, channels
+// 0 .. C-1): the first maximum in the window's raster order among its pixels
+// inside the frame; g (coarse, points of gcs floats) is added there into out
+// (fine, points of ocs floats).  Windows do not overlap, so no point is
+// written twice.
+__global__ void __launch_bounds__(256)
+k_pool2_back(const float *__restrict__ a, int acs, const float *__restrict__ g, int gcs, float *__restrict__ out,
+             int ocs, int n, int h, int w, int C)
+{
+    const int h2 = (h + 1) / 2, w2 = (w + 1) / 2, q4 = C / 4;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)n * h2 * w2 * q4) return;
+    const int64_t pc = i / q4;
+    const int c = (int)(i - pc * q4) * 4;
+    const int f = (int)(pc / ((int64_t)h2 * w2)), k = (int)(pc - (int64_t)f * h2 * w2);
+    const int y2 = k / w2, x2 = k - y2 * w2;
+    const int64_t base = (int64_t)f * h * w;
+    float m[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    const int64_t first = base + (int64_t)(2 * y2) * w + 2 * x2;   // inside the frame for every window
+    int64_t at[4] = {first, first, first, first};
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const int y = 2 * y2 + dy, x = 2 * x2 + dx;
+            if (y < h && x < w) {
+                const int64_t pt = base + (int64_t)y * w + x;
+                const float4 v = *reinterpret_cast<const float4 *>(a + pt * acs + c);
+                const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (vv[r] > m[r]) {
+                        m[r] = vv[r];
+                        at[r] = pt;
+                    }
+            }
+        }
+    const float4 gv = *reinterpret_cast<const float4 *>(g + pc * gcs + c);
+    const float gg[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[at[r] * ocs + c + r] += gg[r];
+}
+
+// k_up2_back: the nearest upsampling's gradient: out (coarse, points of ocs
+// floats) = the sum of g (fine, points of gcs floats) over the (up to) four
+// fine pixels each coarse pixel fills, in raster order.
+__global__ void __launch_bounds__(256)
+k_up2_back(const float *__restrict__ g, int gcs, float *__restrict__ out, int ocs, int n, int h, int w, int C)
+{
+    const int h2 = (h + 1) / 2, w2 = (w + 1) / 2, q4 = C / 4;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)n * h2 * w2 * q4) return;
+    const int64_t pc = i / q4;
+    const int c = (int)(i - pc * q4) * 4;
+    const int f = (int)(pc / ((int64_t)h2 * w2)), k = (int)(pc - (int64_t)f * h2 * w2);
+    const int y2 = k / w2, x2 = k - y2 * w2;
+    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const int y = 2 * y2 + dy, x = 2 * x2 + dx;
+            if (y < h && x < w) {
+                const float4 v = *reinterpret_cast<const float4 *>(g + ((int64_t)f * h * w + (int64_t)y * w + x) * gcs + c);
+                sum.x += v.x;
+                sum.y += v.y;
+                sum.z += v.z;
+                sum.w += v.w;
+            }
+        }
+    *reinterpret_cast<float4 *>(out + pc * ocs + c) = sum;
 }
 
 template <int C>
@@ -895,6 +977,24 @@ hipError_t launch_1x1_back(int C, const float *g, const float *Wt, int ct, int64
         hipLaunchKernelGGL(k_1x1_back<16>, dim3(grid), dim3(256), lds, s, g, Wt, ct, npx, out);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_pool2_back(const float *a, int acs, const float *g, int gcs, float *out, int ocs, int n, int h, int w,
+                             int C, hipStream_t s)
+{
+    if (C % 4) return hipErrorInvalidValue;
+    const int64_t m = (int64_t)n * ((h + 1) / 2) * ((w + 1) / 2) * (C / 4);
+    hipLaunchKernelGGL(k_pool2_back, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, acs, g, gcs, out, ocs, n, h,
+                       w, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_up2_back(const float *g, int gcs, float *out, int ocs, int n, int h, int w, int C, hipStream_t s)
+{
+    if (C % 4) return hipErrorInvalidValue;
+    const int64_t m = (int64_t)n * ((h + 1) / 2) * ((w + 1) / 2) * (C / 4);
+    hipLaunchKernelGGL(k_up2_back, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, g, gcs, out, ocs, n, h, w, C);
     return hipGetLastError();
 }
 

@@ -381,7 +381,9 @@ NET_D = DenseSpec("D", 32, (2, 4, 8, 16))
 NET_DU = DenseSpec("DU", 32, (2, 4, 8, 16), unet=2)
 # net D with the uncertainty head (the trained form of the dense network)
 NET_DT = DenseSpec("DT", 32, (2, 4, 8, 16), head_outputs=10)
-NETS = {"A": NET_A, "B": NET_B, "AU": NET_AU, "BU": NET_BU, "D": NET_D, "DU": NET_DU, "DT": NET_DT}
+# ... and net DU with it
+NET_DUT = DenseSpec("DUT", 32, (2, 4, 8, 16), head_outputs=10, unet=2)
+NETS = {"A": NET_A, "B": NET_B, "AU": NET_AU, "BU": NET_BU, "D": NET_D, "DU": NET_DU, "DT": NET_DT, "DUT": NET_DUT}
 # pixels (per axis) a two-stage U-Net's output reaches into its input: its
 # final 3x3 conv, and through pooling and nearest upsampling the level-1 and
 # level-2 convolutions

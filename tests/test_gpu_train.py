@@ -11,9 +11,11 @@ against the FP64 training oracle, through the C ABI.
   gradient; forty steps lower the loss; the inference path then runs the
   trained weights (its maps equal the oracle's on dl_get_params' weights);
 * the dense-connection network (backward through the concatenation and the
-  fused 1x1 transition): gradients against the oracle for several widths,
-  depths and dilations, net DT itself, a tall frame; an Adam step and the
-  trained weights in the inference path;
+  fused 1x1 transition) and with the two-stage U-Net (max pooling and
+  upsampling gradients, skip concatenations): gradients against the oracle
+  for several widths, depths, dilations and odd sizes, nets DT and DU with
+  the 10-output head, a tall frame; an Adam step and the trained weights in
+  the inference path;
 * refusals: nets the training kernels do not cover.
 """
 import numpy as np
@@ -139,7 +141,13 @@ def test_adam_step_matches_the_oracle_and_training_lowers_the_loss():
                                         (S.DenseSpec("td3", 32, (1, 3), layers=3, head_outputs=10), 2, 37, 45),
                                         (S.DenseSpec("td16", 16, (1, 2), layers=2, head_outputs=10), 2, 33, 70),
                                         (S.NET_DT, 1, 64, 64),
-                                        (S.DenseSpec("td2", 32, (2,), layers=2, head_outputs=10), 1, 2201, 13)])
+                                        (S.DenseSpec("td2", 32, (2,), layers=2, head_outputs=10), 1, 2201, 13),
+                                        # with the two-stage U-Net: even and odd sizes (partial pooling
+                                        # windows at both levels), C = 16, net DU with the 10-output head
+                                        (S.DenseSpec("tu", 32, (2,), layers=2, head_outputs=10, unet=2), 2, 40, 52),
+                                        (S.DenseSpec("tu", 32, (1, 2), layers=2, head_outputs=10, unet=2), 2, 37, 45),
+                                        (S.DenseSpec("tu16", 16, (2,), layers=3, head_outputs=10, unet=2), 1, 33, 70),
+                                        (S.NET_DUT, 1, 64, 64)])
 def test_dense_gradients_match_the_oracle(spec, n, h, w):
     wts, net = net_and_weights(spec, 13)
     frames, truths = batch(n, h, w, 23, empty_last=n > 1)
@@ -158,8 +166,9 @@ def test_dense_gradients_match_the_oracle(spec, n, h, w):
     assert np.array_equal(loss, loss2) and all(np.array_equal(g[k], g2[k]) for k in g)
 
 
-def test_dense_adam_step_and_the_trained_weights_in_inference():
-    spec = S.DenseSpec("td4", 32, (2, 4), head_outputs=10)
+@pytest.mark.parametrize("spec", [S.DenseSpec("td4", 32, (2, 4), head_outputs=10),
+                                  S.DenseSpec("tu", 32, (2, 4), layers=2, head_outputs=10, unet=2)])
+def test_dense_adam_step_and_the_trained_weights_in_inference(spec):
     wts, net = net_and_weights(spec, 14)
     frames, truths = batch(4, 48, 48, 24, empty_last=False)
     fr = torch.from_numpy(frames).to(DEV)
@@ -194,9 +203,8 @@ def test_nets_the_training_kernels_do_not_cover_are_refused():
         with pytest.raises(dl.DlocError) as e:
             net.train_grad(fr, tr, off)
         assert e.value.code == dl.DL_ERR_UNSUPPORTED, name
-    # dense nets with the U-Net stage or a growth other than 16
-    for spec in (S.DenseSpec("dut", 32, (2, 4), head_outputs=10, unet=2),
-                 S.DenseSpec("dg32", 32, (2,), growth=32, head_outputs=10)):
+    # a dense net with a growth other than 16
+    for spec in (S.DenseSpec("dg32", 32, (2,), growth=32, head_outputs=10),):
         net = dl.Net(S.serialize_weights(spec, S.he_normal_weights(spec, 1)))
         with pytest.raises(dl.DlocError) as e:
             net.train_grad(fr, tr, off)
