@@ -193,6 +193,36 @@ def test_dense_adam_step_and_the_trained_weights_in_inference(spec):
     assert map_rel_err(maps.cpu().numpy(), ref).max() <= TOL
 
 
+@pytest.mark.parametrize("spec", [S.NetSpec("t32", 32, (1, 2), head_outputs=10),
+                                  S.DenseSpec("td", 32, (2,), layers=2, head_outputs=10),
+                                  S.DenseSpec("tu", 16, (1,), layers=2, head_outputs=10, unet=2)])
+@pytest.mark.parametrize("n,h,w,no_emitters", [(2, 5, 3, False), (1, 7, 1, False), (3, 9, 11, True)])
+def test_tiny_frames_and_batches_without_emitters(spec, n, h, w, no_emitters):
+    """Frames narrower than one MFMA step and shorter than a conv tile (1-pixel
+    U-Net levels), and a batch whose frames hold no true emitter (the
+    localisation term vanishes)."""
+    wts, net = net_and_weights(spec, 15)
+    frames, truths = S.render_frames(n, h, w, "tiny", 25, with_truth=True)
+    truths = [S.truth_array(t, h, w) for t in truths]
+    if no_emitters:
+        truths = [t[:0] for t in truths]
+    else:                                # one planted target per frame (frames this small hold no rendered one)
+        for f in range(n):
+            t = np.zeros(1, S.TRUTH_DTYPE)
+            t["x"], t["y"], t["z_nm"], t["photons"] = 0.37 * w + 0.1 * f, 0.61 * h, 120.0 - 40 * f, 2500.0
+            truths[f] = t
+    L, G = T.batch_grads(frames, truths, spec, wts)
+    loss, g = gpu_grads(net, spec, frames, truths)
+    if no_emitters:
+        assert loss[3] == 0.0
+    for i, k in enumerate(["total", "bce", "count", "loc"]):
+        assert abs(loss[i] - L[k]) <= TOL * (abs(L[k]) + 1e-3), (k, loss[i], L[k])
+    for k in G:
+        ref = np.asarray(G[k])
+        err = np.linalg.norm(g[k] - ref) / (np.linalg.norm(ref) + 1e-30)
+        assert np.isfinite(g[k]).all() and err <= TOL, (k, err)
+
+
 def test_nets_the_training_kernels_do_not_cover_are_refused():
     fr = torch.from_numpy(S.render_frames(1, 32, 32, "tiny", 3)).to(DEV)
     tr = torch.zeros((0, 4), dtype=torch.float32, device=DEV)
