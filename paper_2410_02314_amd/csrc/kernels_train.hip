@@ -720,97 +720,118 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float *base, ui
 // (zero off the frame), db[co] = sum_p dy[p][co], for CO output channels (dy:
 // points of dcs floats) and CI input channels (x: points of xcs floats,
 // channels 0 .. CI-1), CI a multiple of CO.  Workgroup (b, cb) takes input
-// channels [cb CO, cb CO + CO); its wave v the batch rows [(8 b + v) rpw, +
-// rpw) (a frame's rows are consecutive), K = 64 / CO pixels of a row per step,
-// all taps per step.  Every operand is a buffer load: a row off the frame is
-// a buffer of no bytes and a column off the frame an offset past the buffer,
-// both of which read zero, so the loads carry no branch.  Four register sets
-// rotate: a step's loads are issued three steps ahead of its matrix
-// instructions.  The eight waves' sums are added in order through LDS, one
-// group of output rows at a time (each wave only stores its accumulators, so
-// they go to LDS without passing through vector registers), and written in
-// the weights' own order: part[b][(co CI + ci) TAPS + tap]; pb[b][co] (cb = 0).
+// channels [cb CO, cb CO + CO).
+//
+// Work unit: a column segment (sps steps of 64 / CO pixels) of a chain of K
+// output rows of one frame spaced by the dilation (y, y + d, .., y + (K-1) d;
+// K = 4 for 3x3, 1 for 1x1); chain c's segments are units c nseg .. c nseg +
+// nseg - 1, and a wave takes cpw consecutive units.  Output row j's tap row u reads input row y + (j + u - 1)
+// d, so the chain's K rows need only K + 2 input rows per step (not 3 K), and
+// all of them add into the same nine accumulators.  Per step: K dy loads, 3 (K
+// + 2) x loads, 9 K matrix instructions.  A frame's chains: blocks of K d rows
+// by residue mod d.  Every operand is a buffer load: a row off the frame is a
+// buffer of no bytes and a column off the frame an offset past the buffer,
+// both of which read zero, so the loads carry no branch; the next step's
+// loads are issued before this step's matrix instructions.  The eight waves'
+// sums are added in order through LDS, one group of output rows at a time
+// (each wave only stores its accumulators, so they go to LDS without passing
+// through vector registers), and written in the weights' own order:
+// part[b][(co CI + ci) TAPS + tap]; pb[b][co] (cb = 0).
 template <int CO, int TAPS>
 __global__ void __launch_bounds__(64 * WG_WAVES)
 k_wgrad(const float *__restrict__ dy, int dcs, const float *__restrict__ x, int xcs, int CI, int n, int h, int w,
-        int d, int rpw, float *__restrict__ part, float *__restrict__ pb)
+        int d, int nseg, int sps, int cpw, float *__restrict__ part, float *__restrict__ pb)
 {
     using M = WgMma<CO>;
     constexpr int PX = 64 / CO;
     constexpr int GR = CO / M::NG;             // output rows per group (8 or 16)
     constexpr int TSR = CO * GR + 4;           // LDS floats per (wave, tap), padded against bank conflicts
     constexpr int NU = TAPS == 9 ? 3 : 1;      // tap rows (and columns)
+    constexpr int K = TAPS == 9 ? 4 : 1;       // output rows per chain
+    constexpr int XR = K + NU - 1;             // input rows per chain
     __shared__ __align__(16) float red[WG_WAVES * TAPS * TSR];
     __shared__ float sb[WG_WAVES][CO];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ch = lane % CO, kp = lane / CO;
     const int cb = blockIdx.y, xch = cb * CO + ch;
-    const int rows = n * h;
-    const int gr0 = (blockIdx.x * WG_WAVES + wave) * rpw, gr1 = min(rows, gr0 + rpw);
+    const int de = TAPS == 9 ? d : 1;                    // row spacing within a chain
+    const int nres = min(de, h), nblk = (h + K * de - 1) / (K * de);
+    const int cpf = nblk * nres;                         // chains per frame
+    const int nun = n * cpf * nseg;                      // units
+    const int u0 = (blockIdx.x * WG_WAVES + wave) * cpw, u1 = min(nun, u0 + cpw);
     const int steps = (w + PX - 1) / PX;
     const uint32_t dbytes = (uint32_t)w * dcs * 4, xbytes = (uint32_t)w * xcs * 4;
     typename M::acc_t acc[TAPS];
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) acc[t] = typename M::acc_t{};
     float bsum = 0.f;
-    __amdgpu_buffer_rsrc_t rd, rx[NU];
-    int gr = gr0, q = 0;
-    auto set_row = [&]() {
-        const int f = gr / h, y = gr - f * h;
-        const float *fx = x + (size_t)f * h * w * xcs;
-        rd = row_rsrc(dy + ((size_t)f * h + y) * w * dcs, dbytes);
+    __amdgpu_buffer_rsrc_t rd[K], rx[XR];
+    int u = u0, q = 0, qend = 0;
+    auto set_unit = [&]() {
+        const int c = u / nseg, sg = u - c * nseg;
+        q = sg * sps;
+        qend = min(steps, q + sps);
+        const int f = c / cpf, cc = c - f * cpf;
+        const int y0 = (cc / nres) * K * de + cc % nres;
+        const float *fx = x + (size_t)f * h * w * xcs, *fd = dy + (size_t)f * h * w * dcs;
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int ys = TAPS == 9 ? y + d * (u - 1) : y;
-            const bool ok = (unsigned)ys < (unsigned)h;
-            rx[u] = row_rsrc(fx + (size_t)(ok ? ys : y) * w * xcs, ok ? xbytes : 0u);
+        for (int j = 0; j < K; ++j) {
+            const int y = y0 + j * de;
+            rd[j] = row_rsrc(fd + (size_t)(y < h ? y : 0) * w * dcs, y < h ? dbytes : 0u);
+        }
+#pragma unroll
+        for (int j = 0; j < XR; ++j) {
+            const int y = y0 + (j - (NU - 1) / 2) * de;       // input row j: output row j - 1 (3x3) or j (1x1)
+            const bool ok = (unsigned)y < (unsigned)h;
+            rx[j] = row_rsrc(fx + (size_t)(ok ? y : 0) * w * xcs, ok ? xbytes : 0u);
         }
     };
-    // loads of step (gr, q), then on to the step after it; past the last row dy
-    // becomes a buffer of no bytes, so a further step adds zeros
-    auto load_next = [&](float &a, float (&b)[TAPS]) {
+    // loads of step (u, q), then on to the step after it; past the last unit
+    // the dy rows become buffers of no bytes, so further steps add zeros
+    auto load_next = [&](float (&a)[K], float (&b)[XR][NU]) {
         const int xx = q * PX + kp;
-        a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rd, xx < w ? (xx * dcs + ch) * 4 : BUF_OOB, 0, 0));
+        const int oa = xx < w ? (xx * dcs + ch) * 4 : BUF_OOB;
+#pragma unroll
+        for (int j = 0; j < K; ++j) a[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rd[j], oa, 0, 0));
 #pragma unroll
         for (int v = 0; v < NU; ++v) {
             const int xs = TAPS == 9 ? xx + d * (v - 1) : xx;
             const int o = (unsigned)xs < (unsigned)w ? (xs * xcs + xch) * 4 : BUF_OOB;
 #pragma unroll
-            for (int u = 0; u < NU; ++u)
-                b[NU * u + v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx[u], o, 0, 0));
+            for (int j = 0; j < XR; ++j)
+                b[j][v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx[j], o, 0, 0));
         }
-        if (++q == steps) {
-            q = 0;
-            if (gr + 1 < gr1) {
-                ++gr;
-                set_row();
+        if (++q == qend) {
+            if (u + 1 < u1) {
+                ++u;
+                set_unit();
             } else {
-                rd = row_rsrc(dy, 0u);
+#pragma unroll
+                for (int j = 0; j < K; ++j) rd[j] = row_rsrc(dy, 0u);
             }
         }
     };
-    auto step = [&](float a, const float (&b)[TAPS]) {
-        bsum += a;
+    auto step = [&](const float (&a)[K], const float (&b)[XR][NU]) {
 #pragma unroll
-        for (int t = 0; t < TAPS; ++t) acc[t] = M::mma(a, b[t], acc[t]);
+        for (int j = 0; j < K; ++j) {
+            bsum += a[j];
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+#pragma unroll
+                for (int v = 0; v < NU; ++v) acc[NU * u + v] = M::mma(a[j], b[j + u][v], acc[NU * u + v]);
+        }
     };
-    if (gr0 < gr1) {
-        const int total = (gr1 - gr0) * steps;
-        set_row();
-        float a0, b0[TAPS], a1, b1[TAPS], a2, b2[TAPS], a3, b3[TAPS];
+    if (u0 < u1) {
+        const int total = (u1 - u0) * sps;           // at least the units' steps (a short last segment adds zeros)
+        set_unit();
+        float a0[K], b0[XR][NU], a1[K], b1[XR][NU];
         load_next(a0, b0);
-        load_next(a1, b1);
-        load_next(a2, b2);
-        for (int it = 0; it < total; it += 4) {   // a total not a multiple of 4 ends with steps of zeros
-            load_next(a3, b3);
+        for (int it = 0; it < total; it += 2) {   // an odd total ends with a step of zeros
+            load_next(a1, b1);
             step(a0, b0);
             load_next(a0, b0);
             step(a1, b1);
-            load_next(a1, b1);
-            step(a2, b2);
-            load_next(a2, b2);
-            step(a3, b3);
         }
     }
     // the bias: the K pixel groups of channel ch
@@ -1073,28 +1094,40 @@ hipError_t launch_head_backward(int C, const float *gm, const float *act, const 
 
 // rows per workgroup: WG_WAVES waves of rpw rows each, rpw the smallest that
 // keeps the batch within 2048 waves (two per SIMD with the 9 x 16 accumulator
-// registers of C = 32)
+// registers of C = 32); the weight gradient runs at most ceil(n h / this)
+// workgroups, which sizes its partial buffers
 int wgrad_rows_per_block(int n, int h) { return WG_WAVES * std::max(1, (n * h + 2047) / 2048); }
 
 hipError_t launch_wgrad_ex(int CO, int taps, const float *dy, int dcs, const float *x, int xcs, int CI, int n, int h,
                            int w, int d, float *part, float *pb, float *tmp, float *gW, float *gb, hipStream_t s)
 {
-    if (!(CO == 16 || CO == 32) || !(taps == 1 || taps == 9) || CI < CO || CI % CO) return hipErrorInvalidValue;
+    if (!(CO == 16 || CO == 32) || !(taps == 1 || taps == 9) || CI < CO || CI % CO || d < 1) return hipErrorInvalidValue;
+    // the kernel's chains (see k_wgrad); their waves are spread over at most
+    // the workgroups the partial buffer was sized for
+    const int K = taps == 9 ? 4 : 1, de = taps == 9 ? d : 1;
+    const int64_t nch = (int64_t)n * ((h + K * de - 1) / (K * de)) * std::min(de, h);
+    // column segments: enough units for about 2048 waves
+    const int steps = (w + 64 / CO - 1) / (64 / CO);
+    int nseg = (int)std::min<int64_t>(steps, std::max<int64_t>(1, (2048 + nch - 1) / nch));
+    const int sps = (steps + nseg - 1) / nseg;
+    nseg = (steps + sps - 1) / sps;
+    const int64_t nun = nch * nseg;
     const int R = wgrad_rows_per_block(n, h);
-    const dim3 grid((n * h + R - 1) / R, CI / CO);
-    const int rpw = R / WG_WAVES;
+    const int64_t nblk_max = ((int64_t)n * h + R - 1) / R;
+    const int cpw = (int)std::max<int64_t>({1, (nun + 2047) / 2048, (nun + WG_WAVES * nblk_max - 1) / (WG_WAVES * nblk_max)});
+    const dim3 grid((unsigned)((nun + (int64_t)WG_WAVES * cpw - 1) / ((int64_t)WG_WAVES * cpw)), CI / CO);
     if (CO == 32 && taps == 9)
-        hipLaunchKernelGGL((k_wgrad<32, 9>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, rpw,
-                           part, pb);
+        hipLaunchKernelGGL((k_wgrad<32, 9>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, nseg,
+                           sps, cpw, part, pb);
     else if (CO == 32)
-        hipLaunchKernelGGL((k_wgrad<32, 1>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, rpw,
-                           part, pb);
+        hipLaunchKernelGGL((k_wgrad<32, 1>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, nseg,
+                           sps, cpw, part, pb);
     else if (taps == 9)
-        hipLaunchKernelGGL((k_wgrad<16, 9>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, rpw,
-                           part, pb);
+        hipLaunchKernelGGL((k_wgrad<16, 9>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, nseg,
+                           sps, cpw, part, pb);
     else
-        hipLaunchKernelGGL((k_wgrad<16, 1>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, rpw,
-                           part, pb);
+        hipLaunchKernelGGL((k_wgrad<16, 1>), grid, dim3(64 * WG_WAVES), 0, s, dy, dcs, x, xcs, CI, n, h, w, d, nseg,
+                           sps, cpw, part, pb);
     reduce_partials(part, CO * CI * taps, gW, pb, CO, gb, (int)grid.x, tmp, s);
     return hipGetLastError();
 }
