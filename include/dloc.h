@@ -496,8 +496,11 @@ typedef struct {
 } dl_truth;
 
 /* Loss and gradient of one batch at the handle's current weights, on the
- * device, queued on `stream`.  The network must be a residual (DLW1) net with
- * the 10-output head and C = 16 or 32; FP32; scalar gain and offset.
+ * device, queued on `stream`.  The network must have the 10-output head and
+ * C = 16 or 32: a residual (DLW1) net, or a dense-connection (DLD1) net of
+ * growth 16 with or without the two-stage U-Net (the max pooling's gradient
+ * goes to each window's first maximum in raster order); FP32; scalar gain and
+ * offset.
  *   d_frames     device uint16 [n][h][w]
  *   d_truth      device dl_truth[], the frames' true emitters, frame by frame,
  *                each inside its frame

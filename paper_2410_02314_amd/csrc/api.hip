@@ -1553,28 +1553,9 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
     }
     auto F = [&](size_t at) { return reinterpret_cast<float *>(net->t_ws + at); };
     float *prm = net->t_params, *grd = d_grad ? d_grad : net->t_grad;
-    // descriptors: frame f's points from f h w, its tiles per block from f times a frame's
-    std::vector<FrameDesc> fd(n);
     Geometry g;
-    g.nf = n;
-    g.tr = dense_tile_rows();
-    g.tc = dense_tile_cols();
-    for (int f = 0; f < n; ++f) {
-        FrameDesc &d = fd[f];
-        std::memset(&d, 0, sizeof d);
-        d.data = d_frames + (size_t)f * h * w;
-        d.stride = w;
-        d.h = h;
-        d.w = w;
-        d.px_off = d.act_off = (int64_t)f * h * w;
-        d.row_start = (int64_t)f * h;
-        for (int b = 0; b < nb; ++b) d.tile_start[b] = (int64_t)f * conv_tiles(h, w, net->dil[b], g.tr, g.tc);
-    }
-    for (int b = 0; b < nb; ++b) g.tiles[b] = (int64_t)n * conv_tiles(h, w, net->dil[b], g.tr, g.tc);
-    g.total_rows = (int64_t)n * h;
-    g.total_px = g.total_act = P;
     FrameDesc *d_fd = nullptr;
-    const int slot = upload_desc(net, fd, s, &d_fd);
+    const int slot = train_geometry(net, d_frames, n, h, w, s, g, &d_fd);
     if (slot < 0) return slot;
     // packed conv weights: [block][conv 1, 2][forward, transposed]
     auto pk = [&](int b, int k, int tr) { return net->t_pack + ((size_t)(b * 2 + k) * 2 + tr) * C * C * 9; };
