@@ -322,6 +322,53 @@ def pipeline(args, S):
            "emitters": out[1][1]})
 
 
+def truth_records(truths):
+    """Ground-truth emitters of a list of frames as records (frame, x, y, z)."""
+    rows = [(f, t["x"], t["y"], t["z_nm"]) for f, ts in enumerate(truths) for t in ts]
+    return np.array(rows, dtype=[("frame", "<i4"), ("x", "<f8"), ("y", "<f8"), ("z", "<f8")])
+
+
+def train_eval(S, spec, w, steps=500, lr=1e-3, nb=16, npool=64, side=128):
+    """What training does to localisation: the net from its initial weights is
+    trained for ``steps`` Adam steps on a pool of ``npool`` synthetic frames
+    (seed 3001, batches of ``nb`` in turn), and its emitter lists on 8
+    held-out frames (seed 3002) are matched to their ground truth within 1 px,
+    before and after."""
+    import torch
+    import paper_2410_02314_amd as dl
+    from tests.parity import match_by_distance
+    fr, tr = S.render_frames(npool, side, side, "tiny", 3001, with_truth=True)
+    tr = [S.truth_array(t, side, side) for t in tr]
+    ef, et = S.render_frames(8, side, side, "tiny", 3002, with_truth=True)
+    ref = truth_records([S.truth_array(t, side, side) for t in et])
+    net = dl.Net(S.serialize_weights(spec, w))
+    dev = torch.device("cuda:0")
+    batches = []
+    for b in range(npool // nb):
+        sl = slice(b * nb, (b + 1) * nb)
+        off = np.zeros(nb + 1, np.int32)
+        rows = []
+        for f, t in enumerate(tr[sl]):
+            off[f + 1] = off[f] + len(t)
+            rows += [[r["x"], r["y"], r["z_nm"], r["photons"]] for r in t]
+        batches.append((torch.from_numpy(fr[sl]).to(dev),
+                        torch.from_numpy(np.asarray(rows, np.float32).reshape(-1, 4)).to(dev),
+                        torch.from_numpy(off).to(dev)))
+
+    def score():
+        m = match_by_distance(net.localize(ef), ref, 1.0)
+        return {"recall": round(m["recall"], 4), "precision": round(m["precision"], 4),
+                "rms_xy_px": round(math.hypot(m["rms_dx_px"], m["rms_dy_px"]) / math.sqrt(2), 4)}
+    before = score()
+    loss = torch.zeros(4, dtype=torch.float32, device=dev)
+    for s in range(steps):
+        d, t, o = batches[s % len(batches)]
+        net.train_step(d, t, o, lr, loss)
+    after = score()
+    return {"steps": steps, "lr": lr, "pool_frames": npool, "eval_frames": 8, "match_radius_px": 1.0,
+            "true_emitters": len(ref), "loss_after": round(float(loss.cpu()[0]), 3), "before": before, "after": after}
+
+
 def train(args, S):
     """Training steps on 16 frames of 128 x 128 with their true emitters: the
     10-output residual net (net AU: C = 32, d = 1, 2, 4), or with --net D the
@@ -377,7 +424,7 @@ def train(args, S):
            "precision": "fp32", "frames": n, "height": side, "width": side},
           {"frames_per_s": round(n / (ms * 1e-3), 1), "emitters_per_batch": int(off[-1]),
            "loss_first_step": round(first, 4), "loss_after": round(last, 4), "steps_timed": args.steps,
-           "conv_tflop_per_step": round(flop / 1e12, 4),
+           "conv_tflop_per_step": round(flop / 1e12, 4), "trained_eval": train_eval(S, spec, w),
            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAKS["fp32"], "unit": "TFLOP/s",
                         "frac": round(tflops / PEAKS["fp32"], 4), "traffic": None,
                         "kernel": "whole training step (convolution FLOP over the step time)"}})

@@ -110,12 +110,20 @@ typedef struct {
     float x_px, y_px, z_nm, photons, prob;
 } dl_emitter;
 
+/* The least standard deviation the uncertainty planes express, in the units
+ * of the head (px; z_scale; ph_scale): sigma = softplus(u) + DL_SIGMA_FLOOR.
+ * The training loss's pixel mixture has no bounded likelihood without it (a
+ * target dimension that never varies, such as z in 2D data, lets sigma go to
+ * zero). */
+#define DL_SIGMA_FLOOR 0.01f
+
 /* Uncertainties of one emitter, 20 bytes, from a network with the 10-output
  * head (Sec. 3.2: each pixel also gives the uncertainty of the position).
- * With u the raw head value and softplus(u) = log(1 + e^u) > 0:
- * sigma_x_px = softplus(u5), sigma_y_px = softplus(u6), sigma_z_nm =
- * softplus(u7) * z_scale, sigma_photons = softplus(u8) * ph_scale,
- * background = softplus(u9) / in_scale (photons per pixel). */
+ * With u the raw head value, softplus(u) = log(1 + e^u) > 0 and s(u) =
+ * softplus(u) + DL_SIGMA_FLOOR:
+ * sigma_x_px = s(u5), sigma_y_px = s(u6), sigma_z_nm = s(u7) * z_scale,
+ * sigma_photons = s(u8) * ph_scale, background = softplus(u9) / in_scale
+ * (photons per pixel). */
 typedef struct {
     float sigma_x_px, sigma_y_px, sigma_z_nm, sigma_photons, background;
 } dl_uncertainty;

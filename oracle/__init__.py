@@ -317,16 +317,28 @@ def softplus(u):
     return np.maximum(u, 0.0) + np.log1p(np.exp(-np.abs(u)))
 
 
+# The least standard deviation the uncertainty planes express (units of the
+# head: px, z_scale, ph_scale).  Without it the training loss's pixel mixture
+# has no bounded likelihood: a target dimension that never varies (z in 2D
+# data) lets sigma go to zero.
+SIGMA_FLOOR = 0.01
+
+
+def sigma_of(u):
+    """A standard deviation from its raw plane: softplus(u) + SIGMA_FLOOR."""
+    return softplus(u) + SIGMA_FLOOR
+
+
 def uncertainties(maps: np.ndarray, det: np.ndarray, spec) -> np.ndarray:
     """Uncertainties of one frame's detections (raster order) from a 10-plane
-    map: each is softplus of its raw plane (positive by construction) times its
+    map: each sigma is sigma_of(raw plane) (positive by construction) times its
     unit -- sigma_x, sigma_y in px, sigma_z * z_scale (nm), sigma_photons *
-    ph_scale, background / in_scale (photons per pixel, the units the input
-    scaling divides out)."""
+    ph_scale; the background is softplus(raw) / in_scale (photons per pixel,
+    the units the input scaling divides out)."""
     assert maps.shape[0] == 10, "the uncertainty head has 10 planes"
     rows, cols = np.nonzero(det)
     out = np.empty(rows.size, UNCERTAINTY_DTYPE)
-    sp = [softplus(maps[5 + q, rows, cols]) for q in range(5)]
+    sp = [sigma_of(maps[5 + q, rows, cols]) for q in range(4)] + [softplus(maps[9, rows, cols])]
     out["sigma_x"] = sp[0]
     out["sigma_y"] = sp[1]
     out["sigma_z"] = sp[2] * spec.z_scale
@@ -337,11 +349,11 @@ def uncertainties(maps: np.ndarray, det: np.ndarray, spec) -> np.ndarray:
 
 def sigma_filter(maps: np.ndarray, det: np.ndarray, max_sigma_px: float) -> np.ndarray:
     """Uncertainty-aware post-processing of a 10-plane map: a detection is kept
-    only if sigma_x = softplus(plane 5) and sigma_y = softplus(plane 6) are both
+    only if sigma_x = sigma_of(plane 5) and sigma_y = sigma_of(plane 6) are both
     <= max_sigma_px.  Applied after the local-maximum test, so a dropped
     maximum does not promote a neighbour."""
     assert maps.shape[0] == 10, "the uncertainty filter needs the 10-output head"
-    return det & (softplus(maps[5]) <= max_sigma_px) & (softplus(maps[6]) <= max_sigma_px)
+    return det & (sigma_of(maps[5]) <= max_sigma_px) & (sigma_of(maps[6]) <= max_sigma_px)
 
 
 def localize(frames: np.ndarray, spec, weights, gain=0.5, offset=100.0, threshold=0.3,

@@ -14,7 +14,7 @@ u_x, u_y, u_z, u_N, background) and its true emitters e = 1 .. E:
   L_bce   = (1/P) sum_k [softplus(l_k) - y_k l_k]                 (BCE on l)
   mu = sum_k p_k,  v = sum_k p_k (1 - p_k) + 1e-4
   L_count = log(2 pi v) / 2 + (E - mu)^2 / (2 v)       (Gaussian count model)
-  m_k = (col + 0.5 + dx, row + 0.5 + dy, dz, ph),  s_kd = softplus(u_kd)
+  m_k = (col + 0.5 + dx, row + 0.5 + dy, dz, ph),  s_kd = softplus(u_kd) + 0.01
   q_ek = log p_k - log mu + sum_d log N(t_ed; m_kd, s_kd^2)
   L_loc   = -sum_e logsumexp_k q_ek        (mixture over pixels, weights p/mu)
   L_frame = L_bce + L_count + L_loc;  the batch loss is the mean over frames.
@@ -33,7 +33,7 @@ from typing import Dict, List, Tuple
 
 import numpy as np
 
-from . import conv3x3, preprocess, softplus
+from . import conv3x3, preprocess, sigma_of, softplus
 
 VAR_EPS = 1e-4
 
@@ -82,7 +82,7 @@ def frame_loss(maps: np.ndarray, truth, spec) -> Tuple[Dict[str, float], np.ndar
     if E:
         rows, cols = np.mgrid[0:h, 0:w].astype(np.float64)
         mean = [cols + 0.5 + maps[1], rows + 0.5 + maps[2], maps[3], maps[4]]
-        s = [softplus(maps[5 + d]) for d in range(4)]
+        s = [sigma_of(maps[5 + d]) for d in range(4)]
         logw = _log_sig(l) - math.log(mu)
         for t in truth:
             tv = [t["x"], t["y"], t["z_nm"] / spec.z_scale, t["photons"] / spec.ph_scale]

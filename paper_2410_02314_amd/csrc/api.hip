@@ -857,13 +857,16 @@ int run_net(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p
 }
 
 // The uncertainty filter as a bound on the raw sigma planes: sigma =
-// softplus(u) <= s iff u <= log(e^s - 1) (softplus is increasing); +inf when
-// the filter is off or the net has no uncertainty planes.
+// softplus(u) + DL_SIGMA_FLOOR <= s iff u <= log(e^(s - floor) - 1)
+// (softplus is increasing); -inf when s is at or below the floor (no sigma
+// passes), +inf when the filter is off or the net has no uncertainty planes.
 float sigma_limit_raw(const dl_net *net)
 {
     const double s = net->cfg.max_sigma_px;
     if (net->nh != 10 || !(s > 0.0)) return INFINITY;
-    return (float)(s > 30.0 ? s : std::log(std::expm1(s)));
+    const double r = s - (double)DL_SIGMA_FLOOR;
+    if (!(r > 0.0)) return -INFINITY;
+    return (float)(r > 30.0 ? r : std::log(std::expm1(r)));
 }
 
 int run_post(dl_net *net, const FrameDesc *d_fd, const Geometry &g, const Plan &p, const float *maps,

@@ -160,7 +160,7 @@ hipError_t stem_c(const FrameDesc *fd, const Geometry &g, const float *w, const 
 // one detection.  With the uncertainty planes and a finite u_max, a local
 // maximum whose raw sigma_x or sigma_y exceeds u_max is dropped (its
 // neighbours are not promoted): softplus is increasing, so this is
-// sigma <= softplus(u_max) without evaluating softplus.
+// sigma <= softplus(u_max) + DL_SIGMA_FLOOR without evaluating softplus.
 //
 // A workgroup (4 waves) takes a band of DBAND rows of one frame.  A wave
 // works on chunks of 256 columns (chunk k of the band goes to wave k mod 4),
@@ -385,10 +385,10 @@ k_emit(const float *__restrict__ maps, int planes, const uint64_t *__restrict__ 
                     // softplus(u) = max(u, 0) + log1p(exp(-|u|)): positive, no overflow
                     auto sp = [](float u) { return fmaxf(u, 0.f) + log1pf(expf(-fabsf(u))); };
                     dl_uncertainty q;
-                    q.sigma_x_px = sp(M[5 * plane + x]);
-                    q.sigma_y_px = sp(M[6 * plane + x]);
-                    q.sigma_z_nm = sp(M[7 * plane + x]) * z_scale;
-                    q.sigma_photons = sp(M[8 * plane + x]) * ph_scale;
+                    q.sigma_x_px = sp(M[5 * plane + x]) + DL_SIGMA_FLOOR;
+                    q.sigma_y_px = sp(M[6 * plane + x]) + DL_SIGMA_FLOOR;
+                    q.sigma_z_nm = (sp(M[7 * plane + x]) + DL_SIGMA_FLOOR) * z_scale;
+                    q.sigma_photons = (sp(M[8 * plane + x]) + DL_SIGMA_FLOOR) * ph_scale;
                     q.background = sp(M[9 * plane + x]) * bg_scale;
                     unc[idx] = q;
                 }

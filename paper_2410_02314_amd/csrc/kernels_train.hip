@@ -318,7 +318,8 @@ __global__ void __launch_bounds__(256) k_zero_u8(uint8_t *__restrict__ p, int64_
 
 // Per pixel, what the mixture terms need, planar over the batch's pixels:
 // term[0] = log p - sum_d log s_d - 2 log(2 pi), term[1 + d] = m_d,
-// term[5 + d] = 1 / s_d (d = x, y, z, N in the units of the targets)
+// term[5 + d] = 1 / s_d (d = x, y, z, N in the units of the targets; s_d =
+// softplus(u_d) + DL_SIGMA_FLOOR)
 __global__ void __launch_bounds__(256)
 k_pix_terms(const float *__restrict__ maps, int n, int h, int w, float *__restrict__ term)
 {
@@ -335,7 +336,7 @@ k_pix_terms(const float *__restrict__ maps, int n, int h, int w, float *__restri
     term[4 * np + i] = M[4 * P + k];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        const float sd = softplusf(M[(5 + d) * P + k]);
+        const float sd = softplusf(M[(5 + d) * P + k]) + DL_SIGMA_FLOOR;
         c -= logf(sd);
         term[(5 + d) * np + i] = 1.f / sd;
     }

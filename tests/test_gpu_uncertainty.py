@@ -78,7 +78,8 @@ def test_fp32_maps_records_and_uncertainties_match_oracle(name, h, w):
     # each record's uncertainties from the GPU's own raw planes, in their units
     raw = got[rec["frame"], 5:, rec["row"], rec["col"]]          # [k][5]
     unit = np.array([1.0, 1.0, spec.z_scale, spec.ph_scale, 1.0 / spec.in_scale])
-    expect = softplus64(raw) * unit
+    floor = np.array([oracle.SIGMA_FLOOR] * 4 + [0.0])          # the sigmas' floor; none on the background
+    expect = (softplus64(raw) + floor) * unit
     gotu = np.stack([unc[f] for f in unc.dtype.names], axis=1).astype(np.float64)
     assert np.all(gotu > 0)
     assert np.allclose(gotu, expect, rtol=1e-6, atol=0)

@@ -173,8 +173,8 @@ PY_MUTANTS = [
      "sp[4] * spec.in_scale",
      [(UNC.test_uncertainty_units_at_zero_raw_value, ())]),
     ("sigma filter reads the z plane", "sigma_filter",
-     "(softplus(maps[6]) <= max_sigma_px)",
-     "(softplus(maps[7]) <= max_sigma_px)",
+     "(sigma_of(maps[6]) <= max_sigma_px)",
+     "(sigma_of(maps[7]) <= max_sigma_px)",
      [(UNC.test_sigma_filter_invariants, ())]),
     ("threshold turned into a logit with the wrong odds", "localize",
      "math.log(threshold / (1.0 - threshold))",

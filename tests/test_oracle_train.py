@@ -71,7 +71,7 @@ def torch_loss(frames, truths, spec, wts, gain=0.5, offset=100.0):
         rows, cols = torch.meshgrid(torch.arange(h, dtype=torch.float64), torch.arange(w, dtype=torch.float64),
                                     indexing="ij")
         mean = [cols + 0.5 + m[1], rows + 0.5 + m[2], m[3], m[4]]
-        sd = [F.softplus(m[5 + d]) for d in range(4)]
+        sd = [F.softplus(m[5 + d]) + 0.01 for d in range(4)]
         for t in truths[f]:
             tv = [t["x"], t["y"], t["z_nm"] / spec.z_scale, t["photons"] / spec.ph_scale]
             q = F.logsigmoid(l) - torch.log(mu)
@@ -130,7 +130,7 @@ def _torch_frame_loss(m, truth, spec):
     rows, cols = torch.meshgrid(torch.arange(h, dtype=torch.float64), torch.arange(w, dtype=torch.float64),
                                 indexing="ij")
     mean = [cols + 0.5 + m[1], rows + 0.5 + m[2], m[3], m[4]]
-    sd = [F.softplus(m[5 + d]) for d in range(4)]
+    sd = [F.softplus(m[5 + d]) + 0.01 for d in range(4)]
     for t in truth:
         tv = [t["x"], t["y"], t["z_nm"] / spec.z_scale, t["photons"] / spec.ph_scale]
         q = F.logsigmoid(l) - torch.log(mu)
@@ -312,7 +312,7 @@ def test_localisation_term_with_one_dominant_pixel():
     L, _ = T.frame_loss(maps, truth, SPEC)
     t = [3.7, 2.1, 140.0 / SPEC.z_scale, 2500.0 / SPEC.ph_scale]
     m = [3 + 0.5 + 0.1, 2 + 0.5 - 0.2, 0.3, 2.0]
-    s = oracle.softplus(np.array([0.2, -0.1, 0.5, 1.0]))
+    s = oracle.softplus(np.array([0.2, -0.1, 0.5, 1.0])) + 0.01
     nll = sum(0.5 * math.log(2 * math.pi) + math.log(s[d]) + (t[d] - m[d]) ** 2 / (2 * s[d] ** 2) for d in range(4))
     assert abs(L["loc"] - nll) <= 1e-9
 

@@ -70,10 +70,11 @@ def test_uncertainty_units_at_zero_raw_value():
     det[1, 2] = det[3, 0] = True
     u = oracle.uncertainties(maps, det, spec)
     ln2 = math.log(2.0)
+    s0 = ln2 + 0.01                      # a sigma at raw 0: softplus(0) plus the 0.01-unit floor
     assert len(u) == 2
-    assert np.allclose(u["sigma_x"], ln2) and np.allclose(u["sigma_y"], ln2)
-    assert np.allclose(u["sigma_z"], ln2 * spec.z_scale)
-    assert np.allclose(u["sigma_photons"], ln2 * spec.ph_scale)
+    assert np.allclose(u["sigma_x"], s0) and np.allclose(u["sigma_y"], s0)
+    assert np.allclose(u["sigma_z"], s0 * spec.z_scale)
+    assert np.allclose(u["sigma_photons"], s0 * spec.ph_scale)
     assert np.allclose(u["background"], ln2 / spec.in_scale)
 
 
@@ -84,7 +85,7 @@ def test_localize_returns_matching_uncertainties():
     assert len(rec) == len(unc) > 0
     for r, q in zip(rec[:20], unc[:20]):
         raw = maps[r["frame"], 5:, r["row"], r["col"]]
-        assert q["sigma_x"] == oracle.softplus(raw[0])
+        assert q["sigma_x"] == oracle.softplus(raw[0]) + 0.01
         assert q["background"] == oracle.softplus(raw[4]) / spec.in_scale
     # the 5-output net's records are those of the 10-output net
     s5, w5 = S.make_net("A", 1)
