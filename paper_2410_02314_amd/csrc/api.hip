@@ -413,6 +413,24 @@ Plan make_plan(const dl_net *net, const Geometry &g, bool ext_maps)
     return p;
 }
 
+// Release a library buffer and clear its pointer whatever the release
+// returns: an error here (a call may report an earlier asynchronous failure)
+// must never leave a pointer that a later release would free again.
+template <class T>
+hipError_t free_dev(T *&p)
+{
+    const hipError_t e = p ? hipFree(p) : hipSuccess;
+    p = nullptr;
+    return e;
+}
+template <class T>
+hipError_t free_host(T *&p)
+{
+    const hipError_t e = p ? hipHostFree(p) : hipSuccess;
+    p = nullptr;
+    return e;
+}
+
 // A run on stream s that uses the handle's workspace is ordered after the
 // previous such run: when that one was queued on another stream, s waits
 // for it on the device (no host synchronisation).  Skipped while s is being
@@ -448,10 +466,10 @@ int ensure_workspace(dl_net *net, size_t bytes, hipStream_t s)
     if (net->ws) {
         HIPCHK(net, hipStreamSynchronize(s));
         HIPCHK(net, hipDeviceSynchronize());
-        HIPCHK(net, hipFree(net->ws));
-        net->ws = nullptr;
+        const hipError_t e = free_dev(net->ws);
         net->ws_bytes = 0;
         net->last_gate_tiles = 0;           // the keep map lived in the old workspace
+        HIPCHK(net, e);
     }
     hipError_t e = hipMalloc(&net->ws, bytes);
     if (e != hipSuccess) {
@@ -470,11 +488,10 @@ int grow_desc(dl_net *net, int n)
     if (n <= net->desc_cap) return DL_OK;
     for (int i = 0; i < DESC_SLOTS; ++i)
         if (net->desc_ev[i]) HIPCHK(net, hipEventSynchronize(net->desc_ev[i]));
-    if (net->h_desc) HIPCHK(net, hipHostFree(net->h_desc));
-    if (net->d_desc) HIPCHK(net, hipFree(net->d_desc));
-    net->h_desc = nullptr;
-    net->d_desc = nullptr;
+    const hipError_t eh = free_host(net->h_desc), ed = free_dev(net->d_desc);
     net->desc_cap = 0;
+    HIPCHK(net, eh);
+    HIPCHK(net, ed);
     int cap = DL_NOALLOC_MAX_FRAMES;
     while (cap < n) cap *= 2;
     HIPCHK(net, hipHostMalloc((void **)&net->h_desc, sizeof(FrameDesc) * cap * DESC_SLOTS, hipHostMallocDefault));
@@ -574,10 +591,10 @@ int pack_dense(dl_net *net)
     net->dense_head_w = (host.size() + 63) / 64 * 64;
     host.resize(net->dense_head_w + head16.size());
     pack_dense_weights(16, C, 1, head16.data(), host.data() + net->dense_head_w);
+    net->packed_precision = -1;     // not packed until the new buffer holds the weights
     if (net->d_dense) {             // a repack (trained weights): kernels still queued may read the old buffer
         HIPCHK(net, hipDeviceSynchronize());
-        HIPCHK(net, hipFree(net->d_dense));
-        net->d_dense = nullptr;
+        HIPCHK(net, free_dev(net->d_dense));
     }
     HIPCHK(net, hipMalloc(&net->d_dense, host.size() * sizeof(float)));
     HIPCHK(net, hipMemcpy(net->d_dense, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -607,10 +624,7 @@ int ensure_packed(dl_net *net)
     HIPCHK(net, hipDeviceSynchronize());
     if (!net->d_wscale) HIPCHK(net, hipMalloc(&net->d_wscale, wscale.size() * sizeof(float)));
     HIPCHK(net, hipMemcpy(net->d_wscale, wscale.data(), wscale.size() * sizeof(float), hipMemcpyHostToDevice));
-    if (net->d_wpk) {
-        HIPCHK(net, hipFree(net->d_wpk));
-        net->d_wpk = nullptr;
-    }
+    HIPCHK(net, free_dev(net->d_wpk));
     HIPCHK(net, hipMalloc(&net->d_wpk, host.size()));
     HIPCHK(net, hipMemcpy(net->d_wpk, host.data(), host.size(), hipMemcpyHostToDevice));
     net->wpk_stride = stride;
@@ -998,6 +1012,7 @@ int scratch_init(dl_net *net)
 // graph points at), the kernel sequence as a hipGraphExec.
 struct dl_graph {
     dl_net *net = nullptr;
+    int dev = 0;                    // the net's device (destroying the graph does not touch the net)
     char *ws = nullptr;
     FrameDesc *d_fd = nullptr;
     hipGraph_t graph = nullptr;
@@ -1031,6 +1046,7 @@ int graph_build(dl_net *net, const std::vector<FrameDesc> &fd, const Geometry &g
     if (!gr) return fail(net, DL_ERR_OOM, "out of host memory");
     if (dyn_proto) *gr = *dyn_proto;        // capacity fields of a dynamic ROI graph
     gr->net = net;
+    gr->dev = net->dev;
     gr->cam_gen = net->cam_gen;
     gr->packed_gen = net->packed_gen;       // ensure_packed ran above
     auto bail = [&](int code) {
@@ -1369,9 +1385,9 @@ int train_run_dense(dl_net *net, const uint16_t *d_frames, int n, int h, int w, 
     const size_t gp1 = take((size_t)P1 * C);
     if (off > net->t_ws_bytes) {
         HIPCHK(net, hipDeviceSynchronize());
-        if (net->t_ws) HIPCHK(net, hipFree(net->t_ws));
-        net->t_ws = nullptr;
+        const hipError_t e = free_dev(net->t_ws);
         net->t_ws_bytes = 0;
+        HIPCHK(net, e);
         if (hipMalloc(&net->t_ws, off) != hipSuccess) return fail(net, DL_ERR_OOM, "training buffers of %zu bytes", off);
         net->t_ws_bytes = off;
     }
@@ -1548,9 +1564,9 @@ int train_run(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const 
     const size_t gpart = take((size_t)grad_chunks(P) * (10 * C + 10));
     if (off > net->t_ws_bytes) {
         HIPCHK(net, hipDeviceSynchronize());
-        if (net->t_ws) HIPCHK(net, hipFree(net->t_ws));
-        net->t_ws = nullptr;
+        const hipError_t e = free_dev(net->t_ws);
         net->t_ws_bytes = 0;
+        HIPCHK(net, e);
         if (hipMalloc(&net->t_ws, off) != hipSuccess) return fail(net, DL_ERR_OOM, "training buffers of %zu bytes", off);
         net->t_ws_bytes = off;
     }
@@ -2217,11 +2233,8 @@ static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_c
         }
     }
     if (fbytes > net->pl_frame_bytes) {
-        for (auto &p : net->pl_frames) {
-            if (p) HIPCHK(net, hipFree(p));
-            p = nullptr;
-        }
         net->pl_frame_bytes = 0;
+        for (auto &p : net->pl_frames) HIPCHK(net, free_dev(p));
         for (auto &p : net->pl_frames)
             if (hipMalloc(&p, fbytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -2230,11 +2243,8 @@ static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_c
         net->pl_frame_bytes = fbytes;
     }
     if (staged && fbytes > net->pl_stage_bytes) {
-        for (auto &p : net->pl_stage) {
-            if (p) HIPCHK(net, hipHostFree(p));
-            p = nullptr;
-        }
         net->pl_stage_bytes = 0;
+        for (auto &p : net->pl_stage) HIPCHK(net, free_host(p));
         for (auto &p : net->pl_stage)
             if (hipHostMalloc((void **)&p, fbytes, hipHostMallocDefault) != hipSuccess) {
                 (void)hipGetLastError();
@@ -2243,11 +2253,8 @@ static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_c
         net->pl_stage_bytes = fbytes;
     }
     if (out_cap > net->pl_out_cap) {
-        for (auto &p : net->pl_out) {
-            if (p) HIPCHK(net, hipFree(p));
-            p = nullptr;
-        }
         net->pl_out_cap = 0;
+        for (auto &p : net->pl_out) HIPCHK(net, free_dev(p));
         for (auto &p : net->pl_out)
             if (hipMalloc(&p, out_cap * sizeof(dl_emitter)) != hipSuccess) {
                 (void)hipGetLastError();
@@ -2256,11 +2263,8 @@ static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_c
         net->pl_out_cap = out_cap;
     }
     if (unc && out_cap > net->pl_unc_cap) {
-        for (auto &p : net->pl_unc) {
-            if (p) HIPCHK(net, hipFree(p));
-            p = nullptr;
-        }
         net->pl_unc_cap = 0;
+        for (auto &p : net->pl_unc) HIPCHK(net, free_dev(p));
         for (auto &p : net->pl_unc)
             if (hipMalloc(&p, out_cap * sizeof(dl_uncertainty)) != hipSuccess) {
                 (void)hipGetLastError();
@@ -2269,11 +2273,10 @@ static int ensure_pipeline(dl_net *net, size_t fbytes, bool staged, size_t out_c
         net->pl_unc_cap = out_cap;
     }
     if (n + 1 > net->pl_counts_n) {
-        if (net->pl_dcounts) HIPCHK(net, hipFree(net->pl_dcounts));
-        if (net->pl_hcounts) HIPCHK(net, hipHostFree(net->pl_hcounts));
-        net->pl_dcounts = nullptr;
-        net->pl_hcounts = nullptr;
+        const hipError_t ed = free_dev(net->pl_dcounts), eh = free_host(net->pl_hcounts);
         net->pl_counts_n = 0;
+        HIPCHK(net, ed);
+        HIPCHK(net, eh);
         HIPCHK(net, hipMalloc(&net->pl_dcounts, (size_t)2 * (n + 1) * 4));
         HIPCHK(net, hipHostMalloc((void **)&net->pl_hcounts, (size_t)2 * (n + 1) * 4, hipHostMallocDefault));
         net->pl_counts_n = n + 1;
@@ -2459,9 +2462,8 @@ int dl_localize_maps(dl_net *net, const uint16_t *frames, int n, int h, int w, f
     hipStream_t cs = net->compute_stream;
     if (mbytes > net->pl_maps_bytes) {
         HIPCHK(net, hipStreamSynchronize(cs));
-        if (net->pl_maps) HIPCHK(net, hipFree(net->pl_maps));
-        net->pl_maps = nullptr;
         net->pl_maps_bytes = 0;
+        HIPCHK(net, free_dev(net->pl_maps));
         if (hipMalloc(&net->pl_maps, mbytes) != hipSuccess) {
             (void)hipGetLastError();
             net->pl_maps = nullptr;
@@ -2715,7 +2717,7 @@ int dl_graph_launch(dl_graph *g, void *stream)
 void dl_graph_destroy(dl_graph *g)
 {
     if (!g) return;
-    (void)hipSetDevice(g->net->dev);
+    (void)hipSetDevice(g->dev);
     (void)hipDeviceSynchronize();
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
