@@ -331,8 +331,8 @@ k_conv(ConvArgs a, Geometry geo)
         return r;
     };
     // Wave 0 alone decodes tiles (the scalar unit is shared by the CU's
-    // waves): it publishes the tile after next in one of two LDS slots during
-    // its epilogue, and every wave picks it up after the next loop-top
+    // waves): it publishes the tile after next in one of two LDS slots from
+    // inside its MFMA loop, and every wave picks it up after the next loop-top
     // barrier.  A slot is rewritten only after every wave has passed the
     // barrier that follows its last reading.
     int *sdec = reinterpret_cast<int *>(sT + L::DOFF);
@@ -700,17 +700,31 @@ k_conv(ConvArgs a, Geometry geo)
                 // (b >= 2), and its scale comes from lane group b.  So this
                 // lane reads half kq & 1 of chunks 4 m + kq / 2 (low 16 bytes)
                 // and 4 m + 2 + kq / 2 (high), and the scale of chunk 4 m + kq.
-                auto chunk_off = [&](int g) {
-                    const int t = g / HPT, hf = g - (g / HPT) * HPT, tc = t < 9 ? t : 4;
-                    return ((tc / 3) * PW + tc % 3) * PS + hf * 32;
+                // Chunk g is half g % HPT of tap g / HPT.  With HPT = 2 (48 or
+                // 64 channels) this lane's chunks are halves kq / 2 of taps 2 m
+                // and 2 m + 1 and its scale chunk is half kq & 1 of tap
+                // 2 m + kq / 2; with HPT = 1 they are taps 4 m + kq / 2,
+                // 4 m + 2 + kq / 2 and 4 m + kq.  A tap's point offset depends
+                // on m alone (scalar); the lane adds a fixed part.
+                auto tap_off = [&](int t) {
+                    const int tc = t < 9 ? t : 4;
+                    return ((tc / 3) * PW + tc % 3) * PS;
                 };
-                auto scale_off = [&](int g) {
-                    const int t = g / HPT, hf = g - (g / HPT) * HPT, tc = t < 9 ? t : 4;
-                    return ((tc / 3) * PW + tc % 3) * PS + L::CT8 + hf;
-                };
-                const int lo_off = chunk_off(4 * m + (kq >> 1)) + 16 * (kq & 1);
-                const int hi_off = chunk_off(4 * m + 2 + (kq >> 1)) + 16 * (kq & 1);
-                const int soff = scale_off(4 * m + kq);
+                const int kh = kq >> 1, kl = kq & 1;
+                int lo_off, hi_off, soff;
+                if constexpr (HPT == 2) {
+                    const int p0 = tap_off(2 * m), p1 = tap_off(2 * m + 1);
+                    lo_off = p0 + kh * 32 + 16 * kl;
+                    hi_off = p1 + kh * 32 + 16 * kl;
+                    soff = (kh ? p1 : p0) + L::CT8 + kl;
+                } else {
+                    static_assert(HPT == 1, "FP8 taps hold one or two 32-channel groups");
+                    const int p0 = tap_off(4 * m), p1 = tap_off(4 * m + 1);
+                    const int p2 = tap_off(4 * m + 2), p3 = tap_off(4 * m + 3);
+                    lo_off = (kh ? p1 : p0) + 16 * kl;
+                    hi_off = (kh ? p3 : p2) + 16 * kl;
+                    soff = (kq == 0 ? p0 : kq == 1 ? p1 : kq == 2 ? p2 : p3) + L::CT8;
+                }
                 v8i av[NB], bv[PB];
                 int sb[PB];
 #pragma unroll
