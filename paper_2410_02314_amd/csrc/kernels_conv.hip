@@ -544,6 +544,20 @@ k_conv(ConvArgs a, Geometry geo)
             for (int p = 0; p < PB; ++p) acc[nb][p] = v4f{0.f, 0.f, 0.f, 0.f};
         // LDS address of lattice point (row wave + u, column 16 p + j + v) for tap (u, v), u, v in 0..2
         auto pt_addr = [&](int p, int tap) { return sT + ((wave + tap / 3) * PW + 16 * p + j + tap % 3) * PS; };
+        // BF16 forms: byte offset, from the lane's tap-0 point, of K chunk
+        // 4 m + kq (8 channels of one tap; chunk c is channels 8 (c mod CH8) ..
+        // of tap c / CH8).  Step m (a constant once the K loop is unrolled)
+        // starts at channel group r of tap tb; lane group kq's chunk is group
+        // r + kq of that tap, or, when that reaches CH8, group r + kq - CH8 of
+        // the next one (4 lane groups never span more than two taps, since
+        // CH8 >= 2).  Chunks past the ninth tap carry zero weights and read
+        // any in-tile point (the centre tap's).
+        auto bf16_chunk_off = [&](int m) {
+            constexpr int CH8 = KPlan<C, DL_BF16>::CH8;        // the same for both BF16 forms
+            auto tap_off = [](int t) { return ((t / 3) * PW + t % 3) * PS; };
+            const int tb = 4 * m / CH8, r = 4 * m - tb * CH8, tn = tb + 1 < 9 ? tb + 1 : 4;
+            return kq * 16 + (kq >= CH8 - r ? tap_off(tn) + (r - CH8) * 16 : tap_off(tb) + r * 16);
+        };
 
         // Wave 0 decodes the tile the next iteration prefetches (or that tile
         // again when it is the last) into the slot the next iteration reads.
@@ -626,20 +640,18 @@ k_conv(ConvArgs a, Geometry geo)
                 }
             }
         } else if constexpr (P == DL_BF16) {
-            constexpr int CH8 = KPlan<C, P>::CH8, NCH = KPlan<C, P>::NCH, NIT = KPlan<C, P>::NIT;
+            constexpr int NIT = KPlan<C, P>::NIT;
             const char *sW = sT + L::WOFF;
 #pragma unroll
             for (int m = 0; m < NIT; ++m) {
                 if (m == NIT / 2) ahead();
-                const int ch = 4 * m + kq;
-                const int tap = ch < NCH ? ch / CH8 : 4;          // padding chunks have zero weights
-                const int c0 = ch < NCH ? (ch - (ch / CH8) * CH8) * 8 : 0;
+                const int co = bf16_chunk_off(m);
                 v4f av[NB], bv[PB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     av[nb] = *reinterpret_cast<const v4f *>(sW + ((m * NB + nb) * 64 + lane) * 16);
 #pragma unroll
-                for (int p = 0; p < PB; ++p) bv[p] = *reinterpret_cast<const v4f *>(pt_addr(p, tap) + c0 * 2);
+                for (int p = 0; p < PB; ++p) bv[p] = *reinterpret_cast<const v4f *>(pt_addr(p, 0) + co);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -651,13 +663,11 @@ k_conv(ConvArgs a, Geometry geo)
             // as BF16, with both halves of every operand; the operands of step
             // m + 1 are read while the MFMAs of step m run (past the last step
             // step 0 is read again and not used)
-            constexpr int CH8 = KPlan<C, P>::CH8, NCH = KPlan<C, P>::NCH, NIT = KPlan<C, P>::NIT;
+            constexpr int NIT = KPlan<C, P>::NIT;
             constexpr int HALF = KPlan<C, P>::HALF;
             const char *sW = sT + L::WOFF;
             auto operands = [&](int m, v4f (&ah)[NB], v4f (&al)[NB], v4f (&bh)[PB], v4f (&bl)[PB]) {
-                const int ch = 4 * m + kq;
-                const int tap = ch < NCH ? ch / CH8 : 4;          // padding chunks have zero weights
-                const int c0 = ch < NCH ? (ch - (ch / CH8) * CH8) * 8 : 0;
+                const int co = bf16_chunk_off(m);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     const int wo = ((m * NB + nb) * 64 + lane) * 16;
@@ -666,7 +676,7 @@ k_conv(ConvArgs a, Geometry geo)
                 }
 #pragma unroll
                 for (int p = 0; p < PB; ++p) {
-                    const char *pa = pt_addr(p, tap) + c0 * 2;
+                    const char *pa = pt_addr(p, 0) + co;
                     bh[p] = *reinterpret_cast<const v4f *>(pa);
                     bl[p] = *reinterpret_cast<const v4f *>(pa + 2 * C);
                 }
