@@ -524,11 +524,12 @@ typedef struct {
  *   count          log(2 pi v) / 2 + (E - mu)^2 / (2 v)
  *   localisation   -sum_e log sum_k (p_k / mu) prod_d N(t_ed; m_kd, s_kd^2),
  *                  m_k = (col + 0.5 + dx, row + 0.5 + dy, dz, ph), s = softplus
- *                  of the raw uncertainty planes, t_e = (x, y, z_nm / z_scale,
- *                  photons / ph_scale)
- * and the batch loss is the mean over frames.  Training buffers are the
- * handle's (grown on demand).  Errors: DL_ERR_INVALID_ARG, DL_ERR_UNSUPPORTED,
- * DL_ERR_OOM, DL_ERR_DEVICE. */
+ *                  of the raw uncertainty planes + DL_SIGMA_FLOOR, t_e = (x, y,
+ *                  z_nm / z_scale, photons / ph_scale)
+ * and the batch loss is the mean over frames.  A batch holds at most 2^26
+ * pixels and a frame row at most 2^20 (DL_ERR_UNSUPPORTED beyond).  Training
+ * buffers are the handle's (grown on demand).  Errors: DL_ERR_INVALID_ARG,
+ * DL_ERR_UNSUPPORTED, DL_ERR_OOM, DL_ERR_DEVICE. */
 int dl_train_grad(dl_net *net, const uint16_t *d_frames, int n, int h, int w, const dl_truth *d_truth,
                   const int32_t *d_truth_off, int ntruth, void *stream, float *d_grad, float *d_loss);
 

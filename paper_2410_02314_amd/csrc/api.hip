@@ -1261,6 +1261,9 @@ int train_check(dl_net *net, const uint16_t *d_frames, int n, int h, int w, cons
         return fail(net, DL_ERR_INVALID_ARG, "d_truth_off and d_loss must be given, d_truth when ntruth > 0");
     if ((int64_t)n * h * w > ((int64_t)1 << 26))
         return fail(net, DL_ERR_UNSUPPORTED, "a training batch holds at most 2^26 pixels");
+    // the weight-gradient kernels address within a row with 32-bit byte
+    // offsets (up to 96 floats per point)
+    if (w > (1 << 20)) return fail(net, DL_ERR_UNSUPPORTED, "training frame rows hold at most 2^20 pixels (got %d)", w);
     return DL_OK;
 }
 

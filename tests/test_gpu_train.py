@@ -259,3 +259,11 @@ def test_nets_the_training_kernels_do_not_cover_are_refused():
         with pytest.raises(dl.DlocError) as e:
             net.train_grad(fr, tr, off)
         assert e.value.code == dl.DL_ERR_UNSUPPORTED, spec.name
+    # a frame row wider than the weight-gradient kernels' 32-bit row offsets
+    # cover (refused before any work is queued)
+    spec, w = S.make_net("AU", 1)
+    net = dl.Net(S.serialize_weights(spec, w))
+    wide = torch.from_numpy(np.zeros((1, 1, (1 << 20) + 64), np.uint16)).to(DEV)
+    with pytest.raises(dl.DlocError) as e:
+        net.train_grad(wide, tr, off)
+    assert e.value.code == dl.DL_ERR_UNSUPPORTED and "2^20" in str(e.value)
