@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--sparse-layout", default="iid", choices=["iid", "cell"],
                     help="sparse workload: empty 256^2 tiles chosen independently (iid) or around one "
                          "compact occupied region (cell)")
+    ap.add_argument("--train-eval-steps", type=int, default=500,
+                    help="train workload: Adam steps of the trained-net evaluation that follows the timed steps "
+                         "(0 = leave it out, e.g. under a profiler)")
     ap.add_argument("--net", default="B", choices=["B", "BU", "D", "DU"],
                     help="full workload: net B with the 5-output head, BU, the same net with the "
                          "10-output head (per-pixel uncertainties and background), D, the "

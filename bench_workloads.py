@@ -424,7 +424,8 @@ def train(args, S):
            "precision": "fp32", "frames": n, "height": side, "width": side},
           {"frames_per_s": round(n / (ms * 1e-3), 1), "emitters_per_batch": int(off[-1]),
            "loss_first_step": round(first, 4), "loss_after": round(last, 4), "steps_timed": args.steps,
-           "conv_tflop_per_step": round(flop / 1e12, 4), "trained_eval": train_eval(S, spec, w),
+           "conv_tflop_per_step": round(flop / 1e12, 4),
+           "trained_eval": train_eval(S, spec, w, steps=args.train_eval_steps) if args.train_eval_steps > 0 else None,
            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAKS["fp32"], "unit": "TFLOP/s",
                         "frac": round(tflops / PEAKS["fp32"], 4), "traffic": None,
                         "kernel": "whole training step (convolution FLOP over the step time)"}})
